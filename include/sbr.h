@@ -1,0 +1,201 @@
+/*
+ * sbr.h -- C-ABI of the MI355X SBR (shooting-and-bouncing-ray) channel library.
+ *
+ * Method: Wang et al., "An SBR Based Ray Tracing Channel Modeling Method for
+ * THz and Massive MIMO Communications" (arXiv 2208.10006), Section II.  The
+ * four calls follow its four steps (Sec. II-A): ray launching, ray tracing,
+ * ray reception and ray calculation, with the THz corrections of Sec. II-B
+ * and the MIMO outputs of Sec. II-C.
+ *
+ * Conventions (all calls):
+ *   - SI units: metres, seconds, hertz, S/m.  Angles in degrees unless noted.
+ *   - Every call returns an sbr_status; nothing throws across the ABI.  On a
+ *     non-OK status no output is written, no handle is created, and
+ *     sbr_last_error() (thread-local) describes the failure.  HIP runtime
+ *     failures map to SBR_E_DEVICE with the HIP error string in the message.
+ *   - Input arrays are borrowed for the duration of the call.  By default they
+ *     are host pointers and are copied before the call returns; with
+ *     SBR_IN_DEVICE they are device pointers on the context's device, read in
+ *     stream order (they must stay valid until the context stream passes the
+ *     call).
+ *   - Output arrays are caller-allocated.  By default host pointers (the call
+ *     synchronises the context stream before returning); with SBR_OUT_DEVICE
+ *     device pointers written in stream order.
+ *   - Handles are owned by the library until sbr_release().  A trace keeps
+ *     its scene alive, a path set keeps its trace alive (reference counts).
+ *   - Determinism: identical inputs give bitwise-identical outputs (sorted
+ *     keys, fixed reduction orders, no floating-point atomics).
+ *   - Threading: one context per host thread.
+ */
+#ifndef SBR_H_
+#define SBR_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SBR_OK = 0,
+  SBR_E_INVALID_ARG = -1,   /* bad size, NaN/Inf, degenerate triangle, ...   */
+  SBR_E_OUT_OF_MEMORY = -2, /* device allocation failed                        */
+  SBR_E_DEVICE = -3,        /* HIP runtime error or a kernel-reported failure  */
+  SBR_E_CAPACITY = -4,      /* an output buffer is too small (size in message) */
+  SBR_E_STATE = -5,         /* call order violated (e.g. stats before channel) */
+  SBR_E_UNSUPPORTED = -6
+} sbr_status;
+
+#define SBR_IN_DEVICE 0x1u  /* pointer inputs are device pointers              */
+#define SBR_OUT_DEVICE 0x2u /* pointer outputs are device pointers             */
+
+#define SBR_POL_V 0 /* theta-hat of the departure / arrival direction */
+#define SBR_POL_H 1 /* phi-hat of the departure / arrival direction   */
+
+#define SBR_MAX_BOUNCES 16
+
+typedef struct sbr_context_s* sbr_context_t; /* device, stream, tuning         */
+typedef struct sbr_scene_s* sbr_scene_t;     /* triangles, face groups, LBVH   */
+typedef struct sbr_trace_s* sbr_trace_t;     /* per-ray hit chains ("RT tree") */
+typedef struct sbr_paths_s* sbr_paths_t;     /* unique validated paths         */
+
+/* One propagation path (Sec. II-A-4: a multipath component of eq. (2)/(4)).
+ * tx, rx: element indices; order: number of reflections; groups: the face
+ * groups reflected from, in order (-1 padded).  Angles: AoD = direction of
+ * travel leaving the Tx, AoA = direction from the Rx toward the last
+ * interaction; azimuth atan2(y, x) in (-180, 180], elevation asin(z). */
+typedef struct {
+  int32_t tx, rx, order, flags;
+  int32_t groups[SBR_MAX_BOUNCES];
+  double length_m, delay_s;
+  float aod_az, aod_el, aoa_az, aoa_el;
+  float power; /* band mean of |a_n(f)|^2 over the last sbr_channel grid; 0 before */
+  int32_t pad;
+} sbr_path_record;
+
+/* ------------------------------------------------------------------------ */
+/* Context.  device: HIP ordinal.  hip_stream: a hipStream_t to run on, or
+ * NULL for a library-owned stream.  */
+sbr_status sbr_context_create(int device, void* hip_stream, sbr_context_t* out);
+/* Block until all work queued by this context has finished. */
+sbr_status sbr_synchronize(sbr_context_t ctx);
+
+/* Scene (Sec. III-A: triangle scenes; Sec. II-B-1 / eq. (6)-(8): per-surface
+ * relative permittivity, conductivity and roughness).
+ * tri_xyz: [T][3][3] vertices (FP64, metres).  eps_r >= 1, sigma >= 0 (S/m),
+ * rough_std >= 0 (m), each [T] FP32.  T = 0 is allowed (free space).
+ * Triangles are double sided.  Coplanar triangles with equal materials form
+ * one face group (the reflector a path key names).  Errors: INVALID_ARG on
+ * NaN/Inf, negative size, bad material or a triangle of area <= 1e-12 diag^2
+ * (the message names the index). */
+sbr_status sbr_scene_build(sbr_context_t ctx, const double* tri_xyz, int64_t T, const float* eps_r,
+                           const float* sigma_S_per_m, const float* rough_std_m, uint32_t flags,
+                           sbr_scene_t* out);
+
+/* Launch + trace (Sec. II-A-1, II-A-2).  Every Tx element (eq. (11)) launches
+ * 10 N^2 + 2 rays along the frequency-N icosahedral geodesic directions
+ * (its own spherical wavefront), and each ray is reflected specularly up to
+ * max_bounces times; the (max_bounces+1)-th hit absorbs it.  The per-ray hit
+ * chain is kept on the device for sbr_receive.
+ * tx_xyz: [Nt][3] FP64.  1 <= geodesic_N <= 46340 ("level L" = N = 2^L),
+ * 0 <= max_bounces <= 16, Nt * (10 N^2 + 2) < 2^32. */
+sbr_status sbr_trace(sbr_context_t ctx, sbr_scene_t scene, const double* tx_xyz, int32_t Nt,
+                     int32_t geodesic_N, int32_t max_bounces, uint32_t flags, sbr_trace_t* out);
+/* rays = Nt (10N^2+2); segments = closest-hit queries actually traced. */
+sbr_status sbr_trace_info(sbr_trace_t tr, int64_t* rays, int64_t* segments);
+/* Per-ray hit triangles [rays][K+1] (original triangle index; -1 miss,
+ * -2 not traced because the ray ended earlier).  Host or device output. */
+sbr_status sbr_trace_hits(sbr_trace_t tr, int32_t* seq, uint32_t flags);
+
+/* Reception (Sec. II-A-3) and path extraction.  A segment with origin o,
+ * unit direction d, end t_end and unfolded length L before it is captured by
+ * Rx q when t* = (q - o).d lies in [0, t_end] and |q - o - t* d| <=
+ * radius_coeff * alpha * (L + t*) / sqrt(3).  alpha_rad <= 0 selects the mean
+ * great-circle angle between neighbouring geodesic rays.  Captures are
+ * reduced to unique keys (Tx, Rx, face-group sequence); every key is rebuilt
+ * exactly by the image method (Sec. I) in FP64 and kept only when its
+ * reflection points lie on their faces, on the incidence side, unoccluded.
+ * rx_xyz: [Nr][3] FP64, no Rx may coincide with a Tx. */
+sbr_status sbr_receive(sbr_context_t ctx, sbr_trace_t tr, const double* rx_xyz, int32_t Nr, double alpha_rad,
+                       double radius_coeff, uint32_t flags, sbr_paths_t* out);
+/* capture events, distinct keys before validation, valid paths */
+sbr_status sbr_paths_info(sbr_paths_t ps, int64_t* events, int64_t* keys, int64_t* paths);
+sbr_status sbr_paths_count(sbr_paths_t ps, int64_t* n);
+/* Capture events behind the paths (diagnostic): global ray id (tx * rays +
+ * ray), receiver and segment index k of each capture, host arrays of length
+ * >= events (sbr_paths_info); unordered.  Any output may be NULL. */
+sbr_status sbr_paths_events(sbr_paths_t ps, int64_t capacity, uint32_t* ray, int32_t* rx, int32_t* k,
+                            int64_t* written);
+/* Host copy of the path list, ordered by (rx, tx, delay). */
+sbr_status sbr_paths_get(sbr_paths_t ps, int64_t capacity, sbr_path_record* out, int64_t* written);
+
+/* Ray calculation (Sec. II-A-4 and II-B): the field of every path at every
+ * frequency, eq. (1) with the Kirchhoff-corrected Fresnel coefficients of
+ * eq. (6)-(8), the free-space factor that eq. (3) turns into Friis for unit
+ * isotropic antennas, and per-frequency specific attenuation (dB/m) and
+ * dispersion (deg/m) tables standing for eq. (9)-(10) (NULL = none); then the
+ * coherent sum per (f, Rx, Tx) of eq. (2) = h_qp of eq. (13)-(14):
+ *   H[f][q][p] = sum over paths n of (p, q) of a_n(f).
+ * a_n(f) = lambda/(4 pi d) e_rx . [prod rho R] e_tx 10^(-g d/20) e^{-j(2 pi f d/c + pi phi d/180)};
+ * the phase is taken as 2 pi frac(f d / c) in FP64; the sum is FP64.
+ * H_c64: [Nf][Nr][Nt] interleaved (re, im) FP32, may be NULL if H_c128 given;
+ * H_c128: same shape FP64 or NULL.  Also stores each path's band-mean power. */
+sbr_status sbr_channel(sbr_context_t ctx, sbr_paths_t ps, const double* freq_hz, int32_t Nf,
+                       const float* atm_db_per_m, const float* atm_deg_per_m, int32_t pol_tx, int32_t pol_rx,
+                       void* H_c64, double* H_c128, uint32_t flags);
+/* Per-path amplitudes a_n(f), [n_paths][Nf] interleaved FP64, same arguments
+ * as sbr_channel (diagnostic / parity output). */
+sbr_status sbr_path_field(sbr_context_t ctx, sbr_paths_t ps, const double* freq_hz, int32_t Nf,
+                          const float* atm_db_per_m, const float* atm_deg_per_m, int32_t pol_tx, int32_t pol_rx,
+                          double* a_c128, uint32_t flags);
+
+/* Per (Rx, Tx) statistics from the path powers of the last sbr_channel:
+ * pg_db: 10 log10 sum P_n (incoherent path gain; -inf when no path),
+ * tau_rms_s: eq. (5), mean_angles: [Nr][Nt][4] power-weighted (circular mean
+ * azimuth, arithmetic mean elevation) of AoD then AoA.  Any output may be
+ * NULL.  SBR_E_STATE before sbr_channel. */
+sbr_status sbr_stats(sbr_paths_t ps, float* pg_db, float* tau_rms_s, float* mean_angles, uint32_t flags);
+
+/* MIMO capacity, eq. (15)-(17): C(SNR) = band mean of
+ * log2 det(I + SNR/Nt W_f), W = Hn Hn^H (Nt >= Nr) or Hn^H Hn (Nt < Nr).
+ * normalize = 1: Hn = H sqrt(Nt Nr / Q), Q = band mean of ||H_f||_F^2
+ * (the paper's Q scaling read as a Frobenius normalisation); 0: Hn = H.
+ * H_c64: [Nf][Nr][Nt] interleaved FP32; snr_db: [Nsnr]; C_bits_per_hz: [Nsnr]
+ * FP64.  min(Nr, Nt) <= 128. */
+sbr_status sbr_capacity(sbr_context_t ctx, const void* H_c64, int32_t Nf, int32_t Nr, int32_t Nt,
+                        const double* snr_db, int32_t Nsnr, int32_t normalize, double* C_bits_per_hz,
+                        uint32_t flags);
+
+/* Launch directions (Sec. II-A-1) for parity checks: dirs [count][3] FP64 of
+ * ray ids first .. first+count-1; and the edge-angle statistics (radians) of
+ * the geodesic triangulation (any output may be NULL). */
+sbr_status sbr_geodesic(sbr_context_t ctx, int32_t N, int64_t first, int64_t count, double* dirs, uint32_t flags);
+sbr_status sbr_geodesic_alpha(sbr_context_t ctx, int32_t N, double* mean, double* min, double* max);
+
+/* Scene queries: face group and plane id of every triangle (host [T]). */
+sbr_status sbr_scene_info(sbr_scene_t s, int32_t* n_groups, int32_t* n_planes, int32_t* bvh_depth);
+sbr_status sbr_scene_groups(sbr_scene_t s, int32_t* group, int32_t* plane);
+
+/* Live per-kernel timing (measurement support, not part of the method).
+ * When enabled, the library records a pair of HIP events on the context
+ * stream around every kernel launch it makes and accumulates the elapsed time
+ * per kernel class ("bounce", "replay_capture", "rebuild", "channel", "sort",
+ * "lbvh", "keys", "stats", "capacity", "alpha", "misc").  Enabling clears the
+ * totals; a query synchronises the stream.  Unknown names report 0. */
+sbr_status sbr_profile_enable(sbr_context_t ctx, int enable);
+sbr_status sbr_profile_query(sbr_context_t ctx, const char* kernel, double* total_ms, int64_t* launches);
+/* Traversal work counters: with counting enabled (sbr_context_count_work),
+ * later traces also count BVH node visits and ray-triangle tests of the
+ * closest-hit search; sbr_trace_work returns them (0 when not counted). */
+sbr_status sbr_context_count_work(sbr_context_t ctx, int enable);
+sbr_status sbr_trace_work(sbr_trace_t tr, int64_t* node_visits, int64_t* tri_tests);
+
+/* Release any handle (context, scene, trace, paths); NULL is ignored. */
+void sbr_release(void* handle);
+const char* sbr_last_error(void);
+const char* sbr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SBR_H_ */

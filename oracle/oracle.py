@@ -55,7 +55,8 @@ def lib():
                               C.c_double, C.c_double, P, C.c_int64, P, P, P,
                               C.c_int64, P, P, P, P, C.c_int]
         L.orc_paths.argtypes = [P, C.c_int, P, P, P, P, P, C.c_int, P, C.c_int64, P]
-        L.orc_field.argtypes = [P, C.c_int, P, P, P, P, P, C.c_int, P, C.c_int64, P, C.c_int, P, P, P]
+        L.orc_field.argtypes = [P, C.c_int, P, P, P, P, P, C.c_int, P, C.c_int64, P, C.c_int, P, P,
+                                C.c_int, C.c_int, P]
         L.orc_fresnel.argtypes = [C.c_double] * 4 + [P] * 4
         L.orc_roughness.restype = C.c_double
         L.orc_roughness.argtypes = [C.c_double] * 3
@@ -156,7 +157,11 @@ def sbr(w, ray_ids=None, alpha: float | None = None, coeff: float | None = None,
         if tot <= cap:
             break
         cap = int(tot)
-    return TraceResult(ray_ids, seq, tv, amb, ek[:tot], er[:tot], ea[:tot], eq[:tot])
+    ea, eq, ek, er = ea[:tot], eq[:tot], ek[:tot], er[:tot]
+    cap_ = (ea & 4) == 0
+    res = TraceResult(ray_ids, seq, tv, amb, ek[cap_], er[cap_], ea[cap_], eq[cap_])
+    res.near_key, res.near_ray = ek[~cap_], er[~cap_]
+    return res
 
 
 def unique_keys(ev_key: np.ndarray) -> np.ndarray:
@@ -177,7 +182,8 @@ def paths(w, keys: np.ndarray) -> np.ndarray:
     return rec
 
 
-def field(w, keys: np.ndarray, freq=None, atm_db=None, atm_deg=None) -> np.ndarray:
+def field(w, keys: np.ndarray, freq=None, atm_db=None, atm_deg=None, pol_tx: int = 0,
+          pol_rx: int = 0) -> np.ndarray:
     """Complex amplitude a_n(f) of each key, [n, Nf] complex128."""
     tri, e, s, r, tx, rx = _arrays(w)
     keys = np.ascontiguousarray(keys, np.int32)
@@ -188,7 +194,7 @@ def field(w, keys: np.ndarray, freq=None, atm_db=None, atm_deg=None) -> np.ndarr
     ag = None if atm_deg is None else np.ascontiguousarray(atm_deg, np.float32)
     out = np.zeros((len(keys), len(freq), 2))
     lib().orc_field(_p(tri), w.T, _p(e), _p(s), _p(r), _p(tx), _p(rx), w.max_bounces, _p(keys),
-                    len(keys), _p(freq), len(freq), _p(ad), _p(ag), _p(out))
+                    len(keys), _p(freq), len(freq), _p(ad), _p(ag), int(pol_tx), int(pol_rx), _p(out))
     return out[..., 0] + 1j * out[..., 1]
 
 

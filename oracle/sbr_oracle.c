@@ -333,7 +333,9 @@ static int ev_cmp(const void* A, const void* B) {
   return a->q - b->q;
 }
 
-/* returns the number of events (may exceed ev_cap; then only ev_cap are written) */
+/* returns the number of events (may exceed ev_cap; then only ev_cap are written).
+ * ev_amb bits: 1 capture within 1e-5 of the sphere or segment ends, 2 the ray
+ * had an ambiguous hit at a bounce <= k, 4 near miss (recorded, not captured). */
 int64_t orc_sbr(const double* tri, int T, const float* eps, const float* sig, const float* rough,
                 const double* tx, int Nt, const double* rx, int Nr, int N, int K,
                 double alpha, double coeff, const int64_t* ray_ids, int64_t nrays,
@@ -384,14 +386,15 @@ int64_t orc_sbr(const double* tri, int T, const float* eps, const float* sig, co
         if (ts < 0.0 || ts > tend) continue;
         double dist = nrm(sub(w, scl(d, ts)));
         double rad = rfac * (L + ts);
-        if (dist <= rad) {
+        /* captures, plus near misses within the 1e-5 band (flag 4, not a capture) */
+        if (dist <= rad * (1.0 + 1e-5)) {
           event_t e; memset(&e, 0, sizeof e);
           e.p = p; e.q = q; e.k = k; e.ray = gid;
           for (int i = 0; i < 16; ++i) e.g[i] = i < k ? grp[i] : -1;
           double scale = isfinite(tend) ? tend : ts;
           int camb = fabs(dist - rad) <= 1e-5 * rad || ts <= 1e-5 * (L + ts) ||
                      (isfinite(tend) && tend - ts <= 1e-5 * scale);
-          e.amb = (uint8_t)((camb ? 1 : 0) | (amb_acc ? 2 : 0));
+          e.amb = (uint8_t)((camb ? 1 : 0) | (amb_acc ? 2 : 0) | (dist > rad ? 4 : 0));
           e.ratio = dist / rad;
           ev_push(&bufs[tid], &e);
         }
@@ -427,7 +430,7 @@ int64_t orc_sbr(const double* tri, int T, const float* eps, const float* sig, co
  * 6. Exact path geometry from a key by the image method (Sec. I).
  * S_0 = T_p, S_i = mirror of S_{i-1} in plane(g_i); back from X_{k+1} = R_q:
  * X_i = plane(g_i) cut by the line S_i -> X_{i+1}.  Valid when every X_i is
- * inside (inclusive) some triangle of g_i, X_{i-1} and X_{i+1} are strictly
+ * inside (inclusive, barycentric margin 1e-9) some triangle of g_i, X_{i-1} and X_{i+1} are strictly
  * on the same side of plane(g_i), and no triangle crosses any leg
  * X_{i-1} -> X_i at parameter s in (1e-9, 1 - 1e-9) (triangles of the two
  * end groups are ignored).  plane(g) is that of the group's lowest triangle.
@@ -440,7 +443,10 @@ static int in_tri(const scene_t* S, int t, v3 x) {
   double v = (d11 * d20 - d01 * d21) / den;
   double w = (d00 * d21 - d01 * d20) / den;
   double u = 1.0 - v - w;
-  return u >= 0.0 && v >= 0.0 && w >= 0.0;
+  /* inclusive, with a 1e-9 barycentric margin: a face group is the union of
+   * its triangles and a point on a shared edge must not fall through a
+   * rounding crack between them */
+  return u >= -1e-9 && v >= -1e-9 && w >= -1e-9;
 }
 
 static int blocked(const scene_t* S, v3 a, v3 b, int ga, int gb) {
@@ -456,10 +462,10 @@ static int blocked(const scene_t* S, v3 a, v3 b, int ga, int gb) {
     double inv = 1.0 / det;
     v3 tvec = sub(a, v0);
     double u = dot(tvec, pv) * inv;
-    if (u < 0.0 || u > 1.0) continue;
+    if (u < -1e-9 || u > 1.0 + 1e-9) continue;
     v3 qv = crs(tvec, e1);
     double v = dot(D, qv) * inv;
-    if (v < 0.0 || u + v > 1.0) continue;
+    if (v < -1e-9 || u + v > 1.0 + 1e-9) continue;  /* same crack-free margin as in_tri */
     double s = dot(e2, qv) * inv;
     if (s > 1e-9 && s < 1.0 - 1e-9) return 1;
   }
@@ -559,6 +565,12 @@ static v3 theta_hat(v3 u) {
   if (st > 0.0) { cp = u.x / st; sp = u.y / st; }
   return mk(ct * cp, ct * sp, -st);
 }
+static v3 phi_hat(v3 u) {
+  double phi = atan2(u.y, u.x);  /* atan2(0, 0) = 0 at the poles */
+  return mk(-sin(phi), cos(phi), 0.0);
+}
+/* antenna polarisation: 0 = theta-hat (vertical), 1 = phi-hat (horizontal) */
+static v3 pol_vec(v3 u, int pol) { return pol ? phi_hat(u) : theta_hat(u); }
 
 void orc_fresnel(double eps_r, double sigma, double f, double cos_i,
                  double* rte_re, double* rte_im, double* rtm_re, double* rtm_im) {
@@ -579,7 +591,8 @@ double orc_roughness(double rough_std, double f, double cos_i) {
 /* a[n][Nf][2] (re, im); paths that fail validation get 0 */
 int orc_field(const double* tri, int T, const float* eps, const float* sig, const float* rough,
               const double* tx, const double* rx, int K, const int32_t* keys, int64_t n,
-              const double* freq, int Nf, const float* atm_db, const float* atm_deg, double* a) {
+              const double* freq, int Nf, const float* atm_db, const float* atm_deg, int pol_tx, int pol_rx,
+              double* a) {
   scene_t S; scene_init(&S, tri, T, eps, sig, rough);
 #ifdef _OPENMP
 #pragma omp parallel for schedule(dynamic, 4)
@@ -598,7 +611,7 @@ int orc_field(const double* tri, int T, const float* eps, const float* sig, cons
       double f = freq[fi];
       double lam = ORC_C0 / f;
       v3 kd = unit(sub(X[1], X[0]));
-      v3 th = theta_hat(kd);
+      v3 th = pol_vec(kd, pol_tx);
       c3 E = {th.x, th.y, th.z};
       for (int b = 1; b <= k; ++b) {
         int gi = kk[3 + b - 1];
@@ -630,7 +643,7 @@ int orc_field(const double* tri, int T, const float* eps, const float* sig, cons
         E.z = cs_ * s.z + cp_ * pout.z;
         kd = kr;
       }
-      v3 tr = theta_hat(kd);
+      v3 tr = pol_vec(kd, pol_rx);
       double complex pol = E.x * tr.x + E.y * tr.y + E.z * tr.z;
       double amp = lam / (4.0 * ORC_PI * len);
       if (atm_db) amp *= pow(10.0, -(double)atm_db[fi] * len / 20.0);

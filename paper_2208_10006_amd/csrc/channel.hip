@@ -1,0 +1,366 @@
+// channel.hip -- ray calculation (Sec. II-A-4, II-B, II-C).
+//
+// Field of path n at frequency f (eq. (1) with reflections only):
+//   a_n(f) = lambda/(4 pi d) * e_rx . [prod_b rho_b R_b] e_tx
+//            * 10^(-gamma(f) d / 20) * exp(-j pi [2 frac(f d / c) + phi(f) d / 180])
+// R_b: Fresnel TE/TM of the smooth interface (eps_c = eps_r - j sigma/(2 pi f eps0)),
+// rho_b: Kirchhoff roughness factor exp(-g/2), g = (4 pi sigma_h cos_i / lambda)^2
+// (eq. (6)-(8)); gamma, phi: attenuation / dispersion tables standing for
+// eq. (9)-(10).  Everything is FP64: at THz carriers over hundreds of metres
+// f d / c reaches 1e6 cycles, and the coherent sum of eq. (2) must stay
+// accurate in deep fades where sum |a_n| >> |sum a_n|.
+//
+// H (eq. (13)-(14)): one block per (rx, tx) pair walks that pair's paths in
+// their stored (delay) order and keeps the running sum for its frequencies in
+// registers -- a segmented reduction with a fixed order and no atomics.
+#include <algorithm>
+#include <cmath>
+
+#include "sbr_device.hpp"
+#include "sbr_internal.hpp"
+
+namespace sbr {
+namespace {
+
+inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+struct FieldArgs {
+  const double* freq;
+  const float* atm_db;
+  const float* atm_deg;
+  int Nf, ptx, prx;
+};
+
+__device__ inline cd path_amplitude(const double* __restrict__ G, const FieldArgs& A, int fi) {
+  const double f = A.freq[fi];
+  const double d = G[0];
+  const int k = (int)G[1];
+  cd pol;
+  if (k == 0) {
+    pol = cd{G[10 + 2 * A.prx + A.ptx], 0.0};
+  } else {
+    cd v0{G[2 + 2 * A.ptx], 0.0}, v1{G[3 + 2 * A.ptx], 0.0};
+    const double eim = -1.0 / (2.0 * kPi * f * kEps0);
+    for (int b = 0; b < k; ++b) {
+      const double* B = G + kGeoHead + kGeoPerBounce * b;
+      const double cs = B[0];
+      const cd ec{B[1], B[2] * eim};
+      const cd root = csqrt_p(cd{ec.re - (1.0 - cs * cs), ec.im});
+      const cd rte = cdiv(cd{cs - root.re, -root.im}, cd{cs + root.re, root.im});
+      const cd ecc = cscale(ec, cs);
+      const cd rtm = cdiv(csub(ecc, root), cadd(ecc, root));
+      double rho = 1.0;
+      if (B[3] > 0.0) {
+        const double gg = 4.0 * kPi * B[3] * cs * f / kC0;
+        rho = exp(-0.5 * gg * gg);
+      }
+      const cd a0 = cscale(cmul(rte, v0), rho), a1 = cscale(cmul(rtm, v1), rho);
+      if (b < k - 1) {
+        v0 = cadd(cscale(a0, B[4]), cscale(a1, B[5]));
+        v1 = cadd(cscale(a0, B[6]), cscale(a1, B[7]));
+      } else {
+        pol = cadd(cscale(a0, G[6 + 2 * A.prx]), cscale(a1, G[7 + 2 * A.prx]));
+      }
+    }
+  }
+  double amp = kC0 / (4.0 * kPi * f * d);
+  if (A.atm_db) amp *= exp10(-(double)A.atm_db[fi] * d / 20.0);
+  const double cyc = f * d / kC0;
+  double ph = 2.0 * (cyc - floor(cyc));  // in units of pi
+  if (A.atm_deg) ph += (double)A.atm_deg[fi] * d / 180.0;
+  double sn, cn;
+  sincospi(ph, &sn, &cn);
+  const cd e{amp * cn, -amp * sn};
+  return cmul(pol, e);
+}
+
+constexpr int kChanThreads = 256;
+constexpr int kChanFPT = 4;  // frequencies per thread per chunk
+constexpr int kChanChunk = kChanThreads * kChanFPT;
+
+__global__ __launch_bounds__(kChanThreads) void k_channel(const double* __restrict__ geo, int stride,
+                                                          const int32_t* __restrict__ seg_start, FieldArgs A, int Nr,
+                                                          int Nt, float2* __restrict__ H64, double2* __restrict__ H128,
+                                                          double* __restrict__ power) {
+  __shared__ double wsum[kChanThreads / kWave];
+  const int64_t seg = blockIdx.x;
+  const int q = (int)(seg / Nt), p = (int)(seg - (int64_t)q * Nt);
+  const int n0 = seg_start[seg], n1 = seg_start[seg + 1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int c0 = 0; c0 < A.Nf; c0 += kChanChunk) {
+    cd acc[kChanFPT];
+#pragma unroll
+    for (int j = 0; j < kChanFPT; ++j) acc[j] = cd{0.0, 0.0};
+    for (int n = n0; n < n1; ++n) {
+      const double* G = geo + (int64_t)n * stride;
+      double ps = 0.0;
+#pragma unroll
+      for (int j = 0; j < kChanFPT; ++j) {
+        const int fi = c0 + j * kChanThreads + threadIdx.x;
+        if (fi < A.Nf) {
+          const cd a = path_amplitude(G, A, fi);
+          acc[j] = cadd(acc[j], a);
+          ps += a.re * a.re + a.im * a.im;
+        }
+      }
+      if (power) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) ps += __shfl_xor(ps, o, 64);
+        if (lane == 0) wsum[wv] = ps;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          double t = 0.0;
+          for (int w = 0; w < kChanThreads / kWave; ++w) t += wsum[w];
+          const double prev = c0 == 0 ? 0.0 : power[n];
+          const double tot = prev + t;
+          power[n] = (c0 + kChanChunk >= A.Nf) ? tot / (double)A.Nf : tot;
+        }
+        __syncthreads();
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kChanFPT; ++j) {
+      const int fi = c0 + j * kChanThreads + threadIdx.x;
+      if (fi < A.Nf) {
+        const int64_t o = ((int64_t)fi * Nr + q) * Nt + p;
+        if (H128) H128[o] = make_double2(acc[j].re, acc[j].im);
+        if (H64) H64[o] = make_float2((float)acc[j].re, (float)acc[j].im);
+      }
+    }
+  }
+}
+
+__global__ void k_path_field(const double* __restrict__ geo, int stride, int64_t n, FieldArgs A,
+                             double2* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * A.Nf) return;
+  const int64_t pth = i / A.Nf;
+  const int fi = (int)(i - pth * A.Nf);
+  const cd a = path_amplitude(geo + pth * stride, A, fi);
+  out[i] = make_double2(a.re, a.im);
+}
+
+// per (rx, tx): incoherent path gain, RMS delay spread (eq. (5)), mean angles
+__global__ void k_stats(const int32_t* __restrict__ seg_start, int64_t nseg, const double* __restrict__ power,
+                        const double* __restrict__ info, const float* __restrict__ ang, float* __restrict__ pg_db,
+                        float* __restrict__ tau, float* __restrict__ angles) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nseg) return;
+  double P = 0, Pt = 0, Pt2 = 0, cd_ = 0, sd = 0, ed = 0, ca = 0, sa = 0, ea = 0;
+  for (int n = seg_start[s]; n < seg_start[s + 1]; ++n) {
+    const double w = power[n], t = info[2 * n + 1];
+    P += w;
+    Pt += w * t;
+    Pt2 += w * t * t;
+    double sn, cn;
+    sincospi((double)ang[4 * n] / 180.0, &sn, &cn);
+    cd_ += w * cn, sd += w * sn, ed += w * ang[4 * n + 1];
+    sincospi((double)ang[4 * n + 2] / 180.0, &sn, &cn);
+    ca += w * cn, sa += w * sn, ea += w * ang[4 * n + 3];
+  }
+  if (pg_db) pg_db[s] = P > 0 ? (float)(10.0 * log10(P)) : -INFINITY;
+  if (tau) {
+    double v = 0.0;
+    if (P > 0) {
+      const double m1 = Pt / P, m2 = Pt2 / P;
+      v = m2 - m1 * m1;
+    }
+    tau[s] = (float)sqrt(v > 0 ? v : 0.0);
+  }
+  if (angles) {
+    float* a = angles + 4 * s;
+    if (P > 0) {
+      a[0] = (float)(atan2(sd, cd_) * (180.0 / kPi));
+      a[1] = (float)(ed / P);
+      a[2] = (float)(atan2(sa, ca) * (180.0 / kPi));
+      a[3] = (float)(ea / P);
+    } else {
+      a[0] = a[1] = a[2] = a[3] = 0.0f;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- capacity
+// per-frequency squared Frobenius norm (block per f, fixed reduction order)
+__global__ __launch_bounds__(256) void k_cap_frob(const float2* __restrict__ H, int Nr, int Nt,
+                                                  double* __restrict__ frob) {
+  const int f = blockIdx.x;
+  const int64_t m = (int64_t)Nr * Nt;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < m; i += 256) {
+    const float2 h = H[(int64_t)f * m + i];
+    s += (double)h.x * h.x + (double)h.y * h.y;
+  }
+  __shared__ double sm[256];
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) frob[f] = sm[0];
+}
+
+// scale^2 applied to W: Nt Nr / mean_f ||H_f||^2 (normalize) or 1
+__global__ __launch_bounds__(256) void k_cap_scale(const double* __restrict__ frob, int Nf, int Nr, int Nt,
+                                                   int normalize, double* __restrict__ scale2) {
+  double s = 0.0;
+  for (int f = threadIdx.x; f < Nf; f += 256) s += frob[f];
+  __shared__ double sm[256];
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double q = sm[0] / Nf;
+    *scale2 = normalize ? (q > 0 ? (double)Nt * Nr / q : 0.0) : 1.0;
+  }
+}
+
+// block per frequency: W = s^2 Hn Hn^H (n = min(Nr, Nt)), then for every SNR
+// a Cholesky factor of I + SNR/Nt W and log2 det = 2 sum log2 L_ii.
+__global__ __launch_bounds__(256) void k_cap_logdet(const float2* __restrict__ H, int Nr, int Nt,
+                                                    const double* __restrict__ scale2, const double* __restrict__ snr_db,
+                                                    int Nsnr, double2* __restrict__ work, double* __restrict__ cf) {
+  const int f = blockIdx.x;
+  const int n = Nr <= Nt ? Nr : Nt;
+  const int m = Nr <= Nt ? Nt : Nr;
+  const bool rows = Nt >= Nr;  // W = H H^H over columns; else W = H^H H over rows
+  const float2* Hf = H + (int64_t)f * Nr * Nt;
+  double2* W = work + (int64_t)f * 2 * n * n;
+  double2* M = W + (int64_t)n * n;
+  const double s2 = *scale2;
+  for (int e = threadIdx.x; e < n * n; e += 256) {
+    const int i = e / n, j = e - (e / n) * n;
+    double re = 0.0, im = 0.0;
+    for (int t = 0; t < m; ++t) {
+      // a = X[i][t], b = X[j][t] with X = H (rows) or H^T conj'd (cols)
+      float2 a, b;
+      if (rows) {
+        a = Hf[(int64_t)i * Nt + t], b = Hf[(int64_t)j * Nt + t];
+        // a * conj(b)
+        re += (double)a.x * b.x + (double)a.y * b.y;
+        im += (double)a.y * b.x - (double)a.x * b.y;
+      } else {
+        a = Hf[(int64_t)t * Nt + i], b = Hf[(int64_t)t * Nt + j];
+        // conj(a) * b
+        re += (double)a.x * b.x + (double)a.y * b.y;
+        im += (double)a.x * b.y - (double)a.y * b.x;
+      }
+    }
+    W[e] = make_double2(re * s2, im * s2);
+  }
+  __syncthreads();
+  __shared__ double logs[256];
+  for (int si = 0; si < Nsnr; ++si) {
+    const double g = pow(10.0, snr_db[si] / 10.0) / Nt;
+    for (int e = threadIdx.x; e < n * n; e += 256) {
+      const int i = e / n, j = e - (e / n) * n;
+      double2 w = W[e];
+      M[e] = make_double2((i == j ? 1.0 : 0.0) + g * w.x, g * w.y);
+    }
+    __syncthreads();
+    // right-looking Cholesky, lower triangle, in place
+    for (int j = 0; j < n; ++j) {
+      const double djj = sqrt(M[j * n + j].x);
+      __syncthreads();
+      for (int i = j + 1 + threadIdx.x; i < n; i += 256) {
+        double2 v = M[i * n + j];
+        M[i * n + j] = make_double2(v.x / djj, v.y / djj);
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) M[j * n + j] = make_double2(djj, 0.0);
+      const int rem = n - j - 1;
+      for (int e = threadIdx.x; e < rem * rem; e += 256) {
+        const int i = j + 1 + e / rem, l = j + 1 + (e - (e / rem) * rem);
+        if (l > i) continue;
+        const double2 a = M[i * n + j], b = M[l * n + j];
+        // M[i][l] -= a * conj(b)
+        double2 c = M[i * n + l];
+        c.x -= a.x * b.x + a.y * b.y;
+        c.y -= a.y * b.x - a.x * b.y;
+        M[i * n + l] = c;
+      }
+      __syncthreads();
+    }
+    double lg = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) lg += log2(M[i * n + i].x);
+    logs[threadIdx.x] = lg;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (threadIdx.x < o) logs[threadIdx.x] += logs[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) cf[(int64_t)si * gridDim.x + f] = 2.0 * logs[0];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_cap_mean(const double* __restrict__ cf, int Nf, int Nsnr,
+                                                  double* __restrict__ out) {
+  __shared__ double sm[256];
+  for (int si = 0; si < Nsnr; ++si) {
+    double s = 0.0;
+    for (int f = threadIdx.x; f < Nf; f += 256) s += cf[(int64_t)si * Nf + f];
+    sm[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[si] = sm[0] / Nf;
+    __syncthreads();
+  }
+}
+
+FieldArgs field_args(const ChannelArgs& a) { return FieldArgs{a.freq, a.atm_db, a.atm_deg, a.Nf, a.pol_tx, a.pol_rx}; }
+
+}  // namespace
+
+void run_channel(sbr_paths_s* ps, const ChannelArgs& a, float2* H64, double2* H128, hipStream_t s) {
+  const int Nt = ps->trace->Nt, Nr = ps->Nr;
+  const int64_t nseg = (int64_t)Nr * Nt;
+  SBR_CHECK(nseg < (int64_t(1) << 31), SBR_E_UNSUPPORTED, "too many (rx, tx) pairs");
+  { ::sbr::TimedLaunch tl_("channel", s); hipLaunchKernelGGL(k_channel, dim3((unsigned)nseg), dim3(kChanThreads), 0, s, ps->geo.as<double>(),
+                     geo_stride(ps->trace->K), ps->seg_start.as<int32_t>(), field_args(a), Nr, Nt, H64, H128,
+                     ps->power.as<double>()); }
+  SBR_LAUNCH_CHECK();
+  ps->have_power = true;
+}
+
+void run_path_field(sbr_paths_s* ps, const ChannelArgs& a, double2* out, hipStream_t s) {
+  const int64_t n = ps->n_paths;
+  if (n == 0 || a.Nf == 0) return;
+  { ::sbr::TimedLaunch tl_("path_field", s); hipLaunchKernelGGL(k_path_field, dim3(nblk(n * a.Nf, 256)), dim3(256), 0, s, ps->geo.as<double>(),
+                     geo_stride(ps->trace->K), n, field_args(a), out); }
+  SBR_LAUNCH_CHECK();
+}
+
+void run_stats(sbr_paths_s* ps, float* pg_db, float* tau, float* angles, hipStream_t s) {
+  const int64_t nseg = (int64_t)ps->Nr * ps->trace->Nt;
+  { ::sbr::TimedLaunch tl_("stats", s); hipLaunchKernelGGL(k_stats, dim3(nblk(nseg, 256)), dim3(256), 0, s, ps->seg_start.as<int32_t>(), nseg,
+                     ps->power.as<double>(), ps->info.as<double>(), ps->ang.as<float>(), pg_db, tau, angles); }
+  SBR_LAUNCH_CHECK();
+}
+
+void run_capacity(const float2* H, int Nf, int Nr, int Nt, const double* snr_db, int Nsnr, int normalize,
+                  double* C_out, hipStream_t s) {
+  const int n = std::min(Nr, Nt);
+  Buf frob, sc, work, cf;
+  frob.alloc((size_t)Nf * 8, s);
+  sc.alloc(8, s);
+  work.alloc((size_t)Nf * 2 * n * n * sizeof(double2), s);
+  cf.alloc((size_t)Nf * Nsnr * 8, s);
+  { ::sbr::TimedLaunch tl_("capacity", s); hipLaunchKernelGGL(k_cap_frob, dim3(Nf), dim3(256), 0, s, H, Nr, Nt, frob.as<double>()); }
+  { ::sbr::TimedLaunch tl_("capacity", s); hipLaunchKernelGGL(k_cap_scale, dim3(1), dim3(256), 0, s, frob.as<double>(), Nf, Nr, Nt, normalize,
+                     sc.as<double>()); }
+  { ::sbr::TimedLaunch tl_("capacity", s); hipLaunchKernelGGL(k_cap_logdet, dim3(Nf), dim3(256), 0, s, H, Nr, Nt, sc.as<double>(), snr_db, Nsnr,
+                     work.as<double2>(), cf.as<double>()); }
+  { ::sbr::TimedLaunch tl_("capacity", s); hipLaunchKernelGGL(k_cap_mean, dim3(1), dim3(256), 0, s, cf.as<double>(), Nf, Nsnr, C_out); }
+  SBR_LAUNCH_CHECK();
+  SBR_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace sbr

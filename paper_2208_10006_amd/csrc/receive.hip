@@ -1,0 +1,712 @@
+// receive.hip -- ray reception and effective-path extraction (Sec. II-A-3,
+// and the "pick out effective paths" of Sec. II-A-2).
+//
+//  1. replay:   every ray's FP64 chain is rebuilt from its hit chain (the
+//               per-ray record the trace kept) and each segment is tested
+//               against the receivers through an LBVH over the Rx points:
+//               captured when the closest approach lies inside the segment
+//               and within coeff * alpha * (unfolded distance) / sqrt(3).
+//  2. keys:     capture -> (rx*Nt + tx, 64-bit hash of (k, g_1..g_k));
+//               radix sort; duplicates (several rays, or both triangles of a
+//               wall, finding one geometric path) collapse to one key by an
+//               exact sequence comparison inside equal-hash runs.
+//  3. rebuild:  each key is rebuilt by the image method in FP64 (Sec. I) and
+//               kept when its reflection points lie on their faces, on the
+//               incidence side, and no triangle blocks a leg (any-hit LBVH
+//               traversal with FP64 triangle tests); the frequency-
+//               independent part of the field (polarisation chain, incidence
+//               cosines, materials) is stored for the channel kernels.
+//  4. order:    valid paths sorted by (rx, tx, delay); CSR per (rx, tx).
+#include <algorithm>
+#include <cmath>
+
+#include "sbr_device.hpp"
+#include "sbr_internal.hpp"
+
+namespace sbr {
+namespace {
+
+inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+
+struct ReplayParams {
+  GeoTables G;
+  int N, K, Nr;
+  int64_t T;
+  int64_t R, NR;
+  const double* tx;
+  const int32_t* seq;
+  const double4* tplane;
+  const float4* rnodes;
+  const uint32_t* rorder;
+  float rroot[6];
+  const double* rx;
+  double rc[3], rrad;  // Rx bounding sphere (FP64); FP32 Rx frame centred on rc
+  double rfac;         // coeff * alpha / sqrt(3)
+  uint32_t* ev_count;
+  uint64_t ev_cap;
+  uint32_t* ev_ray;
+  uint32_t* ev_qk;     // q << 5 | k
+};
+
+template <int STACK>
+__global__ __launch_bounds__(256) void k_replay_capture(const ReplayParams P) {
+  __shared__ int32_t stack_mem[256 / kWave][STACK][kWave];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int32_t* stk = &stack_mem[wv][0][lane];
+  const int64_t rid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (rid >= P.NR) return;
+  const int p = (int)(rid / P.R);
+  d3 o = ld3(P.tx + 3 * p);
+  d3 d = geo_dir(P.G, P.N, rid - (int64_t)p * P.R);
+  double L = 0.0;
+  const d3 rc = mk3(P.rc[0], P.rc[1], P.rc[2]);
+  for (int k = 0; k <= P.K; ++k) {
+    int32_t tri = P.seq[(int64_t)k * P.NR + rid];
+    if (tri >= P.T) tri = -1;  // defensive: chain entries are triangle ids or -1
+    double4 pl = make_double4(0, 0, 0, 0);
+    double tend = INFINITY;
+    if (tri >= 0) {
+      pl = P.tplane[tri];
+      tend = advance_t(pl, o, d);
+    }
+    // ---------------- capture test of segment (o, d, [0, tend], L)
+    // any capture has t* = (q - o).d <= |q - o| <= |o - rc| + rrad
+    const double thi = fmin(tend, norm(o - rc) + P.rrad);
+    if (thi >= 0.0) {
+      const double rmax = P.rfac * (L + thi);
+      const float3 org = make_float3((float)(o.x - rc.x), (float)(o.y - rc.y), (float)(o.z - rc.z));
+      const float3 dir = make_float3((float)d.x, (float)d.y, (float)d.z);
+      const float infl = (float)(rmax + 1e-5 * (fabs(o.x - rc.x) + fabs(o.y - rc.y) + fabs(o.z - rc.z) + thi) + 1e-6);
+      const float tmax = (float)thi * 1.00001f + 1e-6f;
+      auto safe_inv = [](float v) { return 1.0f / (fabsf(v) > 1e-20f ? v : copysignf(1e-20f, v)); };
+      const float3 inv = make_float3(safe_inv(dir.x), safe_inv(dir.y), safe_inv(dir.z));
+      auto box_hit = [&](float lx, float ly, float lz, float hx, float hy, float hz) {
+        lx -= infl, ly -= infl, lz -= infl, hx += infl, hy += infl, hz += infl;
+        const float t0x = (lx - org.x) * inv.x, t1x = (hx - org.x) * inv.x;
+        const float t0y = (ly - org.y) * inv.y, t1y = (hy - org.y) * inv.y;
+        const float t0z = (lz - org.z) * inv.z, t1z = (hz - org.z) * inv.z;
+        const float tmin = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
+        const float tmx = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
+        return tmin <= tmx * 1.0000004f;
+      };
+      auto leaf_test = [&](int32_t leaf) {
+        const int q = (int)P.rorder[leaf];
+        const d3 w = ld3(P.rx + 3 * q) - o;
+        const double ts = dot(w, d);
+        if (ts < 0.0 || ts > tend) return;
+        const double dist = norm(w - d * ts);
+        const double rad = P.rfac * (L + ts);
+        if (dist <= rad) {
+          const uint32_t e = atomicAdd(P.ev_count, 1u);
+          if (e < P.ev_cap) {
+            P.ev_ray[e] = (uint32_t)rid;
+            P.ev_qk[e] = ((uint32_t)q << 5) | (uint32_t)k;
+          }
+        }
+      };
+      if (box_hit(P.rroot[0], P.rroot[1], P.rroot[2], P.rroot[3], P.rroot[4], P.rroot[5])) {
+        int sp = 0;
+        int32_t node = 0;
+        while (true) {
+          const float4 n0 = P.rnodes[4 * node], n1 = P.rnodes[4 * node + 1], n2 = P.rnodes[4 * node + 2],
+                       n3 = P.rnodes[4 * node + 3];
+          bool hl = box_hit(n0.x, n0.y, n0.z, n0.w, n1.x, n1.y);
+          bool hr = box_hit(n1.z, n1.w, n2.x, n2.y, n2.z, n2.w);
+          const int32_t cl = __float_as_int(n3.x), cr = __float_as_int(n3.y);
+          if (hl && cl < 0) {
+            leaf_test(~cl);
+            hl = false;
+          }
+          // a single-receiver tree repeats leaf 0 with an empty right box
+          if (hr && cr < 0 && cr != cl) {
+            leaf_test(~cr);
+          }
+          if (cr < 0) hr = false;
+          if (hl && hr) {
+            stk[kWave * sp] = cr;
+            ++sp;
+            node = cl;
+          } else if (hl) {
+            node = cl;
+          } else if (hr) {
+            node = cr;
+          } else {
+            if (sp == 0) break;
+            --sp;
+            node = stk[kWave * sp];
+          }
+        }
+      }
+    }
+    if (tri < 0 || k == P.K) break;
+    o = o + d * tend;
+    L += tend;
+    d = reflect(d, pl);
+  }
+}
+
+// ---------------------------------------------------------------- keys
+__device__ inline uint64_t mix64(uint64_t h, uint64_t v) {
+  h ^= v + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
+  h ^= h >> 31;
+  h *= 0xbf58476d1ce4e5b9ull;
+  h ^= h >> 29;
+  return h;
+}
+
+struct KeyParams {
+  const uint32_t* ev_ray;
+  const uint32_t* ev_qk;
+  const int32_t* seq;
+  const int32_t* tgroup;
+  int64_t R, NR;
+  int Nt;
+  int64_t n;
+};
+
+__device__ inline int ev_groups(const KeyParams& P, int64_t e, int32_t* g) {
+  const uint32_t rid = P.ev_ray[e];
+  const int k = (int)(P.ev_qk[e] & 31u);
+  for (int i = 0; i < k; ++i) g[i] = P.tgroup[P.seq[(int64_t)i * P.NR + rid]];
+  return k;
+}
+
+__global__ void k_event_keys(const KeyParams P, uint64_t* __restrict__ hkey, uint32_t* __restrict__ vals,
+                             uint64_t* __restrict__ segkey) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= P.n) return;
+  int32_t g[SBR_MAX_BOUNCES];
+  const int k = ev_groups(P, e, g);
+  uint64_t h = mix64(0x5bd1e995ull, (uint64_t)k);
+  for (int i = 0; i < k; ++i) h = mix64(h, (uint64_t)(uint32_t)g[i]);
+  const uint32_t rid = P.ev_ray[e];
+  const int64_t p = rid / P.R;
+  const uint64_t q = P.ev_qk[e] >> 5;
+  hkey[e] = h;
+  vals[e] = (uint32_t)e;
+  segkey[e] = q * (uint64_t)P.Nt + (uint64_t)p;
+}
+
+// head flag: first occurrence of its exact key within its (segment, hash) run
+__global__ void k_unique_heads(const KeyParams P, const uint32_t* __restrict__ perm,
+                               const uint64_t* __restrict__ seg_sorted, const uint64_t* __restrict__ hkey,
+                               uint32_t* __restrict__ head) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P.n) return;
+  const uint32_t e = perm[i];
+  uint32_t is_head = 1;
+  int32_t g[SBR_MAX_BOUNCES], g2[SBR_MAX_BOUNCES];
+  int k = -1;
+  for (int64_t j = i - 1; j >= 0; --j) {
+    const uint32_t e2 = perm[j];
+    if (seg_sorted[j] != seg_sorted[i] || hkey[e2] != hkey[e]) break;
+    if (k < 0) k = ev_groups(P, e, g);
+    const int k2 = ev_groups(P, e2, g2);
+    bool same = k2 == k;
+    for (int t = 0; same && t < k; ++t) same = g[t] == g2[t];
+    if (same) {
+      is_head = 0;
+      break;
+    }
+  }
+  head[i] = is_head;
+}
+
+__global__ void k_compact_heads(const uint32_t* __restrict__ perm, const uint32_t* __restrict__ head,
+                                const uint32_t* __restrict__ pos, int64_t n, uint32_t* __restrict__ key_event) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (head[i]) key_event[pos[i]] = perm[i];
+}
+
+// ---------------------------------------------------------------- rebuild
+struct RebuildParams {
+  KeyParams kp;
+  const uint32_t* key_event;
+  int64_t n_keys;
+  int K, stride;
+  const double* tx;
+  const double* rx;
+  const double4* gplane;
+  const float4* gmat;
+  const int32_t* gstart;
+  const int32_t* gtri;
+  const double* tri64;
+  const float4* nodes;
+  const float4* tri32;
+  float root[6];
+  double cx, cy, cz;
+  int has_bvh;
+  // outputs (indexed by key)
+  uint32_t* valid;
+  double* geo;
+  double* info;    // length, delay
+  float* ang;      // 4
+  int32_t* key;    // 4 + K: tx, rx, k, flags, g...
+  uint64_t* seg;
+};
+
+// Point-in-triangle for a point on the triangle's plane: the three edge
+// functions, normalised by |n|^2, are its barycentric coordinates.  Inclusive
+// with a 1e-9 margin so that a reflection point on an edge shared by two
+// triangles of one face group is never rejected by both through rounding.
+__device__ inline bool in_triangle(const double* t, d3 x) {
+  const d3 a = ld3(t), b = ld3(t + 3), c = ld3(t + 6);
+  const d3 n = cross(b - a, c - a);
+  const double inv = 1.0 / dot(n, n);
+  const double w0 = dot(n, cross(b - a, x - a)) * inv;
+  const double w1 = dot(n, cross(c - b, x - b)) * inv;
+  const double w2 = dot(n, cross(a - c, x - c)) * inv;
+  return w0 >= -1e-9 && w1 >= -1e-9 && w2 >= -1e-9;
+}
+
+// any triangle (outside groups ga, gb) crossing the open leg a -> b at s in (1e-9, 1-1e-9)
+template <int STACK>
+__device__ bool leg_blocked(const RebuildParams& P, int32_t* stk, d3 a, d3 b, int ga, int gb) {
+  if (!P.has_bvh) return false;
+  const d3 D = b - a;
+  const d3 ac = a - mk3(P.cx, P.cy, P.cz);
+  auto inv1 = [](double v) { return 1.0 / (fabs(v) > 1e-300 ? v : copysign(1e-300, v)); };
+  const d3 inv = mk3(inv1(D.x), inv1(D.y), inv1(D.z));
+  auto box_hit = [&](double lx, double ly, double lz, double hx, double hy, double hz) {
+    const double t0x = (lx - ac.x) * inv.x, t1x = (hx - ac.x) * inv.x;
+    const double t0y = (ly - ac.y) * inv.y, t1y = (hy - ac.y) * inv.y;
+    const double t0z = (lz - ac.z) * inv.z, t1z = (hz - ac.z) * inv.z;
+    const double tmin = fmax(fmax(fmin(t0x, t1x), fmin(t0y, t1y)), fmax(fmin(t0z, t1z), 0.0));
+    const double tmx = fmin(fmin(fmax(t0x, t1x), fmax(t0y, t1y)), fmin(fmax(t0z, t1z), 1.0));
+    return tmin <= tmx * (1.0 + 1e-12) + 1e-300;
+  };
+  auto tri_block = [&](int32_t leaf) -> bool {
+    const int grp = __float_as_int(P.tri32[3 * leaf + 2].w);
+    if (grp == ga || grp == gb) return false;
+    const int orig = __float_as_int(P.tri32[3 * leaf].w);
+    const double* t = P.tri64 + 9 * (int64_t)orig;
+    const d3 v0 = ld3(t), e1 = ld3(t + 3) - v0, e2 = ld3(t + 6) - v0;
+    const d3 pv = cross(D, e2);
+    const double det = dot(e1, pv);
+    if (det == 0.0) return false;
+    const double inv_det = 1.0 / det;
+    const d3 tv = a - v0;
+    const double u = dot(tv, pv) * inv_det;
+    if (u < -1e-9 || u > 1.0 + 1e-9) return false;
+    const d3 qv = cross(tv, e1);
+    const double v = dot(D, qv) * inv_det;
+    if (v < -1e-9 || u + v > 1.0 + 1e-9) return false;  // crack-free margin, as for the faces
+    const double s = dot(e2, qv) * inv_det;
+    return s > 1e-9 && s < 1.0 - 1e-9;
+  };
+  if (!box_hit(P.root[0], P.root[1], P.root[2], P.root[3], P.root[4], P.root[5])) return false;
+  int sp = 0;
+  int32_t node = 0;
+  while (true) {
+    const float4 n0 = P.nodes[4 * node], n1 = P.nodes[4 * node + 1], n2 = P.nodes[4 * node + 2],
+                 n3 = P.nodes[4 * node + 3];
+    bool hl = box_hit(n0.x, n0.y, n0.z, n0.w, n1.x, n1.y);
+    bool hr = box_hit(n1.z, n1.w, n2.x, n2.y, n2.z, n2.w);
+    const int32_t cl = __float_as_int(n3.x), cr = __float_as_int(n3.y);
+    if (hl && cl < 0) {
+      if (tri_block(~cl)) return true;
+      hl = false;
+    }
+    if (hr && cr < 0) {
+      if (cr != cl && tri_block(~cr)) return true;
+      hr = false;
+    }
+    if (hl && hr) {
+      stk[kWave * sp] = cr;
+      ++sp;
+      node = cl;
+    } else if (hl) {
+      node = cl;
+    } else if (hr) {
+      node = cr;
+    } else {
+      if (sp == 0) return false;
+      --sp;
+      node = stk[kWave * sp];
+    }
+  }
+}
+
+__device__ inline d3 mirror(d3 x, double4 pl) {
+  const d3 n = mk3(pl.x, pl.y, pl.z);
+  return x - n * (2.0 * (dot(n, x) - pl.w));
+}
+
+template <int STACK>
+__global__ __launch_bounds__(128) void k_rebuild(const RebuildParams P) {
+  __shared__ int32_t stack_mem[128 / kWave][STACK][kWave];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int32_t* stk = &stack_mem[wv][0][lane];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P.n_keys) return;
+  const uint32_t e = P.key_event[i];
+  int32_t g[SBR_MAX_BOUNCES];
+  const int k = ev_groups(P.kp, e, g);
+  const uint32_t rid = P.kp.ev_ray[e];
+  const int p = (int)(rid / P.kp.R);
+  const int q = (int)(P.kp.ev_qk[e] >> 5);
+  int32_t* kk = P.key + i * (4 + P.K);
+  kk[0] = p, kk[1] = q, kk[2] = k, kk[3] = 0;
+  for (int t = 0; t < P.K; ++t) kk[4 + t] = t < k ? g[t] : -1;
+  P.seg[i] = (uint64_t)q * (uint64_t)P.kp.Nt + (uint64_t)p;
+  const d3 T = ld3(P.tx + 3 * p), Rq = ld3(P.rx + 3 * q);
+  // images S_1..S_k
+  d3 S[SBR_MAX_BOUNCES + 1];
+  S[0] = T;
+  for (int t = 1; t <= k; ++t) S[t] = mirror(S[t - 1], P.gplane[g[t - 1]]);
+  d3 X[SBR_MAX_BOUNCES + 2];
+  X[0] = T;
+  X[k + 1] = Rq;
+  bool ok = true;
+  for (int t = k; t >= 1 && ok; --t) {
+    const double4 pl = P.gplane[g[t - 1]];
+    const d3 n = mk3(pl.x, pl.y, pl.z);
+    const d3 D = X[t + 1] - S[t];
+    const double den = dot(n, D);
+    if (den == 0.0) {
+      ok = false;
+      break;
+    }
+    X[t] = S[t] + D * ((pl.w - dot(n, S[t])) / den);
+  }
+  for (int t = 1; t <= k && ok; ++t) {
+    const int gi = g[t - 1];
+    bool inside = false;
+    for (int j = P.gstart[gi]; j < P.gstart[gi + 1] && !inside; ++j)
+      inside = in_triangle(P.tri64 + 9 * (int64_t)P.gtri[j], X[t]);
+    const double4 pl = P.gplane[gi];
+    const d3 n = mk3(pl.x, pl.y, pl.z);
+    const double sa = dot(n, X[t - 1]) - pl.w, sb = dot(n, X[t + 1]) - pl.w;
+    ok = inside && (sa * sb > 0.0);
+  }
+  for (int t = 1; t <= k + 1 && ok; ++t) {
+    const int ga = t >= 2 ? g[t - 2] : -1;
+    const int gb = t <= k ? g[t - 1] : -1;
+    ok = !leg_blocked<STACK>(P, stk, X[t - 1], X[t], ga, gb);
+  }
+  P.valid[i] = ok ? 1u : 0u;
+  if (!ok) return;
+  double len = 0.0;
+  for (int t = 1; t <= k + 1; ++t) len += norm(X[t] - X[t - 1]);
+  P.info[2 * i] = len;
+  P.info[2 * i + 1] = len / kC0;
+  const d3 kdep = normalize(X[1] - X[0]);
+  const d3 toward = normalize(X[k] - X[k + 1]);
+  P.ang[4 * i] = (float)(atan2(kdep.y, kdep.x) * (180.0 / kPi));
+  P.ang[4 * i + 1] = (float)(asin(fmax(-1.0, fmin(1.0, kdep.z))) * (180.0 / kPi));
+  P.ang[4 * i + 2] = (float)(atan2(toward.y, toward.x) * (180.0 / kPi));
+  P.ang[4 * i + 3] = (float)(asin(fmax(-1.0, fmin(1.0, toward.z))) * (180.0 / kPi));
+  // ---------------- frequency-independent polarisation chain
+  double* G = P.geo + i * (int64_t)P.stride;
+  for (int t = 0; t < P.stride; ++t) G[t] = 0.0;
+  G[0] = len;
+  G[1] = k;
+  d3 th0, ph0;
+  sph_hats(kdep, &th0, &ph0);
+  if (k == 0) {
+    // e_rx . e_tx with both ends seeing the same direction
+    G[10] = dot(th0, th0), G[11] = dot(th0, ph0), G[12] = dot(ph0, th0), G[13] = dot(ph0, ph0);
+    return;
+  }
+  d3 kin = kdep, s_prev{}, pout_prev{};
+  for (int b = 1; b <= k; ++b) {
+    const double4 pl = P.gplane[g[b - 1]];
+    d3 n = mk3(pl.x, pl.y, pl.z);
+    if (dot(kin, n) > 0.0) n = n * -1.0;
+    const double cs = -dot(kin, n);
+    d3 s = cross(kin, n);
+    const double sn = norm(s);
+    if (sn < 1e-15) {
+      const d3 ref = fabs(kin.z) < 0.9 ? mk3(0, 0, 1) : mk3(1, 0, 0);
+      s = normalize(cross(kin, ref));
+    } else {
+      s = s * (1.0 / sn);
+    }
+    const d3 pin = cross(s, kin);
+    const d3 kout = kin - n * (2.0 * dot(kin, n));
+    const d3 pout = cross(s, kout);
+    const float4 m = P.gmat[g[b - 1]];
+    double* B = G + kGeoHead + kGeoPerBounce * (b - 1);
+    B[0] = cs, B[1] = m.x, B[2] = m.y, B[3] = m.z;
+    if (b == 1) {
+      G[2] = dot(th0, s), G[3] = dot(th0, pin), G[4] = dot(ph0, s), G[5] = dot(ph0, pin);
+    } else {
+      double* Bp = G + kGeoHead + kGeoPerBounce * (b - 2);
+      Bp[4] = dot(s_prev, s), Bp[5] = dot(pout_prev, s), Bp[6] = dot(s_prev, pin), Bp[7] = dot(pout_prev, pin);
+    }
+    s_prev = s, pout_prev = pout;
+    kin = kout;
+  }
+  d3 thr, phr;
+  sph_hats(kin, &thr, &phr);
+  G[6] = dot(thr, s_prev), G[7] = dot(thr, pout_prev), G[8] = dot(phr, s_prev), G[9] = dot(phr, pout_prev);
+}
+
+// ---------------------------------------------------------------- ordering
+__global__ void k_valid_keys(const uint32_t* __restrict__ valid, const uint32_t* __restrict__ pos,
+                             const uint64_t* __restrict__ seg, const double* __restrict__ info, int64_t n,
+                             uint64_t* __restrict__ dkey, uint32_t* __restrict__ didx, uint64_t* __restrict__ vseg) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || !valid[i]) return;
+  const uint32_t j = pos[i];
+  dkey[j] = (uint64_t)__double_as_longlong(info[2 * i + 1]);  // delay >= 0: bit order = numeric order
+  didx[j] = (uint32_t)i;
+  vseg[j] = seg[i];
+}
+
+__global__ void k_gather_paths(const uint32_t* __restrict__ order, int64_t n, int stride, int K,
+                               const double* __restrict__ geo_in, const double* __restrict__ info_in,
+                               const float* __restrict__ ang_in, const int32_t* __restrict__ key_in,
+                               double* __restrict__ geo, double* __restrict__ info, float* __restrict__ ang,
+                               int32_t* __restrict__ key, uint64_t* __restrict__ seg_in, uint64_t* __restrict__ seg) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t s = order[i];
+  for (int t = 0; t < stride; ++t) geo[i * stride + t] = geo_in[(int64_t)s * stride + t];
+  info[2 * i] = info_in[2 * s], info[2 * i + 1] = info_in[2 * s + 1];
+  for (int t = 0; t < 4; ++t) ang[4 * i + t] = ang_in[4 * s + t];
+  for (int t = 0; t < 4 + K; ++t) key[i * (4 + K) + t] = key_in[(int64_t)s * (4 + K) + t];
+  seg[i] = seg_in[s];
+}
+
+__global__ void k_seg_start(const uint64_t* __restrict__ seg, int64_t n, int64_t nseg, int32_t* __restrict__ start) {
+  const int64_t sidx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (sidx > nseg) return;
+  int64_t lo = 0, hi = n;  // first i with seg[i] >= sidx
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (seg[mid] < (uint64_t)sidx) lo = mid + 1;
+    else hi = mid;
+  }
+  start[sidx] = (int32_t)lo;
+}
+
+int bits_for(uint64_t v) {
+  int b = 0;
+  while (b < 64 && (v >> b) != 0) ++b;
+  return b;
+}
+
+}  // namespace
+
+void run_receive(sbr_paths_s* ps, hipStream_t s) {
+  sbr_trace_s* tr = ps->trace;
+  sbr_scene_s* sc = tr->scene;
+  const int Nr = ps->Nr, Nt = tr->Nt, K = tr->K;
+  // ---------------- Rx LBVH (FP32 boxes in a frame centred on the Rx bounding sphere)
+  std::vector<double> hrx(3 * (size_t)Nr);
+  SBR_HIP(hipMemcpyAsync(hrx.data(), ps->rx.p, hrx.size() * 8, hipMemcpyDeviceToHost, s));
+  SBR_HIP(hipStreamSynchronize(s));
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int q = 0; q < Nr; ++q)
+    for (int c = 0; c < 3; ++c) lo[c] = std::min(lo[c], hrx[3 * q + c]), hi[c] = std::max(hi[c], hrx[3 * q + c]);
+  double rc[3], rrad = 0.0;
+  for (int c = 0; c < 3; ++c) rc[c] = 0.5 * (lo[c] + hi[c]);
+  for (int q = 0; q < Nr; ++q) {
+    double d2 = 0;
+    for (int c = 0; c < 3; ++c) d2 += (hrx[3 * q + c] - rc[c]) * (hrx[3 * q + c] - rc[c]);
+    rrad = std::max(rrad, std::sqrt(d2));
+  }
+  rrad = rrad * (1.0 + 1e-12) + 1e-12;
+  std::vector<float> blo(3 * (size_t)Nr), bhi(3 * (size_t)Nr);
+  float flo[3] = {1e30f, 1e30f, 1e30f}, fhi[3] = {-1e30f, -1e30f, -1e30f};
+  for (int q = 0; q < Nr; ++q)
+    for (int c = 0; c < 3; ++c) {
+      const double v = hrx[3 * q + c] - rc[c];
+      blo[3 * q + c] = std::nextafter((float)v, -INFINITY);
+      bhi[3 * q + c] = std::nextafter((float)v, INFINITY);
+      flo[c] = std::min(flo[c], blo[3 * q + c]);
+      fhi[c] = std::max(fhi[c], bhi[3 * q + c]);
+    }
+  Buf dlo, dhi, rnodes, rorder, rroot;
+  dlo.alloc(blo.size() * 4, s);
+  dhi.alloc(bhi.size() * 4, s);
+  SBR_HIP(hipMemcpyAsync(dlo.p, blo.data(), blo.size() * 4, hipMemcpyHostToDevice, s));
+  SBR_HIP(hipMemcpyAsync(dhi.p, bhi.data(), bhi.size() * 4, hipMemcpyHostToDevice, s));
+  rnodes.alloc((size_t)std::max(Nr - 1, 1) * 64, s);
+  rorder.alloc((size_t)Nr * 4, s);
+  rroot.alloc(32, s);
+  const int rdepth =
+      build_lbvh(dlo.as<float>(), dhi.as<float>(), Nr, flo, fhi, BvhOut{rnodes.as<float4>(), rorder.as<uint32_t>(),
+                                                                         rroot.as<float>()}, s);
+  SBR_CHECK(rdepth <= 64, SBR_E_UNSUPPORTED, "receiver tree depth %d", rdepth);
+  float hroot[8];
+  SBR_HIP(hipMemcpyAsync(hroot, rroot.p, 24, hipMemcpyDeviceToHost, s));
+  SBR_HIP(hipStreamSynchronize(s));
+
+  // ---------------- replay + capture (grow the event buffer and retry on overflow)
+  ReplayParams P{};
+  P.G = geo_tables();
+  P.N = tr->N, P.K = K, P.Nr = Nr, P.R = tr->R, P.NR = tr->NR;
+  P.T = sc->T;
+  P.tx = tr->tx.as<double>();
+  P.seq = tr->seq.as<int32_t>();
+  P.tplane = sc->tplane.as<double4>();
+  P.rnodes = rnodes.as<float4>();
+  P.rorder = rorder.as<uint32_t>();
+  for (int k = 0; k < 6; ++k) P.rroot[k] = hroot[k];
+  P.rx = ps->rx.as<double>();
+  for (int c = 0; c < 3; ++c) P.rc[c] = rc[c];
+  P.rrad = rrad;
+  P.rfac = ps->coeff * ps->alpha / std::sqrt(3.0);
+  Buf cnt;
+  cnt.alloc(16, s);
+  uint64_t cap = std::max<uint64_t>(1u << 20, (uint64_t)tr->NR / 8);
+  Buf& ev_ray = ps->ev_ray;
+  Buf& ev_qk = ps->ev_qk;
+  uint32_t n_ev = 0;
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    ev_ray.alloc(cap * 4, s);
+    ev_qk.alloc(cap * 4, s);
+    fill_u32(cnt.as<uint32_t>(), 0, 1, s);
+    P.ev_count = cnt.as<uint32_t>();
+    P.ev_cap = cap;
+    P.ev_ray = ev_ray.as<uint32_t>();
+    P.ev_qk = ev_qk.as<uint32_t>();
+    const unsigned g = nblk(tr->NR, 256);
+    if (rdepth <= 16)
+      { ::sbr::TimedLaunch tl_("replay_capture", s); hipLaunchKernelGGL(k_replay_capture<16>, dim3(g), dim3(256), 0, s, P); }
+    else if (rdepth <= 32)
+      { ::sbr::TimedLaunch tl_("replay_capture", s); hipLaunchKernelGGL(k_replay_capture<32>, dim3(g), dim3(256), 0, s, P); }
+    else
+      { ::sbr::TimedLaunch tl_("replay_capture", s); hipLaunchKernelGGL(k_replay_capture<64>, dim3(g), dim3(256), 0, s, P); }
+    SBR_LAUNCH_CHECK();
+    SBR_HIP(hipMemcpyAsync(&n_ev, cnt.p, 4, hipMemcpyDeviceToHost, s));
+    SBR_HIP(hipStreamSynchronize(s));
+    if (n_ev <= cap) break;
+    cap = (uint64_t)n_ev + n_ev / 8 + 1024;
+  }
+  SBR_CHECK(n_ev <= cap, SBR_E_CAPACITY, "capture events overflow (%u)", n_ev);
+  SBR_CHECK(n_ev < 0x7fffffffu, SBR_E_UNSUPPORTED, "too many capture events (%u)", n_ev);
+  ps->n_events = n_ev;
+  const int64_t E = n_ev;
+  const int stride = geo_stride(K);
+  ps->n_keys = 0;
+  ps->n_paths = 0;
+  const int64_t nseg = (int64_t)Nr * Nt;
+  ps->seg_start.alloc((size_t)(nseg + 1) * 4, s);
+  if (E == 0) {
+    fill_u32(ps->seg_start.as<uint32_t>(), 0, nseg + 1, s);
+    return;
+  }
+  // ---------------- keys, sort by (segment, hash), exact dedup
+  KeyParams kp{ev_ray.as<uint32_t>(), ev_qk.as<uint32_t>(), tr->seq.as<int32_t>(), sc->tgroup.as<int32_t>(),
+               tr->R, tr->NR, Nt, E};
+  Buf hk, hk2, v1, v2, sk, sk2, temp;
+  hk.alloc(E * 8, s), hk2.alloc(E * 8, s), v1.alloc(E * 4, s), v2.alloc(E * 4, s);
+  sk.alloc(E * 8, s), sk2.alloc(E * 8, s);
+  temp.alloc(std::max(radix_sort_temp_bytes(E), scan_temp_bytes(E)), s);
+  { ::sbr::TimedLaunch tl_("keys", s); hipLaunchKernelGGL(k_event_keys, dim3(nblk(E, 256)), dim3(256), 0, s, kp, hk.as<uint64_t>(), v1.as<uint32_t>(),
+                     sk.as<uint64_t>()); }
+  SBR_LAUNCH_CHECK();
+  // stage 1: by hash (64 bits) -> permutation in v2
+  radix_sort_pairs(hk.as<uint64_t>(), v1.as<uint32_t>(), hk2.as<uint64_t>(), v2.as<uint32_t>(), E, 0, 64, temp.p, s);
+  // hk was clobbered: rebuild hash per event
+  { ::sbr::TimedLaunch tl_("keys", s); hipLaunchKernelGGL(k_event_keys, dim3(nblk(E, 256)), dim3(256), 0, s, kp, hk.as<uint64_t>(), v1.as<uint32_t>(),
+                     sk.as<uint64_t>()); }
+  // stage 2: stable by segment
+  gather_u64(sk.as<uint64_t>(), v2.as<uint32_t>(), sk2.as<uint64_t>(), E, s);
+  const int sbits = std::max(1, bits_for((uint64_t)nseg));
+  radix_sort_pairs(sk2.as<uint64_t>(), v2.as<uint32_t>(), hk2.as<uint64_t>(), v1.as<uint32_t>(), E, 0, sbits, temp.p,
+                   s);
+  // now: v1 = event permutation, hk2 = sorted segment ids, hk = hash per event
+  Buf head, pos, tot;
+  head.alloc(E * 4, s), pos.alloc(E * 4, s), tot.alloc(8, s);
+  { ::sbr::TimedLaunch tl_("keys", s); hipLaunchKernelGGL(k_unique_heads, dim3(nblk(E, 256)), dim3(256), 0, s, kp, v1.as<uint32_t>(), hk2.as<uint64_t>(),
+                     hk.as<uint64_t>(), head.as<uint32_t>()); }
+  SBR_LAUNCH_CHECK();
+  exclusive_scan_u32(head.as<uint32_t>(), pos.as<uint32_t>(), E, tot.as<uint32_t>(), temp.p, s);
+  uint32_t n_keys = 0;
+  SBR_HIP(hipMemcpyAsync(&n_keys, tot.p, 4, hipMemcpyDeviceToHost, s));
+  SBR_HIP(hipStreamSynchronize(s));
+  ps->n_keys = n_keys;
+  Buf key_event;
+  key_event.alloc((size_t)n_keys * 4, s);
+  { ::sbr::TimedLaunch tl_("keys", s); hipLaunchKernelGGL(k_compact_heads, dim3(nblk(E, 256)), dim3(256), 0, s, v1.as<uint32_t>(), head.as<uint32_t>(),
+                     pos.as<uint32_t>(), E, key_event.as<uint32_t>()); }
+  SBR_LAUNCH_CHECK();
+  // ---------------- exact rebuild + validation
+  const int64_t nk = n_keys;
+  Buf valid, geo, info, ang, key, seg;
+  valid.alloc(nk * 4, s), geo.alloc(nk * stride * 8, s), info.alloc(nk * 16, s), ang.alloc(nk * 16, s);
+  key.alloc(nk * (4 + K) * 4, s), seg.alloc(nk * 8, s);
+  RebuildParams RP{};
+  RP.kp = kp;
+  RP.key_event = key_event.as<uint32_t>();
+  RP.n_keys = nk;
+  RP.K = K;
+  RP.stride = stride;
+  RP.tx = tr->tx.as<double>();
+  RP.rx = ps->rx.as<double>();
+  RP.gplane = sc->gplane.as<double4>();
+  RP.gmat = sc->gmat.as<float4>();
+  RP.gstart = sc->gstart.as<int32_t>();
+  RP.gtri = sc->gtri.as<int32_t>();
+  RP.tri64 = sc->tri64.as<double>();
+  RP.nodes = sc->nodes.as<float4>();
+  RP.tri32 = sc->tri32.as<float4>();
+  for (int k = 0; k < 6; ++k) RP.root[k] = sc->root_host[k];
+  RP.cx = sc->center[0], RP.cy = sc->center[1], RP.cz = sc->center[2];
+  RP.has_bvh = sc->T > 0;
+  RP.valid = valid.as<uint32_t>();
+  RP.geo = geo.as<double>();
+  RP.info = info.as<double>();
+  RP.ang = ang.as<float>();
+  RP.key = key.as<int32_t>();
+  RP.seg = seg.as<uint64_t>();
+  {
+    const unsigned g = nblk(nk, 128);
+    const int depth = sc->bvh_depth;
+    if (depth <= 16)
+      { ::sbr::TimedLaunch tl_("rebuild", s); hipLaunchKernelGGL(k_rebuild<16>, dim3(g), dim3(128), 0, s, RP); }
+    else if (depth <= 32)
+      { ::sbr::TimedLaunch tl_("rebuild", s); hipLaunchKernelGGL(k_rebuild<32>, dim3(g), dim3(128), 0, s, RP); }
+    else
+      { ::sbr::TimedLaunch tl_("rebuild", s); hipLaunchKernelGGL(k_rebuild<64>, dim3(g), dim3(128), 0, s, RP); }
+    SBR_LAUNCH_CHECK();
+  }
+  exclusive_scan_u32(valid.as<uint32_t>(), pos.as<uint32_t>(), nk, tot.as<uint32_t>(), temp.p, s);
+  uint32_t n_paths = 0;
+  SBR_HIP(hipMemcpyAsync(&n_paths, tot.p, 4, hipMemcpyDeviceToHost, s));
+  SBR_HIP(hipStreamSynchronize(s));
+  ps->n_paths = n_paths;
+  const int64_t np = n_paths;
+  ps->geo.alloc(std::max<int64_t>(np, 1) * stride * 8, s);
+  ps->info.alloc(std::max<int64_t>(np, 1) * 16, s);
+  ps->ang.alloc(std::max<int64_t>(np, 1) * 16, s);
+  ps->key.alloc(std::max<int64_t>(np, 1) * (4 + K) * 4, s);
+  ps->power.alloc(std::max<int64_t>(np, 1) * 8, s);
+  if (np == 0) {
+    fill_u32(ps->seg_start.as<uint32_t>(), 0, nseg + 1, s);
+    return;
+  }
+  // ---------------- order by (segment, delay)
+  Buf dk, dk2, di, di2, vseg, vseg2, fseg;
+  dk.alloc(np * 8, s), dk2.alloc(np * 8, s), di.alloc(np * 4, s), di2.alloc(np * 4, s);
+  vseg.alloc(np * 8, s), vseg2.alloc(np * 8, s), fseg.alloc(np * 8, s);
+  { ::sbr::TimedLaunch tl_("order", s); hipLaunchKernelGGL(k_valid_keys, dim3(nblk(nk, 256)), dim3(256), 0, s, valid.as<uint32_t>(), pos.as<uint32_t>(),
+                     seg.as<uint64_t>(), info.as<double>(), nk, dk.as<uint64_t>(), di.as<uint32_t>(),
+                     vseg.as<uint64_t>()); }
+  SBR_LAUNCH_CHECK();
+  Buf ptemp;
+  ptemp.alloc(radix_sort_temp_bytes(np), s);
+  radix_sort_pairs(dk.as<uint64_t>(), di.as<uint32_t>(), dk2.as<uint64_t>(), di2.as<uint32_t>(), np, 0, 64, ptemp.p, s);
+  // segment of each delay-sorted entry: seg[di2[i]] (seg indexed by key)
+  gather_u64(seg.as<uint64_t>(), di2.as<uint32_t>(), vseg2.as<uint64_t>(), np, s);
+  radix_sort_pairs(vseg2.as<uint64_t>(), di2.as<uint32_t>(), vseg.as<uint64_t>(), di.as<uint32_t>(), np, 0, sbits,
+                   ptemp.p, s);
+  // di = key index of each final path
+  { ::sbr::TimedLaunch tl_("order", s); hipLaunchKernelGGL(k_gather_paths, dim3(nblk(np, 256)), dim3(256), 0, s, di.as<uint32_t>(), np, stride, K,
+                     geo.as<double>(), info.as<double>(), ang.as<float>(), key.as<int32_t>(), ps->geo.as<double>(),
+                     ps->info.as<double>(), ps->ang.as<float>(), ps->key.as<int32_t>(), seg.as<uint64_t>(),
+                     fseg.as<uint64_t>()); }
+  SBR_LAUNCH_CHECK();
+  { ::sbr::TimedLaunch tl_("order", s); hipLaunchKernelGGL(k_seg_start, dim3(nblk(nseg + 1, 256)), dim3(256), 0, s, fseg.as<uint64_t>(), np, nseg,
+                     ps->seg_start.as<int32_t>()); }
+  SBR_LAUNCH_CHECK();
+  SBR_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace sbr

@@ -1,0 +1,891 @@
+// sbr_api.hip -- the C-ABI of libsbr: handles, validation, host-side face
+// grouping, buffer management and the order of kernel launches.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <unordered_map>
+#include <vector>
+
+#include "sbr_device.hpp"
+#include "sbr_internal.hpp"
+
+namespace sbr {
+
+static thread_local std::string g_err;
+
+void set_error(const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+
+void Buf::alloc(size_t n, hipStream_t s) {
+  reset();
+  stream = s;
+  bytes = n;
+  if (n == 0) n = 16;
+  hipError_t e = hipMallocAsync(&p, n, s);
+  if (e != hipSuccess) {
+    p = nullptr;
+    bytes = 0;
+    set_error("device allocation of %zu bytes failed: %s", n, hipGetErrorString(e));
+    throw Error{SBR_E_OUT_OF_MEMORY};
+  }
+}
+
+void Buf::reset() {
+  if (p) (void)hipFreeAsync(p, stream);
+  p = nullptr;
+  bytes = 0;
+}
+
+thread_local Prof* g_prof = nullptr;
+
+TimedLaunch::TimedLaunch(const char* n, hipStream_t st) : name(n), s(st) {
+  if (g_prof && g_prof->enabled) {
+    if (hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) {
+      (void)hipEventRecord(a, s);
+    } else {
+      a = b = nullptr;
+    }
+  }
+}
+TimedLaunch::~TimedLaunch() {
+  if (a && b && g_prof) {
+    (void)hipEventRecord(b, s);
+    g_prof->pending.push_back(Prof::Pending{name, a, b});
+  }
+}
+void Prof::resolve() {
+  for (auto& p : pending) {
+    float ms = 0.0f;
+    (void)hipEventSynchronize(p.b);
+    (void)hipEventElapsedTime(&ms, p.a, p.b);
+    bool found = false;
+    for (auto& e : acc)
+      if (e.first == p.name) {
+        e.second.first += ms;
+        e.second.second += 1;
+        found = true;
+      }
+    if (!found) acc.push_back({p.name, {(double)ms, 1}});
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  pending.clear();
+}
+void Prof::clear() {
+  resolve();
+  acc.clear();
+}
+
+void retain(Handle* h) { h->refs.fetch_add(1); }
+void release(Handle* h) {
+  if (h && h->refs.fetch_sub(1) == 1) delete h;
+}
+
+namespace {
+
+inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+// run f, mapping exceptions to status codes
+template <class F>
+sbr_status guard(F&& f) {
+  try {
+    (void)hipGetLastError();  // a launch check must only see errors of this call
+    f();
+    return SBR_OK;
+  } catch (const Error& e) {
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return SBR_E_OUT_OF_MEMORY;
+  } catch (...) {
+    set_error("unexpected internal error");
+    return SBR_E_DEVICE;
+  }
+}
+
+template <class H>
+H* check_handle(void* p, int kind, const char* what) {
+  SBR_CHECK(p != nullptr, SBR_E_INVALID_ARG, "%s handle is NULL", what);
+  SBR_CHECK(static_cast<Handle*>(p)->kind == kind, SBR_E_INVALID_ARG, "%s handle has the wrong type", what);
+  return static_cast<H*>(p);
+}
+
+// copy an input array to the host (it may be a device pointer)
+template <class T>
+std::vector<T> to_host(const T* p, size_t n, uint32_t flags, hipStream_t s) {
+  std::vector<T> v(n);
+  if (n == 0) return v;
+  SBR_CHECK(p != nullptr, SBR_E_INVALID_ARG, "input array is NULL");
+  if (flags & SBR_IN_DEVICE) {
+    SBR_HIP(hipMemcpyAsync(v.data(), p, n * sizeof(T), hipMemcpyDeviceToHost, s));
+    SBR_HIP(hipStreamSynchronize(s));
+  } else {
+    std::memcpy(v.data(), p, n * sizeof(T));
+  }
+  return v;
+}
+
+// upload an input array into a library buffer (device-to-device when the input is on the device)
+// Host sources are consumed before returning (the caller may free them at
+// once); device sources are copied in stream order.
+template <class T>
+void upload(Buf& b, const T* p, size_t n, uint32_t flags, hipStream_t s) {
+  b.alloc(n * sizeof(T), s);
+  if (n == 0) return;
+  SBR_CHECK(p != nullptr, SBR_E_INVALID_ARG, "input array is NULL");
+  if (flags & SBR_IN_DEVICE) {
+    SBR_HIP(hipMemcpyAsync(b.p, p, n * sizeof(T), hipMemcpyDeviceToDevice, s));
+  } else {
+    SBR_HIP(hipMemcpyAsync(b.p, p, n * sizeof(T), hipMemcpyHostToDevice, s));
+    SBR_HIP(hipStreamSynchronize(s));
+  }
+}
+
+void set_device(sbr_context_s* c) {
+  SBR_HIP(hipSetDevice(c->device));
+  g_prof = &c->prof;
+}
+
+// ---------------------------------------------------------------- face groups
+struct Plane {
+  double n[3], c;
+};
+
+struct Key4 {
+  int64_t a, b, c, d;
+  bool operator==(const Key4& o) const { return a == o.a && b == o.b && c == o.c && d == o.d; }
+};
+struct Key4Hash {
+  size_t operator()(const Key4& k) const {
+    uint64_t h = 1469598103934665603ull;
+    for (int64_t v : {k.a, k.b, k.c, k.d}) h = (h ^ (uint64_t)v) * 1099511628211ull;
+    return (size_t)h;
+  }
+};
+
+int uf_find(std::vector<int>& p, int x) {
+  while (p[x] != x) {
+    p[x] = p[p[x]];
+    x = p[x];
+  }
+  return x;
+}
+void uf_join(std::vector<int>& p, int a, int b) {
+  a = uf_find(p, a), b = uf_find(p, b);
+  if (a < b) p[b] = a;
+  else if (b < a) p[a] = b;
+}
+
+// Pairs with |n_a . n_b| >= 1 - 1e-12 and matching offsets (1e-9 diag) share a
+// plane; with equal materials also a group.  Candidate pairs come from a hash
+// grid over (n, c) whose cells are wider than both tolerances, probing the
+// 3^4 neighbouring cells of (n, c) and of (-n, -c).
+void face_groups(const std::vector<Plane>& pl, const float* eps, const float* sig, const float* rough, double diag,
+                 std::vector<int32_t>& group, std::vector<int32_t>& plane, int& ngroups, int& nplanes) {
+  const int T = (int)pl.size();
+  const double hn = 4e-6, hc = std::max(4e-9 * diag, 1e-300);
+  std::unordered_map<Key4, std::vector<int>, Key4Hash> grid;
+  grid.reserve(T * 2 + 1);
+  auto key = [&](const double* n, double c) {
+    return Key4{(int64_t)std::floor(n[0] / hn), (int64_t)std::floor(n[1] / hn), (int64_t)std::floor(n[2] / hn),
+                (int64_t)std::floor(c / hc)};
+  };
+  for (int t = 0; t < T; ++t) grid[key(pl[t].n, pl[t].c)].push_back(t);
+  std::vector<int> pp(T), pg(T);
+  for (int t = 0; t < T; ++t) pp[t] = pg[t] = t;
+  for (int a = 0; a < T; ++a) {
+    for (int sgn = -1; sgn <= 1; sgn += 2) {
+      const double n[3] = {sgn * pl[a].n[0], sgn * pl[a].n[1], sgn * pl[a].n[2]};
+      const Key4 k0 = key(n, sgn * pl[a].c);
+      for (int dx = -1; dx <= 1; ++dx)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dz = -1; dz <= 1; ++dz)
+            for (int dc = -1; dc <= 1; ++dc) {
+              auto it = grid.find(Key4{k0.a + dx, k0.b + dy, k0.c + dz, k0.d + dc});
+              if (it == grid.end()) continue;
+              for (int b : it->second) {
+                if (b <= a) continue;
+                const double nd = pl[a].n[0] * pl[b].n[0] + pl[a].n[1] * pl[b].n[1] + pl[a].n[2] * pl[b].n[2];
+                if (std::fabs(nd) < 1.0 - 1e-12) continue;
+                const double s = nd > 0 ? 1.0 : -1.0;
+                if (std::fabs(pl[a].c - s * pl[b].c) > 1e-9 * diag) continue;
+                uf_join(pp, a, b);
+                if (eps[a] == eps[b] && sig[a] == sig[b] && rough[a] == rough[b]) uf_join(pg, a, b);
+              }
+            }
+    }
+  }
+  std::vector<int> gid(T, -1), pid(T, -1);
+  ngroups = nplanes = 0;
+  group.assign(T, 0);
+  plane.assign(T, 0);
+  for (int t = 0; t < T; ++t) {
+    const int rg = uf_find(pg, t), rp = uf_find(pp, t);
+    if (gid[rg] < 0) gid[rg] = ngroups++;
+    if (pid[rp] < 0) pid[rp] = nplanes++;
+    group[t] = gid[rg];
+    plane[t] = pid[rp];
+  }
+}
+
+__global__ void k_tri_gather(const uint32_t* __restrict__ order, int64_t n, const float* __restrict__ v32,
+                             const int32_t* __restrict__ plane, const int32_t* __restrict__ group,
+                             float4* __restrict__ tri) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t t = order[i];
+  const float* v = v32 + 9 * (int64_t)t;
+  tri[3 * i] = make_float4(v[0], v[1], v[2], __int_as_float((int)t));
+  tri[3 * i + 1] = make_float4(v[3], v[4], v[5], __int_as_float(plane[t]));
+  tri[3 * i + 2] = make_float4(v[6], v[7], v[8], __int_as_float(group[t]));
+}
+
+__global__ void k_hits_out(const int32_t* __restrict__ seq, int64_t NR, int K, int32_t* __restrict__ out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= NR) return;
+  bool ended = false;
+  for (int k = 0; k <= K; ++k) {
+    int32_t v = -2;
+    if (!ended) {
+      v = seq[(int64_t)k * NR + r];
+      if (v < 0) ended = true;
+    }
+    out[r * (K + 1) + k] = v;
+  }
+}
+
+double alpha_for(sbr_context_s* c, int N) {
+  for (auto& pr : c->alpha_cache)
+    if (pr.first == N) return pr.second;
+  double mean = 0;
+  geodesic_edge_stats(N, &mean, nullptr, nullptr, c->stream);
+  c->alpha_cache.emplace_back(N, mean);
+  return mean;
+}
+
+bool finite_all(const double* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+}  // namespace
+}  // namespace sbr
+
+using namespace sbr;
+
+sbr_context_s::~sbr_context_s() {
+  if (stream) (void)hipStreamSynchronize(stream);
+  prof.clear();
+  if (g_prof == &prof) g_prof = nullptr;
+  if (own_stream && stream) (void)hipStreamDestroy(stream);
+}
+sbr_scene_s::~sbr_scene_s() {
+  if (ctx) (void)hipSetDevice(ctx->device);
+  nodes.reset(), root_box.reset(), tri32.reset(), tri64.reset(), tplane.reset(), tgroup.reset(), tplaneid.reset();
+  gplane.reset(), gmat.reset(), gstart.reset(), gtri.reset();
+  if (ctx) release(ctx);
+}
+sbr_trace_s::~sbr_trace_s() {
+  if (ctx) (void)hipSetDevice(ctx->device);
+  tx.reset(), seq.reset(), counters.reset(), work.reset();
+  if (scene) release(scene);
+  if (ctx) release(ctx);
+}
+sbr_paths_s::~sbr_paths_s() {
+  if (ctx) (void)hipSetDevice(ctx->device);
+  rx.reset(), key.reset(), geo.reset(), info.reset(), ang.reset(), power.reset(), seg_start.reset();
+  ev_ray.reset(), ev_qk.reset();
+  if (trace) release(trace);
+  if (ctx) release(ctx);
+}
+
+extern "C" {
+
+const char* sbr_last_error(void) { return g_err.c_str(); }
+const char* sbr_version(void) { return "sbr-mi355x 0.1 (gfx950)"; }
+
+void sbr_release(void* h) {
+  if (!h) return;
+  release(static_cast<Handle*>(h));
+}
+
+sbr_status sbr_context_create(int device, void* hip_stream, sbr_context_t* out) {
+  return guard([&] {
+    SBR_CHECK(out != nullptr, SBR_E_INVALID_ARG, "out is NULL");
+    int ndev = 0;
+    SBR_HIP(hipGetDeviceCount(&ndev));
+    SBR_CHECK(device >= 0 && device < ndev, SBR_E_INVALID_ARG, "device %d of %d", device, ndev);
+    SBR_HIP(hipSetDevice(device));
+    auto* c = new sbr_context_s();
+    c->device = device;
+    if (hip_stream) {
+      c->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+      hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+      if (e != hipSuccess) {
+        delete c;
+        SBR_HIP(e);
+      }
+      c->own_stream = true;
+    }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+      c->num_cus = cus;
+    // keep freed stream-ordered memory cached in the pool between calls
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+      uint64_t thr = UINT64_MAX;
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    *out = c;
+  });
+}
+
+sbr_status sbr_synchronize(sbr_context_t ctx) {
+  return guard([&] {
+    auto* c = check_handle<sbr_context_s>(ctx, kContext, "context");
+    set_device(c);
+    SBR_HIP(hipStreamSynchronize(c->stream));
+  });
+}
+
+sbr_status sbr_scene_build(sbr_context_t ctx, const double* tri_xyz, int64_t T, const float* eps_r,
+                           const float* sigma, const float* rough, uint32_t flags, sbr_scene_t* out) {
+  return guard([&] {
+    auto* c = check_handle<sbr_context_s>(ctx, kContext, "context");
+    SBR_CHECK(out != nullptr, SBR_E_INVALID_ARG, "out is NULL");
+    SBR_CHECK(T >= 0 && T < (int64_t(1) << 30), SBR_E_INVALID_ARG, "triangle count %lld", (long long)T);
+    set_device(c);
+    hipStream_t s = c->stream;
+    const auto tri = to_host(tri_xyz, (size_t)T * 9, flags, s);
+    const auto er = to_host(eps_r, (size_t)T, flags, s);
+    const auto sg = to_host(sigma, (size_t)T, flags, s);
+    const auto rh = to_host(rough, (size_t)T, flags, s);
+    SBR_CHECK(finite_all(tri.data(), tri.size()), SBR_E_INVALID_ARG, "triangle coordinates must be finite");
+    for (int64_t t = 0; t < T; ++t) {
+      SBR_CHECK(std::isfinite(er[t]) && er[t] >= 1.0f, SBR_E_INVALID_ARG, "eps_r[%lld] = %g (needs >= 1)",
+                (long long)t, er[t]);
+      SBR_CHECK(std::isfinite(sg[t]) && sg[t] >= 0.0f, SBR_E_INVALID_ARG, "sigma[%lld] = %g", (long long)t, sg[t]);
+      SBR_CHECK(std::isfinite(rh[t]) && rh[t] >= 0.0f, SBR_E_INVALID_ARG, "rough[%lld] = %g", (long long)t, rh[t]);
+    }
+    auto* sc = new sbr_scene_s();
+    sc->ctx = c;
+    retain(c);
+    try {
+      sc->T = T;
+      double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+      for (int64_t t = 0; t < T; ++t)
+        for (int v = 0; v < 3; ++v)
+          for (int k = 0; k < 3; ++k) {
+            lo[k] = std::min(lo[k], tri[9 * t + 3 * v + k]);
+            hi[k] = std::max(hi[k], tri[9 * t + 3 * v + k]);
+          }
+      if (T > 0) {
+        for (int k = 0; k < 3; ++k) sc->center[k] = 0.5 * (lo[k] + hi[k]);
+        sc->diag = std::sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
+                             (hi[2] - lo[2]) * (hi[2] - lo[2]));
+      }
+      std::vector<Plane> pl((size_t)T);
+      for (int64_t t = 0; t < T; ++t) {
+        const d3 a = ld3(&tri[9 * t]), b = ld3(&tri[9 * t + 3]), cc = ld3(&tri[9 * t + 6]);
+        const d3 nn = cross(b - a, cc - a);
+        const double area2 = norm(nn);
+        SBR_CHECK(0.5 * area2 > 1e-12 * sc->diag * sc->diag, SBR_E_INVALID_ARG,
+                  "triangle %lld is degenerate (area %g)", (long long)t, 0.5 * area2);
+        const d3 n = nn * (1.0 / area2);
+        pl[t] = Plane{{n.x, n.y, n.z}, dot(n, a)};
+      }
+      face_groups(pl, er.data(), sg.data(), rh.data(), sc->diag, sc->h_group, sc->h_plane, sc->n_groups,
+                  sc->n_planes);
+      if (T == 0) {
+        sc->gstart.alloc(4, s);
+        fill_u32(sc->gstart.as<uint32_t>(), 0, 1, s);
+        SBR_HIP(hipStreamSynchronize(s));
+        *out = sc;
+        return;
+      }
+      // per-triangle FP64 planes, per-group plane/material/members
+      std::vector<double4> tpl((size_t)T);
+      for (int64_t t = 0; t < T; ++t) tpl[t] = make_double4(pl[t].n[0], pl[t].n[1], pl[t].n[2], pl[t].c);
+      const int G = sc->n_groups;
+      std::vector<int32_t> gfirst(G, -1), gstart(G + 1, 0), gtri((size_t)T), fill(G, 0);
+      for (int64_t t = 0; t < T; ++t) {
+        const int g = sc->h_group[t];
+        if (gfirst[g] < 0) gfirst[g] = (int)t;
+        gstart[g + 1]++;
+      }
+      for (int g = 0; g < G; ++g) gstart[g + 1] += gstart[g];
+      for (int64_t t = 0; t < T; ++t) {
+        const int g = sc->h_group[t];
+        gtri[gstart[g] + fill[g]++] = (int)t;
+      }
+      std::vector<double4> gpl(G);
+      std::vector<float4> gmt(G);
+      for (int g = 0; g < G; ++g) {
+        gpl[g] = tpl[gfirst[g]];
+        gmt[g] = make_float4(er[gfirst[g]], sg[gfirst[g]], rh[gfirst[g]], 0.0f);
+      }
+      // FP32 vertices centred on the scene box and their (outward rounded in the builder) boxes
+      std::vector<float> v32((size_t)T * 9), blo((size_t)T * 3), bhi((size_t)T * 3);
+      float slo[3] = {1e30f, 1e30f, 1e30f}, shi[3] = {-1e30f, -1e30f, -1e30f};
+      for (int64_t t = 0; t < T; ++t) {
+        for (int k = 0; k < 3; ++k) {
+          float mn = 1e30f, mx = -1e30f;
+          for (int v = 0; v < 3; ++v) {
+            const float x = (float)(tri[9 * t + 3 * v + k] - sc->center[k]);
+            v32[9 * t + 3 * v + k] = x;
+            mn = std::min(mn, x), mx = std::max(mx, x);
+          }
+          blo[3 * t + k] = mn, bhi[3 * t + k] = mx;
+          slo[k] = std::min(slo[k], mn), shi[k] = std::max(shi[k], mx);
+        }
+      }
+      Buf dv32, dlo, dhi, order;
+      upload(sc->tri64, tri.data(), tri.size(), 0, s);
+      upload(sc->tplane, tpl.data(), tpl.size(), 0, s);
+      upload(sc->tgroup, sc->h_group.data(), sc->h_group.size(), 0, s);
+      upload(sc->tplaneid, sc->h_plane.data(), sc->h_plane.size(), 0, s);
+      upload(sc->gplane, gpl.data(), gpl.size(), 0, s);
+      upload(sc->gmat, gmt.data(), gmt.size(), 0, s);
+      upload(sc->gstart, gstart.data(), gstart.size(), 0, s);
+      upload(sc->gtri, gtri.data(), gtri.size(), 0, s);
+      upload(dv32, v32.data(), v32.size(), 0, s);
+      upload(dlo, blo.data(), blo.size(), 0, s);
+      upload(dhi, bhi.data(), bhi.size(), 0, s);
+      sc->nodes.alloc((size_t)std::max<int64_t>(T - 1, 1) * 64, s);
+      sc->root_box.alloc(32, s);
+      order.alloc((size_t)T * 4, s);
+      sc->bvh_depth = build_lbvh(dlo.as<float>(), dhi.as<float>(), T, slo, shi,
+                                 BvhOut{sc->nodes.as<float4>(), order.as<uint32_t>(), sc->root_box.as<float>()}, s);
+      SBR_CHECK(sc->bvh_depth <= 64, SBR_E_UNSUPPORTED, "BVH depth %d exceeds the traversal stack", sc->bvh_depth);
+      sc->tri32.alloc((size_t)T * 48, s);
+      hipLaunchKernelGGL(k_tri_gather, dim3(nblk(T, 256)), dim3(256), 0, s, order.as<uint32_t>(), T,
+                         dv32.as<float>(), sc->tplaneid.as<int32_t>(), sc->tgroup.as<int32_t>(),
+                         sc->tri32.as<float4>());
+      SBR_LAUNCH_CHECK();
+      SBR_HIP(hipMemcpyAsync(sc->root_host, sc->root_box.p, 24, hipMemcpyDeviceToHost, s));
+      SBR_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+      release(sc);
+      throw;
+    }
+    *out = sc;
+  });
+}
+
+sbr_status sbr_scene_info(sbr_scene_t s, int32_t* n_groups, int32_t* n_planes, int32_t* bvh_depth) {
+  return guard([&] {
+    auto* sc = check_handle<sbr_scene_s>(s, kScene, "scene");
+    if (n_groups) *n_groups = sc->n_groups;
+    if (n_planes) *n_planes = sc->n_planes;
+    if (bvh_depth) *bvh_depth = sc->bvh_depth;
+  });
+}
+
+sbr_status sbr_scene_groups(sbr_scene_t s, int32_t* group, int32_t* plane) {
+  return guard([&] {
+    auto* sc = check_handle<sbr_scene_s>(s, kScene, "scene");
+    if (group) std::copy(sc->h_group.begin(), sc->h_group.end(), group);
+    if (plane) std::copy(sc->h_plane.begin(), sc->h_plane.end(), plane);
+  });
+}
+
+sbr_status sbr_trace(sbr_context_t ctx, sbr_scene_t scene, const double* tx_xyz, int32_t Nt, int32_t N,
+                     int32_t K, uint32_t flags, sbr_trace_t* out) {
+  return guard([&] {
+    auto* c = check_handle<sbr_context_s>(ctx, kContext, "context");
+    auto* sc = check_handle<sbr_scene_s>(scene, kScene, "scene");
+    SBR_CHECK(out != nullptr, SBR_E_INVALID_ARG, "out is NULL");
+    SBR_CHECK(Nt >= 1, SBR_E_INVALID_ARG, "Nt = %d", Nt);
+    SBR_CHECK(N >= 1 && N <= 46340, SBR_E_INVALID_ARG, "geodesic_N = %d", N);
+    SBR_CHECK(K >= 0 && K <= SBR_MAX_BOUNCES, SBR_E_INVALID_ARG, "max_bounces = %d", K);
+    const int64_t R = 10LL * N * N + 2;
+    SBR_CHECK((int64_t)Nt * R < (int64_t(1) << 32) - (int64_t(1) << 22), SBR_E_UNSUPPORTED,
+              "Nt * rays = %lld exceeds 2^32 - 2^22",
+              (long long)Nt * R);
+    set_device(c);
+    hipStream_t s = c->stream;
+    const auto htx = to_host(tx_xyz, (size_t)Nt * 3, flags, s);
+    SBR_CHECK(finite_all(htx.data(), htx.size()), SBR_E_INVALID_ARG, "tx coordinates must be finite");
+    auto* tr = new sbr_trace_s();
+    tr->ctx = c, tr->scene = sc;
+    retain(c), retain(sc);
+    try {
+      tr->Nt = Nt, tr->N = N, tr->K = K, tr->R = R, tr->NR = (int64_t)Nt * R;
+      tr->h_tx = htx;
+      upload(tr->tx, tr->h_tx.data(), tr->h_tx.size(), 0, s);
+      tr->seq.alloc((size_t)(K + 1) * tr->NR * 4, s);
+      tr->counters.alloc((size_t)2 * (K + 1) * 4, s);
+      Buf ra, rb;
+      ra.alloc(trace_ray_bytes(tr->NR), s);
+      if (K > 0) rb.alloc(trace_ray_bytes(tr->NR), s);
+      TraceLaunch L{};
+      L.scene = sc, L.tx = tr->tx.as<double>(), L.Nt = Nt, L.N = N, L.K = K, L.R = R, L.NR = tr->NR;
+      L.seq = tr->seq.as<int32_t>();
+      L.counters = tr->counters.as<uint32_t>();
+      L.work = nullptr;
+      if (c->count_work) {
+        tr->work.alloc(16, s);
+        fill_u32(tr->work.as<uint32_t>(), 0, 4, s);
+        L.work = tr->work.as<unsigned long long>();
+        tr->counted = true;
+      }
+      L.block = 256;
+      L.grid = c->num_cus * c->tune.trace_blocks_per_cu;
+      launch_trace(L, ra.p, K > 0 ? rb.p : ra.p, s);
+    } catch (...) {
+      release(tr);
+      throw;
+    }
+    *out = tr;
+  });
+}
+
+sbr_status sbr_trace_info(sbr_trace_t t, int64_t* rays, int64_t* segments) {
+  return guard([&] {
+    auto* tr = check_handle<sbr_trace_s>(t, kTrace, "trace");
+    set_device(tr->ctx);
+    if (tr->segments < 0) {
+      std::vector<uint32_t> cnt(2 * (tr->K + 1));
+      SBR_HIP(hipMemcpyAsync(cnt.data(), tr->counters.p, cnt.size() * 4, hipMemcpyDeviceToHost, tr->ctx->stream));
+      SBR_HIP(hipStreamSynchronize(tr->ctx->stream));
+      int64_t seg = tr->NR;
+      for (int k = 0; k < tr->K; ++k) seg += cnt[tr->K + 1 + k];
+      tr->segments = seg;
+    }
+    if (rays) *rays = tr->NR;
+    if (segments) *segments = tr->segments;
+  });
+}
+
+sbr_status sbr_trace_hits(sbr_trace_t t, int32_t* seq, uint32_t flags) {
+  return guard([&] {
+    auto* tr = check_handle<sbr_trace_s>(t, kTrace, "trace");
+    SBR_CHECK(seq != nullptr, SBR_E_INVALID_ARG, "seq is NULL");
+    set_device(tr->ctx);
+    hipStream_t s = tr->ctx->stream;
+    const size_t n = (size_t)tr->NR * (tr->K + 1);
+    Buf tmp;
+    int32_t* dst = seq;
+    if (!(flags & SBR_OUT_DEVICE)) {
+      tmp.alloc(n * 4, s);
+      dst = tmp.as<int32_t>();
+    }
+    { ::sbr::TimedLaunch tl_("misc", s); hipLaunchKernelGGL(k_hits_out, dim3(nblk(tr->NR, 256)), dim3(256), 0, s, tr->seq.as<int32_t>(), tr->NR, tr->K,
+                       dst); }
+    SBR_LAUNCH_CHECK();
+    if (!(flags & SBR_OUT_DEVICE)) {
+      SBR_HIP(hipMemcpyAsync(seq, dst, n * 4, hipMemcpyDeviceToHost, s));
+      SBR_HIP(hipStreamSynchronize(s));
+    }
+  });
+}
+
+sbr_status sbr_receive(sbr_context_t ctx, sbr_trace_t t, const double* rx_xyz, int32_t Nr, double alpha_rad,
+                       double radius_coeff, uint32_t flags, sbr_paths_t* out) {
+  return guard([&] {
+    auto* c = check_handle<sbr_context_s>(ctx, kContext, "context");
+    auto* tr = check_handle<sbr_trace_s>(t, kTrace, "trace");
+    SBR_CHECK(out != nullptr, SBR_E_INVALID_ARG, "out is NULL");
+    SBR_CHECK(Nr >= 1 && (int64_t)Nr < (int64_t(1) << 26), SBR_E_INVALID_ARG, "Nr = %d", Nr);
+    SBR_CHECK((int64_t)Nr * tr->Nt < (int64_t(1) << 31), SBR_E_UNSUPPORTED, "Nr * Nt too large");
+    SBR_CHECK(std::isfinite(radius_coeff) && radius_coeff > 0, SBR_E_INVALID_ARG, "radius_coeff = %g",
+              radius_coeff);
+    SBR_CHECK(std::isfinite(alpha_rad), SBR_E_INVALID_ARG, "alpha must be finite");
+    set_device(c);
+    hipStream_t s = c->stream;
+    const auto hrx = to_host(rx_xyz, (size_t)Nr * 3, flags, s);
+    SBR_CHECK(finite_all(hrx.data(), hrx.size()), SBR_E_INVALID_ARG, "rx coordinates must be finite");
+    for (int q = 0; q < Nr; ++q)
+      for (int p = 0; p < tr->Nt; ++p)
+        SBR_CHECK(!(hrx[3 * q] == tr->h_tx[3 * p] && hrx[3 * q + 1] == tr->h_tx[3 * p + 1] &&
+                    hrx[3 * q + 2] == tr->h_tx[3 * p + 2]),
+                  SBR_E_INVALID_ARG, "rx %d coincides with tx %d", q, p);
+    auto* ps = new sbr_paths_s();
+    ps->ctx = c, ps->trace = tr;
+    retain(c), retain(tr);
+    try {
+      ps->Nr = Nr;
+      ps->coeff = radius_coeff;
+      ps->alpha = alpha_rad > 0 ? alpha_rad : alpha_for(c, tr->N);
+      upload(ps->rx, hrx.data(), hrx.size(), 0, s);
+      run_receive(ps, s);
+    } catch (...) {
+      release(ps);
+      throw;
+    }
+    *out = ps;
+  });
+}
+
+sbr_status sbr_paths_info(sbr_paths_t p, int64_t* events, int64_t* keys, int64_t* paths) {
+  return guard([&] {
+    auto* ps = check_handle<sbr_paths_s>(p, kPaths, "paths");
+    if (events) *events = ps->n_events;
+    if (keys) *keys = ps->n_keys;
+    if (paths) *paths = ps->n_paths;
+  });
+}
+
+sbr_status sbr_paths_count(sbr_paths_t p, int64_t* n) {
+  return guard([&] {
+    auto* ps = check_handle<sbr_paths_s>(p, kPaths, "paths");
+    SBR_CHECK(n != nullptr, SBR_E_INVALID_ARG, "n is NULL");
+    *n = ps->n_paths;
+  });
+}
+
+sbr_status sbr_paths_events(sbr_paths_t p, int64_t capacity, uint32_t* ray, int32_t* rx, int32_t* k,
+                            int64_t* written) {
+  return guard([&] {
+    auto* ps = check_handle<sbr_paths_s>(p, kPaths, "paths");
+    const int64_t n = ps->n_events;
+    SBR_CHECK(capacity >= n, SBR_E_CAPACITY, "paths_events needs capacity %lld", (long long)n);
+    set_device(ps->ctx);
+    hipStream_t s = ps->ctx->stream;
+    std::vector<uint32_t> r((size_t)n), qk((size_t)n);
+    if (n > 0) {
+      SBR_HIP(hipMemcpyAsync(r.data(), ps->ev_ray.p, n * 4, hipMemcpyDeviceToHost, s));
+      SBR_HIP(hipMemcpyAsync(qk.data(), ps->ev_qk.p, n * 4, hipMemcpyDeviceToHost, s));
+      SBR_HIP(hipStreamSynchronize(s));
+    }
+    for (int64_t i = 0; i < n; ++i) {
+      if (ray) ray[i] = r[i];
+      if (rx) rx[i] = (int32_t)(qk[i] >> 5);
+      if (k) k[i] = (int32_t)(qk[i] & 31u);
+    }
+    if (written) *written = n;
+  });
+}
+
+sbr_status sbr_paths_get(sbr_paths_t p, int64_t capacity, sbr_path_record* out, int64_t* written) {
+  return guard([&] {
+    auto* ps = check_handle<sbr_paths_s>(p, kPaths, "paths");
+    const int64_t n = ps->n_paths;
+    SBR_CHECK(capacity >= n, SBR_E_CAPACITY, "paths_get needs capacity %lld", (long long)n);
+    SBR_CHECK(out != nullptr || n == 0, SBR_E_INVALID_ARG, "out is NULL");
+    set_device(ps->ctx);
+    hipStream_t s = ps->ctx->stream;
+    const int K = ps->trace->K;
+    std::vector<int32_t> key((size_t)n * (4 + K));
+    std::vector<double> info((size_t)n * 2), pw((size_t)n);
+    std::vector<float> ang((size_t)n * 4);
+    if (n > 0) {
+      SBR_HIP(hipMemcpyAsync(key.data(), ps->key.p, key.size() * 4, hipMemcpyDeviceToHost, s));
+      SBR_HIP(hipMemcpyAsync(info.data(), ps->info.p, info.size() * 8, hipMemcpyDeviceToHost, s));
+      SBR_HIP(hipMemcpyAsync(ang.data(), ps->ang.p, ang.size() * 4, hipMemcpyDeviceToHost, s));
+      if (ps->have_power) SBR_HIP(hipMemcpyAsync(pw.data(), ps->power.p, pw.size() * 8, hipMemcpyDeviceToHost, s));
+      SBR_HIP(hipStreamSynchronize(s));
+    }
+    for (int64_t i = 0; i < n; ++i) {
+      sbr_path_record& r = out[i];
+      std::memset(&r, 0, sizeof r);
+      const int32_t* k = &key[i * (4 + K)];
+      r.tx = k[0], r.rx = k[1], r.order = k[2], r.flags = k[3];
+      for (int j = 0; j < SBR_MAX_BOUNCES; ++j) r.groups[j] = j < K ? k[4 + j] : -1;
+      r.length_m = info[2 * i], r.delay_s = info[2 * i + 1];
+      r.aod_az = ang[4 * i], r.aod_el = ang[4 * i + 1], r.aoa_az = ang[4 * i + 2], r.aoa_el = ang[4 * i + 3];
+      r.power = ps->have_power ? (float)pw[i] : 0.0f;
+    }
+    if (written) *written = n;
+  });
+}
+
+namespace {
+struct FieldInputs {
+  Buf f, adb, adeg;
+  ChannelArgs a{};
+};
+void field_inputs(FieldInputs& F, const double* freq, int Nf, const float* atm_db, const float* atm_deg, int ptx,
+                  int prx, uint32_t flags, hipStream_t s) {
+  SBR_CHECK(Nf >= 1, SBR_E_INVALID_ARG, "Nf = %d", Nf);
+  SBR_CHECK(ptx == SBR_POL_V || ptx == SBR_POL_H, SBR_E_INVALID_ARG, "pol_tx = %d", ptx);
+  SBR_CHECK(prx == SBR_POL_V || prx == SBR_POL_H, SBR_E_INVALID_ARG, "pol_rx = %d", prx);
+  const auto hf = to_host(freq, (size_t)Nf, flags, s);
+  for (int i = 0; i < Nf; ++i)
+    SBR_CHECK(std::isfinite(hf[i]) && hf[i] > 0, SBR_E_INVALID_ARG, "freq[%d] = %g", i, hf[i]);
+  upload(F.f, freq, (size_t)Nf, flags, s);
+  if (atm_db) upload(F.adb, atm_db, (size_t)Nf, flags, s);
+  if (atm_deg) upload(F.adeg, atm_deg, (size_t)Nf, flags, s);
+  F.a = ChannelArgs{F.f.as<double>(), atm_db ? F.adb.as<float>() : nullptr, atm_deg ? F.adeg.as<float>() : nullptr,
+                    Nf, ptx, prx};
+}
+}  // namespace
+
+sbr_status sbr_channel(sbr_context_t ctx, sbr_paths_t p, const double* freq, int32_t Nf, const float* atm_db,
+                       const float* atm_deg, int32_t pol_tx, int32_t pol_rx, void* H_c64, double* H_c128,
+                       uint32_t flags) {
+  return guard([&] {
+    auto* c = check_handle<sbr_context_s>(ctx, kContext, "context");
+    auto* ps = check_handle<sbr_paths_s>(p, kPaths, "paths");
+    set_device(c);
+    hipStream_t s = c->stream;
+    FieldInputs F;
+    field_inputs(F, freq, Nf, atm_db, atm_deg, pol_tx, pol_rx, flags, s);
+    const size_t nH = (size_t)Nf * ps->Nr * ps->trace->Nt;
+    Buf t64, t128;
+    float2* d64 = static_cast<float2*>(H_c64);
+    double2* d128 = reinterpret_cast<double2*>(H_c128);
+    const bool dev_out = flags & SBR_OUT_DEVICE;
+    if (!dev_out) {
+      if (H_c64) t64.alloc(nH * 8, s), d64 = t64.as<float2>();
+      if (H_c128) t128.alloc(nH * 16, s), d128 = t128.as<double2>();
+    }
+    run_channel(ps, F.a, d64, d128, s);
+    if (!dev_out) {
+      if (H_c64) SBR_HIP(hipMemcpyAsync(H_c64, d64, nH * 8, hipMemcpyDeviceToHost, s));
+      if (H_c128) SBR_HIP(hipMemcpyAsync(H_c128, d128, nH * 16, hipMemcpyDeviceToHost, s));
+      SBR_HIP(hipStreamSynchronize(s));
+    }
+  });
+}
+
+sbr_status sbr_path_field(sbr_context_t ctx, sbr_paths_t p, const double* freq, int32_t Nf, const float* atm_db,
+                          const float* atm_deg, int32_t pol_tx, int32_t pol_rx, double* a_c128, uint32_t flags) {
+  return guard([&] {
+    auto* c = check_handle<sbr_context_s>(ctx, kContext, "context");
+    auto* ps = check_handle<sbr_paths_s>(p, kPaths, "paths");
+    SBR_CHECK(a_c128 != nullptr || ps->n_paths == 0, SBR_E_INVALID_ARG, "output is NULL");
+    set_device(c);
+    hipStream_t s = c->stream;
+    FieldInputs F;
+    field_inputs(F, freq, Nf, atm_db, atm_deg, pol_tx, pol_rx, flags, s);
+    const size_t n = (size_t)ps->n_paths * Nf;
+    Buf tmp;
+    double2* dst = reinterpret_cast<double2*>(a_c128);
+    if (!(flags & SBR_OUT_DEVICE)) tmp.alloc(n * 16, s), dst = tmp.as<double2>();
+    run_path_field(ps, F.a, dst, s);
+    if (!(flags & SBR_OUT_DEVICE)) {
+      if (n) SBR_HIP(hipMemcpyAsync(a_c128, dst, n * 16, hipMemcpyDeviceToHost, s));
+      SBR_HIP(hipStreamSynchronize(s));
+    }
+  });
+}
+
+sbr_status sbr_stats(sbr_paths_t p, float* pg_db, float* tau, float* angles, uint32_t flags) {
+  return guard([&] {
+    auto* ps = check_handle<sbr_paths_s>(p, kPaths, "paths");
+    SBR_CHECK(ps->have_power, SBR_E_STATE, "sbr_stats needs a preceding sbr_channel");
+    set_device(ps->ctx);
+    hipStream_t s = ps->ctx->stream;
+    const size_t nseg = (size_t)ps->Nr * ps->trace->Nt;
+    if (flags & SBR_OUT_DEVICE) {
+      run_stats(ps, pg_db, tau, angles, s);
+      return;
+    }
+    Buf a, b, cbuf;
+    if (pg_db) a.alloc(nseg * 4, s);
+    if (tau) b.alloc(nseg * 4, s);
+    if (angles) cbuf.alloc(nseg * 16, s);
+    run_stats(ps, a.as<float>(), b.as<float>(), cbuf.as<float>(), s);
+    if (pg_db) SBR_HIP(hipMemcpyAsync(pg_db, a.p, nseg * 4, hipMemcpyDeviceToHost, s));
+    if (tau) SBR_HIP(hipMemcpyAsync(tau, b.p, nseg * 4, hipMemcpyDeviceToHost, s));
+    if (angles) SBR_HIP(hipMemcpyAsync(angles, cbuf.p, nseg * 16, hipMemcpyDeviceToHost, s));
+    SBR_HIP(hipStreamSynchronize(s));
+  });
+}
+
+sbr_status sbr_capacity(sbr_context_t ctx, const void* H_c64, int32_t Nf, int32_t Nr, int32_t Nt,
+                        const double* snr_db, int32_t Nsnr, int32_t normalize, double* C, uint32_t flags) {
+  return guard([&] {
+    auto* c = check_handle<sbr_context_s>(ctx, kContext, "context");
+    SBR_CHECK(Nf >= 1 && Nr >= 1 && Nt >= 1 && Nsnr >= 1, SBR_E_INVALID_ARG, "capacity sizes");
+    SBR_CHECK(std::min(Nr, Nt) <= 128, SBR_E_UNSUPPORTED, "min(Nr, Nt) = %d > 128", std::min(Nr, Nt));
+    SBR_CHECK(H_c64 && snr_db && C, SBR_E_INVALID_ARG, "NULL argument");
+    set_device(c);
+    hipStream_t s = c->stream;
+    Buf h, sn, out;
+    upload(h, static_cast<const float2*>(H_c64), (size_t)Nf * Nr * Nt, flags, s);
+    upload(sn, snr_db, (size_t)Nsnr, flags, s);
+    out.alloc((size_t)Nsnr * 8, s);
+    run_capacity(h.as<float2>(), Nf, Nr, Nt, sn.as<double>(), Nsnr, normalize, out.as<double>(), s);
+    SBR_HIP(hipMemcpyAsync(C, out.p, (size_t)Nsnr * 8,
+                           (flags & SBR_OUT_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    SBR_HIP(hipStreamSynchronize(s));
+  });
+}
+
+sbr_status sbr_profile_enable(sbr_context_t ctx, int enable) {
+  return guard([&] {
+    auto* c = check_handle<sbr_context_s>(ctx, kContext, "context");
+    set_device(c);
+    c->prof.clear();
+    c->prof.enabled = enable != 0;
+  });
+}
+
+sbr_status sbr_profile_query(sbr_context_t ctx, const char* kernel, double* total_ms, int64_t* launches) {
+  return guard([&] {
+    auto* c = check_handle<sbr_context_s>(ctx, kContext, "context");
+    SBR_CHECK(kernel != nullptr, SBR_E_INVALID_ARG, "kernel name is NULL");
+    set_device(c);
+    c->prof.resolve();
+    double ms = 0.0;
+    int64_t n = 0;
+    for (auto& e : c->prof.acc)
+      if (e.first == kernel) ms = e.second.first, n = e.second.second;
+    if (total_ms) *total_ms = ms;
+    if (launches) *launches = n;
+  });
+}
+
+sbr_status sbr_context_count_work(sbr_context_t ctx, int enable) {
+  return guard([&] {
+    auto* c = check_handle<sbr_context_s>(ctx, kContext, "context");
+    c->count_work = enable != 0;
+  });
+}
+
+sbr_status sbr_trace_work(sbr_trace_t t, int64_t* node_visits, int64_t* tri_tests) {
+  return guard([&] {
+    auto* tr = check_handle<sbr_trace_s>(t, kTrace, "trace");
+    set_device(tr->ctx);
+    uint64_t w[2] = {0, 0};
+    if (tr->counted) {
+      SBR_HIP(hipMemcpyAsync(w, tr->work.p, 16, hipMemcpyDeviceToHost, tr->ctx->stream));
+      SBR_HIP(hipStreamSynchronize(tr->ctx->stream));
+    }
+    if (node_visits) *node_visits = (int64_t)w[0];
+    if (tri_tests) *tri_tests = (int64_t)w[1];
+  });
+}
+
+sbr_status sbr_geodesic(sbr_context_t ctx, int32_t N, int64_t first, int64_t count, double* dirs, uint32_t flags) {
+  return guard([&] {
+    auto* c = check_handle<sbr_context_s>(ctx, kContext, "context");
+    const int64_t R = 10LL * N * N + 2;
+    SBR_CHECK(N >= 1 && N <= 46340 && first >= 0 && count >= 0 && first + count <= R, SBR_E_INVALID_ARG,
+              "geodesic range");
+    SBR_CHECK(dirs != nullptr || count == 0, SBR_E_INVALID_ARG, "dirs is NULL");
+    set_device(c);
+    hipStream_t s = c->stream;
+    Buf tmp;
+    double* dst = dirs;
+    if (!(flags & SBR_OUT_DEVICE)) tmp.alloc((size_t)count * 24, s), dst = tmp.as<double>();
+    launch_geodesic(N, first, count, dst, s);
+    if (!(flags & SBR_OUT_DEVICE)) {
+      if (count) SBR_HIP(hipMemcpyAsync(dirs, dst, (size_t)count * 24, hipMemcpyDeviceToHost, s));
+      SBR_HIP(hipStreamSynchronize(s));
+    }
+  });
+}
+
+sbr_status sbr_geodesic_alpha(sbr_context_t ctx, int32_t N, double* mean, double* mn, double* mx) {
+  return guard([&] {
+    auto* c = check_handle<sbr_context_s>(ctx, kContext, "context");
+    SBR_CHECK(N >= 1 && N <= 46340, SBR_E_INVALID_ARG, "N = %d", N);
+    set_device(c);
+    geodesic_edge_stats(N, mean, mn, mx, c->stream);
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,137 @@
+// sbr_device.hpp -- device-side helpers shared by the libsbr kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sbr {
+
+// ----------------------------------------------------------------- FP64 vectors
+struct d3 {
+  double x, y, z;
+};
+__host__ __device__ inline d3 mk3(double x, double y, double z) { return d3{x, y, z}; }
+__host__ __device__ inline d3 operator+(d3 a, d3 b) { return d3{a.x + b.x, a.y + b.y, a.z + b.z}; }
+__host__ __device__ inline d3 operator-(d3 a, d3 b) { return d3{a.x - b.x, a.y - b.y, a.z - b.z}; }
+__host__ __device__ inline d3 operator*(d3 a, double s) { return d3{a.x * s, a.y * s, a.z * s}; }
+__host__ __device__ inline double dot(d3 a, d3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__host__ __device__ inline d3 cross(d3 a, d3 b) {
+  return d3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__host__ __device__ inline double norm(d3 a) { return sqrt(dot(a, a)); }
+__host__ __device__ inline d3 normalize(d3 a) { return a * (1.0 / norm(a)); }
+__host__ __device__ inline d3 ld3(const double* p) { return d3{p[0], p[1], p[2]}; }
+
+// ----------------------------------------------------------------- FP64 complex
+struct cd {
+  double re, im;
+};
+__device__ inline cd cmk(double r, double i) { return cd{r, i}; }
+__device__ inline cd cadd(cd a, cd b) { return cd{a.re + b.re, a.im + b.im}; }
+__device__ inline cd csub(cd a, cd b) { return cd{a.re - b.re, a.im - b.im}; }
+__device__ inline cd cmul(cd a, cd b) { return cd{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ inline cd cscale(cd a, double s) { return cd{a.re * s, a.im * s}; }
+__device__ inline cd cdiv(cd a, cd b) {
+  // Smith's algorithm (avoids overflow for large |b|)
+  if (fabs(b.re) >= fabs(b.im)) {
+    double r = b.im / b.re, den = b.re + b.im * r;
+    return cd{(a.re + a.im * r) / den, (a.im - a.re * r) / den};
+  }
+  double r = b.re / b.im, den = b.re * r + b.im;
+  return cd{(a.re * r + a.im) / den, (a.im * r - a.re) / den};
+}
+// principal square root
+__device__ inline cd csqrt_p(cd z) {
+  double m = hypot(z.re, z.im);
+  if (m == 0.0) return cd{0.0, 0.0};
+  if (z.re >= 0.0) {
+    double r = sqrt(0.5 * (m + z.re));
+    return cd{r, z.im / (2.0 * r)};
+  }
+  double i = sqrt(0.5 * (m - z.re));
+  if (z.im < 0.0 || (z.im == 0.0 && signbit(z.im))) i = -i;
+  return cd{z.im / (2.0 * i), i};
+}
+
+// ----------------------------------------------------------------- geodesic
+// Icosahedron tables passed by value to kernels (built on the host by search).
+struct GeoTables {
+  double v[12][3];
+  int e[30][2];
+  int f[20][3];
+};
+const GeoTables& geo_tables();
+
+// Direction of ray id of the frequency-N class-I geodesic (Sec. II-A-1):
+// 12 corners, then 30 edges x (N-1) interior points from the lower vertex,
+// then 20 faces x (N-1)(N-2)/2 interior points in row-major (i, j) order.
+__device__ inline d3 geo_dir(const GeoTables& G, int N, int64_t id) {
+  if (id < 12) return ld3(G.v[id]);
+  id -= 12;
+  const int64_t ne = 30LL * (N - 1);
+  if (id < ne) {
+    const int e = (int)(id / (N - 1));
+    const int i = (int)(id - (int64_t)e * (N - 1)) + 1;
+    const d3 a = ld3(G.v[G.e[e][0]]), b = ld3(G.v[G.e[e][1]]);
+    const double w = (double)i / (double)N;
+    return normalize(a + (b - a) * w);
+  }
+  id -= ne;
+  const int64_t per = (int64_t)(N - 1) * (N - 2) / 2;
+  const int f = (int)(id / per);
+  const int64_t l = id - (int64_t)f * per;
+  // rows i = 1..N-2 hold N-1-i points; points before row i:
+  //   S(i) = (i-1)(N-1) - (i-1) i / 2.  Invert with a real root, then fix up.
+  const double M = (double)(N - 1);
+  const double disc = (M - 0.5) * (M - 0.5) - 2.0 * (double)l;
+  int i = (int)floor((M - 0.5) - sqrt(disc > 0 ? disc : 0.0)) + 1;
+  if (i < 1) i = 1;
+  if (i > N - 2) i = N - 2;
+  auto S = [&](int r) -> int64_t { return (int64_t)(r - 1) * (N - 1) - (int64_t)(r - 1) * r / 2; };
+  while (i > 1 && S(i) > l) --i;
+  while (i < N - 2 && S(i + 1) <= l) ++i;
+  const int j = (int)(l - S(i)) + 1;
+  const d3 a = ld3(G.v[G.f[f][0]]), b = ld3(G.v[G.f[f][1]]), c = ld3(G.v[G.f[f][2]]);
+  const double wi = (double)i / (double)N, wj = (double)j / (double)N;
+  return normalize(a + (b - a) * wi + (c - a) * wj);
+}
+
+// ----------------------------------------------------------------- FP64 ray step
+// Exact continuation of a ray whose FP32 traversal selected a triangle with
+// plane (n, c): the hit distance is re-evaluated in FP64 on that plane, so the
+// ray state never accumulates FP32 rounding between bounces.
+__device__ inline double plane_t(const double4 pl, d3 o, d3 d) {
+  const d3 n = mk3(pl.x, pl.y, pl.z);
+  return (pl.w - dot(n, o)) / dot(n, d);
+}
+// distance to the selected plane, used by both the trace and the replay so the
+// two rebuild the same FP64 chain (a degenerate value collapses to 0)
+__device__ inline double advance_t(const double4 pl, d3 o, d3 d) {
+  const double t = plane_t(pl, o, d);
+  return (t >= 0.0 && t < INFINITY) ? t : 0.0;
+}
+// specular reflection about the plane normal (Snell's law, Sec. II-A-2)
+__device__ inline d3 reflect(d3 d, const double4 pl) {
+  const d3 n = mk3(pl.x, pl.y, pl.z);
+  return d - n * (2.0 * dot(d, n));
+}
+
+// spherical unit vectors of a propagation direction (phi = atan2(y, x), 0 at the poles)
+__device__ inline void sph_hats(d3 u, d3* th, d3* ph) {
+  const double st = sqrt(u.x * u.x + u.y * u.y);
+  double cp = 1.0, sp = 0.0;
+  if (st > 0.0) {
+    cp = u.x / st;
+    sp = u.y / st;
+  }
+  *th = mk3(u.z * cp, u.z * sp, -st);
+  *ph = mk3(-sp, cp, 0.0);
+}
+
+// ----------------------------------------------------------------- wave helpers
+__device__ inline uint64_t lanemask_lt() {
+  const int lane = threadIdx.x & 63;
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+}  // namespace sbr

@@ -1,0 +1,258 @@
+// sbr_internal.hpp -- internal types of libsbr (not part of the C-ABI).
+//
+// Data layout in HBM (structure of arrays everywhere a kernel streams):
+//   scene:  FP32 centred triangles in LBVH leaf order (3 x float4 per
+//           triangle: v0|tri id, v1|plane id, v2|group id), 64-byte BVH nodes
+//           holding both child boxes, FP64 per-triangle planes (n, c) and
+//           vertices for the exact FP64 steps, per-group plane/material and a
+//           CSR of group members.
+//   trace:  hit chain seq[k][ray] (int32, k-major so each bounce writes one
+//           contiguous plane), ping-pong FP64 ray SoA between bounces.
+//   paths:  per path a FP64 geometry record (stride 14 + 8K doubles) with the
+//           frequency-independent polarisation chain, (rx, tx)-major order.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sbr.h"
+
+namespace sbr {
+
+// ----------------------------------------------------------------- constants
+constexpr double kC0 = 299792458.0;        // m/s
+constexpr double kEps0 = 8.8541878128e-12; // F/m
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kWave = 64;
+
+// path geometry record (FP64): header then 8 doubles per bounce
+//   [0] length  [1] order k
+//   [2..5]  c_init for V (2) and H (2): components of the Tx polarisation on (s_1, p_in_1)
+//   [6..9]  w for V (2) and H (2): Rx polarisation on (s_k, p_out_k)
+//   [10..13] line-of-sight e_rx . e_tx for VV, VH, HV, HH (k = 0)
+//   bounce b: cos_i, eps_r, sigma, rough, G00, G01, G10, G11 (G maps (s_b,p_out_b)
+//             amplitudes onto (s_{b+1}, p_in_{b+1}))
+constexpr int kGeoHead = 14;
+constexpr int kGeoPerBounce = 8;
+inline int geo_stride(int K) { return kGeoHead + kGeoPerBounce * (K > 0 ? K : 1); }
+
+// ----------------------------------------------------------------- errors
+void set_error(const char* fmt, ...);
+struct Error {
+  sbr_status st;
+};
+
+#define SBR_HIP(call)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess) {                                                                \
+      ::sbr::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, __LINE__); \
+      throw ::sbr::Error{e_ == hipErrorOutOfMemory ? SBR_E_OUT_OF_MEMORY : SBR_E_DEVICE};  \
+    }                                                                                      \
+  } while (0)
+
+#define SBR_CHECK(cond, status, ...)         \
+  do {                                       \
+    if (!(cond)) {                           \
+      ::sbr::set_error(__VA_ARGS__);         \
+      throw ::sbr::Error{status};            \
+    }                                        \
+  } while (0)
+
+#define SBR_LAUNCH_CHECK() SBR_HIP(hipGetLastError())
+
+// ----------------------------------------------------------------- handles
+enum Kind : int { kContext = 0x5bc0, kScene, kTrace, kPaths };
+
+struct Handle {
+  int kind;
+  std::atomic<int> refs{1};
+  explicit Handle(int k) : kind(k) {}
+  virtual ~Handle() = default;
+};
+void retain(Handle* h);
+void release(Handle* h);
+
+// device buffer owned by a handle (stream-ordered allocation)
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipStream_t stream = nullptr;
+  Buf() = default;
+  Buf(const Buf&) = delete;
+  Buf& operator=(const Buf&) = delete;
+  ~Buf() { reset(); }
+  void alloc(size_t n, hipStream_t s);
+  void reset();
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Live kernel timing: HIP events around launches, accumulated per kernel class.
+struct Prof {
+  bool enabled = false;
+  struct Pending {
+    std::string name;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<std::pair<std::string, std::pair<double, int64_t>>> acc;
+  void resolve();  // synchronises on the recorded events
+  void clear();
+};
+// the profiler of the context whose API call is running on this thread
+extern thread_local Prof* g_prof;
+struct TimedLaunch {
+  hipEvent_t a = nullptr, b = nullptr;
+  const char* name;
+  hipStream_t s;
+  TimedLaunch(const char* n, hipStream_t st);
+  ~TimedLaunch();
+};
+
+struct Tuning {
+  int trace_block = 256;      // threads per block of the bounce kernel
+  int trace_blocks_per_cu = 4; // resident blocks per CU of the persistent grid
+  int replay_block = 256;
+};
+
+}  // namespace sbr
+
+struct sbr_context_s : sbr::Handle {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int num_cus = 256;
+  sbr::Tuning tune;
+  sbr::Prof prof;
+  bool count_work = false;
+  // cached geodesic edge statistics per N
+  std::vector<std::pair<int, double>> alpha_cache;
+  sbr_context_s() : Handle(sbr::kContext) {}
+  ~sbr_context_s() override;
+};
+
+struct sbr_scene_s : sbr::Handle {
+  sbr_context_s* ctx = nullptr;
+  int64_t T = 0;
+  int n_groups = 0, n_planes = 0, bvh_depth = 0;
+  double center[3] = {0, 0, 0};
+  double diag = 0.0;
+  float root_host[6] = {0, 0, 0, 0, 0, 0};
+  std::vector<int32_t> h_group, h_plane;
+  sbr::Buf nodes;    // float4[4] per internal node (T-1, at least 1 when T >= 1)
+  sbr::Buf root_box; // float[8]
+  sbr::Buf tri32;    // float4[3] per triangle in leaf order
+  sbr::Buf tri64;    // double[9] per triangle, original order, absolute coordinates
+  sbr::Buf tplane;   // double4 per triangle: n, c (absolute coordinates)
+  sbr::Buf tgroup;   // int per triangle
+  sbr::Buf tplaneid; // int per triangle
+  sbr::Buf gplane;   // double4 per group (plane of its lowest triangle)
+  sbr::Buf gmat;     // float4 per group: eps_r, sigma, rough, 0
+  sbr::Buf gstart;   // int[G+1]
+  sbr::Buf gtri;     // int[T]
+  sbr_scene_s() : Handle(sbr::kScene) {}
+  ~sbr_scene_s() override;
+};
+
+struct sbr_trace_s : sbr::Handle {
+  sbr_context_s* ctx = nullptr;
+  sbr_scene_s* scene = nullptr;
+  int Nt = 0, N = 0, K = 0;
+  int64_t R = 0, NR = 0;
+  std::vector<double> h_tx;
+  sbr::Buf tx;      // double[Nt][3]
+  sbr::Buf seq;     // int32[(K+1)][NR]
+  sbr::Buf counters; // uint32: per bounce {queue, n_in} ...
+  sbr::Buf work;     // uint64[2]: node visits, triangle tests (when counted)
+  bool counted = false;
+  int64_t segments = -1;  // host copy once read
+  sbr_trace_s() : Handle(sbr::kTrace) {}
+  ~sbr_trace_s() override;
+};
+
+struct sbr_paths_s : sbr::Handle {
+  sbr_context_s* ctx = nullptr;
+  sbr_trace_s* trace = nullptr;
+  int Nr = 0;
+  double alpha = 0, coeff = 1;
+  int64_t n_events = 0, n_keys = 0, n_paths = 0;
+  sbr::Buf rx;        // double[Nr][3]
+  sbr::Buf key;       // int32[n][4 + K]: tx, rx, k, flags, g_1..g_K
+  sbr::Buf geo;       // double[n][stride]
+  sbr::Buf info;      // double[n][2]: length, delay
+  sbr::Buf ang;       // float[n][4]: aod az/el, aoa az/el (deg)
+  sbr::Buf power;     // double[n] band-mean |a|^2
+  sbr::Buf seg_start; // int32[Nr*Nt + 1]
+  sbr::Buf ev_ray;    // uint32[n_events] capture events (kept for diagnostics)
+  sbr::Buf ev_qk;     // uint32[n_events]: rx << 5 | k
+  bool have_power = false;
+  sbr_paths_s() : Handle(sbr::kPaths) {}
+  ~sbr_paths_s() override;
+};
+
+namespace sbr {
+
+// ----------------------------------------------------------------- launchers
+// sort.hip
+size_t radix_sort_temp_bytes(int64_t n);
+// Stable LSD sort of (key, val) by key bits [bit_lo, bit_hi); results in
+// keys_out/vals_out (inputs are clobbered).  temp from radix_sort_temp_bytes.
+void radix_sort_pairs(uint64_t* keys_in, uint32_t* vals_in, uint64_t* keys_out, uint32_t* vals_out, int64_t n,
+                      int bit_lo, int bit_hi, void* temp, hipStream_t s);
+size_t scan_temp_bytes(int64_t n);
+// exclusive scan of uint32 (in place allowed); total written to *total_dev if non-null
+void exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total_dev, void* temp,
+                        hipStream_t s);
+void fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+void iota_u32(uint32_t* p, int64_t n, hipStream_t s);
+void gather_u64(const uint64_t* src, const uint32_t* idx, uint64_t* dst, int64_t n, hipStream_t s);
+
+// bvh.hip: LBVH over n primitives given their FP32 boxes (lo, hi) -> nodes,
+// leaf permutation (sorted position -> primitive), root box.  Returns depth.
+struct BvhOut {
+  float4* nodes;     // [max(n-1,1)][4]
+  uint32_t* order;   // [n] primitive of each leaf
+  float* root_box;   // [8]
+};
+int build_lbvh(const float* box_lo, const float* box_hi, int64_t n, const float scene_lo[3],
+               const float scene_hi[3], BvhOut out, hipStream_t s);
+
+// geodesic.hip
+void upload_geodesic_tables(int device);
+void launch_geodesic(int N, int64_t first, int64_t count, double* dirs, hipStream_t s);
+void geodesic_edge_stats(int N, double* mean, double* mn, double* mx, hipStream_t s);
+
+// trace.hip
+struct TraceLaunch {
+  const sbr_scene_s* scene;
+  const double* tx;
+  int Nt, N, K;
+  int64_t R, NR;
+  int32_t* seq;
+  uint32_t* counters;  // [2*(K+1)]: queue[k], n_in[k+1] (n_in[0] = NR)
+  unsigned long long* work;  // node visits, triangle tests, or null (no counting)
+  int grid, block;
+};
+void launch_trace(const TraceLaunch& L, void* ray_a, void* ray_b, hipStream_t s);
+size_t trace_ray_bytes(int64_t NR);
+
+// receive.hip
+void run_receive(sbr_paths_s* ps, hipStream_t s);
+
+// channel.hip
+struct ChannelArgs {
+  const double* freq;
+  const float* atm_db;
+  const float* atm_deg;
+  int Nf, pol_tx, pol_rx;
+};
+void run_channel(sbr_paths_s* ps, const ChannelArgs& a, float2* H64, double2* H128, hipStream_t s);
+void run_path_field(sbr_paths_s* ps, const ChannelArgs& a, double2* out, hipStream_t s);
+void run_stats(sbr_paths_s* ps, float* pg_db, float* tau, float* angles, hipStream_t s);
+void run_capacity(const float2* H, int Nf, int Nr, int Nt, const double* snr_db, int Nsnr, int normalize,
+                  double* C_out, hipStream_t s);
+
+}  // namespace sbr

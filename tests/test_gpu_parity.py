@@ -1,0 +1,240 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU FP64 oracle.
+
+Each case prints its name, seed and sizes before touching the GPU so a
+failing run names its case.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import oracle as O
+from paper_2208_10006_amd import workloads as W
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2208_10006_amd import sbr
+    return sbr
+
+
+@pytest.fixture(scope="module")
+def ctx(S):
+    return S.Context(0)
+
+
+def banner(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def exhaustive(N):
+    m, lo, hi = O.edge_stats(N)
+    return 1.05 * hi / m
+
+
+# ------------------------------------------------------------------ launch
+@pytest.mark.parametrize("N", [1, 2, 3, 7, 64])
+def test_geodesic_full(S, ctx, N):
+    banner("geodesic full", N)
+    g = S.sbr_geodesic(ctx, N)
+    o = O.geodesic(N)
+    assert np.max(np.abs(g - o)) <= 4e-16
+
+
+@pytest.mark.parametrize("N", [316, 1024])
+def test_geodesic_sampled(S, ctx, N):
+    banner("geodesic sampled", N)
+    R = 10 * N * N + 2
+    rng = np.random.default_rng(N)
+    for first in [0, 12, 12 + 30 * (N - 1) - 5, R - 4000] + list(rng.integers(0, R - 2000, 4)):
+        g = S.sbr_geodesic(ctx, N, int(first), 2000)
+        o = O.geodesic(N, int(first), 2000)
+        assert np.max(np.abs(g - o)) <= 4e-16, first
+
+
+@pytest.mark.parametrize("N", [1, 4, 64, 316])
+def test_alpha(S, ctx, N):
+    banner("alpha", N)
+    g = S.sbr_geodesic_alpha(ctx, N)
+    o = O.edge_stats(N)
+    for a, b in zip(g, o):
+        assert abs(a - b) <= 1e-13 * b
+
+
+# ------------------------------------------------------------------ scene
+@pytest.mark.parametrize("which", ["tiny_room", "random", "urban", "office"])
+def test_scene_groups(S, ctx, which):
+    banner("scene groups", which)
+    w = {"tiny_room": lambda: W.tiny_room(), "random": lambda: W.random_box_scene(5, n_boxes=12),
+         "urban": lambda: W.urban_canyon(), "office": lambda: W.massive_mimo_office()}[which]()
+    sc = S.sbr_scene_build(ctx, w.tri, w.eps_r, w.sigma, w.rough)
+    g, p = S.sbr_scene_groups(sc, w.T)
+    og, op, ng = O.scene_groups(w)
+    assert np.array_equal(g, og) and np.array_equal(p, op)
+    info = S.sbr_scene_info(sc)
+    assert info["groups"] == ng and 1 <= info["bvh_depth"] <= 64
+
+
+# ------------------------------------------------------------------ full parity cases
+def _full_case(S, ctx, w, coeff=None, pol=(0, 0), exact_keys=False):
+    from tests import parity as PT
+    g, _, _ = O.scene_groups(w)
+    gr = PT.gpu_run(ctx, w, coeff=coeff, pol_tx=pol[0], pol_rx=pol[1])
+    ora = O.run(w, coeff=coeff)
+    rep = PT.compare(w, gr, ora, g, pol_tx=pol[0], pol_rx=pol[1])
+    print(rep)
+    PT.assert_report(rep, allow_excused=not exact_keys)
+    assert gr.trace_info["segments"] == ora.trace.segments or rep.hit_excused > 0
+    return gr, ora, rep
+
+
+def test_tiny_room_full(S, ctx):
+    banner("tiny room (10x8x3 m, 12 tri, N=64, K=3, 28 GHz)")
+    w = W.tiny_room()
+    gr, ora, rep = _full_case(S, ctx, w)
+    assert gr.trace_info["segments"] == 163848
+    # derived outputs: PG, RMS delay spread, mean angles
+    from tests import parity as PT
+    pg, tau, ang = S.sbr_stats(gr.res.paths)
+    vk, rec = ora.keys[ora.valid], ora.rec[ora.valid]
+    opg, otau, oang = PT.oracle_stats(vk, rec, ora.a, 1, 1)
+    assert abs(pg[0, 0] - opg[0, 0]) < 1e-4
+    assert abs(tau[0, 0] - otau[0, 0]) <= 1e-5 * otau[0, 0]
+    assert np.max(np.abs(ang - oang)) < 2e-3
+    # per-path records: delay, angles, power
+    recs = gr.res.records
+    assert np.all(np.diff(recs["delay_s"]) >= 0)
+    assert np.allclose(recs["power"], np.mean(np.abs(gr.a) ** 2, axis=1), rtol=1e-6)
+
+
+def test_tiny_room_exhaustive_lattice(S, ctx):
+    banner("tiny room exhaustive sphere")
+    w = W.tiny_room()
+    gr, ora, rep = _full_case(S, ctx, w, coeff=exhaustive(64), exact_keys=True)
+    assert len(gr.keys) == 63
+    assert list(np.bincount([k[2] for k in gr.keys])) == [1, 6, 18, 38]
+
+
+@pytest.mark.parametrize("scene", ["free_space", "one_plane", "two_parallel_planes", "two_perpendicular_planes",
+                                   "diagonal"])
+def test_plane_scenes(S, ctx, scene):
+    banner("plane scene", scene)
+    if scene == "diagonal":  # specular point exactly on the edge shared by the wall's two triangles
+        w = W.one_plane(tx=(2.0, 10.0, 10.0), rx=(5.0, 10.0, 10.0), K=1, N=24)
+    else:
+        w = getattr(W, scene)()
+    _full_case(S, ctx, w, coeff=exhaustive(w.geodesic_N), exact_keys=True)
+
+
+@pytest.mark.parametrize("pol", [(0, 1), (1, 0), (1, 1)])
+def test_polarisations(S, ctx, pol):
+    banner("polarisation", pol)
+    w = W.random_box_scene(3, n_boxes=8, n_rx=3, N=20, K=2, freq=(28e9, 60e9))
+    _full_case(S, ctx, w, pol=pol)
+
+
+@pytest.mark.parametrize("seed,N,K,nrx", [(1, 24, 3, 6), (2, 40, 3, 10), (4, 32, 4, 5), (7, 17, 5, 3)])
+def test_random_scenes(S, ctx, seed, N, K, nrx):
+    banner("random scene", seed, N, K, nrx)
+    w = W.random_box_scene(seed, n_boxes=20, n_rx=nrx, N=N, K=K, freq=(28e9, 140e9, 300e9))
+    w.atm_db_per_m = np.array([0.0001, 0.002, 0.02], np.float32)
+    w.atm_deg_per_m = np.array([0.5, -1.0, 2.0], np.float32)
+    _full_case(S, ctx, w)
+
+
+@pytest.mark.slow
+def test_urban_reduced_full(S, ctx):
+    """Urban canyon geometry (2,402 triangles, 1,000 Rx, 256 subcarriers with
+    the synthetic atmosphere) at a reduced launch density, full oracle."""
+    banner("urban canyon N=48 K=6")
+    w = W.urban_canyon(N=48)
+    _full_case(S, ctx, w)
+
+
+@pytest.mark.slow
+def test_office_subset_full(S, ctx):
+    """Massive-MIMO office (5,004 triangles, 8x8 Rx UPA, 100 GHz) with two Tx
+    elements at a reduced density and 16 subcarriers, full oracle."""
+    banner("office 2 tx N=40 K=4")
+    w = W.massive_mimo_office(N=40, nf=16).subset_tx([0, 255])
+    _full_case(S, ctx, w)
+
+
+# ------------------------------------------------------------------ capacity
+@pytest.mark.parametrize("shape", [(1, 1, 1), (3, 4, 8), (5, 8, 4), (2, 64, 64), (2, 16, 128)])
+def test_capacity(S, ctx, shape):
+    banner("capacity", shape)
+    rng = np.random.default_rng(sum(shape))
+    H = ((rng.normal(size=shape) + 1j * rng.normal(size=shape)) * 1e-5).astype(np.complex64)
+    snr = np.arange(0, 31, 5, dtype=np.float64)
+    c = S.sbr_capacity(ctx, H, snr, normalize=1)
+    o = O.capacity(H.astype(np.complex128), snr, normalize=True)
+    assert np.allclose(c, o, rtol=1e-9, atol=1e-12), (c, o)
+    # raw mode (no normalisation): scale H so SNR |h|^2 is O(1)
+    Hs = (H * 1e5).astype(np.complex64)
+    c = S.sbr_capacity(ctx, Hs, snr, normalize=0)
+    o = O.capacity(Hs.astype(np.complex128), snr, normalize=False)
+    assert np.allclose(c, o, rtol=1e-9, atol=1e-12), (c, o)
+
+
+# ------------------------------------------------------------------ errors, determinism, device I/O
+def test_error_paths(S, ctx):
+    banner("error paths")
+    w = W.tiny_room()
+    bad = w.tri.copy()
+    bad[3, 1, 2] = np.nan
+    with pytest.raises(S.SbrError) as e:
+        S.sbr_scene_build(ctx, bad, w.eps_r, w.sigma, w.rough)
+    assert e.value.status == -1
+    with pytest.raises(S.SbrError):
+        S.sbr_scene_build(ctx, w.tri, w.eps_r * 0.1, w.sigma, w.rough)
+    deg = w.tri.copy()
+    deg[5, 2] = deg[5, 1]
+    with pytest.raises(S.SbrError) as e:
+        S.sbr_scene_build(ctx, deg, w.eps_r, w.sigma, w.rough)
+    assert "5" in str(e.value)
+    sc = S.sbr_scene_build(ctx, w.tri, w.eps_r, w.sigma, w.rough)
+    for N, K in [(0, 3), (8, -1), (8, 17)]:
+        with pytest.raises(S.SbrError):
+            S.sbr_trace(ctx, sc, w.tx, N, K)
+    tr = S.sbr_trace(ctx, sc, w.tx, 8, 2)
+    with pytest.raises(S.SbrError):
+        S.sbr_receive(ctx, tr, w.tx)  # Rx on the Tx
+    ps = S.sbr_receive(ctx, tr, w.rx)
+    with pytest.raises(S.SbrError) as e:
+        S.sbr_stats(ps)
+    assert e.value.status == -5
+    with pytest.raises(S.SbrError):
+        S.sbr_channel(ctx, ps, np.array([-1.0]), H_c128=np.zeros((1, 1, 1), np.complex128))
+
+
+def test_determinism(S, ctx):
+    banner("determinism")
+    w = W.random_box_scene(9, n_boxes=15, n_rx=4, N=30, K=3, freq=(28e9, 100e9))
+    a = S.run_workload(ctx, w)
+    b = S.run_workload(ctx, w)
+    assert a.H.tobytes() == b.H.tobytes()
+    assert a.records.tobytes() == b.records.tobytes()
+
+
+def test_device_io_matches_host(S, ctx):
+    import torch
+    banner("device I/O")
+    w = W.random_box_scene(6, n_boxes=10, n_rx=3, N=20, K=2, freq=(28e9, 29e9, 30e9))
+    host = S.run_workload(ctx, w)
+    dev = torch.device("cuda", 0)
+    t = lambda x, dt: torch.as_tensor(np.ascontiguousarray(x), dtype=dt, device=dev)
+    sc = S.sbr_scene_build(ctx, t(w.tri, torch.float64), t(w.eps_r, torch.float32), t(w.sigma, torch.float32),
+                           t(w.rough, torch.float32))
+    tr = S.sbr_trace(ctx, sc, t(w.tx, torch.float64), w.geodesic_N, w.max_bounces)
+    ps = S.sbr_receive(ctx, tr, t(w.rx, torch.float64))
+    H = torch.zeros((3, 3, 1), dtype=torch.complex128, device=dev)
+    H64 = torch.zeros((3, 3, 1), dtype=torch.complex64, device=dev)
+    S.sbr_channel(ctx, ps, t(w.freq, torch.float64), H_c64=H64, H_c128=H)
+    S.sbr_synchronize(ctx)
+    assert np.array_equal(H.cpu().numpy(), host.H)
+    assert np.allclose(H64.cpu().numpy(), host.H, rtol=1e-6, atol=1e-12)

@@ -281,6 +281,18 @@ def test_sbr_finds_exactly_the_image_paths(scene):
         assert sum(len(s) == 2 for s in ref) == 1
 
 
+def test_reflection_on_shared_edge_is_valid():
+    """A specular point exactly on the diagonal that splits a wall into two
+    triangles belongs to the face (image method over the whole rectangle)."""
+    # plane x = 0 split along (y, z) = (-50, -40) -> (70, 60); (10, 10) is on that diagonal
+    w = W.one_plane(tx=(2.0, 10.0, 10.0), rx=(5.0, 10.0, 10.0), K=1, N=24)
+    res = O.run(w, coeff=exhaustive_coeff(24))
+    ks = res.keys[res.valid]
+    assert sorted(ks[:, 2]) == [0, 1]
+    rec = O.paths(w, np.array([[0, 0, 1, 0]], np.int32))
+    assert rec[0, 0] == 1.0 and abs(rec[0, 1] - 7.0) < 1e-14
+
+
 def test_box_image_lattice():
     g = gold("box_lattice.json")
     w = W.tiny_room()
