@@ -58,6 +58,21 @@ def step(S, ctx, w, d):
     return sc, tr, ps
 
 
+def committed_traffic(workload):
+    """HBM bytes per bounce launch from the committed counter summary, or None
+    when the kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_bounce_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+            return None
+    return (rec["fetch_bytes_per_step"] + rec["write_bytes_per_step"]) / rec["launches_per_step"]
+
+
 def cpu_baseline(w, target_s=15.0):
     """The oracle as it stands on a strided sample of the same launch:
     trace + receive + paths + field of every stride-th ray."""
@@ -152,10 +167,12 @@ def main():
     S.sbr_context_count_work(ctx, False)
     del sc, tr
     bounce_ms = kernels.get("bounce", {}).get("ms_per_step", float("nan"))
+    traffic = committed_traffic(w.name)
     flop = FLOP_PER_NODE * work["node_visits"] + FLOP_PER_TRI * work["tri_tests"]
     achieved = flop / (bounce_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "kernel": "k_bounce (closest-hit traversal + FP64 reflect + ballot compaction)",
                 "node_visits_per_step": work["node_visits"], "tri_tests_per_step": work["tri_tests"],
                 "ms_per_step": round(bounce_ms, 3)}
