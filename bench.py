@@ -150,7 +150,8 @@ def main():
     t1 = time.perf_counter()
     kernels = {}
     for name in ["bounce", "replay_capture", "rebuild", "channel", "keys", "sort", "scan", "order", "lbvh",
-                 "stats", "misc", "alpha"]:
+                 "stats", "misc", "alpha", "host:scene_build", "host:scene_inputs", "host:face_groups",
+                 "host:scene_upload", "host:rx_tree"]:
         ms, n = S.sbr_profile_query(ctx, name)
         if n:
             kernels[name] = {"ms_per_step": ms / args.steps, "launches_per_step": n / args.steps}

@@ -190,6 +190,15 @@ sbr_status sbr_profile_query(sbr_context_t ctx, const char* kernel, double* tota
 sbr_status sbr_context_count_work(sbr_context_t ctx, int enable);
 sbr_status sbr_trace_work(sbr_trace_t tr, int64_t* node_visits, int64_t* tri_tests);
 
+/* Launch tuning (see the autotuner in the Python package).  Keys:
+ *   "trace_blocks_per_cu"  resident 256-thread blocks per CU of the persistent
+ *                          bounce grid (1..32, default 4)
+ *   "trace_chunk"          rays a wave takes from its queue per atomic (multiple of 64, <= 4096)
+ *   "replay_block"         threads per block of the capture replay (64..1024)
+ * Unknown keys or out-of-range values: SBR_E_INVALID_ARG. */
+sbr_status sbr_context_set_tuning(sbr_context_t ctx, const char* key, int32_t value);
+sbr_status sbr_context_get_tuning(sbr_context_t ctx, const char* key, int32_t* value);
+
 /* Release any handle (context, scene, trace, paths); NULL is ignored. */
 void sbr_release(void* handle);
 const char* sbr_last_error(void);

@@ -178,6 +178,10 @@ int build_lbvh(const float* box_lo, const float* box_hi, int64_t n, const float 
   if (n == 1) {
     { ::sbr::TimedLaunch tl_("lbvh", s); hipLaunchKernelGGL(k_single_leaf, dim3(1), dim3(1), 0, s, box_lo, box_hi, out.nodes, out.order, out.root_box); }
     SBR_LAUNCH_CHECK();
+    if (out.root_host) {
+      SBR_HIP(hipMemcpyAsync(out.root_host, out.root_box, 24, hipMemcpyDeviceToHost, s));
+      SBR_HIP(hipStreamSynchronize(s));
+    }
     return 1;
   }
   Buf codes, codes2, idx, parents, flags, temp;
@@ -212,6 +216,7 @@ int build_lbvh(const float* box_lo, const float* box_hi, int64_t n, const float 
   SBR_LAUNCH_CHECK();
   uint32_t depth = 0;
   SBR_HIP(hipMemcpyAsync(&depth, dd, 4, hipMemcpyDeviceToHost, s));
+  if (out.root_host) SBR_HIP(hipMemcpyAsync(out.root_host, out.root_box, 24, hipMemcpyDeviceToHost, s));
   SBR_HIP(hipStreamSynchronize(s));
   return (int)depth;
 }

@@ -50,10 +50,10 @@ struct ReplayParams {
 };
 
 template <int STACK>
-__global__ __launch_bounds__(256) void k_replay_capture(const ReplayParams P) {
-  __shared__ int32_t stack_mem[256 / kWave][STACK][kWave];
+__global__ __launch_bounds__(1024) void k_replay_capture(const ReplayParams P) {
+  extern __shared__ int32_t stack_dyn[];  // [waves][STACK][64]
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  int32_t* stk = &stack_mem[wv][0][lane];
+  int32_t* stk = stack_dyn + (wv * STACK) * kWave + lane;
   const int64_t rid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (rid >= P.NR) return;
   const int p = (int)(rid / P.R);
@@ -172,8 +172,10 @@ __device__ inline int ev_groups(const KeyParams& P, int64_t e, int32_t* g) {
   return k;
 }
 
-__global__ void k_event_keys(const KeyParams P, uint64_t* __restrict__ hkey, uint32_t* __restrict__ vals,
-                             uint64_t* __restrict__ segkey) {
+// sort key of a capture: (segment = rx * Nt + tx) << 32 | 32-bit hash of the
+// face-group sequence.  Hash collisions only lengthen an equal-key run; the
+// dedup below compares the exact sequences inside each run.
+__global__ void k_event_keys(const KeyParams P, uint64_t* __restrict__ key, uint32_t* __restrict__ vals) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= P.n) return;
   int32_t g[SBR_MAX_BOUNCES];
@@ -183,15 +185,13 @@ __global__ void k_event_keys(const KeyParams P, uint64_t* __restrict__ hkey, uin
   const uint32_t rid = P.ev_ray[e];
   const int64_t p = rid / P.R;
   const uint64_t q = P.ev_qk[e] >> 5;
-  hkey[e] = h;
+  key[e] = ((q * (uint64_t)P.Nt + (uint64_t)p) << 32) | (uint32_t)(h ^ (h >> 32));
   vals[e] = (uint32_t)e;
-  segkey[e] = q * (uint64_t)P.Nt + (uint64_t)p;
 }
 
-// head flag: first occurrence of its exact key within its (segment, hash) run
+// head flag: first occurrence of its exact key within its equal-sort-key run
 __global__ void k_unique_heads(const KeyParams P, const uint32_t* __restrict__ perm,
-                               const uint64_t* __restrict__ seg_sorted, const uint64_t* __restrict__ hkey,
-                               uint32_t* __restrict__ head) {
+                               const uint64_t* __restrict__ key_sorted, uint32_t* __restrict__ head) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= P.n) return;
   const uint32_t e = perm[i];
@@ -199,8 +199,8 @@ __global__ void k_unique_heads(const KeyParams P, const uint32_t* __restrict__ p
   int32_t g[SBR_MAX_BOUNCES], g2[SBR_MAX_BOUNCES];
   int k = -1;
   for (int64_t j = i - 1; j >= 0; --j) {
+    if (key_sorted[j] != key_sorted[i]) break;
     const uint32_t e2 = perm[j];
-    if (seg_sorted[j] != seg_sorted[i] || hkey[e2] != hkey[e]) break;
     if (k < 0) k = ev_groups(P, e, g);
     const int k2 = ev_groups(P, e2, g2);
     bool same = k2 == k;
@@ -445,15 +445,41 @@ __global__ __launch_bounds__(128) void k_rebuild(const RebuildParams P) {
 }
 
 // ---------------------------------------------------------------- ordering
+// order key of a valid path: segment << 32 | FP32 bits of its delay (positive
+// floats order like their bit patterns); equal keys are resolved afterwards by
+// the exact FP64 delay
 __global__ void k_valid_keys(const uint32_t* __restrict__ valid, const uint32_t* __restrict__ pos,
                              const uint64_t* __restrict__ seg, const double* __restrict__ info, int64_t n,
-                             uint64_t* __restrict__ dkey, uint32_t* __restrict__ didx, uint64_t* __restrict__ vseg) {
+                             uint64_t* __restrict__ okey, uint32_t* __restrict__ oidx) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n || !valid[i]) return;
   const uint32_t j = pos[i];
-  dkey[j] = (uint64_t)__double_as_longlong(info[2 * i + 1]);  // delay >= 0: bit order = numeric order
-  didx[j] = (uint32_t)i;
-  vseg[j] = seg[i];
+  okey[j] = (seg[i] << 32) | (uint32_t)__float_as_uint((float)info[2 * i + 1]);
+  oidx[j] = (uint32_t)i;
+}
+
+// Paths whose FP32 delays tie (equal sort keys) are put in exact FP64 delay
+// order, ties broken by key index: the run starting at i is insertion-sorted
+// by the thread that owns its first element.
+__global__ void k_fix_delay_ties(const uint64_t* __restrict__ key, const double* __restrict__ info, int64_t n,
+                                 uint32_t* __restrict__ order) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || (i > 0 && key[i - 1] == key[i])) return;
+  int64_t e = i + 1;
+  while (e < n && key[e] == key[i]) ++e;
+  for (int64_t a = i + 1; a < e; ++a) {
+    const uint32_t v = order[a];
+    const double dv = info[2 * (int64_t)v + 1];
+    int64_t b = a - 1;
+    while (b >= i) {
+      const uint32_t u = order[b];
+      const double du = info[2 * (int64_t)u + 1];
+      if (du < dv || (du == dv && u < v)) break;
+      order[b + 1] = u;
+      --b;
+    }
+    order[b + 1] = v;
+  }
 }
 
 __global__ void k_gather_paths(const uint32_t* __restrict__ order, int64_t n, int stride, int K,
@@ -496,6 +522,7 @@ void run_receive(sbr_paths_s* ps, hipStream_t s) {
   sbr_scene_s* sc = tr->scene;
   const int Nr = ps->Nr, Nt = tr->Nt, K = tr->K;
   // ---------------- Rx LBVH (FP32 boxes in a frame centred on the Rx bounding sphere)
+  HostPhase hp_rx("host:rx_tree");
   std::vector<double> hrx(3 * (size_t)Nr);
   SBR_HIP(hipMemcpyAsync(hrx.data(), ps->rx.p, hrx.size() * 8, hipMemcpyDeviceToHost, s));
   SBR_HIP(hipStreamSynchronize(s));
@@ -528,13 +555,11 @@ void run_receive(sbr_paths_s* ps, hipStream_t s) {
   rnodes.alloc((size_t)std::max(Nr - 1, 1) * 64, s);
   rorder.alloc((size_t)Nr * 4, s);
   rroot.alloc(32, s);
+  float hroot[8];
   const int rdepth =
       build_lbvh(dlo.as<float>(), dhi.as<float>(), Nr, flo, fhi, BvhOut{rnodes.as<float4>(), rorder.as<uint32_t>(),
-                                                                         rroot.as<float>()}, s);
+                                                                         rroot.as<float>(), hroot}, s);
   SBR_CHECK(rdepth <= 64, SBR_E_UNSUPPORTED, "receiver tree depth %d", rdepth);
-  float hroot[8];
-  SBR_HIP(hipMemcpyAsync(hroot, rroot.p, 24, hipMemcpyDeviceToHost, s));
-  SBR_HIP(hipStreamSynchronize(s));
 
   // ---------------- replay + capture (grow the event buffer and retry on overflow)
   ReplayParams P{};
@@ -565,13 +590,16 @@ void run_receive(sbr_paths_s* ps, hipStream_t s) {
     P.ev_cap = cap;
     P.ev_ray = ev_ray.as<uint32_t>();
     P.ev_qk = ev_qk.as<uint32_t>();
-    const unsigned g = nblk(tr->NR, 256);
+    const int rb = ps->ctx->tune.replay_block;
+    const unsigned g = nblk(tr->NR, rb);
+    const size_t lds = (size_t)(rb / kWave) * kWave * sizeof(int32_t) * (rdepth <= 16 ? 16 : rdepth <= 32 ? 32 : 64);
+    ::sbr::TimedLaunch tl_("replay_capture", s);
     if (rdepth <= 16)
-      { ::sbr::TimedLaunch tl_("replay_capture", s); hipLaunchKernelGGL(k_replay_capture<16>, dim3(g), dim3(256), 0, s, P); }
+      hipLaunchKernelGGL(k_replay_capture<16>, dim3(g), dim3(rb), lds, s, P);
     else if (rdepth <= 32)
-      { ::sbr::TimedLaunch tl_("replay_capture", s); hipLaunchKernelGGL(k_replay_capture<32>, dim3(g), dim3(256), 0, s, P); }
+      hipLaunchKernelGGL(k_replay_capture<32>, dim3(g), dim3(rb), lds, s, P);
     else
-      { ::sbr::TimedLaunch tl_("replay_capture", s); hipLaunchKernelGGL(k_replay_capture<64>, dim3(g), dim3(256), 0, s, P); }
+      hipLaunchKernelGGL(k_replay_capture<64>, dim3(g), dim3(rb), lds, s, P);
     SBR_LAUNCH_CHECK();
     SBR_HIP(hipMemcpyAsync(&n_ev, cnt.p, 4, hipMemcpyDeviceToHost, s));
     SBR_HIP(hipStreamSynchronize(s));
@@ -591,31 +619,22 @@ void run_receive(sbr_paths_s* ps, hipStream_t s) {
     fill_u32(ps->seg_start.as<uint32_t>(), 0, nseg + 1, s);
     return;
   }
-  // ---------------- keys, sort by (segment, hash), exact dedup
+  // ---------------- keys, one sort by (segment, hash), exact dedup
   KeyParams kp{ev_ray.as<uint32_t>(), ev_qk.as<uint32_t>(), tr->seq.as<int32_t>(), sc->tgroup.as<int32_t>(),
                tr->R, tr->NR, Nt, E};
-  Buf hk, hk2, v1, v2, sk, sk2, temp;
-  hk.alloc(E * 8, s), hk2.alloc(E * 8, s), v1.alloc(E * 4, s), v2.alloc(E * 4, s);
-  sk.alloc(E * 8, s), sk2.alloc(E * 8, s);
-  temp.alloc(std::max(radix_sort_temp_bytes(E), scan_temp_bytes(E)), s);
-  { ::sbr::TimedLaunch tl_("keys", s); hipLaunchKernelGGL(k_event_keys, dim3(nblk(E, 256)), dim3(256), 0, s, kp, hk.as<uint64_t>(), v1.as<uint32_t>(),
-                     sk.as<uint64_t>()); }
-  SBR_LAUNCH_CHECK();
-  // stage 1: by hash (64 bits) -> permutation in v2
-  radix_sort_pairs(hk.as<uint64_t>(), v1.as<uint32_t>(), hk2.as<uint64_t>(), v2.as<uint32_t>(), E, 0, 64, temp.p, s);
-  // hk was clobbered: rebuild hash per event
-  { ::sbr::TimedLaunch tl_("keys", s); hipLaunchKernelGGL(k_event_keys, dim3(nblk(E, 256)), dim3(256), 0, s, kp, hk.as<uint64_t>(), v1.as<uint32_t>(),
-                     sk.as<uint64_t>()); }
-  // stage 2: stable by segment
-  gather_u64(sk.as<uint64_t>(), v2.as<uint32_t>(), sk2.as<uint64_t>(), E, s);
   const int sbits = std::max(1, bits_for((uint64_t)nseg));
-  radix_sort_pairs(sk2.as<uint64_t>(), v2.as<uint32_t>(), hk2.as<uint64_t>(), v1.as<uint32_t>(), E, 0, sbits, temp.p,
-                   s);
-  // now: v1 = event permutation, hk2 = sorted segment ids, hk = hash per event
+  Buf k1, k2, v1, v2, temp;
+  k1.alloc(E * 8, s), k2.alloc(E * 8, s), v1.alloc(E * 4, s), v2.alloc(E * 4, s);
+  temp.alloc(std::max(radix_sort_temp_bytes(E), scan_temp_bytes(E)), s);
+  { ::sbr::TimedLaunch tl_("keys", s); hipLaunchKernelGGL(k_event_keys, dim3(nblk(E, 256)), dim3(256), 0, s, kp, k1.as<uint64_t>(), v1.as<uint32_t>()); }
+  SBR_LAUNCH_CHECK();
+  radix_sort_pairs(k1.as<uint64_t>(), v1.as<uint32_t>(), k2.as<uint64_t>(), v2.as<uint32_t>(), E, 0, 32 + sbits,
+                   temp.p, s);
+  // now: v2 = event permutation, k2 = sorted keys
   Buf head, pos, tot;
   head.alloc(E * 4, s), pos.alloc(E * 4, s), tot.alloc(8, s);
-  { ::sbr::TimedLaunch tl_("keys", s); hipLaunchKernelGGL(k_unique_heads, dim3(nblk(E, 256)), dim3(256), 0, s, kp, v1.as<uint32_t>(), hk2.as<uint64_t>(),
-                     hk.as<uint64_t>(), head.as<uint32_t>()); }
+  { ::sbr::TimedLaunch tl_("keys", s); hipLaunchKernelGGL(k_unique_heads, dim3(nblk(E, 256)), dim3(256), 0, s, kp, v2.as<uint32_t>(), k2.as<uint64_t>(),
+                     head.as<uint32_t>()); }
   SBR_LAUNCH_CHECK();
   exclusive_scan_u32(head.as<uint32_t>(), pos.as<uint32_t>(), E, tot.as<uint32_t>(), temp.p, s);
   uint32_t n_keys = 0;
@@ -624,7 +643,7 @@ void run_receive(sbr_paths_s* ps, hipStream_t s) {
   ps->n_keys = n_keys;
   Buf key_event;
   key_event.alloc((size_t)n_keys * 4, s);
-  { ::sbr::TimedLaunch tl_("keys", s); hipLaunchKernelGGL(k_compact_heads, dim3(nblk(E, 256)), dim3(256), 0, s, v1.as<uint32_t>(), head.as<uint32_t>(),
+  { ::sbr::TimedLaunch tl_("keys", s); hipLaunchKernelGGL(k_compact_heads, dim3(nblk(E, 256)), dim3(256), 0, s, v2.as<uint32_t>(), head.as<uint32_t>(),
                      pos.as<uint32_t>(), E, key_event.as<uint32_t>()); }
   SBR_LAUNCH_CHECK();
   // ---------------- exact rebuild + validation
@@ -683,22 +702,20 @@ void run_receive(sbr_paths_s* ps, hipStream_t s) {
     return;
   }
   // ---------------- order by (segment, delay)
-  Buf dk, dk2, di, di2, vseg, vseg2, fseg;
-  dk.alloc(np * 8, s), dk2.alloc(np * 8, s), di.alloc(np * 4, s), di2.alloc(np * 4, s);
-  vseg.alloc(np * 8, s), vseg2.alloc(np * 8, s), fseg.alloc(np * 8, s);
+  Buf ok1, ok2, oi1, oi2, fseg;
+  ok1.alloc(np * 8, s), ok2.alloc(np * 8, s), oi1.alloc(np * 4, s), oi2.alloc(np * 4, s), fseg.alloc(np * 8, s);
   { ::sbr::TimedLaunch tl_("order", s); hipLaunchKernelGGL(k_valid_keys, dim3(nblk(nk, 256)), dim3(256), 0, s, valid.as<uint32_t>(), pos.as<uint32_t>(),
-                     seg.as<uint64_t>(), info.as<double>(), nk, dk.as<uint64_t>(), di.as<uint32_t>(),
-                     vseg.as<uint64_t>()); }
+                     seg.as<uint64_t>(), info.as<double>(), nk, ok1.as<uint64_t>(), oi1.as<uint32_t>()); }
   SBR_LAUNCH_CHECK();
   Buf ptemp;
   ptemp.alloc(radix_sort_temp_bytes(np), s);
-  radix_sort_pairs(dk.as<uint64_t>(), di.as<uint32_t>(), dk2.as<uint64_t>(), di2.as<uint32_t>(), np, 0, 64, ptemp.p, s);
-  // segment of each delay-sorted entry: seg[di2[i]] (seg indexed by key)
-  gather_u64(seg.as<uint64_t>(), di2.as<uint32_t>(), vseg2.as<uint64_t>(), np, s);
-  radix_sort_pairs(vseg2.as<uint64_t>(), di2.as<uint32_t>(), vseg.as<uint64_t>(), di.as<uint32_t>(), np, 0, sbits,
+  radix_sort_pairs(ok1.as<uint64_t>(), oi1.as<uint32_t>(), ok2.as<uint64_t>(), oi2.as<uint32_t>(), np, 0, 32 + sbits,
                    ptemp.p, s);
-  // di = key index of each final path
-  { ::sbr::TimedLaunch tl_("order", s); hipLaunchKernelGGL(k_gather_paths, dim3(nblk(np, 256)), dim3(256), 0, s, di.as<uint32_t>(), np, stride, K,
+  uint32_t* order_idx = oi2.as<uint32_t>();
+  { ::sbr::TimedLaunch tl_("order", s); hipLaunchKernelGGL(k_fix_delay_ties, dim3(nblk(np, 256)), dim3(256), 0, s, ok2.as<uint64_t>(), info.as<double>(), np, order_idx); }
+  SBR_LAUNCH_CHECK();
+  // order_idx = key index of each final path
+  { ::sbr::TimedLaunch tl_("order", s); hipLaunchKernelGGL(k_gather_paths, dim3(nblk(np, 256)), dim3(256), 0, s, order_idx, np, stride, K,
                      geo.as<double>(), info.as<double>(), ang.as<float>(), key.as<int32_t>(), ps->geo.as<double>(),
                      ps->info.as<double>(), ps->ang.as<float>(), ps->key.as<int32_t>(), seg.as<uint64_t>(),
                      fseg.as<uint64_t>()); }

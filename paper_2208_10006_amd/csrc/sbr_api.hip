@@ -1,6 +1,7 @@
 // sbr_api.hip -- the C-ABI of libsbr: handles, validation, host-side face
 // grouping, buffer management and the order of kernel launches.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -61,6 +62,26 @@ TimedLaunch::~TimedLaunch() {
     g_prof->pending.push_back(Prof::Pending{name, a, b});
   }
 }
+static double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+void prof_add(const char* name, double ms) {
+  if (!g_prof || !g_prof->enabled) return;
+  for (auto& e : g_prof->acc)
+    if (e.first == name) {
+      e.second.first += ms;
+      e.second.second += 1;
+      return;
+    }
+  g_prof->acc.push_back({name, {ms, 1}});
+}
+HostPhase::HostPhase(const char* n) : name(n) {
+  if (g_prof && g_prof->enabled) t0 = now_ms();
+}
+HostPhase::~HostPhase() {
+  if (g_prof && g_prof->enabled) prof_add(name, now_ms() - t0);
+}
+
 void Prof::resolve() {
   for (auto& p : pending) {
     float ms = 0.0f;
@@ -149,6 +170,34 @@ void upload(Buf& b, const T* p, size_t n, uint32_t flags, hipStream_t s) {
   }
 }
 
+// Host->device uploads of host-built arrays go through one pinned staging
+// area owned by the context: each array is memcpy'd into it and copied
+// asynchronously; the caller synchronises the stream before the staging area
+// is written again.
+struct Stager {
+  sbr_context_s* c;
+  size_t off = 0;
+  explicit Stager(sbr_context_s* cc) : c(cc) {}
+  template <class T>
+  void put(Buf& b, const T* src, size_t n, hipStream_t s) {
+    b.alloc(n * sizeof(T), s);
+    if (n == 0) return;
+    const size_t bytes = n * sizeof(T);
+    const size_t at = (off + 255) & ~size_t(255);
+    if (at + bytes > c->stage_bytes) {
+      SBR_CHECK(off == 0, SBR_E_DEVICE, "staging area resized while in use");
+      if (c->stage) (void)hipHostFree(c->stage);
+      c->stage = nullptr;
+      c->stage_bytes = 0;
+      SBR_HIP(hipHostMalloc(&c->stage, at + bytes + (1 << 20), hipHostMallocDefault));
+      c->stage_bytes = at + bytes + (1 << 20);
+    }
+    std::memcpy(static_cast<char*>(c->stage) + at, src, bytes);
+    SBR_HIP(hipMemcpyAsync(b.p, static_cast<char*>(c->stage) + at, bytes, hipMemcpyHostToDevice, s));
+    off = at + bytes;
+  }
+};
+
 void set_device(sbr_context_s* c) {
   SBR_HIP(hipSetDevice(c->device));
   g_prof = &c->prof;
@@ -185,38 +234,65 @@ void uf_join(std::vector<int>& p, int a, int b) {
 }
 
 // Pairs with |n_a . n_b| >= 1 - 1e-12 and matching offsets (1e-9 diag) share a
-// plane; with equal materials also a group.  Candidate pairs come from a hash
-// grid over (n, c) whose cells are wider than both tolerances, probing the
-// 3^4 neighbouring cells of (n, c) and of (-n, -c).
+// plane; with equal materials also a group (transitive closure, ids in order
+// of the lowest triangle).  Candidate pairs come from a hash grid over the
+// sign-canonical (n, c) with cells far wider than the tolerances; a triangle
+// probes a neighbouring cell only along a dimension where it lies within the
+// tolerance of the cell border, and also probes (-n, -c) when its largest
+// normal component is not clearly the largest.
 void face_groups(const std::vector<Plane>& pl, const float* eps, const float* sig, const float* rough, double diag,
                  std::vector<int32_t>& group, std::vector<int32_t>& plane, int& ngroups, int& nplanes) {
   const int T = (int)pl.size();
-  const double hn = 4e-6, hc = std::max(4e-9 * diag, 1e-300);
+  const double tol_n = 2e-6;  // |n_a - n_b| <= 1.42e-6 when n_a . n_b >= 1 - 1e-12
+  const double tol_c = 1e-9 * diag * (1.0 + 1e-9) + 1e-300;
+  const double hn = 1.0 / 1024.0, hc = std::max(1e-3 * diag, 1e-300);
+  struct Canon {
+    double v[4];
+    bool ambiguous;
+  };
+  std::vector<Canon> cn(T);
+  for (int t = 0; t < T; ++t) {
+    const double* n = pl[t].n;
+    int imax = 0;
+    for (int k = 1; k < 3; ++k)
+      if (std::fabs(n[k]) > std::fabs(n[imax])) imax = k;
+    double second = 0.0;
+    for (int k = 0; k < 3; ++k)
+      if (k != imax) second = std::max(second, std::fabs(n[k]));
+    const double sgn = n[imax] < 0 ? -1.0 : 1.0;
+    cn[t] = Canon{{sgn * n[0], sgn * n[1], sgn * n[2], sgn * pl[t].c}, std::fabs(n[imax]) - second < 4 * tol_n};
+  }
+  auto cell = [&](const double* v, int k) { return (int64_t)std::floor(v[k] / (k < 3 ? hn : hc)); };
   std::unordered_map<Key4, std::vector<int>, Key4Hash> grid;
   grid.reserve(T * 2 + 1);
-  auto key = [&](const double* n, double c) {
-    return Key4{(int64_t)std::floor(n[0] / hn), (int64_t)std::floor(n[1] / hn), (int64_t)std::floor(n[2] / hn),
-                (int64_t)std::floor(c / hc)};
-  };
-  for (int t = 0; t < T; ++t) grid[key(pl[t].n, pl[t].c)].push_back(t);
+  for (int t = 0; t < T; ++t) grid[Key4{cell(cn[t].v, 0), cell(cn[t].v, 1), cell(cn[t].v, 2), cell(cn[t].v, 3)}].push_back(t);
   std::vector<int> pp(T), pg(T);
   for (int t = 0; t < T; ++t) pp[t] = pg[t] = t;
   for (int a = 0; a < T; ++a) {
-    for (int sgn = -1; sgn <= 1; sgn += 2) {
-      const double n[3] = {sgn * pl[a].n[0], sgn * pl[a].n[1], sgn * pl[a].n[2]};
-      const Key4 k0 = key(n, sgn * pl[a].c);
-      for (int dx = -1; dx <= 1; ++dx)
-        for (int dy = -1; dy <= 1; ++dy)
-          for (int dz = -1; dz <= 1; ++dz)
-            for (int dc = -1; dc <= 1; ++dc) {
-              auto it = grid.find(Key4{k0.a + dx, k0.b + dy, k0.c + dz, k0.d + dc});
+    for (int flip = 0; flip < (cn[a].ambiguous ? 2 : 1); ++flip) {
+      double v[4];
+      for (int k = 0; k < 4; ++k) v[k] = flip ? -cn[a].v[k] : cn[a].v[k];
+      int64_t base[4];
+      int lo[4], hi[4];
+      for (int k = 0; k < 4; ++k) {
+        const double h = k < 3 ? hn : hc, tol = k < 3 ? tol_n : tol_c;
+        base[k] = cell(v, k);
+        const double f = v[k] / h - (double)base[k];
+        lo[k] = f * h <= tol ? -1 : 0;
+        hi[k] = (1.0 - f) * h <= tol ? 1 : 0;
+      }
+      for (int dx = lo[0]; dx <= hi[0]; ++dx)
+        for (int dy = lo[1]; dy <= hi[1]; ++dy)
+          for (int dz = lo[2]; dz <= hi[2]; ++dz)
+            for (int dc = lo[3]; dc <= hi[3]; ++dc) {
+              auto it = grid.find(Key4{base[0] + dx, base[1] + dy, base[2] + dz, base[3] + dc});
               if (it == grid.end()) continue;
               for (int b : it->second) {
-                if (b <= a) continue;
+                if (b == a) continue;
                 const double nd = pl[a].n[0] * pl[b].n[0] + pl[a].n[1] * pl[b].n[1] + pl[a].n[2] * pl[b].n[2];
                 if (std::fabs(nd) < 1.0 - 1e-12) continue;
-                const double s = nd > 0 ? 1.0 : -1.0;
-                if (std::fabs(pl[a].c - s * pl[b].c) > 1e-9 * diag) continue;
+                const double sg = nd > 0 ? 1.0 : -1.0;
+                if (std::fabs(pl[a].c - sg * pl[b].c) > 1e-9 * diag) continue;
                 uf_join(pp, a, b);
                 if (eps[a] == eps[b] && sig[a] == sig[b] && rough[a] == rough[b]) uf_join(pg, a, b);
               }
@@ -284,6 +360,7 @@ using namespace sbr;
 
 sbr_context_s::~sbr_context_s() {
   if (stream) (void)hipStreamSynchronize(stream);
+  if (stage) (void)hipHostFree(stage);
   prof.clear();
   if (g_prof == &prof) g_prof = nullptr;
   if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -366,10 +443,16 @@ sbr_status sbr_scene_build(sbr_context_t ctx, const double* tri_xyz, int64_t T, 
     SBR_CHECK(T >= 0 && T < (int64_t(1) << 30), SBR_E_INVALID_ARG, "triangle count %lld", (long long)T);
     set_device(c);
     hipStream_t s = c->stream;
-    const auto tri = to_host(tri_xyz, (size_t)T * 9, flags, s);
-    const auto er = to_host(eps_r, (size_t)T, flags, s);
-    const auto sg = to_host(sigma, (size_t)T, flags, s);
-    const auto rh = to_host(rough, (size_t)T, flags, s);
+    HostPhase hp_all("host:scene_build");
+    std::vector<double> tri;
+    std::vector<float> er, sg, rh;
+    {
+      HostPhase hp("host:scene_inputs");
+      tri = to_host(tri_xyz, (size_t)T * 9, flags, s);
+      er = to_host(eps_r, (size_t)T, flags, s);
+      sg = to_host(sigma, (size_t)T, flags, s);
+      rh = to_host(rough, (size_t)T, flags, s);
+    }
     SBR_CHECK(finite_all(tri.data(), tri.size()), SBR_E_INVALID_ARG, "triangle coordinates must be finite");
     for (int64_t t = 0; t < T; ++t) {
       SBR_CHECK(std::isfinite(er[t]) && er[t] >= 1.0f, SBR_E_INVALID_ARG, "eps_r[%lld] = %g (needs >= 1)",
@@ -404,8 +487,11 @@ sbr_status sbr_scene_build(sbr_context_t ctx, const double* tri_xyz, int64_t T, 
         const d3 n = nn * (1.0 / area2);
         pl[t] = Plane{{n.x, n.y, n.z}, dot(n, a)};
       }
-      face_groups(pl, er.data(), sg.data(), rh.data(), sc->diag, sc->h_group, sc->h_plane, sc->n_groups,
-                  sc->n_planes);
+      {
+        HostPhase hp("host:face_groups");
+        face_groups(pl, er.data(), sg.data(), rh.data(), sc->diag, sc->h_group, sc->h_plane, sc->n_groups,
+                    sc->n_planes);
+      }
       if (T == 0) {
         sc->gstart.alloc(4, s);
         fill_u32(sc->gstart.as<uint32_t>(), 0, 1, s);
@@ -450,29 +536,41 @@ sbr_status sbr_scene_build(sbr_context_t ctx, const double* tri_xyz, int64_t T, 
         }
       }
       Buf dv32, dlo, dhi, order;
-      upload(sc->tri64, tri.data(), tri.size(), 0, s);
-      upload(sc->tplane, tpl.data(), tpl.size(), 0, s);
-      upload(sc->tgroup, sc->h_group.data(), sc->h_group.size(), 0, s);
-      upload(sc->tplaneid, sc->h_plane.data(), sc->h_plane.size(), 0, s);
-      upload(sc->gplane, gpl.data(), gpl.size(), 0, s);
-      upload(sc->gmat, gmt.data(), gmt.size(), 0, s);
-      upload(sc->gstart, gstart.data(), gstart.size(), 0, s);
-      upload(sc->gtri, gtri.data(), gtri.size(), 0, s);
-      upload(dv32, v32.data(), v32.size(), 0, s);
-      upload(dlo, blo.data(), blo.size(), 0, s);
-      upload(dhi, bhi.data(), bhi.size(), 0, s);
+      HostPhase hp_up("host:scene_upload");
+      // staging must hold everything before the first copy is issued (it is not resized in use)
+      const size_t need = tri.size() * 8 + tpl.size() * 32 + 2 * sc->h_group.size() * 4 + gpl.size() * 32 +
+                          gmt.size() * 16 + gstart.size() * 4 + gtri.size() * 4 + (v32.size() + 6 * T) * 4 + 16 * 256;
+      if (c->stage_bytes < need) {
+        if (c->stage) (void)hipHostFree(c->stage);
+        c->stage = nullptr;
+        c->stage_bytes = 0;
+        SBR_HIP(hipHostMalloc(&c->stage, need, hipHostMallocDefault));
+        c->stage_bytes = need;
+      }
+      Stager st(c);
+      st.put(sc->tri64, tri.data(), tri.size(), s);
+      st.put(sc->tplane, tpl.data(), tpl.size(), s);
+      st.put(sc->tgroup, sc->h_group.data(), sc->h_group.size(), s);
+      st.put(sc->tplaneid, sc->h_plane.data(), sc->h_plane.size(), s);
+      st.put(sc->gplane, gpl.data(), gpl.size(), s);
+      st.put(sc->gmat, gmt.data(), gmt.size(), s);
+      st.put(sc->gstart, gstart.data(), gstart.size(), s);
+      st.put(sc->gtri, gtri.data(), gtri.size(), s);
+      st.put(dv32, v32.data(), v32.size(), s);
+      st.put(dlo, blo.data(), blo.size(), s);
+      st.put(dhi, bhi.data(), bhi.size(), s);
       sc->nodes.alloc((size_t)std::max<int64_t>(T - 1, 1) * 64, s);
       sc->root_box.alloc(32, s);
       order.alloc((size_t)T * 4, s);
       sc->bvh_depth = build_lbvh(dlo.as<float>(), dhi.as<float>(), T, slo, shi,
-                                 BvhOut{sc->nodes.as<float4>(), order.as<uint32_t>(), sc->root_box.as<float>()}, s);
+                                 BvhOut{sc->nodes.as<float4>(), order.as<uint32_t>(), sc->root_box.as<float>(),
+                                        sc->root_host}, s);
       SBR_CHECK(sc->bvh_depth <= 64, SBR_E_UNSUPPORTED, "BVH depth %d exceeds the traversal stack", sc->bvh_depth);
       sc->tri32.alloc((size_t)T * 48, s);
       hipLaunchKernelGGL(k_tri_gather, dim3(nblk(T, 256)), dim3(256), 0, s, order.as<uint32_t>(), T,
                          dv32.as<float>(), sc->tplaneid.as<int32_t>(), sc->tgroup.as<int32_t>(),
                          sc->tri32.as<float4>());
       SBR_LAUNCH_CHECK();
-      SBR_HIP(hipMemcpyAsync(sc->root_host, sc->root_box.p, 24, hipMemcpyDeviceToHost, s));
       SBR_HIP(hipStreamSynchronize(s));
     } catch (...) {
       release(sc);
@@ -524,7 +622,7 @@ sbr_status sbr_trace(sbr_context_t ctx, sbr_scene_t scene, const double* tx_xyz,
       tr->h_tx = htx;
       upload(tr->tx, tr->h_tx.data(), tr->h_tx.size(), 0, s);
       tr->seq.alloc((size_t)(K + 1) * tr->NR * 4, s);
-      tr->counters.alloc((size_t)2 * (K + 1) * 4, s);
+      tr->counters.alloc((size_t)trace_counter_words(K) * 4, s);
       Buf ra, rb;
       ra.alloc(trace_ray_bytes(tr->NR), s);
       if (K > 0) rb.alloc(trace_ray_bytes(tr->NR), s);
@@ -541,6 +639,7 @@ sbr_status sbr_trace(sbr_context_t ctx, sbr_scene_t scene, const double* tx_xyz,
       }
       L.block = 256;
       L.grid = c->num_cus * c->tune.trace_blocks_per_cu;
+      L.chunk = c->tune.trace_chunk;
       launch_trace(L, ra.p, K > 0 ? rb.p : ra.p, s);
     } catch (...) {
       release(tr);
@@ -555,11 +654,11 @@ sbr_status sbr_trace_info(sbr_trace_t t, int64_t* rays, int64_t* segments) {
     auto* tr = check_handle<sbr_trace_s>(t, kTrace, "trace");
     set_device(tr->ctx);
     if (tr->segments < 0) {
-      std::vector<uint32_t> cnt(2 * (tr->K + 1));
+      std::vector<uint32_t> cnt(tr->K + 1);
       SBR_HIP(hipMemcpyAsync(cnt.data(), tr->counters.p, cnt.size() * 4, hipMemcpyDeviceToHost, tr->ctx->stream));
       SBR_HIP(hipStreamSynchronize(tr->ctx->stream));
       int64_t seg = tr->NR;
-      for (int k = 0; k < tr->K; ++k) seg += cnt[tr->K + 1 + k];
+      for (int k = 0; k < tr->K; ++k) seg += cnt[k];
       tr->segments = seg;
     }
     if (rays) *rays = tr->NR;
@@ -835,6 +934,38 @@ sbr_status sbr_profile_query(sbr_context_t ctx, const char* kernel, double* tota
       if (e.first == kernel) ms = e.second.first, n = e.second.second;
     if (total_ms) *total_ms = ms;
     if (launches) *launches = n;
+  });
+}
+
+sbr_status sbr_context_set_tuning(sbr_context_t ctx, const char* key, int32_t value) {
+  return guard([&] {
+    auto* c = check_handle<sbr_context_s>(ctx, kContext, "context");
+    SBR_CHECK(key != nullptr, SBR_E_INVALID_ARG, "key is NULL");
+    const std::string k(key);
+    if (k == "trace_blocks_per_cu") {
+      SBR_CHECK(value >= 1 && value <= 32, SBR_E_INVALID_ARG, "trace_blocks_per_cu = %d", value);
+      c->tune.trace_blocks_per_cu = value;
+    } else if (k == "trace_chunk") {
+      SBR_CHECK(value >= 64 && value <= 4096 && value % 64 == 0, SBR_E_INVALID_ARG, "trace_chunk = %d", value);
+      c->tune.trace_chunk = value;
+    } else if (k == "replay_block") {
+      SBR_CHECK(value >= 64 && value <= 1024 && value % 64 == 0, SBR_E_INVALID_ARG, "replay_block = %d", value);
+      c->tune.replay_block = value;
+    } else {
+      SBR_CHECK(false, SBR_E_INVALID_ARG, "unknown tuning key '%s'", key);
+    }
+  });
+}
+
+sbr_status sbr_context_get_tuning(sbr_context_t ctx, const char* key, int32_t* value) {
+  return guard([&] {
+    auto* c = check_handle<sbr_context_s>(ctx, kContext, "context");
+    SBR_CHECK(key != nullptr && value != nullptr, SBR_E_INVALID_ARG, "NULL argument");
+    const std::string k(key);
+    if (k == "trace_blocks_per_cu") *value = c->tune.trace_blocks_per_cu;
+    else if (k == "trace_chunk") *value = c->tune.trace_chunk;
+    else if (k == "replay_block") *value = c->tune.replay_block;
+    else SBR_CHECK(false, SBR_E_INVALID_ARG, "unknown tuning key '%s'", key);
   });
 }
 

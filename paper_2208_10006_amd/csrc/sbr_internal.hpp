@@ -112,9 +112,18 @@ struct TimedLaunch {
   ~TimedLaunch();
 };
 
+// Wall time of a host-side phase, accumulated under "host:<name>" when profiling.
+struct HostPhase {
+  const char* name;
+  double t0 = 0.0;
+  explicit HostPhase(const char* n);
+  ~HostPhase();
+};
+void prof_add(const char* name, double ms);
+
 struct Tuning {
-  int trace_block = 256;      // threads per block of the bounce kernel
-  int trace_blocks_per_cu = 4; // resident blocks per CU of the persistent grid
+  int trace_blocks_per_cu = 4; // resident 256-thread blocks per CU of the persistent grid
+  int trace_chunk = 64;        // rays per wave per queue pull (64 or 128)
   int replay_block = 256;
 };
 
@@ -128,6 +137,8 @@ struct sbr_context_s : sbr::Handle {
   sbr::Tuning tune;
   sbr::Prof prof;
   bool count_work = false;
+  void* stage = nullptr;  // pinned host staging for uploads
+  size_t stage_bytes = 0;
   // cached geodesic edge statistics per N
   std::vector<std::pair<int, double>> alpha_cache;
   sbr_context_s() : Handle(sbr::kContext) {}
@@ -216,6 +227,7 @@ struct BvhOut {
   float4* nodes;     // [max(n-1,1)][4]
   uint32_t* order;   // [n] primitive of each leaf
   float* root_box;   // [8]
+  float* root_host;  // optional host copy of the root box (6 floats), filled before return
 };
 int build_lbvh(const float* box_lo, const float* box_hi, int64_t n, const float scene_lo[3],
                const float scene_hi[3], BvhOut out, hipStream_t s);
@@ -232,12 +244,13 @@ struct TraceLaunch {
   int Nt, N, K;
   int64_t R, NR;
   int32_t* seq;
-  uint32_t* counters;  // [2*(K+1)]: queue[k], n_in[k+1] (n_in[0] = NR)
+  uint32_t* counters;  // trace_counter_words(K): survivors per bounce, then queue slots
   unsigned long long* work;  // node visits, triangle tests, or null (no counting)
-  int grid, block;
+  int grid, block, chunk;
 };
 void launch_trace(const TraceLaunch& L, void* ray_a, void* ray_b, hipStream_t s);
 size_t trace_ray_bytes(int64_t NR);
+int64_t trace_counter_words(int K);
 
 // receive.hip
 void run_receive(sbr_paths_s* ps, hipStream_t s);

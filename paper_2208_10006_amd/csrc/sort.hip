@@ -154,6 +154,24 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t* in, 
   }
 }
 
+// whole scan in one block for short arrays (each thread owns a contiguous run)
+__global__ __launch_bounds__(kScanThreads) void k_scan_small(const uint32_t* in, uint32_t* out, int64_t n,
+                                                           uint32_t* __restrict__ total_out) {
+  const int64_t per = (n + kScanThreads - 1) / kScanThreads;
+  const int64_t lo = (int64_t)threadIdx.x * per;
+  const int64_t hi = lo + per < n ? lo + per : n;
+  uint32_t s = 0;
+  for (int64_t i = lo; i < hi; ++i) s += in[i];
+  uint32_t tot;
+  uint32_t pre = block_exclusive_scan(s, &tot);
+  for (int64_t i = lo; i < hi; ++i) {
+    const uint32_t v = in[i];
+    out[i] = pre;
+    pre += v;
+  }
+  if (threadIdx.x == 0 && total_out) *total_out = tot;
+}
+
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -178,6 +196,11 @@ void exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* 
                         hipStream_t s) {
   if (n <= 0) {
     if (total_dev) fill_u32(total_dev, 0, 1, s);
+    return;
+  }
+  if (n <= 65536) {
+    { ::sbr::TimedLaunch tl_("scan", s); hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(kScanThreads), 0, s, in, out, n, total_dev); }
+    SBR_LAUNCH_CHECK();
     return;
   }
   const int64_t nb = cdiv(n, kScanTile);

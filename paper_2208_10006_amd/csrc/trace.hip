@@ -182,6 +182,7 @@ struct BounceParams {
   uint32_t* queue;
   int32_t* seq_k;
   int has_bvh;
+  int chunk;
   unsigned long long* work;
 };
 
@@ -204,13 +205,33 @@ __global__ __launch_bounds__(256) void k_bounce(const BounceParams P) {
   const uint64_t n_in = first ? (uint64_t)P.n_first : (uint64_t)*P.n_in_ptr;
   const uint64_t lt = lanemask_lt();
   uint32_t n_node = 0, n_tri = 0;  // work counters (COUNT builds only)
+  // Work distribution: the rays of the bounce are cut into 8 contiguous
+  // slices, one per XCD, each with its own queue counter on its own cache
+  // line.  Workgroups are dispatched round-robin over the 8 XCDs, so a wave
+  // drains the slice of its own XCD first (atomics stay in that XCD's L2) and
+  // then steals from the others.  A wave pulls `chunk` rays per atomic and
+  // traces them 64 at a time.
+  const int home = blockIdx.x & 7;
+  int tried = 0;
+  uint64_t base = 0, lo = 0, hi = 0;
+  uint32_t sub = 0;
   while (true) {
-    uint32_t base = 0;
-    if (lane == 0) base = atomicAdd(P.queue, (uint32_t)kWave);
-    base = __shfl(base, 0, 64);
-    if ((uint64_t)base >= n_in) break;
-    const uint64_t idx = (uint64_t)base + lane;
-    const bool active = idx < n_in;
+    if (sub == 0) {
+      const int x = (home + tried) & 7;
+      lo = n_in * (uint64_t)x / 8;
+      hi = n_in * (uint64_t)(x + 1) / 8;
+      uint32_t b = 0;
+      if (lane == 0) b = atomicAdd(P.queue + 32 * x, (uint32_t)P.chunk);
+      base = lo + __shfl(b, 0, 64);
+      if (base >= hi) {
+        if (++tried == 8) break;
+        continue;
+      }
+    }
+    const uint64_t idx = base + sub + lane;
+    sub += kWave;
+    if (sub >= (uint32_t)P.chunk || base + sub >= hi) sub = 0;
+    const bool active = idx < hi;
     // ------------------------------------------------ load / generate the FP64 ray
     d3 o = mk3(0, 0, 0), d = mk3(0, 0, 1);
     double L = 0.0;
@@ -402,6 +423,8 @@ void geodesic_edge_stats(int N, double* mean, double* mn, double* mx, hipStream_
   if (mx) *mx = h[2];
 }
 
+int64_t trace_counter_words(int K) { return 32 + 256 * (int64_t)(K + 1); }
+
 size_t trace_ray_bytes(int64_t NR) { return (size_t)NR * (7 * sizeof(double) + 2 * sizeof(uint32_t)); }
 
 void launch_trace(const TraceLaunch& T, void* ray_a, void* ray_b, hipStream_t s) {
@@ -421,16 +444,18 @@ void launch_trace(const TraceLaunch& T, void* ray_a, void* ray_b, hipStream_t s)
   P.K = T.K;
   P.n_first = T.NR;
   P.work = T.work;
+  P.chunk = T.chunk;
   const int depth = sc->bvh_depth;
-  fill_u32(T.counters, 0, 2 * (T.K + 1), s);
+  // counters: [0..K] survivors of each bounce; then per bounce 8 queue slots of 128 B
+  fill_u32(T.counters, 0, trace_counter_words(T.K), s);
   // every chain entry starts as "miss"; the bounce kernels overwrite the ones they trace
   fill_u32(reinterpret_cast<uint32_t*>(T.seq), 0xffffffffu, (int64_t)(T.K + 1) * T.NR, s);
   RaySoA A = soa_of(ray_a, T.NR), B = soa_of(ray_b, T.NR);
   for (int k = 0; k <= T.K; ++k) {
     P.k = k;
-    P.queue = T.counters + k;
-    P.n_in_ptr = k > 0 ? T.counters + (T.K + 1) + (k - 1) : nullptr;
-    P.n_out_ptr = T.counters + (T.K + 1) + k;
+    P.queue = T.counters + 32 + 256 * k;
+    P.n_in_ptr = k > 0 ? T.counters + (k - 1) : nullptr;
+    P.n_out_ptr = T.counters + k;
     P.in = (k % 2 == 1) ? A : B;
     P.out = (k % 2 == 1) ? B : A;
     P.seq_k = T.seq + (int64_t)k * T.NR;

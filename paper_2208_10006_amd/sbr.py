@@ -77,6 +77,8 @@ def _load():
         "sbr_profile_query": [P, C.c_char_p, P, P],
         "sbr_context_count_work": [P, C.c_int],
         "sbr_trace_work": [P, P, P],
+        "sbr_context_set_tuning": [P, C.c_char_p, I32],
+        "sbr_context_get_tuning": [P, C.c_char_p, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -368,6 +370,16 @@ def sbr_trace_work(tr: Trace):
     nv, nt = C.c_int64(), C.c_int64()
     _call("sbr_trace_work", tr.h, C.byref(nv), C.byref(nt))
     return {"node_visits": nv.value, "tri_tests": nt.value}
+
+
+def sbr_context_set_tuning(ctx: Context, key: str, value: int):
+    _call("sbr_context_set_tuning", ctx.h, key.encode(), int(value))
+
+
+def sbr_context_get_tuning(ctx: Context, key: str) -> int:
+    v = C.c_int32()
+    _call("sbr_context_get_tuning", ctx.h, key.encode(), C.byref(v))
+    return v.value
 
 
 def sbr_version() -> str:

@@ -66,11 +66,40 @@ def test_alpha(S, ctx, N):
 
 
 # ------------------------------------------------------------------ scene
-@pytest.mark.parametrize("which", ["tiny_room", "random", "urban", "office"])
+def _tricky_planes():
+    """Coplanar triangles with mixed winding on planes whose largest normal
+    components tie (45-degree walls, a (1,1,1) roof), offsets near hash-cell
+    borders, and one material change inside a plane."""
+    rng = np.random.default_rng(12)
+    tris, eps = [], []
+    for c in (5.0, 5.0 + 1e-12, 7.25, 1e-3 * 3):  # x + y = c walls (second one coplanar within tolerance)
+        n = np.array([1.0, 1.0, 0.0]) / np.sqrt(2)
+        u = np.array([1.0, -1.0, 0.0]) / np.sqrt(2)
+        o = n * c / np.sqrt(2) * np.sqrt(2)
+        for k in range(3):
+            a = o + u * rng.uniform(-5, 5) + np.array([0, 0, rng.uniform(0, 3)])
+            b = o + u * rng.uniform(-5, 5) + np.array([0, 0, rng.uniform(0, 3)])
+            d = o + u * rng.uniform(-5, 5) + np.array([0, 0, rng.uniform(0, 3)])
+            tris.append([a, b, d] if k % 2 else [a, d, b])
+            eps.append(5.0 if k < 2 else 6.0)
+    n3 = np.ones(3) / np.sqrt(3)
+    e1 = np.array([1.0, -1.0, 0.0]) / np.sqrt(2)
+    e2 = np.cross(n3, e1)
+    for k in range(4):
+        a, b, d = (n3 * 4.0 + e1 * rng.uniform(-3, 3) + e2 * rng.uniform(-3, 3) for _ in range(3))
+        tris.append([a, b, d] if k % 2 else [d, b, a])
+        eps.append(4.0)
+    T = len(tris)
+    return W.Workload("tricky", np.array(tris), np.array(eps, np.float32), np.full(T, 0.01, np.float32),
+                      np.zeros(T, np.float32), np.zeros((1, 3)), np.ones((1, 3)), np.array([28e9]))
+
+
+@pytest.mark.parametrize("which", ["tiny_room", "random", "urban", "office", "tricky"])
 def test_scene_groups(S, ctx, which):
     banner("scene groups", which)
     w = {"tiny_room": lambda: W.tiny_room(), "random": lambda: W.random_box_scene(5, n_boxes=12),
-         "urban": lambda: W.urban_canyon(), "office": lambda: W.massive_mimo_office()}[which]()
+         "urban": lambda: W.urban_canyon(), "office": lambda: W.massive_mimo_office(),
+         "tricky": _tricky_planes}[which]()
     sc = S.sbr_scene_build(ctx, w.tri, w.eps_r, w.sigma, w.rough)
     g, p = S.sbr_scene_groups(sc, w.T)
     og, op, ng = O.scene_groups(w)
