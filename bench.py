@@ -107,6 +107,62 @@ def cpu_baseline(w, target_s=15.0):
                       f"full receive + paths + {len(w.freq)}-frequency field, {dt:.1f} s"}
 
 
+def batched_main(args):
+    """Batched uneven workload: many independent scenes traced by one
+    persistent launch per bounce, then received and accumulated per scene."""
+    import numpy as np
+    import torch
+    from paper_2208_10006_amd import sbr as S
+    from paper_2208_10006_amd import workloads as W
+
+    seeds = list(range(4000, 4000 + args.scenes))
+    ws = [W.batched_uneven(s) for s in seeds]
+    dev = torch.device("cuda", 0)
+    ins = [make_inputs(w, torch, dev) for w in ws]
+    ctx = S.context_for_torch(0)
+    log(f"[bench] batched: {len(ws)} scenes, T {sum(w.T for w in ws)} triangles, "
+        f"{sum(w.rays_per_element for w in ws)} rays")
+
+    def one_step():
+        scenes = [S.sbr_scene_build(ctx, d["tri"], d["eps"], d["sig"], d["rough"]) for d in ins]
+        trs = S.sbr_trace_batch(ctx, scenes, [d["tx"] for d in ins], [w.geodesic_N for w in ws],
+                                [w.max_bounces for w in ws])
+        for w, d, tr in zip(ws, ins, trs):
+            ps = S.sbr_receive(ctx, tr, d["rx"], 0.0, w.radius_coeff)
+            S.sbr_channel(ctx, ps, d["freq"], None, None, S.SBR_POL_V, S.SBR_POL_V, H_c64=d["H"])
+            S.sbr_stats_device(ps, d["pg"], d["tau"], d["ang"])
+        return scenes, trs
+
+    for i in range(args.warmup):
+        scenes, trs = one_step()
+    torch.cuda.synchronize()
+    segs = sum(S.sbr_trace_info(t)["segments"] for t in trs)
+    del scenes, trs
+    S.sbr_profile_enable(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat = []
+    for i in range(args.steps):
+        scenes, trs = one_step()
+        lat += [S.sbr_trace_latency(t) for t in trs]
+        del scenes, trs
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    bounce_ms, _ = S.sbr_profile_query(ctx, "bounce")
+    lat = np.array(lat)
+    out = {"metric": "traced ray-segments/s (batched uneven scenes)", "value": segs * args.steps / (t1 - t0),
+           "unit": "ray-segments/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": (t1 - t0) * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32 traversal / f64 ray state, phase and H", "data": "synthetic",
+           "config": {"workload": f"batched uneven: {len(ws)} scenes (seeds {seeds[0]}-{seeds[-1]}), "
+                                  "room/office/urban, T lognormal 100-50k, rays 2^14-2^22, K 2-8, one launch per bounce",
+                      "segments_per_step": segs, "bounce_ms_per_step": bounce_ms / args.steps,
+                      "trace_segments_per_s": segs / (bounce_ms / args.steps * 1e-3),
+                      "scene_latency_ms": {"p50": float(np.percentile(lat, 50)), "p90": float(np.percentile(lat, 90)),
+                                           "p99": float(np.percentile(lat, 99)), "max": float(lat.max())}}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,12 +171,15 @@ def main():
     ap.add_argument("--workload", default="urban_canyon")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--scenes", type=int, default=64, help="batched_uneven: number of scenes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding "
               "is a design note, not a measured path", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "batched_uneven":
+        return batched_main(args)
     import torch
     from paper_2208_10006_amd import sbr as S
     from paper_2208_10006_amd import workloads as W
@@ -131,6 +190,13 @@ def main():
     ctx = S.context_for_torch(0)
     log(f"[bench] workload {w.name}: T={w.T} Nt={len(w.tx)} N={w.geodesic_N} K={w.max_bounces} "
         f"Nr={len(w.rx)} Nf={len(w.freq)}")
+    # launch parameters from the autotuner (searched once, cached per problem class)
+    from paper_2208_10006_amd import autotune as A
+    sc0 = S.sbr_scene_build(ctx, d["tri"], d["eps"], d["sig"], d["rough"])
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    tuned = A.autotune_trace(ctx, sc0, d["tx"], w.geodesic_N, w.max_bounces, w.T, arch=arch)
+    del sc0
+    log(f"[bench] tuned launch: {tuned['config']} ({tuned['bounce_ms']:.3f} ms per trace)")
     for i in range(args.warmup):
         sc, tr, ps = step(S, ctx, w, d)
         log(f"[bench] warmup {i} done")
@@ -186,7 +252,7 @@ def main():
                                   f"{len(w.rx)} Rx, N={w.geodesic_N} ({10 * w.geodesic_N ** 2 + 2} rays), "
                                   f"K={w.max_bounces}, {len(w.freq)} subcarriers at 300 GHz",
                       "segments_per_step": segments, "paths": pinfo["paths"], "capture_events": pinfo["events"]},
-           "kernels": kernels, "roofline": roofline}
+           "kernels": kernels, "roofline": roofline, "tuning": tuned["config"]}
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle on a sample) ...")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

@@ -101,6 +101,18 @@ sbr_status sbr_scene_build(sbr_context_t ctx, const double* tri_xyz, int64_t T, 
  * 0 <= max_bounces <= 16, Nt * (10 N^2 + 2) < 2^32. */
 sbr_status sbr_trace(sbr_context_t ctx, sbr_scene_t scene, const double* tx_xyz, int32_t Nt,
                      int32_t geodesic_N, int32_t max_bounces, uint32_t flags, sbr_trace_t* out);
+/* Batched launch + trace of n independent problems (scenes of any size, own
+ * Tx arrays, launch densities and bounce limits): the rays of all of them
+ * are traced by one persistent launch per bounce (breadth-first over the
+ * whole batch), and out[i] is an ordinary trace handle of problem i.
+ * tx_xyz[i]: [Nt[i]][3] FP64 (host pointers, or device with SBR_IN_DEVICE).
+ * Sum of all rays < 2^32 - 2^22. */
+sbr_status sbr_trace_batch(sbr_context_t ctx, int32_t n, const sbr_scene_t* scenes, const double* const* tx_xyz,
+                           const int32_t* Nt, const int32_t* geodesic_N, const int32_t* max_bounces, uint32_t flags,
+                           sbr_trace_t* out);
+/* Device-side latency of a batched trace: wall-clock time (ms) from the first
+ * to the last ray chunk of this problem; -1 for traces not made in a batch. */
+sbr_status sbr_trace_latency(sbr_trace_t tr, double* ms);
 /* rays = Nt (10N^2+2); segments = closest-hit queries actually traced. */
 sbr_status sbr_trace_info(sbr_trace_t tr, int64_t* rays, int64_t* segments);
 /* Per-ray hit triangles [rays][K+1] (original triangle index; -1 miss,
@@ -195,6 +207,9 @@ sbr_status sbr_trace_work(sbr_trace_t tr, int64_t* node_visits, int64_t* tri_tes
  *                          bounce grid (1..32, default 4)
  *   "trace_chunk"          rays a wave takes from its queue per atomic (multiple of 64, <= 4096)
  *   "replay_block"         threads per block of the capture replay (64..1024)
+ *   "trace_graph"          1: the bounce loop of sbr_trace runs as a hipGraph built
+ *                          once per (bounces, tree depth class) and replayed with
+ *                          updated kernel arguments; 0 (default): direct launches
  * Unknown keys or out-of-range values: SBR_E_INVALID_ARG. */
 sbr_status sbr_context_set_tuning(sbr_context_t ctx, const char* key, int32_t value);
 sbr_status sbr_context_get_tuning(sbr_context_t ctx, const char* key, int32_t* value);

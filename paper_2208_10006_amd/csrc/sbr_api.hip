@@ -338,6 +338,21 @@ __global__ void k_hits_out(const int32_t* __restrict__ seq, int64_t NR, int K, i
   }
 }
 
+// segments of one trace counted from its hit chains (traced entries per ray)
+__global__ void k_count_segments(const int32_t* __restrict__ seq, int64_t NR, int K,
+                                 unsigned long long* __restrict__ total) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long c = 0;
+  if (r < NR) {
+    for (int k = 0; k <= K; ++k) {
+      ++c;
+      if (seq[(int64_t)k * NR + r] < 0) break;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(total, c);
+}
+
 double alpha_for(sbr_context_s* c, int N) {
   for (auto& pr : c->alpha_cache)
     if (pr.first == N) return pr.second;
@@ -360,6 +375,7 @@ using namespace sbr;
 
 sbr_context_s::~sbr_context_s() {
   if (stream) (void)hipStreamSynchronize(stream);
+  for (auto* g : graphs) delete g;
   if (stage) (void)hipHostFree(stage);
   prof.clear();
   if (g_prof == &prof) g_prof = nullptr;
@@ -627,6 +643,7 @@ sbr_status sbr_trace(sbr_context_t ctx, sbr_scene_t scene, const double* tx_xyz,
       ra.alloc(trace_ray_bytes(tr->NR), s);
       if (K > 0) rb.alloc(trace_ray_bytes(tr->NR), s);
       TraceLaunch L{};
+      L.ctx = c;
       L.scene = sc, L.tx = tr->tx.as<double>(), L.Nt = Nt, L.N = N, L.K = K, L.R = R, L.NR = tr->NR;
       L.seq = tr->seq.as<int32_t>();
       L.counters = tr->counters.as<uint32_t>();
@@ -649,10 +666,102 @@ sbr_status sbr_trace(sbr_context_t ctx, sbr_scene_t scene, const double* tx_xyz,
   });
 }
 
+sbr_status sbr_trace_batch(sbr_context_t ctx, int32_t n, const sbr_scene_t* scenes, const double* const* tx_xyz,
+                           const int32_t* Nt, const int32_t* Nv, const int32_t* Kv, uint32_t flags,
+                           sbr_trace_t* out) {
+  return guard([&] {
+    auto* c = check_handle<sbr_context_s>(ctx, kContext, "context");
+    SBR_CHECK(n >= 1 && scenes && tx_xyz && Nt && Nv && Kv && out, SBR_E_INVALID_ARG, "batch arguments");
+    int64_t total = 0;
+    for (int i = 0; i < n; ++i) {
+      check_handle<sbr_scene_s>(scenes[i], kScene, "scene");
+      SBR_CHECK(Nt[i] >= 1, SBR_E_INVALID_ARG, "Nt[%d] = %d", i, Nt[i]);
+      SBR_CHECK(Nv[i] >= 1 && Nv[i] <= 46340, SBR_E_INVALID_ARG, "geodesic_N[%d] = %d", i, Nv[i]);
+      SBR_CHECK(Kv[i] >= 0 && Kv[i] <= SBR_MAX_BOUNCES, SBR_E_INVALID_ARG, "max_bounces[%d] = %d", i, Kv[i]);
+      total += (int64_t)Nt[i] * (10LL * Nv[i] * Nv[i] + 2);
+    }
+    SBR_CHECK(total < (int64_t(1) << 32) - (int64_t(1) << 22), SBR_E_UNSUPPORTED, "batch of %lld rays", (long long)total);
+    set_device(c);
+    hipStream_t s = c->stream;
+    std::vector<sbr_trace_s*> trs;
+    try {
+      for (int i = 0; i < n; ++i) {
+        auto* sc = static_cast<sbr_scene_s*>(scenes[i]);
+        const auto htx = to_host(tx_xyz[i], (size_t)Nt[i] * 3, flags, s);
+        SBR_CHECK(finite_all(htx.data(), htx.size()), SBR_E_INVALID_ARG, "tx[%d] coordinates must be finite", i);
+        auto* tr = new sbr_trace_s();
+        tr->ctx = c, tr->scene = sc;
+        retain(c), retain(sc);
+        trs.push_back(tr);
+        tr->Nt = Nt[i], tr->N = Nv[i], tr->K = Kv[i], tr->R = 10LL * Nv[i] * Nv[i] + 2;
+        tr->NR = (int64_t)Nt[i] * tr->R;
+        tr->h_tx = htx;
+        tr->batched = true;
+        tr->seq.alloc((size_t)(tr->K + 1) * tr->NR * 4, s);
+        tr->counters.alloc(4, s);
+      }
+      Stager st(c);
+      {
+        size_t need = 0;
+        for (auto* tr : trs) need += tr->h_tx.size() * 8 + 256;
+        if (c->stage_bytes < need) {
+          if (c->stage) (void)hipHostFree(c->stage);
+          c->stage = nullptr;
+          c->stage_bytes = 0;
+          SBR_HIP(hipHostMalloc(&c->stage, need, hipHostMallocDefault));
+          c->stage_bytes = need;
+        }
+      }
+      for (auto* tr : trs) st.put(tr->tx, tr->h_tx.data(), tr->h_tx.size(), s);
+      int Kmax = 0;
+      for (auto* tr : trs) Kmax = std::max(Kmax, tr->K);
+      Buf ra, rb, cnt, stamps;
+      ra.alloc(trace_ray_bytes(total), s);
+      rb.alloc(trace_ray_bytes(total), s);
+      cnt.alloc((size_t)trace_counter_words(Kmax) * 4, s);
+      stamps.alloc((size_t)2 * n * 8, s);
+      unsigned long long* t_first = stamps.as<unsigned long long>();
+      launch_trace_batch(trs, c->num_cus * c->tune.trace_blocks_per_cu, c->tune.trace_chunk, ra.p, rb.p,
+                         cnt.as<uint32_t>(), t_first, t_first + n, s);
+      std::vector<unsigned long long> h(2 * (size_t)n);
+      SBR_HIP(hipMemcpyAsync(h.data(), stamps.p, h.size() * 8, hipMemcpyDeviceToHost, s));
+      SBR_HIP(hipStreamSynchronize(s));
+      int khz = 100000;
+      (void)hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device);
+      for (int i = 0; i < n; ++i)
+        trs[i]->latency_ms = h[n + i] >= h[i] ? (double)(h[n + i] - h[i]) / (double)khz : 0.0;
+    } catch (...) {
+      for (auto* tr : trs) release(tr);
+      throw;
+    }
+    for (int i = 0; i < n; ++i) out[i] = trs[i];
+  });
+}
+
+sbr_status sbr_trace_latency(sbr_trace_t t, double* ms) {
+  return guard([&] {
+    auto* tr = check_handle<sbr_trace_s>(t, kTrace, "trace");
+    SBR_CHECK(ms != nullptr, SBR_E_INVALID_ARG, "ms is NULL");
+    *ms = tr->latency_ms;
+  });
+}
+
 sbr_status sbr_trace_info(sbr_trace_t t, int64_t* rays, int64_t* segments) {
   return guard([&] {
     auto* tr = check_handle<sbr_trace_s>(t, kTrace, "trace");
     set_device(tr->ctx);
+    if (tr->segments < 0 && tr->batched) {
+      hipStream_t s = tr->ctx->stream;
+      Buf cnt;
+      cnt.alloc(8, s);
+      fill_u32(cnt.as<uint32_t>(), 0, 2, s);
+      { TimedLaunch tl_("misc", s); hipLaunchKernelGGL(k_count_segments, dim3(nblk(tr->NR, 256)), dim3(256), 0, s, tr->seq.as<int32_t>(), tr->NR, tr->K, cnt.as<unsigned long long>()); }
+      SBR_LAUNCH_CHECK();
+      unsigned long long v = 0;
+      SBR_HIP(hipMemcpyAsync(&v, cnt.p, 8, hipMemcpyDeviceToHost, s));
+      SBR_HIP(hipStreamSynchronize(s));
+      tr->segments = (int64_t)v;
+    }
     if (tr->segments < 0) {
       std::vector<uint32_t> cnt(tr->K + 1);
       SBR_HIP(hipMemcpyAsync(cnt.data(), tr->counters.p, cnt.size() * 4, hipMemcpyDeviceToHost, tr->ctx->stream));
@@ -951,6 +1060,9 @@ sbr_status sbr_context_set_tuning(sbr_context_t ctx, const char* key, int32_t va
     } else if (k == "replay_block") {
       SBR_CHECK(value >= 64 && value <= 1024 && value % 64 == 0, SBR_E_INVALID_ARG, "replay_block = %d", value);
       c->tune.replay_block = value;
+    } else if (k == "trace_graph") {
+      SBR_CHECK(value == 0 || value == 1, SBR_E_INVALID_ARG, "trace_graph = %d", value);
+      c->tune.trace_graph = value;
     } else {
       SBR_CHECK(false, SBR_E_INVALID_ARG, "unknown tuning key '%s'", key);
     }
@@ -965,6 +1077,7 @@ sbr_status sbr_context_get_tuning(sbr_context_t ctx, const char* key, int32_t* v
     if (k == "trace_blocks_per_cu") *value = c->tune.trace_blocks_per_cu;
     else if (k == "trace_chunk") *value = c->tune.trace_chunk;
     else if (k == "replay_block") *value = c->tune.replay_block;
+    else if (k == "trace_graph") *value = c->tune.trace_graph;
     else SBR_CHECK(false, SBR_E_INVALID_ARG, "unknown tuning key '%s'", key);
   });
 }

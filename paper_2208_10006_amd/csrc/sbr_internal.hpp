@@ -125,6 +125,17 @@ struct Tuning {
   int trace_blocks_per_cu = 4; // resident 256-thread blocks per CU of the persistent grid
   int trace_chunk = 64;        // rays per wave per queue pull (64 or 128)
   int replay_block = 256;
+  int trace_graph = 0;         // 1: replay the bounce loop as a cached hipGraph
+};
+
+// An instantiated bounce-loop graph: init kernels + one kernel node per bounce,
+// built once per shape and replayed with updated kernel arguments.
+struct TraceGraph {
+  int K = -1, depth_bucket = 0, count = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<hipGraphNode_t> nodes;  // fill counters, fill seq, bounce 0..K
+  ~TraceGraph();
 };
 
 }  // namespace sbr
@@ -139,6 +150,7 @@ struct sbr_context_s : sbr::Handle {
   bool count_work = false;
   void* stage = nullptr;  // pinned host staging for uploads
   size_t stage_bytes = 0;
+  std::vector<sbr::TraceGraph*> graphs;  // cached bounce-loop graphs
   // cached geodesic edge statistics per N
   std::vector<std::pair<int, double>> alpha_cache;
   sbr_context_s() : Handle(sbr::kContext) {}
@@ -180,6 +192,8 @@ struct sbr_trace_s : sbr::Handle {
   sbr::Buf work;     // uint64[2]: node visits, triangle tests (when counted)
   bool counted = false;
   int64_t segments = -1;  // host copy once read
+  bool batched = false;   // traced by sbr_trace_batch (segments counted from the chains)
+  double latency_ms = -1.0;
   sbr_trace_s() : Handle(sbr::kTrace) {}
   ~sbr_trace_s() override;
 };
@@ -239,6 +253,7 @@ void geodesic_edge_stats(int N, double* mean, double* mn, double* mx, hipStream_
 
 // trace.hip
 struct TraceLaunch {
+  sbr_context_s* ctx;
   const sbr_scene_s* scene;
   const double* tx;
   int Nt, N, K;
@@ -249,6 +264,10 @@ struct TraceLaunch {
   int grid, block, chunk;
 };
 void launch_trace(const TraceLaunch& L, void* ray_a, void* ray_b, hipStream_t s);
+// one persistent launch per bounce over the rays of all traces (their seq,
+// tx, N, K and scenes set); per-trace first/last wall-clock stamps
+void launch_trace_batch(const std::vector<sbr_trace_s*>& trs, int grid, int chunk, void* ray_a, void* ray_b,
+                        uint32_t* counters, unsigned long long* t_first, unsigned long long* t_last, hipStream_t s);
 size_t trace_ray_bytes(int64_t NR);
 int64_t trace_counter_words(int K);
 

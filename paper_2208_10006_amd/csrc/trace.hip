@@ -163,27 +163,41 @@ inline RaySoA soa_of(void* base, int64_t cap) {
   return r;
 }
 
-struct BounceParams {
+__global__ void k_fill_u32_graph(uint32_t* p, uint32_t v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Everything the bounce kernel needs about one scene and its launch.
+struct SceneDesc {
   const float4* nodes;
   const float4* tri;      // 3 per leaf: v0|orig id, v1|plane id, v2|group id
   const double4* tplane;  // per original triangle
   const int32_t* tplaneid;
-  float root[6];
-  double cx, cy, cz;      // FP32 frame centre
-  GeoTables G;
-  int N;
-  int64_t R;
   const double* tx;
-  int k, K;
-  int64_t n_first;        // rays of bounce 0 (generated, not read)
+  int32_t* seq;           // [(K+1)][NR]
+  float root[6];
+  int has_bvh, N, K, pad;
+  double cx, cy, cz;      // FP32 frame centre
+  int64_t R, NR, ray_off; // rays per element, rays of the scene, first global ray id
+};
+
+struct BounceParams {
+  SceneDesc one;                // single-scene launches
+  const SceneDesc* table;       // batched launches: per-scene descriptors
+  const int64_t* offs;          // batched: ray_off of every scene, then the total
+  int n_scenes;
+  GeoTables G;
+  int k;
+  int64_t n_first;              // rays of bounce 0 (generated, not read)
   const uint32_t* n_in_ptr;
   RaySoA in, out;
   uint32_t* n_out_ptr;
   uint32_t* queue;
-  int32_t* seq_k;
-  int has_bvh;
   int chunk;
   unsigned long long* work;
+  unsigned long long* t_first;  // batched: per-scene first/last wall-clock stamp
+  unsigned long long* t_last;
 };
 
 __device__ inline float sel(float3 v, int k) { return k == 0 ? v.x : (k == 1 ? v.y : v.z); }
@@ -196,12 +210,23 @@ __device__ inline float off1(float p, float n) {
   return fabsf(p) < kOrigin ? p + kFloatScale * n : pi;
 }
 
-template <int STACK, bool COUNT>
+// scene of a global ray id: last s with offs[s] <= id
+__device__ inline int scene_of(const int64_t* offs, int n, uint64_t id) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((uint64_t)offs[mid] <= id) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int STACK, bool COUNT, bool MULTI>
 __global__ __launch_bounds__(256) void k_bounce(const BounceParams P) {
   __shared__ int32_t stack_mem[256 / kWave][STACK][kWave];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int32_t* stk = &stack_mem[wv][0][lane];
-  const bool first = P.k == 0, last = P.k == P.K;
+  const bool first = P.k == 0;
   const uint64_t n_in = first ? (uint64_t)P.n_first : (uint64_t)*P.n_in_ptr;
   const uint64_t lt = lanemask_lt();
   uint32_t n_node = 0, n_tri = 0;  // work counters (COUNT builds only)
@@ -235,14 +260,11 @@ __global__ __launch_bounds__(256) void k_bounce(const BounceParams P) {
     // ------------------------------------------------ load / generate the FP64 ray
     d3 o = mk3(0, 0, 0), d = mk3(0, 0, 1);
     double L = 0.0;
-    uint32_t rid = 0;
+    uint32_t rid = 0;  // global ray id
     int32_t prev = -1;
     if (active) {
       if (first) {
         rid = (uint32_t)idx;
-        const int p = (int)(idx / (uint64_t)P.R);
-        o = ld3(P.tx + 3 * p);
-        d = geo_dir(P.G, P.N, (int64_t)(idx - (uint64_t)p * P.R));
       } else {
         o = mk3(P.in.ox[idx], P.in.oy[idx], P.in.oz[idx]);
         d = mk3(P.in.dx[idx], P.in.dy[idx], P.in.dz[idx]);
@@ -251,16 +273,37 @@ __global__ __launch_bounds__(256) void k_bounce(const BounceParams P) {
         prev = P.in.prev[idx];
       }
     }
+    int sid = 0;
+    if (MULTI) sid = active ? scene_of(P.offs, P.n_scenes, rid) : 0;
+    const SceneDesc& SD = MULTI ? P.table[sid] : P.one;
+    const uint64_t lrid = (uint64_t)rid - (uint64_t)(MULTI ? SD.ray_off : 0);
+    if (MULTI && P.t_first && active) {
+      // first and last lanes of the wave stamp their scenes
+      const bool edge = lane == 0 || lane == 63 || !(idx + 1 < hi);
+      if (edge) {
+        const unsigned long long t = wall_clock64();
+        atomicMin(P.t_first + sid, t);
+        atomicMax(P.t_last + sid, t);
+      }
+    }
+    const bool last = P.k == SD.K;
+    if (active && first) {
+      const int p = (int)(lrid / (uint64_t)SD.R);
+      o = ld3(SD.tx + 3 * p);
+      d = geo_dir(P.G, SD.N, (int64_t)(lrid - (uint64_t)p * SD.R));
+    }
     // ------------------------------------------------ FP32 closest hit
     int32_t hit = -1;  // leaf (sorted) index
     float thit = INFINITY;
-    if (active && P.has_bvh) {
-      float3 org = make_float3((float)(o.x - P.cx), (float)(o.y - P.cy), (float)(o.z - P.cz));
+    if (active && SD.has_bvh) {
+      const float4* __restrict__ nodes = SD.nodes;
+      const float4* __restrict__ tri = SD.tri;
+      float3 org = make_float3((float)(o.x - SD.cx), (float)(o.y - SD.cy), (float)(o.z - SD.cz));
       const float3 dir = make_float3((float)d.x, (float)d.y, (float)d.z);
       int32_t skip_plane = -1;
       if (prev >= 0) {
-        skip_plane = P.tplaneid[prev];
-        const double4 pl = P.tplane[prev];
+        skip_plane = SD.tplaneid[prev];
+        const double4 pl = SD.tplane[prev];
         float sgn = (pl.x * d.x + pl.y * d.y + pl.z * d.z) >= 0.0 ? 1.0f : -1.0f;
         org.x = off1(org.x, sgn * (float)pl.x);
         org.y = off1(org.y, sgn * (float)pl.y);
@@ -293,7 +336,7 @@ __global__ __launch_bounds__(256) void k_bounce(const BounceParams P) {
       };
       auto tri_test = [&](int32_t leaf) {
         if (COUNT) ++n_tri;
-        const float4 a = P.tri[3 * leaf], b = P.tri[3 * leaf + 1], c = P.tri[3 * leaf + 2];
+        const float4 a = tri[3 * leaf], b = tri[3 * leaf + 1], c = tri[3 * leaf + 2];
         if (__float_as_int(b.w) == skip_plane) return;
         const float3 A = make_float3(a.x - org.x, a.y - org.y, a.z - org.z);
         const float3 B = make_float3(b.x - org.x, b.y - org.y, b.z - org.z);
@@ -319,13 +362,13 @@ __global__ __launch_bounds__(256) void k_bounce(const BounceParams P) {
         }
       };
       float tn;
-      if (box_hit(P.root[0], P.root[1], P.root[2], P.root[3], P.root[4], P.root[5], INFINITY, tn)) {
+      if (box_hit(SD.root[0], SD.root[1], SD.root[2], SD.root[3], SD.root[4], SD.root[5], INFINITY, tn)) {
         int sp = 0;
         int32_t node = 0;
         while (true) {
           if (COUNT) ++n_node;
-          const float4 n0 = P.nodes[4 * node], n1 = P.nodes[4 * node + 1], n2 = P.nodes[4 * node + 2],
-                       n3 = P.nodes[4 * node + 3];
+          const float4 n0 = nodes[4 * node], n1 = nodes[4 * node + 1], n2 = nodes[4 * node + 2],
+                       n3 = nodes[4 * node + 3];
           float tl, tr;
           bool hl = box_hit(n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, thit, tl);
           bool hr = box_hit(n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, thit, tr);
@@ -335,7 +378,7 @@ __global__ __launch_bounds__(256) void k_bounce(const BounceParams P) {
             hl = false;
           }
           if (hr && cr < 0) {
-            tri_test(~cr);
+            if (cr != cl) tri_test(~cr);
             hr = false;
           }
           if (hl && hr) {
@@ -354,14 +397,14 @@ __global__ __launch_bounds__(256) void k_bounce(const BounceParams P) {
           }
         }
       }
+      if (hit >= 0) hit = __float_as_int(tri[3 * hit].w);  // original triangle id
     }
     // ------------------------------------------------ record, reflect in FP64, compact
-    int32_t orig = -1;
-    if (hit >= 0) orig = __float_as_int(P.tri[3 * hit].w);
-    if (active) P.seq_k[rid] = orig;
+    const int32_t orig = hit;
+    if (active) SD.seq[(int64_t)P.k * SD.NR + (int64_t)lrid] = orig;
     const bool live = active && orig >= 0 && !last;
     if (live) {
-      const double4 pl = P.tplane[orig];
+      const double4 pl = SD.tplane[orig];
       const double t = advance_t(pl, o, d);
       o = o + d * t;
       L += t;
@@ -396,6 +439,28 @@ __global__ __launch_bounds__(256) void k_bounce(const BounceParams P) {
   }
 }
 
+SceneDesc scene_desc(const sbr_scene_s* sc, const double* tx, int N, int K, int64_t R, int64_t NR, int32_t* seq,
+                     int64_t ray_off) {
+  SceneDesc D{};
+  D.has_bvh = sc->T > 0;
+  D.nodes = sc->nodes.as<float4>();
+  D.tri = sc->tri32.as<float4>();
+  D.tplane = sc->tplane.as<double4>();
+  D.tplaneid = sc->tplaneid.as<int32_t>();
+  for (int k = 0; k < 6; ++k) D.root[k] = sc->root_host[k];
+  D.cx = sc->center[0], D.cy = sc->center[1], D.cz = sc->center[2];
+  D.tx = tx;
+  D.N = N, D.K = K, D.R = R, D.NR = NR, D.seq = seq, D.ray_off = ray_off;
+  return D;
+}
+
+template <bool COUNT, bool MULTI>
+void launch_bounce(int depth, dim3 g, const BounceParams& P, hipStream_t s) {
+  if (depth <= 16) hipLaunchKernelGGL((k_bounce<16, COUNT, MULTI>), g, dim3(256), 0, s, P);
+  else if (depth <= 32) hipLaunchKernelGGL((k_bounce<32, COUNT, MULTI>), g, dim3(256), 0, s, P);
+  else hipLaunchKernelGGL((k_bounce<64, COUNT, MULTI>), g, dim3(256), 0, s, P);
+}
+
 }  // namespace
 
 void upload_geodesic_tables(int) {}
@@ -427,51 +492,169 @@ int64_t trace_counter_words(int K) { return 32 + 256 * (int64_t)(K + 1); }
 
 size_t trace_ray_bytes(int64_t NR) { return (size_t)NR * (7 * sizeof(double) + 2 * sizeof(uint32_t)); }
 
+TraceGraph::~TraceGraph() {
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+}
+
+namespace {
+template <bool COUNT>
+const void* bounce_fn(int depth) {
+  if (depth <= 16) return reinterpret_cast<const void*>(&k_bounce<16, COUNT, false>);
+  if (depth <= 32) return reinterpret_cast<const void*>(&k_bounce<32, COUNT, false>);
+  return reinterpret_cast<const void*>(&k_bounce<64, COUNT, false>);
+}
+hipKernelNodeParams knode(const void* fn, dim3 g, dim3 b, void** args) {
+  hipKernelNodeParams p{};
+  p.func = const_cast<void*>(fn);
+  p.gridDim = g;
+  p.blockDim = b;
+  p.sharedMemBytes = 0;
+  p.kernelParams = args;
+  p.extra = nullptr;
+  return p;
+}
+}  // namespace
+
+// The bounce loop as a graph: fill(counters) -> fill(seq) -> bounce 0 -> ... ->
+// bounce K, all kernel nodes (no memset nodes).  Built on first use for a
+// (K, depth class, counting) shape, then only the kernel arguments are updated.
+void launch_trace_graph(const TraceLaunch& T, const BounceParams* P, int nP, hipStream_t s) {
+  sbr_context_s* c = T.ctx;
+  const int depth = T.scene->bvh_depth;
+  const int bucket = depth <= 16 ? 16 : depth <= 32 ? 32 : 64;
+  const int count = T.work ? 1 : 0;
+  TraceGraph* G = nullptr;
+  for (auto* g : c->graphs)
+    if (g->K == T.K && g->depth_bucket == bucket && g->count == count) G = g;
+  uint32_t* cnt = T.counters;
+  int64_t ncnt = trace_counter_words(T.K);
+  uint32_t v0 = 0, vneg = 0xffffffffu;
+  uint32_t* seqp = reinterpret_cast<uint32_t*>(T.seq);
+  int64_t nseq = (int64_t)(T.K + 1) * T.NR;
+  void* a_cnt[] = {&cnt, &v0, &ncnt};
+  void* a_seq[] = {&seqp, &vneg, &nseq};
+  std::vector<BounceParams> Pc(P, P + nP);
+  std::vector<void*> a_b(nP);
+  for (int k = 0; k < nP; ++k) a_b[k] = &Pc[k];
+  const void* ffill = reinterpret_cast<const void*>(&k_fill_u32_graph);
+  const dim3 gc((unsigned)((ncnt + 255) / 256)), gs((unsigned)((nseq + 255) / 256)), gb(T.grid), b256(256);
+  const void* fb = count ? bounce_fn<true>(depth) : bounce_fn<false>(depth);
+  if (!G) {
+    G = new TraceGraph();
+    G->K = T.K, G->depth_bucket = bucket, G->count = count;
+    SBR_HIP(hipGraphCreate(&G->graph, 0));
+    hipGraphNode_t prev = nullptr;
+    auto add = [&](const void* fn, dim3 g, void** args) {
+      hipKernelNodeParams kp = knode(fn, g, b256, args);
+      hipGraphNode_t n;
+      SBR_HIP(hipGraphAddKernelNode(&n, G->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
+      G->nodes.push_back(n);
+      prev = n;
+    };
+    add(ffill, gc, a_cnt);
+    add(ffill, gs, a_seq);
+    for (int k = 0; k < nP; ++k) add(fb, gb, &a_b[k]);
+    SBR_HIP(hipGraphInstantiate(&G->exec, G->graph, nullptr, nullptr, 0));
+    c->graphs.push_back(G);
+  } else {
+    hipKernelNodeParams kp = knode(ffill, gc, b256, a_cnt);
+    SBR_HIP(hipGraphExecKernelNodeSetParams(G->exec, G->nodes[0], &kp));
+    kp = knode(ffill, gs, b256, a_seq);
+    SBR_HIP(hipGraphExecKernelNodeSetParams(G->exec, G->nodes[1], &kp));
+    for (int k = 0; k < nP; ++k) {
+      kp = knode(fb, gb, b256, &a_b[k]);
+      SBR_HIP(hipGraphExecKernelNodeSetParams(G->exec, G->nodes[2 + k], &kp));
+    }
+  }
+  ::sbr::TimedLaunch tl_("bounce", s);
+  SBR_HIP(hipGraphLaunch(G->exec, s));
+}
+
 void launch_trace(const TraceLaunch& T, void* ray_a, void* ray_b, hipStream_t s) {
-  const sbr_scene_s* sc = T.scene;
   BounceParams P{};
-  P.has_bvh = sc->T > 0;
-  P.nodes = sc->nodes.as<float4>();
-  P.tri = sc->tri32.as<float4>();
-  P.tplane = sc->tplane.as<double4>();
-  P.tplaneid = sc->tplaneid.as<int32_t>();
-  for (int k = 0; k < 6; ++k) P.root[k] = sc->root_host[k];
-  P.cx = sc->center[0], P.cy = sc->center[1], P.cz = sc->center[2];
+  P.one = scene_desc(T.scene, T.tx, T.N, T.K, T.R, T.NR, T.seq, 0);
+  P.n_scenes = 1;
   P.G = geo_tables();
-  P.N = T.N;
-  P.R = T.R;
-  P.tx = T.tx;
-  P.K = T.K;
   P.n_first = T.NR;
   P.work = T.work;
   P.chunk = T.chunk;
-  const int depth = sc->bvh_depth;
+  const int depth = T.scene->bvh_depth;
+  RaySoA A = soa_of(ray_a, T.NR), B = soa_of(ray_b, T.NR);
+  std::vector<BounceParams> Pk(T.K + 1, P);
+  for (int k = 0; k <= T.K; ++k) {
+    Pk[k].k = k;
+    Pk[k].queue = T.counters + 32 + 256 * k;
+    Pk[k].n_in_ptr = k > 0 ? T.counters + (k - 1) : nullptr;
+    Pk[k].n_out_ptr = T.counters + k;
+    Pk[k].in = (k % 2 == 1) ? A : B;
+    Pk[k].out = (k % 2 == 1) ? B : A;
+  }
+  if (T.ctx && T.ctx->tune.trace_graph) {
+    launch_trace_graph(T, Pk.data(), T.K + 1, s);
+    return;
+  }
   // counters: [0..K] survivors of each bounce; then per bounce 8 queue slots of 128 B
   fill_u32(T.counters, 0, trace_counter_words(T.K), s);
   // every chain entry starts as "miss"; the bounce kernels overwrite the ones they trace
   fill_u32(reinterpret_cast<uint32_t*>(T.seq), 0xffffffffu, (int64_t)(T.K + 1) * T.NR, s);
-  RaySoA A = soa_of(ray_a, T.NR), B = soa_of(ray_b, T.NR);
   for (int k = 0; k <= T.K; ++k) {
-    P.k = k;
-    P.queue = T.counters + 32 + 256 * k;
-    P.n_in_ptr = k > 0 ? T.counters + (k - 1) : nullptr;
-    P.n_out_ptr = T.counters + k;
-    P.in = (k % 2 == 1) ? A : B;
-    P.out = (k % 2 == 1) ? B : A;
-    P.seq_k = T.seq + (int64_t)k * T.NR;
-    const dim3 g(T.grid), b(256);
     ::sbr::TimedLaunch tl_("bounce", s);
-    if (T.work) {
-      if (depth <= 16) hipLaunchKernelGGL((k_bounce<16, true>), g, b, 0, s, P);
-      else if (depth <= 32) hipLaunchKernelGGL((k_bounce<32, true>), g, b, 0, s, P);
-      else hipLaunchKernelGGL((k_bounce<64, true>), g, b, 0, s, P);
-    } else {
-      if (depth <= 16) hipLaunchKernelGGL((k_bounce<16, false>), g, b, 0, s, P);
-      else if (depth <= 32) hipLaunchKernelGGL((k_bounce<32, false>), g, b, 0, s, P);
-      else hipLaunchKernelGGL((k_bounce<64, false>), g, b, 0, s, P);
-    }
+    if (T.work) launch_bounce<true, false>(depth, dim3(T.grid), Pk[k], s);
+    else launch_bounce<false, false>(depth, dim3(T.grid), Pk[k], s);
     SBR_LAUNCH_CHECK();
   }
+}
+
+void launch_trace_batch(const std::vector<sbr_trace_s*>& trs, int grid, int chunk, void* ray_a, void* ray_b,
+                        uint32_t* counters, unsigned long long* t_first, unsigned long long* t_last, hipStream_t s) {
+  const int n = (int)trs.size();
+  std::vector<SceneDesc> tab(n);
+  std::vector<int64_t> offs(n + 1);
+  int64_t off = 0;
+  int depth = 1, Kmax = 0;
+  for (int i = 0; i < n; ++i) {
+    sbr_trace_s* t = trs[i];
+    tab[i] = scene_desc(t->scene, t->tx.as<double>(), t->N, t->K, t->R, t->NR, t->seq.as<int32_t>(), off);
+    offs[i] = off;
+    off += t->NR;
+    depth = std::max(depth, t->scene->bvh_depth);
+    Kmax = std::max(Kmax, t->K);
+  }
+  offs[n] = off;
+  Buf dtab, doffs;
+  dtab.alloc(sizeof(SceneDesc) * n, s);
+  doffs.alloc(sizeof(int64_t) * (n + 1), s);
+  SBR_HIP(hipMemcpyAsync(dtab.p, tab.data(), sizeof(SceneDesc) * n, hipMemcpyHostToDevice, s));
+  SBR_HIP(hipMemcpyAsync(doffs.p, offs.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s));
+  fill_u32(counters, 0, trace_counter_words(Kmax), s);
+  fill_u32(reinterpret_cast<uint32_t*>(t_first), 0xffffffffu, 2 * (int64_t)n, s);
+  fill_u32(reinterpret_cast<uint32_t*>(t_last), 0u, 2 * (int64_t)n, s);
+  for (sbr_trace_s* t : trs)
+    fill_u32(t->seq.as<uint32_t>(), 0xffffffffu, (int64_t)(t->K + 1) * t->NR, s);
+  BounceParams P{};
+  P.table = dtab.as<SceneDesc>();
+  P.offs = doffs.as<int64_t>();
+  P.n_scenes = n;
+  P.G = geo_tables();
+  P.n_first = off;
+  P.chunk = chunk;
+  P.t_first = t_first;
+  P.t_last = t_last;
+  RaySoA A = soa_of(ray_a, off), B = soa_of(ray_b, off);
+  for (int k = 0; k <= Kmax; ++k) {
+    P.k = k;
+    P.queue = counters + 32 + 256 * k;
+    P.n_in_ptr = k > 0 ? counters + (k - 1) : nullptr;
+    P.n_out_ptr = counters + k;
+    P.in = (k % 2 == 1) ? A : B;
+    P.out = (k % 2 == 1) ? B : A;
+    ::sbr::TimedLaunch tl_("bounce", s);
+    launch_bounce<false, true>(depth, dim3(grid), P, s);
+    SBR_LAUNCH_CHECK();
+  }
+  // host copies of the table must outlive the copies: synchronise before they go
+  SBR_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace sbr

@@ -79,6 +79,8 @@ def _load():
         "sbr_trace_work": [P, P, P],
         "sbr_context_set_tuning": [P, C.c_char_p, I32],
         "sbr_context_get_tuning": [P, C.c_char_p, P],
+        "sbr_trace_batch": [P, I32, P, P, P, P, P, U32, P],
+        "sbr_trace_latency": [P, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -213,6 +215,34 @@ def sbr_trace(ctx: Context, scene: Scene, tx, geodesic_N: int, max_bounces: int)
     tr.Nt, tr.N, tr.K = n, geodesic_N, max_bounces
     tr.R = 10 * geodesic_N * geodesic_N + 2
     return tr
+
+
+def sbr_trace_batch(ctx: Context, scenes, txs, geodesic_N, max_bounces):
+    """One breadth-first persistent launch per bounce over all problems; returns traces."""
+    n = len(scenes)
+    arrs = [_Arr(t, np.float64, F64) for t in txs]
+    flags = _flags(arrs, SBR_IN_DEVICE)
+    sc = (C.c_void_p * n)(*[x.h for x in scenes])
+    tx = (C.c_void_p * n)(*[a.ptr for a in arrs])
+    nt = np.array([(a.ref.numel() if _is_torch(a.ref) else a.ref.size) // 3 for a in arrs], np.int32)
+    nv = np.ascontiguousarray(geodesic_N, np.int32)
+    kv = np.ascontiguousarray(max_bounces, np.int32)
+    out = (C.c_void_p * n)()
+    _call("sbr_trace_batch", ctx.h, n, sc, tx, nt.ctypes.data_as(C.c_void_p), nv.ctypes.data_as(C.c_void_p),
+          kv.ctypes.data_as(C.c_void_p), flags, out)
+    res = []
+    for i in range(n):
+        tr = Trace(C.c_void_p(out[i]), (ctx, scenes[i], arrs[i]))
+        tr.Nt, tr.N, tr.K = int(nt[i]), int(nv[i]), int(kv[i])
+        tr.R = 10 * tr.N * tr.N + 2
+        res.append(tr)
+    return res
+
+
+def sbr_trace_latency(tr: Trace) -> float:
+    v = C.c_double()
+    _call("sbr_trace_latency", tr.h, C.byref(v))
+    return v.value
 
 
 def sbr_trace_info(tr: Trace):

@@ -267,3 +267,69 @@ def test_device_io_matches_host(S, ctx):
     S.sbr_synchronize(ctx)
     assert np.array_equal(H.cpu().numpy(), host.H)
     assert np.allclose(H64.cpu().numpy(), host.H, rtol=1e-6, atol=1e-12)
+
+
+# ------------------------------------------------------------------ batched multi-scene launch
+def test_batched_trace_matches_individual(S, ctx):
+    """One persistent launch per bounce over several uneven problems gives the
+    same hit chains, paths and H as tracing each problem alone."""
+    banner("batched trace")
+    ws = [W.tiny_room(N=24), W.random_box_scene(21, n_boxes=12, n_rx=3, N=16, K=4),
+          W.batched_uneven(4003), W.random_box_scene(22, n_boxes=5, n_rx=2, N=9, K=1), W.free_space(N=5)]
+    scenes = [S.sbr_scene_build(ctx, w.tri, w.eps_r, w.sigma, w.rough) for w in ws]
+    trs = S.sbr_trace_batch(ctx, scenes, [w.tx for w in ws], [w.geodesic_N for w in ws],
+                            [w.max_bounces for w in ws])
+    for w, sc, tb in zip(ws, scenes, trs):
+        ts = S.sbr_trace(ctx, sc, w.tx, w.geodesic_N, w.max_bounces)
+        assert np.array_equal(S.sbr_trace_hits(tb), S.sbr_trace_hits(ts)), w.name
+        assert S.sbr_trace_info(tb)["segments"] == S.sbr_trace_info(ts)["segments"]
+        assert S.sbr_trace_latency(tb) > 0 and S.sbr_trace_latency(ts) == -1.0
+        pb = S.sbr_receive(ctx, tb, w.rx)
+        pi = S.sbr_receive(ctx, ts, w.rx)
+        Hb = np.zeros((len(w.freq), len(w.rx), 1), np.complex128)
+        Hi = np.zeros_like(Hb)
+        S.sbr_channel(ctx, pb, w.freq, H_c128=Hb)
+        S.sbr_channel(ctx, pi, w.freq, H_c128=Hi)
+        assert np.array_equal(Hb, Hi)
+
+
+def test_trace_graph_replays(S, ctx):
+    """The cached hipGraph bounce loop gives the eager result on every replay,
+    with eager traces and synchronisations in between, across scenes that
+    share a graph shape (same K and tree-depth class)."""
+    banner("trace graph replays")
+    ws = [W.random_box_scene(31, n_boxes=10, n_rx=2, N=20, K=3), W.random_box_scene(32, n_boxes=14, n_rx=2, N=28, K=3),
+          W.tiny_room(N=16, K=3)]
+    scenes = [S.sbr_scene_build(ctx, w.tri, w.eps_r, w.sigma, w.rough) for w in ws]
+    S.sbr_context_set_tuning(ctx, "trace_graph", 0)
+    ref = [S.sbr_trace_hits(S.sbr_trace(ctx, sc, w.tx, w.geodesic_N, w.max_bounces)) for w, sc in zip(ws, scenes)]
+    try:
+        for rep in range(3):
+            for i, (w, sc) in enumerate(zip(ws, scenes)):
+                S.sbr_context_set_tuning(ctx, "trace_graph", 1)
+                g = S.sbr_trace(ctx, sc, w.tx, w.geodesic_N, w.max_bounces)
+                S.sbr_context_set_tuning(ctx, "trace_graph", 0)
+                e = S.sbr_trace(ctx, sc, w.tx, w.geodesic_N, w.max_bounces)  # eager work in between
+                assert np.array_equal(S.sbr_trace_hits(g), ref[i]), (rep, i)
+                assert np.array_equal(S.sbr_trace_hits(e), ref[i])
+                assert S.sbr_trace_info(g)["segments"] == S.sbr_trace_info(e)["segments"]
+                S.sbr_synchronize(ctx)
+    finally:
+        S.sbr_context_set_tuning(ctx, "trace_graph", 0)
+
+
+def test_autotuner_picks_and_applies(S, ctx, tmp_path):
+    banner("autotuner")
+    from paper_2208_10006_amd import autotune as A
+    w = W.random_box_scene(33, n_boxes=12, n_rx=2, N=40, K=3)
+    sc = S.sbr_scene_build(ctx, w.tri, w.eps_r, w.sigma, w.rough)
+    ref = S.sbr_trace_hits(S.sbr_trace(ctx, sc, w.tx, w.geodesic_N, w.max_bounces))
+    path = str(tmp_path / "tuning.json")
+    e = A.autotune_trace(ctx, sc, w.tx, w.geodesic_N, w.max_bounces, w.T, cache_path=path, reps=1,
+                         grid={"trace_blocks_per_cu": (2, 4), "trace_chunk": (64, 128), "trace_graph": (0, 1)})
+    assert len(e["searched"]) == 8 and A.current(ctx) == e["config"]
+    # every tuned setting traces the same rays to the same hits
+    assert np.array_equal(S.sbr_trace_hits(S.sbr_trace(ctx, sc, w.tx, w.geodesic_N, w.max_bounces)), ref)
+    e2 = A.autotune_trace(ctx, sc, w.tx, w.geodesic_N, w.max_bounces, w.T, cache_path=path)
+    assert e2["config"] == e["config"]  # served from the cache
+    A.apply(ctx, {"trace_blocks_per_cu": 4, "trace_chunk": 64, "trace_graph": 0})
