@@ -1,0 +1,115 @@
+// nn_api.hip -- C-ABI wrappers of the surrogate kernels (include/sbr_nn.h).
+#include <cmath>
+#include <functional>
+
+#include "../../include/sbr_nn.h"
+#include "sbr_internal.hpp"
+
+namespace sbr {
+sbr_status nn_guard_call(sbr_context_t ctx, const std::function<void(hipStream_t)>& f);
+}
+
+using namespace sbr;
+
+#define NN_ENTRY(body)                                                                    \
+  return nn_guard_call(ctx, [&](hipStream_t s) { body; })
+#define NN_REQUIRE(cond, ...) SBR_CHECK(cond, SBR_E_INVALID_ARG, __VA_ARGS__)
+
+extern "C" {
+
+sbr_status sbr_nn_gemm_bf16(sbr_context_t ctx, int32_t M, int32_t N, int32_t K, const void* A, int64_t a_si,
+                            int64_t a_sk, const void* B, int64_t b_sk, int64_t b_sj, const float* bias, void* C,
+                            int64_t ldc, uint32_t flags) {
+  NN_ENTRY({
+    NN_REQUIRE(M >= 0 && N >= 0 && K >= 0 && (M == 0 || N == 0 || (C && (K == 0 || (A && B)))), "gemm arguments");
+    NN_REQUIRE((flags & ~7u) == 0, "gemm flags 0x%x", flags);
+    nn_gemm(M, N, K, A, a_si, a_sk, B, b_sk, b_sj, bias, C, ldc, flags, s);
+  });
+}
+
+sbr_status sbr_nn_im2col(sbr_context_t ctx, const void* x, int32_t n, int32_t H, int32_t W, int32_t C, void* col) {
+  NN_ENTRY({
+    NN_REQUIRE(x && col && n > 0 && H > 0 && W > 0 && C > 0 && H % 2 == 0 && W % 2 == 0, "im2col arguments");
+    nn_im2col(x, n, H, W, C, col, s);
+  });
+}
+
+sbr_status sbr_nn_col2im(sbr_context_t ctx, const float* dcol, int32_t n, int32_t H, int32_t W, int32_t C, float* dx) {
+  NN_ENTRY({
+    NN_REQUIRE(dcol && dx && n > 0 && H > 0 && W > 0 && C > 0 && H % 2 == 0 && W % 2 == 0, "col2im arguments");
+    nn_col2im(dcol, n, H, W, C, dx, s);
+  });
+}
+
+sbr_status sbr_nn_fourier(sbr_context_t ctx, const float* x, int64_t n, int32_t D, int32_t L, const void* emb,
+                          int32_t E, const int32_t* scene, int32_t F, void* out) {
+  NN_ENTRY({
+    NN_REQUIRE(x && out && n >= 0 && D >= 0 && L >= 0 && L <= 30 && E >= 0 && F >= E + D + 2 * D * L,
+               "fourier arguments");
+    NN_REQUIRE(E == 0 || (emb && scene), "fourier embedding");
+    if (n > 0) nn_fourier(x, n, D, L, emb, E, scene, F, out, s);
+  });
+}
+
+sbr_status sbr_nn_relu_backward(sbr_context_t ctx, const float* g, const void* y, int64_t n, float* gout, void* gbf) {
+  NN_ENTRY({
+    NN_REQUIRE(g && y && n >= 0 && (gout || gbf), "relu_backward arguments");
+    if (n > 0) nn_relu_bwd(g, y, n, gout, gbf, s);
+  });
+}
+
+sbr_status sbr_nn_cast_bf16(sbr_context_t ctx, const float* a, int64_t n, void* b) {
+  NN_ENTRY({
+    NN_REQUIRE(a && b && n >= 0, "cast arguments");
+    if (n > 0) nn_cast(a, n, b, s);
+  });
+}
+
+sbr_status sbr_nn_mse(sbr_context_t ctx, const float* pred, int64_t ldp, const float* target, const float* weight,
+                      int64_t n, int32_t T, float scale, float* dpred, int64_t ldd, double* loss) {
+  NN_ENTRY({
+    NN_REQUIRE(pred && target && dpred && loss && n >= 0 && T > 0, "mse arguments");
+    nn_mse(pred, ldp, target, weight, n, T, scale, dpred, ldd, loss, s);
+  });
+}
+
+sbr_status sbr_nn_colsum(sbr_context_t ctx, const float* g, int64_t M, int32_t N, int64_t ld, float* out,
+                         int32_t accumulate) {
+  NN_ENTRY({
+    NN_REQUIRE(g && out && M >= 0 && N > 0, "colsum arguments");
+    nn_colsum(g, M, N, ld, out, accumulate, s);
+  });
+}
+
+sbr_status sbr_nn_adam(sbr_context_t ctx, float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1,
+                       float b2, float eps, float wd, int32_t step, void* wbf) {
+  NN_ENTRY({
+    NN_REQUIRE(w && g && m && v && n >= 0 && step >= 1, "adam arguments");
+    if (n > 0) nn_adam(w, g, m, v, n, lr, b1, b2, eps, wd, step, wbf, s);
+  });
+}
+
+sbr_status sbr_nn_ensemble(sbr_context_t ctx, const float* out, int32_t E, int64_t member_stride, int64_t n,
+                           int64_t ld, int32_t t, float threshold, float* mean, float* spread, uint8_t* mask) {
+  NN_ENTRY({
+    NN_REQUIRE(out && mean && E >= 1 && n >= 0 && t >= 0 && t < ld, "ensemble arguments");
+    if (n > 0) nn_ensemble(out, E, member_stride, n, ld, t, threshold, mean, spread, mask, s);
+  });
+}
+
+sbr_status sbr_nn_gather_rows(sbr_context_t ctx, const void* src, int64_t row_bytes, const int64_t* idx, int64_t n,
+                              void* dst) {
+  NN_ENTRY({
+    NN_REQUIRE(src && idx && dst && n >= 0 && row_bytes > 0 && row_bytes % 4 == 0, "gather arguments");
+    if (n > 0) nn_gather_rows(src, row_bytes, idx, n, dst, s);
+  });
+}
+
+sbr_status sbr_nn_onehot_bf16(sbr_context_t ctx, const int32_t* idx, int64_t n, int32_t width, void* out) {
+  NN_ENTRY({
+    NN_REQUIRE(idx && out && n >= 0 && width > 0, "onehot arguments");
+    if (n > 0) nn_onehot(idx, n, width, out, s);
+  });
+}
+
+}  // extern "C"

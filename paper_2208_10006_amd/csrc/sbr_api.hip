@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <unordered_map>
 #include <vector>
 
@@ -369,6 +370,15 @@ bool finite_all(const double* p, size_t n) {
 }
 
 }  // namespace
+
+// entry of the surrogate kernels: context check, device, profiler, error mapping
+sbr_status nn_guard_call(sbr_context_t ctx, const std::function<void(hipStream_t)>& f) {
+  return guard([&] {
+    auto* c = check_handle<sbr_context_s>(ctx, kContext, "context");
+    set_device(c);
+    f(c->stream);
+  });
+}
 }  // namespace sbr
 
 using namespace sbr;

@@ -225,6 +225,68 @@ def _urban_geometry(rng, n_boxes=200, tx_xy=(0.0, 0.0), half=250.0):
     return tris, eps, rough, boxes
 
 
+def _outside_footprints(px, py, boxes, margin):
+    """Boolean mask of points farther than `margin` from every yawed footprint."""
+    px = np.asarray(px, float)[:, None]
+    py = np.asarray(py, float)[:, None]
+    b = np.asarray(boxes, float)
+    if len(b) == 0:
+        return np.ones(px.shape[0], bool)
+    cx, cy, hx, hy, yaw = b[:, 0], b[:, 1], b[:, 2], b[:, 3], b[:, 4]
+    d = _footprint_dist(px, py, cx[None, :], cy[None, :], hx[None, :], hy[None, :], yaw[None, :])
+    return np.all(d > margin, axis=1)
+
+
+def height_map(boxes, heights, n: int = 128, half: float = 250.0) -> np.ndarray:
+    """Max building height per pixel on an n x n grid over [-half, half]^2
+    (pixel centres), divided by 60 m.  [n][n] float32, row = y, column = x."""
+    c = (np.arange(n) + 0.5) * (2 * half / n) - half
+    gx, gy = np.meshgrid(c, c, indexing="xy")
+    hm = np.zeros(n * n)
+    px, py = gx.ravel(), gy.ravel()
+    for (cx, cy, hx, hy, yaw), h in zip(boxes, heights):
+        inside = _footprint_dist(px, py, cx, cy, hx, hy, yaw) <= 0.0
+        hm[inside] = np.maximum(hm[inside], h)
+    return (hm / 60.0).reshape(n, n).astype(np.float32)
+
+
+def urban_surrogate_scene(seed: int, n_rx: int = 1000, random_rx: bool = False, N: int = 1024, K: int = 6):
+    """Urban-canyon generator for the surrogate: carrier f_c ~ logU(28, 300) GHz,
+    Tx at a random outdoor xy at 25 m, Rx either the grid points of the
+    configured canyon (first n_rx outside footprints) or n_rx uniform random
+    outdoor points at 1.5 m.  Returns (workload, height map, building heights)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    fc = float(np.exp(rng.uniform(np.log(28e9), np.log(300e9))))
+    while True:
+        tx_xy = rng.uniform(-200.0, 200.0, size=2)
+        tris, eps, rough, boxes = _urban_geometry(rng, tx_xy=tuple(tx_xy))
+        if _outside_footprints([tx_xy[0]], [tx_xy[1]], [b[:5] for b in boxes], 15.0)[0]:
+            break
+    T = len(tris)
+    tri, e, s, r = _pack(tris, eps, [0.0326] * T, rough)
+    fb = [b[:5] for b in boxes]
+    if random_rx:
+        pts = np.zeros((0, 2))
+        while len(pts) < n_rx:
+            cand = rng.uniform(-236.25, 236.25, size=(4 * n_rx, 2))
+            ok = _outside_footprints(cand[:, 0], cand[:, 1], fb, 1.0)
+            far = np.hypot(cand[:, 0] - tx_xy[0], cand[:, 1] - tx_xy[1]) > 1.0
+            pts = np.concatenate([pts, cand[ok & far]])
+        pts = pts[:n_rx]
+    else:
+        g = (np.arange(64) - 31.5) * 7.5
+        gx, gy = np.meshgrid(g, g, indexing="ij")
+        allp = np.stack([gx.ravel(), gy.ravel()], axis=1)[rng.permutation(64 * 64)]
+        ok = _outside_footprints(allp[:, 0], allp[:, 1], fb, 1.0)
+        pts = allp[ok][:n_rx]
+    rx = np.concatenate([pts, np.full((len(pts), 1), 1.5)], axis=1)
+    atm = np.array([0.001 + 0.029 * np.exp(-((fc - 300e9) / 2.5e9) ** 2)], np.float32)
+    w = Workload(f"urban_surrogate_{seed}", tri, e, s, r, np.array([[tx_xy[0], tx_xy[1], 25.0]]), rx,
+                 np.array([fc]), atm_db_per_m=atm, geodesic_N=N, max_bounces=K)
+    heights = [b[5] for b in boxes]
+    return w, height_map(fb, heights), heights
+
+
 def urban_canyon(seed: int = 2, N: int = 1024, K: int = 6, n_rx: int = 1000,
                  fc: float = 300e9, bw: float = 10e9, nf: int = 256,
                  tx=(0.0, 0.0, 25.0)) -> Workload:
@@ -241,14 +303,10 @@ def urban_canyon(seed: int = 2, N: int = 1024, K: int = 6, n_rx: int = 1000,
     gx, gy = np.meshgrid(g, g, indexing="ij")
     pts = np.stack([gx.ravel(), gy.ravel()], axis=1)
     perm = rng.permutation(len(pts))
-    keep = []
-    for i in perm:
-        px, py = pts[i]
-        if all(_footprint_dist(px, py, b[0], b[1], b[2], b[3], b[4]) > 1.0 for b in boxes):
-            keep.append((px, py, 1.5))
-        if len(keep) == n_rx:
-            break
-    rx = np.array(keep, float)
+    cand = pts[perm]
+    ok = _outside_footprints(cand[:, 0], cand[:, 1], [b[:5] for b in boxes], 1.0)
+    sel = cand[ok][:n_rx]
+    rx = np.concatenate([sel, np.full((len(sel), 1), 1.5)], axis=1)
     k = np.arange(nf)
     df = bw / nf
     freq = fc + (k - nf // 2) * df

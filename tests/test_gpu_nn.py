@@ -1,0 +1,274 @@
+"""GPU tests of the surrogate building blocks (include/sbr_nn.h) against plain
+FP64 numpy and the CPU surrogate reference.
+
+GEMM cases use small integers (exact in bfloat16, every partial sum exact in
+FP32) so the matrix-core result must equal the FP64 product bit for bit in
+every operand layout; random-valued cases then check rounding behaviour.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import surrogate_ref as R
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_2208_10006_amd import sbr, nn
+    return torch, sbr, nn, sbr.Context(0)
+
+
+def banner(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(torch, a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def host(t):
+    if str(t.dtype) == "torch.bfloat16":
+        return t.float().cpu().numpy().astype(np.float64)
+    return t.cpu().numpy()
+
+
+def sync(torch):
+    torch.cuda.synchronize()
+
+
+def run_gemm(env, A, B, layout, bias=None, flags=0, C0=None, out_bf16=False):
+    """A [M][K], B [K][N] (numpy); `layout` chooses the strides the kernel sees."""
+    torch, S, nn, ctx = env
+    M, K = A.shape
+    N = B.shape[1]
+    if layout in ("fwd", "bwd_data"):
+        Ad = dev(torch, A, torch.bfloat16)
+        a_si, a_sk = K, 1
+    else:  # A stored transposed ([K][M], "bwd_weight")
+        Ad = dev(torch, A.T, torch.bfloat16)
+        a_si, a_sk = 1, M
+    if layout in ("fwd", "bwd_weight"):
+        Bd = dev(torch, B, torch.bfloat16)
+        b_sk, b_sj = N, 1
+    else:  # B stored transposed ([N][K], "bwd_data")
+        Bd = dev(torch, B.T, torch.bfloat16)
+        b_sk, b_sj = 1, K
+    dt = torch.bfloat16 if out_bf16 else torch.float32
+    Cd = dev(torch, C0, dt) if C0 is not None else torch.full((M, N), 7.0, dtype=dt, device="cuda")
+    bd = dev(torch, bias, torch.float32) if bias is not None else None
+    f = flags | (nn.OUT_BF16 if out_bf16 else 0)
+    nn.sbr_nn_gemm_bf16(ctx, M, N, K, Ad, a_si, a_sk, Bd, b_sk, b_sj, bd, Cd, N, f)
+    sync(torch)
+    return host(Cd)
+
+
+SHAPES = [(1, 1, 1), (16, 16, 32), (64, 64, 32), (64, 64, 64), (100, 70, 45), (130, 257, 300), (5, 3, 1000),
+          (300, 2, 17)]
+
+
+@pytest.mark.parametrize("layout", ["fwd", "bwd_data", "bwd_weight"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_gemm_exact_integers(env, layout, shape):
+    M, N, K = shape
+    banner("gemm exact", layout, M, N, K)
+    rng = np.random.default_rng(M * 1000 + N * 10 + K)
+    A = rng.integers(-4, 5, (M, K)).astype(np.float64)
+    B = rng.integers(-4, 5, (K, N)).astype(np.float64)
+    C = run_gemm(env, A, B, layout)
+    assert np.array_equal(C, A @ B)
+
+
+def test_gemm_operand_positions(env):
+    """One-hot operands: C[i][j] = A[i][k] B[k][j] for a single k isolates the
+    lane layout of each operand (a wrong row/column/k mapping moves the 1)."""
+    M, N, K = 48, 40, 96
+    banner("gemm positions", M, N, K)
+    rng = np.random.default_rng(5)
+    for layout in ["fwd", "bwd_data", "bwd_weight"]:
+        for _ in range(3):
+            k = int(rng.integers(0, K))
+            A = np.zeros((M, K))
+            B = np.zeros((K, N))
+            A[:, k] = np.arange(M) + 1
+            B[k, :] = (np.arange(N) + 1) * 64
+            C = run_gemm(env, A, B, layout)
+            assert np.array_equal(C, A @ B), (layout, k)
+
+
+def test_gemm_k_zero_gives_bias(env):
+    torch, S, nn, ctx = env
+    banner("gemm K=0")
+    bias = np.arange(9, dtype=np.float32)
+    A = np.zeros((5, 0))
+    B = np.zeros((0, 9))
+    C = run_gemm(env, A, B, "fwd", bias=bias)
+    assert np.array_equal(C, np.tile(bias, (5, 1)))
+
+
+@pytest.mark.parametrize("layout", ["fwd", "bwd_data", "bwd_weight"])
+def test_gemm_random_values_and_flags(env, layout):
+    M, N, K = 197, 131, 259
+    banner("gemm flags", layout, M, N, K)
+    rng = np.random.default_rng(11)
+    A = R.bf16(rng.standard_normal((M, K)))
+    B = R.bf16(rng.standard_normal((K, N)))
+    bias = rng.standard_normal(N).astype(np.float32)
+    ref = A @ B + bias.astype(np.float64)
+    tol = 2e-6 * (np.abs(A) @ np.abs(B) + np.abs(bias)) + 1e-30
+    C = run_gemm(env, A, B, layout, bias=bias)
+    assert np.all(np.abs(C - ref) <= tol)
+    Cr = run_gemm(env, A, B, layout, bias=bias, flags=1)
+    assert np.all(np.abs(Cr - np.maximum(ref, 0)) <= tol)
+    assert np.all(Cr >= 0)
+    # bf16 output: the FP32 result rounded once
+    Cb = run_gemm(env, A, B, layout, bias=bias, flags=1, out_bf16=True)
+    assert np.array_equal(Cb, R.bf16(np.maximum(C, 0).astype(np.float32)))
+    # accumulate into an existing FP32 C
+    C0 = rng.standard_normal((M, N)).astype(np.float32)
+    Ca = run_gemm(env, A, B, layout, bias=bias, flags=4, C0=C0)
+    assert np.all(np.abs(Ca - (ref + C0)) <= tol + 1e-6 * np.abs(C0))
+
+
+def test_gemm_rejects_bad_arguments(env):
+    torch, S, nn, ctx = env
+    banner("gemm errors")
+    x = torch.zeros(16, dtype=torch.bfloat16, device="cuda")
+    with pytest.raises(Exception):
+        nn.sbr_nn_gemm_bf16(ctx, 4, 4, 4, x, 4, 1, x, 4, 1, None, x, 4, 0x10)
+    with pytest.raises(Exception):
+        nn.sbr_nn_gemm_bf16(ctx, -1, 4, 4, x, 4, 1, x, 4, 1, None, x, 4, 0)
+    with pytest.raises(Exception):
+        nn.sbr_nn_im2col(ctx, x, 1, 3, 4, 1, x)
+
+
+@pytest.mark.parametrize("shape", [(1, 2, 2, 1), (2, 8, 6, 3), (3, 16, 16, 16), (1, 128, 128, 1)])
+def test_im2col_col2im(env, shape):
+    torch, S, nn, ctx = env
+    n, H, W, C = shape
+    banner("im2col/col2im", shape)
+    rng = np.random.default_rng(H * W + C)
+    x = R.bf16(rng.standard_normal(shape))
+    xd = dev(torch, x, torch.bfloat16)
+    col = torch.empty((n * (H // 2) * (W // 2), 9 * C), dtype=torch.bfloat16, device="cuda")
+    nn.sbr_nn_im2col(ctx, xd, n, H, W, C, col)
+    d = rng.standard_normal(col.shape).astype(np.float32)
+    dx = torch.empty(shape, dtype=torch.float32, device="cuda")
+    nn.sbr_nn_col2im(ctx, dev(torch, d, torch.float32), n, H, W, C, dx)
+    sync(torch)
+    assert np.array_equal(host(col), R.conv_patches(x))
+    ref = R.conv_patches_adjoint(d.astype(np.float64), n, H, W, C)
+    assert np.allclose(host(dx), ref, rtol=1e-6, atol=1e-6)
+
+
+def test_fourier_features(env):
+    torch, S, nn, ctx = env
+    n, D, L, E, F, Sn = 777, 7, 8, 16, 144, 3
+    banner("fourier", n, D, L, E, F)
+    rng = np.random.default_rng(3)
+    x = rng.uniform(-1, 1, (n, D)).astype(np.float32)
+    x[0, :] = 0.0
+    x[1, :] = 0.5
+    emb = R.bf16(rng.standard_normal((Sn, E)))
+    scene = rng.integers(0, Sn, n).astype(np.int32)
+    out = torch.empty((n, F), dtype=torch.bfloat16, device="cuda")
+    nn.sbr_nn_fourier(ctx, dev(torch, x, torch.float32), n, D, L, dev(torch, emb, torch.bfloat16), E,
+                      dev(torch, scene, torch.int32), F, out)
+    sync(torch)
+    g = host(out)
+    arch = R.Arch(E=E, D=D, L=L, F=F)
+    ref = R.features(arch, emb, x.astype(np.float64), scene, lambda a: a)
+    assert np.array_equal(g[:, :E + D], R.bf16(ref[:, :E + D]))
+    assert np.all(g[:, E + D + 2 * D * L:] == 0)
+    fr, fg = ref[:, E + D:E + D + 2 * D * L], g[:, E + D:E + D + 2 * D * L]
+    assert np.all(np.abs(fg - fr) <= 2.0 ** -8 * np.abs(fr) + 1e-7)
+
+
+def test_elementwise_kernels(env):
+    torch, S, nn, ctx = env
+    banner("relu_backward/cast/colsum/gather/onehot")
+    rng = np.random.default_rng(4)
+    n = 10007
+    g = rng.standard_normal(n).astype(np.float32)
+    y = R.bf16(rng.standard_normal(n))
+    y[::7] = 0.0
+    gout = torch.empty(n, dtype=torch.float32, device="cuda")
+    gbf = torch.empty(n, dtype=torch.bfloat16, device="cuda")
+    nn.sbr_nn_relu_backward(ctx, dev(torch, g, torch.float32), dev(torch, y, torch.bfloat16), n, gout, gbf)
+    cast = torch.empty(n, dtype=torch.bfloat16, device="cuda")
+    nn.sbr_nn_cast_bf16(ctx, dev(torch, g, torch.float32), n, cast)
+    M, N, ld = 3001, 37, 40
+    m = rng.standard_normal((M, ld)).astype(np.float32)
+    cs = torch.full((N,), 1.5, dtype=torch.float32, device="cuda")
+    nn.sbr_nn_colsum(ctx, dev(torch, m, torch.float32), M, N, ld, cs, 1)
+    src = rng.standard_normal((50, 12)).astype(np.float32)
+    idx = rng.integers(0, 50, 333).astype(np.int64)
+    dst = torch.empty((333, 12), dtype=torch.float32, device="cuda")
+    nn.sbr_nn_gather_rows(ctx, dev(torch, src, torch.float32), 48, dev(torch, idx, torch.int64), 333, dst)
+    sc = rng.integers(0, 9, 100).astype(np.int32)
+    oh = torch.empty((100, 9), dtype=torch.bfloat16, device="cuda")
+    nn.sbr_nn_onehot_bf16(ctx, dev(torch, sc, torch.int32), 100, 9, oh)
+    sync(torch)
+    want = np.where(y > 0, g, 0.0).astype(np.float32)
+    assert np.array_equal(host(gout), want)
+    assert np.array_equal(host(gbf), R.bf16(want))
+    assert np.array_equal(host(cast), R.bf16(g))
+    assert np.allclose(host(cs), 1.5 + m[:, :N].astype(np.float64).sum(0), rtol=1e-6, atol=1e-5)
+    assert np.array_equal(host(dst), src[idx])
+    assert np.array_equal(host(oh), (sc[:, None] == np.arange(9)[None, :]).astype(np.float64))
+
+
+def test_mse_adam_ensemble(env):
+    torch, S, nn, ctx = env
+    banner("mse/adam/ensemble")
+    rng = np.random.default_rng(6)
+    n, T, ldp = 5003, 2, 3
+    pred = rng.standard_normal((n, ldp)).astype(np.float32)
+    tgt = rng.standard_normal((n, T)).astype(np.float32)
+    w = (rng.random((n, T)) < 0.8).astype(np.float32)
+    dpred = torch.zeros((n, T), dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    scale = 1.0 / w.sum()
+    nn.sbr_nn_mse(ctx, dev(torch, pred, torch.float32), ldp, dev(torch, tgt, torch.float32),
+                  dev(torch, w, torch.float32), n, T, scale, dpred, T, loss)
+    sync(torch)
+    L, dL = R.mse(pred[:, :T].astype(np.float64), tgt.astype(np.float64), w.astype(np.float64))
+    assert abs(loss.item() - L) <= 1e-6 * L
+    assert np.allclose(host(dpred), dL, rtol=1e-5, atol=1e-9)
+
+    m = 4099
+    W0 = rng.standard_normal(m).astype(np.float32)
+    wd = dev(torch, W0, torch.float32)
+    md = torch.zeros(m, dtype=torch.float32, device="cuda")
+    vd = torch.zeros(m, dtype=torch.float32, device="cuda")
+    wb = torch.empty(m, dtype=torch.bfloat16, device="cuda")
+    Wr, Mr, Vr = W0.astype(np.float64), np.zeros(m), np.zeros(m)
+    lr, b1, b2, eps, dec = 1e-3, 0.9, 0.999, 1e-8, 1e-4
+    for step in range(1, 4):
+        G = rng.standard_normal(m).astype(np.float32)
+        nn.sbr_nn_adam(ctx, wd, dev(torch, G, torch.float32), md, vd, m, lr, b1, b2, eps, dec, step, wb)
+        gg = G + dec * Wr
+        Mr = b1 * Mr + (1 - b1) * gg
+        Vr = b2 * Vr + (1 - b2) * gg * gg
+        Wr = Wr - lr * (Mr / (1 - b1 ** step)) / (np.sqrt(Vr / (1 - b2 ** step)) + eps)
+    sync(torch)
+    assert np.allclose(host(wd), Wr, rtol=1e-5, atol=1e-6)
+    assert np.array_equal(host(wb), R.bf16(host(wd)))
+
+    E, nn_, ld = 4, 1001, 2
+    outs = rng.standard_normal((E, nn_, ld)).astype(np.float32)
+    mean = torch.empty(nn_, dtype=torch.float32, device="cuda")
+    spread = torch.empty(nn_, dtype=torch.float32, device="cuda")
+    mask = torch.empty(nn_, dtype=torch.uint8, device="cuda")
+    nn.sbr_nn_ensemble(ctx, dev(torch, outs, torch.float32), E, nn_ * ld, nn_, ld, 0, 1.0, mean, spread, mask)
+    sync(torch)
+    o = outs[:, :, 0].astype(np.float64)
+    assert np.allclose(host(mean), o.mean(0), rtol=1e-6, atol=1e-6)
+    sd = o.std(0)
+    assert np.allclose(host(spread), sd, rtol=1e-5, atol=1e-6)
+    far = np.abs(sd - 1.0) > 1e-5
+    assert np.array_equal(host(mask)[far].astype(bool), (sd > 1.0)[far])
