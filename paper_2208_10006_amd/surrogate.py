@@ -1,0 +1,500 @@
+"""Learned radio-map surrogate with SBR fallback, driven on the GPU through
+the libsbr surrogate kernels (include/sbr_nn.h).
+
+What it predicts: for one Rx point, the incoherent path gain
+PG = 10 log10 sum_n P_n (dB) and the RMS delay spread of eq. (5) that the SBR
+path produces at the carrier, from
+  * the scene's 128 x 128 height map (max building height per pixel, / 60 m),
+    encoded once per scene by four 3x3 / stride-2 convolutions (1 -> 16 -> 32
+    -> 64 -> 128 channels, ReLU) and a linear layer to a 128-wide embedding,
+  * seven normalised scalars (Tx xyz, Rx xyz, log f) and their Fourier
+    features sin / cos (2^l pi x), l < 8,
+  * an MLP of six ReLU layers of width 256 and a linear output of width 2.
+Four members (different initialisations, bootstrap resamples of the
+training set) form an ensemble; where the members' PG spread exceeds a
+threshold (1 dB) the caller re-runs the full SBR path for that Rx.
+
+Every arithmetic step runs in the library's kernels: BF16 matrix-core GEMMs
+with FP32 accumulation for the convolutions (im2col / col2im around the
+GEMM) and linear layers, forward and backward; FP32 master weights with
+Adam; the ensemble mean / spread / fallback mask.  This module only
+allocates tensors, prepares batches and sequences the calls.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from . import nn as K
+from . import sbr as S
+
+BF16 = torch.bfloat16
+F32 = torch.float32
+LOG_F_LO, LOG_F_HI = math.log(28e9), math.log(300e9)
+PG_OFFSET_DB, PG_SCALE_DB = 120.0, 20.0   # target 0 = (PG + 120) / 20
+TAU_SCALE_NS = 100.0                       # target 1 = tau_rms / 100 ns
+
+
+@dataclass
+class Arch:
+    H: int = 128
+    chans: Tuple[int, ...] = (1, 16, 32, 64, 128)
+    E: int = 128
+    D: int = 7
+    L: int = 8
+    F: int = 256
+    width: int = 256
+    depth: int = 6
+    T: int = 2
+
+    @property
+    def n_conv(self) -> int:
+        return len(self.chans) - 1
+
+    @property
+    def stem_hw(self) -> int:
+        return self.H >> self.n_conv
+
+    @property
+    def flat(self) -> int:
+        return self.stem_hw ** 2 * self.chans[-1]
+
+    def shapes(self) -> List[Tuple[str, Tuple[int, ...]]]:
+        """Parameter names and shapes in storage order (weights [in][out])."""
+        out = []
+        for i in range(self.n_conv):
+            out += [(f"conv{i}_w", (9 * self.chans[i], self.chans[i + 1])), (f"conv{i}_b", (self.chans[i + 1],))]
+        out += [("emb_w", (self.flat, self.E)), ("emb_b", (self.E,))]
+        fin = self.F
+        for i in range(self.depth):
+            out += [(f"mlp{i}_w", (fin, self.width)), (f"mlp{i}_b", (self.width,))]
+            fin = self.width
+        out += [("out_w", (fin, self.T)), ("out_b", (self.T,))]
+        return out
+
+
+# ---------------------------------------------------------------- stream
+class Runtime:
+    """One torch stream and a library context on that stream.  Every torch op
+    (allocation, copy, fill) and every library call of the surrogate runs on
+    it inside ``with rt:``, so buffers are produced, consumed and recycled by
+    torch's caching allocator in one stream order.  Entering waits for the
+    caller's current stream; results are complete once ``rt.synchronize()``
+    returns."""
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        self.stream = torch.cuda.Stream(device)
+        self.ctx = S.Context(device, self.stream.cuda_stream)
+        self._cms: List = []
+
+    def __enter__(self) -> "Runtime":
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        cm = torch.cuda.stream(self.stream)
+        cm.__enter__()
+        self._cms.append(cm)
+        return self
+
+    def __exit__(self, *exc) -> None:
+        self._cms.pop().__exit__(*exc)
+
+    def synchronize(self) -> None:
+        self.stream.synchronize()
+
+
+# ---------------------------------------------------------------- inputs
+def normalise_inputs(tx: np.ndarray, rx: np.ndarray, freq_hz: float) -> np.ndarray:
+    """[n][7] float32: Tx x/250, y/250, z/60, Rx x/250, y/250, z/60, log f mapped to [-1, 1]."""
+    n = len(rx)
+    x = np.empty((n, 7), np.float32)
+    x[:, 0:3] = np.asarray(tx, float).reshape(1, 3) / np.array([250.0, 250.0, 60.0])
+    x[:, 3:6] = np.asarray(rx, float) / np.array([250.0, 250.0, 60.0])
+    x[:, 6] = 2.0 * (math.log(freq_hz) - LOG_F_LO) / (LOG_F_HI - LOG_F_LO) - 1.0
+    return x
+
+
+def targets_from_sbr(pg_db: np.ndarray, tau_s: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+    """Normalised targets [n][2] and weights [n][2] (0 where SBR found no path)."""
+    pg = np.asarray(pg_db, np.float64).reshape(-1)
+    tau = np.asarray(tau_s, np.float64).reshape(-1)
+    ok = np.isfinite(pg)
+    t = np.zeros((len(pg), 2), np.float32)
+    t[ok, 0] = (pg[ok] + PG_OFFSET_DB) / PG_SCALE_DB
+    t[ok, 1] = tau[ok] * 1e9 / TAU_SCALE_NS
+    w = np.repeat(ok[:, None], 2, axis=1).astype(np.float32)
+    return t, w
+
+
+def pg_db_from_output(out: np.ndarray) -> np.ndarray:
+    return np.asarray(out, np.float64) * PG_SCALE_DB - PG_OFFSET_DB
+
+
+# ---------------------------------------------------------------- one member
+class Member:
+    """One MLP of the ensemble: FP32 master weights, their BF16 copy, Adam
+    moments and gradients, each one flat device buffer with per-parameter views."""
+
+    def __init__(self, arch: Arch, rt: Runtime, seed: int, device: str = "cuda"):
+        self.arch, self.rt, self.ctx, self.seed = arch, rt, rt.ctx, seed
+        self.layout: Dict[str, Tuple[int, Tuple[int, ...]]] = {}
+        off = 0
+        for name, shp in arch.shapes():
+            self.layout[name] = (off, shp)
+            off += int(np.prod(shp))
+        self.n = off
+        with rt:
+            self.w32 = torch.zeros(off, dtype=F32, device=device)
+            self.wbf = torch.zeros(off, dtype=BF16, device=device)
+            self.grad = torch.zeros(off, dtype=F32, device=device)
+            self.m = torch.zeros(off, dtype=F32, device=device)
+            self.v = torch.zeros(off, dtype=F32, device=device)
+        self.step = 0
+        self.init(seed)
+
+    def view(self, buf: torch.Tensor, name: str) -> torch.Tensor:
+        off, shp = self.layout[name]
+        return buf[off:off + int(np.prod(shp))].view(*shp)
+
+    def init(self, seed: int) -> None:
+        """He-uniform weights (limit sqrt(6 / fan_in)), zero biases, output layer x 0.1."""
+        rng = np.random.Generator(np.random.PCG64(seed))
+        host = np.zeros(self.n, np.float32)
+        for name, (off, shp) in self.layout.items():
+            if name.endswith("_w"):
+                lim = math.sqrt(6.0 / shp[0])
+                v = rng.uniform(-lim, lim, shp) * (0.1 if name == "out_w" else 1.0)
+                host[off:off + v.size] = v.ravel()
+        self.load_flat(host)
+
+    def load_flat(self, host: np.ndarray) -> None:
+        with self.rt:
+            self.w32.copy_(torch.as_tensor(np.asarray(host, np.float32)))
+            K.sbr_nn_cast_bf16(self.ctx, self.w32, self.n, self.wbf)
+            self.m.zero_()
+            self.v.zero_()
+        self.step = 0
+
+    def load(self, params: Dict[str, np.ndarray]) -> None:
+        host = np.zeros(self.n, np.float32)
+        for name, (off, shp) in self.layout.items():
+            host[off:off + int(np.prod(shp))] = np.asarray(params[name], np.float32).reshape(-1)
+        self.load_flat(host)
+
+    def state(self) -> Dict[str, np.ndarray]:
+        self.rt.synchronize()
+        w = self.w32.cpu().numpy()
+        return {n: w[o:o + int(np.prod(s))].reshape(s).copy() for n, (o, s) in self.layout.items()}
+
+    def grads(self) -> Dict[str, np.ndarray]:
+        self.rt.synchronize()
+        g = self.grad.cpu().numpy()
+        return {n: g[o:o + int(np.prod(s))].reshape(s).copy() for n, (o, s) in self.layout.items()}
+
+    def adam(self, lr: float, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8, wd: float = 0.0) -> None:
+        self.step += 1
+        K.sbr_nn_adam(self.ctx, self.w32, self.grad, self.m, self.v, self.n, lr, b1, b2, eps, wd, self.step, self.wbf)
+
+
+# ---------------------------------------------------------------- network passes
+class Workspace:
+    """Activation buffers for a (scenes, points) batch shape, reused across calls."""
+
+    def __init__(self, arch: Arch, S_: int, n: int, train: bool, device: str = "cuda"):
+        a = arch
+        self.S, self.n = S_, n
+        hw = a.H
+        self.col, self.act = [], []
+        for i in range(a.n_conv):
+            ho = hw // 2
+            rows = S_ * ho * ho
+            self.col.append(torch.empty((rows, 9 * a.chans[i]), dtype=BF16, device=device))
+            self.act.append(torch.empty((rows, a.chans[i + 1]), dtype=BF16, device=device))
+            hw = ho
+        self.emb = torch.empty((S_, a.E), dtype=BF16, device=device)
+        self.feat = torch.empty((n, a.F), dtype=BF16, device=device)
+        nh = a.depth if train else 2
+        self.h = [torch.empty((n, a.width), dtype=BF16, device=device) for _ in range(nh)]
+        self.out = torch.empty((n, a.T), dtype=F32, device=device)
+        if train:
+            wmax = max(a.width, a.F)
+            self.dout = torch.empty((n, a.T), dtype=F32, device=device)
+            self.g_bf = torch.empty((n, a.T), dtype=BF16, device=device)
+            self.dh = torch.empty((n, wmax), dtype=F32, device=device)
+            self.dz = torch.empty((n, wmax), dtype=F32, device=device)
+            self.dz_bf = torch.empty((n, wmax), dtype=BF16, device=device)
+            self.onehot = torch.empty((n, S_), dtype=BF16, device=device)
+            self.demb = torch.empty((S_, a.E), dtype=F32, device=device)
+            big = max(max(c.numel() for c in self.col), S_ * a.flat, *(t.numel() for t in self.act))
+            self.sdz = torch.empty(big, dtype=F32, device=device)
+            self.sdz_bf = torch.empty(big, dtype=BF16, device=device)
+            self.sda = torch.empty(big, dtype=F32, device=device)
+            self.sdcol = torch.empty(big, dtype=F32, device=device)
+            self.loss = torch.zeros(1, dtype=torch.float64, device=device)
+
+
+def _gemm(ctx, M, N, Kd, A, a_si, a_sk, B, b_sk, b_sj, bias, C, ldc, flags=0):
+    K.sbr_nn_gemm_bf16(ctx, M, N, Kd, A, a_si, a_sk, B, b_sk, b_sj, bias, C, ldc, flags)
+
+
+def stem_forward(mem: Member, ws: Workspace, hmap_bf: torch.Tensor) -> None:
+    """hmap_bf [S][H][H] bf16 -> ws.emb [S][E] bf16 (conv stem + linear, ReLU)."""
+    a, ctx = mem.arch, mem.ctx
+    x = hmap_bf
+    hw = a.H
+    for i in range(a.n_conv):
+        C, Co = a.chans[i], a.chans[i + 1]
+        K.sbr_nn_im2col(ctx, x, ws.S, hw, hw, C, ws.col[i])
+        rows = ws.col[i].shape[0]
+        _gemm(ctx, rows, Co, 9 * C, ws.col[i], 9 * C, 1, mem.view(mem.wbf, f"conv{i}_w"), Co, 1,
+              mem.view(mem.w32, f"conv{i}_b"), ws.act[i], Co, K.RELU | K.OUT_BF16)
+        x = ws.act[i]
+        hw //= 2
+    _gemm(ctx, ws.S, a.E, a.flat, ws.act[-1], a.flat, 1, mem.view(mem.wbf, "emb_w"), a.E, 1,
+          mem.view(mem.w32, "emb_b"), ws.emb, a.E, K.RELU | K.OUT_BF16)
+
+
+def mlp_forward(mem: Member, ws: Workspace, x: torch.Tensor, scene: torch.Tensor, n: int, out: torch.Tensor,
+                keep: bool) -> None:
+    """Features of n points -> out [n][T] FP32.  keep: store every hidden layer (training)."""
+    a, ctx = mem.arch, mem.ctx
+    K.sbr_nn_fourier(ctx, x, n, a.D, a.L, ws.emb, a.E, scene, a.F, ws.feat)
+    h, fin = ws.feat, a.F
+    for i in range(a.depth):
+        dst = ws.h[i] if keep else ws.h[i & 1]
+        _gemm(ctx, n, a.width, fin, h, fin, 1, mem.view(mem.wbf, f"mlp{i}_w"), a.width, 1,
+              mem.view(mem.w32, f"mlp{i}_b"), dst, a.width, K.RELU | K.OUT_BF16)
+        h, fin = dst, a.width
+    _gemm(ctx, n, a.T, fin, h, fin, 1, mem.view(mem.wbf, "out_w"), a.T, 1, mem.view(mem.w32, "out_b"), out, a.T)
+
+
+def backward(mem: Member, ws: Workspace, hmap_bf: torch.Tensor, scene: torch.Tensor, n: int,
+             trace: Optional[dict] = None) -> None:
+    """Gradients of all parameters into mem.grad from ws.dout = d loss / d out.
+    trace: if a dict, receives copies of the bfloat16 intermediate gradients
+    (layer checks)."""
+    a, ctx = mem.arch, mem.ctx
+    keep = (lambda name, t: trace.__setitem__(name, t.clone())) if trace is not None else (lambda name, t: None)
+    G = lambda name: mem.view(mem.grad, name)  # noqa: E731
+    Wb = lambda name: mem.view(mem.wbf, name)  # noqa: E731
+    T, Wd = a.T, a.width
+    K.sbr_nn_cast_bf16(ctx, ws.dout, n * T, ws.g_bf)
+    keep("g", ws.g_bf)
+    last = ws.h[a.depth - 1]
+    _gemm(ctx, Wd, T, n, last, 1, Wd, ws.g_bf, T, 1, None, G("out_w"), T)
+    K.sbr_nn_colsum(ctx, ws.dout, n, T, T, G("out_b"), 0)
+    _gemm(ctx, n, Wd, T, ws.g_bf, T, 1, Wb("out_w"), 1, T, None, ws.dh, Wd)
+    for i in reversed(range(a.depth)):
+        h_in = ws.h[i - 1] if i > 0 else ws.feat
+        fin = Wd if i > 0 else a.F
+        K.sbr_nn_relu_backward(ctx, ws.dh, ws.h[i], n * Wd, ws.dz, ws.dz_bf)
+        keep(f"mlp{i}", ws.dz_bf.view(-1)[:n * Wd])
+        K.sbr_nn_colsum(ctx, ws.dz, n, Wd, Wd, G(f"mlp{i}_b"), 0)
+        _gemm(ctx, fin, Wd, n, h_in, 1, fin, ws.dz_bf, Wd, 1, None, G(f"mlp{i}_w"), Wd)
+        # d input: all columns for hidden layers, only the embedding columns for the first
+        nout = fin if i > 0 else a.E
+        _gemm(ctx, n, nout, Wd, ws.dz_bf, Wd, 1, Wb(f"mlp{i}_w"), 1, Wd, None, ws.dh, nout)
+    # embedding: per-scene sum of the bf16 gradient rows, as onehot^T @ dh_emb
+    K.sbr_nn_cast_bf16(ctx, ws.dh, n * a.E, ws.dz_bf)
+    keep("dh_emb", ws.dz_bf.view(-1)[:n * a.E])
+    K.sbr_nn_onehot_bf16(ctx, scene, n, ws.S, ws.onehot)
+    _gemm(ctx, ws.S, a.E, n, ws.onehot, 1, ws.S, ws.dz_bf, a.E, 1, None, ws.demb, a.E)
+    Sn = ws.S
+    K.sbr_nn_relu_backward(ctx, ws.demb, ws.emb, Sn * a.E, ws.sdz, ws.sdz_bf)
+    keep("emb", ws.sdz_bf[:Sn * a.E])
+    K.sbr_nn_colsum(ctx, ws.sdz, Sn, a.E, a.E, G("emb_b"), 0)
+    _gemm(ctx, a.flat, a.E, Sn, ws.act[-1], 1, a.flat, ws.sdz_bf, a.E, 1, None, G("emb_w"), a.E)
+    _gemm(ctx, Sn, a.flat, a.E, ws.sdz_bf, a.E, 1, Wb("emb_w"), 1, a.E, None, ws.sda, a.flat)
+    hw = a.stem_hw
+    for i in reversed(range(a.n_conv)):
+        C, Co = a.chans[i], a.chans[i + 1]
+        rows = ws.act[i].shape[0]
+        K.sbr_nn_relu_backward(ctx, ws.sda, ws.act[i], rows * Co, ws.sdz, ws.sdz_bf)
+        keep(f"conv{i}", ws.sdz_bf[:rows * Co])
+        K.sbr_nn_colsum(ctx, ws.sdz, rows, Co, Co, G(f"conv{i}_b"), 0)
+        _gemm(ctx, 9 * C, Co, rows, ws.col[i], 1, 9 * C, ws.sdz_bf, Co, 1, None, G(f"conv{i}_w"), Co)
+        if i > 0:
+            _gemm(ctx, rows, 9 * C, Co, ws.sdz_bf, Co, 1, Wb(f"conv{i}_w"), 1, Co, None, ws.sdcol, 9 * C)
+            K.sbr_nn_col2im(ctx, ws.sdcol, Sn, 2 * hw, 2 * hw, C, ws.sda)
+        hw *= 2
+
+
+# ---------------------------------------------------------------- dataset
+@dataclass
+class Dataset:
+    """Training / evaluation points on the device."""
+    hmap: torch.Tensor          # [S][H][H] bf16
+    x: torch.Tensor             # [n][7] f32
+    scene: torch.Tensor         # [n] int32
+    target: torch.Tensor        # [n][2] f32
+    weight: torch.Tensor        # [n][2] f32
+    pg_db: np.ndarray           # [n] SBR PG (dB; -inf where no path), host
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[0])
+
+
+def sbr_labels(ctx: S.Context, w, rx: Optional[np.ndarray] = None, alpha: float = 0.0) -> Tuple[np.ndarray, np.ndarray]:
+    """Full SBR path for one scene (build, trace, receive, channel at the
+    workload's frequencies, stats): PG dB and tau_rms s per Rx (host arrays,
+    complete on return)."""
+    sc = S.sbr_scene_build(ctx, w.tri, w.eps_r, w.sigma, w.rough)
+    tr = S.sbr_trace(ctx, sc, w.tx, w.geodesic_N, w.max_bounces)
+    ps = S.sbr_receive(ctx, tr, w.rx if rx is None else rx, alpha, w.radius_coeff)
+    S.sbr_channel(ctx, ps, w.freq, w.atm_db_per_m, w.atm_deg_per_m)
+    pg, tau, _ = S.sbr_stats(ps)
+    return pg[:, 0].astype(np.float64), tau[:, 0].astype(np.float64)
+
+
+def make_dataset(scenes, labels) -> Dataset:
+    """scenes: list of (workload, height map); labels: list of (pg_db, tau_s)."""
+    hm, xs, sc, ts, ws, pgs = [], [], [], [], [], []
+    for s, ((w, h), (pg, tau)) in enumerate(zip(scenes, labels)):
+        hm.append(h)
+        xs.append(normalise_inputs(w.tx[0], w.rx, float(w.freq[0])))
+        sc.append(np.full(len(w.rx), s, np.int32))
+        t, wt = targets_from_sbr(pg, tau)
+        ts.append(t)
+        ws.append(wt)
+        pgs.append(pg)
+    cuda = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(dt).cuda()  # noqa: E731
+    return Dataset(cuda(np.stack(hm), BF16), cuda(np.concatenate(xs), F32), cuda(np.concatenate(sc), torch.int32),
+                   cuda(np.concatenate(ts), F32), cuda(np.concatenate(ws), F32), np.concatenate(pgs))
+
+
+# ---------------------------------------------------------------- ensemble
+class Ensemble:
+    def __init__(self, arch: Arch, rt: Runtime, members: int = 4, seed: int = 0):
+        self.arch, self.rt, self.ctx = arch, rt, rt.ctx
+        self.members = [Member(arch, rt, seed * 1000 + 17 * m + 1) for m in range(members)]
+        self._ws: Dict[tuple, Workspace] = {}
+
+    def workspace(self, S_: int, n: int, train: bool) -> Workspace:
+        key = (S_, n, train)
+        if key not in self._ws:
+            self._ws = {k: v for k, v in self._ws.items() if k[2] != train}  # one shape per mode
+            with self.rt:
+                self._ws[key] = Workspace(self.arch, S_, n, train)
+        return self._ws[key]
+
+    # -- training
+    def train(self, data: Dataset, steps: int, batch: int = 4096, lr: float = 2e-3, lr_end: float = 1e-4,
+              seed: int = 0, log=None) -> List[float]:
+        """Adam on each member over bootstrap resamples (cosine learning-rate
+        decay); the stem runs on every training scene each step."""
+        with self.rt:
+            losses = self._train(data, steps, batch, lr, lr_end, seed, log)
+        self.rt.synchronize()
+        return losses
+
+    def _train(self, data, steps, batch, lr, lr_end, seed, log):
+        ctx, a = self.ctx, self.arch
+        valid = np.nonzero(data.pg_db > -np.inf)[0]
+        Sn = int(data.hmap.shape[0])
+        ws = self.workspace(Sn, batch, True)
+        xb = torch.empty((batch, a.D), dtype=F32, device="cuda")
+        sb = torch.empty(batch, dtype=torch.int32, device="cuda")
+        tb = torch.empty((batch, a.T), dtype=F32, device="cuda")
+        wb = torch.empty((batch, a.T), dtype=F32, device="cuda")
+        losses = []
+        for mi, mem in enumerate(self.members):
+            rng = np.random.Generator(np.random.PCG64(seed * 7919 + mi))
+            boot = rng.choice(valid, size=len(valid), replace=True)
+            idx_all = torch.as_tensor(rng.choice(boot, size=(steps, batch), replace=True).astype(np.int64)).cuda()
+            for it in range(steps):
+                idx = idx_all[it]
+                K.sbr_nn_gather_rows(ctx, data.x, 4 * a.D, idx, batch, xb)
+                K.sbr_nn_gather_rows(ctx, data.scene, 4, idx, batch, sb)
+                K.sbr_nn_gather_rows(ctx, data.target, 4 * a.T, idx, batch, tb)
+                K.sbr_nn_gather_rows(ctx, data.weight, 4 * a.T, idx, batch, wb)
+                stem_forward(mem, ws, data.hmap)
+                mlp_forward(mem, ws, xb, sb, batch, ws.out, keep=True)
+                K.sbr_nn_mse(ctx, ws.out, a.T, tb, wb, batch, a.T, 1.0 / (batch * a.T), ws.dout, a.T, ws.loss)
+                backward(mem, ws, data.hmap, sb, batch)
+                frac = it / max(steps - 1, 1)
+                mem.adam(lr_end + 0.5 * (lr - lr_end) * (1 + math.cos(math.pi * frac)))
+                if log is not None and (it % 200 == 0 or it == steps - 1):
+                    losses.append(float(ws.loss.item()))
+                    log(f"member {mi} step {it} loss {losses[-1]:.5f}")
+        return losses
+
+    # -- inference
+    def predict(self, hmap: torch.Tensor, x: torch.Tensor, scene: torch.Tensor, chunk: int = 1 << 18,
+                threshold_db: float = 1.0):
+        """Ensemble over all members for n points: (mean out [n][T], PG spread dB [n],
+        fallback mask [n] uint8), device tensors, complete on return."""
+        with self.rt:
+            res = self._predict(hmap, x, scene, chunk, threshold_db)
+        self.rt.synchronize()
+        return res
+
+    def _predict(self, hmap, x, scene, chunk, threshold_db):
+        ctx, a = self.ctx, self.arch
+        n = int(x.shape[0])
+        Sn = int(hmap.shape[0])
+        E = len(self.members)
+        outs = torch.empty((E, n, a.T), dtype=F32, device="cuda")
+        chunk = min(chunk, n)
+        ws = self.workspace(Sn, chunk, False)
+        for mi, mem in enumerate(self.members):
+            stem_forward(mem, ws, hmap)
+            for s in range(0, n, chunk):
+                m = min(chunk, n - s)
+                mlp_forward(mem, ws, x[s:s + m], scene[s:s + m], m, outs[mi, s:s + m], keep=False)
+        mean = torch.empty((n, a.T), dtype=F32, device="cuda")
+        spread = torch.empty(n, dtype=F32, device="cuda")
+        mask = torch.empty(n, dtype=torch.uint8, device="cuda")
+        scratch = torch.empty(n, dtype=F32, device="cuda")
+        for t in range(a.T):
+            K.sbr_nn_ensemble(ctx, outs, E, n * a.T, n, a.T, t, threshold_db / PG_SCALE_DB,
+                              scratch, spread if t == 0 else None, mask if t == 0 else None)
+            mean[:, t].copy_(scratch)
+        spread.mul_(PG_SCALE_DB)
+        return mean, spread, mask
+
+
+# ---------------------------------------------------------------- fallback
+def surrogate_with_fallback(ens: Ensemble, scenes: Sequence, data: Dataset, threshold_db: float = 1.0,
+                            alpha: float = 0.0):
+    """Predict every point; re-run the SBR path (trace the scene, receive only
+    the flagged Rx) for scenes with flagged points; merge.  Returns
+    (pg_db [n] host, tau_s [n] host, mask [n] host bool, timings dict)."""
+    ctx = ens.ctx
+    t0 = time.perf_counter()
+    mean, spread, mask = ens.predict(data.hmap, data.x, data.scene, threshold_db=threshold_db)
+    t1 = time.perf_counter()
+    out = mean.cpu().numpy()
+    m = mask.cpu().numpy().astype(bool)
+    pg = pg_db_from_output(out[:, 0])
+    tau = out[:, 1].astype(np.float64) * TAU_SCALE_NS * 1e-9
+    start = 0
+    n_fb_scenes = 0
+    for (w, _h) in scenes:
+        nr = len(w.rx)
+        sel = np.nonzero(m[start:start + nr])[0]
+        if len(sel):
+            n_fb_scenes += 1
+            p, t = sbr_labels(ctx, w, rx=np.ascontiguousarray(w.rx[sel]), alpha=alpha)
+            pg[start + sel] = p
+            tau[start + sel] = t
+        start += nr
+    ens.rt.synchronize()
+    t2 = time.perf_counter()
+    return pg, tau, m, {"surrogate_s": t1 - t0, "fallback_s": t2 - t1, "fallback_scenes": n_fb_scenes}
+
+
+def gate(pg_pred: np.ndarray, pg_sbr: np.ndarray) -> dict:
+    """Path-gain error against plain SBR over the Rx where SBR found a path."""
+    ok = np.isfinite(pg_sbr)
+    pred = np.where(np.isfinite(pg_pred), pg_pred, -400.0)
+    e = np.abs(pred[ok] - pg_sbr[ok])
+    if e.size == 0:
+        return {"mae_db": 0.0, "p90_db": 0.0, "p99_db": 0.0, "n": 0}
+    return {"mae_db": float(e.mean()), "p90_db": float(np.percentile(e, 90)), "p99_db": float(np.percentile(e, 99)),
+            "n": int(e.size)}

@@ -17,9 +17,15 @@ from oracle import surrogate_ref as R
 
 @pytest.fixture(scope="module")
 def env():
+    """Tensors and kernels share one stream (temporaries passed to the
+    asynchronous calls are recycled by torch only in that stream's order)."""
     import torch
     from paper_2208_10006_amd import sbr, nn
-    return torch, sbr, nn, sbr.Context(0)
+    from paper_2208_10006_amd.surrogate import Runtime
+    rt = Runtime(0)
+    with rt:
+        yield torch, sbr, nn, rt.ctx
+    rt.synchronize()
 
 
 def banner(*a):

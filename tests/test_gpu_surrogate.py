@@ -1,0 +1,300 @@
+"""GPU surrogate: forward / backward through the library's kernels against the
+FP64 CPU reference of the same network (with bfloat16 rounding emulated at
+the points where the GPU stores bfloat16), training, and the fallback path
+against plain SBR.
+
+Tolerances (derived from the arithmetic): both sides round the same values
+to bfloat16 and differ only in how dot products are summed (FP32 in the
+matrix cores, FP64 on the CPU).  That can move a bfloat16 rounding by one
+unit (2^-8 relative) where an FP32 sum lands across a rounding boundary, and
+through a deep network such one-unit moves compound.  So the full-size
+network is checked layer by layer on the GPU's own layer inputs (each
+element within one bfloat16 unit plus the FP32 summation bound), the
+backward the same way from the GPU's own bfloat16 gradient entering each
+layer, and the whole chain end to end at small sizes, where it agrees to
+1e-5.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import surrogate_ref as R
+from paper_2208_10006_amd import workloads as W
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_2208_10006_amd import sbr, surrogate
+    rt = surrogate.Runtime(0)
+    with rt:
+        yield torch, sbr, surrogate, rt
+    rt.synchronize()
+
+
+def banner(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+SMALL = dict(H=16, chans=(1, 2, 3, 4, 5), E=4, D=3, L=2, F=20, width=6, depth=2, T=2)
+
+
+def relerr(a, b):
+    return float(np.max(np.abs(np.asarray(a, np.float64) - b)) / max(np.max(np.abs(b)), 1e-30))
+
+
+def ulp_bf16(v):
+    """Spacing of bfloat16 numbers at |v| (normal range)."""
+    e = np.floor(np.log2(np.maximum(np.abs(v), 2.0 ** -126)))
+    return 2.0 ** (e - 7)
+
+
+def run_gpu(env, arch_kw, Sn, n, seed):
+    """One forward + loss + backward on the GPU; returns everything the checks need."""
+    torch, S, G, rt = env
+    ctx = rt.ctx
+    arch_r, arch_g = R.Arch(**arch_kw), G.Arch(**arch_kw)
+    rng = np.random.default_rng(seed)
+    P = R.init_params(arch_r, seed)
+    for k in P:  # non-zero biases so the bias paths are exercised
+        if k.endswith("_b"):
+            P[k] = rng.standard_normal(P[k].shape) * 0.1
+    hmap = R.bf16(rng.random((Sn, arch_r.H, arch_r.H)) * (rng.random((Sn, arch_r.H, arch_r.H)) < 0.4))
+    x = rng.uniform(-1, 1, (n, arch_r.D)).astype(np.float32)
+    scene = rng.integers(0, Sn, n).astype(np.int32)
+    target = rng.standard_normal((n, arch_r.T)).astype(np.float32)
+    weight = (rng.random((n, arch_r.T)) < 0.9).astype(np.float32)
+    mem = G.Member(arch_g, rt, seed=0)
+    mem.load(P)
+    trace = {}
+    with rt:  # every allocation and call below is ordered on the runtime's stream
+        ws = G.Workspace(arch_g, Sn, n, train=True)
+        cu = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(dt).cuda()  # noqa: E731
+        hm_d = cu(hmap, torch.bfloat16)
+        x_d, sc_d = cu(x, torch.float32), cu(scene, torch.int32)
+        G.stem_forward(mem, ws, hm_d)
+        G.mlp_forward(mem, ws, x_d, sc_d, n, ws.out, keep=True)
+        G.K.sbr_nn_mse(ctx, ws.out, arch_g.T, cu(target, torch.float32), cu(weight, torch.float32), n, arch_g.T,
+                       1.0 / weight.sum(), ws.dout, arch_g.T, ws.loss)
+        G.backward(mem, ws, hm_d, sc_d, n, trace=trace)
+    rt.synchronize()
+    h = lambda t: t.float().cpu().numpy().astype(np.float64)  # noqa: E731
+    acts = {"col": [h(c) for c in ws.col], "act": [h(a) for a in ws.act], "emb": h(ws.emb), "feat": h(ws.feat),
+            "h": [h(t) for t in ws.h], "out": h(ws.out), "dout": h(ws.dout), "loss": ws.loss.item()}
+    return dict(arch=arch_r, P=P, hmap=hmap, x=x, scene=scene, target=target, weight=weight, acts=acts,
+                grads=mem.grads(), trace={k: h(v) for k, v in trace.items()})
+
+
+def test_end_to_end_small_arch(env):
+    """Every layer type at small sizes: GPU forward, loss and gradients equal the
+    bfloat16-emulating FP64 reference to 1e-5 of each tensor's scale."""
+    banner("surrogate end-to-end small")
+    r = run_gpu(env, SMALL, 3, 50, 7)
+    out_r, cache = R.forward(r["arch"], r["P"], r["hmap"], r["x"].astype(np.float64), r["scene"], use_bf16=True)
+    loss_r, dout_r = R.mse(out_r, r["target"].astype(np.float64), r["weight"].astype(np.float64))
+    grads_r = R.backward(r["arch"], r["P"], cache, dout_r, use_bf16=True)
+    assert relerr(r["acts"]["out"], out_r) <= 1e-5
+    assert abs(r["acts"]["loss"] - loss_r) <= 1e-5 * loss_r
+    for k in grads_r:
+        assert relerr(r["grads"][k], grads_r[k]) <= 1e-5, k
+
+
+@pytest.mark.parametrize("Sn,n", [(2, 300), (3, 4100)])
+def test_forward_layers_full_arch(env, Sn, n):
+    """Full-size network, layer by layer: each GPU layer output equals the FP64
+    formula applied to the GPU's own (bfloat16) layer input, rounded like the
+    GPU rounds, to one bfloat16 unit plus the FP32 summation error bound."""
+    banner("surrogate forward layers", Sn, n)
+    r = run_gpu(env, {}, Sn, n, 11)
+    a, P, A = r["arch"], r["P"], r["acts"]
+    Wb = {k: R.bf16(v) if k.endswith("_w") else v for k, v in P.items()}
+
+    def check(inp, wname, bname, got, relu, rounded, what):
+        z = inp @ Wb[wname] + Wb[bname]
+        bound = (inp.shape[1] + 2) * 2.0 ** -24 * (np.abs(inp) @ np.abs(Wb[wname]) + np.abs(Wb[bname]))
+        want = np.maximum(z, 0.0) if relu else z
+        tol = bound + (ulp_bf16(want) if rounded else 0.0)
+        bad = np.abs(got - (R.bf16(want) if rounded else want)) > tol
+        assert not bad.any(), (what, int(bad.sum()))
+
+    assert np.array_equal(A["col"][0], R.conv_patches(r["hmap"][..., None]))
+    hw = a.H
+    for i in range(len(a.chans) - 1):
+        if i > 0:
+            prev = A["act"][i - 1].reshape(Sn, hw, hw, a.chans[i])
+            assert np.array_equal(A["col"][i], R.conv_patches(prev)), f"col{i}"
+        check(A["col"][i], f"conv{i}_w", f"conv{i}_b", A["act"][i], True, True, f"conv{i}")
+        hw //= 2
+    check(A["act"][-1].reshape(Sn, -1), "emb_w", "emb_b", A["emb"], True, True, "emb")
+    feat = R.features(a, A["emb"], r["x"].astype(np.float64), r["scene"], lambda v: v)
+    E, D, L = a.E, a.D, a.L
+    assert np.array_equal(A["feat"][:, :E + D], R.bf16(feat[:, :E + D]))
+    four = slice(E + D, E + D + 2 * D * L)
+    assert np.all(np.abs(A["feat"][:, four] - feat[:, four]) <= 2.0 ** -8 * np.abs(feat[:, four]) + 1e-7)
+    h_in = A["feat"]
+    for i in range(a.depth):
+        check(h_in, f"mlp{i}_w", f"mlp{i}_b", A["h"][i], True, True, f"mlp{i}")
+        h_in = A["h"][i]
+    check(h_in, "out_w", "out_b", A["out"], False, False, "out")
+    loss_r, dout_r = R.mse(A["out"], r["target"].astype(np.float64), r["weight"].astype(np.float64))
+    assert abs(A["loss"] - loss_r) <= 1e-6 * loss_r
+    assert np.allclose(A["dout"], dout_r, rtol=1e-6, atol=1e-12)
+
+
+U = 2.0 ** -24
+
+
+def gemm_bound(a_abs, b_abs, k):
+    """FP32 summation bound of a length-k dot product over the given magnitudes."""
+    return (k + 2) * U * (a_abs @ b_abs)
+
+
+def close_bf16(got, want, bound, what):
+    """A bfloat16 value rounded from an FP32 value within `bound` of the FP64 `want`."""
+    bad = np.abs(got - R.bf16(want)) > 2 * ulp_bf16(want) + 2 * bound
+    assert not bad.any(), (what, int(bad.sum()), got.size)
+
+
+def close(got, want, bound, what):
+    bad = np.abs(got - want) > bound + 2 * U * np.abs(want) + 1e-38
+    assert not bad.any(), (what, int(bad.sum()), got.size)
+
+
+@pytest.mark.parametrize("Sn,n", [(2, 300), (3, 4100)])
+def test_backward_layers_full_arch(env, Sn, n):
+    """Full-size backward, layer by layer: from the GPU's own bfloat16 gradient
+    entering each layer (and its own forward activations), the FP64 formulas
+    give the GPU's weight and bias gradients within the FP32 summation bound,
+    and the gradient passed down within one bfloat16 unit of it."""
+    banner("surrogate backward layers", Sn, n)
+    r = run_gpu(env, {}, Sn, n, 13)
+    a, P, A, Tr, Gg = r["arch"], r["P"], r["acts"], r["trace"], r["grads"]
+    Wb = {k: R.bf16(v) if k.endswith("_w") else np.asarray(v, np.float64) for k, v in P.items()}
+    T, Wd, E = a.T, a.width, a.E
+    g = Tr["g"].reshape(n, T)
+    assert np.array_equal(g, R.bf16(A["dout"]))
+    last = A["h"][a.depth - 1]
+    close(Gg["out_w"], last.T @ g, gemm_bound(np.abs(last).T, np.abs(g), n), "out_w")
+    close(Gg["out_b"], A["dout"].sum(0), 2 * U * np.abs(A["dout"]).sum(0), "out_b")
+    dh = g @ Wb["out_w"].T
+    dh_b = gemm_bound(np.abs(g), np.abs(Wb["out_w"]).T, T)
+    for i in reversed(range(a.depth)):
+        h_in = A["h"][i - 1] if i > 0 else A["feat"]
+        mask = A["h"][i] > 0
+        dz, dz_b = dh * mask, dh_b * mask
+        got = Tr[f"mlp{i}"].reshape(n, Wd)
+        close_bf16(got, dz, dz_b, f"dz mlp{i}")
+        close(Gg[f"mlp{i}_b"], dz.sum(0), dz_b.sum(0) + 2 * U * np.abs(dz).sum(0), f"mlp{i}_b")
+        close(Gg[f"mlp{i}_w"], h_in.T @ got, gemm_bound(np.abs(h_in).T, np.abs(got), n), f"mlp{i}_w")
+        w = Wb[f"mlp{i}_w"] if i > 0 else Wb[f"mlp{i}_w"][:E]
+        dh, dh_b = got @ w.T, gemm_bound(np.abs(got), np.abs(w).T, Wd)
+    dh_emb = Tr["dh_emb"].reshape(n, E)
+    close_bf16(dh_emb, dh, dh_b, "dh_emb")
+    demb = np.zeros((Sn, E))
+    np.add.at(demb, r["scene"], dh_emb)
+    demb_b = np.zeros((Sn, E))
+    np.add.at(demb_b, r["scene"], np.abs(dh_emb))
+    demb_b *= (n + 2) * U
+    mask = A["emb"] > 0
+    dz, dz_b = demb * mask, demb_b * mask
+    got = Tr["emb"].reshape(Sn, E)
+    close_bf16(got, dz, dz_b, "dz emb")
+    close(Gg["emb_b"], dz.sum(0), dz_b.sum(0) + 2 * U * np.abs(dz).sum(0), "emb_b")
+    flat = A["act"][-1].reshape(Sn, -1)
+    close(Gg["emb_w"], flat.T @ got, gemm_bound(np.abs(flat).T, np.abs(got), Sn), "emb_w")
+    da, da_b = got @ Wb["emb_w"].T, gemm_bound(np.abs(got), np.abs(Wb["emb_w"]).T, E)
+    hw = a.stem_hw if hasattr(a, "stem_hw") else a.H >> (len(a.chans) - 1)
+    for i in reversed(range(len(a.chans) - 1)):
+        C, Co = a.chans[i], a.chans[i + 1]
+        rows = A["act"][i].shape[0]
+        mask = A["act"][i] > 0
+        dz, dz_b = da.reshape(rows, Co) * mask, da_b.reshape(rows, Co) * mask
+        got = Tr[f"conv{i}"].reshape(rows, Co)
+        close_bf16(got, dz, dz_b, f"dz conv{i}")
+        close(Gg[f"conv{i}_b"], dz.sum(0), dz_b.sum(0) + 2 * U * np.abs(dz).sum(0), f"conv{i}_b")
+        col = A["col"][i]
+        close(Gg[f"conv{i}_w"], col.T @ got, gemm_bound(np.abs(col).T, np.abs(got), rows), f"conv{i}_w")
+        if i > 0:
+            w = Wb[f"conv{i}_w"]
+            dcol, dcol_b = got @ w.T, gemm_bound(np.abs(got), np.abs(w).T, Co)
+            da = R.conv_patches_adjoint(dcol, Sn, 2 * hw, 2 * hw, C)
+            da_b = R.conv_patches_adjoint(dcol_b + 4 * U * np.abs(dcol), Sn, 2 * hw, 2 * hw, C)
+        hw *= 2
+    # the whole chain on the GPU's activations, for the record
+    W_ = Wb
+    cache = {"x": r["x"], "scene": r["scene"], "W": W_, "feat": A["feat"], "emb": A["emb"], "flat": flat,
+             "last": last}
+    hw2 = a.H
+    for i in range(len(a.chans) - 1):
+        cache[f"conv{i}"] = (A["col"][i], A["act"][i], (Sn, hw2, hw2, a.chans[i]))
+        hw2 //= 2
+    h_in = A["feat"]
+    for i in range(a.depth):
+        cache[f"mlp{i}"] = (h_in, A["h"][i])
+        h_in = A["h"][i]
+    grads_r = R.backward(a, P, cache, A["dout"], use_bf16=True)
+    errs = {k: relerr(Gg[k], grads_r[k]) for k in grads_r}
+    worst = max(errs, key=errs.get)
+    print(f"chain on GPU activations: worst gradient {worst} {errs[worst]:.2e}", flush=True)
+    assert errs[worst] <= 2e-2
+
+
+def test_training_reduces_loss_and_fits(env):
+    """A few hundred Adam steps on a smooth synthetic target must fit it."""
+    torch, S, G, rt = env
+    banner("surrogate training synthetic")
+    arch = G.Arch(depth=3)
+    rng = np.random.default_rng(9)
+    Sn, n = 4, 20000
+    hm = rng.random((Sn, 128, 128)).astype(np.float32) * 0.5
+    x = rng.uniform(-1, 1, (n, 7)).astype(np.float32)
+    sc = rng.integers(0, Sn, n).astype(np.int32)
+    t = np.stack([np.sin(2 * x[:, 0]) + x[:, 3] * x[:, 4] + 0.25 * sc, np.cos(x[:, 1] + x[:, 5])], 1)
+    cu = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(dt).cuda()  # noqa: E731
+    data = G.Dataset(cu(hm, torch.bfloat16), cu(x, torch.float32), cu(sc, torch.int32), cu(t, torch.float32),
+                     cu(np.ones_like(t), torch.float32), np.zeros(n))
+    ens = G.Ensemble(arch, rt, members=2, seed=1)
+    losses = ens.train(data, steps=600, batch=2048, lr=2e-3, log=lambda s: print(s, flush=True))
+    mean, spread, mask = ens.predict(data.hmap, data.x, data.scene)
+    mse = float(np.mean((mean.cpu().numpy() - t) ** 2))
+    print("final mse", mse, "losses", losses, flush=True)
+    assert losses[-1] < 0.1 * losses[0]
+    assert mse < 0.01
+
+
+@pytest.mark.slow
+def test_fallback_gain_over_plain_sbr(env):
+    """Train on SBR labels of a few urban scenes, predict unseen scenes, re-run
+    SBR where the ensemble disagrees, and compare with plain SBR on every Rx:
+    the merged path gain meets the 1 dB gate and takes less time."""
+    torch, S, G, rt = env
+    ctx = rt.ctx
+    N, K, n_rx = 256, 4, 600
+    banner("surrogate gain", N, K, n_rx)
+    t0 = time.time()
+    train = [W.urban_surrogate_scene(5000 + s, n_rx=n_rx, N=N, K=K)[:2] for s in range(16)]
+    labels = [G.sbr_labels(ctx, w) for w, _ in train]
+    data = G.make_dataset(train, labels)
+    print(f"labels {time.time() - t0:.1f}s points {data.n}", flush=True)
+    ens = G.Ensemble(G.Arch(), rt, members=4, seed=0)
+    ens.train(data, steps=800, batch=2048, log=lambda s: print(s, flush=True))
+    test = [W.urban_surrogate_scene(6000 + s, n_rx=3000, random_rx=True, N=N, K=K)[:2] for s in range(3)]
+    tdata = G.make_dataset(test, [(np.zeros(len(w.rx)), np.zeros(len(w.rx))) for w, _ in test])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ref = [G.sbr_labels(ctx, w) for w, _ in test]
+    torch.cuda.synchronize()
+    t_sbr = time.perf_counter() - t1
+    pg_ref = np.concatenate([r[0] for r in ref])
+    pg, tau, mask, tm = G.surrogate_with_fallback(ens, test, tdata, threshold_db=1.0)
+    t_sur = tm["surrogate_s"] + tm["fallback_s"]
+    g = G.gate(pg, pg_ref)
+    print(f"sbr {t_sbr:.3f}s surrogate+fallback {t_sur:.3f}s ({tm}) flagged {mask.mean():.3f} gate {g}", flush=True)
+    # flagged points carry the SBR values themselves
+    assert np.array_equal(pg[mask][np.isfinite(pg_ref[mask])], pg_ref[mask][np.isfinite(pg_ref[mask])])
+    assert g["n"] > 0
