@@ -37,9 +37,22 @@ sbr_status sbr_nn_im2col(sbr_context_t ctx, const void* x, int32_t n, int32_t H,
 /* adjoint of sbr_nn_im2col: dx[n][H][W][C] = sum of the dcol entries that read it (FP32) */
 sbr_status sbr_nn_col2im(sbr_context_t ctx, const float* dcol, int32_t n, int32_t H, int32_t W, int32_t C, float* dx);
 /* feature rows out[n][F] (bf16): emb[scene[i]][0..E), x[i][0..D), then
- * sin(2^l pi x_d), cos(2^l pi x_d) for d < D, l < L (d-major), zero padded to F. */
+ * sin(2^l pi x_d), cos(2^l pi x_d) for d < D, l < L (d-major), then
+ * extra[i][0..X) (extra may be NULL when X == 0), zero padded to F. */
 sbr_status sbr_nn_fourier(sbr_context_t ctx, const float* x, int64_t n, int32_t D, int32_t L, const void* emb,
-                          int32_t E, const int32_t* scene, int32_t F, void* out);
+                          int32_t E, const int32_t* scene, const float* extra, int32_t X, int32_t F, void* out);
+/* Per-link inputs of the surrogate from raw[n][7] = (Tx x, y, z, Rx x, y, z
+ * in metres, f in Hz) and the scene height maps hmap[S][H][H] (bf16, height /
+ * 60 m; row = y, column = x; pixel centres at -half + (c + 0.5) 2 half / H):
+ * x[n][7] = (Tx x/half, y/half, z/60, Rx x/half, y/half, z/60, log f mapped
+ * from [ln 28 GHz, ln 300 GHz] to [-1, 1]); extra[n][3] = (free-space path
+ * gain as (120 - 20 log10(4 pi d f / c)) / 20 with d >= 1 m, minimum of
+ * (segment height - terrain) / 60 over the Tx-Rx segment, mean of
+ * max(0, terrain - segment height) / 60), the terrain sampled bilinearly
+ * (edge-clamped) at `samples` points (k + 0.5) / samples along the segment. */
+sbr_status sbr_nn_link_features(sbr_context_t ctx, const float* raw, int64_t n, const int32_t* scene,
+                                const void* hmap, int32_t H, float half_extent_m, int32_t samples, float* x,
+                                float* extra);
 /* gout / gbf (either may be NULL) = g * (y > 0), y bf16 */
 sbr_status sbr_nn_relu_backward(sbr_context_t ctx, const float* g, const void* y, int64_t n, float* gout, void* gbf);
 sbr_status sbr_nn_cast_bf16(sbr_context_t ctx, const float* a, int64_t n, void* b);

@@ -4,9 +4,10 @@ Network (the learned part that predicts SBR outputs):
   stem   : four 3x3 / stride-2 / pad-1 convolutions with ReLU on a height
            map [H][W][1] (channels last), then a linear layer with ReLU to an
            embedding of width E, once per scene;
-  inputs : per point the embedding of its scene, D raw scalars and their
-           Fourier features sin(2^l pi x), cos(2^l pi x), l < L, zero padded
-           to width F;
+  inputs : per point the embedding of its scene, D raw scalars, their
+           Fourier features sin(2^l pi x), cos(2^l pi x), l < L, and X link
+           features (free-space gain, terrain clearance and obstruction along
+           the Tx-Rx segment over the height map), zero padded to width F;
   MLP    : `depth` hidden linear layers of width Wd with ReLU, then a linear
            layer to T outputs;
   loss   : weighted mean squared error.
@@ -41,6 +42,7 @@ class Arch:
     width: int = 256
     depth: int = 6
     T: int = 2
+    X: int = 3
 
     @property
     def stem_hw(self):
@@ -86,6 +88,53 @@ def fourier(x, L):
     return out
 
 
+C0 = 299_792_458.0
+
+
+def terrain(hmap2d, px, py, half):
+    """Bilinear (edge-clamped) interpolation of a height map [H][H] whose pixel
+    (r, c) is centred at (-half + (c + 0.5) * 2 half / H, -half + (r + 0.5) * 2 half / H)."""
+    H = hmap2d.shape[0]
+    pix = 2.0 * half / H
+    u = (np.asarray(px, float) + half) / pix - 0.5
+    w = (np.asarray(py, float) + half) / pix - 0.5
+    c0 = np.clip(np.floor(u).astype(int), 0, H - 2)
+    r0 = np.clip(np.floor(w).astype(int), 0, H - 2)
+    fu = np.clip(u - c0, 0.0, 1.0)
+    fw = np.clip(w - r0, 0.0, 1.0)
+    h00, h01 = hmap2d[r0, c0], hmap2d[r0, c0 + 1]
+    h10, h11 = hmap2d[r0 + 1, c0], hmap2d[r0 + 1, c0 + 1]
+    return (1 - fw) * ((1 - fu) * h00 + fu * h01) + fw * ((1 - fu) * h10 + fu * h11)
+
+
+def link_features(raw, scene, hmap, half=250.0, samples=128):
+    """raw [n][7] = (Tx xyz, Rx xyz in m, f in Hz), hmap [S][H][H] (height / 60)
+    -> x [n][7] normalised scalars, extra [n][3] link features:
+    free-space path gain (120 - 20 log10(4 pi d f / c)) / 20 (d >= 1 m),
+    min over the Tx-Rx segment of (segment height - terrain) / 60, and the
+    mean of max(0, terrain - segment height) / 60, terrain sampled at
+    (k + 0.5) / samples along the segment."""
+    raw = np.asarray(raw, np.float64)
+    n = len(raw)
+    tx, rx, f = raw[:, 0:3], raw[:, 3:6], raw[:, 6]
+    x = np.zeros((n, 7))
+    x[:, 0:2] = tx[:, 0:2] / half
+    x[:, 2] = tx[:, 2] / 60.0
+    x[:, 3:5] = rx[:, 0:2] / half
+    x[:, 5] = rx[:, 2] / 60.0
+    x[:, 6] = 2.0 * (np.log(f) - np.log(28e9)) / (np.log(300e9) - np.log(28e9)) - 1.0
+    d = np.maximum(np.linalg.norm(rx - tx, axis=1), 1.0)
+    extra = np.zeros((n, 3))
+    extra[:, 0] = (120.0 - 20.0 * np.log10(4.0 * np.pi * d * f / C0)) / 20.0
+    for i in range(n):
+        t = (np.arange(samples) + 0.5) / samples
+        p = tx[i][None, :] + t[:, None] * (rx[i] - tx[i])[None, :]
+        h = 60.0 * terrain(np.asarray(hmap[scene[i]], np.float64), p[:, 0], p[:, 1], half)
+        extra[i, 1] = np.min(p[:, 2] - h) / 60.0
+        extra[i, 2] = np.mean(np.maximum(h - p[:, 2], 0.0)) / 60.0
+    return x, extra
+
+
 def init_params(arch: Arch, seed: int):
     """He-uniform weights, zero biases (the GPU driver uses the same recipe)."""
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -110,16 +159,19 @@ def init_params(arch: Arch, seed: int):
     return P
 
 
-def features(arch, emb, x, scene, r):
+def features(arch, emb, x, scene, r, extra=None):
     f = np.zeros((len(x), arch.F))
     f[:, :arch.E] = emb[scene]
     f[:, arch.E:arch.E + arch.D] = x
-    f[:, arch.E + arch.D:arch.E + arch.D + 2 * arch.D * arch.L] = r(fourier(x, arch.L))
+    fe = arch.E + arch.D + 2 * arch.D * arch.L
+    f[:, arch.E + arch.D:fe] = r(fourier(x, arch.L))
+    if arch.X:
+        f[:, fe:fe + arch.X] = extra
     return f
 
 
-def forward(arch: Arch, P, hmap, x, scene, use_bf16=False):
-    """hmap [S][H][W] (normalised heights), x [n][D], scene [n] -> out [n][T], cache."""
+def forward(arch: Arch, P, hmap, x, scene, use_bf16=False, extra=None):
+    """hmap [S][H][W] (normalised heights), x [n][D], scene [n], extra [n][X] -> out [n][T], cache."""
     r = bf16 if use_bf16 else (lambda a: np.asarray(a, np.float64))
     W = {k: r(v) if k.endswith("_w") else np.asarray(v, np.float64) for k, v in P.items()}
     cache = {"x": x, "scene": scene}
@@ -136,7 +188,7 @@ def forward(arch: Arch, P, hmap, x, scene, use_bf16=False):
     flat = a.reshape(S, -1)
     emb = r(np.maximum(flat @ W["emb_w"] + W["emb_b"], 0.0))
     cache["flat"], cache["emb"] = flat, emb
-    h = r(features(arch, emb, x, scene, r))
+    h = r(features(arch, emb, x, scene, r, extra))
     cache["feat"] = h
     for i in range(arch.depth):
         hn = r(np.maximum(h @ W[f"mlp{i}_w"] + W[f"mlp{i}_b"], 0.0))
@@ -192,6 +244,6 @@ def backward(arch: Arch, P, cache, dout, use_bf16=False):
     return G
 
 
-def loss_of(arch, P, hmap, x, scene, target, weight):
-    out, _ = forward(arch, P, hmap, x, scene)
+def loss_of(arch, P, hmap, x, scene, target, weight, extra=None):
+    out, _ = forward(arch, P, hmap, x, scene, extra=extra)
     return mse(out, target, weight)[0]

@@ -26,91 +26,171 @@ inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 // ---------------------------------------------------------------- GEMM
 // C[i][j] = sum_k A(i,k) B(k,j) (+ bias[j]) (ReLU) with A(i,k) = A[i*a_si + k*a_sk]
 // and B(k,j) = B[k*b_sk + j*b_sj] (bf16), FP32 accumulation on
-// v_mfma_f32_16x16x32_bf16.  Block tile 64 x 64, K step 32, 4 waves each
-// owning a 32 x 32 quarter (2 x 2 MFMA tiles).  Tiles are staged in LDS
-// k-contiguous per row / column so one 16-byte LDS read feeds one operand.
-constexpr int TM = 64, TN = 64, TK = 32, TKP = TK + 8;  // padded row (80 B) avoids bank conflicts
+// v_mfma_f32_16x16x32_bf16.  Square block tile T x T (T = 64 or 128), K step
+// 64, 4 waves in a 2 x 2 arrangement each owning a (T/2) x (T/2) quarter.
+// Both operands are staged in LDS k-contiguous per row (A) / column (B) so
+// one 16-byte LDS read feeds one MFMA operand; the next K step's global loads
+// are issued into registers before the current step's MFMAs.
+//
+// Operand load modes (chosen on the host from strides and alignment):
+//   kKC  k contiguous (stride 1 along k), 16-byte vector loads of 8 k values;
+//   kRC  row (A) / column (B) contiguous, 16-byte vector loads of 8 rows;
+//   kGen any strides, element loads, same register layout as kRC.
+// Split-K: blockIdx selects (tile, k-slice); with more than one slice each
+// block writes its FP32 partial tile and k_gemm_reduce sums the slices in
+// order (deterministic) before the epilogue.
+constexpr int BK = 64, BKP = BK + 8;  // padded LDS row: 144 B, conflict-free 16-byte reads
 
 enum : uint32_t { kRelu = 1u, kOutBf16 = 2u, kAccum = 4u };
+enum LoadMode { kKC = 0, kRC = 1, kGen = 2 };
 
-__global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const __bf16* __restrict__ A, int64_t a_si,
-                                                   int64_t a_sk, const __bf16* __restrict__ B, int64_t b_sk,
-                                                   int64_t b_sj, const float* __restrict__ bias, void* __restrict__ C,
-                                                   int64_t ldc, uint32_t flags) {
-  __shared__ __bf16 As[TM][TKP];
-  __shared__ __bf16 Bs[TN][TKP];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int i0 = blockIdx.y * TM, j0 = blockIdx.x * TN;
-  const int wi = (wv >> 1) * 32, wj = (wv & 1) * 32;
-  f32x4 acc[2][2];
-  for (int r = 0; r < 2; ++r)
-    for (int c = 0; c < 2; ++c) acc[r][c] = f32x4{0, 0, 0, 0};
-  const bool a_kc = a_sk == 1, b_kc = b_sk == 1;
-  for (int k0 = 0; k0 < K; k0 += TK) {
-    // ---- stage A (64 x 32) and B (32 x 64): 256 threads x 8 elements each
-    {
-      if (a_kc) {  // k contiguous: thread loads 8 consecutive k of one row
-        const int r = tid >> 2, kk = (tid & 3) * 8;
-        const int i = i0 + r;
+// One operand tile (ROWS x BK) of X(r, k) = X[r*s_r + k*s_k], r in [r0, rmax), k in [k0, kend).
+template <int ROWS, int MODE>
+struct TileLoader {
+  static constexpr int CHUNKS = ROWS * BK / 8 / 256;  // 16-byte chunks per thread
+  bf16x8 v[CHUNKS];
+
+  __device__ void load(const __bf16* __restrict__ X, int64_t s_r, int64_t s_k, int r0, int rmax, int k0, int kend) {
+    const int tid = threadIdx.x;
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const int k = k0 + kk + t;
-          As[r][kk + t] = (i < M && k < K) ? A[(int64_t)i * a_si + k] : f2bf(0.0f);
+    for (int c = 0; c < CHUNKS; ++c) {
+      const int q = tid + c * 256;
+      if (MODE == kKC) {  // chunk = 8 consecutive k of one row
+        const int r = q / (BK / 8), kq = (q % (BK / 8)) * 8;
+        const int row = r0 + r, k = k0 + kq;
+        if (row < rmax && k + 8 <= kend) {
+          v[c] = *reinterpret_cast<const bf16x8*>(X + (int64_t)row * s_r + k);
+        } else {
+#pragma unroll
+          for (int t = 0; t < 8; ++t)
+            v[c][t] = (row < rmax && k + t < kend) ? X[(int64_t)row * s_r + k + t] : f2bf(0.0f);
         }
-      } else {  // i contiguous: thread loads 8 consecutive rows of one k
-        const int kk = tid >> 3, r = (tid & 7) * 8;
-        const int k = k0 + kk;
+      } else {  // chunk = 8 consecutive rows of one k
+        const int kk = q / (ROWS / 8), r8 = (q % (ROWS / 8)) * 8;
+        const int row = r0 + r8, k = k0 + kk;
+        if (MODE == kRC && k < kend && row + 8 <= rmax) {
+          v[c] = *reinterpret_cast<const bf16x8*>(X + row + (int64_t)k * s_k);
+        } else {
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const int i = i0 + r + t;
-          As[r + t][kk] = (i < M && k < K) ? A[(int64_t)i * a_si + (int64_t)k * a_sk] : f2bf(0.0f);
-        }
-      }
-      if (b_kc) {  // k contiguous: 8 consecutive k of one column
-        const int c = tid >> 2, kk = (tid & 3) * 8;
-        const int j = j0 + c;
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const int k = k0 + kk + t;
-          Bs[c][kk + t] = (j < N && k < K) ? B[k + (int64_t)j * b_sj] : f2bf(0.0f);
-        }
-      } else {  // j contiguous: 8 consecutive columns of one k
-        const int kk = tid >> 3, c = (tid & 7) * 8;
-        const int k = k0 + kk;
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const int j = j0 + c + t;
-          Bs[c + t][kk] = (j < N && k < K) ? B[(int64_t)k * b_sk + (int64_t)j * b_sj] : f2bf(0.0f);
+          for (int t = 0; t < 8; ++t)
+            v[c][t] = (k < kend && row + t < rmax) ? X[(int64_t)(row + t) * s_r + (int64_t)k * s_k] : f2bf(0.0f);
         }
       }
     }
+  }
+
+  __device__ void store(__bf16 (*S)[BKP]) const {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < CHUNKS; ++c) {
+      const int q = tid + c * 256;
+      if (MODE == kKC) {
+        const int r = q / (BK / 8), kq = (q % (BK / 8)) * 8;
+        *reinterpret_cast<bf16x8*>(&S[r][kq]) = v[c];
+      } else {
+        const int kk = q / (ROWS / 8), r8 = (q % (ROWS / 8)) * 8;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) S[r8 + t][kk] = v[c][t];
+      }
+    }
+  }
+};
+
+struct GemmArgs {
+  int M, N, K, kchunk, tiles_n, ntiles;
+  const __bf16* A;
+  int64_t a_si, a_sk;
+  const __bf16* B;
+  int64_t b_sk, b_sj;
+  const float* bias;
+  void* C;
+  int64_t ldc;
+  uint32_t flags;
+  float* partial;  // [splits][M][N] when split, else nullptr
+};
+
+__device__ inline void epilogue_store(const GemmArgs& g, int i, int j, float v) {
+  if (g.bias) v += g.bias[j];
+  const int64_t o = (int64_t)i * g.ldc + j;
+  if (g.flags & kAccum) v += (g.flags & kOutBf16) ? bf2f(static_cast<const __bf16*>(g.C)[o]) : static_cast<const float*>(g.C)[o];
+  if (g.flags & kRelu) v = fmaxf(v, 0.0f);
+  if (g.flags & kOutBf16) static_cast<__bf16*>(g.C)[o] = f2bf(v);
+  else static_cast<float*>(g.C)[o] = v;
+}
+
+template <int T, int AMODE, int BMODE>
+__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
+  constexpr int WT = T / 2, FT = WT / 16;  // wave tile, MFMA tiles per wave side
+  __shared__ __bf16 As[T][BKP];
+  __shared__ __bf16 Bs[T][BKP];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // block -> (tile, k-slice); tiles of one XCD (block id mod 8) are contiguous
+  // so blocks that share A rows share an L2
+  const int b = blockIdx.x;
+  const int split = b / g.ntiles, bt = b - split * g.ntiles;
+  const int tile = (g.ntiles % 8 == 0) ? (bt % 8) * (g.ntiles / 8) + bt / 8 : bt;
+  const int i0 = (tile / g.tiles_n) * T, j0 = (tile % g.tiles_n) * T;
+  const int kb = split * g.kchunk, ke = min(g.K, kb + g.kchunk);
+  const int wi = (wv >> 1) * WT, wj = (wv & 1) * WT;
+  f32x4 acc[FT][FT];
+#pragma unroll
+  for (int r = 0; r < FT; ++r)
+#pragma unroll
+    for (int c = 0; c < FT; ++c) acc[r][c] = f32x4{0, 0, 0, 0};
+  TileLoader<T, AMODE> la;
+  TileLoader<T, BMODE> lb;
+  if (kb < ke) {
+    la.load(g.A, g.a_si, g.a_sk, i0, g.M, kb, ke);
+    lb.load(g.B, g.b_sj, g.b_sk, j0, g.N, kb, ke);
+  }
+  const int fr = lane & 15, fk = (lane >> 4) * 8;
+  for (int k0 = kb; k0 < ke; k0 += BK) {
+    la.store(As);
+    lb.store(Bs);
     __syncthreads();
-    // ---- MFMA: lane l holds row/col (l % 16) and k = (l / 16) * 8 .. + 7
-    const int fr = lane & 15, fk = (lane >> 4) * 8;
-    bf16x8 af[2], bfv[2];
-    for (int r = 0; r < 2; ++r) af[r] = *reinterpret_cast<const bf16x8*>(&As[wi + r * 16 + fr][fk]);
-    for (int c = 0; c < 2; ++c) bfv[c] = *reinterpret_cast<const bf16x8*>(&Bs[wj + c * 16 + fr][fk]);
-    for (int r = 0; r < 2; ++r)
-      for (int c = 0; c < 2; ++c) acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[r], bfv[c], acc[r][c], 0, 0, 0);
+    if (k0 + BK < ke) {  // next step's loads in flight during this step's MFMAs
+      la.load(g.A, g.a_si, g.a_sk, i0, g.M, k0 + BK, ke);
+      lb.load(g.B, g.b_sj, g.b_sk, j0, g.N, k0 + BK, ke);
+    }
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 32) {
+      bf16x8 af[FT], bfv[FT];
+#pragma unroll
+      for (int r = 0; r < FT; ++r) af[r] = *reinterpret_cast<const bf16x8*>(&As[wi + r * 16 + fr][kk + fk]);
+#pragma unroll
+      for (int c = 0; c < FT; ++c) bfv[c] = *reinterpret_cast<const bf16x8*>(&Bs[wj + c * 16 + fr][kk + fk]);
+#pragma unroll
+      for (int r = 0; r < FT; ++r)
+#pragma unroll
+        for (int c = 0; c < FT; ++c)
+          acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[r], bfv[c], acc[r][c], 0, 0, 0);
+    }
     __syncthreads();
   }
-  // ---- epilogue: acc[r][c][q] is C[wi + r*16 + (lane/16)*4 + q][wj + c*16 + lane%16]
-  for (int r = 0; r < 2; ++r)
-    for (int c = 0; c < 2; ++c) {
+  // acc[r][c][q] is C[wi + r*16 + (lane/16)*4 + q][wj + c*16 + lane%16]
+#pragma unroll
+  for (int r = 0; r < FT; ++r)
+#pragma unroll
+    for (int c = 0; c < FT; ++c) {
       const int j = j0 + wj + c * 16 + (lane & 15);
-      if (j >= N) continue;
-      const float bj = bias ? bias[j] : 0.0f;
+      if (j >= g.N) continue;
+#pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int i = i0 + wi + r * 16 + (lane >> 4) * 4 + q;
-        if (i >= M) continue;
-        float v = acc[r][c][q] + bj;
-        const int64_t o = (int64_t)i * ldc + j;
-        if (flags & kAccum) v += (flags & kOutBf16) ? bf2f(static_cast<__bf16*>(C)[o]) : static_cast<float*>(C)[o];
-        if (flags & kRelu) v = fmaxf(v, 0.0f);
-        if (flags & kOutBf16) static_cast<__bf16*>(C)[o] = f2bf(v);
-        else static_cast<float*>(C)[o] = v;
+        if (i >= g.M) continue;
+        if (g.partial) g.partial[((int64_t)split * g.M + i) * g.N + j] = acc[r][c][q];
+        else epilogue_store(g, i, j, acc[r][c][q]);
       }
     }
+}
+
+__global__ void k_gemm_reduce(GemmArgs g, int splits) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t mn = (int64_t)g.M * g.N;
+  if (e >= mn) return;
+  float s = 0.0f;
+  for (int z = 0; z < splits; ++z) s += g.partial[z * mn + e];
+  epilogue_store(g, (int)(e / g.N), (int)(e % g.N), s);
 }
 
 // ---------------------------------------------------------------- conv helpers
@@ -154,25 +234,80 @@ __global__ void k_col2im(const float* __restrict__ dcol, int n, int H, int W, in
 }
 
 // ---------------------------------------------------------------- elementwise
-// feature row of point i: [emb(scene(i)) (E), raw x (D), sin(2^l pi x_d), cos(2^l pi x_d) for l < L] zero padded to F
+// feature row of point i: [emb(scene(i)) (E), raw x (D), sin(2^l pi x_d), cos(2^l pi x_d) for l < L,
+// extra (X)] zero padded to F
 __global__ void k_fourier(const float* __restrict__ x, int64_t n, int D, int L, const __bf16* __restrict__ emb, int E,
-                          const int32_t* __restrict__ scene, int F, __bf16* __restrict__ out) {
+                          const int32_t* __restrict__ scene, const float* __restrict__ extra, int X, int F,
+                          __bf16* __restrict__ out) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n * F) return;
   const int64_t i = e / F;
   const int f = (int)(e - i * F);
+  const int fe = E + D + 2 * D * L;
   float v = 0.0f;
   if (f < E) {
     v = bf2f(emb[(int64_t)scene[i] * E + f]);
   } else if (f < E + D) {
     v = x[i * D + (f - E)];
-  } else if (f < E + D + 2 * D * L) {
+  } else if (f < fe) {
     const int g = f - E - D;
     const int d = g / (2 * L), r = g - d * 2 * L, l = r >> 1;
     const double a = (double)x[i * D + d] * (double)(1 << l);  // sin / cos (2^l pi x) via sinpi / cospi
     v = (r & 1) ? (float)cospi(a) : (float)sinpi(a);
+  } else if (f < fe + X) {
+    v = extra[i * X + (f - fe)];
   }
   out[e] = f2bf(v);
+}
+
+// Link features of point i from its raw row (Tx x, y, z, Rx x, y, z in metres,
+// f in Hz) and its scene's height map hmap[s][H][H] (bf16, height / 60 m;
+// pixel (r, c) centred at (-half + (c + 0.5) * 2 half / H, -half + (r + 0.5) * 2 half / H)):
+//   x[i][0..6]   Tx x / half, y / half, z / 60, Rx the same, log f mapped
+//                from [ln 28 GHz, ln 300 GHz] to [-1, 1];
+//   extra[i][0]  free-space path gain in the network's target units,
+//                (-20 log10(4 pi d f / c) + 120) / 20, d >= 1 m;
+//   extra[i][1]  min over the segment of (segment height - terrain height) / 60;
+//   extra[i][2]  mean over the segment of max(0, terrain - segment height) / 60,
+// the terrain sampled bilinearly (edge-clamped) at samples points (k + 0.5) / samples.
+__device__ inline float hmap_bilinear(const __bf16* __restrict__ m, int H, float half, float px, float py) {
+  const float pix = 2.0f * half / (float)H;
+  const float u = (px + half) / pix - 0.5f, w = (py + half) / pix - 0.5f;
+  const int c0 = min(max((int)floorf(u), 0), H - 2), r0 = min(max((int)floorf(w), 0), H - 2);
+  const float fu = fminf(fmaxf(u - (float)c0, 0.0f), 1.0f), fw = fminf(fmaxf(w - (float)r0, 0.0f), 1.0f);
+  const float h00 = bf2f(m[r0 * H + c0]), h01 = bf2f(m[r0 * H + c0 + 1]);
+  const float h10 = bf2f(m[(r0 + 1) * H + c0]), h11 = bf2f(m[(r0 + 1) * H + c0 + 1]);
+  return (1.0f - fw) * ((1.0f - fu) * h00 + fu * h01) + fw * ((1.0f - fu) * h10 + fu * h11);
+}
+
+__global__ void k_link_features(const float* __restrict__ raw, int64_t n, const int32_t* __restrict__ scene,
+                                const __bf16* __restrict__ hmap, int H, float half, int samples, float* __restrict__ x,
+                                float* __restrict__ extra) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float* p = raw + i * 7;
+  const float tx = p[0], ty = p[1], tz = p[2], rx = p[3], ry = p[4], rz = p[5], f = p[6];
+  float* xo = x + i * 7;
+  xo[0] = tx / half, xo[1] = ty / half, xo[2] = tz / 60.0f;
+  xo[3] = rx / half, xo[4] = ry / half, xo[5] = rz / 60.0f;
+  const float lo = logf(28e9f), hi = logf(300e9f);
+  xo[6] = 2.0f * (logf(f) - lo) / (hi - lo) - 1.0f;
+  const float dx = rx - tx, dy = ry - ty, dz = rz - tz;
+  const float d = fmaxf(sqrtf(dx * dx + dy * dy + dz * dz), 1.0f);
+  const float fspl = 20.0f * log10f(4.0f * 3.14159265358979f * d * f / 299792458.0f);
+  const __bf16* m = hmap + (int64_t)scene[i] * H * H;
+  float clr = 3.0e38f, sh = 0.0f;
+  for (int k = 0; k < samples; ++k) {
+    const float t = ((float)k + 0.5f) / (float)samples;
+    const float h = 60.0f * hmap_bilinear(m, H, half, tx + t * dx, ty + t * dy);
+    const float z = tz + t * dz;
+    clr = fminf(clr, z - h);
+    sh += fmaxf(h - z, 0.0f);
+  }
+  float* eo = extra + i * 3;
+  eo[0] = (120.0f - fspl) / 20.0f;
+  eo[1] = clr / 60.0f;
+  eo[2] = sh / (float)samples / 60.0f;
 }
 
 // g (fp32, in place allowed) <- g * (y > 0); optional bf16 copy
@@ -214,20 +349,31 @@ __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ pred, int
   if (threadIdx.x == 0) partial[blockIdx.x] = sm[0];
 }
 
-// column sums of a [M][N] fp32 matrix (bias gradients), fixed order: block per column tile
-__global__ __launch_bounds__(256) void k_colsum(const float* __restrict__ g, int64_t M, int N, int64_t ld,
-                                                float* __restrict__ out, int accumulate) {
-  const int j = blockIdx.x;
+// column sums of a [M][N] fp32 matrix (bias gradients), deterministic two-pass:
+// block (column group of 64, row chunk) -> partial[chunk][j] in FP64, then
+// k_colsum_final adds the chunks in order.
+constexpr int kColsumRows = 1024;
+__global__ __launch_bounds__(256) void k_colsum_part(const float* __restrict__ g, int64_t M, int N, int64_t ld,
+                                                     double* __restrict__ partial) {
+  const int jl = threadIdx.x & 63, rg = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + jl;
+  const int64_t r0 = (int64_t)blockIdx.y * kColsumRows, r1 = min<int64_t>(M, r0 + kColsumRows);
   double s = 0.0;
-  for (int64_t i = threadIdx.x; i < M; i += 256) s += g[i * ld + j];
-  __shared__ double sm[256];
-  sm[threadIdx.x] = s;
+  if (j < N)
+    for (int64_t i = r0 + rg; i < r1; i += 4) s += g[i * ld + j];
+  __shared__ double sm[4][64];
+  sm[rg][jl] = s;
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[j] = (accumulate ? out[j] : 0.0f) + (float)sm[0];
+  if (rg == 0 && j < N) partial[(int64_t)blockIdx.y * N + j] = ((sm[0][jl] + sm[1][jl]) + sm[2][jl]) + sm[3][jl];
+}
+
+__global__ void k_colsum_final(const double* __restrict__ partial, int chunks, int N, float* __restrict__ out,
+                               int accumulate) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  double s = 0.0;
+  for (int c = 0; c < chunks; ++c) s += partial[(int64_t)c * N + j];
+  out[j] = (accumulate ? out[j] : 0.0f) + (float)s;
 }
 
 __global__ void k_sum_f64(const double* __restrict__ p, int64_t n, double* __restrict__ out) {
@@ -313,13 +459,58 @@ void nn_onehot(const int32_t* idx, int64_t n, int width, void* out, hipStream_t 
 }
 
 // ---------------------------------------------------------------- launchers
+namespace {
+int load_mode(const void* X, int64_t s_r, int64_t s_k) {
+  const bool al = (reinterpret_cast<uintptr_t>(X) & 15) == 0;
+  if (s_k == 1 && s_r % 8 == 0 && al) return kKC;
+  if (s_r == 1 && s_k % 8 == 0 && al) return kRC;
+  return kGen;
+}
+
+template <int T>
+void launch_gemm_t(const GemmArgs& g, int am, int bm, int blocks, hipStream_t s) {
+#define SBR_GEMM_CASE(A_, B_) \
+  if (am == A_ && bm == B_) { hipLaunchKernelGGL((k_gemm_bf16<T, A_, B_>), dim3(blocks), dim3(256), 0, s, g); return; }
+  SBR_GEMM_CASE(kKC, kKC) SBR_GEMM_CASE(kKC, kRC) SBR_GEMM_CASE(kKC, kGen)
+  SBR_GEMM_CASE(kRC, kKC) SBR_GEMM_CASE(kRC, kRC) SBR_GEMM_CASE(kRC, kGen)
+  SBR_GEMM_CASE(kGen, kKC) SBR_GEMM_CASE(kGen, kRC) SBR_GEMM_CASE(kGen, kGen)
+#undef SBR_GEMM_CASE
+}
+}  // namespace
+
 void nn_gemm(int M, int N, int K, const void* A, int64_t a_si, int64_t a_sk, const void* B, int64_t b_sk,
              int64_t b_sj, const float* bias, void* C, int64_t ldc, uint32_t flags, hipStream_t s) {
   if (M <= 0 || N <= 0) return;
-  const dim3 g(nblk(N, TN), nblk(M, TM));
+  int num_cus = 256;
+  {
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&num_cus, hipDeviceAttributeMultiprocessorCount, dev);
+  }
+  // 128-wide tiles when they alone fill the chip, else 64
+  const int64_t t128 = (int64_t)((M + 127) / 128) * ((N + 127) / 128);
+  const int T = t128 >= 2 * num_cus ? 128 : 64;
+  const int tiles_m = (M + T - 1) / T, tiles_n = (N + T - 1) / T, ntiles = tiles_m * tiles_n;
+  // split K when the tiles leave the chip idle and K is long
+  const int ksteps = (K + BK - 1) / BK;
+  int splits = 1;
+  if (ntiles < 2 * num_cus && ksteps >= 8) splits = std::max(1, std::min((4 * num_cus + ntiles - 1) / ntiles, ksteps / 4));
+  const int kchunk = ((ksteps + splits - 1) / splits) * BK;
+  if (K > 0) splits = (K + kchunk - 1) / kchunk;
+  GemmArgs g{M, N, K, kchunk, tiles_n, ntiles, static_cast<const __bf16*>(A), a_si, a_sk,
+             static_cast<const __bf16*>(B), b_sk, b_sj, bias, C, ldc, flags, nullptr};
+  Buf part;
+  if (splits > 1) {
+    part.alloc((size_t)splits * M * N * 4, s);
+    g.partial = part.as<float>();
+  }
+  const int am = load_mode(A, a_si, a_sk), bm = load_mode(B, b_sj, b_sk);
   ::sbr::TimedLaunch tl_("nn_gemm", s);
-  hipLaunchKernelGGL(k_gemm_bf16, g, dim3(256), 0, s, M, N, K, static_cast<const __bf16*>(A), a_si, a_sk,
-                     static_cast<const __bf16*>(B), b_sk, b_sj, bias, C, ldc, flags);
+  if (T == 128) launch_gemm_t<128>(g, am, bm, ntiles * splits, s);
+  else launch_gemm_t<64>(g, am, bm, ntiles * splits, s);
+  if (splits > 1) {
+    const int64_t mn = (int64_t)M * N;
+    hipLaunchKernelGGL(k_gemm_reduce, dim3(nblk(mn, 256)), dim3(256), 0, s, g, splits);
+  }
   SBR_LAUNCH_CHECK();
 }
 void nn_im2col(const void* x, int n, int H, int W, int C, void* col, hipStream_t s) {
@@ -335,11 +526,18 @@ void nn_col2im(const float* dcol, int n, int H, int W, int C, float* dx, hipStre
   hipLaunchKernelGGL(k_col2im, dim3(nblk(total, 256)), dim3(256), 0, s, dcol, n, H, W, C, dx);
   SBR_LAUNCH_CHECK();
 }
-void nn_fourier(const float* x, int64_t n, int D, int L, const void* emb, int E, const int32_t* scene, int F,
-                void* out, hipStream_t s) {
+void nn_fourier(const float* x, int64_t n, int D, int L, const void* emb, int E, const int32_t* scene,
+                const float* extra, int X, int F, void* out, hipStream_t s) {
   ::sbr::TimedLaunch tl_("nn_elem", s);
   hipLaunchKernelGGL(k_fourier, dim3(nblk(n * F, 256)), dim3(256), 0, s, x, n, D, L, static_cast<const __bf16*>(emb),
-                     E, scene, F, static_cast<__bf16*>(out));
+                     E, scene, extra, X, F, static_cast<__bf16*>(out));
+  SBR_LAUNCH_CHECK();
+}
+void nn_link_features(const float* raw, int64_t n, const int32_t* scene, const void* hmap, int H, float half,
+                      int samples, float* x, float* extra, hipStream_t s) {
+  ::sbr::TimedLaunch tl_("nn_elem", s);
+  hipLaunchKernelGGL(k_link_features, dim3(nblk(n, 256)), dim3(256), 0, s, raw, n, scene,
+                     static_cast<const __bf16*>(hmap), H, half, samples, x, extra);
   SBR_LAUNCH_CHECK();
 }
 void nn_relu_bwd(const float* g, const void* y, int64_t n, float* gout, void* gbf, hipStream_t s) {
@@ -365,8 +563,13 @@ void nn_mse(const float* pred, int64_t ldp, const float* target, const float* we
   SBR_LAUNCH_CHECK();
 }
 void nn_colsum(const float* g, int64_t M, int N, int64_t ld, float* out, int accumulate, hipStream_t s) {
+  const int chunks = (int)std::max<int64_t>(1, (M + kColsumRows - 1) / kColsumRows);
+  Buf part;
+  part.alloc((size_t)chunks * N * 8, s);
   ::sbr::TimedLaunch tl_("nn_elem", s);
-  hipLaunchKernelGGL(k_colsum, dim3(N), dim3(256), 0, s, g, M, N, ld, out, accumulate);
+  hipLaunchKernelGGL(k_colsum_part, dim3((N + 63) / 64, chunks), dim3(256), 0, s, g, M, N, ld, part.as<double>());
+  hipLaunchKernelGGL(k_colsum_final, dim3((N + 255) / 256), dim3(256), 0, s, part.as<double>(), chunks, N, out,
+                     accumulate);
   SBR_LAUNCH_CHECK();
 }
 void nn_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,

@@ -42,12 +42,24 @@ sbr_status sbr_nn_col2im(sbr_context_t ctx, const float* dcol, int32_t n, int32_
 }
 
 sbr_status sbr_nn_fourier(sbr_context_t ctx, const float* x, int64_t n, int32_t D, int32_t L, const void* emb,
-                          int32_t E, const int32_t* scene, int32_t F, void* out) {
+                          int32_t E, const int32_t* scene, const float* extra, int32_t X, int32_t F, void* out) {
   NN_ENTRY({
-    NN_REQUIRE(x && out && n >= 0 && D >= 0 && L >= 0 && L <= 30 && E >= 0 && F >= E + D + 2 * D * L,
+    NN_REQUIRE(x && out && n >= 0 && D >= 0 && L >= 0 && L <= 30 && E >= 0 && X >= 0 &&
+                   F >= E + D + 2 * D * L + X,
                "fourier arguments");
     NN_REQUIRE(E == 0 || (emb && scene), "fourier embedding");
-    if (n > 0) nn_fourier(x, n, D, L, emb, E, scene, F, out, s);
+    NN_REQUIRE(X == 0 || extra, "fourier extra columns");
+    if (n > 0) nn_fourier(x, n, D, L, emb, E, scene, extra, X, F, out, s);
+  });
+}
+
+sbr_status sbr_nn_link_features(sbr_context_t ctx, const float* raw, int64_t n, const int32_t* scene,
+                                const void* hmap, int32_t H, float half_extent_m, int32_t samples, float* x,
+                                float* extra) {
+  NN_ENTRY({
+    NN_REQUIRE(raw && scene && hmap && x && extra && n >= 0 && H >= 2 && half_extent_m > 0.0f && samples >= 1,
+               "link_features arguments");
+    if (n > 0) nn_link_features(raw, n, scene, hmap, H, half_extent_m, samples, x, extra, s);
   });
 }
 

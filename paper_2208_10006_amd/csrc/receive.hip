@@ -18,6 +18,7 @@
 //               cosines, materials) is stored for the channel kernels.
 //  4. order:    valid paths sorted by (rx, tx, delay); CSR per (rx, tx).
 #include <algorithm>
+#include <optional>
 #include <cmath>
 
 #include "sbr_device.hpp"
@@ -524,8 +525,13 @@ void run_receive(sbr_paths_s* ps, hipStream_t s) {
   // ---------------- Rx LBVH (FP32 boxes in a frame centred on the Rx bounding sphere)
   HostPhase hp_rx("host:rx_tree");
   std::vector<double> hrx(3 * (size_t)Nr);
-  SBR_HIP(hipMemcpyAsync(hrx.data(), ps->rx.p, hrx.size() * 8, hipMemcpyDeviceToHost, s));
-  SBR_HIP(hipStreamSynchronize(s));
+  {
+    HostPhase hp("host:rx_readback");
+    SBR_HIP(hipMemcpyAsync(hrx.data(), ps->rx.p, hrx.size() * 8, hipMemcpyDeviceToHost, s));
+    SBR_HIP(hipStreamSynchronize(s));
+  }
+  std::optional<HostPhase> hp_step;
+  hp_step.emplace("host:rx_boxes");
   double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
   for (int q = 0; q < Nr; ++q)
     for (int c = 0; c < 3; ++c) lo[c] = std::min(lo[c], hrx[3 * q + c]), hi[c] = std::max(hi[c], hrx[3 * q + c]);
@@ -552,6 +558,7 @@ void run_receive(sbr_paths_s* ps, hipStream_t s) {
   dhi.alloc(bhi.size() * 4, s);
   SBR_HIP(hipMemcpyAsync(dlo.p, blo.data(), blo.size() * 4, hipMemcpyHostToDevice, s));
   SBR_HIP(hipMemcpyAsync(dhi.p, bhi.data(), bhi.size() * 4, hipMemcpyHostToDevice, s));
+  hp_step.emplace("host:rx_lbvh");
   rnodes.alloc((size_t)std::max(Nr - 1, 1) * 64, s);
   rorder.alloc((size_t)Nr * 4, s);
   rroot.alloc(32, s);
@@ -560,6 +567,7 @@ void run_receive(sbr_paths_s* ps, hipStream_t s) {
       build_lbvh(dlo.as<float>(), dhi.as<float>(), Nr, flo, fhi, BvhOut{rnodes.as<float4>(), rorder.as<uint32_t>(),
                                                                          rroot.as<float>(), hroot}, s);
   SBR_CHECK(rdepth <= 64, SBR_E_UNSUPPORTED, "receiver tree depth %d", rdepth);
+  hp_step.reset();
 
   // ---------------- replay + capture (grow the event buffer and retry on overflow)
   ReplayParams P{};

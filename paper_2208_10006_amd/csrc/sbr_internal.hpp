@@ -138,25 +138,6 @@ struct TraceGraph {
   ~TraceGraph();
 };
 
-// nn.hip (surrogate)
-void nn_gemm(int M, int N, int K, const void* A, int64_t a_si, int64_t a_sk, const void* B, int64_t b_sk,
-             int64_t b_sj, const float* bias, void* C, int64_t ldc, uint32_t flags, hipStream_t s);
-void nn_im2col(const void* x, int n, int H, int W, int C, void* col, hipStream_t s);
-void nn_col2im(const float* dcol, int n, int H, int W, int C, float* dx, hipStream_t s);
-void nn_fourier(const float* x, int64_t n, int D, int L, const void* emb, int E, const int32_t* scene, int F,
-                void* out, hipStream_t s);
-void nn_relu_bwd(const float* g, const void* y, int64_t n, float* gout, void* gbf, hipStream_t s);
-void nn_cast(const float* a, int64_t n, void* b, hipStream_t s);
-void nn_mse(const float* pred, int64_t ldp, const float* target, const float* weight, int64_t n, int T, float scale,
-            float* dpred, int64_t ldd, double* loss, hipStream_t s);
-void nn_colsum(const float* g, int64_t M, int N, int64_t ld, float* out, int accumulate, hipStream_t s);
-void nn_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
-             float wd, int step, void* wbf, hipStream_t s);
-void nn_gather_rows(const void* src, int64_t row_bytes, const int64_t* idx, int64_t n, void* dst, hipStream_t s);
-void nn_onehot(const int32_t* idx, int64_t n, int width, void* out, hipStream_t s);
-void nn_ensemble(const float* out, int E, int64_t member_stride, int64_t n, int64_t ld, int t, float threshold,
-                 float* mean, float* spread, uint8_t* mask, hipStream_t s);
-
 }  // namespace sbr
 
 struct sbr_context_s : sbr::Handle {
@@ -311,8 +292,10 @@ void nn_gemm(int M, int N, int K, const void* A, int64_t a_si, int64_t a_sk, con
              int64_t b_sj, const float* bias, void* C, int64_t ldc, uint32_t flags, hipStream_t s);
 void nn_im2col(const void* x, int n, int H, int W, int C, void* col, hipStream_t s);
 void nn_col2im(const float* dcol, int n, int H, int W, int C, float* dx, hipStream_t s);
-void nn_fourier(const float* x, int64_t n, int D, int L, const void* emb, int E, const int32_t* scene, int F,
-                void* out, hipStream_t s);
+void nn_fourier(const float* x, int64_t n, int D, int L, const void* emb, int E, const int32_t* scene,
+                const float* extra, int X, int F, void* out, hipStream_t s);
+void nn_link_features(const float* raw, int64_t n, const int32_t* scene, const void* hmap, int H, float half,
+                      int samples, float* x, float* extra, hipStream_t s);
 void nn_relu_bwd(const float* g, const void* y, int64_t n, float* gout, void* gbf, hipStream_t s);
 void nn_cast(const float* a, int64_t n, void* b, hipStream_t s);
 void nn_mse(const float* pred, int64_t ldp, const float* target, const float* weight, int64_t n, int T, float scale,

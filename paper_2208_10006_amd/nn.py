@@ -16,7 +16,8 @@ _SIG = {
     "sbr_nn_gemm_bf16": [P, I32, I32, I32, P, I64, I64, P, I64, I64, P, P, I64, U32],
     "sbr_nn_im2col": [P, P, I32, I32, I32, I32, P],
     "sbr_nn_col2im": [P, P, I32, I32, I32, I32, P],
-    "sbr_nn_fourier": [P, P, I64, I32, I32, P, I32, P, I32, P],
+    "sbr_nn_fourier": [P, P, I64, I32, I32, P, I32, P, P, I32, I32, P],
+    "sbr_nn_link_features": [P, P, I64, P, P, I32, F, I32, P, P],
     "sbr_nn_relu_backward": [P, P, P, I64, P, P],
     "sbr_nn_cast_bf16": [P, P, I64, P],
     "sbr_nn_mse": [P, P, I64, P, P, I64, I32, F, P, I64, P],
@@ -53,8 +54,12 @@ def sbr_nn_col2im(ctx, dcol, n, H, W, Cch, dx):
     S._call("sbr_nn_col2im", ctx.h, _p(dcol), n, H, W, Cch, _p(dx))
 
 
-def sbr_nn_fourier(ctx, x, n, D, Lb, emb, E, scene, Fw, out):
-    S._call("sbr_nn_fourier", ctx.h, _p(x), n, D, Lb, _p(emb), E, _p(scene), Fw, _p(out))
+def sbr_nn_fourier(ctx, x, n, D, Lb, emb, E, scene, Fw, out, extra=None, X=0):
+    S._call("sbr_nn_fourier", ctx.h, _p(x), n, D, Lb, _p(emb), E, _p(scene), _p(extra), X, Fw, _p(out))
+
+
+def sbr_nn_link_features(ctx, raw, n, scene, hmap, H, half, samples, x, extra):
+    S._call("sbr_nn_link_features", ctx.h, _p(raw), n, _p(scene), _p(hmap), H, float(half), samples, _p(x), _p(extra))
 
 
 def sbr_nn_relu_backward(ctx, g, y, n, gout=None, gbf=None):

@@ -7,12 +7,16 @@ path produces at the carrier, from
   * the scene's 128 x 128 height map (max building height per pixel, / 60 m),
     encoded once per scene by four 3x3 / stride-2 convolutions (1 -> 16 -> 32
     -> 64 -> 128 channels, ReLU) and a linear layer to a 128-wide embedding,
-  * seven normalised scalars (Tx xyz, Rx xyz, log f) and their Fourier
-    features sin / cos (2^l pi x), l < 8,
+  * seven normalised scalars (Tx xyz, Rx xyz, log f), their Fourier
+    features sin / cos (2^l pi x), l < 8, and three link features computed
+    from the same inputs (free-space path gain, and the terrain clearance
+    and obstruction of the straight Tx-Rx segment over the height map),
   * an MLP of six ReLU layers of width 256 and a linear output of width 2.
-Four members (different initialisations, bootstrap resamples of the
-training set) form an ensemble; where the members' PG spread exceeds a
-threshold (1 dB) the caller re-runs the full SBR path for that Rx.
+Rx where SBR finds no path are trained towards a -200 dB floor and a
+prediction below -180 dB reads as "no path".  Four members (different
+initialisations, bootstrap resamples of the training set) form an
+ensemble; where the members' PG spread exceeds a threshold (1 dB) the
+caller re-runs the full SBR path for that Rx.
 
 Every arithmetic step runs in the library's kernels: BF16 matrix-core GEMMs
 with FP32 accumulation for the convolutions (im2col / col2im around the
@@ -37,7 +41,10 @@ BF16 = torch.bfloat16
 F32 = torch.float32
 LOG_F_LO, LOG_F_HI = math.log(28e9), math.log(300e9)
 PG_OFFSET_DB, PG_SCALE_DB = 120.0, 20.0   # target 0 = (PG + 120) / 20
+PG_FLOOR_DB, PG_NO_PATH_DB = -200.0, -180.0  # no-path target; predictions below read as no path
 TAU_SCALE_NS = 100.0                       # target 1 = tau_rms / 100 ns
+HALF_EXTENT_M = 250.0                      # height maps cover [-250, 250]^2 m
+LINK_SAMPLES = 128                         # terrain samples along a Tx-Rx segment
 
 
 @dataclass
@@ -51,6 +58,7 @@ class Arch:
     width: int = 256
     depth: int = 6
     T: int = 2
+    X: int = 3
 
     @property
     def n_conv(self) -> int:
@@ -108,30 +116,34 @@ class Runtime:
 
 
 # ---------------------------------------------------------------- inputs
-def normalise_inputs(tx: np.ndarray, rx: np.ndarray, freq_hz: float) -> np.ndarray:
-    """[n][7] float32: Tx x/250, y/250, z/60, Rx x/250, y/250, z/60, log f mapped to [-1, 1]."""
+def raw_inputs(tx: np.ndarray, rx: np.ndarray, freq_hz: float) -> np.ndarray:
+    """[n][7] float32 rows (Tx x, y, z, Rx x, y, z in metres, f in Hz) for one Tx."""
     n = len(rx)
-    x = np.empty((n, 7), np.float32)
-    x[:, 0:3] = np.asarray(tx, float).reshape(1, 3) / np.array([250.0, 250.0, 60.0])
-    x[:, 3:6] = np.asarray(rx, float) / np.array([250.0, 250.0, 60.0])
-    x[:, 6] = 2.0 * (math.log(freq_hz) - LOG_F_LO) / (LOG_F_HI - LOG_F_LO) - 1.0
-    return x
+    r = np.empty((n, 7), np.float32)
+    r[:, 0:3] = np.asarray(tx, float).reshape(1, 3)
+    r[:, 3:6] = rx
+    r[:, 6] = freq_hz
+    return r
 
 
 def targets_from_sbr(pg_db: np.ndarray, tau_s: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
-    """Normalised targets [n][2] and weights [n][2] (0 where SBR found no path)."""
+    """Normalised targets [n][2] and weights [n][2]: PG for every Rx (the floor
+    where SBR found no path), delay spread only where there is a path."""
     pg = np.asarray(pg_db, np.float64).reshape(-1)
     tau = np.asarray(tau_s, np.float64).reshape(-1)
     ok = np.isfinite(pg)
     t = np.zeros((len(pg), 2), np.float32)
-    t[ok, 0] = (pg[ok] + PG_OFFSET_DB) / PG_SCALE_DB
+    t[:, 0] = (np.where(ok, pg, PG_FLOOR_DB) + PG_OFFSET_DB) / PG_SCALE_DB
     t[ok, 1] = tau[ok] * 1e9 / TAU_SCALE_NS
-    w = np.repeat(ok[:, None], 2, axis=1).astype(np.float32)
+    w = np.ones((len(pg), 2), np.float32)
+    w[:, 1] = ok
     return t, w
 
 
 def pg_db_from_output(out: np.ndarray) -> np.ndarray:
-    return np.asarray(out, np.float64) * PG_SCALE_DB - PG_OFFSET_DB
+    """Network PG output -> dB, -inf where it reads as no path."""
+    pg = np.asarray(out, np.float64) * PG_SCALE_DB - PG_OFFSET_DB
+    return np.where(pg < PG_NO_PATH_DB, -np.inf, pg)
 
 
 # ---------------------------------------------------------------- one member
@@ -259,10 +271,10 @@ def stem_forward(mem: Member, ws: Workspace, hmap_bf: torch.Tensor) -> None:
 
 
 def mlp_forward(mem: Member, ws: Workspace, x: torch.Tensor, scene: torch.Tensor, n: int, out: torch.Tensor,
-                keep: bool) -> None:
+                keep: bool, extra: Optional[torch.Tensor] = None) -> None:
     """Features of n points -> out [n][T] FP32.  keep: store every hidden layer (training)."""
     a, ctx = mem.arch, mem.ctx
-    K.sbr_nn_fourier(ctx, x, n, a.D, a.L, ws.emb, a.E, scene, a.F, ws.feat)
+    K.sbr_nn_fourier(ctx, x, n, a.D, a.L, ws.emb, a.E, scene, a.F, ws.feat, extra, a.X)
     h, fin = ws.feat, a.F
     for i in range(a.depth):
         dst = ws.h[i] if keep else ws.h[i & 1]
@@ -328,7 +340,8 @@ def backward(mem: Member, ws: Workspace, hmap_bf: torch.Tensor, scene: torch.Ten
 class Dataset:
     """Training / evaluation points on the device."""
     hmap: torch.Tensor          # [S][H][H] bf16
-    x: torch.Tensor             # [n][7] f32
+    x: torch.Tensor             # [n][7] f32 normalised scalars
+    extra: torch.Tensor         # [n][X] f32 link features
     scene: torch.Tensor         # [n] int32
     target: torch.Tensor        # [n][2] f32
     weight: torch.Tensor        # [n][2] f32
@@ -340,32 +353,51 @@ class Dataset:
         return int(self.x.shape[0])
 
 
-def sbr_labels(ctx: S.Context, w, rx: Optional[np.ndarray] = None, alpha: float = 0.0) -> Tuple[np.ndarray, np.ndarray]:
+def sbr_labels(ctx: S.Context, w, rx: Optional[np.ndarray] = None, alpha: float = 0.0,
+               times: Optional[dict] = None) -> Tuple[np.ndarray, np.ndarray]:
     """Full SBR path for one scene (build, trace, receive, channel at the
     workload's frequencies, stats): PG dB and tau_rms s per Rx (host arrays,
     complete on return)."""
+    t0 = time.perf_counter()
     sc = S.sbr_scene_build(ctx, w.tri, w.eps_r, w.sigma, w.rough)
     tr = S.sbr_trace(ctx, sc, w.tx, w.geodesic_N, w.max_bounces)
+    if times is not None:
+        S.sbr_synchronize(ctx)
+        t1 = time.perf_counter()
+        times["trace_s"] = times.get("trace_s", 0.0) + (t1 - t0)
     ps = S.sbr_receive(ctx, tr, w.rx if rx is None else rx, alpha, w.radius_coeff)
     S.sbr_channel(ctx, ps, w.freq, w.atm_db_per_m, w.atm_deg_per_m)
     pg, tau, _ = S.sbr_stats(ps)
+    if times is not None:
+        times["receive_s"] = times.get("receive_s", 0.0) + (time.perf_counter() - t1)
     return pg[:, 0].astype(np.float64), tau[:, 0].astype(np.float64)
 
 
-def make_dataset(scenes, labels) -> Dataset:
-    """scenes: list of (workload, height map); labels: list of (pg_db, tau_s)."""
-    hm, xs, sc, ts, ws, pgs = [], [], [], [], [], []
+def make_dataset(rt: Runtime, scenes, labels, arch: Optional[Arch] = None) -> Dataset:
+    """scenes: list of (workload, height map); labels: list of (pg_db, tau_s).
+    The network inputs are computed on the GPU (sbr_nn_link_features)."""
+    arch = arch or Arch()
+    hm, raws, sc, ts, ws, pgs = [], [], [], [], [], []
     for s, ((w, h), (pg, tau)) in enumerate(zip(scenes, labels)):
         hm.append(h)
-        xs.append(normalise_inputs(w.tx[0], w.rx, float(w.freq[0])))
+        raws.append(raw_inputs(w.tx[0], w.rx, float(w.freq[0])))
         sc.append(np.full(len(w.rx), s, np.int32))
         t, wt = targets_from_sbr(pg, tau)
         ts.append(t)
         ws.append(wt)
         pgs.append(pg)
-    cuda = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(dt).cuda()  # noqa: E731
-    return Dataset(cuda(np.stack(hm), BF16), cuda(np.concatenate(xs), F32), cuda(np.concatenate(sc), torch.int32),
-                   cuda(np.concatenate(ts), F32), cuda(np.concatenate(ws), F32), np.concatenate(pgs))
+    with rt:
+        cuda = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(dt).cuda()  # noqa: E731
+        raw = cuda(np.concatenate(raws), F32)
+        n = int(raw.shape[0])
+        hmap, scene = cuda(np.stack(hm), BF16), cuda(np.concatenate(sc), torch.int32)
+        x = torch.empty((n, arch.D), dtype=F32, device="cuda")
+        extra = torch.empty((n, arch.X), dtype=F32, device="cuda")
+        K.sbr_nn_link_features(rt.ctx, raw, n, scene, hmap, arch.H, HALF_EXTENT_M, LINK_SAMPLES, x, extra)
+        d = Dataset(hmap, x, extra, scene, cuda(np.concatenate(ts), F32), cuda(np.concatenate(ws), F32),
+                    np.concatenate(pgs))
+    rt.synchronize()
+    return d
 
 
 # ---------------------------------------------------------------- ensemble
@@ -385,9 +417,10 @@ class Ensemble:
 
     # -- training
     def train(self, data: Dataset, steps: int, batch: int = 4096, lr: float = 2e-3, lr_end: float = 1e-4,
-              seed: int = 0, log=None) -> List[float]:
+              seed: int = 0, log=None, weight_decay: float = 0.0) -> List[float]:
         """Adam on each member over bootstrap resamples (cosine learning-rate
         decay); the stem runs on every training scene each step."""
+        self.weight_decay = weight_decay
         with self.rt:
             losses = self._train(data, steps, batch, lr, lr_end, seed, log)
         self.rt.synchronize()
@@ -395,10 +428,11 @@ class Ensemble:
 
     def _train(self, data, steps, batch, lr, lr_end, seed, log):
         ctx, a = self.ctx, self.arch
-        valid = np.nonzero(data.pg_db > -np.inf)[0]
+        valid = np.arange(data.n)
         Sn = int(data.hmap.shape[0])
         ws = self.workspace(Sn, batch, True)
         xb = torch.empty((batch, a.D), dtype=F32, device="cuda")
+        eb = torch.empty((batch, a.X), dtype=F32, device="cuda")
         sb = torch.empty(batch, dtype=torch.int32, device="cuda")
         tb = torch.empty((batch, a.T), dtype=F32, device="cuda")
         wb = torch.empty((batch, a.T), dtype=F32, device="cuda")
@@ -410,31 +444,32 @@ class Ensemble:
             for it in range(steps):
                 idx = idx_all[it]
                 K.sbr_nn_gather_rows(ctx, data.x, 4 * a.D, idx, batch, xb)
+                K.sbr_nn_gather_rows(ctx, data.extra, 4 * a.X, idx, batch, eb)
                 K.sbr_nn_gather_rows(ctx, data.scene, 4, idx, batch, sb)
                 K.sbr_nn_gather_rows(ctx, data.target, 4 * a.T, idx, batch, tb)
                 K.sbr_nn_gather_rows(ctx, data.weight, 4 * a.T, idx, batch, wb)
                 stem_forward(mem, ws, data.hmap)
-                mlp_forward(mem, ws, xb, sb, batch, ws.out, keep=True)
-                K.sbr_nn_mse(ctx, ws.out, a.T, tb, wb, batch, a.T, 1.0 / (batch * a.T), ws.dout, a.T, ws.loss)
+                mlp_forward(mem, ws, xb, sb, batch, ws.out, keep=True, extra=eb)
+                K.sbr_nn_mse(ctx, ws.out, a.T, tb, wb, batch, a.T, 1.0 / batch, ws.dout, a.T, ws.loss)
                 backward(mem, ws, data.hmap, sb, batch)
                 frac = it / max(steps - 1, 1)
-                mem.adam(lr_end + 0.5 * (lr - lr_end) * (1 + math.cos(math.pi * frac)))
+                mem.adam(lr_end + 0.5 * (lr - lr_end) * (1 + math.cos(math.pi * frac)), wd=self.weight_decay)
                 if log is not None and (it % 200 == 0 or it == steps - 1):
                     losses.append(float(ws.loss.item()))
                     log(f"member {mi} step {it} loss {losses[-1]:.5f}")
         return losses
 
     # -- inference
-    def predict(self, hmap: torch.Tensor, x: torch.Tensor, scene: torch.Tensor, chunk: int = 1 << 18,
-                threshold_db: float = 1.0):
+    def predict(self, hmap: torch.Tensor, x: torch.Tensor, extra: torch.Tensor, scene: torch.Tensor,
+                chunk: int = 1 << 18, threshold_db: float = 1.0):
         """Ensemble over all members for n points: (mean out [n][T], PG spread dB [n],
         fallback mask [n] uint8), device tensors, complete on return."""
         with self.rt:
-            res = self._predict(hmap, x, scene, chunk, threshold_db)
+            res = self._predict(hmap, x, extra, scene, chunk, threshold_db)
         self.rt.synchronize()
         return res
 
-    def _predict(self, hmap, x, scene, chunk, threshold_db):
+    def _predict(self, hmap, x, extra, scene, chunk, threshold_db):
         ctx, a = self.ctx, self.arch
         n = int(x.shape[0])
         Sn = int(hmap.shape[0])
@@ -446,7 +481,8 @@ class Ensemble:
             stem_forward(mem, ws, hmap)
             for s in range(0, n, chunk):
                 m = min(chunk, n - s)
-                mlp_forward(mem, ws, x[s:s + m], scene[s:s + m], m, outs[mi, s:s + m], keep=False)
+                mlp_forward(mem, ws, x[s:s + m], scene[s:s + m], m, outs[mi, s:s + m], keep=False,
+                            extra=extra[s:s + m])
         mean = torch.empty((n, a.T), dtype=F32, device="cuda")
         spread = torch.empty(n, dtype=F32, device="cuda")
         mask = torch.empty(n, dtype=torch.uint8, device="cuda")
@@ -461,16 +497,22 @@ class Ensemble:
 
 # ---------------------------------------------------------------- fallback
 def surrogate_with_fallback(ens: Ensemble, scenes: Sequence, data: Dataset, threshold_db: float = 1.0,
-                            alpha: float = 0.0):
+                            alpha: float = 0.0, prediction=None):
     """Predict every point; re-run the SBR path (trace the scene, receive only
     the flagged Rx) for scenes with flagged points; merge.  Returns
-    (pg_db [n] host, tau_s [n] host, mask [n] host bool, timings dict)."""
+    (pg_db [n] host, tau_s [n] host, mask [n] host bool, timings dict).
+    prediction: (mean [n][T], spread dB [n]) host arrays of an earlier
+    predict() to reuse (its time is then not counted)."""
     ctx = ens.ctx
     t0 = time.perf_counter()
-    mean, spread, mask = ens.predict(data.hmap, data.x, data.scene, threshold_db=threshold_db)
+    if prediction is None:
+        mean, spread, _ = ens.predict(data.hmap, data.x, data.extra, data.scene, threshold_db=threshold_db)
+        out = mean.cpu().numpy()
+        m = spread.cpu().numpy() > threshold_db
+    else:
+        out, sp = prediction
+        m = sp > threshold_db
     t1 = time.perf_counter()
-    out = mean.cpu().numpy()
-    m = mask.cpu().numpy().astype(bool)
     pg = pg_db_from_output(out[:, 0])
     tau = out[:, 1].astype(np.float64) * TAU_SCALE_NS * 1e-9
     start = 0
@@ -486,15 +528,143 @@ def surrogate_with_fallback(ens: Ensemble, scenes: Sequence, data: Dataset, thre
         start += nr
     ens.rt.synchronize()
     t2 = time.perf_counter()
-    return pg, tau, m, {"surrogate_s": t1 - t0, "fallback_s": t2 - t1, "fallback_scenes": n_fb_scenes}
+    return pg, tau, m, {"surrogate_s": t1 - t0, "fallback_s": t2 - t1, "fallback_scenes": n_fb_scenes,
+                        "fallback_rx": int(m.sum())}
 
 
 def gate(pg_pred: np.ndarray, pg_sbr: np.ndarray) -> dict:
     """Path-gain error against plain SBR over the Rx where SBR found a path."""
     ok = np.isfinite(pg_sbr)
-    pred = np.where(np.isfinite(pg_pred), pg_pred, -400.0)
+    pred = np.where(np.isfinite(pg_pred), pg_pred, PG_FLOOR_DB)
     e = np.abs(pred[ok] - pg_sbr[ok])
     if e.size == 0:
         return {"mae_db": 0.0, "p90_db": 0.0, "p99_db": 0.0, "n": 0}
     return {"mae_db": float(e.mean()), "p90_db": float(np.percentile(e, 90)), "p99_db": float(np.percentile(e, 99)),
             "n": int(e.size)}
+
+
+# ---------------------------------------------------------------- full pipeline
+@dataclass
+class PipelineConfig:
+    """Radio-map surrogate workload: urban scenes of the canyon generator with
+    f_c ~ logU(28, 300) GHz and a random outdoor Tx at 25 m."""
+    train_seeds: Sequence[int] = tuple(range(5000, 5100))
+    test_seeds: Sequence[int] = tuple(range(6000, 6064))
+    n_rx_train: int = 1000
+    n_rx_test: int = 15625
+    geodesic_N: int = 1024
+    max_bounces: int = 6
+    members: int = 4
+    steps: int = 3000
+    batch: int = 4096
+    lr: float = 2e-3
+    weight_decay: float = 1e-4
+    threshold_db: float = 1.0
+    sweep_db: Sequence[float] = (2.0, 3.0, 5.0)
+
+
+def mlp_flops_per_point(arch: Arch) -> int:
+    """Multiply-adds x 2 of the point MLP (the per-point part of inference)."""
+    f, fin = 0, arch.F
+    for _ in range(arch.depth):
+        f += 2 * fin * arch.width
+        fin = arch.width
+    return f + 2 * fin * arch.T
+
+
+def stem_flops_per_scene(arch: Arch) -> int:
+    f, hw = 0, arch.H
+    for i in range(arch.n_conv):
+        hw //= 2
+        f += 2 * hw * hw * 9 * arch.chans[i] * arch.chans[i + 1]
+    return f + 2 * arch.flat * arch.E
+
+
+def run_pipeline(cfg: PipelineConfig, log=print) -> dict:
+    """Labels from SBR, training, then on unseen scenes: plain SBR on every Rx
+    versus surrogate + SBR fallback, with the path-gain gate.  Times are wall
+    clock with the GPU synchronised at both ends; scene generation (host
+    numpy) is input preparation and not timed."""
+    from . import workloads as W
+    rt = Runtime(0)
+    arch = Arch()
+    res: dict = {"config": {k: (list(v)[:1] + ["..", list(v)[-1]] if isinstance(v, (range, tuple)) else v)
+                            for k, v in cfg.__dict__.items()}}
+    t = time.perf_counter()
+    train = [W.urban_surrogate_scene(s, n_rx=cfg.n_rx_train, N=cfg.geodesic_N, K=cfg.max_bounces)[:2]
+             for s in cfg.train_seeds]
+    log(f"[surrogate] {len(train)} training scenes generated in {time.perf_counter() - t:.1f}s")
+    rt.synchronize()
+    t = time.perf_counter()
+    labels = [sbr_labels(rt.ctx, w) for w, _ in train]
+    rt.synchronize()
+    res["label_s"] = time.perf_counter() - t
+    data = make_dataset(rt, train, labels, arch)
+    res["train_points"] = data.n
+    res["train_points_with_path"] = int(np.isfinite(data.pg_db).sum())
+    log(f"[surrogate] labels {res['label_s']:.2f}s, {res['train_points_with_path']}/{data.n} Rx with a path")
+    ens = Ensemble(arch, rt, cfg.members, seed=0)
+    t = time.perf_counter()
+    losses = ens.train(data, cfg.steps, cfg.batch, cfg.lr, log=lambda s: log("[surrogate] " + s),
+                       weight_decay=cfg.weight_decay)
+    res["train_s"] = time.perf_counter() - t
+    res["train_loss"] = losses
+    del data
+    t = time.perf_counter()
+    test = [W.urban_surrogate_scene(s, n_rx=cfg.n_rx_test, random_rx=True, N=cfg.geodesic_N, K=cfg.max_bounces)[:2]
+            for s in cfg.test_seeds]
+    log(f"[surrogate] {len(test)} test scenes generated in {time.perf_counter() - t:.1f}s")
+    tdata = make_dataset(rt, test, [(np.zeros(len(w.rx)), np.zeros(len(w.rx))) for w, _ in test], arch)
+    n = tdata.n
+    # plain SBR on every Rx
+    rt.synchronize()
+    t = time.perf_counter()
+    ref = []
+    for i, (w, _) in enumerate(test):
+        ref.append(sbr_labels(rt.ctx, w))
+    rt.synchronize()
+    t_sbr = time.perf_counter() - t
+    stage: dict = {}
+    for w, _ in test[:8]:
+        sbr_labels(rt.ctx, w, times=stage)
+    res["sbr_stage_s_per_scene"] = {k: v / 8 for k, v in stage.items()}
+    pg_ref = np.concatenate([r[0] for r in ref])
+    log(f"[surrogate] plain SBR {t_sbr:.2f}s for {n} Rx ({n / t_sbr:.4g} Rx/s)")
+    # surrogate inference alone (for the matrix-core roofline), then with fallback
+    S.sbr_profile_enable(rt.ctx, True)
+    t = time.perf_counter()
+    ens.predict(tdata.hmap, tdata.x, tdata.extra, tdata.scene, threshold_db=cfg.threshold_db)
+    t_inf = time.perf_counter() - t
+    gemm_ms, gemm_n = S.sbr_profile_query(rt.ctx, "nn_gemm")
+    S.sbr_profile_enable(rt.ctx, False)
+    pg, tau, mask, tm = surrogate_with_fallback(ens, test, tdata, threshold_db=cfg.threshold_db)
+    t_sur = tm["surrogate_s"] + tm["fallback_s"]
+    g = gate(pg, pg_ref)
+    # other spread thresholds, reusing one prediction (fallback time measured per threshold)
+    mean, spread, _ = ens.predict(tdata.hmap, tdata.x, tdata.extra, tdata.scene)
+    pred = (mean.cpu().numpy(), spread.cpu().numpy())
+    sweep = []
+    for th in cfg.sweep_db:
+        p2, _, m2, t2 = surrogate_with_fallback(ens, test, tdata, threshold_db=th, prediction=pred)
+        sweep.append({"threshold_db": th, "fallback_frac": float(m2.mean()), "fallback_scenes": t2["fallback_scenes"],
+                      "with_fallback_s": tm["surrogate_s"] + t2["fallback_s"],
+                      "gain": t_sbr / (tm["surrogate_s"] + t2["fallback_s"]), "gate": gate(p2, pg_ref)})
+        log(f"[surrogate] threshold {th} dB: {sweep[-1]}")
+    res["sweep"] = sweep
+    flops = len(ens.members) * (n * mlp_flops_per_point(arch) + len(test) * stem_flops_per_scene(arch))
+    res.update({
+        "n_rx": n, "n_scenes": len(test), "test_rx_with_path": int(np.isfinite(pg_ref).sum()),
+        "sbr_s": t_sbr, "sbr_rx_per_s": n / t_sbr,
+        "surrogate_only_s": t_inf, "surrogate_only_rx_per_s": n / t_inf,
+        "surrogate_s": tm["surrogate_s"], "fallback_s": tm["fallback_s"], "fallback_scenes": tm["fallback_scenes"],
+        "fallback_frac": float(mask.mean()), "with_fallback_s": t_sur, "with_fallback_rx_per_s": n / t_sur,
+        "gain": t_sbr / t_sur, "gate": g,
+        "inference_flops": flops, "gemm_ms": gemm_ms, "gemm_launches": gemm_n,
+        "gemm_tflops": flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else None,
+    })
+    # error of the surrogate alone on the Rx it kept (the fallback ones carry SBR values)
+    res["kept_gate"] = gate(pg[~mask], pg_ref[~mask])
+    log(f"[surrogate] surrogate {tm['surrogate_s']:.3f}s + fallback {tm['fallback_s']:.2f}s "
+        f"({tm['fallback_scenes']} scenes, {mask.mean():.3f} of Rx) vs SBR {t_sbr:.2f}s: gain {res['gain']:.2f}, "
+        f"gate {g}")
+    return res

@@ -73,8 +73,10 @@ def run_gemm(env, A, B, layout, bias=None, flags=0, C0=None, out_bf16=False):
     return host(Cd)
 
 
+# covers 64- and 128-wide tiles, split-K (long K, few tiles), ragged edges and
+# every operand load mode (k-contiguous, row-contiguous, general strides)
 SHAPES = [(1, 1, 1), (16, 16, 32), (64, 64, 32), (64, 64, 64), (100, 70, 45), (130, 257, 300), (5, 3, 1000),
-          (300, 2, 17)]
+          (300, 2, 17), (65536, 128, 64), (65600, 136, 72), (9, 16, 409600), (256, 256, 4096)]
 
 
 @pytest.mark.parametrize("layout", ["fwd", "bwd_data", "bwd_weight"])
@@ -181,15 +183,19 @@ def test_fourier_features(env):
     x[1, :] = 0.5
     emb = R.bf16(rng.standard_normal((Sn, E)))
     scene = rng.integers(0, Sn, n).astype(np.int32)
+    X = 2
+    extra = rng.normal(size=(n, X)).astype(np.float32)
     out = torch.empty((n, F), dtype=torch.bfloat16, device="cuda")
     nn.sbr_nn_fourier(ctx, dev(torch, x, torch.float32), n, D, L, dev(torch, emb, torch.bfloat16), E,
-                      dev(torch, scene, torch.int32), F, out)
+                      dev(torch, scene, torch.int32), F, out, dev(torch, extra, torch.float32), X)
     sync(torch)
     g = host(out)
-    arch = R.Arch(E=E, D=D, L=L, F=F)
-    ref = R.features(arch, emb, x.astype(np.float64), scene, lambda a: a)
+    arch = R.Arch(E=E, D=D, L=L, F=F, X=X)
+    ref = R.features(arch, emb, x.astype(np.float64), scene, lambda a: a, extra.astype(np.float64))
+    fe = E + D + 2 * D * L
     assert np.array_equal(g[:, :E + D], R.bf16(ref[:, :E + D]))
-    assert np.all(g[:, E + D + 2 * D * L:] == 0)
+    assert np.array_equal(g[:, fe:fe + X], R.bf16(extra))
+    assert np.all(g[:, fe + X:] == 0)
     fr, fg = ref[:, E + D:E + D + 2 * D * L], g[:, E + D:E + D + 2 * D * L]
     assert np.all(np.abs(fg - fr) <= 2.0 ** -8 * np.abs(fr) + 1e-7)
 

@@ -41,7 +41,7 @@ def banner(*a):
     sys.stdout.flush()
 
 
-SMALL = dict(H=16, chans=(1, 2, 3, 4, 5), E=4, D=3, L=2, F=20, width=6, depth=2, T=2)
+SMALL = dict(H=16, chans=(1, 2, 3, 4, 5), E=4, D=3, L=2, F=24, width=6, depth=2, T=2, X=2)
 
 
 def relerr(a, b):
@@ -66,6 +66,7 @@ def run_gpu(env, arch_kw, Sn, n, seed):
             P[k] = rng.standard_normal(P[k].shape) * 0.1
     hmap = R.bf16(rng.random((Sn, arch_r.H, arch_r.H)) * (rng.random((Sn, arch_r.H, arch_r.H)) < 0.4))
     x = rng.uniform(-1, 1, (n, arch_r.D)).astype(np.float32)
+    extra = rng.normal(size=(n, arch_r.X)).astype(np.float32)
     scene = rng.integers(0, Sn, n).astype(np.int32)
     target = rng.standard_normal((n, arch_r.T)).astype(np.float32)
     weight = (rng.random((n, arch_r.T)) < 0.9).astype(np.float32)
@@ -76,9 +77,9 @@ def run_gpu(env, arch_kw, Sn, n, seed):
         ws = G.Workspace(arch_g, Sn, n, train=True)
         cu = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(dt).cuda()  # noqa: E731
         hm_d = cu(hmap, torch.bfloat16)
-        x_d, sc_d = cu(x, torch.float32), cu(scene, torch.int32)
+        x_d, sc_d, ex_d = cu(x, torch.float32), cu(scene, torch.int32), cu(extra, torch.float32)
         G.stem_forward(mem, ws, hm_d)
-        G.mlp_forward(mem, ws, x_d, sc_d, n, ws.out, keep=True)
+        G.mlp_forward(mem, ws, x_d, sc_d, n, ws.out, keep=True, extra=ex_d)
         G.K.sbr_nn_mse(ctx, ws.out, arch_g.T, cu(target, torch.float32), cu(weight, torch.float32), n, arch_g.T,
                        1.0 / weight.sum(), ws.dout, arch_g.T, ws.loss)
         G.backward(mem, ws, hm_d, sc_d, n, trace=trace)
@@ -86,7 +87,7 @@ def run_gpu(env, arch_kw, Sn, n, seed):
     h = lambda t: t.float().cpu().numpy().astype(np.float64)  # noqa: E731
     acts = {"col": [h(c) for c in ws.col], "act": [h(a) for a in ws.act], "emb": h(ws.emb), "feat": h(ws.feat),
             "h": [h(t) for t in ws.h], "out": h(ws.out), "dout": h(ws.dout), "loss": ws.loss.item()}
-    return dict(arch=arch_r, P=P, hmap=hmap, x=x, scene=scene, target=target, weight=weight, acts=acts,
+    return dict(arch=arch_r, P=P, hmap=hmap, x=x, extra=extra, scene=scene, target=target, weight=weight, acts=acts,
                 grads=mem.grads(), trace={k: h(v) for k, v in trace.items()})
 
 
@@ -95,7 +96,8 @@ def test_end_to_end_small_arch(env):
     bfloat16-emulating FP64 reference to 1e-5 of each tensor's scale."""
     banner("surrogate end-to-end small")
     r = run_gpu(env, SMALL, 3, 50, 7)
-    out_r, cache = R.forward(r["arch"], r["P"], r["hmap"], r["x"].astype(np.float64), r["scene"], use_bf16=True)
+    out_r, cache = R.forward(r["arch"], r["P"], r["hmap"], r["x"].astype(np.float64), r["scene"], use_bf16=True,
+                             extra=r["extra"].astype(np.float64))
     loss_r, dout_r = R.mse(out_r, r["target"].astype(np.float64), r["weight"].astype(np.float64))
     grads_r = R.backward(r["arch"], r["P"], cache, dout_r, use_bf16=True)
     assert relerr(r["acts"]["out"], out_r) <= 1e-5
@@ -131,11 +133,14 @@ def test_forward_layers_full_arch(env, Sn, n):
         check(A["col"][i], f"conv{i}_w", f"conv{i}_b", A["act"][i], True, True, f"conv{i}")
         hw //= 2
     check(A["act"][-1].reshape(Sn, -1), "emb_w", "emb_b", A["emb"], True, True, "emb")
-    feat = R.features(a, A["emb"], r["x"].astype(np.float64), r["scene"], lambda v: v)
+    feat = R.features(a, A["emb"], r["x"].astype(np.float64), r["scene"], lambda v: v,
+                      r["extra"].astype(np.float64))
     E, D, L = a.E, a.D, a.L
+    fe = E + D + 2 * D * L
     assert np.array_equal(A["feat"][:, :E + D], R.bf16(feat[:, :E + D]))
-    four = slice(E + D, E + D + 2 * D * L)
+    four = slice(E + D, fe)
     assert np.all(np.abs(A["feat"][:, four] - feat[:, four]) <= 2.0 ** -8 * np.abs(feat[:, four]) + 1e-7)
+    assert np.array_equal(A["feat"][:, fe:], R.bf16(feat[:, fe:]))
     h_in = A["feat"]
     for i in range(a.depth):
         check(h_in, f"mlp{i}_w", f"mlp{i}_b", A["h"][i], True, True, f"mlp{i}")
@@ -244,6 +249,31 @@ def test_backward_layers_full_arch(env, Sn, n):
     assert errs[worst] <= 2e-2
 
 
+def test_link_features_match_reference(env):
+    """GPU link features against the FP64 reference on urban scenes (all
+    features are continuous in the inputs, so FP32 agrees to ~1e-5)."""
+    torch, S, G, rt = env
+    banner("link features")
+    scenes = [W.urban_surrogate_scene(7000 + s, n_rx=300, random_rx=True, N=8, K=1)[:2] for s in range(3)]
+    raw = np.concatenate([G.raw_inputs(w.tx[0], w.rx, float(w.freq[0])) for w, _ in scenes])
+    scene = np.concatenate([np.full(len(w.rx), i, np.int32) for i, (w, _) in enumerate(scenes)])
+    hm = np.stack([h for _, h in scenes])
+    hm_bf = R.bf16(hm)
+    cu = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(dt).cuda()  # noqa: E731
+    n = len(raw)
+    x = torch.empty((n, 7), dtype=torch.float32, device="cuda")
+    ex = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+    G.K.sbr_nn_link_features(rt.ctx, cu(raw, torch.float32), n, cu(scene, torch.int32), cu(hm, torch.bfloat16),
+                             128, G.HALF_EXTENT_M, G.LINK_SAMPLES, x, ex)
+    rt.synchronize()
+    xr, er = R.link_features(raw.astype(np.float64), scene, hm_bf, G.HALF_EXTENT_M, G.LINK_SAMPLES)
+    assert np.allclose(x.cpu().numpy(), xr, rtol=1e-6, atol=1e-6)
+    eg = ex.cpu().numpy()
+    assert np.all(np.abs(eg[:, 0] - er[:, 0]) <= 1e-5)
+    assert np.all(np.abs(eg[:, 1:] - er[:, 1:]) <= 1e-4)
+    assert (er[:, 2] > 0).any() and (er[:, 2] == 0).any()  # both blocked and clear links occur
+
+
 def test_training_reduces_loss_and_fits(env):
     """A few hundred Adam steps on a smooth synthetic target must fit it."""
     torch, S, G, rt = env
@@ -256,11 +286,11 @@ def test_training_reduces_loss_and_fits(env):
     sc = rng.integers(0, Sn, n).astype(np.int32)
     t = np.stack([np.sin(2 * x[:, 0]) + x[:, 3] * x[:, 4] + 0.25 * sc, np.cos(x[:, 1] + x[:, 5])], 1)
     cu = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(dt).cuda()  # noqa: E731
-    data = G.Dataset(cu(hm, torch.bfloat16), cu(x, torch.float32), cu(sc, torch.int32), cu(t, torch.float32),
-                     cu(np.ones_like(t), torch.float32), np.zeros(n))
+    data = G.Dataset(cu(hm, torch.bfloat16), cu(x, torch.float32), cu(np.zeros((n, arch.X)), torch.float32),
+                     cu(sc, torch.int32), cu(t, torch.float32), cu(np.ones_like(t), torch.float32), np.zeros(n))
     ens = G.Ensemble(arch, rt, members=2, seed=1)
     losses = ens.train(data, steps=600, batch=2048, lr=2e-3, log=lambda s: print(s, flush=True))
-    mean, spread, mask = ens.predict(data.hmap, data.x, data.scene)
+    mean, spread, mask = ens.predict(data.hmap, data.x, data.extra, data.scene)
     mse = float(np.mean((mean.cpu().numpy() - t) ** 2))
     print("final mse", mse, "losses", losses, flush=True)
     assert losses[-1] < 0.1 * losses[0]
@@ -279,12 +309,12 @@ def test_fallback_gain_over_plain_sbr(env):
     t0 = time.time()
     train = [W.urban_surrogate_scene(5000 + s, n_rx=n_rx, N=N, K=K)[:2] for s in range(16)]
     labels = [G.sbr_labels(ctx, w) for w, _ in train]
-    data = G.make_dataset(train, labels)
+    data = G.make_dataset(rt, train, labels)
     print(f"labels {time.time() - t0:.1f}s points {data.n}", flush=True)
     ens = G.Ensemble(G.Arch(), rt, members=4, seed=0)
     ens.train(data, steps=800, batch=2048, log=lambda s: print(s, flush=True))
     test = [W.urban_surrogate_scene(6000 + s, n_rx=3000, random_rx=True, N=N, K=K)[:2] for s in range(3)]
-    tdata = G.make_dataset(test, [(np.zeros(len(w.rx)), np.zeros(len(w.rx))) for w, _ in test])
+    tdata = G.make_dataset(rt, test, [(np.zeros(len(w.rx)), np.zeros(len(w.rx))) for w, _ in test])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ref = [G.sbr_labels(ctx, w) for w, _ in test]
