@@ -163,6 +163,76 @@ def batched_main(args):
     print(json.dumps(out), flush=True)
 
 
+PEAK_BF16_TFLOPS = 2500.0
+
+
+def surrogate_cpu_baseline(ens, test, target_s=15.0):
+    """The FP64 reference network (all members, plus the link features) on a
+    strided sample of the evaluation points, timed on the host cores."""
+    import numpy as np
+    from oracle import surrogate_ref as R
+    from paper_2208_10006_amd import surrogate as G
+    a = ens.arch
+    arch = R.Arch(H=a.H, chans=a.chans, E=a.E, D=a.D, L=a.L, F=a.F, width=a.width, depth=a.depth, T=a.T, X=a.X)
+    params = [m.state() for m in ens.members]
+    hm = np.stack([h for _, h in test]).astype(np.float64)
+    raw = np.concatenate([G.raw_inputs(w.tx[0], w.rx, float(w.freq[0])) for w, _ in test]).astype(np.float64)
+    scene = np.concatenate([np.full(len(w.rx), i) for i, (w, _) in enumerate(test)])
+
+    def run(stride):
+        ids = np.arange(0, len(raw), stride)
+        t0 = time.perf_counter()
+        x, ex = R.link_features(raw[ids], scene[ids], hm, G.HALF_EXTENT_M, G.LINK_SAMPLES)
+        for P in params:
+            R.forward(arch, P, hm, x, scene[ids], extra=ex)
+        return time.perf_counter() - t0, len(ids)
+
+    stride = 4096
+    dt, n = run(stride)
+    stride = max(1, int(stride * dt / target_s))
+    dt, n = run(stride)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": n / dt, "unit": "Rx-channels/s", "cores": cores, "kind": "oracle",
+            "sample": f"every {stride}-th of {len(raw)} evaluation Rx ({n} points): link features + "
+                      f"{len(params)}-member FP64 network including the per-scene stem, {dt:.1f} s"}
+
+
+def surrogate_main(args):
+    """Learned radio-map surrogate with SBR fallback versus plain SBR on the
+    same Rx: labels from SBR, training on the GPU, then 64 unseen scenes."""
+    from paper_2208_10006_amd import surrogate as G
+    cfg = G.PipelineConfig()
+    if args.surrogate_steps:
+        cfg.steps = args.surrogate_steps
+    res = G.run_pipeline(cfg, log=log)
+    ens, test = res.pop("_ensemble"), res.pop("_test")
+    tflops = res["gemm_tflops"]
+    out = {"metric": "Rx channels/s: surrogate + SBR fallback at <=1 dB path-gain MAE",
+           "value": res["with_fallback_rx_per_s"], "unit": "Rx-channels/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+           "ms_per_step": res["with_fallback_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "bf16 (FP32 accumulate); SBR fallback f32/f64", "data": "synthetic",
+           "config": {"workload": f"radio-map surrogate: {res['n_scenes']} unseen urban scenes x "
+                                  f"{cfg.n_rx_test} random outdoor Rx (seeds {cfg.test_seeds[0]}-{cfg.test_seeds[-1]}), "
+                                  f"trained on {len(cfg.train_seeds)} scenes x {cfg.n_rx_train} Rx, "
+                                  f"N={cfg.geodesic_N}, K={cfg.max_bounces}, 4 x MLP 6x256",
+                      "n_rx": res["n_rx"], "threshold_db": cfg.threshold_db},
+           "plain_sbr_rx_per_s": res["sbr_rx_per_s"], "gain_vs_plain_sbr": res["gain"], "gate": res["gate"],
+           "fallback_frac": res["fallback_frac"], "fallback_scenes": res["fallback_scenes"],
+           "surrogate_only_rx_per_s": res["surrogate_only_rx_per_s"], "kept_gate": res.get("kept_gate"),
+           "sbr_stage_s_per_scene": res["sbr_stage_s_per_scene"], "threshold_sweep": res["sweep"],
+           "training": {"label_s": res["label_s"], "train_s": res["train_s"], "steps": cfg.steps,
+                        "batch": cfg.batch, "points": res["train_points"],
+                        "points_with_path": res["train_points_with_path"], "final_loss": res["train_loss"][-1]},
+           "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(tflops / PEAK_BF16_TFLOPS, 4), "traffic": None,
+                        "kernel": "k_gemm_bf16 (all surrogate GEMMs of one 1M-point ensemble inference)",
+                        "flops": res["inference_flops"], "gemm_ms": res["gemm_ms"]}}
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (FP64 reference network on a sample) ...")
+        out["cpu_baseline"] = surrogate_cpu_baseline(ens, test, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -172,6 +242,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--scenes", type=int, default=64, help="batched_uneven: number of scenes")
+    ap.add_argument("--surrogate-steps", type=int, default=0, help="surrogate: training steps per member")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding "
@@ -180,6 +251,8 @@ def main():
 
     if args.workload == "batched_uneven":
         return batched_main(args)
+    if args.workload == "surrogate":
+        return surrogate_main(args)
     import torch
     from paper_2208_10006_amd import sbr as S
     from paper_2208_10006_amd import workloads as W

@@ -383,8 +383,15 @@ sbr_status nn_guard_call(sbr_context_t ctx, const std::function<void(hipStream_t
 
 using namespace sbr;
 
+void* sbr_context_s::scratch_get(int slot, size_t bytes, hipStream_t s) {
+  Buf& b = scratch[slot];
+  if (b.p == nullptr || b.bytes < bytes || b.stream != s) b.alloc(bytes + bytes / 8, s);
+  return b.p;
+}
+
 sbr_context_s::~sbr_context_s() {
   if (stream) (void)hipStreamSynchronize(stream);
+  for (auto& b : scratch) b.reset();
   for (auto* g : graphs) delete g;
   if (stage) (void)hipHostFree(stage);
   prof.clear();
@@ -649,9 +656,8 @@ sbr_status sbr_trace(sbr_context_t ctx, sbr_scene_t scene, const double* tx_xyz,
       upload(tr->tx, tr->h_tx.data(), tr->h_tx.size(), 0, s);
       tr->seq.alloc((size_t)(K + 1) * tr->NR * 4, s);
       tr->counters.alloc((size_t)trace_counter_words(K) * 4, s);
-      Buf ra, rb;
-      ra.alloc(trace_ray_bytes(tr->NR), s);
-      if (K > 0) rb.alloc(trace_ray_bytes(tr->NR), s);
+      void* ra = c->scratch_get(0, trace_ray_bytes(tr->NR), s);
+      void* rb = K > 0 ? c->scratch_get(1, trace_ray_bytes(tr->NR), s) : ra;
       TraceLaunch L{};
       L.ctx = c;
       L.scene = sc, L.tx = tr->tx.as<double>(), L.Nt = Nt, L.N = N, L.K = K, L.R = R, L.NR = tr->NR;
@@ -667,7 +673,7 @@ sbr_status sbr_trace(sbr_context_t ctx, sbr_scene_t scene, const double* tx_xyz,
       L.block = 256;
       L.grid = c->num_cus * c->tune.trace_blocks_per_cu;
       L.chunk = c->tune.trace_chunk;
-      launch_trace(L, ra.p, K > 0 ? rb.p : ra.p, s);
+      launch_trace(L, ra, rb, s);
     } catch (...) {
       release(tr);
       throw;
@@ -725,13 +731,13 @@ sbr_status sbr_trace_batch(sbr_context_t ctx, int32_t n, const sbr_scene_t* scen
       for (auto* tr : trs) st.put(tr->tx, tr->h_tx.data(), tr->h_tx.size(), s);
       int Kmax = 0;
       for (auto* tr : trs) Kmax = std::max(Kmax, tr->K);
-      Buf ra, rb, cnt, stamps;
-      ra.alloc(trace_ray_bytes(total), s);
-      rb.alloc(trace_ray_bytes(total), s);
+      void* ra = c->scratch_get(0, trace_ray_bytes(total), s);
+      void* rb = c->scratch_get(1, trace_ray_bytes(total), s);
+      Buf cnt, stamps;
       cnt.alloc((size_t)trace_counter_words(Kmax) * 4, s);
       stamps.alloc((size_t)2 * n * 8, s);
       unsigned long long* t_first = stamps.as<unsigned long long>();
-      launch_trace_batch(trs, c->num_cus * c->tune.trace_blocks_per_cu, c->tune.trace_chunk, ra.p, rb.p,
+      launch_trace_batch(trs, c->num_cus * c->tune.trace_blocks_per_cu, c->tune.trace_chunk, ra, rb,
                          cnt.as<uint32_t>(), t_first, t_first + n, s);
       std::vector<unsigned long long> h(2 * (size_t)n);
       SBR_HIP(hipMemcpyAsync(h.data(), stamps.p, h.size() * 8, hipMemcpyDeviceToHost, s));

@@ -153,6 +153,11 @@ struct sbr_context_s : sbr::Handle {
   std::vector<sbr::TraceGraph*> graphs;  // cached bounce-loop graphs
   // cached geodesic edge statistics per N
   std::vector<std::pair<int, double>> alpha_cache;
+  // grow-only device scratch reused by successive calls on this context's
+  // stream (the two ray buffers of a trace); large per-call allocations from
+  // the stream-ordered pool can stall while the pool grows
+  sbr::Buf scratch[2];
+  void* scratch_get(int slot, size_t bytes, hipStream_t s);
   sbr_context_s() : Handle(sbr::kContext) {}
   ~sbr_context_s() override;
 };

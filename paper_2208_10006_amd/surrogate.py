@@ -517,19 +517,26 @@ def surrogate_with_fallback(ens: Ensemble, scenes: Sequence, data: Dataset, thre
     tau = out[:, 1].astype(np.float64) * TAU_SCALE_NS * 1e-9
     start = 0
     n_fb_scenes = 0
+    per_scene = []
+    stage: dict = {}
     for (w, _h) in scenes:
         nr = len(w.rx)
         sel = np.nonzero(m[start:start + nr])[0]
         if len(sel):
             n_fb_scenes += 1
-            p, t = sbr_labels(ctx, w, rx=np.ascontiguousarray(w.rx[sel]), alpha=alpha)
+            ts = time.perf_counter()
+            p, t = sbr_labels(ctx, w, rx=np.ascontiguousarray(w.rx[sel]), alpha=alpha, times=stage)
+            per_scene.append(time.perf_counter() - ts)
             pg[start + sel] = p
             tau[start + sel] = t
         start += nr
     ens.rt.synchronize()
     t2 = time.perf_counter()
+    ps = np.array(per_scene) if per_scene else np.zeros(1)
     return pg, tau, m, {"surrogate_s": t1 - t0, "fallback_s": t2 - t1, "fallback_scenes": n_fb_scenes,
-                        "fallback_rx": int(m.sum())}
+                        "fallback_rx": int(m.sum()),
+                        "fallback_scene_ms": {"p50": 1e3 * float(np.median(ps)), "max": 1e3 * float(ps.max())},
+                        "fallback_stage_s": stage}
 
 
 def gate(pg_pred: np.ndarray, pg_sbr: np.ndarray) -> dict:
@@ -555,7 +562,7 @@ class PipelineConfig:
     geodesic_N: int = 1024
     max_bounces: int = 6
     members: int = 4
-    steps: int = 3000
+    steps: int = 2000
     batch: int = 4096
     lr: float = 2e-3
     weight_decay: float = 1e-4
@@ -647,10 +654,13 @@ def run_pipeline(cfg: PipelineConfig, log=print) -> dict:
     for th in cfg.sweep_db:
         p2, _, m2, t2 = surrogate_with_fallback(ens, test, tdata, threshold_db=th, prediction=pred)
         sweep.append({"threshold_db": th, "fallback_frac": float(m2.mean()), "fallback_scenes": t2["fallback_scenes"],
+                      "fallback_scene_ms": t2["fallback_scene_ms"], "fallback_stage_s": t2["fallback_stage_s"],
                       "with_fallback_s": tm["surrogate_s"] + t2["fallback_s"],
                       "gain": t_sbr / (tm["surrogate_s"] + t2["fallback_s"]), "gate": gate(p2, pg_ref)})
         log(f"[surrogate] threshold {th} dB: {sweep[-1]}")
     res["sweep"] = sweep
+    res["fallback_scene_ms"] = tm["fallback_scene_ms"]
+    res["_ensemble"], res["_test"] = ens, test
     flops = len(ens.members) * (n * mlp_flops_per_point(arch) + len(test) * stem_flops_per_scene(arch))
     res.update({
         "n_rx": n, "n_scenes": len(test), "test_rx_with_path": int(np.isfinite(pg_ref).sum()),
