@@ -239,6 +239,7 @@ struct RebuildParams {
   float root[6];
   double cx, cy, cz;
   int has_bvh;
+  int n_big, big_off;  // oversized triangles outside the LBVH (tri32 entries big_off ..)
   // outputs (indexed by key)
   uint32_t* valid;
   double* geo;
@@ -265,7 +266,7 @@ __device__ inline bool in_triangle(const double* t, d3 x) {
 // any triangle (outside groups ga, gb) crossing the open leg a -> b at s in (1e-9, 1-1e-9)
 template <int STACK>
 __device__ bool leg_blocked(const RebuildParams& P, int32_t* stk, d3 a, d3 b, int ga, int gb) {
-  if (!P.has_bvh) return false;
+  if (!P.has_bvh && P.n_big == 0) return false;
   const d3 D = b - a;
   const d3 ac = a - mk3(P.cx, P.cy, P.cz);
   auto inv1 = [](double v) { return 1.0 / (fabs(v) > 1e-300 ? v : copysign(1e-300, v)); };
@@ -297,6 +298,9 @@ __device__ bool leg_blocked(const RebuildParams& P, int32_t* stk, d3 a, d3 b, in
     const double s = dot(e2, qv) * inv_det;
     return s > 1e-9 && s < 1.0 - 1e-9;
   };
+  for (int q = 0; q < P.n_big; ++q)
+    if (tri_block(P.big_off + q)) return true;
+  if (!P.has_bvh) return false;
   if (!box_hit(P.root[0], P.root[1], P.root[2], P.root[3], P.root[4], P.root[5])) return false;
   int sp = 0;
   int32_t node = 0;
@@ -676,7 +680,9 @@ void run_receive(sbr_paths_s* ps, hipStream_t s) {
   RP.tri32 = sc->tri32.as<float4>();
   for (int k = 0; k < 6; ++k) RP.root[k] = sc->root_host[k];
   RP.cx = sc->center[0], RP.cy = sc->center[1], RP.cz = sc->center[2];
-  RP.has_bvh = sc->T > 0;
+  RP.has_bvh = sc->n_bvh > 0;
+  RP.n_big = sc->n_big;
+  RP.big_off = (int)sc->n_bvh;
   RP.valid = valid.as<uint32_t>();
   RP.geo = geo.as<double>();
   RP.info = info.as<double>();

@@ -313,16 +313,18 @@ void face_groups(const std::vector<Plane>& pl, const float* eps, const float* si
   }
 }
 
-__global__ void k_tri_gather(const uint32_t* __restrict__ order, int64_t n, const float* __restrict__ v32,
-                             const int32_t* __restrict__ plane, const int32_t* __restrict__ group,
-                             float4* __restrict__ tri) {
+// tri[off + i] = triangle map[order ? order[i] : i] (FP32 vertices | original id, plane id, group id)
+__global__ void k_tri_gather(const uint32_t* __restrict__ order, const int32_t* __restrict__ map, int64_t n,
+                             int64_t off, const float* __restrict__ v32, const int32_t* __restrict__ plane,
+                             const int32_t* __restrict__ group, float4* __restrict__ tri) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const uint32_t t = order[i];
+  const int32_t t = map[order ? order[i] : (uint32_t)i];
   const float* v = v32 + 9 * (int64_t)t;
-  tri[3 * i] = make_float4(v[0], v[1], v[2], __int_as_float((int)t));
-  tri[3 * i + 1] = make_float4(v[3], v[4], v[5], __int_as_float(plane[t]));
-  tri[3 * i + 2] = make_float4(v[6], v[7], v[8], __int_as_float(group[t]));
+  const int64_t o = 3 * (off + i);
+  tri[o] = make_float4(v[0], v[1], v[2], __int_as_float(t));
+  tri[o + 1] = make_float4(v[3], v[4], v[5], __int_as_float(plane[t]));
+  tri[o + 2] = make_float4(v[6], v[7], v[8], __int_as_float(group[t]));
 }
 
 __global__ void k_hits_out(const int32_t* __restrict__ seq, int64_t NR, int K, int32_t* __restrict__ out) {
@@ -553,26 +555,59 @@ sbr_status sbr_scene_build(sbr_context_t ctx, const double* tri_xyz, int64_t T, 
         gpl[g] = tpl[gfirst[g]];
         gmt[g] = make_float4(er[gfirst[g]], sg[gfirst[g]], rh[gfirst[g]], 0.0f);
       }
-      // FP32 vertices centred on the scene box and their (outward rounded in the builder) boxes
-      std::vector<float> v32((size_t)T * 9), blo((size_t)T * 3), bhi((size_t)T * 3);
-      float slo[3] = {1e30f, 1e30f, 1e30f}, shi[3] = {-1e30f, -1e30f, -1e30f};
+      // Oversized triangles (box diagonal above a quarter of the scene's, at
+      // most kMaxBig, largest first) stay out of the LBVH: in a Morton-ordered
+      // tree every ancestor of such a leaf gets a box as large as the scene
+      // (a city's ground plane inflates a whole root-to-leaf chain), so
+      // nearly every ray would descend those chains.  Every ray tests them
+      // directly instead, before the traversal, which also gives the
+      // traversal an early closest-hit bound.
+      constexpr int kMaxBig = 16;
+      std::vector<std::pair<double, int32_t>> cand;
       for (int64_t t = 0; t < T; ++t) {
+        double d2 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+          const double a = tri[9 * t + k], b = tri[9 * t + 3 + k], cc = tri[9 * t + 6 + k];
+          const double e = std::max(a, std::max(b, cc)) - std::min(a, std::min(b, cc));
+          d2 += e * e;
+        }
+        if (d2 > 0.0625 * sc->diag * sc->diag) cand.push_back({d2, (int32_t)t});
+      }
+      std::sort(cand.begin(), cand.end(), [](const auto& x, const auto& y) {
+        return x.first > y.first || (x.first == y.first && x.second < y.second);
+      });
+      if (cand.size() > (size_t)kMaxBig) cand.resize(kMaxBig);
+      std::vector<int32_t> big_ids;
+      std::vector<char> is_big((size_t)T, 0);
+      for (const auto& cb : cand) big_ids.push_back(cb.second), is_big[cb.second] = 1;
+      std::sort(big_ids.begin(), big_ids.end());
+      std::vector<int32_t> bvh_ids;
+      for (int64_t t = 0; t < T; ++t)
+        if (!is_big[t]) bvh_ids.push_back((int32_t)t);
+      sc->n_big = (int)big_ids.size();
+      sc->n_bvh = (int64_t)bvh_ids.size();
+      // FP32 vertices centred on the scene box; boxes of the LBVH triangles
+      // (rounded outward in the builder)
+      std::vector<float> v32((size_t)T * 9), blo((size_t)sc->n_bvh * 3), bhi((size_t)sc->n_bvh * 3);
+      float slo[3] = {1e30f, 1e30f, 1e30f}, shi[3] = {-1e30f, -1e30f, -1e30f};
+      for (int64_t t = 0; t < T; ++t)
+        for (int k = 0; k < 3; ++k)
+          for (int v = 0; v < 3; ++v) v32[9 * t + 3 * v + k] = (float)(tri[9 * t + 3 * v + k] - sc->center[k]);
+      for (int64_t j = 0; j < sc->n_bvh; ++j) {
+        const int64_t t = bvh_ids[j];
         for (int k = 0; k < 3; ++k) {
           float mn = 1e30f, mx = -1e30f;
-          for (int v = 0; v < 3; ++v) {
-            const float x = (float)(tri[9 * t + 3 * v + k] - sc->center[k]);
-            v32[9 * t + 3 * v + k] = x;
-            mn = std::min(mn, x), mx = std::max(mx, x);
-          }
-          blo[3 * t + k] = mn, bhi[3 * t + k] = mx;
+          for (int v = 0; v < 3; ++v) mn = std::min(mn, v32[9 * t + 3 * v + k]), mx = std::max(mx, v32[9 * t + 3 * v + k]);
+          blo[3 * j + k] = mn, bhi[3 * j + k] = mx;
           slo[k] = std::min(slo[k], mn), shi[k] = std::max(shi[k], mx);
         }
       }
-      Buf dv32, dlo, dhi, order;
+      Buf dv32, dlo, dhi, order, dbvh_ids, dbig_ids;
       HostPhase hp_up("host:scene_upload");
       // staging must hold everything before the first copy is issued (it is not resized in use)
       const size_t need = tri.size() * 8 + tpl.size() * 32 + 2 * sc->h_group.size() * 4 + gpl.size() * 32 +
-                          gmt.size() * 16 + gstart.size() * 4 + gtri.size() * 4 + (v32.size() + 6 * T) * 4 + 16 * 256;
+                          gmt.size() * 16 + gstart.size() * 4 + gtri.size() * 4 + (v32.size() + 6 * T) * 4 +
+                          (size_t)T * 4 + 20 * 256;
       if (c->stage_bytes < need) {
         if (c->stage) (void)hipHostFree(c->stage);
         c->stage = nullptr;
@@ -592,18 +627,31 @@ sbr_status sbr_scene_build(sbr_context_t ctx, const double* tri_xyz, int64_t T, 
       st.put(dv32, v32.data(), v32.size(), s);
       st.put(dlo, blo.data(), blo.size(), s);
       st.put(dhi, bhi.data(), bhi.size(), s);
-      sc->nodes.alloc((size_t)std::max<int64_t>(T - 1, 1) * 64, s);
+      st.put(dbvh_ids, bvh_ids.data(), bvh_ids.size(), s);
+      st.put(dbig_ids, big_ids.data(), big_ids.size(), s);
+      sc->nodes.alloc((size_t)std::max<int64_t>(sc->n_bvh - 1, 1) * 64, s);
       sc->root_box.alloc(32, s);
-      order.alloc((size_t)T * 4, s);
-      sc->bvh_depth = build_lbvh(dlo.as<float>(), dhi.as<float>(), T, slo, shi,
-                                 BvhOut{sc->nodes.as<float4>(), order.as<uint32_t>(), sc->root_box.as<float>(),
-                                        sc->root_host}, s);
-      SBR_CHECK(sc->bvh_depth <= 64, SBR_E_UNSUPPORTED, "BVH depth %d exceeds the traversal stack", sc->bvh_depth);
       sc->tri32.alloc((size_t)T * 48, s);
-      hipLaunchKernelGGL(k_tri_gather, dim3(nblk(T, 256)), dim3(256), 0, s, order.as<uint32_t>(), T,
-                         dv32.as<float>(), sc->tplaneid.as<int32_t>(), sc->tgroup.as<int32_t>(),
-                         sc->tri32.as<float4>());
-      SBR_LAUNCH_CHECK();
+      if (sc->n_bvh > 0) {
+        order.alloc((size_t)sc->n_bvh * 4, s);
+        sc->bvh_depth = build_lbvh(dlo.as<float>(), dhi.as<float>(), sc->n_bvh, slo, shi,
+                                   BvhOut{sc->nodes.as<float4>(), order.as<uint32_t>(), sc->root_box.as<float>(),
+                                          sc->root_host}, s);
+        SBR_CHECK(sc->bvh_depth <= 64, SBR_E_UNSUPPORTED, "BVH depth %d exceeds the traversal stack",
+                  sc->bvh_depth);
+        hipLaunchKernelGGL(k_tri_gather, dim3(nblk(sc->n_bvh, 256)), dim3(256), 0, s, order.as<uint32_t>(),
+                           dbvh_ids.as<int32_t>(), sc->n_bvh, (int64_t)0, dv32.as<float>(),
+                           sc->tplaneid.as<int32_t>(), sc->tgroup.as<int32_t>(), sc->tri32.as<float4>());
+        SBR_LAUNCH_CHECK();
+      } else {
+        sc->bvh_depth = 1;
+      }
+      if (sc->n_big > 0) {
+        hipLaunchKernelGGL(k_tri_gather, dim3(1), dim3(64), 0, s, (const uint32_t*)nullptr, dbig_ids.as<int32_t>(),
+                           (int64_t)sc->n_big, sc->n_bvh, dv32.as<float>(), sc->tplaneid.as<int32_t>(),
+                           sc->tgroup.as<int32_t>(), sc->tri32.as<float4>());
+        SBR_LAUNCH_CHECK();
+      }
       SBR_HIP(hipStreamSynchronize(s));
     } catch (...) {
       release(sc);

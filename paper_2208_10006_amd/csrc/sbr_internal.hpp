@@ -166,6 +166,10 @@ struct sbr_scene_s : sbr::Handle {
   sbr_context_s* ctx = nullptr;
   int64_t T = 0;
   int n_groups = 0, n_planes = 0, bvh_depth = 0;
+  // triangles in the LBVH (leaves 0 .. n_bvh-1 of tri32) and oversized ones
+  // kept out of it (tri32 entries n_bvh .. T-1, tested by every ray directly)
+  int64_t n_bvh = 0;
+  int n_big = 0;
   double center[3] = {0, 0, 0};
   double diag = 0.0;
   float root_host[6] = {0, 0, 0, 0, 0, 0};

@@ -177,7 +177,8 @@ struct SceneDesc {
   const double* tx;
   int32_t* seq;           // [(K+1)][NR]
   float root[6];
-  int has_bvh, N, K, pad;
+  int has_bvh, N, K, n_big;
+  int big_off, pad;       // oversized triangles: tri entries big_off .. big_off + n_big - 1
   double cx, cy, cz;      // FP32 frame centre
   int64_t R, NR, ray_off; // rays per element, rays of the scene, first global ray id
 };
@@ -295,7 +296,7 @@ __global__ __launch_bounds__(256) void k_bounce(const BounceParams P) {
     // ------------------------------------------------ FP32 closest hit
     int32_t hit = -1;  // leaf (sorted) index
     float thit = INFINITY;
-    if (active && SD.has_bvh) {
+    if (active && (SD.has_bvh || SD.n_big > 0)) {
       const float4* __restrict__ nodes = SD.nodes;
       const float4* __restrict__ tri = SD.tri;
       float3 org = make_float3((float)(o.x - SD.cx), (float)(o.y - SD.cy), (float)(o.z - SD.cz));
@@ -361,8 +362,9 @@ __global__ __launch_bounds__(256) void k_bounce(const BounceParams P) {
           hit = leaf;
         }
       };
+      for (int b = 0; b < SD.n_big; ++b) tri_test(SD.big_off + b);
       float tn;
-      if (box_hit(SD.root[0], SD.root[1], SD.root[2], SD.root[3], SD.root[4], SD.root[5], INFINITY, tn)) {
+      if (SD.has_bvh && box_hit(SD.root[0], SD.root[1], SD.root[2], SD.root[3], SD.root[4], SD.root[5], thit, tn)) {
         int sp = 0;
         int32_t node = 0;
         while (true) {
@@ -442,7 +444,9 @@ __global__ __launch_bounds__(256) void k_bounce(const BounceParams P) {
 SceneDesc scene_desc(const sbr_scene_s* sc, const double* tx, int N, int K, int64_t R, int64_t NR, int32_t* seq,
                      int64_t ray_off) {
   SceneDesc D{};
-  D.has_bvh = sc->T > 0;
+  D.has_bvh = sc->n_bvh > 0;
+  D.n_big = sc->n_big;
+  D.big_off = (int)sc->n_bvh;
   D.nodes = sc->nodes.as<float4>();
   D.tri = sc->tri32.as<float4>();
   D.tplane = sc->tplane.as<double4>();
