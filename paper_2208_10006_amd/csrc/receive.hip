@@ -225,7 +225,8 @@ __global__ void k_compact_heads(const uint32_t* __restrict__ perm, const uint32_
 struct RebuildParams {
   KeyParams kp;
   const uint32_t* key_event;
-  int64_t n_keys;
+  int64_t n_keys;               // capacity of the per-key arrays (an upper bound of the key count)
+  const uint32_t* n_keys_dev;   // the key count, on the device
   int K, stride;
   const double* tx;
   const double* rx;
@@ -346,6 +347,10 @@ __global__ __launch_bounds__(128) void k_rebuild(const RebuildParams P) {
   int32_t* stk = &stack_mem[wv][0][lane];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= P.n_keys) return;
+  if (i >= (int64_t)*P.n_keys_dev) {  // slot beyond the keys: no path
+    P.valid[i] = 0u;
+    return;
+  }
   const uint32_t e = P.key_event[i];
   int32_t g[SBR_MAX_BOUNCES];
   const int k = ev_groups(P.kp, e, g);
@@ -522,18 +527,12 @@ int bits_for(uint64_t v) {
 
 }  // namespace
 
-void run_receive(sbr_paths_s* ps, hipStream_t s) {
+void run_receive(sbr_paths_s* ps, const double* hrx, hipStream_t s) {
   sbr_trace_s* tr = ps->trace;
   sbr_scene_s* sc = tr->scene;
   const int Nr = ps->Nr, Nt = tr->Nt, K = tr->K;
   // ---------------- Rx LBVH (FP32 boxes in a frame centred on the Rx bounding sphere)
   HostPhase hp_rx("host:rx_tree");
-  std::vector<double> hrx(3 * (size_t)Nr);
-  {
-    HostPhase hp("host:rx_readback");
-    SBR_HIP(hipMemcpyAsync(hrx.data(), ps->rx.p, hrx.size() * 8, hipMemcpyDeviceToHost, s));
-    SBR_HIP(hipStreamSynchronize(s));
-  }
   std::optional<HostPhase> hp_step;
   hp_step.emplace("host:rx_boxes");
   double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
@@ -649,17 +648,15 @@ void run_receive(sbr_paths_s* ps, hipStream_t s) {
                      head.as<uint32_t>()); }
   SBR_LAUNCH_CHECK();
   exclusive_scan_u32(head.as<uint32_t>(), pos.as<uint32_t>(), E, tot.as<uint32_t>(), temp.p, s);
-  uint32_t n_keys = 0;
-  SBR_HIP(hipMemcpyAsync(&n_keys, tot.p, 4, hipMemcpyDeviceToHost, s));
-  SBR_HIP(hipStreamSynchronize(s));
-  ps->n_keys = n_keys;
+  // the key count stays on the device: per-key arrays are sized by the event
+  // count (an upper bound) and the rebuild reads the count itself
   Buf key_event;
-  key_event.alloc((size_t)n_keys * 4, s);
+  key_event.alloc((size_t)E * 4, s);
   { ::sbr::TimedLaunch tl_("keys", s); hipLaunchKernelGGL(k_compact_heads, dim3(nblk(E, 256)), dim3(256), 0, s, v2.as<uint32_t>(), head.as<uint32_t>(),
                      pos.as<uint32_t>(), E, key_event.as<uint32_t>()); }
   SBR_LAUNCH_CHECK();
   // ---------------- exact rebuild + validation
-  const int64_t nk = n_keys;
+  const int64_t nk = E;
   Buf valid, geo, info, ang, key, seg;
   valid.alloc(nk * 4, s), geo.alloc(nk * stride * 8, s), info.alloc(nk * 16, s), ang.alloc(nk * 16, s);
   key.alloc(nk * (4 + K) * 4, s), seg.alloc(nk * 8, s);
@@ -667,6 +664,7 @@ void run_receive(sbr_paths_s* ps, hipStream_t s) {
   RP.kp = kp;
   RP.key_event = key_event.as<uint32_t>();
   RP.n_keys = nk;
+  RP.n_keys_dev = tot.as<uint32_t>();
   RP.K = K;
   RP.stride = stride;
   RP.tx = tr->tx.as<double>();
@@ -700,10 +698,15 @@ void run_receive(sbr_paths_s* ps, hipStream_t s) {
       { ::sbr::TimedLaunch tl_("rebuild", s); hipLaunchKernelGGL(k_rebuild<64>, dim3(g), dim3(128), 0, s, RP); }
     SBR_LAUNCH_CHECK();
   }
-  exclusive_scan_u32(valid.as<uint32_t>(), pos.as<uint32_t>(), nk, tot.as<uint32_t>(), temp.p, s);
-  uint32_t n_paths = 0;
-  SBR_HIP(hipMemcpyAsync(&n_paths, tot.p, 4, hipMemcpyDeviceToHost, s));
+  Buf tot2;
+  tot2.alloc(8, s);
+  exclusive_scan_u32(valid.as<uint32_t>(), pos.as<uint32_t>(), nk, tot2.as<uint32_t>(), temp.p, s);
+  uint32_t counts[2] = {0, 0};  // keys, paths
+  SBR_HIP(hipMemcpyAsync(&counts[0], tot.p, 4, hipMemcpyDeviceToHost, s));
+  SBR_HIP(hipMemcpyAsync(&counts[1], tot2.p, 4, hipMemcpyDeviceToHost, s));
   SBR_HIP(hipStreamSynchronize(s));
+  ps->n_keys = counts[0];
+  const uint32_t n_paths = counts[1];
   ps->n_paths = n_paths;
   const int64_t np = n_paths;
   ps->geo.alloc(std::max<int64_t>(np, 1) * stride * 8, s);
@@ -737,7 +740,8 @@ void run_receive(sbr_paths_s* ps, hipStream_t s) {
   { ::sbr::TimedLaunch tl_("order", s); hipLaunchKernelGGL(k_seg_start, dim3(nblk(nseg + 1, 256)), dim3(256), 0, s, fseg.as<uint64_t>(), np, nseg,
                      ps->seg_start.as<int32_t>()); }
   SBR_LAUNCH_CHECK();
-  SBR_HIP(hipStreamSynchronize(s));
+  // no final synchronisation: the path arrays are written in stream order and
+  // the temporaries are released in stream order
 }
 
 }  // namespace sbr

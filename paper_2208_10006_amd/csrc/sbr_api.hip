@@ -652,7 +652,10 @@ sbr_status sbr_scene_build(sbr_context_t ctx, const double* tri_xyz, int64_t T, 
                            sc->tgroup.as<int32_t>(), sc->tri32.as<float4>());
         SBR_LAUNCH_CHECK();
       }
-      SBR_HIP(hipStreamSynchronize(s));
+      // The staged copies were consumed before the LBVH depth readback synchronised
+      // the stream (without a tree, synchronise here so the staging area is free);
+      // the leaf gather runs in stream order before any trace of this scene.
+      if (sc->n_bvh == 0) SBR_HIP(hipStreamSynchronize(s));
     } catch (...) {
       release(sc);
       throw;
@@ -701,7 +704,9 @@ sbr_status sbr_trace(sbr_context_t ctx, sbr_scene_t scene, const double* tx_xyz,
     try {
       tr->Nt = Nt, tr->N = N, tr->K = K, tr->R = R, tr->NR = (int64_t)Nt * R;
       tr->h_tx = htx;
-      upload(tr->tx, tr->h_tx.data(), tr->h_tx.size(), 0, s);
+      // a device-resident input is copied on the device (no second host round trip)
+      if (flags & SBR_IN_DEVICE) upload(tr->tx, tx_xyz, tr->h_tx.size(), flags, s);
+      else upload(tr->tx, tr->h_tx.data(), tr->h_tx.size(), 0, s);
       tr->seq.alloc((size_t)(K + 1) * tr->NR * 4, s);
       tr->counters.alloc((size_t)trace_counter_words(K) * 4, s);
       void* ra = c->scratch_get(0, trace_ray_bytes(tr->NR), s);
@@ -889,8 +894,9 @@ sbr_status sbr_receive(sbr_context_t ctx, sbr_trace_t t, const double* rx_xyz, i
       ps->Nr = Nr;
       ps->coeff = radius_coeff;
       ps->alpha = alpha_rad > 0 ? alpha_rad : alpha_for(c, tr->N);
-      upload(ps->rx, hrx.data(), hrx.size(), 0, s);
-      run_receive(ps, s);
+      if (flags & SBR_IN_DEVICE) upload(ps->rx, rx_xyz, hrx.size(), flags, s);
+      else upload(ps->rx, hrx.data(), hrx.size(), 0, s);
+      run_receive(ps, hrx.data(), s);
     } catch (...) {
       release(ps);
       throw;

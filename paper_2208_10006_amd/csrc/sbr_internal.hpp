@@ -281,7 +281,7 @@ size_t trace_ray_bytes(int64_t NR);
 int64_t trace_counter_words(int K);
 
 // receive.hip
-void run_receive(sbr_paths_s* ps, hipStream_t s);
+void run_receive(sbr_paths_s* ps, const double* hrx, hipStream_t s);  // hrx: host copy of the Rx points
 
 // channel.hip
 struct ChannelArgs {
