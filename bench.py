@@ -43,6 +43,8 @@ def make_inputs(w, torch, dev):
     }
     Nf, Nr, Nt = len(w.freq), len(w.rx), len(w.tx)
     d["H"] = torch.empty((Nf, Nr, Nt), dtype=torch.complex64, device=dev)
+    # MIMO capacity (eq. 15-17) at SNR 0, 5, ..., 30 dB when both ends are arrays
+    d["snr"] = t(list(range(0, 31, 5)), torch.float64) if Nr > 1 and Nt > 1 else None
     d["pg"] = torch.empty((Nr, Nt), dtype=torch.float32, device=dev)
     d["tau"] = torch.empty((Nr, Nt), dtype=torch.float32, device=dev)
     d["ang"] = torch.empty((Nr, Nt, 4), dtype=torch.float32, device=dev)
@@ -54,6 +56,8 @@ def step(S, ctx, w, d):
     tr = S.sbr_trace(ctx, sc, d["tx"], w.geodesic_N, w.max_bounces)
     ps = S.sbr_receive(ctx, tr, d["rx"], 0.0, w.radius_coeff)
     S.sbr_channel(ctx, ps, d["freq"], d["atm"], None, S.SBR_POL_V, S.SBR_POL_V, H_c64=d["H"])
+    if d.get("snr") is not None:
+        d["capacity"] = S.sbr_capacity(ctx, d["H"], d["snr"])
     S.sbr_stats_device(ps, d["pg"], d["tau"], d["ang"])
     return sc, tr, ps
 
@@ -71,6 +75,17 @@ def committed_traffic(workload):
         if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
             return None
     return (rec["fetch_bytes_per_step"] + rec["write_bytes_per_step"]) / rec["launches_per_step"]
+
+
+def describe(w):
+    rays = 10 * w.geodesic_N ** 2 + 2
+    f0, f1 = float(w.freq.min()) / 1e9, float(w.freq.max()) / 1e9
+    head = {"urban_canyon": f"500x500 m ground + 200 boxes ({w.T} tri), 1 Tx at 25 m, {len(w.rx)} Rx at 1.5 m",
+            "massive_mimo_office": f"30x20x3 m office hall, 208 desks + 208 partitions ({w.T} tri), "
+                                   f"{len(w.tx)}-element Tx UPA and {len(w.rx)}-element Rx UPA at lambda/2",
+            "tiny_room": f"10x8x3 m room ({w.T} tri), 1 Tx, 1 Rx"}.get(w.name, f"{w.T} triangles, {len(w.tx)} Tx, {len(w.rx)} Rx")
+    return (f"{w.name}: {head}, N={w.geodesic_N} ({rays} rays per Tx element), K={w.max_bounces}, "
+            f"{len(w.freq)} subcarriers over {f0:.3f}-{f1:.3f} GHz")
 
 
 def cpu_baseline(w, target_s=15.0):
@@ -321,10 +336,10 @@ def main():
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32 traversal / f64 ray state, phase and H",
            "data": "synthetic",
-           "config": {"workload": f"{w.name}: 500x500 m ground + 200 boxes ({w.T} tri), 1 Tx at 25 m, "
-                                  f"{len(w.rx)} Rx, N={w.geodesic_N} ({10 * w.geodesic_N ** 2 + 2} rays), "
-                                  f"K={w.max_bounces}, {len(w.freq)} subcarriers at 300 GHz",
-                      "segments_per_step": segments, "paths": pinfo["paths"], "capture_events": pinfo["events"]},
+           "config": {"workload": describe(w),
+                      "segments_per_step": segments, "paths": pinfo["paths"], "capture_events": pinfo["events"],
+                      "capacity_bits_per_hz_snr_0_to_30_db": [round(float(v), 4) for v in d["capacity"]]
+                      if d.get("capacity") is not None else None},
            "kernels": kernels, "roofline": roofline, "tuning": tuned["config"]}
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle on a sample) ...")
