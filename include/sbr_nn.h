@@ -53,6 +53,19 @@ sbr_status sbr_nn_fourier(sbr_context_t ctx, const float* x, int64_t n, int32_t 
 sbr_status sbr_nn_link_features(sbr_context_t ctx, const float* raw, int64_t n, const int32_t* scene,
                                 const void* hmap, int32_t H, float half_extent_m, int32_t samples, float* x,
                                 float* extra);
+/* Fused inference of one member's point MLP for n points, all hidden layers
+ * kept on chip: row i of the first layer's input is
+ * [emb[scene[i]][0..128) | shared[i][0..128)] (bf16), each hidden layer
+ * l < depth computes ReLU(x W_l + bias[l]) with W_l given transposed in
+ * wt[l][256 out][256 in] (bf16) and bias[l][256] (FP32), rounded to bf16
+ * like sbr_nn_gemm_bf16 with SBR_NN_RELU | SBR_NN_OUT_BF16; then
+ * out[i][t] = sum_k x[k] out_w[k][t] + out_b[t] (out_w bf16 [256][T], FP32
+ * sums), t < T.  shared, emb and wt must be 16-byte aligned. */
+sbr_status sbr_nn_mlp_infer(sbr_context_t ctx, int64_t n, const void* shared, const void* emb,
+                            const int32_t* scene, const void* wt, const float* bias, int32_t depth, const void* out_w,
+                            const float* out_b, int32_t T, float* out);
+/* dst[c][r] = src[r][c] for a bf16 matrix src[rows][cols] (dst != src) */
+sbr_status sbr_nn_transpose_bf16(sbr_context_t ctx, const void* src, int32_t rows, int32_t cols, void* dst);
 /* gout / gbf (either may be NULL) = g * (y > 0), y bf16 */
 sbr_status sbr_nn_relu_backward(sbr_context_t ctx, const float* g, const void* y, int64_t n, float* gout, void* gbf);
 sbr_status sbr_nn_cast_bf16(sbr_context_t ctx, const float* a, int64_t n, void* b);

@@ -193,6 +193,95 @@ __global__ void k_gemm_reduce(GemmArgs g, int splits) {
   epilogue_store(g, (int)(e / g.N), (int)(e % g.N), s);
 }
 
+// ---------------------------------------------------------------- fused MLP inference
+// All hidden layers of one ensemble member for a block of kMlpBM points, the
+// activations kept in LDS between layers (HBM sees only the inputs and the
+// outputs).  Layer l: act <- ReLU(act W_l + b_l) in BF16 with FP32
+// accumulation on v_mfma_f32_16x16x32_bf16; wave w owns output columns
+// [64w, 64w + 64) for all kMlpBM rows (6 x 4 MFMA tiles, 96 accumulator
+// registers); after a barrier the results overwrite the same LDS rows.  The
+// weights are read as k-contiguous 16-byte fragments from a transposed copy
+// ([out][in], L2-resident: 128 KB per layer).  Input row = [emb(scene) (128) |
+// shared features (128)]; output layer 256 -> T by FMA (FP32 accumulation of
+// BF16 products), like the unfused path.
+constexpr int kMlpW = 256, kMlpBM = 96, kMlpLd = kMlpW + 8;  // padded LDS row (528 B)
+
+__global__ __launch_bounds__(256) void k_mlp_fused(int64_t n, const __bf16* __restrict__ shared,
+                                                   const __bf16* __restrict__ emb, const int32_t* __restrict__ scene,
+                                                   const __bf16* __restrict__ wt, const float* __restrict__ bias,
+                                                   int depth, const __bf16* __restrict__ out_w,
+                                                   const float* __restrict__ out_b, int T, float* __restrict__ out) {
+  __shared__ __bf16 act[kMlpBM][kMlpLd];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * kMlpBM;
+  // ---- input rows: 32 chunks of 8 bf16 per row (16 embedding, 16 shared)
+  for (int q = tid; q < kMlpBM * 32; q += 256) {
+    const int r = q >> 5, c = q & 31;
+    const int64_t row = r0 + r;
+    bf16x8 v;
+    if (row < n) {
+      v = c < 16 ? *reinterpret_cast<const bf16x8*>(emb + (int64_t)scene[row] * 128 + c * 8)
+                 : *reinterpret_cast<const bf16x8*>(shared + row * 128 + (c - 16) * 8);
+    } else {
+      for (int t = 0; t < 8; ++t) v[t] = f2bf(0.0f);
+    }
+    *reinterpret_cast<bf16x8*>(&act[r][c * 8]) = v;
+  }
+  __syncthreads();
+  const int fr = lane & 15, fk = (lane >> 4) * 8;
+  constexpr int RT = kMlpBM / 16;
+  for (int l = 0; l < depth; ++l) {
+    const __bf16* W = wt + (int64_t)l * kMlpW * kMlpW;
+    f32x4 acc[RT][4];
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[r][c] = f32x4{0, 0, 0, 0};
+    for (int k0 = 0; k0 < kMlpW; k0 += 32) {
+      bf16x8 bfr[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        bfr[c] = *reinterpret_cast<const bf16x8*>(W + (int64_t)(wv * 64 + c * 16 + fr) * kMlpW + k0 + fk);
+#pragma unroll
+      for (int r = 0; r < RT; ++r) {
+        const bf16x8 afr = *reinterpret_cast<const bf16x8*>(&act[r * 16 + fr][k0 + fk]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr, bfr[c], acc[r][c], 0, 0, 0);
+      }
+    }
+    __syncthreads();  // every wave has read this layer's input
+    const float* b = bias + (int64_t)l * kMlpW;
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int col = wv * 64 + c * 16 + fr;
+        const float bj = b[col];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) act[r * 16 + (lane >> 4) * 4 + q][col] = f2bf(fmaxf(acc[r][c][q] + bj, 0.0f));
+      }
+    __syncthreads();
+  }
+  // ---- output layer: one (row, output) dot product per thread
+  for (int q = tid; q < kMlpBM * T; q += 256) {
+    const int r = q / T, o = q - r * T;
+    const int64_t row = r0 + r;
+    if (row >= n) continue;
+    float sum = 0.0f;
+    for (int k = 0; k < kMlpW; ++k) sum = fmaf(bf2f(act[r][k]), bf2f(out_w[k * T + o]), sum);
+    out[row * T + o] = sum + out_b[o];
+  }
+}
+
+// dst[c][r] = src[r][c] for a [rows][cols] bf16 matrix
+__global__ void k_transpose_bf16(const __bf16* __restrict__ src, int rows, int cols, __bf16* __restrict__ dst) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)rows * cols) return;
+  const int r = (int)(e / cols), c = (int)(e - (int64_t)r * cols);
+  dst[(int64_t)c * rows + r] = src[e];
+}
+
 // ---------------------------------------------------------------- conv helpers
 // x: [n][H][W][C] bf16 (channels last); col: [n*Ho*Wo][9*C] bf16, column index
 // (ky*3 + kx)*C + c; 3x3 window, stride 2, zero padding 1; Ho = H/2.
@@ -511,6 +600,22 @@ void nn_gemm(int M, int N, int K, const void* A, int64_t a_si, int64_t a_sk, con
     const int64_t mn = (int64_t)M * N;
     hipLaunchKernelGGL(k_gemm_reduce, dim3(nblk(mn, 256)), dim3(256), 0, s, g, splits);
   }
+  SBR_LAUNCH_CHECK();
+}
+void nn_mlp_fused(int64_t n, const void* shared, const void* emb, const int32_t* scene, const void* wt,
+                  const float* bias, int depth, const void* out_w, const float* out_b, int T, float* out,
+                  hipStream_t s) {
+  if (n <= 0) return;
+  ::sbr::TimedLaunch tl_("nn_mlp", s);
+  hipLaunchKernelGGL(k_mlp_fused, dim3(nblk(n, kMlpBM)), dim3(256), 0, s, n, static_cast<const __bf16*>(shared),
+                     static_cast<const __bf16*>(emb), scene, static_cast<const __bf16*>(wt), bias, depth,
+                     static_cast<const __bf16*>(out_w), out_b, T, out);
+  SBR_LAUNCH_CHECK();
+}
+void nn_transpose(const void* src, int rows, int cols, void* dst, hipStream_t s) {
+  ::sbr::TimedLaunch tl_("nn_elem", s);
+  hipLaunchKernelGGL(k_transpose_bf16, dim3(nblk((int64_t)rows * cols, 256)), dim3(256), 0, s,
+                     static_cast<const __bf16*>(src), rows, cols, static_cast<__bf16*>(dst));
   SBR_LAUNCH_CHECK();
 }
 void nn_im2col(const void* x, int n, int H, int W, int C, void* col, hipStream_t s) {

@@ -53,6 +53,26 @@ sbr_status sbr_nn_fourier(sbr_context_t ctx, const float* x, int64_t n, int32_t 
   });
 }
 
+sbr_status sbr_nn_mlp_infer(sbr_context_t ctx, int64_t n, const void* shared, const void* emb,
+                            const int32_t* scene, const void* wt, const float* bias, int32_t depth, const void* out_w,
+                            const float* out_b, int32_t T, float* out) {
+  NN_ENTRY({
+    NN_REQUIRE(n >= 0 && depth >= 1 && depth <= 64 && T >= 1 && T <= 64, "mlp_infer sizes");
+    NN_REQUIRE(n == 0 || (shared && emb && scene && wt && bias && out_w && out_b && out), "mlp_infer arguments");
+    NN_REQUIRE(n == 0 || ((reinterpret_cast<uintptr_t>(shared) | reinterpret_cast<uintptr_t>(emb) |
+                           reinterpret_cast<uintptr_t>(wt)) & 15) == 0,
+               "mlp_infer: shared, emb and wt must be 16-byte aligned");
+    nn_mlp_fused(n, shared, emb, scene, wt, bias, depth, out_w, out_b, T, out, s);
+  });
+}
+
+sbr_status sbr_nn_transpose_bf16(sbr_context_t ctx, const void* src, int32_t rows, int32_t cols, void* dst) {
+  NN_ENTRY({
+    NN_REQUIRE(src && dst && rows >= 0 && cols >= 0 && src != dst, "transpose arguments");
+    if ((int64_t)rows * cols > 0) nn_transpose(src, rows, cols, dst, s);
+  });
+}
+
 sbr_status sbr_nn_link_features(sbr_context_t ctx, const float* raw, int64_t n, const int32_t* scene,
                                 const void* hmap, int32_t H, float half_extent_m, int32_t samples, float* x,
                                 float* extra) {

@@ -303,6 +303,10 @@ void nn_im2col(const void* x, int n, int H, int W, int C, void* col, hipStream_t
 void nn_col2im(const float* dcol, int n, int H, int W, int C, float* dx, hipStream_t s);
 void nn_fourier(const float* x, int64_t n, int D, int L, const void* emb, int E, const int32_t* scene,
                 const float* extra, int X, int F, void* out, hipStream_t s);
+void nn_mlp_fused(int64_t n, const void* shared, const void* emb, const int32_t* scene, const void* wt,
+                  const float* bias, int depth, const void* out_w, const float* out_b, int T, float* out,
+                  hipStream_t s);
+void nn_transpose(const void* src, int rows, int cols, void* dst, hipStream_t s);
 void nn_link_features(const float* raw, int64_t n, const int32_t* scene, const void* hmap, int H, float half,
                       int samples, float* x, float* extra, hipStream_t s);
 void nn_relu_bwd(const float* g, const void* y, int64_t n, float* gout, void* gbf, hipStream_t s);

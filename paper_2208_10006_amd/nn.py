@@ -26,6 +26,8 @@ _SIG = {
     "sbr_nn_ensemble": [P, P, I32, I64, I64, I64, I32, F, P, P, P],
     "sbr_nn_gather_rows": [P, P, I64, P, I64, P],
     "sbr_nn_onehot_bf16": [P, P, I64, I32, P],
+    "sbr_nn_mlp_infer": [P, I64, P, P, P, P, P, I32, P, P, I32, P],
+    "sbr_nn_transpose_bf16": [P, P, I32, I32, P],
 }
 for _n, _a in _SIG.items():
     _f = getattr(L, _n)
@@ -94,3 +96,12 @@ def sbr_nn_gather_rows(ctx, src, row_bytes, idx, n, dst):
 
 def sbr_nn_onehot_bf16(ctx, idx, n, width, out):
     S._call("sbr_nn_onehot_bf16", ctx.h, _p(idx), n, width, _p(out))
+
+
+def sbr_nn_mlp_infer(ctx, n, shared, emb, scene, wt, bias, depth, out_w, out_b, T, out):
+    S._call("sbr_nn_mlp_infer", ctx.h, n, _p(shared), _p(emb), _p(scene), _p(wt), _p(bias), depth, _p(out_w),
+            _p(out_b), T, _p(out))
+
+
+def sbr_nn_transpose_bf16(ctx, src, rows, cols, dst):
+    S._call("sbr_nn_transpose_bf16", ctx.h, _p(src), rows, cols, _p(dst))

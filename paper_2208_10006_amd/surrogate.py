@@ -461,28 +461,51 @@ class Ensemble:
 
     # -- inference
     def predict(self, hmap: torch.Tensor, x: torch.Tensor, extra: torch.Tensor, scene: torch.Tensor,
-                chunk: int = 1 << 18, threshold_db: float = 1.0):
+                chunk: int = 1 << 18, threshold_db: float = 1.0, fused: Optional[bool] = None):
         """Ensemble over all members for n points: (mean out [n][T], PG spread dB [n],
-        fallback mask [n] uint8), device tensors, complete on return."""
+        fallback mask [n] uint8), device tensors, complete on return.  fused:
+        all hidden layers of a member in one kernel (default when the
+        architecture has the 256-wide shape it supports) or layer by layer."""
         with self.rt:
-            res = self._predict(hmap, x, extra, scene, chunk, threshold_db)
+            res = self._predict(hmap, x, extra, scene, chunk, threshold_db, fused)
         self.rt.synchronize()
         return res
 
-    def _predict(self, hmap, x, extra, scene, chunk, threshold_db):
+    def fused_ok(self) -> bool:
+        a = self.arch
+        return a.width == 256 and a.F == 256 and a.E == 128 and a.D + 2 * a.D * a.L + a.X <= 128
+
+    def _predict(self, hmap, x, extra, scene, chunk, threshold_db, fused=None):
         ctx, a = self.ctx, self.arch
         n = int(x.shape[0])
         Sn = int(hmap.shape[0])
         E = len(self.members)
         outs = torch.empty((E, n, a.T), dtype=F32, device="cuda")
-        chunk = min(chunk, n)
-        ws = self.workspace(Sn, chunk, False)
-        for mi, mem in enumerate(self.members):
-            stem_forward(mem, ws, hmap)
-            for s in range(0, n, chunk):
-                m = min(chunk, n - s)
-                mlp_forward(mem, ws, x[s:s + m], scene[s:s + m], m, outs[mi, s:s + m], keep=False,
-                            extra=extra[s:s + m])
+        fused = self.fused_ok() if fused is None else fused
+        if fused:
+            # member-independent input columns once, then all hidden layers of
+            # each member in one kernel (activations stay on chip)
+            ws = self.workspace(Sn, 1, False)
+            shared = torch.empty((n, 128), dtype=BF16, device="cuda")
+            K.sbr_nn_fourier(ctx, x, n, a.D, a.L, None, 0, None, 128, shared, extra, a.X)
+            wt = torch.empty((a.depth, a.width, a.width), dtype=BF16, device="cuda")
+            bias = torch.empty((a.depth, a.width), dtype=F32, device="cuda")
+            for mi, mem in enumerate(self.members):
+                stem_forward(mem, ws, hmap)
+                for i in range(a.depth):
+                    K.sbr_nn_transpose_bf16(ctx, mem.view(mem.wbf, f"mlp{i}_w"), a.width, a.width, wt[i])
+                    bias[i].copy_(mem.view(mem.w32, f"mlp{i}_b"))
+                K.sbr_nn_mlp_infer(ctx, n, shared, ws.emb, scene, wt, bias, a.depth, mem.view(mem.wbf, "out_w"),
+                                   mem.view(mem.w32, "out_b"), a.T, outs[mi])
+        else:
+            chunk = min(chunk, n)
+            ws = self.workspace(Sn, chunk, False)
+            for mi, mem in enumerate(self.members):
+                stem_forward(mem, ws, hmap)
+                for s in range(0, n, chunk):
+                    m = min(chunk, n - s)
+                    mlp_forward(mem, ws, x[s:s + m], scene[s:s + m], m, outs[mi, s:s + m], keep=False,
+                                extra=extra[s:s + m])
         mean = torch.empty((n, a.T), dtype=F32, device="cuda")
         spread = torch.empty(n, dtype=F32, device="cuda")
         mask = torch.empty(n, dtype=torch.uint8, device="cuda")
@@ -642,7 +665,15 @@ def run_pipeline(cfg: PipelineConfig, log=print) -> dict:
     t = time.perf_counter()
     ens.predict(tdata.hmap, tdata.x, tdata.extra, tdata.scene, threshold_db=cfg.threshold_db)
     t_inf = time.perf_counter() - t
-    gemm_ms, gemm_n = S.sbr_profile_query(rt.ctx, "nn_gemm")
+    mlp_ms, mlp_n = S.sbr_profile_query(rt.ctx, "nn_mlp")
+    stem_ms, _ = S.sbr_profile_query(rt.ctx, "nn_gemm")
+    S.sbr_profile_enable(rt.ctx, False)
+    # the layer-by-layer path on the same points, for comparison
+    S.sbr_profile_enable(rt.ctx, True)
+    t = time.perf_counter()
+    ens.predict(tdata.hmap, tdata.x, tdata.extra, tdata.scene, threshold_db=cfg.threshold_db, fused=False)
+    t_unf = time.perf_counter() - t
+    unf_ms, _ = S.sbr_profile_query(rt.ctx, "nn_gemm")
     S.sbr_profile_enable(rt.ctx, False)
     pg, tau, mask, tm = surrogate_with_fallback(ens, test, tdata, threshold_db=cfg.threshold_db)
     t_sur = tm["surrogate_s"] + tm["fallback_s"]
@@ -661,7 +692,8 @@ def run_pipeline(cfg: PipelineConfig, log=print) -> dict:
     res["sweep"] = sweep
     res["fallback_scene_ms"] = tm["fallback_scene_ms"]
     res["_ensemble"], res["_test"] = ens, test
-    flops = len(ens.members) * (n * mlp_flops_per_point(arch) + len(test) * stem_flops_per_scene(arch))
+    mlp_flops = len(ens.members) * n * mlp_flops_per_point(arch)
+    flops = mlp_flops + len(ens.members) * len(test) * stem_flops_per_scene(arch)
     res.update({
         "n_rx": n, "n_scenes": len(test), "test_rx_with_path": int(np.isfinite(pg_ref).sum()),
         "sbr_s": t_sbr, "sbr_rx_per_s": n / t_sbr,
@@ -669,8 +701,10 @@ def run_pipeline(cfg: PipelineConfig, log=print) -> dict:
         "surrogate_s": tm["surrogate_s"], "fallback_s": tm["fallback_s"], "fallback_scenes": tm["fallback_scenes"],
         "fallback_frac": float(mask.mean()), "with_fallback_s": t_sur, "with_fallback_rx_per_s": n / t_sur,
         "gain": t_sbr / t_sur, "gate": g,
-        "inference_flops": flops, "gemm_ms": gemm_ms, "gemm_launches": gemm_n,
-        "gemm_tflops": flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else None,
+        "inference_flops": flops, "mlp_flops": mlp_flops, "mlp_ms": mlp_ms, "mlp_launches": mlp_n,
+        "mlp_tflops": mlp_flops / (mlp_ms * 1e-3) / 1e12 if mlp_ms > 0 else None, "stem_gemm_ms": stem_ms,
+        "unfused_s": t_unf, "unfused_gemm_ms": unf_ms,
+        "unfused_gemm_tflops": flops / (unf_ms * 1e-3) / 1e12 if unf_ms > 0 else None,
     })
     # error of the surrogate alone on the Rx it kept (the fallback ones carry SBR values)
     res["kept_gate"] = gate(pg[~mask], pg_ref[~mask])

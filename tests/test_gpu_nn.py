@@ -284,3 +284,51 @@ def test_mse_adam_ensemble(env):
     assert np.allclose(host(spread), sd, rtol=1e-5, atol=1e-6)
     far = np.abs(sd - 1.0) > 1e-5
     assert np.array_equal(host(mask)[far].astype(bool), (sd > 1.0)[far])
+
+
+def test_transpose_bf16(env):
+    torch, S, nn, ctx = env
+    banner("transpose")
+    rng = np.random.default_rng(8)
+    a = R.bf16(rng.standard_normal((37, 300)))
+    out = torch.empty((300, 37), dtype=torch.bfloat16, device="cuda")
+    nn.sbr_nn_transpose_bf16(ctx, dev(torch, a, torch.bfloat16), 37, 300, out)
+    sync(torch)
+    assert np.array_equal(host(out), a.T)
+
+
+@pytest.mark.parametrize("n", [1, 95, 96, 1000, 20011])
+def test_mlp_fused_exact(env, n):
+    """Fused inference against the plain definition, on values where every
+    sum is exact in FP32 and every layer output is a bfloat16 number: inputs
+    on a 2^-6 grid in [-2, 2], eight non-zero weights of +-1/8 per output
+    column, biases on the 2^-6 grid in [-1/4, 0], output weights on a 2^-3
+    grid.  Then GPU and reference must agree bit for bit."""
+    torch, S, nn, ctx = env
+    banner("mlp fused exact", n)
+    rng = np.random.default_rng(n)
+    Sn, depth, T = 5, 6, 2
+    emb = rng.integers(-127, 128, (Sn, 128)) / 64.0
+    shared = rng.integers(-127, 128, (n, 128)) / 64.0
+    scene = rng.integers(0, Sn, n).astype(np.int32)
+    W = np.zeros((depth, 256, 256))
+    for l in range(depth):
+        for j in range(256):
+            rows = rng.choice(256, 8, replace=False)
+            W[l, rows, j] = rng.choice([-0.125, 0.125], 8)
+    b = -rng.integers(0, 17, (depth, 256)) / 64.0
+    ow = rng.integers(-8, 9, (256, T)) / 8.0
+    ob = rng.standard_normal(T).astype(np.float32)
+    # reference: the definition, in FP64 (exact here), bf16 rounding between layers
+    h = np.concatenate([emb[scene], shared], axis=1)
+    for l in range(depth):
+        h = R.bf16(np.maximum(h @ W[l] + b[l], 0.0))
+    ref = h @ ow + ob.astype(np.float64)
+    wt = np.ascontiguousarray(np.transpose(W, (0, 2, 1)))
+    out = torch.empty((n, T), dtype=torch.float32, device="cuda")
+    nn.sbr_nn_mlp_infer(ctx, n, dev(torch, shared, torch.bfloat16), dev(torch, emb, torch.bfloat16),
+                        dev(torch, scene, torch.int32), dev(torch, wt, torch.bfloat16),
+                        dev(torch, b, torch.float32), depth, dev(torch, ow, torch.bfloat16),
+                        dev(torch, ob, torch.float32), T, out)
+    sync(torch)
+    assert np.array_equal(host(out), ref.astype(np.float32))

@@ -328,3 +328,30 @@ def test_fallback_gain_over_plain_sbr(env):
     # flagged points carry the SBR values themselves
     assert np.array_equal(pg[mask][np.isfinite(pg_ref[mask])], pg_ref[mask][np.isfinite(pg_ref[mask])])
     assert g["n"] > 0
+
+
+def test_fused_inference_matches_layer_by_layer(env):
+    """The fused kernel and the layer-by-layer GEMMs compute the same network;
+    they differ only in FP32 summation order inside the matrix cores, i.e. in
+    rare one-unit bfloat16 roundings of hidden activations (the layer-by-layer
+    path is pinned to the reference layer by layer).  Bound: 1e-2 of the
+    largest output, on random weights and inputs."""
+    torch, S, G, rt = env
+    banner("fused vs layer-by-layer inference")
+    arch = G.Arch()
+    rng = np.random.default_rng(21)
+    Sn, n = 3, 5000
+    ens = G.Ensemble(arch, rt, members=2, seed=4)
+    cu = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(dt).cuda()  # noqa: E731
+    with rt:
+        hm = cu(rng.random((Sn, 128, 128)) * 0.5, torch.bfloat16)
+        x = cu(rng.uniform(-1, 1, (n, 7)), torch.float32)
+        ex = cu(rng.normal(size=(n, 3)), torch.float32)
+        sc = cu(rng.integers(0, Sn, n), torch.int32)
+    a, sa, _ = ens.predict(hm, x, ex, sc, fused=True)
+    b, sb, _ = ens.predict(hm, x, ex, sc, fused=False)
+    a, b = a.cpu().numpy(), b.cpu().numpy()
+    err = float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+    print("fused vs layer-by-layer: max rel", err, flush=True)
+    assert err <= 1e-2
+    assert np.allclose(sa.cpu().numpy(), sb.cpu().numpy(), atol=0.05 * 20)
