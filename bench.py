@@ -164,6 +164,13 @@ def batched_main(args):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     bounce_ms, _ = S.sbr_profile_query(ctx, "bounce")
+    kernels = {}
+    for name in ["bounce", "replay_capture", "rebuild", "channel", "keys", "sort", "scan", "order", "lbvh", "stats",
+                 "misc", "host:scene_build", "host:scene_inputs", "host:face_groups", "host:scene_upload",
+                 "host:rx_tree"]:
+        ms, n = S.sbr_profile_query(ctx, name)
+        if n:
+            kernels[name] = {"ms_per_step": ms / args.steps, "launches_per_step": n / args.steps}
     lat = np.array(lat)
     out = {"metric": "traced ray-segments/s (batched uneven scenes)", "value": segs * args.steps / (t1 - t0),
            "unit": "ray-segments/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -174,7 +181,8 @@ def batched_main(args):
                       "segments_per_step": segs, "bounce_ms_per_step": bounce_ms / args.steps,
                       "trace_segments_per_s": segs / (bounce_ms / args.steps * 1e-3),
                       "scene_latency_ms": {"p50": float(np.percentile(lat, 50)), "p90": float(np.percentile(lat, 90)),
-                                           "p99": float(np.percentile(lat, 99)), "max": float(lat.max())}}}
+                                           "p99": float(np.percentile(lat, 99)), "max": float(lat.max())}},
+           "kernels": kernels}
     print(json.dumps(out), flush=True)
 
 

@@ -1,6 +1,7 @@
 // sbr_api.hip -- the C-ABI of libsbr: handles, validation, host-side face
 // grouping, buffer management and the order of kernel launches.
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -264,12 +265,57 @@ void face_groups(const std::vector<Plane>& pl, const float* eps, const float* si
     cn[t] = Canon{{sgn * n[0], sgn * n[1], sgn * n[2], sgn * pl[t].c}, std::fabs(n[imax]) - second < 4 * tol_n};
   }
   auto cell = [&](const double* v, int k) { return (int64_t)std::floor(v[k] / (k < 3 ? hn : hc)); };
-  std::unordered_map<Key4, std::vector<int>, Key4Hash> grid;
-  grid.reserve(T * 2 + 1);
-  for (int t = 0; t < T; ++t) grid[Key4{cell(cn[t].v, 0), cell(cn[t].v, 1), cell(cn[t].v, 2), cell(cn[t].v, 3)}].push_back(t);
+  // Triangles whose canonical (n, c) are bitwise equal form one class (many
+  // box bottoms lie exactly on a floor): they are joined directly, and only
+  // one representative per class enters the pairwise tolerance tests, which
+  // gives the same transitive closure as testing every pair.  Within a
+  // class, members of equal material are joined into one group; across
+  // classes, the per-material representatives of matching materials are.
+  auto bits = [](double x) {
+    int64_t b;
+    std::memcpy(&b, &x, 8);
+    return b;
+  };
   std::vector<int> pp(T), pg(T);
   for (int t = 0; t < T; ++t) pp[t] = pg[t] = t;
-  for (int a = 0; a < T; ++a) {
+  struct Class {
+    int rep;
+    std::vector<std::pair<std::array<float, 3>, int>> mats;  // material -> representative triangle
+  };
+  std::vector<Class> classes;
+  {
+    std::unordered_map<Key4, int, Key4Hash> cls;
+    cls.reserve(T * 2 + 1);
+    for (int t = 0; t < T; ++t) {
+      const Key4 k{bits(cn[t].v[0]), bits(cn[t].v[1]), bits(cn[t].v[2]), bits(cn[t].v[3])};
+      auto it = cls.find(k);
+      const std::array<float, 3> m{eps[t], sig[t], rough[t]};
+      if (it == cls.end()) {
+        cls.emplace(k, (int)classes.size());
+        classes.push_back(Class{t, {{m, t}}});
+        continue;
+      }
+      Class& C = classes[it->second];
+      uf_join(pp, C.rep, t);
+      bool found = false;
+      for (auto& mt : C.mats)
+        if (mt.first == m) {
+          uf_join(pg, mt.second, t);
+          found = true;
+          break;
+        }
+      if (!found) C.mats.push_back({m, t});
+    }
+  }
+  const int NC = (int)classes.size();
+  std::unordered_map<Key4, std::vector<int>, Key4Hash> grid;  // cell -> classes
+  grid.reserve(NC * 2 + 1);
+  for (int q = 0; q < NC; ++q) {
+    const double* v = cn[classes[q].rep].v;
+    grid[Key4{cell(v, 0), cell(v, 1), cell(v, 2), cell(v, 3)}].push_back(q);
+  }
+  for (int qa = 0; qa < NC; ++qa) {
+    const int a = classes[qa].rep;
     for (int flip = 0; flip < (cn[a].ambiguous ? 2 : 1); ++flip) {
       double v[4];
       for (int k = 0; k < 4; ++k) v[k] = flip ? -cn[a].v[k] : cn[a].v[k];
@@ -288,14 +334,17 @@ void face_groups(const std::vector<Plane>& pl, const float* eps, const float* si
             for (int dc = lo[3]; dc <= hi[3]; ++dc) {
               auto it = grid.find(Key4{base[0] + dx, base[1] + dy, base[2] + dz, base[3] + dc});
               if (it == grid.end()) continue;
-              for (int b : it->second) {
-                if (b == a) continue;
+              for (int qb : it->second) {
+                if (qb == qa) continue;
+                const int b = classes[qb].rep;
                 const double nd = pl[a].n[0] * pl[b].n[0] + pl[a].n[1] * pl[b].n[1] + pl[a].n[2] * pl[b].n[2];
                 if (std::fabs(nd) < 1.0 - 1e-12) continue;
                 const double sg = nd > 0 ? 1.0 : -1.0;
                 if (std::fabs(pl[a].c - sg * pl[b].c) > 1e-9 * diag) continue;
                 uf_join(pp, a, b);
-                if (eps[a] == eps[b] && sig[a] == sig[b] && rough[a] == rough[b]) uf_join(pg, a, b);
+                for (const auto& ma : classes[qa].mats)
+                  for (const auto& mb : classes[qb].mats)
+                    if (ma.first == mb.first) uf_join(pg, ma.second, mb.second);
               }
             }
     }
