@@ -532,10 +532,35 @@ sbr_status sbr_scene_build(sbr_context_t ctx, const double* tri_xyz, int64_t T, 
     std::vector<float> er, sg, rh;
     {
       HostPhase hp("host:scene_inputs");
-      tri = to_host(tri_xyz, (size_t)T * 9, flags, s);
-      er = to_host(eps_r, (size_t)T, flags, s);
-      sg = to_host(sigma, (size_t)T, flags, s);
-      rh = to_host(rough, (size_t)T, flags, s);
+      if ((flags & SBR_IN_DEVICE) && T > 0) {
+        // device inputs: four copies into the pinned staging area, one synchronisation
+        SBR_CHECK(tri_xyz && eps_r && sigma && rough, SBR_E_INVALID_ARG, "input array is NULL");
+        const size_t bt = (size_t)T * 72, bm = (size_t)T * 4, o1 = (bt + 255) & ~size_t(255);
+        const size_t o2 = o1 + ((bm + 255) & ~size_t(255)), o3 = o2 + ((bm + 255) & ~size_t(255));
+        const size_t need = o3 + bm;
+        if (c->stage_bytes < need) {
+          if (c->stage) (void)hipHostFree(c->stage);
+          c->stage = nullptr;
+          c->stage_bytes = 0;
+          SBR_HIP(hipHostMalloc(&c->stage, need, hipHostMallocDefault));
+          c->stage_bytes = need;
+        }
+        char* st = static_cast<char*>(c->stage);
+        SBR_HIP(hipMemcpyAsync(st, tri_xyz, bt, hipMemcpyDeviceToHost, s));
+        SBR_HIP(hipMemcpyAsync(st + o1, eps_r, bm, hipMemcpyDeviceToHost, s));
+        SBR_HIP(hipMemcpyAsync(st + o2, sigma, bm, hipMemcpyDeviceToHost, s));
+        SBR_HIP(hipMemcpyAsync(st + o3, rough, bm, hipMemcpyDeviceToHost, s));
+        SBR_HIP(hipStreamSynchronize(s));
+        tri.assign(reinterpret_cast<const double*>(st), reinterpret_cast<const double*>(st) + (size_t)T * 9);
+        er.assign(reinterpret_cast<const float*>(st + o1), reinterpret_cast<const float*>(st + o1) + T);
+        sg.assign(reinterpret_cast<const float*>(st + o2), reinterpret_cast<const float*>(st + o2) + T);
+        rh.assign(reinterpret_cast<const float*>(st + o3), reinterpret_cast<const float*>(st + o3) + T);
+      } else {
+        tri = to_host(tri_xyz, (size_t)T * 9, flags, s);
+        er = to_host(eps_r, (size_t)T, flags, s);
+        sg = to_host(sigma, (size_t)T, flags, s);
+        rh = to_host(rough, (size_t)T, flags, s);
+      }
     }
     SBR_CHECK(finite_all(tri.data(), tri.size()), SBR_E_INVALID_ARG, "triangle coordinates must be finite");
     for (int64_t t = 0; t < T; ++t) {
