@@ -227,6 +227,127 @@ void gather_u64(const uint64_t* src, const uint32_t* idx, uint64_t* dst, int64_t
   SBR_LAUNCH_CHECK();
 }
 
+// Inclusive scan over the 64 lanes of a wave with DPP moves: shifts by 1, 2,
+// 4 and 8 within each row of 16 lanes, then the row_bcast:15 and row_bcast:31
+// broadcasts carry row totals into the rows above (GFX9 DPP controls).  Every
+// lane of the wave must be active.
+__device__ inline uint32_t wave_inclusive_scan(uint32_t x, int lane) {
+  const int rl = lane & 15;
+  uint32_t t;
+  t = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x111, 0xf, 0xf, false);
+  if (rl >= 1) x += t;
+  t = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x112, 0xf, 0xf, false);
+  if (rl >= 2) x += t;
+  t = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x114, 0xf, 0xf, false);
+  if (rl >= 4) x += t;
+  t = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x118, 0xf, 0xf, false);
+  if (rl >= 8) x += t;
+  t = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x142, 0xf, 0xf, false);
+  if ((lane & 31) >= 16) x += t;
+  t = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x143, 0xf, 0xf, false);
+  if (lane >= 32) x += t;
+  return x;
+}
+
+// Small arrays (up to kSmallSort keys): the whole LSD radix sort in one
+// workgroup, 4-bit digits, with the keys and values resident in LDS between
+// one coalesced load and one coalesced store.  Each pass, every thread holds
+// its contiguous chunk of at most kSmallPer entries in registers and counts
+// its digits, the workgroup computes the exclusive offsets of those counts in
+// (digit, thread) order, and each thread scatters its chunk in order into the
+// LDS arrays, which keeps the sort stable.
+constexpr int kSmallThreads = 512, kSmallPer = 24, kSmallSort = kSmallThreads * kSmallPer;
+
+__global__ __launch_bounds__(kSmallThreads) void k_radix_sort_small(const uint64_t* __restrict__ kin,
+                                                                  const uint32_t* __restrict__ vin,
+                                                                  uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                                  int n, int bit_lo, int bit_hi) {
+  __shared__ uint64_t lk[kSmallSort];
+  __shared__ uint32_t lv[kSmallSort];
+  __shared__ uint32_t wtot[8][kSmallThreads / 64];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int per = (n + kSmallThreads - 1) / kSmallThreads;  // <= kSmallPer
+  const int i0 = min(n, t * per), m = min(n, i0 + per) - i0;
+  const int npass = (bit_hi - bit_lo + 3) / 4;
+  {
+    uint64_t kr[kSmallPer];
+    uint32_t vr[kSmallPer];
+#pragma unroll
+    for (int u = 0; u < kSmallPer; ++u) {
+      const int i = u * kSmallThreads + t;
+      if (i < n) kr[u] = kin[i], vr[u] = vin[i];
+    }
+#pragma unroll
+    for (int u = 0; u < kSmallPer; ++u) {
+      const int i = u * kSmallThreads + t;
+      if (i < n) lk[i] = kr[u], lv[i] = vr[u];
+    }
+  }
+  __syncthreads();
+  for (int p = 0; p < npass; ++p) {
+    const int shift = bit_lo + 4 * p;
+    uint64_t ck[kSmallPer];
+    uint32_t cv[kSmallPer];
+    uint32_t cnt[16];
+#pragma unroll
+    for (int d = 0; d < 16; ++d) cnt[d] = 0;
+#pragma unroll
+    for (int u = 0; u < kSmallPer; ++u)
+      if (u < m) {
+        ck[u] = lk[i0 + u], cv[u] = lv[i0 + u];
+        const int d = (int)((ck[u] >> shift) & 15u);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) cnt[q] += (q == d) ? 1u : 0u;
+      }
+    // exclusive offsets in (digit, thread) order.  Counts of digit pairs are
+    // packed in 16-bit halves (no total exceeds kSmallSort < 2^16), scanned
+    // across the wave with DPP, and the wave totals exchanged through LDS.
+    // The barrier also orders every thread's chunk read before any scatter
+    // into the same arrays.
+    uint32_t x[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      x[j] = wave_inclusive_scan(cnt[2 * j] | (cnt[2 * j + 1] << 16), lane);
+      if (lane == 63) wtot[j][wv] = x[j];
+    }
+    __syncthreads();
+    uint32_t base = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      uint32_t before = 0, total = 0;
+#pragma unroll
+      for (int w = 0; w < kSmallThreads / 64; ++w) {
+        const uint32_t sw = wtot[j][w];
+        before += w < wv ? sw : 0u;
+        total += sw;
+      }
+      const uint32_t incl = before + x[j];
+      cnt[2 * j] = base + (incl & 0xffffu) - cnt[2 * j];
+      base += total & 0xffffu;
+      cnt[2 * j + 1] = base + (incl >> 16) - cnt[2 * j + 1];
+      base += total >> 16;
+    }
+#pragma unroll
+    for (int u = 0; u < kSmallPer; ++u)
+      if (u < m) {
+        const int d = (int)((ck[u] >> shift) & 15u);
+        uint32_t pos = 0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+          if (q == d) pos = cnt[q]++;
+        lk[pos] = ck[u];
+        lv[pos] = cv[u];
+      }
+    // the scatter is the next pass's input; the barrier also keeps the next
+    // pass's totals from overwriting wtot while it is read
+    __syncthreads();
+  }
+  for (int i = t; i < n; i += kSmallThreads) {
+    kout[i] = lk[i];
+    vout[i] = lv[i];
+  }
+}
+
 size_t radix_sort_temp_bytes(int64_t n) {
   const int64_t nb = cdiv(n > 0 ? n : 1, kTile);
   const int64_t hist = nb * kRadix;
@@ -241,6 +362,11 @@ void radix_sort_pairs(uint64_t* keys_in, uint32_t* vals_in, uint64_t* keys_out, 
   if (npass <= 0) {
     SBR_HIP(hipMemcpyAsync(keys_out, keys_in, n * 8, hipMemcpyDeviceToDevice, s));
     SBR_HIP(hipMemcpyAsync(vals_out, vals_in, n * 4, hipMemcpyDeviceToDevice, s));
+    return;
+  }
+  if (n <= kSmallSort) {
+    { ::sbr::TimedLaunch tl_("sort", s); hipLaunchKernelGGL(k_radix_sort_small, dim3(1), dim3(kSmallThreads), 0, s, keys_in, vals_in, keys_out, vals_out, (int)n, bit_lo, bit_hi); }
+    SBR_LAUNCH_CHECK();
     return;
   }
   const int64_t nb = cdiv(n, kTile);
