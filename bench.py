@@ -2,7 +2,7 @@
 """Throughput of the SBR hot path on one MI355X: traced ray-segments/s.
 
 One step = the whole path over one synthetic urban-canyon workload, inputs
-already resident in HBM: scene build (face groups + LBVH), launch + trace
+already resident in HBM: scene build (face groups + BVH), launch + trace
 (breadth-first bounce loop), reception + path extraction (capture, dedup,
 exact image-method rebuild), channel (H[f, Nr, Nt] in FP64, complex64 out) and
 per-link statistics (path gain, RMS delay spread, mean angles).
@@ -165,7 +165,7 @@ def batched_main(args):
     t1 = time.perf_counter()
     bounce_ms, _ = S.sbr_profile_query(ctx, "bounce")
     kernels = {}
-    for name in ["bounce", "replay_capture", "rebuild", "channel", "keys", "sort", "scan", "order", "lbvh", "stats",
+    for name in ["bounce", "replay_capture", "rebuild", "channel", "keys", "sort", "scan", "order", "bvh", "stats",
                  "misc", "host:scene_build", "host:scene_inputs", "host:face_groups", "host:scene_upload",
                  "host:rx_tree"]:
         ms, n = S.sbr_profile_query(ctx, name)
@@ -314,7 +314,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kernels = {}
-    for name in ["bounce", "replay_capture", "rebuild", "channel", "keys", "sort", "scan", "order", "lbvh",
+    for name in ["bounce", "replay_capture", "rebuild", "channel", "keys", "sort", "scan", "order", "bvh",
                  "stats", "misc", "alpha", "host:scene_build", "host:scene_inputs", "host:face_groups",
                  "host:scene_upload", "host:rx_tree"]:
         ms, n = S.sbr_profile_query(ctx, name)

@@ -55,7 +55,7 @@ typedef enum {
 #define SBR_MAX_BOUNCES 16
 
 typedef struct sbr_context_s* sbr_context_t; /* device, stream, tuning         */
-typedef struct sbr_scene_s* sbr_scene_t;     /* triangles, face groups, LBVH   */
+typedef struct sbr_scene_s* sbr_scene_t;     /* triangles, face groups, BVH    */
 typedef struct sbr_trace_s* sbr_trace_t;     /* per-ray hit chains ("RT tree") */
 typedef struct sbr_paths_s* sbr_paths_t;     /* unique validated paths         */
 
@@ -192,7 +192,7 @@ sbr_status sbr_scene_groups(sbr_scene_t s, int32_t* group, int32_t* plane);
  * When enabled, the library records a pair of HIP events on the context
  * stream around every kernel launch it makes and accumulates the elapsed time
  * per kernel class ("bounce", "replay_capture", "rebuild", "channel", "sort",
- * "lbvh", "keys", "stats", "capacity", "alpha", "misc").  Enabling clears the
+ * "bvh", "keys", "stats", "capacity", "alpha", "misc").  Enabling clears the
  * totals; a query synchronises the stream.  Unknown names report 0. */
 sbr_status sbr_profile_enable(sbr_context_t ctx, int enable);
 sbr_status sbr_profile_query(sbr_context_t ctx, const char* kernel, double* total_ms, int64_t* launches);

@@ -1,17 +1,21 @@
-// bvh.hip -- linear BVH built on the GPU (Karras 2012, "Maximizing
-// Parallelism in the Construction of BVHs, Octrees, and k-d Trees"):
-// 30-bit Morton codes of primitive centroids -> stable radix sort (ties keep
-// primitive order, which makes the augmented key (code, index) unique) ->
-// one thread per internal node finds its key range and split from the
-// longest common prefix -> bottom-up box refit where the second thread to
-// reach a node (atomic counter, acquire/release) merges its two children.
+// bvh.hip -- BVH over primitive boxes, built on the GPU.  Both builders
+// start from 30-bit Morton codes of the primitive centroids, stably radix
+// sorted (ties keep primitive order, so the key (code, index) is unique):
+//  * up to kPlocMax primitives: PLOC clustering in one workgroup (Meister and
+//    Bittner 2018), which gives surface-area-aware trees;
+//  * beyond: the linear BVH of Karras 2012 ("Maximizing Parallelism in the
+//    Construction of BVHs, Octrees, and k-d Trees"): one thread per internal
+//    node finds its key range and split from the longest common prefix, then
+//    a bottom-up box refit where the second thread to reach a node (atomic
+//    counter, acquire/release) merges its two children.
 //
 // Node layout (64 B, four float4): both child boxes inline so one node fetch
 // serves the two slab tests of the traversal:
 //   [0] Llo.x Llo.y Llo.z Lhi.x  [1] Lhi.y Lhi.z Rlo.x Rlo.y
 //   [2] Rlo.z Rhi.x Rhi.y Rhi.z  [3] childL childR (int; leaf = ~sorted index)
-// Leaf boxes are widened by one float ulp on each side so that they also
-// contain the FP64 geometry the FP32 vertices were rounded from.
+// The root is node 0.  Leaf boxes are widened by one float ulp on each side
+// so that they also contain the FP64 geometry the FP32 vertices were rounded
+// from.
 #include "sbr_device.hpp"
 #include "sbr_internal.hpp"
 
@@ -168,15 +172,206 @@ __global__ void k_single_leaf(const float* __restrict__ lo, const float* __restr
   for (int k = 0; k < 6; ++k) root_box[k] = b[k];
 }
 
+// ---------------------------------------------------------------------------
+// PLOC (Meister and Bittner 2018, "Parallel Locally-Ordered Clustering for
+// Bounding Volume Hierarchy Construction"), one workgroup.  The clusters start
+// as the Morton-ordered leaves.  Each pass, every cluster finds its nearest
+// neighbour among the kPlocR clusters on either side (distance = surface area
+// of the merged box; ties ordered by the pair's indices, which makes the order
+// on pairs strict, so the closest pair is always mutual and every pass merges
+// at least one pair); mutual neighbours merge into a new node at the lower
+// position, and a block scan compacts the cluster array.  Internal nodes are
+// numbered downward from n - 2 in creation order, so the last merge, the
+// root, is node 0.  The height and internal-node count of each cluster are
+// carried along; the root's height is the tree depth.  A final top-down
+// pass (passes in reverse, each node placing its children) renumbers the
+// nodes in depth-first order, left child first, so that every subtree is a
+// contiguous range of nodes, as in the linear BVH: the rays of a wave walking
+// nearby subtrees then share cache lines.
+constexpr int kPlocThreads = 1024, kPlocR = 16, kPlocTile = kPlocThreads + 2 * kPlocR;
+constexpr int64_t kPlocMax = kBvhPlocMax;  // pair keys hold two 16-bit cluster indices
+static_assert(kPlocMax <= 65536, "PLOC pair keys hold 16-bit cluster indices");
+
+struct PlocArgs {
+  const float* lo;  // primitive boxes [n][3]
+  const float* hi;
+  const uint32_t* order;  // Morton order of the primitives
+  int n;
+  float* box[2];    // cluster boxes, SoA: component c of cluster i at c * n + i
+  int32_t* id[2];   // node index, or ~leaf
+  int32_t* ht[2];   // subtree height in internal nodes
+  int32_t* sz[2];   // internal nodes in the subtree
+  int32_t* nn;      // nearest neighbour
+  float4* tmp;      // nodes in creation order [n - 1][4]
+  int32_t* nsz;     // internal nodes below and including each created node
+  int32_t* dfs;     // depth-first number of each created node
+  int32_t* pass_next;  // first free node index at the start of each pass [n + 1]
+  float4* nodes;
+  float* root_box;
+  uint32_t* depth;
+};
+
+__device__ inline float merged_area(const float a[6], const float b[6]) {
+  const float ex = fmaxf(a[3], b[3]) - fminf(a[0], b[0]);
+  const float ey = fmaxf(a[4], b[4]) - fminf(a[1], b[1]);
+  const float ez = fmaxf(a[5], b[5]) - fminf(a[2], b[2]);
+  return ex * ey + ey * ez + ez * ex;
+}
+
+__global__ __launch_bounds__(kPlocThreads) void k_ploc(const PlocArgs A) {
+  __shared__ float sb[6][kPlocTile];
+  __shared__ uint32_t wsum[kPlocThreads / 64];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int n = A.n;
+  for (int i = t; i < n; i += kPlocThreads) {
+    const uint32_t p = A.order[i];
+    for (int c = 0; c < 3; ++c) {
+      A.box[0][c * n + i] = nextafterf(A.lo[3 * p + c], -INFINITY);
+      A.box[0][(3 + c) * n + i] = nextafterf(A.hi[3 * p + c], INFINITY);
+    }
+    A.id[0][i] = ~i;
+    A.ht[0][i] = 0;
+    A.sz[0][i] = 0;
+  }
+  __syncthreads();
+  int m = n, cur = 0, next = n - 2;
+  // every pass merges at least one pair, so n - 1 passes always suffice; the
+  // bound only guarantees that the loop ends
+  int pass = 0;
+  for (; m > 1 && pass < n; ++pass) {
+    if (t == 0) A.pass_next[pass] = next;
+    const float* B = A.box[cur];
+    // ---- nearest neighbours, one tile of kPlocThreads clusters at a time
+    for (int base = 0; base < m; base += kPlocThreads) {
+      for (int k = t; k < kPlocTile; k += kPlocThreads) {
+        const int g = base - kPlocR + k;
+        if (g >= 0 && g < m)
+          for (int c = 0; c < 6; ++c) sb[c][k] = B[c * n + g];
+      }
+      __syncthreads();
+      const int i = base + t;
+      if (i < m) {
+        float a[6];
+        for (int c = 0; c < 6; ++c) a[c] = sb[c][t + kPlocR];
+        uint64_t best = ~0ull;
+        const int j0 = max(0, i - kPlocR), j1 = min(m - 1, i + kPlocR);
+        for (int j = j0; j <= j1; ++j) {
+          if (j == i) continue;
+          float b[6];
+          for (int c = 0; c < 6; ++c) b[c] = sb[c][j - base + kPlocR];
+          const uint32_t lo = (uint32_t)min(i, j), hi = (uint32_t)max(i, j);
+          const uint64_t key = ((uint64_t)__float_as_uint(merged_area(a, b)) << 32) | (lo << 16) | hi;
+          best = key < best ? key : best;
+        }
+        const uint32_t lo = (uint32_t)(best >> 16) & 0xffffu, hi = (uint32_t)best & 0xffffu;
+        A.nn[i] = min((int)(lo == (uint32_t)i ? hi : lo), m - 1);
+      }
+      __syncthreads();
+    }
+    // ---- merge mutual pairs into the other buffer, compacted
+    float* Bo = A.box[cur ^ 1];
+    int32_t* Io = A.id[cur ^ 1];
+    int32_t* Ho = A.ht[cur ^ 1];
+    int32_t* So = A.sz[cur ^ 1];
+    int kept = 0, merged = 0;
+    for (int base = 0; base < m; base += kPlocThreads) {
+      const int i = base + t;
+      int j = -1;
+      bool keep = false, merge = false;
+      if (i < m) {
+        j = A.nn[i];
+        const bool mutual = A.nn[j] == i;
+        merge = mutual && i < j;
+        keep = !mutual || i < j;
+      }
+      // keep counts in the low half, merge counts in the high half (<= kPlocThreads each)
+      const uint32_t x = wave_inclusive_scan((keep ? 1u : 0u) | (merge ? 0x10000u : 0u), lane);
+      if (lane == 63) wsum[wv] = x;
+      __syncthreads();
+      uint32_t before = 0, total = 0;
+      for (int w = 0; w < kPlocThreads / 64; ++w) {
+        const uint32_t sw = wsum[w];
+        before += w < wv ? sw : 0u;
+        total += sw;
+      }
+      const uint32_t excl = before + x - ((keep ? 1u : 0u) | (merge ? 0x10000u : 0u));
+      if (keep) {
+        const int pos = kept + (int)(excl & 0xffffu);
+        float a[6];
+        for (int c = 0; c < 6; ++c) a[c] = B[c * n + i];
+        int32_t nid = A.id[cur][i], h = A.ht[cur][i], z = A.sz[cur][i];
+        if (merge) {
+          const int node = next - merged - (int)(excl >> 16);
+          float b[6];
+          for (int c = 0; c < 6; ++c) b[c] = B[c * n + j];
+          const int32_t jid = A.id[cur][j];
+          A.tmp[4 * node] = make_float4(a[0], a[1], a[2], a[3]);
+          A.tmp[4 * node + 1] = make_float4(a[4], a[5], b[0], b[1]);
+          A.tmp[4 * node + 2] = make_float4(b[2], b[3], b[4], b[5]);
+          A.tmp[4 * node + 3] = make_float4(__int_as_float(nid), __int_as_float(jid), 0.0f, 0.0f);
+          for (int c = 0; c < 3; ++c) a[c] = fminf(a[c], b[c]), a[3 + c] = fmaxf(a[3 + c], b[3 + c]);
+          h = 1 + max(h, A.ht[cur][j]);
+          z = 1 + z + A.sz[cur][j];
+          A.nsz[node] = z;
+          nid = node;
+        }
+        for (int c = 0; c < 6; ++c) Bo[c * n + pos] = a[c];
+        Io[pos] = nid;
+        Ho[pos] = h;
+        So[pos] = z;
+      }
+      kept += (int)(total & 0xffffu);
+      merged += (int)(total >> 16);
+      __syncthreads();  // wsum is rewritten by the next tile
+    }
+    next -= merged;
+    m = kept;
+    cur ^= 1;
+  }
+  if (t == 0) {
+    for (int c = 0; c < 6; ++c) A.root_box[c] = A.box[cur][c * n];
+    *A.depth = m == 1 ? (uint32_t)A.ht[cur][0] : 0xffffffffu;
+    A.pass_next[pass] = next;  // = -1 once the root exists
+    A.dfs[0] = 0;
+  }
+  if (m != 1) return;
+  __syncthreads();
+  // ---- depth-first numbering: a node's parent was created in a later pass,
+  // so walking the passes backwards numbers every parent before its children
+  for (int p = pass - 1; p >= 0; --p) {
+    const int first = A.pass_next[p + 1] + 1, last = A.pass_next[p];
+    for (int x = first + t; x <= last; x += kPlocThreads) {
+      const int d = A.dfs[x];
+      const float4 c = A.tmp[4 * x + 3];
+      const int32_t cl = __float_as_int(c.x), cr = __float_as_int(c.y);
+      const int left = cl >= 0 ? A.nsz[cl] : 0;
+      if (cl >= 0) A.dfs[cl] = d + 1;
+      if (cr >= 0) A.dfs[cr] = d + 1 + left;
+    }
+    __syncthreads();
+  }
+  for (int x = t; x < n - 1; x += kPlocThreads) {
+    const int d = A.dfs[x];
+    float4 c = A.tmp[4 * x + 3];
+    const int32_t cl = __float_as_int(c.x), cr = __float_as_int(c.y);
+    c.x = __int_as_float(cl >= 0 ? A.dfs[cl] : cl);
+    c.y = __int_as_float(cr >= 0 ? A.dfs[cr] : cr);
+    A.nodes[4 * d] = A.tmp[4 * x];
+    A.nodes[4 * d + 1] = A.tmp[4 * x + 1];
+    A.nodes[4 * d + 2] = A.tmp[4 * x + 2];
+    A.nodes[4 * d + 3] = c;
+  }
+}
+
 inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
 
-int build_lbvh(const float* box_lo, const float* box_hi, int64_t n, const float scene_lo[3], const float scene_hi[3],
-               BvhOut out, hipStream_t s) {
-  SBR_CHECK(n >= 1 && n < (int64_t(1) << 31), SBR_E_UNSUPPORTED, "LBVH over %lld primitives", (long long)n);
+int build_bvh(const float* box_lo, const float* box_hi, int64_t n, const float scene_lo[3], const float scene_hi[3],
+              BvhOut out, hipStream_t s) {
+  SBR_CHECK(n >= 1 && n < (int64_t(1) << 31), SBR_E_UNSUPPORTED, "BVH over %lld primitives", (long long)n);
   if (n == 1) {
-    { ::sbr::TimedLaunch tl_("lbvh", s); hipLaunchKernelGGL(k_single_leaf, dim3(1), dim3(1), 0, s, box_lo, box_hi, out.nodes, out.order, out.root_box); }
+    { ::sbr::TimedLaunch tl_("bvh", s); hipLaunchKernelGGL(k_single_leaf, dim3(1), dim3(1), 0, s, box_lo, box_hi, out.nodes, out.order, out.root_box); }
     SBR_LAUNCH_CHECK();
     if (out.root_host) {
       SBR_HIP(hipMemcpyAsync(out.root_host, out.root_box, 24, hipMemcpyDeviceToHost, s));
@@ -184,11 +379,16 @@ int build_lbvh(const float* box_lo, const float* box_hi, int64_t n, const float 
     }
     return 1;
   }
+  const bool ploc = n <= kPlocMax;
   Buf codes, codes2, idx, parents, flags, temp;
   codes.alloc(n * 8, s);
   codes2.alloc(n * 8, s);
   idx.alloc(n * 4, s);
-  parents.alloc(2 * n * 4, s);
+  // PLOC scratch (4-byte words): boxes 12 n, id / height / size pairs 6 n,
+  // nn, nsz, dfs 3 n, pass_next n + 1, then creation-order nodes 16 (n - 1)
+  // at the next 16-byte boundary
+  const int64_t tmp_off = (22 * n + 1 + 3) & ~int64_t(3);
+  parents.alloc((ploc ? tmp_off + 16 * (n - 1) : 2 * n) * 4, s);
   flags.alloc((n + 1) * 4, s);
   temp.alloc(radix_sort_temp_bytes(n), s);
   float3 slo = make_float3(scene_lo[0], scene_lo[1], scene_lo[2]);
@@ -196,23 +396,42 @@ int build_lbvh(const float* box_lo, const float* box_hi, int64_t n, const float 
   ie.x = scene_hi[0] > scene_lo[0] ? 1.0f / (scene_hi[0] - scene_lo[0]) : 0.0f;
   ie.y = scene_hi[1] > scene_lo[1] ? 1.0f / (scene_hi[1] - scene_lo[1]) : 0.0f;
   ie.z = scene_hi[2] > scene_lo[2] ? 1.0f / (scene_hi[2] - scene_lo[2]) : 0.0f;
-  { ::sbr::TimedLaunch tl_("lbvh", s); hipLaunchKernelGGL(k_morton, dim3(blocks(n, 256)), dim3(256), 0, s, box_lo, box_hi, n, slo, ie,
+  { ::sbr::TimedLaunch tl_("bvh", s); hipLaunchKernelGGL(k_morton, dim3(blocks(n, 256)), dim3(256), 0, s, box_lo, box_hi, n, slo, ie,
                      codes.as<uint64_t>(), idx.as<uint32_t>()); }
   SBR_LAUNCH_CHECK();
   radix_sort_pairs(codes.as<uint64_t>(), idx.as<uint32_t>(), codes2.as<uint64_t>(), out.order, n, 0, 30,
                    temp.p, s);
+  uint32_t* dd = flags.as<uint32_t>() + n;
+  if (ploc) {
+    PlocArgs A{};
+    A.lo = box_lo, A.hi = box_hi, A.order = out.order, A.n = (int)n;
+    float* f = parents.as<float>();
+    A.box[0] = f, A.box[1] = f + 6 * n;
+    int32_t* q = parents.as<int32_t>() + 12 * n;
+    A.id[0] = q, A.id[1] = q + n, A.ht[0] = q + 2 * n, A.ht[1] = q + 3 * n, A.sz[0] = q + 4 * n;
+    A.sz[1] = q + 5 * n, A.nn = q + 6 * n, A.nsz = q + 7 * n, A.dfs = q + 8 * n, A.pass_next = q + 9 * n;
+    A.tmp = reinterpret_cast<float4*>(parents.as<int32_t>() + tmp_off);
+    A.nodes = out.nodes, A.root_box = out.root_box, A.depth = dd;
+    { ::sbr::TimedLaunch tl_("bvh", s); hipLaunchKernelGGL(k_ploc, dim3(1), dim3(kPlocThreads), 0, s, A); }
+    SBR_LAUNCH_CHECK();
+    uint32_t depth = 0;
+    SBR_HIP(hipMemcpyAsync(&depth, dd, 4, hipMemcpyDeviceToHost, s));
+    if (out.root_host) SBR_HIP(hipMemcpyAsync(out.root_host, out.root_box, 24, hipMemcpyDeviceToHost, s));
+    SBR_HIP(hipStreamSynchronize(s));
+    SBR_CHECK(depth != 0xffffffffu, SBR_E_DEVICE, "BVH clustering did not reach a single root");
+    return (int)depth;
+  }
   int32_t* pint = parents.as<int32_t>();
   int32_t* pleaf = pint + n;
-  { ::sbr::TimedLaunch tl_("lbvh", s); hipLaunchKernelGGL(k_karras, dim3(blocks(n - 1, 256)), dim3(256), 0, s, codes2.as<uint64_t>(), n, out.nodes, pint,
+  { ::sbr::TimedLaunch tl_("bvh", s); hipLaunchKernelGGL(k_karras, dim3(blocks(n - 1, 256)), dim3(256), 0, s, codes2.as<uint64_t>(), n, out.nodes, pint,
                      pleaf); }
   SBR_LAUNCH_CHECK();
   fill_u32(flags.as<uint32_t>(), 0, n + 1, s);
-  { ::sbr::TimedLaunch tl_("lbvh", s); hipLaunchKernelGGL(k_refit, dim3(blocks(n, 256)), dim3(256), 0, s, box_lo, box_hi, out.order, n, out.nodes, pint,
+  { ::sbr::TimedLaunch tl_("bvh", s); hipLaunchKernelGGL(k_refit, dim3(blocks(n, 256)), dim3(256), 0, s, box_lo, box_hi, out.order, n, out.nodes, pint,
                      pleaf, flags.as<uint32_t>(), out.root_box); }
   SBR_LAUNCH_CHECK();
-  uint32_t* dd = flags.as<uint32_t>() + n;
   fill_u32(dd, 0, 1, s);
-  { ::sbr::TimedLaunch tl_("lbvh", s); hipLaunchKernelGGL(k_depth, dim3(blocks(n, 256)), dim3(256), 0, s, pint, pleaf, n, dd); }
+  { ::sbr::TimedLaunch tl_("bvh", s); hipLaunchKernelGGL(k_depth, dim3(blocks(n, 256)), dim3(256), 0, s, pint, pleaf, n, dd); }
   SBR_LAUNCH_CHECK();
   uint32_t depth = 0;
   SBR_HIP(hipMemcpyAsync(&depth, dd, 4, hipMemcpyDeviceToHost, s));

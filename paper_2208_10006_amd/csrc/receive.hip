@@ -3,7 +3,7 @@
 //
 //  1. replay:   every ray's FP64 chain is rebuilt from its hit chain (the
 //               per-ray record the trace kept) and each segment is tested
-//               against the receivers through an LBVH over the Rx points:
+//               against the receivers through a BVH over the Rx points:
 //               captured when the closest approach lies inside the segment
 //               and within coeff * alpha * (unfolded distance) / sqrt(3).
 //  2. keys:     capture -> (rx*Nt + tx, 64-bit hash of (k, g_1..g_k));
@@ -12,7 +12,7 @@
 //               exact sequence comparison inside equal-hash runs.
 //  3. rebuild:  each key is rebuilt by the image method in FP64 (Sec. I) and
 //               kept when its reflection points lie on their faces, on the
-//               incidence side, and no triangle blocks a leg (any-hit LBVH
+//               incidence side, and no triangle blocks a leg (any-hit BVH
 //               traversal with FP64 triangle tests); the frequency-
 //               independent part of the field (polarisation chain, incidence
 //               cosines, materials) is stored for the channel kernels.
@@ -240,7 +240,7 @@ struct RebuildParams {
   float root[6];
   double cx, cy, cz;
   int has_bvh;
-  int n_big, big_off;  // oversized triangles outside the LBVH (tri32 entries big_off ..)
+  int n_big, big_off;  // oversized triangles outside the BVH (tri32 entries big_off ..)
   // outputs (indexed by key)
   uint32_t* valid;
   double* geo;
@@ -531,7 +531,7 @@ void run_receive(sbr_paths_s* ps, const double* hrx, hipStream_t s) {
   sbr_trace_s* tr = ps->trace;
   sbr_scene_s* sc = tr->scene;
   const int Nr = ps->Nr, Nt = tr->Nt, K = tr->K;
-  // ---------------- Rx LBVH (FP32 boxes in a frame centred on the Rx bounding sphere)
+  // ---------------- Rx BVH (FP32 boxes in a frame centred on the Rx bounding sphere)
   HostPhase hp_rx("host:rx_tree");
   std::optional<HostPhase> hp_step;
   hp_step.emplace("host:rx_boxes");
@@ -567,7 +567,7 @@ void run_receive(sbr_paths_s* ps, const double* hrx, hipStream_t s) {
   rroot.alloc(32, s);
   float hroot[8];
   const int rdepth =
-      build_lbvh(dlo.as<float>(), dhi.as<float>(), Nr, flo, fhi, BvhOut{rnodes.as<float4>(), rorder.as<uint32_t>(),
+      build_bvh(dlo.as<float>(), dhi.as<float>(), Nr, flo, fhi, BvhOut{rnodes.as<float4>(), rorder.as<uint32_t>(),
                                                                          rroot.as<float>(), hroot}, s);
   SBR_CHECK(rdepth <= 64, SBR_E_UNSUPPORTED, "receiver tree depth %d", rdepth);
   hp_step.reset();

@@ -629,16 +629,18 @@ sbr_status sbr_scene_build(sbr_context_t ctx, const double* tri_xyz, int64_t T, 
         gpl[g] = tpl[gfirst[g]];
         gmt[g] = make_float4(er[gfirst[g]], sg[gfirst[g]], rh[gfirst[g]], 0.0f);
       }
-      // Oversized triangles (box diagonal above a quarter of the scene's, at
-      // most kMaxBig, largest first) stay out of the LBVH: in a Morton-ordered
-      // tree every ancestor of such a leaf gets a box as large as the scene
-      // (a city's ground plane inflates a whole root-to-leaf chain), so
-      // nearly every ray would descend those chains.  Every ray tests them
-      // directly instead, before the traversal, which also gives the
-      // traversal an early closest-hit bound.
+      // Scenes built with the Morton-ordered LBVH (above kBvhPlocMax
+      // triangles) keep oversized triangles (box diagonal above a quarter of
+      // the scene's, at most kMaxBig, largest first) out of the tree: there
+      // every ancestor of such a leaf gets a box as large as the scene (a
+      // city's ground plane inflates a whole root-to-leaf chain), so nearly
+      // every ray would descend those chains.  Every ray tests them directly
+      // instead, before the traversal.  PLOC clustering merges large boxes
+      // late, near the root, by itself, so smaller scenes keep every
+      // triangle in the tree.
       constexpr int kMaxBig = 16;
       std::vector<std::pair<double, int32_t>> cand;
-      for (int64_t t = 0; t < T; ++t) {
+      for (int64_t t = 0; T > kBvhPlocMax && t < T; ++t) {
         double d2 = 0.0;
         for (int k = 0; k < 3; ++k) {
           const double a = tri[9 * t + k], b = tri[9 * t + 3 + k], cc = tri[9 * t + 6 + k];
@@ -660,7 +662,7 @@ sbr_status sbr_scene_build(sbr_context_t ctx, const double* tri_xyz, int64_t T, 
         if (!is_big[t]) bvh_ids.push_back((int32_t)t);
       sc->n_big = (int)big_ids.size();
       sc->n_bvh = (int64_t)bvh_ids.size();
-      // FP32 vertices centred on the scene box; boxes of the LBVH triangles
+      // FP32 vertices centred on the scene box; boxes of the tree's triangles
       // (rounded outward in the builder)
       std::vector<float> v32((size_t)T * 9), blo((size_t)sc->n_bvh * 3), bhi((size_t)sc->n_bvh * 3);
       float slo[3] = {1e30f, 1e30f, 1e30f}, shi[3] = {-1e30f, -1e30f, -1e30f};
@@ -708,7 +710,7 @@ sbr_status sbr_scene_build(sbr_context_t ctx, const double* tri_xyz, int64_t T, 
       sc->tri32.alloc((size_t)T * 48, s);
       if (sc->n_bvh > 0) {
         order.alloc((size_t)sc->n_bvh * 4, s);
-        sc->bvh_depth = build_lbvh(dlo.as<float>(), dhi.as<float>(), sc->n_bvh, slo, shi,
+        sc->bvh_depth = build_bvh(dlo.as<float>(), dhi.as<float>(), sc->n_bvh, slo, shi,
                                    BvhOut{sc->nodes.as<float4>(), order.as<uint32_t>(), sc->root_box.as<float>(),
                                           sc->root_host}, s);
         SBR_CHECK(sc->bvh_depth <= 64, SBR_E_UNSUPPORTED, "BVH depth %d exceeds the traversal stack",
@@ -726,7 +728,7 @@ sbr_status sbr_scene_build(sbr_context_t ctx, const double* tri_xyz, int64_t T, 
                            sc->tgroup.as<int32_t>(), sc->tri32.as<float4>());
         SBR_LAUNCH_CHECK();
       }
-      // The staged copies were consumed before the LBVH depth readback synchronised
+      // The staged copies were consumed before the BVH depth readback synchronised
       // the stream (without a tree, synchronise here so the staging area is free);
       // the leaf gather runs in stream order before any trace of this scene.
       if (sc->n_bvh == 0) SBR_HIP(hipStreamSynchronize(s));
@@ -906,11 +908,12 @@ sbr_status sbr_trace_info(sbr_trace_t t, int64_t* rays, int64_t* segments) {
       tr->segments = (int64_t)v;
     }
     if (tr->segments < 0) {
-      std::vector<uint32_t> cnt(tr->K + 1);
+      std::vector<uint32_t> cnt((size_t)trace_counter_words(tr->K));
       SBR_HIP(hipMemcpyAsync(cnt.data(), tr->counters.p, cnt.size() * 4, hipMemcpyDeviceToHost, tr->ctx->stream));
       SBR_HIP(hipStreamSynchronize(tr->ctx->stream));
-      int64_t seg = tr->NR;
-      for (int k = 0; k < tr->K; ++k) seg += cnt[k];
+      int64_t seg = tr->NR;  // survivors of bounce k are the rays of bounce k + 1
+      for (int k = 0; k < tr->K; ++k)
+        for (int x = 0; x < 8; ++x) seg += cnt[(size_t)kCtrWords * k + kCtrOut + 32 * x];
       tr->segments = seg;
     }
     if (rays) *rays = tr->NR;

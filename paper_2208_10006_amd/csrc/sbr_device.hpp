@@ -134,4 +134,26 @@ __device__ inline uint64_t lanemask_lt() {
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
+// Inclusive scan over the 64 lanes of a wave with DPP moves: shifts by 1, 2,
+// 4 and 8 within each row of 16 lanes, then the row_bcast:15 and row_bcast:31
+// broadcasts carry row totals into the rows above (GFX9 DPP controls).  Every
+// lane of the wave must be active.
+__device__ inline uint32_t wave_inclusive_scan(uint32_t x, int lane) {
+  const int rl = lane & 15;
+  uint32_t t;
+  t = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x111, 0xf, 0xf, false);
+  if (rl >= 1) x += t;
+  t = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x112, 0xf, 0xf, false);
+  if (rl >= 2) x += t;
+  t = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x114, 0xf, 0xf, false);
+  if (rl >= 4) x += t;
+  t = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x118, 0xf, 0xf, false);
+  if (rl >= 8) x += t;
+  t = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x142, 0xf, 0xf, false);
+  if ((lane & 31) >= 16) x += t;
+  t = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x143, 0xf, 0xf, false);
+  if (lane >= 32) x += t;
+  return x;
+}
+
 }  // namespace sbr

@@ -1,7 +1,7 @@
 // sbr_internal.hpp -- internal types of libsbr (not part of the C-ABI).
 //
 // Data layout in HBM (structure of arrays everywhere a kernel streams):
-//   scene:  FP32 centred triangles in LBVH leaf order (3 x float4 per
+//   scene:  FP32 centred triangles in BVH leaf order (3 x float4 per
 //           triangle: v0|tri id, v1|plane id, v2|group id), 64-byte BVH nodes
 //           holding both child boxes, FP64 per-triangle planes (n, c) and
 //           vertices for the exact FP64 steps, per-group plane/material and a
@@ -166,7 +166,7 @@ struct sbr_scene_s : sbr::Handle {
   sbr_context_s* ctx = nullptr;
   int64_t T = 0;
   int n_groups = 0, n_planes = 0, bvh_depth = 0;
-  // triangles in the LBVH (leaves 0 .. n_bvh-1 of tri32) and oversized ones
+  // triangles in the BVH (leaves 0 .. n_bvh-1 of tri32) and oversized ones
   // kept out of it (tri32 entries n_bvh .. T-1, tested by every ray directly)
   int64_t n_bvh = 0;
   int n_big = 0;
@@ -197,7 +197,7 @@ struct sbr_trace_s : sbr::Handle {
   std::vector<double> h_tx;
   sbr::Buf tx;      // double[Nt][3]
   sbr::Buf seq;     // int32[(K+1)][NR]
-  sbr::Buf counters; // uint32: per bounce {queue, n_in} ...
+  sbr::Buf counters; // uint32: trace_counter_words(K), one block per bounce
   sbr::Buf work;     // uint64[2]: node visits, triangle tests (when counted)
   bool counted = false;
   int64_t segments = -1;  // host copy once read
@@ -244,16 +244,18 @@ void fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 void iota_u32(uint32_t* p, int64_t n, hipStream_t s);
 void gather_u64(const uint64_t* src, const uint32_t* idx, uint64_t* dst, int64_t n, hipStream_t s);
 
-// bvh.hip: LBVH over n primitives given their FP32 boxes (lo, hi) -> nodes,
-// leaf permutation (sorted position -> primitive), root box.  Returns depth.
+// bvh.hip: BVH over n primitives given their FP32 boxes (lo, hi) -> nodes,
+// leaf permutation (sorted position -> primitive), root box.  PLOC clustering
+// up to kBvhPlocMax primitives, Karras LBVH beyond.  Returns the depth.
+constexpr int64_t kBvhPlocMax = 65536;
 struct BvhOut {
   float4* nodes;     // [max(n-1,1)][4]
   uint32_t* order;   // [n] primitive of each leaf
   float* root_box;   // [8]
   float* root_host;  // optional host copy of the root box (6 floats), filled before return
 };
-int build_lbvh(const float* box_lo, const float* box_hi, int64_t n, const float scene_lo[3],
-               const float scene_hi[3], BvhOut out, hipStream_t s);
+int build_bvh(const float* box_lo, const float* box_hi, int64_t n, const float scene_lo[3],
+              const float scene_hi[3], BvhOut out, hipStream_t s);
 
 // geodesic.hip
 void upload_geodesic_tables(int device);
@@ -268,7 +270,7 @@ struct TraceLaunch {
   int Nt, N, K;
   int64_t R, NR;
   int32_t* seq;
-  uint32_t* counters;  // trace_counter_words(K): survivors per bounce, then queue slots
+  uint32_t* counters;  // trace_counter_words(K): one kCtrWords block per bounce
   unsigned long long* work;  // node visits, triangle tests, or null (no counting)
   int grid, block, chunk;
 };
@@ -278,6 +280,10 @@ void launch_trace(const TraceLaunch& L, void* ray_a, void* ray_b, hipStream_t s)
 void launch_trace_batch(const std::vector<sbr_trace_s*>& trs, int grid, int chunk, void* ray_a, void* ray_b,
                         uint32_t* counters, unsigned long long* t_first, unsigned long long* t_last, hipStream_t s);
 size_t trace_ray_bytes(int64_t NR);
+// Trace counters: per bounce a block of kCtrWords words holding, for each of
+// the 8 ray regions x, the queue position (kCtrQueue + 32 x), the number of
+// survivors written (kCtrOut + 32 x) and an "empty" flag (kCtrDone + 32 x).
+constexpr int kCtrQueue = 0, kCtrOut = 256, kCtrDone = 512, kCtrWords = 1024;
 int64_t trace_counter_words(int K);
 
 // receive.hip

@@ -227,28 +227,6 @@ void gather_u64(const uint64_t* src, const uint32_t* idx, uint64_t* dst, int64_t
   SBR_LAUNCH_CHECK();
 }
 
-// Inclusive scan over the 64 lanes of a wave with DPP moves: shifts by 1, 2,
-// 4 and 8 within each row of 16 lanes, then the row_bcast:15 and row_bcast:31
-// broadcasts carry row totals into the rows above (GFX9 DPP controls).  Every
-// lane of the wave must be active.
-__device__ inline uint32_t wave_inclusive_scan(uint32_t x, int lane) {
-  const int rl = lane & 15;
-  uint32_t t;
-  t = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x111, 0xf, 0xf, false);
-  if (rl >= 1) x += t;
-  t = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x112, 0xf, 0xf, false);
-  if (rl >= 2) x += t;
-  t = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x114, 0xf, 0xf, false);
-  if (rl >= 4) x += t;
-  t = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x118, 0xf, 0xf, false);
-  if (rl >= 8) x += t;
-  t = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x142, 0xf, 0xf, false);
-  if ((lane & 31) >= 16) x += t;
-  t = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x143, 0xf, 0xf, false);
-  if (lane >= 32) x += t;
-  return x;
-}
-
 // Small arrays (up to kSmallSort keys): the whole LSD radix sort in one
 // workgroup, 4-bit digits, with the keys and values resident in LDS between
 // one coalesced load and one coalesced store.  Each pass, every thread holds

@@ -191,10 +191,12 @@ struct BounceParams {
   GeoTables G;
   int k;
   int64_t n_first;              // rays of bounce 0 (generated, not read)
-  const uint32_t* n_in_ptr;
   RaySoA in, out;
-  uint32_t* n_out_ptr;
-  uint32_t* queue;
+  // Counter block of this bounce and of the previous one (kCtrWords words
+  // each): queue, output count and drained flag of each of the 8 regions,
+  // every word on its own 128-byte line.
+  uint32_t* ctr;
+  const uint32_t* ctr_in;
   int chunk;
   unsigned long long* work;
   unsigned long long* t_first;  // batched: per-scene first/last wall-clock stamp
@@ -228,28 +230,40 @@ __global__ __launch_bounds__(256) void k_bounce(const BounceParams P) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int32_t* stk = &stack_mem[wv][0][lane];
   const bool first = P.k == 0;
-  const uint64_t n_in = first ? (uint64_t)P.n_first : (uint64_t)*P.n_in_ptr;
+  const uint64_t nf = (uint64_t)P.n_first;
   const uint64_t lt = lanemask_lt();
   uint32_t n_node = 0, n_tri = 0;  // work counters (COUNT builds only)
-  // Work distribution: the rays of the bounce are cut into 8 contiguous
-  // slices, one per XCD, each with its own queue counter on its own cache
-  // line.  Workgroups are dispatched round-robin over the 8 XCDs, so a wave
-  // drains the slice of its own XCD first (atomics stay in that XCD's L2) and
-  // then steals from the others.  A wave pulls `chunk` rays per atomic and
-  // traces them 64 at a time.
+  // Work distribution: the rays of bounce 0 are cut into 8 contiguous
+  // regions, one per XCD, and every region keeps its index range for the
+  // whole trace: the survivors of region x are appended to the same range of
+  // the other ray buffer (never more than its input), so each region has its
+  // own queue and output counters and no counter is shared by the whole chip
+  // (atomics on one address serialise).  Workgroups are dispatched
+  // round-robin over the 8 XCDs, so a wave drains the region of its own XCD
+  // first and then steals from the others; a region found empty is flagged
+  // so that later waves skip its queue without an atomic.  A wave pulls
+  // `chunk` rays per atomic and traces them 64 at a time.
   const int home = blockIdx.x & 7;
-  int tried = 0;
+  int tried = 0, reg = 0;
   uint64_t base = 0, lo = 0, hi = 0;
   uint32_t sub = 0;
   while (true) {
     if (sub == 0) {
-      const int x = (home + tried) & 7;
-      lo = n_in * (uint64_t)x / 8;
-      hi = n_in * (uint64_t)(x + 1) / 8;
-      uint32_t b = 0;
-      if (lane == 0) b = atomicAdd(P.queue + 32 * x, (uint32_t)P.chunk);
-      base = lo + __shfl(b, 0, 64);
-      if (base >= hi) {
+      reg = (home + tried) & 7;
+      lo = nf * (uint64_t)reg / 8;
+      hi = first ? nf * (uint64_t)(reg + 1) / 8 : lo + (uint64_t)P.ctr_in[kCtrOut + 32 * reg];
+      uint32_t b = 0xffffffffu;
+      if (lane == 0) {
+        uint32_t* q = P.ctr + kCtrQueue + 32 * reg;
+        uint32_t* done = P.ctr + kCtrDone + 32 * reg;
+        if (__hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+          b = atomicAdd(q, (uint32_t)P.chunk);
+          if (lo + b >= hi) __hip_atomic_store(done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+      b = __shfl(b, 0, 64);
+      base = lo + b;
+      if (b == 0xffffffffu || base >= hi) {
         if (++tried == 8) break;
         continue;
       }
@@ -415,10 +429,10 @@ __global__ __launch_bounds__(256) void k_bounce(const BounceParams P) {
     const uint64_t m = __ballot(live);
     if (m != 0) {
       uint32_t ob = 0;
-      if (lane == 0) ob = atomicAdd(P.n_out_ptr, (uint32_t)__popcll(m));
+      if (lane == 0) ob = atomicAdd(P.ctr + kCtrOut + 32 * reg, (uint32_t)__popcll(m));
       ob = __shfl(ob, 0, 64);
       if (live) {
-        const uint32_t j = ob + (uint32_t)__popcll(m & lt);
+        const uint64_t j = lo + ob + (uint32_t)__popcll(m & lt);
         P.out.ox[j] = o.x, P.out.oy[j] = o.y, P.out.oz[j] = o.z;
         P.out.dx[j] = d.x, P.out.dy[j] = d.y, P.out.dz[j] = d.z;
         P.out.L[j] = L;
@@ -492,7 +506,7 @@ void geodesic_edge_stats(int N, double* mean, double* mn, double* mx, hipStream_
   if (mx) *mx = h[2];
 }
 
-int64_t trace_counter_words(int K) { return 32 + 256 * (int64_t)(K + 1); }
+int64_t trace_counter_words(int K) { return (int64_t)kCtrWords * (K + 1); }
 
 size_t trace_ray_bytes(int64_t NR) { return (size_t)NR * (7 * sizeof(double) + 2 * sizeof(uint32_t)); }
 
@@ -588,9 +602,8 @@ void launch_trace(const TraceLaunch& T, void* ray_a, void* ray_b, hipStream_t s)
   std::vector<BounceParams> Pk(T.K + 1, P);
   for (int k = 0; k <= T.K; ++k) {
     Pk[k].k = k;
-    Pk[k].queue = T.counters + 32 + 256 * k;
-    Pk[k].n_in_ptr = k > 0 ? T.counters + (k - 1) : nullptr;
-    Pk[k].n_out_ptr = T.counters + k;
+    Pk[k].ctr = T.counters + (int64_t)kCtrWords * k;
+    Pk[k].ctr_in = k > 0 ? T.counters + (int64_t)kCtrWords * (k - 1) : nullptr;
     Pk[k].in = (k % 2 == 1) ? A : B;
     Pk[k].out = (k % 2 == 1) ? B : A;
   }
@@ -598,7 +611,6 @@ void launch_trace(const TraceLaunch& T, void* ray_a, void* ray_b, hipStream_t s)
     launch_trace_graph(T, Pk.data(), T.K + 1, s);
     return;
   }
-  // counters: [0..K] survivors of each bounce; then per bounce 8 queue slots of 128 B
   fill_u32(T.counters, 0, trace_counter_words(T.K), s);
   // every chain entry starts as "miss"; the bounce kernels overwrite the ones they trace
   fill_u32(reinterpret_cast<uint32_t*>(T.seq), 0xffffffffu, (int64_t)(T.K + 1) * T.NR, s);
@@ -648,9 +660,8 @@ void launch_trace_batch(const std::vector<sbr_trace_s*>& trs, int grid, int chun
   RaySoA A = soa_of(ray_a, off), B = soa_of(ray_b, off);
   for (int k = 0; k <= Kmax; ++k) {
     P.k = k;
-    P.queue = counters + 32 + 256 * k;
-    P.n_in_ptr = k > 0 ? counters + (k - 1) : nullptr;
-    P.n_out_ptr = counters + k;
+    P.ctr = counters + (int64_t)kCtrWords * k;
+    P.ctr_in = k > 0 ? counters + (int64_t)kCtrWords * (k - 1) : nullptr;
     P.in = (k % 2 == 1) ? A : B;
     P.out = (k % 2 == 1) ? B : A;
     ::sbr::TimedLaunch tl_("bounce", s);
