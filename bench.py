@@ -77,6 +77,33 @@ def committed_traffic(workload):
     return (rec["fetch_bytes_per_step"] + rec["write_bytes_per_step"]) / rec["launches_per_step"]
 
 
+KERNEL_CLASSES = ["bounce", "replay_capture", "rebuild", "channel", "keys", "sort", "scan", "order", "bvh", "stats",
+                  "misc", "alpha", "host:scene_build", "host:scene_inputs", "host:face_groups", "host:scene_upload",
+                  "host:rx_tree"]
+
+
+def breakdown(S, ctx, run, steps=2, exclude=()):
+    """Per-class kernel and host-phase times from extra, untimed steps with
+    every class profiled (the event records add host overhead, which is why
+    the timed steps profile the dominant kernel only)."""
+    import torch
+    S.sbr_profile_only(ctx, None)
+    S.sbr_profile_enable(ctx, True)
+    for _ in range(steps):
+        h = run()
+        del h
+    torch.cuda.synchronize()
+    out = {}
+    for name in KERNEL_CLASSES:
+        if name in exclude:
+            continue
+        ms, n = S.sbr_profile_query(ctx, name)
+        if n:
+            out[name] = {"ms_per_step": ms / steps, "launches_per_step": n / steps}
+    S.sbr_profile_enable(ctx, False)
+    return out
+
+
 def describe(w):
     rays = 10 * w.geodesic_N ** 2 + 2
     f0, f1 = float(w.freq.min()) / 1e9, float(w.freq.max()) / 1e9
@@ -153,6 +180,7 @@ def batched_main(args):
     torch.cuda.synchronize()
     segs = sum(S.sbr_trace_info(t)["segments"] for t in trs)
     del scenes, trs
+    S.sbr_profile_only(ctx, "bounce")
     S.sbr_profile_enable(ctx, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -163,14 +191,10 @@ def batched_main(args):
         del scenes, trs
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    bounce_ms, _ = S.sbr_profile_query(ctx, "bounce")
-    kernels = {}
-    for name in ["bounce", "replay_capture", "rebuild", "channel", "keys", "sort", "scan", "order", "bvh", "stats",
-                 "misc", "host:scene_build", "host:scene_inputs", "host:face_groups", "host:scene_upload",
-                 "host:rx_tree"]:
-        ms, n = S.sbr_profile_query(ctx, name)
-        if n:
-            kernels[name] = {"ms_per_step": ms / args.steps, "launches_per_step": n / args.steps}
+    bounce_ms, bounce_n = S.sbr_profile_query(ctx, "bounce")
+    S.sbr_profile_enable(ctx, False)
+    kernels = {"bounce": {"ms_per_step": bounce_ms / args.steps, "launches_per_step": bounce_n / args.steps}}
+    kernels.update(breakdown(S, ctx, one_step, exclude=("bounce",)))
     lat = np.array(lat)
     out = {"metric": "traced ray-segments/s (batched uneven scenes)", "value": segs * args.steps / (t1 - t0),
            "unit": "ray-segments/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -305,6 +329,10 @@ def main():
     segments = info["segments"]
     del sc, tr, ps
 
+    # timed steps: live HIP-event timing of the dominant kernel only (two
+    # event records per bounce launch), so the step time carries no
+    # profiling overhead for the other kernels
+    S.sbr_profile_only(ctx, "bounce")
     S.sbr_profile_enable(ctx, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -313,17 +341,14 @@ def main():
         del handles
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    kernels = {}
-    for name in ["bounce", "replay_capture", "rebuild", "channel", "keys", "sort", "scan", "order", "bvh",
-                 "stats", "misc", "alpha", "host:scene_build", "host:scene_inputs", "host:face_groups",
-                 "host:scene_upload", "host:rx_tree"]:
-        ms, n = S.sbr_profile_query(ctx, name)
-        if n:
-            kernels[name] = {"ms_per_step": ms / args.steps, "launches_per_step": n / args.steps}
+    bounce_ms_total, bounce_launches = S.sbr_profile_query(ctx, "bounce")
     S.sbr_profile_enable(ctx, False)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = segments * args.steps / (t1 - t0)
     log(f"[bench] {args.steps} steps: {ms_per_step:.2f} ms/step, {value:.4g} segments/s")
+    kernels = {"bounce": {"ms_per_step": bounce_ms_total / args.steps,
+                          "launches_per_step": bounce_launches / args.steps}}
+    kernels.update(breakdown(S, ctx, lambda: step(S, ctx, w, d), exclude=("bounce",)))
 
     # work counts for the dominant kernel (a separate, untimed trace)
     S.sbr_context_count_work(ctx, True)

@@ -195,6 +195,11 @@ sbr_status sbr_scene_groups(sbr_scene_t s, int32_t* group, int32_t* plane);
  * "bvh", "keys", "stats", "capacity", "alpha", "misc").  Enabling clears the
  * totals; a query synchronises the stream.  Unknown names report 0. */
 sbr_status sbr_profile_enable(sbr_context_t ctx, int enable);
+/* Restrict the live timing to one kernel class (its launches only, no host
+ * phases), so that measuring one kernel adds two event records per launch of
+ * that class and nothing else; NULL or "" times every class again.  Clears
+ * the totals.  Unknown names time nothing. */
+sbr_status sbr_profile_only(sbr_context_t ctx, const char* kernel);
 sbr_status sbr_profile_query(sbr_context_t ctx, const char* kernel, double* total_ms, int64_t* launches);
 /* Traversal work counters: with counting enabled (sbr_context_count_work),
  * later traces also count BVH node visits and ray-triangle tests of the

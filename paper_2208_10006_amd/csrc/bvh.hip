@@ -189,6 +189,7 @@ __global__ void k_single_leaf(const float* __restrict__ lo, const float* __restr
 // contiguous range of nodes, as in the linear BVH: the rays of a wave walking
 // nearby subtrees then share cache lines.
 constexpr int kPlocThreads = 1024, kPlocR = 16, kPlocTile = kPlocThreads + 2 * kPlocR;
+constexpr int kPlocLds = 2 * kPlocThreads;  // clusters kept in LDS for the last passes
 constexpr int64_t kPlocMax = kBvhPlocMax;  // pair keys hold two 16-bit cluster indices
 static_assert(kPlocMax <= 65536, "PLOC pair keys hold 16-bit cluster indices");
 
@@ -221,6 +222,9 @@ __device__ inline float merged_area(const float a[6], const float b[6]) {
 __global__ __launch_bounds__(kPlocThreads) void k_ploc(const PlocArgs A) {
   __shared__ float sb[6][kPlocTile];
   __shared__ uint32_t wsum[kPlocThreads / 64];
+  // the passes with at most kPlocLds clusters keep them in LDS
+  __shared__ float lb[6][kPlocLds];
+  __shared__ int32_t lid[kPlocLds], lht[kPlocLds], lsz[kPlocLds], lnn[kPlocLds];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int n = A.n;
   for (int i = t; i < n; i += kPlocThreads) {
@@ -238,7 +242,7 @@ __global__ __launch_bounds__(kPlocThreads) void k_ploc(const PlocArgs A) {
   // every pass merges at least one pair, so n - 1 passes always suffice; the
   // bound only guarantees that the loop ends
   int pass = 0;
-  for (; m > 1 && pass < n; ++pass) {
+  for (; m > kPlocLds && pass < n; ++pass) {
     if (t == 0) A.pass_next[pass] = next;
     const float* B = A.box[cur];
     // ---- nearest neighbours, one tile of kPlocThreads clusters at a time
@@ -328,13 +332,108 @@ __global__ __launch_bounds__(kPlocThreads) void k_ploc(const PlocArgs A) {
     m = kept;
     cur ^= 1;
   }
+  // ---- the remaining passes in LDS: each thread owns clusters t and
+  // t + kPlocThreads, reads everything it needs, and after a barrier writes
+  // the compacted clusters in place
+  const bool in_lds = m <= kPlocLds;
+  if (in_lds) {
+    for (int i = t; i < m; i += kPlocThreads) {
+      for (int c = 0; c < 6; ++c) lb[c][i] = A.box[cur][c * n + i];
+      lid[i] = A.id[cur][i], lht[i] = A.ht[cur][i], lsz[i] = A.sz[cur][i];
+    }
+    __syncthreads();
+    for (; m > 1 && pass < n; ++pass) {
+      if (t == 0) A.pass_next[pass] = next;
+      for (int i = t; i < m; i += kPlocThreads) {
+        float a[6];
+        for (int c = 0; c < 6; ++c) a[c] = lb[c][i];
+        uint64_t best = ~0ull;
+        const int j0 = max(0, i - kPlocR), j1 = min(m - 1, i + kPlocR);
+        for (int j = j0; j <= j1; ++j) {
+          if (j == i) continue;
+          float b[6];
+          for (int c = 0; c < 6; ++c) b[c] = lb[c][j];
+          const uint32_t lo = (uint32_t)min(i, j), hi = (uint32_t)max(i, j);
+          const uint64_t key = ((uint64_t)__float_as_uint(merged_area(a, b)) << 32) | (lo << 16) | hi;
+          best = key < best ? key : best;
+        }
+        const uint32_t lo = (uint32_t)(best >> 16) & 0xffffu, hi = (uint32_t)best & 0xffffu;
+        lnn[i] = min((int)(lo == (uint32_t)i ? hi : lo), m - 1);
+      }
+      __syncthreads();
+      int kept = 0, merged = 0;
+      bool wkeep[2];
+      int wpos[2];
+      float wbox[2][6];
+      int32_t wid[2], wht[2], wsz[2];
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int i = t + e * kPlocThreads;
+        int j = -1;
+        bool keep = false, merge = false;
+        if (i < m) {
+          j = lnn[i];
+          const bool mutual = lnn[j] == i;
+          merge = mutual && i < j;
+          keep = !mutual || i < j;
+        }
+        const uint32_t x = wave_inclusive_scan((keep ? 1u : 0u) | (merge ? 0x10000u : 0u), lane);
+        if (lane == 63) wsum[wv] = x;
+        __syncthreads();
+        uint32_t before = 0, total = 0;
+        for (int w = 0; w < kPlocThreads / 64; ++w) {
+          const uint32_t sw = wsum[w];
+          before += w < wv ? sw : 0u;
+          total += sw;
+        }
+        const uint32_t excl = before + x - ((keep ? 1u : 0u) | (merge ? 0x10000u : 0u));
+        wkeep[e] = keep;
+        wpos[e] = kept + (int)(excl & 0xffffu);
+        if (keep) {
+          for (int c = 0; c < 6; ++c) wbox[e][c] = lb[c][i];
+          wid[e] = lid[i], wht[e] = lht[i], wsz[e] = lsz[i];
+          if (merge) {
+            const int node = next - merged - (int)(excl >> 16);
+            float b[6];
+            for (int c = 0; c < 6; ++c) b[c] = lb[c][j];
+            const float* a = wbox[e];
+            A.tmp[4 * node] = make_float4(a[0], a[1], a[2], a[3]);
+            A.tmp[4 * node + 1] = make_float4(a[4], a[5], b[0], b[1]);
+            A.tmp[4 * node + 2] = make_float4(b[2], b[3], b[4], b[5]);
+            A.tmp[4 * node + 3] = make_float4(__int_as_float(wid[e]), __int_as_float(lid[j]), 0.0f, 0.0f);
+            for (int c = 0; c < 3; ++c)
+              wbox[e][c] = fminf(wbox[e][c], b[c]), wbox[e][3 + c] = fmaxf(wbox[e][3 + c], b[3 + c]);
+            wht[e] = 1 + max(wht[e], lht[j]);
+            wsz[e] = 1 + wsz[e] + lsz[j];
+            A.nsz[node] = wsz[e];
+            wid[e] = node;
+          }
+        }
+        kept += (int)(total & 0xffffu);
+        merged += (int)(total >> 16);
+        __syncthreads();  // wsum is rewritten next; all reads of this pass are done after the last one
+      }
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+        if (wkeep[e]) {
+          const int pos = wpos[e];
+          for (int c = 0; c < 6; ++c) lb[c][pos] = wbox[e][c];
+          lid[pos] = wid[e], lht[pos] = wht[e], lsz[pos] = wsz[e];
+        }
+      __syncthreads();
+      next -= merged;
+      m = kept;
+    }
+  }
   if (t == 0) {
-    for (int c = 0; c < 6; ++c) A.root_box[c] = A.box[cur][c * n];
-    *A.depth = m == 1 ? (uint32_t)A.ht[cur][0] : 0xffffffffu;
+    if (in_lds) {
+      for (int c = 0; c < 6; ++c) A.root_box[c] = lb[c][0];
+    }
+    *A.depth = in_lds && m == 1 ? (uint32_t)lht[0] : 0xffffffffu;
     A.pass_next[pass] = next;  // = -1 once the root exists
     A.dfs[0] = 0;
   }
-  if (m != 1) return;
+  if (!in_lds || m != 1) return;
   __syncthreads();
   // ---- depth-first numbering: a node's parent was created in a later pass,
   // so walking the passes backwards numbers every parent before its children
@@ -368,18 +467,22 @@ inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 }  // namespace
 
 int build_bvh(const float* box_lo, const float* box_hi, int64_t n, const float scene_lo[3], const float scene_hi[3],
-              BvhOut out, hipStream_t s) {
+              BvhOut out, hipStream_t s, bool linear) {
   SBR_CHECK(n >= 1 && n < (int64_t(1) << 31), SBR_E_UNSUPPORTED, "BVH over %lld primitives", (long long)n);
   if (n == 1) {
     { ::sbr::TimedLaunch tl_("bvh", s); hipLaunchKernelGGL(k_single_leaf, dim3(1), dim3(1), 0, s, box_lo, box_hi, out.nodes, out.order, out.root_box); }
     SBR_LAUNCH_CHECK();
+    if (out.depth_dev) {
+      fill_u32(out.depth_dev, 1, 1, s);
+      return 0;
+    }
     if (out.root_host) {
       SBR_HIP(hipMemcpyAsync(out.root_host, out.root_box, 24, hipMemcpyDeviceToHost, s));
       SBR_HIP(hipStreamSynchronize(s));
     }
     return 1;
   }
-  const bool ploc = n <= kPlocMax;
+  const bool ploc = !linear && n <= kPlocMax;
   Buf codes, codes2, idx, parents, flags, temp;
   codes.alloc(n * 8, s);
   codes2.alloc(n * 8, s);
@@ -401,7 +504,7 @@ int build_bvh(const float* box_lo, const float* box_hi, int64_t n, const float s
   SBR_LAUNCH_CHECK();
   radix_sort_pairs(codes.as<uint64_t>(), idx.as<uint32_t>(), codes2.as<uint64_t>(), out.order, n, 0, 30,
                    temp.p, s);
-  uint32_t* dd = flags.as<uint32_t>() + n;
+  uint32_t* dd = out.depth_dev ? out.depth_dev : flags.as<uint32_t>() + n;
   if (ploc) {
     PlocArgs A{};
     A.lo = box_lo, A.hi = box_hi, A.order = out.order, A.n = (int)n;
@@ -414,6 +517,7 @@ int build_bvh(const float* box_lo, const float* box_hi, int64_t n, const float s
     A.nodes = out.nodes, A.root_box = out.root_box, A.depth = dd;
     { ::sbr::TimedLaunch tl_("bvh", s); hipLaunchKernelGGL(k_ploc, dim3(1), dim3(kPlocThreads), 0, s, A); }
     SBR_LAUNCH_CHECK();
+    if (out.depth_dev) return 0;
     uint32_t depth = 0;
     SBR_HIP(hipMemcpyAsync(&depth, dd, 4, hipMemcpyDeviceToHost, s));
     if (out.root_host) SBR_HIP(hipMemcpyAsync(out.root_host, out.root_box, 24, hipMemcpyDeviceToHost, s));
@@ -433,6 +537,7 @@ int build_bvh(const float* box_lo, const float* box_hi, int64_t n, const float s
   fill_u32(dd, 0, 1, s);
   { ::sbr::TimedLaunch tl_("bvh", s); hipLaunchKernelGGL(k_depth, dim3(blocks(n, 256)), dim3(256), 0, s, pint, pleaf, n, dd); }
   SBR_LAUNCH_CHECK();
+  if (out.depth_dev) return 0;
   uint32_t depth = 0;
   SBR_HIP(hipMemcpyAsync(&depth, dd, 4, hipMemcpyDeviceToHost, s));
   if (out.root_host) SBR_HIP(hipMemcpyAsync(out.root_host, out.root_box, 24, hipMemcpyDeviceToHost, s));

@@ -8,7 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
-#include <unordered_map>
+#include <mutex>
 #include <vector>
 
 #include "sbr_device.hpp"
@@ -27,33 +27,103 @@ void set_error(const char* fmt, ...) {
   g_err = buf;
 }
 
+namespace {
+struct CachedBlock {
+  void* p;
+  size_t cap;
+  hipStream_t s;
+};
+std::mutex g_cache_mu;
+std::vector<CachedBlock> g_cache;  // oldest first
+size_t g_cache_bytes = 0;
+constexpr size_t kCacheMax = size_t(4) << 30;       // cached bytes over all streams
+constexpr size_t kCacheBlockMax = size_t(256) << 20;  // larger blocks are freed at once
+// block size for a request: 1/16 steps of the power of two above it, at least 4 KiB
+size_t block_size(size_t n) {
+  if (n <= 4096) return 4096;
+  size_t q = 4096;
+  while (q < n) q <<= 1;
+  const size_t g = std::max<size_t>(q / 16, 4096);
+  return (n + g - 1) / g * g;
+}
+}  // namespace
+
 void Buf::alloc(size_t n, hipStream_t s) {
   reset();
-  stream = s;
-  bytes = n;
-  if (n == 0) n = 16;
-  hipError_t e = hipMallocAsync(&p, n, s);
+  const size_t want = block_size(n);
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    int best = -1;
+    for (size_t i = 0; i < g_cache.size(); ++i) {
+      const CachedBlock& b = g_cache[i];
+      if (b.s == s && b.cap >= want && b.cap <= 2 * want && (best < 0 || b.cap < g_cache[best].cap)) best = (int)i;
+    }
+    if (best >= 0) {
+      p = g_cache[best].p, cap = g_cache[best].cap;
+      g_cache_bytes -= cap;
+      g_cache.erase(g_cache.begin() + best);
+      stream = s, bytes = n;
+      return;
+    }
+  }
+  hipError_t e = hipMallocAsync(&p, want, s);
   if (e != hipSuccess) {
     p = nullptr;
-    bytes = 0;
-    set_error("device allocation of %zu bytes failed: %s", n, hipGetErrorString(e));
+    set_error("device allocation of %zu bytes failed: %s", want, hipGetErrorString(e));
     throw Error{SBR_E_OUT_OF_MEMORY};
   }
+  stream = s, bytes = n, cap = want;
 }
 
 void Buf::reset() {
-  if (p) (void)hipFreeAsync(p, stream);
+  if (p) {
+    if (cap > kCacheBlockMax) {
+      (void)hipFreeAsync(p, stream);
+    } else {
+      std::lock_guard<std::mutex> lk(g_cache_mu);
+      g_cache.push_back(CachedBlock{p, cap, stream});
+      g_cache_bytes += cap;
+      while (g_cache_bytes > kCacheMax && !g_cache.empty()) {
+        (void)hipFreeAsync(g_cache.front().p, g_cache.front().s);
+        g_cache_bytes -= g_cache.front().cap;
+        g_cache.erase(g_cache.begin());
+      }
+    }
+  }
   p = nullptr;
   bytes = 0;
+  cap = 0;
+}
+
+void buf_cache_flush(hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  for (size_t i = 0; i < g_cache.size();) {
+    if (g_cache[i].s == s) {
+      (void)hipFreeAsync(g_cache[i].p, s);
+      g_cache_bytes -= g_cache[i].cap;
+      g_cache.erase(g_cache.begin() + i);
+    } else {
+      ++i;
+    }
+  }
 }
 
 thread_local Prof* g_prof = nullptr;
 
 TimedLaunch::TimedLaunch(const char* n, hipStream_t st) : name(n), s(st) {
-  if (g_prof && g_prof->enabled) {
-    if (hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) {
+  if (g_prof && g_prof->wants(n)) {
+    auto take = [](hipEvent_t* e) {
+      if (!g_prof->spare.empty()) {
+        *e = g_prof->spare.back();
+        g_prof->spare.pop_back();
+        return true;
+      }
+      return hipEventCreate(e) == hipSuccess;
+    };
+    if (take(&a) && take(&b)) {
       (void)hipEventRecord(a, s);
     } else {
+      if (a) g_prof->spare.push_back(a);
       a = b = nullptr;
     }
   }
@@ -78,10 +148,10 @@ void prof_add(const char* name, double ms) {
   g_prof->acc.push_back({name, {ms, 1}});
 }
 HostPhase::HostPhase(const char* n) : name(n) {
-  if (g_prof && g_prof->enabled) t0 = now_ms();
+  if (g_prof && g_prof->enabled && g_prof->only.empty()) t0 = now_ms();
 }
 HostPhase::~HostPhase() {
-  if (g_prof && g_prof->enabled) prof_add(name, now_ms() - t0);
+  if (g_prof && g_prof->enabled && g_prof->only.empty()) prof_add(name, now_ms() - t0);
 }
 
 void Prof::resolve() {
@@ -97,14 +167,19 @@ void Prof::resolve() {
         found = true;
       }
     if (!found) acc.push_back({p.name, {(double)ms, 1}});
-    (void)hipEventDestroy(p.a);
-    (void)hipEventDestroy(p.b);
+    spare.push_back(p.a);
+    spare.push_back(p.b);
   }
   pending.clear();
 }
 void Prof::clear() {
   resolve();
   acc.clear();
+}
+void Prof::destroy_events() {
+  resolve();
+  for (hipEvent_t e : spare) (void)hipEventDestroy(e);
+  spare.clear();
 }
 
 void retain(Handle* h) { h->refs.fetch_add(1); }
@@ -222,6 +297,42 @@ struct Key4Hash {
   }
 };
 
+// Open-addressing map from Key4 to an int (linear probing, power-of-two
+// capacity of at least twice the entries); -1 marks an empty slot's value.
+struct FlatMap4 {
+  std::vector<Key4> keys;
+  std::vector<int> vals;
+  size_t mask = 0;
+  explicit FlatMap4(size_t n) {
+    size_t cap = 16;
+    while (cap < 2 * n + 16) cap <<= 1;
+    keys.resize(cap);
+    vals.assign(cap, -1);
+    mask = cap - 1;
+  }
+  size_t slot(const Key4& k) const {
+    uint64_t h = (uint64_t)Key4Hash{}(k);
+    h ^= h >> 33;
+    h *= 0xff51afd7ed558ccdull;
+    h ^= h >> 33;
+    size_t i = (size_t)h & mask;
+    while (vals[i] >= 0 && !(keys[i] == k)) i = (i + 1) & mask;
+    return i;
+  }
+  // value stored for k, or -1
+  int get(const Key4& k) const { return vals[slot(k)]; }
+  // value stored for k; stores v first when k is absent
+  int get_or_put(const Key4& k, int v) {
+    const size_t i = slot(k);
+    if (vals[i] < 0) keys[i] = k, vals[i] = v;
+    return vals[i];
+  }
+  void put(const Key4& k, int v) {
+    const size_t i = slot(k);
+    keys[i] = k, vals[i] = v;
+  }
+};
+
 int uf_find(std::vector<int>& p, int x) {
   while (p[x] != x) {
     p[x] = p[p[x]];
@@ -284,18 +395,16 @@ void face_groups(const std::vector<Plane>& pl, const float* eps, const float* si
   };
   std::vector<Class> classes;
   {
-    std::unordered_map<Key4, int, Key4Hash> cls;
-    cls.reserve(T * 2 + 1);
+    FlatMap4 cls((size_t)T);
     for (int t = 0; t < T; ++t) {
       const Key4 k{bits(cn[t].v[0]), bits(cn[t].v[1]), bits(cn[t].v[2]), bits(cn[t].v[3])};
-      auto it = cls.find(k);
+      const int q = cls.get_or_put(k, (int)classes.size());
       const std::array<float, 3> m{eps[t], sig[t], rough[t]};
-      if (it == cls.end()) {
-        cls.emplace(k, (int)classes.size());
+      if (q == (int)classes.size()) {
         classes.push_back(Class{t, {{m, t}}});
         continue;
       }
-      Class& C = classes[it->second];
+      Class& C = classes[q];
       uf_join(pp, C.rep, t);
       bool found = false;
       for (auto& mt : C.mats)
@@ -308,11 +417,14 @@ void face_groups(const std::vector<Plane>& pl, const float* eps, const float* si
     }
   }
   const int NC = (int)classes.size();
-  std::unordered_map<Key4, std::vector<int>, Key4Hash> grid;  // cell -> classes
-  grid.reserve(NC * 2 + 1);
+  // cell -> classes, as a list threaded through next_in_cell
+  FlatMap4 grid((size_t)NC);
+  std::vector<int> next_in_cell(NC, -1);
   for (int q = 0; q < NC; ++q) {
     const double* v = cn[classes[q].rep].v;
-    grid[Key4{cell(v, 0), cell(v, 1), cell(v, 2), cell(v, 3)}].push_back(q);
+    const Key4 k{cell(v, 0), cell(v, 1), cell(v, 2), cell(v, 3)};
+    next_in_cell[q] = grid.get(k);
+    grid.put(k, q);
   }
   for (int qa = 0; qa < NC; ++qa) {
     const int a = classes[qa].rep;
@@ -332,9 +444,8 @@ void face_groups(const std::vector<Plane>& pl, const float* eps, const float* si
         for (int dy = lo[1]; dy <= hi[1]; ++dy)
           for (int dz = lo[2]; dz <= hi[2]; ++dz)
             for (int dc = lo[3]; dc <= hi[3]; ++dc) {
-              auto it = grid.find(Key4{base[0] + dx, base[1] + dy, base[2] + dz, base[3] + dc});
-              if (it == grid.end()) continue;
-              for (int qb : it->second) {
+              for (int qb = grid.get(Key4{base[0] + dx, base[1] + dy, base[2] + dz, base[3] + dc}); qb >= 0;
+                   qb = next_in_cell[qb]) {
                 if (qb == qa) continue;
                 const int b = classes[qb].rep;
                 const double nd = pl[a].n[0] * pl[b].n[0] + pl[a].n[1] * pl[b].n[1] + pl[a].n[2] * pl[b].n[2];
@@ -444,8 +555,13 @@ sbr_context_s::~sbr_context_s() {
   if (stream) (void)hipStreamSynchronize(stream);
   for (auto& b : scratch) b.reset();
   for (auto* g : graphs) delete g;
+  if (stream) {
+    buf_cache_flush(stream);
+    (void)hipStreamSynchronize(stream);
+  }
   if (stage) (void)hipHostFree(stage);
   prof.clear();
+  prof.destroy_events();
   if (g_prof == &prof) g_prof = nullptr;
   if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
@@ -586,49 +702,18 @@ sbr_status sbr_scene_build(sbr_context_t ctx, const double* tri_xyz, int64_t T, 
         sc->diag = std::sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
                              (hi[2] - lo[2]) * (hi[2] - lo[2]));
       }
-      std::vector<Plane> pl((size_t)T);
-      for (int64_t t = 0; t < T; ++t) {
-        const d3 a = ld3(&tri[9 * t]), b = ld3(&tri[9 * t + 3]), cc = ld3(&tri[9 * t + 6]);
-        const d3 nn = cross(b - a, cc - a);
-        const double area2 = norm(nn);
-        SBR_CHECK(0.5 * area2 > 1e-12 * sc->diag * sc->diag, SBR_E_INVALID_ARG,
-                  "triangle %lld is degenerate (area %g)", (long long)t, 0.5 * area2);
-        const d3 n = nn * (1.0 / area2);
-        pl[t] = Plane{{n.x, n.y, n.z}, dot(n, a)};
-      }
-      {
-        HostPhase hp("host:face_groups");
-        face_groups(pl, er.data(), sg.data(), rh.data(), sc->diag, sc->h_group, sc->h_plane, sc->n_groups,
-                    sc->n_planes);
-      }
       if (T == 0) {
+        HostPhase hp("host:face_groups");
+        face_groups({}, er.data(), sg.data(), rh.data(), sc->diag, sc->h_group, sc->h_plane, sc->n_groups,
+                    sc->n_planes);
         sc->gstart.alloc(4, s);
         fill_u32(sc->gstart.as<uint32_t>(), 0, 1, s);
         SBR_HIP(hipStreamSynchronize(s));
         *out = sc;
         return;
       }
-      // per-triangle FP64 planes, per-group plane/material/members
-      std::vector<double4> tpl((size_t)T);
-      for (int64_t t = 0; t < T; ++t) tpl[t] = make_double4(pl[t].n[0], pl[t].n[1], pl[t].n[2], pl[t].c);
-      const int G = sc->n_groups;
-      std::vector<int32_t> gfirst(G, -1), gstart(G + 1, 0), gtri((size_t)T), fill(G, 0);
-      for (int64_t t = 0; t < T; ++t) {
-        const int g = sc->h_group[t];
-        if (gfirst[g] < 0) gfirst[g] = (int)t;
-        gstart[g + 1]++;
-      }
-      for (int g = 0; g < G; ++g) gstart[g + 1] += gstart[g];
-      for (int64_t t = 0; t < T; ++t) {
-        const int g = sc->h_group[t];
-        gtri[gstart[g] + fill[g]++] = (int)t;
-      }
-      std::vector<double4> gpl(G);
-      std::vector<float4> gmt(G);
-      for (int g = 0; g < G; ++g) {
-        gpl[g] = tpl[gfirst[g]];
-        gmt[g] = make_float4(er[gfirst[g]], sg[gfirst[g]], rh[gfirst[g]], 0.0f);
-      }
+      // ---- geometry the tree needs, uploaded first so that the GPU builds
+      // the BVH while the host groups faces
       // Scenes built with the Morton-ordered LBVH (above kBvhPlocMax
       // triangles) keep oversized triangles (box diagonal above a quarter of
       // the scene's, at most kMaxBig, largest first) out of the tree: there
@@ -679,11 +764,11 @@ sbr_status sbr_scene_build(sbr_context_t ctx, const double* tri_xyz, int64_t T, 
         }
       }
       Buf dv32, dlo, dhi, order, dbvh_ids, dbig_ids;
-      HostPhase hp_up("host:scene_upload");
-      // staging must hold everything before the first copy is issued (it is not resized in use)
-      const size_t need = tri.size() * 8 + tpl.size() * 32 + 2 * sc->h_group.size() * 4 + gpl.size() * 32 +
-                          gmt.size() * 16 + gstart.size() * 4 + gtri.size() * 4 + (v32.size() + 6 * T) * 4 +
-                          (size_t)T * 4 + 20 * 256;
+      // staging must hold everything before the first copy is issued (it is
+      // not resized in use); the group arrays are bounded by G <= T
+      const size_t need = tri.size() * 8 + (size_t)T * 32 + 2 * (size_t)T * 4 + (size_t)T * 32 + (size_t)T * 16 +
+                          ((size_t)T + 1) * 4 + (size_t)T * 4 + (v32.size() + 6 * T) * 4 + (size_t)T * 4 +
+                          20 * 256;
       if (c->stage_bytes < need) {
         if (c->stage) (void)hipHostFree(c->stage);
         c->stage = nullptr;
@@ -692,35 +777,76 @@ sbr_status sbr_scene_build(sbr_context_t ctx, const double* tri_xyz, int64_t T, 
         c->stage_bytes = need;
       }
       Stager st(c);
-      st.put(sc->tri64, tri.data(), tri.size(), s);
-      st.put(sc->tplane, tpl.data(), tpl.size(), s);
-      st.put(sc->tgroup, sc->h_group.data(), sc->h_group.size(), s);
-      st.put(sc->tplaneid, sc->h_plane.data(), sc->h_plane.size(), s);
-      st.put(sc->gplane, gpl.data(), gpl.size(), s);
-      st.put(sc->gmat, gmt.data(), gmt.size(), s);
-      st.put(sc->gstart, gstart.data(), gstart.size(), s);
-      st.put(sc->gtri, gtri.data(), gtri.size(), s);
-      st.put(dv32, v32.data(), v32.size(), s);
-      st.put(dlo, blo.data(), blo.size(), s);
-      st.put(dhi, bhi.data(), bhi.size(), s);
-      st.put(dbvh_ids, bvh_ids.data(), bvh_ids.size(), s);
-      st.put(dbig_ids, big_ids.data(), big_ids.size(), s);
+      {
+        HostPhase hp_up("host:scene_upload");
+        st.put(dv32, v32.data(), v32.size(), s);
+        st.put(dlo, blo.data(), blo.size(), s);
+        st.put(dhi, bhi.data(), bhi.size(), s);
+        st.put(dbvh_ids, bvh_ids.data(), bvh_ids.size(), s);
+      }
       sc->nodes.alloc((size_t)std::max<int64_t>(sc->n_bvh - 1, 1) * 64, s);
-      sc->root_box.alloc(32, s);
+      sc->root_box.alloc(32, s);  // 6 floats of root box, then the depth word
       sc->tri32.alloc((size_t)T * 48, s);
+      uint32_t* depth_dev = reinterpret_cast<uint32_t*>(sc->root_box.as<float>() + 6);
       if (sc->n_bvh > 0) {
         order.alloc((size_t)sc->n_bvh * 4, s);
-        sc->bvh_depth = build_bvh(dlo.as<float>(), dhi.as<float>(), sc->n_bvh, slo, shi,
-                                   BvhOut{sc->nodes.as<float4>(), order.as<uint32_t>(), sc->root_box.as<float>(),
-                                          sc->root_host}, s);
-        SBR_CHECK(sc->bvh_depth <= 64, SBR_E_UNSUPPORTED, "BVH depth %d exceeds the traversal stack",
-                  sc->bvh_depth);
+        build_bvh(dlo.as<float>(), dhi.as<float>(), sc->n_bvh, slo, shi,
+                  BvhOut{sc->nodes.as<float4>(), order.as<uint32_t>(), sc->root_box.as<float>(), nullptr, depth_dev}, s);
+      }
+      // ---- planes, face groups and group tables on the host (overlapping the build)
+      std::vector<Plane> pl((size_t)T);
+      for (int64_t t = 0; t < T; ++t) {
+        const d3 a = ld3(&tri[9 * t]), b = ld3(&tri[9 * t + 3]), cc = ld3(&tri[9 * t + 6]);
+        const d3 nn = cross(b - a, cc - a);
+        const double area2 = norm(nn);
+        SBR_CHECK(0.5 * area2 > 1e-12 * sc->diag * sc->diag, SBR_E_INVALID_ARG,
+                  "triangle %lld is degenerate (area %g)", (long long)t, 0.5 * area2);
+        const d3 n = nn * (1.0 / area2);
+        pl[t] = Plane{{n.x, n.y, n.z}, dot(n, a)};
+      }
+      {
+        HostPhase hp("host:face_groups");
+        face_groups(pl, er.data(), sg.data(), rh.data(), sc->diag, sc->h_group, sc->h_plane, sc->n_groups,
+                    sc->n_planes);
+      }
+      // per-triangle FP64 planes, per-group plane/material/members
+      std::vector<double4> tpl((size_t)T);
+      for (int64_t t = 0; t < T; ++t) tpl[t] = make_double4(pl[t].n[0], pl[t].n[1], pl[t].n[2], pl[t].c);
+      const int G = sc->n_groups;
+      std::vector<int32_t> gfirst(G, -1), gstart(G + 1, 0), gtri((size_t)T), fill(G, 0);
+      for (int64_t t = 0; t < T; ++t) {
+        const int g = sc->h_group[t];
+        if (gfirst[g] < 0) gfirst[g] = (int)t;
+        gstart[g + 1]++;
+      }
+      for (int g = 0; g < G; ++g) gstart[g + 1] += gstart[g];
+      for (int64_t t = 0; t < T; ++t) {
+        const int g = sc->h_group[t];
+        gtri[gstart[g] + fill[g]++] = (int)t;
+      }
+      std::vector<double4> gpl(G);
+      std::vector<float4> gmt(G);
+      for (int g = 0; g < G; ++g) {
+        gpl[g] = tpl[gfirst[g]];
+        gmt[g] = make_float4(er[gfirst[g]], sg[gfirst[g]], rh[gfirst[g]], 0.0f);
+      }
+      {
+        HostPhase hp_up("host:scene_upload");
+        st.put(sc->tri64, tri.data(), tri.size(), s);
+        st.put(sc->tplane, tpl.data(), tpl.size(), s);
+        st.put(sc->tgroup, sc->h_group.data(), sc->h_group.size(), s);
+        st.put(sc->tplaneid, sc->h_plane.data(), sc->h_plane.size(), s);
+        st.put(sc->gplane, gpl.data(), gpl.size(), s);
+        st.put(sc->gmat, gmt.data(), gmt.size(), s);
+        st.put(sc->gstart, gstart.data(), gstart.size(), s);
+        st.put(sc->gtri, gtri.data(), gtri.size(), s);
+        st.put(dbig_ids, big_ids.data(), big_ids.size(), s);
+      }
+      if (sc->n_bvh > 0) {
         hipLaunchKernelGGL(k_tri_gather, dim3(nblk(sc->n_bvh, 256)), dim3(256), 0, s, order.as<uint32_t>(),
                            dbvh_ids.as<int32_t>(), sc->n_bvh, (int64_t)0, dv32.as<float>(),
                            sc->tplaneid.as<int32_t>(), sc->tgroup.as<int32_t>(), sc->tri32.as<float4>());
         SBR_LAUNCH_CHECK();
-      } else {
-        sc->bvh_depth = 1;
       }
       if (sc->n_big > 0) {
         hipLaunchKernelGGL(k_tri_gather, dim3(1), dim3(64), 0, s, (const uint32_t*)nullptr, dbig_ids.as<int32_t>(),
@@ -728,11 +854,26 @@ sbr_status sbr_scene_build(sbr_context_t ctx, const double* tri_xyz, int64_t T, 
                            sc->tgroup.as<int32_t>(), sc->tri32.as<float4>());
         SBR_LAUNCH_CHECK();
       }
-      // The staged copies were consumed before the BVH depth readback synchronised
-      // the stream (without a tree, synchronise here so the staging area is free);
-      // the leaf gather runs in stream order before any trace of this scene.
-      if (sc->n_bvh == 0) SBR_HIP(hipStreamSynchronize(s));
+      // one synchronisation: root box and depth of the tree; it also frees the staging area
+      sc->bvh_depth = 1;
+      if (sc->n_bvh > 0) {
+        float rb[7];
+        SBR_HIP(hipMemcpyAsync(rb, sc->root_box.p, sizeof rb, hipMemcpyDeviceToHost, s));
+        SBR_HIP(hipStreamSynchronize(s));
+        for (int k = 0; k < 6; ++k) sc->root_host[k] = rb[k];
+        uint32_t depth;
+        std::memcpy(&depth, &rb[6], 4);
+        SBR_CHECK(depth != 0xffffffffu, SBR_E_DEVICE, "BVH clustering did not reach a single root");
+        sc->bvh_depth = (int)depth;
+        SBR_CHECK(sc->bvh_depth <= 64, SBR_E_UNSUPPORTED, "BVH depth %d exceeds the traversal stack",
+                  sc->bvh_depth);
+      } else {
+        SBR_HIP(hipStreamSynchronize(s));
+      }
     } catch (...) {
+      // copies from the staging area and the tree build may still be in
+      // flight: let them finish before the scene and the staging area go
+      (void)hipStreamSynchronize(s);
       release(sc);
       throw;
     }
@@ -1175,6 +1316,15 @@ sbr_status sbr_profile_enable(sbr_context_t ctx, int enable) {
     set_device(c);
     c->prof.clear();
     c->prof.enabled = enable != 0;
+  });
+}
+
+sbr_status sbr_profile_only(sbr_context_t ctx, const char* kernel) {
+  return guard([&] {
+    auto* c = check_handle<sbr_context_s>(ctx, kContext, "context");
+    set_device(c);
+    c->prof.clear();
+    c->prof.only = kernel ? kernel : "";
   });
 }
 

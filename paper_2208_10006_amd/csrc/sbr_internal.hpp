@@ -77,9 +77,16 @@ void retain(Handle* h);
 void release(Handle* h);
 
 // device buffer owned by a handle (stream-ordered allocation)
+// Device buffer.  Blocks are stream-ordered allocations; a released block is
+// kept in a per-stream cache and handed to the next allocation of a fitting
+// size on the same stream without a HIP call (stream order makes the reuse
+// safe), so the many short-lived temporaries of an API call cost no runtime
+// calls once the sizes have been seen.  buf_cache_flush(stream) frees the
+// cached blocks of a stream before it goes away.
 struct Buf {
   void* p = nullptr;
   size_t bytes = 0;
+  size_t cap = 0;  // size of the block behind p
   hipStream_t stream = nullptr;
   Buf() = default;
   Buf(const Buf&) = delete;
@@ -89,18 +96,23 @@ struct Buf {
   void reset();
   template <class T> T* as() const { return static_cast<T*>(p); }
 };
+void buf_cache_flush(hipStream_t s);
 
 // Live kernel timing: HIP events around launches, accumulated per kernel class.
 struct Prof {
   bool enabled = false;
+  std::string only;  // time only this kernel class (and no host phases); empty: everything
   struct Pending {
     std::string name;
     hipEvent_t a, b;
   };
   std::vector<Pending> pending;
+  std::vector<hipEvent_t> spare;  // events returned by resolve(), reused by later launches
   std::vector<std::pair<std::string, std::pair<double, int64_t>>> acc;
+  bool wants(const char* name) const { return enabled && (only.empty() || only == name); }
   void resolve();  // synchronises on the recorded events
   void clear();
+  void destroy_events();
 };
 // the profiler of the context whose API call is running on this thread
 extern thread_local Prof* g_prof;
@@ -246,16 +258,20 @@ void gather_u64(const uint64_t* src, const uint32_t* idx, uint64_t* dst, int64_t
 
 // bvh.hip: BVH over n primitives given their FP32 boxes (lo, hi) -> nodes,
 // leaf permutation (sorted position -> primitive), root box.  PLOC clustering
-// up to kBvhPlocMax primitives, Karras LBVH beyond.  Returns the depth.
+// up to kBvhPlocMax primitives unless `linear` is set, Karras LBVH otherwise.
+// Returns the depth.
 constexpr int64_t kBvhPlocMax = 65536;
 struct BvhOut {
   float4* nodes;     // [max(n-1,1)][4]
   uint32_t* order;   // [n] primitive of each leaf
   float* root_box;   // [8]
   float* root_host;  // optional host copy of the root box (6 floats), filled before return
+  // optional: asynchronous build.  The depth is written to this device word
+  // and build_bvh returns 0 without synchronising (root_host is not filled).
+  uint32_t* depth_dev = nullptr;
 };
 int build_bvh(const float* box_lo, const float* box_hi, int64_t n, const float scene_lo[3],
-              const float scene_hi[3], BvhOut out, hipStream_t s);
+              const float scene_hi[3], BvhOut out, hipStream_t s, bool linear = false);
 
 // geodesic.hip
 void upload_geodesic_tables(int device);

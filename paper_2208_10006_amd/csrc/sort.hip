@@ -234,7 +234,7 @@ void gather_u64(const uint64_t* src, const uint32_t* idx, uint64_t* dst, int64_t
 // its digits, the workgroup computes the exclusive offsets of those counts in
 // (digit, thread) order, and each thread scatters its chunk in order into the
 // LDS arrays, which keeps the sort stable.
-constexpr int kSmallThreads = 512, kSmallPer = 24, kSmallSort = kSmallThreads * kSmallPer;
+constexpr int kSmallThreads = 1024, kSmallPer = 12, kSmallSort = kSmallThreads * kSmallPer;
 
 __global__ __launch_bounds__(kSmallThreads) void k_radix_sort_small(const uint64_t* __restrict__ kin,
                                                                   const uint32_t* __restrict__ vin,
@@ -266,17 +266,24 @@ __global__ __launch_bounds__(kSmallThreads) void k_radix_sort_small(const uint64
     const int shift = bit_lo + 4 * p;
     uint64_t ck[kSmallPer];
     uint32_t cv[kSmallPer];
-    uint32_t cnt[16];
-#pragma unroll
-    for (int d = 0; d < 16; ++d) cnt[d] = 0;
+    // digit counts of the chunk in byte lanes (a chunk holds < 256 keys):
+    // digits 0-7 in c0, 8-15 in c1
+    uint64_t c0 = 0, c1 = 0;
 #pragma unroll
     for (int u = 0; u < kSmallPer; ++u)
       if (u < m) {
         ck[u] = lk[i0 + u], cv[u] = lv[i0 + u];
-        const int d = (int)((ck[u] >> shift) & 15u);
-#pragma unroll
-        for (int q = 0; q < 16; ++q) cnt[q] += (q == d) ? 1u : 0u;
+        const uint32_t d = (uint32_t)(ck[u] >> shift) & 15u;
+        const uint64_t inc = 1ull << (8 * (d & 7u));
+        if (d < 8u) c0 += inc;
+        else c1 += inc;
       }
+    uint32_t cnt[16];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+      cnt[d] = (uint32_t)(c0 >> (8 * d)) & 0xffu;
+      cnt[8 + d] = (uint32_t)(c1 >> (8 * d)) & 0xffu;
+    }
     // exclusive offsets in (digit, thread) order.  Counts of digit pairs are
     // packed in 16-bit halves (no total exceeds kSmallSort < 2^16), scanned
     // across the wave with DPP, and the wave totals exchanged through LDS.

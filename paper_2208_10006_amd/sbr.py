@@ -75,6 +75,7 @@ def _load():
         "sbr_geodesic_alpha": [P, I32, P, P, P],
         "sbr_profile_enable": [P, C.c_int],
         "sbr_profile_query": [P, C.c_char_p, P, P],
+        "sbr_profile_only": [P, C.c_char_p],
         "sbr_context_count_work": [P, C.c_int],
         "sbr_trace_work": [P, P, P],
         "sbr_context_set_tuning": [P, C.c_char_p, I32],
@@ -383,6 +384,10 @@ def sbr_geodesic_alpha(ctx: Context, N: int):
 
 def sbr_profile_enable(ctx: Context, enable: bool = True):
     _call("sbr_profile_enable", ctx.h, int(enable))
+
+
+def sbr_profile_only(ctx: Context, kernel: Optional[str]):
+    _call("sbr_profile_only", ctx.h, kernel.encode() if kernel else None)
 
 
 def sbr_profile_query(ctx: Context, kernel: str):
