@@ -74,60 +74,62 @@ __device__ inline cd path_amplitude(const double* __restrict__ G, const FieldArg
   return cmul(pol, e);
 }
 
-constexpr int kChanThreads = 256;
-constexpr int kChanFPT = 4;  // frequencies per thread per chunk
-constexpr int kChanChunk = kChanThreads * kChanFPT;
+// One block per ((rx, tx) pair, tile of kChanTile frequencies): lane l of
+// every wave owns frequency tile * kChanTile + l, and the waves split the
+// pair's paths by index (wave w takes paths w, w + kChanWaves, ...).  Each
+// wave sums its paths in their stored order; the wave sums are then added in
+// wave order, so every entry of H has a fixed summation order.  The band power
+// of each path is reduced over the tile's lanes into part[n][tile]; a second
+// kernel adds the tiles in order.
+constexpr int kChanTile = 64, kChanWaves = 4, kChanThreads = kChanTile * kChanWaves;
 
 __global__ __launch_bounds__(kChanThreads) void k_channel(const double* __restrict__ geo, int stride,
                                                           const int32_t* __restrict__ seg_start, FieldArgs A, int Nr,
-                                                          int Nt, float2* __restrict__ H64, double2* __restrict__ H128,
-                                                          double* __restrict__ power) {
-  __shared__ double wsum[kChanThreads / kWave];
-  const int64_t seg = blockIdx.x;
+                                                          int Nt, int ntiles, float2* __restrict__ H64,
+                                                          double2* __restrict__ H128, double* __restrict__ part) {
+  __shared__ double sre[kChanWaves][kChanTile], sim[kChanWaves][kChanTile];
+  const int64_t seg = blockIdx.x / ntiles;
+  const int tile = (int)(blockIdx.x - seg * ntiles);
   const int q = (int)(seg / Nt), p = (int)(seg - (int64_t)q * Nt);
   const int n0 = seg_start[seg], n1 = seg_start[seg + 1];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int c0 = 0; c0 < A.Nf; c0 += kChanChunk) {
-    cd acc[kChanFPT];
-#pragma unroll
-    for (int j = 0; j < kChanFPT; ++j) acc[j] = cd{0.0, 0.0};
-    for (int n = n0; n < n1; ++n) {
-      const double* G = geo + (int64_t)n * stride;
-      double ps = 0.0;
-#pragma unroll
-      for (int j = 0; j < kChanFPT; ++j) {
-        const int fi = c0 + j * kChanThreads + threadIdx.x;
-        if (fi < A.Nf) {
-          const cd a = path_amplitude(G, A, fi);
-          acc[j] = cadd(acc[j], a);
-          ps += a.re * a.re + a.im * a.im;
-        }
-      }
-      if (power) {
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) ps += __shfl_xor(ps, o, 64);
-        if (lane == 0) wsum[wv] = ps;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-          double t = 0.0;
-          for (int w = 0; w < kChanThreads / kWave; ++w) t += wsum[w];
-          const double prev = c0 == 0 ? 0.0 : power[n];
-          const double tot = prev + t;
-          power[n] = (c0 + kChanChunk >= A.Nf) ? tot / (double)A.Nf : tot;
-        }
-        __syncthreads();
-      }
+  const int fi = tile * kChanTile + lane;
+  const bool on = fi < A.Nf;
+  cd acc{0.0, 0.0};
+  for (int n = n0 + wv; n < n1; n += kChanWaves) {
+    double ps = 0.0;
+    if (on) {
+      const cd a = path_amplitude(geo + (int64_t)n * stride, A, fi);
+      acc = cadd(acc, a);
+      ps = a.re * a.re + a.im * a.im;
     }
+    if (part) {
 #pragma unroll
-    for (int j = 0; j < kChanFPT; ++j) {
-      const int fi = c0 + j * kChanThreads + threadIdx.x;
-      if (fi < A.Nf) {
-        const int64_t o = ((int64_t)fi * Nr + q) * Nt + p;
-        if (H128) H128[o] = make_double2(acc[j].re, acc[j].im);
-        if (H64) H64[o] = make_float2((float)acc[j].re, (float)acc[j].im);
-      }
+      for (int o = 32; o > 0; o >>= 1) ps += __shfl_xor(ps, o, 64);
+      if (lane == 0) part[(int64_t)n * ntiles + tile] = ps;
     }
   }
+  sre[wv][lane] = acc.re;
+  sim[wv][lane] = acc.im;
+  __syncthreads();
+  if (wv == 0 && on) {
+    double re = sre[0][lane], im = sim[0][lane];
+#pragma unroll
+    for (int w = 1; w < kChanWaves; ++w) re += sre[w][lane], im += sim[w][lane];
+    const int64_t o = ((int64_t)fi * Nr + q) * Nt + p;
+    if (H128) H128[o] = make_double2(re, im);
+    if (H64) H64[o] = make_float2((float)re, (float)im);
+  }
+}
+
+// power[n] = band mean of |a_n(f)|^2: the tiles' partial sums added in order
+__global__ void k_power_final(const double* __restrict__ part, int64_t n, int ntiles, int Nf,
+                              double* __restrict__ power) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double t = 0.0;
+  for (int k = 0; k < ntiles; ++k) t += part[i * ntiles + k];
+  power[i] = t / (double)Nf;
 }
 
 __global__ void k_path_field(const double* __restrict__ geo, int stride, int64_t n, FieldArgs A,
@@ -322,11 +324,20 @@ FieldArgs field_args(const ChannelArgs& a) { return FieldArgs{a.freq, a.atm_db, 
 void run_channel(sbr_paths_s* ps, const ChannelArgs& a, float2* H64, double2* H128, hipStream_t s) {
   const int Nt = ps->trace->Nt, Nr = ps->Nr;
   const int64_t nseg = (int64_t)Nr * Nt;
-  SBR_CHECK(nseg < (int64_t(1) << 31), SBR_E_UNSUPPORTED, "too many (rx, tx) pairs");
-  { ::sbr::TimedLaunch tl_("channel", s); hipLaunchKernelGGL(k_channel, dim3((unsigned)nseg), dim3(kChanThreads), 0, s, ps->geo.as<double>(),
-                     geo_stride(ps->trace->K), ps->seg_start.as<int32_t>(), field_args(a), Nr, Nt, H64, H128,
-                     ps->power.as<double>()); }
+  const int ntiles = (int)((a.Nf + kChanTile - 1) / kChanTile);
+  SBR_CHECK(nseg * ntiles < (int64_t(1) << 31), SBR_E_UNSUPPORTED, "too many (rx, tx) pairs x frequency tiles");
+  const int64_t np = ps->n_paths;
+  Buf part;
+  part.alloc((size_t)std::max<int64_t>(np, 1) * ntiles * sizeof(double), s);
+  { ::sbr::TimedLaunch tl_("channel", s); hipLaunchKernelGGL(k_channel, dim3((unsigned)(nseg * ntiles)), dim3(kChanThreads), 0, s, ps->geo.as<double>(),
+                     geo_stride(ps->trace->K), ps->seg_start.as<int32_t>(), field_args(a), Nr, Nt, ntiles, H64, H128,
+                     part.as<double>()); }
   SBR_LAUNCH_CHECK();
+  if (np > 0) {
+    { ::sbr::TimedLaunch tl_("channel", s); hipLaunchKernelGGL(k_power_final, dim3(nblk(np, 256)), dim3(256), 0, s, part.as<double>(), np, ntiles, a.Nf,
+                       ps->power.as<double>()); }
+    SBR_LAUNCH_CHECK();
+  }
   ps->have_power = true;
 }
 
