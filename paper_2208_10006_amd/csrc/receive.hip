@@ -340,62 +340,81 @@ __device__ inline d3 mirror(d3 x, double4 pl) {
   return x - n * (2.0 * (dot(n, x) - pl.w));
 }
 
+// kRebuildLanes consecutive lanes of a wave serve one key: every lane
+// rebuilds the key's image points (a few FP64 steps), lane j checks the
+// bounces and legs j, j + kRebuildLanes, ... (face, side and occlusion
+// tests), a ballot over the key's lanes combines their verdicts, and the
+// key's first lane writes the outputs.  This keeps one traversal, not k + 1,
+// on each lane's dependent chain.
+constexpr int kRebuildLanes = 8;
+
 template <int STACK>
 __global__ __launch_bounds__(128) void k_rebuild(const RebuildParams P) {
   __shared__ int32_t stack_mem[128 / kWave][STACK][kWave];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int32_t* stk = &stack_mem[wv][0][lane];
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= P.n_keys) return;
-  if (i >= (int64_t)*P.n_keys_dev) {  // slot beyond the keys: no path
-    P.valid[i] = 0u;
-    return;
-  }
-  const uint32_t e = P.key_event[i];
+  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = gt / kRebuildLanes;
+  const int sub = (int)(gt % kRebuildLanes);
+  const int64_t nk = (int64_t)*P.n_keys_dev;
+  const bool have = i < P.n_keys && i < nk;
+  if (i < P.n_keys && i >= nk && sub == 0) P.valid[i] = 0u;  // slot beyond the keys: no path
+  uint32_t e = 0;
   int32_t g[SBR_MAX_BOUNCES];
-  const int k = ev_groups(P.kp, e, g);
-  const uint32_t rid = P.kp.ev_ray[e];
-  const int p = (int)(rid / P.kp.R);
-  const int q = (int)(P.kp.ev_qk[e] >> 5);
-  int32_t* kk = P.key + i * (4 + P.K);
-  kk[0] = p, kk[1] = q, kk[2] = k, kk[3] = 0;
-  for (int t = 0; t < P.K; ++t) kk[4 + t] = t < k ? g[t] : -1;
-  P.seg[i] = (uint64_t)q * (uint64_t)P.kp.Nt + (uint64_t)p;
-  const d3 T = ld3(P.tx + 3 * p), Rq = ld3(P.rx + 3 * q);
-  // images S_1..S_k
-  d3 S[SBR_MAX_BOUNCES + 1];
-  S[0] = T;
-  for (int t = 1; t <= k; ++t) S[t] = mirror(S[t - 1], P.gplane[g[t - 1]]);
+  int k = 0, p = 0, q = 0;
+  bool ok = have;
   d3 X[SBR_MAX_BOUNCES + 2];
-  X[0] = T;
-  X[k + 1] = Rq;
-  bool ok = true;
-  for (int t = k; t >= 1 && ok; --t) {
-    const double4 pl = P.gplane[g[t - 1]];
-    const d3 n = mk3(pl.x, pl.y, pl.z);
-    const d3 D = X[t + 1] - S[t];
-    const double den = dot(n, D);
-    if (den == 0.0) {
-      ok = false;
-      break;
+  if (have) {
+    e = P.key_event[i];
+    k = ev_groups(P.kp, e, g);
+    const uint32_t rid = P.kp.ev_ray[e];
+    p = (int)(rid / P.kp.R);
+    q = (int)(P.kp.ev_qk[e] >> 5);
+    if (sub == 0) {
+      int32_t* kk = P.key + i * (4 + P.K);
+      kk[0] = p, kk[1] = q, kk[2] = k, kk[3] = 0;
+      for (int t = 0; t < P.K; ++t) kk[4 + t] = t < k ? g[t] : -1;
+      P.seg[i] = (uint64_t)q * (uint64_t)P.kp.Nt + (uint64_t)p;
     }
-    X[t] = S[t] + D * ((pl.w - dot(n, S[t])) / den);
+    const d3 T = ld3(P.tx + 3 * p), Rq = ld3(P.rx + 3 * q);
+    // images S_1..S_k
+    d3 S[SBR_MAX_BOUNCES + 1];
+    S[0] = T;
+    for (int t = 1; t <= k; ++t) S[t] = mirror(S[t - 1], P.gplane[g[t - 1]]);
+    X[0] = T;
+    X[k + 1] = Rq;
+    for (int t = k; t >= 1 && ok; --t) {
+      const double4 pl = P.gplane[g[t - 1]];
+      const d3 n = mk3(pl.x, pl.y, pl.z);
+      const d3 D = X[t + 1] - S[t];
+      const double den = dot(n, D);
+      if (den == 0.0) {
+        ok = false;
+        break;
+      }
+      X[t] = S[t] + D * ((pl.w - dot(n, S[t])) / den);
+    }
+    for (int t = 1 + sub; t <= k && ok; t += kRebuildLanes) {
+      const int gi = g[t - 1];
+      bool inside = false;
+      for (int j = P.gstart[gi]; j < P.gstart[gi + 1] && !inside; ++j)
+        inside = in_triangle(P.tri64 + 9 * (int64_t)P.gtri[j], X[t]);
+      const double4 pl = P.gplane[gi];
+      const d3 n = mk3(pl.x, pl.y, pl.z);
+      const double sa = dot(n, X[t - 1]) - pl.w, sb = dot(n, X[t + 1]) - pl.w;
+      ok = inside && (sa * sb > 0.0);
+    }
+    for (int t = 1 + sub; t <= k + 1 && ok; t += kRebuildLanes) {
+      const int ga = t >= 2 ? g[t - 2] : -1;
+      const int gb = t <= k ? g[t - 1] : -1;
+      ok = !leg_blocked<STACK>(P, stk, X[t - 1], X[t], ga, gb);
+    }
   }
-  for (int t = 1; t <= k && ok; ++t) {
-    const int gi = g[t - 1];
-    bool inside = false;
-    for (int j = P.gstart[gi]; j < P.gstart[gi + 1] && !inside; ++j)
-      inside = in_triangle(P.tri64 + 9 * (int64_t)P.gtri[j], X[t]);
-    const double4 pl = P.gplane[gi];
-    const d3 n = mk3(pl.x, pl.y, pl.z);
-    const double sa = dot(n, X[t - 1]) - pl.w, sb = dot(n, X[t + 1]) - pl.w;
-    ok = inside && (sa * sb > 0.0);
-  }
-  for (int t = 1; t <= k + 1 && ok; ++t) {
-    const int ga = t >= 2 ? g[t - 2] : -1;
-    const int gb = t <= k ? g[t - 1] : -1;
-    ok = !leg_blocked<STACK>(P, stk, X[t - 1], X[t], ga, gb);
-  }
+  // a key is valid when none of its lanes failed
+  const uint64_t failed = __ballot(have && !ok);
+  const uint64_t mine = ((1ull << kRebuildLanes) - 1) << (lane & ~(kRebuildLanes - 1));
+  ok = have && (failed & mine) == 0;
+  if (!have || sub != 0) return;
   P.valid[i] = ok ? 1u : 0u;
   if (!ok) return;
   double len = 0.0;
@@ -691,7 +710,7 @@ void run_receive(sbr_paths_s* ps, const double* hrx, hipStream_t s) {
   RP.key = key.as<int32_t>();
   RP.seg = seg.as<uint64_t>();
   {
-    const unsigned g = nblk(nk, 128);
+    const unsigned g = nblk(nk * kRebuildLanes, 128);
     const int depth = sc->bvh_depth;
     if (depth <= 16)
       { ::sbr::TimedLaunch tl_("rebuild", s); hipLaunchKernelGGL(k_rebuild<16>, dim3(g), dim3(128), 0, s, RP); }
