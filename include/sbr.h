@@ -215,6 +215,9 @@ sbr_status sbr_trace_work(sbr_trace_t tr, int64_t* node_visits, int64_t* tri_tes
  *   "trace_graph"          1: the bounce loop of sbr_trace runs as a hipGraph built
  *                          once per (bounces, tree depth class) and replayed with
  *                          updated kernel arguments; 0 (default): direct launches
+ *   "bvh_ploc_max"         scenes built later with up to this many triangles get a
+ *                          PLOC-clustered BVH, larger ones the Morton-ordered LBVH
+ *                          with an oversized-triangle list (0..65536, default 65536)
  * Unknown keys or out-of-range values: SBR_E_INVALID_ARG. */
 sbr_status sbr_context_set_tuning(sbr_context_t ctx, const char* key, int32_t value);
 sbr_status sbr_context_get_tuning(sbr_context_t ctx, const char* key, int32_t* value);

@@ -714,8 +714,8 @@ sbr_status sbr_scene_build(sbr_context_t ctx, const double* tri_xyz, int64_t T, 
       }
       // ---- geometry the tree needs, uploaded first so that the GPU builds
       // the BVH while the host groups faces
-      // Scenes built with the Morton-ordered LBVH (above kBvhPlocMax
-      // triangles) keep oversized triangles (box diagonal above a quarter of
+      // Scenes built with the Morton-ordered LBVH (above the context's
+      // bvh_ploc_max triangles) keep oversized triangles (box diagonal above a quarter of
       // the scene's, at most kMaxBig, largest first) out of the tree: there
       // every ancestor of such a leaf gets a box as large as the scene (a
       // city's ground plane inflates a whole root-to-leaf chain), so nearly
@@ -725,7 +725,8 @@ sbr_status sbr_scene_build(sbr_context_t ctx, const double* tri_xyz, int64_t T, 
       // triangle in the tree.
       constexpr int kMaxBig = 16;
       std::vector<std::pair<double, int32_t>> cand;
-      for (int64_t t = 0; T > kBvhPlocMax && t < T; ++t) {
+      const bool linear_tree = T > c->tune.bvh_ploc_max;
+      for (int64_t t = 0; linear_tree && t < T; ++t) {
         double d2 = 0.0;
         for (int k = 0; k < 3; ++k) {
           const double a = tri[9 * t + k], b = tri[9 * t + 3 + k], cc = tri[9 * t + 6 + k];
@@ -791,7 +792,8 @@ sbr_status sbr_scene_build(sbr_context_t ctx, const double* tri_xyz, int64_t T, 
       if (sc->n_bvh > 0) {
         order.alloc((size_t)sc->n_bvh * 4, s);
         build_bvh(dlo.as<float>(), dhi.as<float>(), sc->n_bvh, slo, shi,
-                  BvhOut{sc->nodes.as<float4>(), order.as<uint32_t>(), sc->root_box.as<float>(), nullptr, depth_dev}, s);
+                  BvhOut{sc->nodes.as<float4>(), order.as<uint32_t>(), sc->root_box.as<float>(), nullptr, depth_dev}, s,
+                  linear_tree);
       }
       // ---- planes, face groups and group tables on the host (overlapping the build)
       std::vector<Plane> pl((size_t)T);
@@ -1360,6 +1362,9 @@ sbr_status sbr_context_set_tuning(sbr_context_t ctx, const char* key, int32_t va
     } else if (k == "trace_graph") {
       SBR_CHECK(value == 0 || value == 1, SBR_E_INVALID_ARG, "trace_graph = %d", value);
       c->tune.trace_graph = value;
+    } else if (k == "bvh_ploc_max") {
+      SBR_CHECK(value >= 0 && value <= kBvhPlocMax, SBR_E_INVALID_ARG, "bvh_ploc_max = %d", value);
+      c->tune.bvh_ploc_max = value;
     } else {
       SBR_CHECK(false, SBR_E_INVALID_ARG, "unknown tuning key '%s'", key);
     }
@@ -1375,6 +1380,7 @@ sbr_status sbr_context_get_tuning(sbr_context_t ctx, const char* key, int32_t* v
     else if (k == "trace_chunk") *value = c->tune.trace_chunk;
     else if (k == "replay_block") *value = c->tune.replay_block;
     else if (k == "trace_graph") *value = c->tune.trace_graph;
+    else if (k == "bvh_ploc_max") *value = c->tune.bvh_ploc_max;
     else SBR_CHECK(false, SBR_E_INVALID_ARG, "unknown tuning key '%s'", key);
   });
 }

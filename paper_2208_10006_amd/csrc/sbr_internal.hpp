@@ -138,6 +138,7 @@ struct Tuning {
   int trace_chunk = 64;        // rays per wave per queue pull (64 or 128)
   int replay_block = 256;
   int trace_graph = 0;         // 1: replay the bounce loop as a cached hipGraph
+  int bvh_ploc_max = 65536;    // scenes up to this many triangles are clustered with PLOC
 };
 
 // An instantiated bounce-loop graph: init kernels + one kernel node per bounce,

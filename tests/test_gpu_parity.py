@@ -175,6 +175,53 @@ def test_random_scenes(S, ctx, seed, N, K, nrx):
     _full_case(S, ctx, w)
 
 
+@pytest.mark.parametrize("which", ["random", "urban"])
+def test_linear_bvh_scenes(S, ctx, which):
+    """The Morton-ordered LBVH with its oversized-triangle list (the builder
+    of scenes above 65,536 triangles), forced on small scenes through the
+    bvh_ploc_max tuning key, against the oracle."""
+    banner("linear BVH", which)
+    if which == "random":
+        w = W.random_box_scene(5, n_boxes=20, n_rx=6, N=24, K=3, freq=(28e9, 140e9))
+    else:
+        w = W.urban_canyon(N=20, K=3, n_rx=40, nf=8)
+    old = S.sbr_context_get_tuning(ctx, "bvh_ploc_max")
+    try:
+        S.sbr_context_set_tuning(ctx, "bvh_ploc_max", 0)
+        sc = S.sbr_scene_build(ctx, w.tri, w.eps_r, w.sigma, w.rough)
+        if which == "urban":  # the ground plane's two triangles go to the list
+            assert S.sbr_scene_info(sc)["bvh_depth"] >= 1
+        del sc
+        _full_case(S, ctx, w)
+    finally:
+        S.sbr_context_set_tuning(ctx, "bvh_ploc_max", old)
+
+
+def test_profile_only_times_one_class(S, ctx):
+    banner("profile only bounce")
+    w = W.random_box_scene(8, n_boxes=10, n_rx=2, N=16, K=3)
+    sc = S.sbr_scene_build(ctx, w.tri, w.eps_r, w.sigma, w.rough)
+    try:
+        S.sbr_profile_only(ctx, "bounce")
+        S.sbr_profile_enable(ctx, True)
+        tr = S.sbr_trace(ctx, sc, w.tx, w.geodesic_N, w.max_bounces)
+        ps = S.sbr_receive(ctx, tr, w.rx)
+        S.sbr_synchronize(ctx)
+        ms, n = S.sbr_profile_query(ctx, "bounce")
+        assert n == w.max_bounces + 1 and ms > 0.0
+        assert S.sbr_profile_query(ctx, "replay_capture") == (0.0, 0)
+        assert S.sbr_profile_query(ctx, "host:rx_tree") == (0.0, 0)
+        S.sbr_profile_only(ctx, None)
+        S.sbr_profile_enable(ctx, True)
+        ps = S.sbr_receive(ctx, tr, w.rx)
+        S.sbr_synchronize(ctx)
+        assert S.sbr_profile_query(ctx, "replay_capture")[1] == 1
+        del ps, tr
+    finally:
+        S.sbr_profile_enable(ctx, False)
+        S.sbr_profile_only(ctx, None)
+
+
 @pytest.mark.slow
 def test_urban_reduced_full(S, ctx):
     """Urban canyon geometry (2,402 triangles, 1,000 Rx, 256 subcarriers with
