@@ -197,6 +197,25 @@ def test_linear_bvh_scenes(S, ctx, which):
         S.sbr_context_set_tuning(ctx, "bvh_ploc_max", old)
 
 
+def test_duplicated_triangles(S, ctx):
+    """Every triangle of the room three times: identical boxes, merged boxes
+    of zero added area and tied pair keys in the BVH clustering, coincident
+    candidates in the closest-hit search."""
+    banner("tiny room, every triangle three times")
+    w = W.tiny_room(N=32, K=3)
+    k = 3
+    w = W.Workload("tiny_room_x3", np.concatenate([w.tri] * k), np.concatenate([w.eps_r] * k),
+                   np.concatenate([w.sigma] * k), np.concatenate([w.rough] * k), w.tx, w.rx, w.freq,
+                   atm_db_per_m=w.atm_db_per_m, atm_deg_per_m=w.atm_deg_per_m, geodesic_N=w.geodesic_N,
+                   max_bounces=w.max_bounces)
+    sc = S.sbr_scene_build(ctx, w.tri, w.eps_r, w.sigma, w.rough)
+    g, p = S.sbr_scene_groups(sc, w.T)
+    og, op, ng = O.scene_groups(w)
+    assert np.array_equal(g, og) and np.array_equal(p, op)
+    del sc
+    _full_case(S, ctx, w)
+
+
 def test_profile_only_times_one_class(S, ctx):
     banner("profile only bounce")
     w = W.random_box_scene(8, n_boxes=10, n_rx=2, N=16, K=3)
