@@ -162,6 +162,8 @@ def batched_main(args):
     dev = torch.device("cuda", 0)
     ins = [make_inputs(w, torch, dev) for w in ws]
     ctx = S.context_for_torch(0)
+    if args.bvh_ploc_max is not None:
+        S.sbr_context_set_tuning(ctx, "bvh_ploc_max", args.bvh_ploc_max)
     log(f"[bench] batched: {len(ws)} scenes, T {sum(w.T for w in ws)} triangles, "
         f"{sum(w.rays_per_element for w in ws)} rays")
 
@@ -293,6 +295,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--scenes", type=int, default=64, help="batched_uneven: number of scenes")
     ap.add_argument("--surrogate-steps", type=int, default=0, help="surrogate: training steps per member")
+    ap.add_argument("--bvh-ploc-max", type=int, default=None,
+                    help="largest scene (triangles) clustered with PLOC; larger ones use the LBVH")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding "

@@ -257,6 +257,14 @@ void fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 void iota_u32(uint32_t* p, int64_t n, hipStream_t s);
 void gather_u64(const uint64_t* src, const uint32_t* idx, uint64_t* dst, int64_t n, hipStream_t s);
 
+// face_groups.hip: plane (n, c) of every triangle in; group and plane id of
+// every triangle, and their counts, out.  eps, sig, rough: materials [T].
+struct Plane {
+  double n[3], c;
+};
+void face_groups(const std::vector<Plane>& pl, const float* eps, const float* sig, const float* rough, double diag,
+                 std::vector<int32_t>& group, std::vector<int32_t>& plane, int& ngroups, int& nplanes);
+
 // bvh.hip: BVH over n primitives given their FP32 boxes (lo, hi) -> nodes,
 // leaf permutation (sorted position -> primitive), root box.  PLOC clustering
 // up to kBvhPlocMax primitives unless `linear` is set, Karras LBVH otherwise.
