@@ -143,13 +143,17 @@ __global__ void k_path_field(const double* __restrict__ geo, int stride, int64_t
 }
 
 // per (rx, tx): incoherent path gain, RMS delay spread (eq. (5)), mean angles
-__global__ void k_stats(const int32_t* __restrict__ seg_start, int64_t nseg, const double* __restrict__ power,
-                        const double* __restrict__ info, const float* __restrict__ ang, float* __restrict__ pg_db,
-                        float* __restrict__ tau, float* __restrict__ angles) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nseg) return;
+// One wave per (rx, tx) pair: lane l takes paths l, l + 64, ... of the pair
+// and the nine sums are combined by an xor butterfly (a fixed order).
+__global__ __launch_bounds__(256) void k_stats(const int32_t* __restrict__ seg_start, int64_t nseg,
+                                               const double* __restrict__ power, const double* __restrict__ info,
+                                               const float* __restrict__ ang, float* __restrict__ pg_db,
+                                               float* __restrict__ tau, float* __restrict__ angles) {
+  const int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int lane = threadIdx.x & 63;
+  if (s >= nseg) return;  // whole waves leave together
   double P = 0, Pt = 0, Pt2 = 0, cd_ = 0, sd = 0, ed = 0, ca = 0, sa = 0, ea = 0;
-  for (int n = seg_start[s]; n < seg_start[s + 1]; ++n) {
+  for (int n = seg_start[s] + lane; n < seg_start[s + 1]; n += kWave) {
     const double w = power[n], t = info[2 * n + 1];
     P += w;
     Pt += w * t;
@@ -160,6 +164,13 @@ __global__ void k_stats(const int32_t* __restrict__ seg_start, int64_t nseg, con
     sincospi((double)ang[4 * n + 2] / 180.0, &sn, &cn);
     ca += w * cn, sa += w * sn, ea += w * ang[4 * n + 3];
   }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    P += __shfl_xor(P, o, 64), Pt += __shfl_xor(Pt, o, 64), Pt2 += __shfl_xor(Pt2, o, 64);
+    cd_ += __shfl_xor(cd_, o, 64), sd += __shfl_xor(sd, o, 64), ed += __shfl_xor(ed, o, 64);
+    ca += __shfl_xor(ca, o, 64), sa += __shfl_xor(sa, o, 64), ea += __shfl_xor(ea, o, 64);
+  }
+  if (lane != 0) return;
   if (pg_db) pg_db[s] = P > 0 ? (float)(10.0 * log10(P)) : -INFINITY;
   if (tau) {
     double v = 0.0;
@@ -351,7 +362,7 @@ void run_path_field(sbr_paths_s* ps, const ChannelArgs& a, double2* out, hipStre
 
 void run_stats(sbr_paths_s* ps, float* pg_db, float* tau, float* angles, hipStream_t s) {
   const int64_t nseg = (int64_t)ps->Nr * ps->trace->Nt;
-  { ::sbr::TimedLaunch tl_("stats", s); hipLaunchKernelGGL(k_stats, dim3(nblk(nseg, 256)), dim3(256), 0, s, ps->seg_start.as<int32_t>(), nseg,
+  { ::sbr::TimedLaunch tl_("stats", s); hipLaunchKernelGGL(k_stats, dim3(nblk(nseg * kWave, 256)), dim3(256), 0, s, ps->seg_start.as<int32_t>(), nseg,
                      ps->power.as<double>(), ps->info.as<double>(), ps->ang.as<float>(), pg_db, tau, angles); }
   SBR_LAUNCH_CHECK();
 }
