@@ -228,13 +228,19 @@ void gather_u64(const uint64_t* src, const uint32_t* idx, uint64_t* dst, int64_t
 }
 
 // Small arrays (up to kSmallSort keys): the whole LSD radix sort in one
-// workgroup, 4-bit digits, with the keys and values resident in LDS between
-// one coalesced load and one coalesced store.  Each pass, every thread holds
-// its contiguous chunk of at most kSmallPer entries in registers and counts
-// its digits, the workgroup computes the exclusive offsets of those counts in
-// (digit, thread) order, and each thread scatters its chunk in order into the
-// LDS arrays, which keeps the sort stable.
+// workgroup with 8-bit digits, keys and values resident in LDS between one
+// coalesced load and one coalesced store.  Wave w owns the contiguous block
+// [w * 64 * P, (w + 1) * 64 * P) of the current order, P = ceil(n / 1024),
+// and walks it in rounds of 64 (element w*64*P + u*64 + lane in round u), so
+// the order (wave, round, lane) is the array order.  In a round, the lanes
+// holding the same digit are found with eight ballots; the lowest of them
+// adds the group's size to the wave's digit count in LDS after every lane of
+// the group has read the count, which gives each element its place among the
+// wave's equal digits.  A scan of the counts in (digit, wave) order turns
+// them into offsets, and every element is written to offset + place: a
+// stable counting sort per pass.
 constexpr int kSmallThreads = 1024, kSmallPer = 12, kSmallSort = kSmallThreads * kSmallPer;
+constexpr int kSmallWaves = kSmallThreads / 64;
 
 __global__ __launch_bounds__(kSmallThreads) void k_radix_sort_small(const uint64_t* __restrict__ kin,
                                                                   const uint32_t* __restrict__ vin,
@@ -242,89 +248,75 @@ __global__ __launch_bounds__(kSmallThreads) void k_radix_sort_small(const uint64
                                                                   int n, int bit_lo, int bit_hi) {
   __shared__ uint64_t lk[kSmallSort];
   __shared__ uint32_t lv[kSmallSort];
-  __shared__ uint32_t wtot[8][kSmallThreads / 64];
+  __shared__ uint16_t hist[kSmallWaves][256];  // per wave and digit: count, then offset
+  __shared__ uint32_t dsum[kSmallWaves / 4];    // digit totals of the scan's 4 waves
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int per = (n + kSmallThreads - 1) / kSmallThreads;  // <= kSmallPer
-  const int i0 = min(n, t * per), m = min(n, i0 + per) - i0;
-  const int npass = (bit_hi - bit_lo + 3) / 4;
-  {
-    uint64_t kr[kSmallPer];
-    uint32_t vr[kSmallPer];
-#pragma unroll
-    for (int u = 0; u < kSmallPer; ++u) {
-      const int i = u * kSmallThreads + t;
-      if (i < n) kr[u] = kin[i], vr[u] = vin[i];
-    }
-#pragma unroll
-    for (int u = 0; u < kSmallPer; ++u) {
-      const int i = u * kSmallThreads + t;
-      if (i < n) lk[i] = kr[u], lv[i] = vr[u];
-    }
-  }
+  const int P = (n + kSmallThreads - 1) / kSmallThreads;  // rounds per wave, <= kSmallPer
+  const int w0 = wv * 64 * P;
+  const int npass = (bit_hi - bit_lo + 7) / 8;
+  const uint64_t lt = lanemask_lt();
+  for (int i = t; i < n; i += kSmallThreads) lk[i] = kin[i], lv[i] = vin[i];
   __syncthreads();
   for (int p = 0; p < npass; ++p) {
-    const int shift = bit_lo + 4 * p;
+    const int shift = bit_lo + 8 * p;
+    for (int d = lane; d < 256; d += 64) hist[wv][d] = 0;
     uint64_t ck[kSmallPer];
     uint32_t cv[kSmallPer];
-    // digit counts of the chunk in byte lanes (a chunk holds < 256 keys):
-    // digits 0-7 in c0, 8-15 in c1
-    uint64_t c0 = 0, c1 = 0;
+    uint32_t place[kSmallPer];
 #pragma unroll
-    for (int u = 0; u < kSmallPer; ++u)
-      if (u < m) {
-        ck[u] = lk[i0 + u], cv[u] = lv[i0 + u];
-        const uint32_t d = (uint32_t)(ck[u] >> shift) & 15u;
-        const uint64_t inc = 1ull << (8 * (d & 7u));
-        if (d < 8u) c0 += inc;
-        else c1 += inc;
+    for (int u = 0; u < kSmallPer; ++u) {
+      if (u >= P) break;  // wave-uniform
+      const int i = w0 + u * 64 + lane;
+      const bool ok = i < n;
+      uint32_t d = 0;
+      if (ok) {
+        ck[u] = lk[i], cv[u] = lv[i];
+        d = (uint32_t)(ck[u] >> shift) & 255u;
       }
-    uint32_t cnt[16];
+      uint64_t m = __ballot(ok);
 #pragma unroll
-    for (int d = 0; d < 8; ++d) {
-      cnt[d] = (uint32_t)(c0 >> (8 * d)) & 0xffu;
-      cnt[8 + d] = (uint32_t)(c1 >> (8 * d)) & 0xffu;
-    }
-    // exclusive offsets in (digit, thread) order.  Counts of digit pairs are
-    // packed in 16-bit halves (no total exceeds kSmallSort < 2^16), scanned
-    // across the wave with DPP, and the wave totals exchanged through LDS.
-    // The barrier also orders every thread's chunk read before any scatter
-    // into the same arrays.
-    uint32_t x[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      x[j] = wave_inclusive_scan(cnt[2 * j] | (cnt[2 * j + 1] << 16), lane);
-      if (lane == 63) wtot[j][wv] = x[j];
+      for (int b = 0; b < 8; ++b) {
+        const uint64_t bb = __ballot(ok && ((d >> b) & 1u));
+        m &= ((d >> b) & 1u) ? bb : ~bb;
+      }
+      const uint32_t before = ok ? hist[wv][d] : 0u;  // every lane reads before the leader writes
+      place[u] = before + (uint32_t)__popcll(m & lt);
+      if (ok && (m & lt) == 0) hist[wv][d] = (uint16_t)(before + (uint32_t)__popcll(m));
     }
     __syncthreads();
-    uint32_t base = 0;
+    // offsets in (digit, wave) order: threads 0..255 own one digit each
+    uint32_t excl_digit = 0;
+    if (t < 256) {
+      uint32_t run = 0;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      uint32_t before = 0, total = 0;
-#pragma unroll
-      for (int w = 0; w < kSmallThreads / 64; ++w) {
-        const uint32_t sw = wtot[j][w];
-        before += w < wv ? sw : 0u;
-        total += sw;
+      for (int w = 0; w < kSmallWaves; ++w) {
+        const uint32_t c = hist[w][t];
+        hist[w][t] = (uint16_t)run;
+        run += c;
       }
-      const uint32_t incl = before + x[j];
-      cnt[2 * j] = base + (incl & 0xffffu) - cnt[2 * j];
-      base += total & 0xffffu;
-      cnt[2 * j + 1] = base + (incl >> 16) - cnt[2 * j + 1];
-      base += total >> 16;
+      const uint32_t incl = wave_inclusive_scan(run, lane);
+      if (lane == 63) dsum[wv] = incl;
+      excl_digit = incl - run;  // digits before this one within the scanning wave
     }
+    __syncthreads();
+    if (t < 256) {
+      uint32_t base = excl_digit;
+      for (int w = 0; w < wv; ++w) base += dsum[w];
 #pragma unroll
-    for (int u = 0; u < kSmallPer; ++u)
-      if (u < m) {
-        const int d = (int)((ck[u] >> shift) & 15u);
-        uint32_t pos = 0;
+      for (int w = 0; w < kSmallWaves; ++w) hist[w][t] = (uint16_t)(hist[w][t] + base);
+    }
+    __syncthreads();  // offsets complete; every element was read before the first barrier
 #pragma unroll
-        for (int q = 0; q < 16; ++q)
-          if (q == d) pos = cnt[q]++;
+    for (int u = 0; u < kSmallPer; ++u) {
+      if (u >= P) break;
+      const int i = w0 + u * 64 + lane;
+      if (i < n) {
+        const uint32_t d = (uint32_t)(ck[u] >> shift) & 255u;
+        const uint32_t pos = (uint32_t)hist[wv][d] + place[u];
         lk[pos] = ck[u];
         lv[pos] = cv[u];
       }
-    // the scatter is the next pass's input; the barrier also keeps the next
-    // pass's totals from overwriting wtot while it is read
+    }
     __syncthreads();
   }
   for (int i = t; i < n; i += kSmallThreads) {
