@@ -190,6 +190,7 @@ __global__ void k_single_leaf(const float* __restrict__ lo, const float* __restr
 // nearby subtrees then share cache lines.
 constexpr int kPlocThreads = 1024, kPlocR = 16, kPlocTile = kPlocThreads + 2 * kPlocR;
 constexpr int kPlocLds = 2 * kPlocThreads;  // clusters kept in LDS for the last passes
+constexpr int kPlocLdsNodes = 2 * kPlocLds;  // trees relabelled in LDS (4 ints per node in lb)
 constexpr int64_t kPlocMax = kBvhPlocMax;  // pair keys hold two 16-bit cluster indices
 static_assert(kPlocMax <= 65536, "PLOC pair keys hold 16-bit cluster indices");
 
@@ -223,7 +224,9 @@ __global__ __launch_bounds__(kPlocThreads) void k_ploc(const PlocArgs A) {
   __shared__ float sb[6][kPlocTile];
   __shared__ uint32_t wsum[kPlocThreads / 64];
   // the passes with at most kPlocLds clusters keep them in LDS
-  __shared__ float lb[6][kPlocLds];
+  // lb rows 0-5 hold the cluster boxes; the eight rows are reused by the
+  // relabelling of trees up to kPlocLdsNodes nodes (children, sizes, numbers)
+  __shared__ float lb[8][kPlocLds];
   __shared__ int32_t lid[kPlocLds], lht[kPlocLds], lsz[kPlocLds], lnn[kPlocLds];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int n = A.n;
@@ -437,6 +440,41 @@ __global__ __launch_bounds__(kPlocThreads) void k_ploc(const PlocArgs A) {
   __syncthreads();
   // ---- depth-first numbering: a node's parent was created in a later pass,
   // so walking the passes backwards numbers every parent before its children
+  if (n - 1 <= kPlocLdsNodes) {
+    // in LDS: children, sizes and numbers of every node
+    int32_t* rcl = reinterpret_cast<int32_t*>(&lb[0][0]);
+    int32_t* rcr = rcl + kPlocLdsNodes;
+    int32_t* rsz = rcr + kPlocLdsNodes;
+    int32_t* rdf = rsz + kPlocLdsNodes;
+    for (int x = t; x < n - 1; x += kPlocThreads) {
+      const float4 c = A.tmp[4 * x + 3];
+      rcl[x] = __float_as_int(c.x), rcr[x] = __float_as_int(c.y), rsz[x] = A.nsz[x];
+    }
+    if (t == 0) rdf[0] = 0;
+    __syncthreads();
+    for (int p = pass - 1; p >= 0; --p) {
+      const int first = A.pass_next[p + 1] + 1, last = A.pass_next[p];
+      for (int x = first + t; x <= last; x += kPlocThreads) {
+        const int d = rdf[x];
+        const int32_t cl = rcl[x], cr = rcr[x];
+        const int left = cl >= 0 ? rsz[cl] : 0;
+        if (cl >= 0) rdf[cl] = d + 1;
+        if (cr >= 0) rdf[cr] = d + 1 + left;
+      }
+      __syncthreads();
+    }
+    for (int x = t; x < n - 1; x += kPlocThreads) {
+      const int d = rdf[x];
+      const int32_t cl = rcl[x], cr = rcr[x];
+      const float4 c = make_float4(__int_as_float(cl >= 0 ? rdf[cl] : cl), __int_as_float(cr >= 0 ? rdf[cr] : cr),
+                                   0.0f, 0.0f);
+      A.nodes[4 * d] = A.tmp[4 * x];
+      A.nodes[4 * d + 1] = A.tmp[4 * x + 1];
+      A.nodes[4 * d + 2] = A.tmp[4 * x + 2];
+      A.nodes[4 * d + 3] = c;
+    }
+    return;
+  }
   for (int p = pass - 1; p >= 0; --p) {
     const int first = A.pass_next[p + 1] + 1, last = A.pass_next[p];
     for (int x = first + t; x <= last; x += kPlocThreads) {
