@@ -349,10 +349,14 @@ __global__ __launch_bounds__(256) void k_bounce(const BounceParams P) {
         tn = tmin;
         return tmin <= tmx * 1.0000004f;
       };
+      // All 48 bytes of the triangle are loaded before any decision, so a
+      // test costs one memory round trip; the rejections are folded into one
+      // final predicate instead of early exits.  t = Tn / det is formed with
+      // the hardware reciprocal (about 1 ulp): t only ranks candidates, and
+      // the selected hit is re-evaluated in FP64 on its plane afterwards.
       auto tri_test = [&](int32_t leaf) {
         if (COUNT) ++n_tri;
         const float4 a = tri[3 * leaf], b = tri[3 * leaf + 1], c = tri[3 * leaf + 2];
-        if (__float_as_int(b.w) == skip_plane) return;
         const float3 A = make_float3(a.x - org.x, a.y - org.y, a.z - org.z);
         const float3 B = make_float3(b.x - org.x, b.y - org.y, b.z - org.z);
         const float3 C = make_float3(c.x - org.x, c.y - org.y, c.z - org.z);
@@ -366,12 +370,11 @@ __global__ __launch_bounds__(256) void k_bounce(const BounceParams P) {
           V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
           W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
         }
-        if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return;
+        const bool outside = (U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f);
         const float det = U + V + W;
-        if (det == 0.0f) return;
         const float Tn = U * (Sz * Akz) + V * (Sz * Bkz) + W * (Sz * Ckz);
-        const float t = Tn / det;
-        if (t > 0.0f && t < thit) {
+        const float t = Tn * __builtin_amdgcn_rcpf(det);
+        if (!outside && det != 0.0f && __float_as_int(b.w) != skip_plane && t > 0.0f && t < thit) {
           thit = t;
           hit = leaf;
         }
@@ -385,32 +388,42 @@ __global__ __launch_bounds__(256) void k_bounce(const BounceParams P) {
           if (COUNT) ++n_node;
           const float4 n0 = nodes[4 * node], n1 = nodes[4 * node + 1], n2 = nodes[4 * node + 2],
                        n3 = nodes[4 * node + 3];
+          // the entry a pop would take, read while the node is in flight
+          // (slot 0 when the stack is empty: in bounds, and then unused)
+          const int32_t top = stk[kWave * (sp > 0 ? sp - 1 : 0)];
           float tl, tr;
           bool hl = box_hit(n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, thit, tl);
           bool hr = box_hit(n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, thit, tr);
           const int32_t cl = __float_as_int(n3.x), cr = __float_as_int(n3.y);
+          // leaf children are collected (left first) and tested at one site
+          // below, so lanes with a left and lanes with a right leaf share a pass
+          int32_t la = -1, lb = -1;
           if (hl && cl < 0) {
-            tri_test(~cl);
+            la = ~cl;
             hl = false;
           }
           if (hr && cr < 0) {
-            if (cr != cl) tri_test(~cr);
+            if (cr != cl) {
+              if (la < 0) la = ~cr;
+              else lb = ~cr;
+            }
             hr = false;
           }
-          if (hl && hr) {
-            const bool lnear = tl <= tr;
-            stk[kWave * sp] = lnear ? cr : cl;
-            ++sp;
-            node = lnear ? cl : cr;
-          } else if (hl) {
-            node = cl;
-          } else if (hr) {
-            node = cr;
-          } else {
-            if (sp == 0) break;
-            --sp;
-            node = stk[kWave * sp];
+          // both hit: descend into the nearer, push the other; one hit:
+          // descend; none: pop (the decision is written as selects so that
+          // the stack read above is not deferred into a pop branch)
+          const bool both = hl && hr, none = !hl && !hr;
+          const bool lnear = tl <= tr;
+          if (both) stk[kWave * sp] = lnear ? cr : cl;
+          const bool done = none && sp == 0;
+          node = both ? (lnear ? cl : cr) : hl ? cl : hr ? cr : top;
+          sp += both ? 1 : (none && sp > 0) ? -1 : 0;
+          while (la >= 0) {
+            tri_test(la);
+            la = lb;
+            lb = -1;
           }
+          if (done) break;
         }
       }
       if (hit >= 0) hit = __float_as_int(tri[3 * hit].w);  // original triangle id
