@@ -147,7 +147,7 @@ struct TraceGraph {
   int K = -1, depth_bucket = 0, count = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  std::vector<hipGraphNode_t> nodes;  // fill counters, fill seq, bounce 0..K
+  std::vector<hipGraphNode_t> nodes;  // fill counters, bounce 0..K
   ~TraceGraph();
 };
 

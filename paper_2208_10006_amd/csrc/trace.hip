@@ -547,8 +547,8 @@ hipKernelNodeParams knode(const void* fn, dim3 g, dim3 b, void** args) {
 }
 }  // namespace
 
-// The bounce loop as a graph: fill(counters) -> fill(seq) -> bounce 0 -> ... ->
-// bounce K, all kernel nodes (no memset nodes).  Built on first use for a
+// The bounce loop as a graph: fill(counters) -> bounce 0 -> ... -> bounce K,
+// all kernel nodes (no memset nodes).  Built on first use for a
 // (K, depth class, counting) shape, then only the kernel arguments are updated.
 void launch_trace_graph(const TraceLaunch& T, const BounceParams* P, int nP, hipStream_t s) {
   sbr_context_s* c = T.ctx;
@@ -560,16 +560,13 @@ void launch_trace_graph(const TraceLaunch& T, const BounceParams* P, int nP, hip
     if (g->K == T.K && g->depth_bucket == bucket && g->count == count) G = g;
   uint32_t* cnt = T.counters;
   int64_t ncnt = trace_counter_words(T.K);
-  uint32_t v0 = 0, vneg = 0xffffffffu;
-  uint32_t* seqp = reinterpret_cast<uint32_t*>(T.seq);
-  int64_t nseq = (int64_t)(T.K + 1) * T.NR;
+  uint32_t v0 = 0;
   void* a_cnt[] = {&cnt, &v0, &ncnt};
-  void* a_seq[] = {&seqp, &vneg, &nseq};
   std::vector<BounceParams> Pc(P, P + nP);
   std::vector<void*> a_b(nP);
   for (int k = 0; k < nP; ++k) a_b[k] = &Pc[k];
   const void* ffill = reinterpret_cast<const void*>(&k_fill_u32_graph);
-  const dim3 gc((unsigned)((ncnt + 255) / 256)), gs((unsigned)((nseq + 255) / 256)), gb(T.grid), b256(256);
+  const dim3 gc((unsigned)((ncnt + 255) / 256)), gb(T.grid), b256(256);
   const void* fb = count ? bounce_fn<true>(depth) : bounce_fn<false>(depth);
   if (!G) {
     G = new TraceGraph();
@@ -584,18 +581,15 @@ void launch_trace_graph(const TraceLaunch& T, const BounceParams* P, int nP, hip
       prev = n;
     };
     add(ffill, gc, a_cnt);
-    add(ffill, gs, a_seq);
     for (int k = 0; k < nP; ++k) add(fb, gb, &a_b[k]);
     SBR_HIP(hipGraphInstantiate(&G->exec, G->graph, nullptr, nullptr, 0));
     c->graphs.push_back(G);
   } else {
     hipKernelNodeParams kp = knode(ffill, gc, b256, a_cnt);
     SBR_HIP(hipGraphExecKernelNodeSetParams(G->exec, G->nodes[0], &kp));
-    kp = knode(ffill, gs, b256, a_seq);
-    SBR_HIP(hipGraphExecKernelNodeSetParams(G->exec, G->nodes[1], &kp));
     for (int k = 0; k < nP; ++k) {
       kp = knode(fb, gb, b256, &a_b[k]);
-      SBR_HIP(hipGraphExecKernelNodeSetParams(G->exec, G->nodes[2 + k], &kp));
+      SBR_HIP(hipGraphExecKernelNodeSetParams(G->exec, G->nodes[1 + k], &kp));
     }
   }
   ::sbr::TimedLaunch tl_("bounce", s);
@@ -624,9 +618,11 @@ void launch_trace(const TraceLaunch& T, void* ray_a, void* ray_b, hipStream_t s)
     launch_trace_graph(T, Pk.data(), T.K + 1, s);
     return;
   }
+  // The hit chain is not initialised: bounce k writes seq[k] (hit or -1) for
+  // every ray it traces, and every ray live after bounce k - 1 is traced at k,
+  // so each chain is written up to its first -1 (or to K), and no reader looks
+  // past that entry.
   fill_u32(T.counters, 0, trace_counter_words(T.K), s);
-  // every chain entry starts as "miss"; the bounce kernels overwrite the ones they trace
-  fill_u32(reinterpret_cast<uint32_t*>(T.seq), 0xffffffffu, (int64_t)(T.K + 1) * T.NR, s);
   for (int k = 0; k <= T.K; ++k) {
     ::sbr::TimedLaunch tl_("bounce", s);
     if (T.work) launch_bounce<true, false>(depth, dim3(T.grid), Pk[k], s);
@@ -659,8 +655,6 @@ void launch_trace_batch(const std::vector<sbr_trace_s*>& trs, int grid, int chun
   fill_u32(counters, 0, trace_counter_words(Kmax), s);
   fill_u32(reinterpret_cast<uint32_t*>(t_first), 0xffffffffu, 2 * (int64_t)n, s);
   fill_u32(reinterpret_cast<uint32_t*>(t_last), 0u, 2 * (int64_t)n, s);
-  for (sbr_trace_s* t : trs)
-    fill_u32(t->seq.as<uint32_t>(), 0xffffffffu, (int64_t)(t->K + 1) * t->NR, s);
   BounceParams P{};
   P.table = dtab.as<SceneDesc>();
   P.offs = doffs.as<int64_t>();
