@@ -31,10 +31,20 @@ __device__ inline uint32_t spread10(uint32_t v) {
   return v;
 }
 
+// Quantised centroid positions in the scene box slo + [0, 1/inv_ext]; with
+// bounds (device lo xyz, hi xyz) the box comes from there, by the same float
+// operations the host uses.
 __global__ void k_morton(const float* __restrict__ lo, const float* __restrict__ hi, int64_t n, float3 slo,
-                         float3 inv_ext, uint64_t* __restrict__ code, uint32_t* __restrict__ idx) {
+                         float3 inv_ext, const float* __restrict__ bounds, uint64_t* __restrict__ code,
+                         uint32_t* __restrict__ idx) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  if (bounds) {
+    slo = make_float3(bounds[0], bounds[1], bounds[2]);
+    inv_ext.x = bounds[3] > bounds[0] ? 1.0f / (bounds[3] - bounds[0]) : 0.0f;
+    inv_ext.y = bounds[4] > bounds[1] ? 1.0f / (bounds[4] - bounds[1]) : 0.0f;
+    inv_ext.z = bounds[5] > bounds[2] ? 1.0f / (bounds[5] - bounds[2]) : 0.0f;
+  }
   const float cx = 0.5f * (lo[3 * i] + hi[3 * i]);
   const float cy = 0.5f * (lo[3 * i + 1] + hi[3 * i + 1]);
   const float cz = 0.5f * (lo[3 * i + 2] + hi[3 * i + 2]);
@@ -532,13 +542,15 @@ int build_bvh(const float* box_lo, const float* box_hi, int64_t n, const float s
   parents.alloc((ploc ? tmp_off + 16 * (n - 1) : 2 * n) * 4, s);
   flags.alloc((n + 1) * 4, s);
   temp.alloc(radix_sort_temp_bytes(n), s);
-  float3 slo = make_float3(scene_lo[0], scene_lo[1], scene_lo[2]);
-  float3 ie;
-  ie.x = scene_hi[0] > scene_lo[0] ? 1.0f / (scene_hi[0] - scene_lo[0]) : 0.0f;
-  ie.y = scene_hi[1] > scene_lo[1] ? 1.0f / (scene_hi[1] - scene_lo[1]) : 0.0f;
-  ie.z = scene_hi[2] > scene_lo[2] ? 1.0f / (scene_hi[2] - scene_lo[2]) : 0.0f;
+  float3 slo = make_float3(0.0f, 0.0f, 0.0f), ie = make_float3(0.0f, 0.0f, 0.0f);
+  if (!out.bounds_dev) {
+    slo = make_float3(scene_lo[0], scene_lo[1], scene_lo[2]);
+    ie.x = scene_hi[0] > scene_lo[0] ? 1.0f / (scene_hi[0] - scene_lo[0]) : 0.0f;
+    ie.y = scene_hi[1] > scene_lo[1] ? 1.0f / (scene_hi[1] - scene_lo[1]) : 0.0f;
+    ie.z = scene_hi[2] > scene_lo[2] ? 1.0f / (scene_hi[2] - scene_lo[2]) : 0.0f;
+  }
   { ::sbr::TimedLaunch tl_("bvh", s); hipLaunchKernelGGL(k_morton, dim3(blocks(n, 256)), dim3(256), 0, s, box_lo, box_hi, n, slo, ie,
-                     codes.as<uint64_t>(), idx.as<uint32_t>()); }
+                     out.bounds_dev, codes.as<uint64_t>(), idx.as<uint32_t>()); }
   SBR_LAUNCH_CHECK();
   radix_sort_pairs(codes.as<uint64_t>(), idx.as<uint32_t>(), codes2.as<uint64_t>(), out.order, n, 0, 30,
                    temp.p, s);

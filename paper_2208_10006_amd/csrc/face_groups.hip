@@ -112,7 +112,14 @@ void face_groups(const std::vector<Plane>& pl, const float* eps, const float* si
     const double sgn = n[imax] < 0 ? -1.0 : 1.0;
     cn[t] = Canon{{sgn * n[0], sgn * n[1], sgn * n[2], sgn * pl[t].c}, std::fabs(n[imax]) - second < 4 * tol_n};
   }
-  auto cell = [&](const double* v, int k) { return (int64_t)std::floor(v[k] / (k < 3 ? hn : hc)); };
+  // cell coordinates by multiplication with the inverse cell sizes and an
+  // inline floor (the same function serves insertion and probing)
+  const double ihn = 1.0 / hn, ihc = 1.0 / hc;
+  auto ifloor = [](double x) {
+    const int64_t i = (int64_t)x;
+    return i - (int64_t)(x < (double)i);
+  };
+  auto cell = [&](const double* v, int k) { return ifloor(v[k] * (k < 3 ? ihn : ihc)); };
   // Triangles whose canonical (n, c) are bitwise equal form one class (many
   // box bottoms lie exactly on a floor): they are joined directly, and only
   // one representative per class enters the pairwise tolerance tests, which
@@ -185,7 +192,7 @@ void face_groups(const std::vector<Plane>& pl, const float* eps, const float* si
       for (int k = 0; k < 4; ++k) {
         const double h = k < 3 ? hn : hc, tol = k < 3 ? tol_n : tol_c;
         base[k] = cell(v, k);
-        const double f = v[k] / h - (double)base[k];
+        const double f = v[k] * (k < 3 ? ihn : ihc) - (double)base[k];
         lo[k] = f * h <= tol ? -1 : 0;
         hi[k] = (1.0 - f) * h <= tol ? 1 : 0;
       }

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <functional>
 #include <mutex>
+#include <optional>
 #include <vector>
 
 #include "sbr_device.hpp"
@@ -36,8 +37,8 @@ struct CachedBlock {
 std::mutex g_cache_mu;
 std::vector<CachedBlock> g_cache;  // oldest first
 size_t g_cache_bytes = 0;
-constexpr size_t kCacheMax = size_t(4) << 30;       // cached bytes over all streams
-constexpr size_t kCacheBlockMax = size_t(256) << 20;  // larger blocks are freed at once
+constexpr size_t kCacheMax = size_t(8) << 30;       // cached bytes over all streams
+constexpr size_t kCacheBlockMax = size_t(1) << 30;  // larger blocks are freed at once
 // block size for a request: 1/16 steps of the power of two above it, at least 4 KiB
 size_t block_size(size_t n) {
   if (n <= 4096) return 4096;
@@ -76,7 +77,7 @@ void Buf::alloc(size_t n, hipStream_t s) {
 }
 
 void Buf::reset() {
-  if (p) {
+  if (p && cap > 0) {  // cap 0: a view, owned elsewhere
     if (cap > kCacheBlockMax) {
       (void)hipFreeAsync(p, stream);
     } else {
@@ -273,6 +274,32 @@ struct Stager {
     SBR_HIP(hipMemcpyAsync(b.p, static_cast<char*>(c->stage) + at, bytes, hipMemcpyHostToDevice, s));
     off = at + bytes;
   }
+  // Packed uploads: add() places arrays side by side in the staging area,
+  // flush() copies them with one transfer into `block` and points each Buf
+  // at its part (views of `block`).  The staging area must already be large
+  // enough (it is not resized here).
+  struct Part {
+    Buf* b;
+    size_t at, bytes;
+  };
+  std::vector<Part> parts;
+  template <class T>
+  void add(Buf& b, const T* src, size_t n) {
+    const size_t bytes = n * sizeof(T);
+    const size_t at = (off + 255) & ~size_t(255);
+    SBR_CHECK(at + bytes <= c->stage_bytes, SBR_E_DEVICE, "staging area too small for packed uploads");
+    if (bytes) std::memcpy(static_cast<char*>(c->stage) + at, src, bytes);
+    parts.push_back(Part{&b, at, bytes});
+    off = at + bytes;
+  }
+  void flush(Buf& block, hipStream_t s) {
+    if (parts.empty()) return;
+    const size_t first = parts.front().at, total = std::max<size_t>(off - first, 1);
+    block.alloc(total, s);
+    SBR_HIP(hipMemcpyAsync(block.p, static_cast<char*>(c->stage) + first, off - first, hipMemcpyHostToDevice, s));
+    for (const Part& q : parts) q.b->view(block.as<char>() + (q.at - first), q.bytes);
+    parts.clear();
+  }
 };
 
 void set_device(sbr_context_s* c) {
@@ -280,18 +307,89 @@ void set_device(sbr_context_s* c) {
   g_prof = &c->prof;
 }
 
-// tri[off + i] = triangle map[order ? order[i] : i] (FP32 vertices | original id, plane id, group id)
+// tri[off + i] = triangle m(order ? order[i] : i), m = map or the identity
+// (FP32 vertices | original id, plane id, group id)
 __global__ void k_tri_gather(const uint32_t* __restrict__ order, const int32_t* __restrict__ map, int64_t n,
                              int64_t off, const float* __restrict__ v32, const int32_t* __restrict__ plane,
                              const int32_t* __restrict__ group, float4* __restrict__ tri) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int32_t t = map[order ? order[i] : (uint32_t)i];
+  const uint32_t u = order ? order[i] : (uint32_t)i;
+  const int32_t t = map ? map[u] : (int32_t)u;
   const float* v = v32 + 9 * (int64_t)t;
   const int64_t o = 3 * (off + i);
   tri[o] = make_float4(v[0], v[1], v[2], __int_as_float(t));
   tri[o + 1] = make_float4(v[3], v[4], v[5], __int_as_float(plane[t]));
   tri[o + 2] = make_float4(v[6], v[7], v[8], __int_as_float(group[t]));
+}
+
+// Scene preparation on the device, so that the tree build starts before the
+// host has the triangles.  Both kernels repeat the host's arithmetic
+// operation for operation (the host computes the same centre and diagonal
+// for its own steps): the FP64 box of all vertices, the centre 0.5 (lo + hi),
+// vertices (float)(x - centre) and per-triangle FP32 boxes.  Rounding is
+// monotone, so the FP32 scene bounds are (float)(lo - centre) and
+// (float)(hi - centre).  Non-finite values (inputs the host then rejects)
+// become 0 so that the tree build always sees finite boxes.
+constexpr int kPrepBlocks = 64;
+__global__ __launch_bounds__(256) void k_scene_bounds(const double* __restrict__ tri, int64_t nv,
+                                                      double* __restrict__ part) {
+  __shared__ double red[6][4];
+  double b[6] = {1e300, 1e300, 1e300, -1e300, -1e300, -1e300};
+  for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < nv; v += (int64_t)gridDim.x * 256)
+    for (int k = 0; k < 3; ++k) {
+      const double x = tri[3 * v + k];
+      b[k] = x < b[k] ? x : b[k];
+      b[3 + k] = x > b[3 + k] ? x : b[3 + k];
+    }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int o = 32; o > 0; o >>= 1)
+    for (int k = 0; k < 6; ++k) {
+      const double y = __shfl_xor(b[k], o, 64);
+      b[k] = k < 3 ? (y < b[k] ? y : b[k]) : (y > b[k] ? y : b[k]);
+    }
+  if (lane == 0)
+    for (int k = 0; k < 6; ++k) red[k][wv] = b[k];
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int k = threadIdx.x;
+    double r = red[k][0];
+    for (int w = 1; w < 4; ++w) r = k < 3 ? (red[k][w] < r ? red[k][w] : r) : (red[k][w] > r ? red[k][w] : r);
+    part[6 * blockIdx.x + k] = r;
+  }
+}
+__device__ inline float finite_or_zero(float f) { return isfinite(f) ? f : 0.0f; }
+__global__ __launch_bounds__(256) void k_scene_prep(const double* __restrict__ tri, int64_t T,
+                                                    const double* __restrict__ part, int nb, float* __restrict__ v32,
+                                                    float* __restrict__ blo, float* __restrict__ bhi,
+                                                    float* __restrict__ bounds) {
+  __shared__ double lh[6], cen[3];
+  if (threadIdx.x < 6) {
+    const int k = threadIdx.x;
+    double r = part[k];
+    for (int j = 1; j < nb; ++j) {
+      const double y = part[6 * j + k];
+      r = k < 3 ? (y < r ? y : r) : (y > r ? y : r);
+    }
+    lh[k] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) cen[threadIdx.x] = 0.5 * (lh[threadIdx.x] + lh[3 + threadIdx.x]);
+  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x < 6) {
+    const int k = threadIdx.x;
+    bounds[k] = finite_or_zero((float)(lh[k] - cen[k % 3]));
+  }
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  float mn[3] = {1e30f, 1e30f, 1e30f}, mx[3] = {-1e30f, -1e30f, -1e30f};
+  for (int v = 0; v < 3; ++v)
+    for (int k = 0; k < 3; ++k) {
+      const float f = finite_or_zero((float)(tri[9 * t + 3 * v + k] - cen[k]));
+      v32[9 * t + 3 * v + k] = f;
+      mn[k] = f < mn[k] ? f : mn[k], mx[k] = mx[k] < f ? f : mx[k];
+    }
+  for (int k = 0; k < 3; ++k) blo[3 * t + k] = mn[k], bhi[3 * t + k] = mx[k];
 }
 
 __global__ void k_hits_out(const int32_t* __restrict__ seq, int64_t NR, int K, int32_t* __restrict__ out) {
@@ -367,6 +465,7 @@ sbr_context_s::~sbr_context_s() {
     (void)hipStreamSynchronize(stream);
   }
   if (stage) (void)hipHostFree(stage);
+  if (ev_inputs) (void)hipEventDestroy(ev_inputs);
   prof.clear();
   prof.destroy_events();
   if (g_prof == &prof) g_prof = nullptr;
@@ -375,7 +474,7 @@ sbr_context_s::~sbr_context_s() {
 sbr_scene_s::~sbr_scene_s() {
   if (ctx) (void)hipSetDevice(ctx->device);
   nodes.reset(), root_box.reset(), tri32.reset(), tri64.reset(), tplane.reset(), tgroup.reset(), tplaneid.reset();
-  gplane.reset(), gmat.reset(), gstart.reset(), gtri.reset();
+  gplane.reset(), gmat.reset(), gstart.reset(), gtri.reset(), tables.reset();
   if (ctx) release(ctx);
 }
 sbr_trace_s::~sbr_trace_s() {
@@ -448,55 +547,99 @@ sbr_status sbr_scene_build(sbr_context_t ctx, const double* tri_xyz, int64_t T, 
     auto* c = check_handle<sbr_context_s>(ctx, kContext, "context");
     SBR_CHECK(out != nullptr, SBR_E_INVALID_ARG, "out is NULL");
     SBR_CHECK(T >= 0 && T < (int64_t(1) << 30), SBR_E_INVALID_ARG, "triangle count %lld", (long long)T);
+    if (T > 0) SBR_CHECK(tri_xyz && eps_r && sigma && rough, SBR_E_INVALID_ARG, "input array is NULL");
     set_device(c);
     hipStream_t s = c->stream;
     HostPhase hp_all("host:scene_build");
-    std::vector<double> tri;
-    std::vector<float> er, sg, rh;
-    {
-      HostPhase hp("host:scene_inputs");
-      if ((flags & SBR_IN_DEVICE) && T > 0) {
-        // device inputs: four copies into the pinned staging area, one synchronisation
-        SBR_CHECK(tri_xyz && eps_r && sigma && rough, SBR_E_INVALID_ARG, "input array is NULL");
-        const size_t bt = (size_t)T * 72, bm = (size_t)T * 4, o1 = (bt + 255) & ~size_t(255);
-        const size_t o2 = o1 + ((bm + 255) & ~size_t(255)), o3 = o2 + ((bm + 255) & ~size_t(255));
-        const size_t need = o3 + bm;
-        if (c->stage_bytes < need) {
-          if (c->stage) (void)hipHostFree(c->stage);
-          c->stage = nullptr;
-          c->stage_bytes = 0;
-          SBR_HIP(hipHostMalloc(&c->stage, need, hipHostMallocDefault));
-          c->stage_bytes = need;
-        }
-        char* st = static_cast<char*>(c->stage);
-        SBR_HIP(hipMemcpyAsync(st, tri_xyz, bt, hipMemcpyDeviceToHost, s));
-        SBR_HIP(hipMemcpyAsync(st + o1, eps_r, bm, hipMemcpyDeviceToHost, s));
-        SBR_HIP(hipMemcpyAsync(st + o2, sigma, bm, hipMemcpyDeviceToHost, s));
-        SBR_HIP(hipMemcpyAsync(st + o3, rough, bm, hipMemcpyDeviceToHost, s));
-        SBR_HIP(hipStreamSynchronize(s));
-        tri.assign(reinterpret_cast<const double*>(st), reinterpret_cast<const double*>(st) + (size_t)T * 9);
-        er.assign(reinterpret_cast<const float*>(st + o1), reinterpret_cast<const float*>(st + o1) + T);
-        sg.assign(reinterpret_cast<const float*>(st + o2), reinterpret_cast<const float*>(st + o2) + T);
-        rh.assign(reinterpret_cast<const float*>(st + o3), reinterpret_cast<const float*>(st + o3) + T);
-      } else {
-        tri = to_host(tri_xyz, (size_t)T * 9, flags, s);
-        er = to_host(eps_r, (size_t)T, flags, s);
-        sg = to_host(sigma, (size_t)T, flags, s);
-        rh = to_host(rough, (size_t)T, flags, s);
-      }
+    const bool dev_in = (flags & SBR_IN_DEVICE) != 0;
+    // Scenes clustered with PLOC keep every triangle in the tree; they are
+    // prepared on the device, so that the tree build starts at once and the
+    // host's face grouping overlaps it.  Larger scenes (Morton-ordered LBVH
+    // with a list of oversized triangles) are prepared on the host.
+    const bool gpu_prep = T > 0 && T <= c->tune.bvh_ploc_max;
+    // One pinned staging area serves the copies of device inputs (read
+    // before the first upload) and the uploads; its size is set here, before
+    // either is issued.
+    const size_t bt = (size_t)T * 72, bm = (size_t)T * 4, o1 = (bt + 255) & ~size_t(255);
+    const size_t o2 = o1 + ((bm + 255) & ~size_t(255)), o3 = o2 + ((bm + 255) & ~size_t(255));
+    const size_t need = std::max(o3 + bm, (size_t)T * (72 + 32 + 8 + 32 + 16 + 4 + 4 + 60 + 4) + 4 + 20 * 256);
+    if (c->stage_bytes < need) {
+      if (c->stage) (void)hipHostFree(c->stage);
+      c->stage = nullptr;
+      c->stage_bytes = 0;
+      SBR_HIP(hipHostMalloc(&c->stage, need, hipHostMallocDefault));
+      c->stage_bytes = need;
     }
-    SBR_CHECK(finite_all(tri.data(), tri.size()), SBR_E_INVALID_ARG, "triangle coordinates must be finite");
-    for (int64_t t = 0; t < T; ++t) {
-      SBR_CHECK(std::isfinite(er[t]) && er[t] >= 1.0f, SBR_E_INVALID_ARG, "eps_r[%lld] = %g (needs >= 1)",
-                (long long)t, er[t]);
-      SBR_CHECK(std::isfinite(sg[t]) && sg[t] >= 0.0f, SBR_E_INVALID_ARG, "sigma[%lld] = %g", (long long)t, sg[t]);
-      SBR_CHECK(std::isfinite(rh[t]) && rh[t] >= 0.0f, SBR_E_INVALID_ARG, "rough[%lld] = %g", (long long)t, rh[t]);
-    }
+    if (dev_in && gpu_prep && !c->ev_inputs) SBR_HIP(hipEventCreateWithFlags(&c->ev_inputs, hipEventDisableTiming));
     auto* sc = new sbr_scene_s();
     sc->ctx = c;
     retain(c);
     try {
       sc->T = T;
+      std::vector<double> tri;
+      std::vector<float> er, sg, rh;
+      Stager st(c);
+      Buf dv32, dlo, dhi, order, dbvh_ids, dbig_ids, dpart, dbounds;
+      uint32_t* depth_dev = nullptr;
+      auto alloc_tree = [&] {
+        sc->nodes.alloc((size_t)std::max<int64_t>(sc->n_bvh - 1, 1) * 64, s);
+        sc->root_box.alloc(32, s);  // 6 floats of root box, then the depth word
+        sc->tri32.alloc((size_t)T * 48, s);
+        depth_dev = reinterpret_cast<uint32_t*>(sc->root_box.as<float>() + 6);
+      };
+      {
+        HostPhase hp("host:scene_inputs");
+        char* stg = static_cast<char*>(c->stage);
+        if (dev_in && T > 0) {
+          // device inputs: four copies into the staging area, then (device
+          // preparation) an event the host waits for, or one synchronisation
+          SBR_HIP(hipMemcpyAsync(stg, tri_xyz, bt, hipMemcpyDeviceToHost, s));
+          SBR_HIP(hipMemcpyAsync(stg + o1, eps_r, bm, hipMemcpyDeviceToHost, s));
+          SBR_HIP(hipMemcpyAsync(stg + o2, sigma, bm, hipMemcpyDeviceToHost, s));
+          SBR_HIP(hipMemcpyAsync(stg + o3, rough, bm, hipMemcpyDeviceToHost, s));
+          if (gpu_prep) SBR_HIP(hipEventRecord(c->ev_inputs, s));
+          else SBR_HIP(hipStreamSynchronize(s));
+        } else if (T > 0) {
+          tri.assign(tri_xyz, tri_xyz + (size_t)T * 9);
+          er.assign(eps_r, eps_r + T), sg.assign(sigma, sigma + T), rh.assign(rough, rough + T);
+        }
+        if (gpu_prep) {
+          if (dev_in) upload(sc->tri64, tri_xyz, (size_t)T * 9, flags, s);
+          else st.put(sc->tri64, tri.data(), tri.size(), s);
+          sc->n_big = 0;
+          sc->n_bvh = T;
+          alloc_tree();
+          dv32.alloc((size_t)T * 36, s), dlo.alloc((size_t)T * 12, s), dhi.alloc((size_t)T * 12, s);
+          dbounds.alloc(32, s), dpart.alloc((size_t)kPrepBlocks * 48, s), order.alloc((size_t)T * 4, s);
+          const int nb = (int)std::min<int64_t>(kPrepBlocks, (3 * T + 255) / 256);
+          hipLaunchKernelGGL(k_scene_bounds, dim3(nb), dim3(256), 0, s, sc->tri64.as<double>(), 3 * T,
+                             dpart.as<double>());
+          SBR_LAUNCH_CHECK();
+          hipLaunchKernelGGL(k_scene_prep, dim3(nblk(T, 256)), dim3(256), 0, s, sc->tri64.as<double>(), T,
+                             dpart.as<double>(), nb, dv32.as<float>(), dlo.as<float>(), dhi.as<float>(),
+                             dbounds.as<float>());
+          SBR_LAUNCH_CHECK();
+          BvhOut bo{sc->nodes.as<float4>(), order.as<uint32_t>(), sc->root_box.as<float>(), nullptr, depth_dev};
+          bo.bounds_dev = dbounds.as<float>();
+          build_bvh(dlo.as<float>(), dhi.as<float>(), T, nullptr, nullptr, bo, s, false);
+          if (dev_in) SBR_HIP(hipEventSynchronize(c->ev_inputs));
+        }
+        if (dev_in && T > 0) {
+          tri.assign(reinterpret_cast<const double*>(stg), reinterpret_cast<const double*>(stg) + (size_t)T * 9);
+          er.assign(reinterpret_cast<const float*>(stg + o1), reinterpret_cast<const float*>(stg + o1) + T);
+          sg.assign(reinterpret_cast<const float*>(stg + o2), reinterpret_cast<const float*>(stg + o2) + T);
+          rh.assign(reinterpret_cast<const float*>(stg + o3), reinterpret_cast<const float*>(stg + o3) + T);
+        }
+      }
+      SBR_CHECK(finite_all(tri.data(), tri.size()), SBR_E_INVALID_ARG, "triangle coordinates must be finite");
+      for (int64_t t = 0; t < T; ++t) {
+        SBR_CHECK(std::isfinite(er[t]) && er[t] >= 1.0f, SBR_E_INVALID_ARG, "eps_r[%lld] = %g (needs >= 1)",
+                  (long long)t, er[t]);
+        SBR_CHECK(std::isfinite(sg[t]) && sg[t] >= 0.0f, SBR_E_INVALID_ARG, "sigma[%lld] = %g", (long long)t,
+                  sg[t]);
+        SBR_CHECK(std::isfinite(rh[t]) && rh[t] >= 0.0f, SBR_E_INVALID_ARG, "rough[%lld] = %g", (long long)t,
+                  rh[t]);
+      }
       double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
       for (int64_t t = 0; t < T; ++t)
         for (int v = 0; v < 3; ++v)
@@ -519,88 +662,74 @@ sbr_status sbr_scene_build(sbr_context_t ctx, const double* tri_xyz, int64_t T, 
         *out = sc;
         return;
       }
-      // ---- geometry the tree needs, uploaded first so that the GPU builds
-      // the BVH while the host groups faces
-      // Scenes built with the Morton-ordered LBVH (above the context's
-      // bvh_ploc_max triangles) keep oversized triangles (box diagonal above a quarter of
-      // the scene's, at most kMaxBig, largest first) out of the tree: there
-      // every ancestor of such a leaf gets a box as large as the scene (a
-      // city's ground plane inflates a whole root-to-leaf chain), so nearly
-      // every ray would descend those chains.  Every ray tests them directly
-      // instead, before the traversal.  PLOC clustering merges large boxes
-      // late, near the root, by itself, so smaller scenes keep every
-      // triangle in the tree.
-      constexpr int kMaxBig = 16;
-      std::vector<std::pair<double, int32_t>> cand;
-      const bool linear_tree = T > c->tune.bvh_ploc_max;
-      for (int64_t t = 0; linear_tree && t < T; ++t) {
-        double d2 = 0.0;
-        for (int k = 0; k < 3; ++k) {
-          const double a = tri[9 * t + k], b = tri[9 * t + 3 + k], cc = tri[9 * t + 6 + k];
-          const double e = std::max(a, std::max(b, cc)) - std::min(a, std::min(b, cc));
-          d2 += e * e;
+      if (!gpu_prep) {
+        // ---- host preparation, uploaded first so that the GPU builds the
+        // BVH while the host groups faces.
+        // Scenes built with the Morton-ordered LBVH (above the context's
+        // bvh_ploc_max triangles) keep oversized triangles (box diagonal above
+        // a quarter of the scene's, at most kMaxBig, largest first) out of the
+        // tree: there every ancestor of such a leaf gets a box as large as the
+        // scene (a city's ground plane inflates a whole root-to-leaf chain),
+        // so nearly every ray would descend those chains.  Every ray tests them
+        // directly instead, before the traversal.  PLOC clustering merges
+        // large boxes late, near the root, by itself, so smaller scenes keep
+        // every triangle in the tree.
+        constexpr int kMaxBig = 16;
+        std::vector<std::pair<double, int32_t>> cand;
+        for (int64_t t = 0; t < T; ++t) {
+          double d2 = 0.0;
+          for (int k = 0; k < 3; ++k) {
+            const double a = tri[9 * t + k], b = tri[9 * t + 3 + k], cc = tri[9 * t + 6 + k];
+            const double e = std::max(a, std::max(b, cc)) - std::min(a, std::min(b, cc));
+            d2 += e * e;
+          }
+          if (d2 > 0.0625 * sc->diag * sc->diag) cand.push_back({d2, (int32_t)t});
         }
-        if (d2 > 0.0625 * sc->diag * sc->diag) cand.push_back({d2, (int32_t)t});
-      }
-      std::sort(cand.begin(), cand.end(), [](const auto& x, const auto& y) {
-        return x.first > y.first || (x.first == y.first && x.second < y.second);
-      });
-      if (cand.size() > (size_t)kMaxBig) cand.resize(kMaxBig);
-      std::vector<int32_t> big_ids;
-      std::vector<char> is_big((size_t)T, 0);
-      for (const auto& cb : cand) big_ids.push_back(cb.second), is_big[cb.second] = 1;
-      std::sort(big_ids.begin(), big_ids.end());
-      std::vector<int32_t> bvh_ids;
-      for (int64_t t = 0; t < T; ++t)
-        if (!is_big[t]) bvh_ids.push_back((int32_t)t);
-      sc->n_big = (int)big_ids.size();
-      sc->n_bvh = (int64_t)bvh_ids.size();
-      // FP32 vertices centred on the scene box; boxes of the tree's triangles
-      // (rounded outward in the builder)
-      std::vector<float> v32((size_t)T * 9), blo((size_t)sc->n_bvh * 3), bhi((size_t)sc->n_bvh * 3);
-      float slo[3] = {1e30f, 1e30f, 1e30f}, shi[3] = {-1e30f, -1e30f, -1e30f};
-      for (int64_t t = 0; t < T; ++t)
-        for (int k = 0; k < 3; ++k)
-          for (int v = 0; v < 3; ++v) v32[9 * t + 3 * v + k] = (float)(tri[9 * t + 3 * v + k] - sc->center[k]);
-      for (int64_t j = 0; j < sc->n_bvh; ++j) {
-        const int64_t t = bvh_ids[j];
-        for (int k = 0; k < 3; ++k) {
-          float mn = 1e30f, mx = -1e30f;
-          for (int v = 0; v < 3; ++v) mn = std::min(mn, v32[9 * t + 3 * v + k]), mx = std::max(mx, v32[9 * t + 3 * v + k]);
-          blo[3 * j + k] = mn, bhi[3 * j + k] = mx;
-          slo[k] = std::min(slo[k], mn), shi[k] = std::max(shi[k], mx);
+        std::sort(cand.begin(), cand.end(), [](const auto& x, const auto& y) {
+          return x.first > y.first || (x.first == y.first && x.second < y.second);
+        });
+        if (cand.size() > (size_t)kMaxBig) cand.resize(kMaxBig);
+        std::vector<int32_t> big_ids;
+        std::vector<char> is_big((size_t)T, 0);
+        for (const auto& cb : cand) big_ids.push_back(cb.second), is_big[cb.second] = 1;
+        std::sort(big_ids.begin(), big_ids.end());
+        std::vector<int32_t> bvh_ids;
+        for (int64_t t = 0; t < T; ++t)
+          if (!is_big[t]) bvh_ids.push_back((int32_t)t);
+        sc->n_big = (int)big_ids.size();
+        sc->n_bvh = (int64_t)bvh_ids.size();
+        // FP32 vertices centred on the scene box; boxes of the tree's
+        // triangles (rounded outward in the builder)
+        std::vector<float> v32((size_t)T * 9), blo((size_t)sc->n_bvh * 3), bhi((size_t)sc->n_bvh * 3);
+        float slo[3] = {1e30f, 1e30f, 1e30f}, shi[3] = {-1e30f, -1e30f, -1e30f};
+        for (int64_t t = 0; t < T; ++t)
+          for (int k = 0; k < 3; ++k)
+            for (int v = 0; v < 3; ++v) v32[9 * t + 3 * v + k] = (float)(tri[9 * t + 3 * v + k] - sc->center[k]);
+        for (int64_t j = 0; j < sc->n_bvh; ++j) {
+          const int64_t t = bvh_ids[j];
+          for (int k = 0; k < 3; ++k) {
+            float mn = 1e30f, mx = -1e30f;
+            for (int v = 0; v < 3; ++v)
+              mn = std::min(mn, v32[9 * t + 3 * v + k]), mx = std::max(mx, v32[9 * t + 3 * v + k]);
+            blo[3 * j + k] = mn, bhi[3 * j + k] = mx;
+            slo[k] = std::min(slo[k], mn), shi[k] = std::max(shi[k], mx);
+          }
         }
-      }
-      Buf dv32, dlo, dhi, order, dbvh_ids, dbig_ids;
-      // staging must hold everything before the first copy is issued (it is
-      // not resized in use); the group arrays are bounded by G <= T
-      const size_t need = tri.size() * 8 + (size_t)T * 32 + 2 * (size_t)T * 4 + (size_t)T * 32 + (size_t)T * 16 +
-                          ((size_t)T + 1) * 4 + (size_t)T * 4 + (v32.size() + 6 * T) * 4 + (size_t)T * 4 +
-                          20 * 256;
-      if (c->stage_bytes < need) {
-        if (c->stage) (void)hipHostFree(c->stage);
-        c->stage = nullptr;
-        c->stage_bytes = 0;
-        SBR_HIP(hipHostMalloc(&c->stage, need, hipHostMallocDefault));
-        c->stage_bytes = need;
-      }
-      Stager st(c);
-      {
-        HostPhase hp_up("host:scene_upload");
-        st.put(dv32, v32.data(), v32.size(), s);
-        st.put(dlo, blo.data(), blo.size(), s);
-        st.put(dhi, bhi.data(), bhi.size(), s);
-        st.put(dbvh_ids, bvh_ids.data(), bvh_ids.size(), s);
-      }
-      sc->nodes.alloc((size_t)std::max<int64_t>(sc->n_bvh - 1, 1) * 64, s);
-      sc->root_box.alloc(32, s);  // 6 floats of root box, then the depth word
-      sc->tri32.alloc((size_t)T * 48, s);
-      uint32_t* depth_dev = reinterpret_cast<uint32_t*>(sc->root_box.as<float>() + 6);
-      if (sc->n_bvh > 0) {
-        order.alloc((size_t)sc->n_bvh * 4, s);
-        build_bvh(dlo.as<float>(), dhi.as<float>(), sc->n_bvh, slo, shi,
-                  BvhOut{sc->nodes.as<float4>(), order.as<uint32_t>(), sc->root_box.as<float>(), nullptr, depth_dev}, s,
-                  linear_tree);
+        {
+          HostPhase hp_up("host:scene_upload");
+          st.put(dv32, v32.data(), v32.size(), s);
+          st.put(dlo, blo.data(), blo.size(), s);
+          st.put(dhi, bhi.data(), bhi.size(), s);
+          st.put(dbvh_ids, bvh_ids.data(), bvh_ids.size(), s);
+          st.put(dbig_ids, big_ids.data(), big_ids.size(), s);
+        }
+        alloc_tree();
+        if (sc->n_bvh > 0) {
+          order.alloc((size_t)sc->n_bvh * 4, s);
+          build_bvh(dlo.as<float>(), dhi.as<float>(), sc->n_bvh, slo, shi,
+                    BvhOut{sc->nodes.as<float4>(), order.as<uint32_t>(), sc->root_box.as<float>(), nullptr, depth_dev},
+                    s, /*linear=*/true);
+        }
       }
       // ---- planes, face groups and group tables on the host (overlapping the build)
       std::vector<Plane> pl((size_t)T);
@@ -641,20 +770,22 @@ sbr_status sbr_scene_build(sbr_context_t ctx, const double* tri_xyz, int64_t T, 
       }
       {
         HostPhase hp_up("host:scene_upload");
-        st.put(sc->tri64, tri.data(), tri.size(), s);
-        st.put(sc->tplane, tpl.data(), tpl.size(), s);
-        st.put(sc->tgroup, sc->h_group.data(), sc->h_group.size(), s);
-        st.put(sc->tplaneid, sc->h_plane.data(), sc->h_plane.size(), s);
-        st.put(sc->gplane, gpl.data(), gpl.size(), s);
-        st.put(sc->gmat, gmt.data(), gmt.size(), s);
-        st.put(sc->gstart, gstart.data(), gstart.size(), s);
-        st.put(sc->gtri, gtri.data(), gtri.size(), s);
-        st.put(dbig_ids, big_ids.data(), big_ids.size(), s);
+        if (!gpu_prep) st.put(sc->tri64, tri.data(), tri.size(), s);
+        st.add(sc->tplane, tpl.data(), tpl.size());
+        st.add(sc->tgroup, sc->h_group.data(), sc->h_group.size());
+        st.add(sc->tplaneid, sc->h_plane.data(), sc->h_plane.size());
+        st.add(sc->gplane, gpl.data(), gpl.size());
+        st.add(sc->gmat, gmt.data(), gmt.size());
+        st.add(sc->gstart, gstart.data(), gstart.size());
+        st.add(sc->gtri, gtri.data(), gtri.size());
+        st.flush(sc->tables, s);
       }
       if (sc->n_bvh > 0) {
+        // leaves in tree order; device-prepared scenes hold every triangle in the tree
         hipLaunchKernelGGL(k_tri_gather, dim3(nblk(sc->n_bvh, 256)), dim3(256), 0, s, order.as<uint32_t>(),
-                           dbvh_ids.as<int32_t>(), sc->n_bvh, (int64_t)0, dv32.as<float>(),
-                           sc->tplaneid.as<int32_t>(), sc->tgroup.as<int32_t>(), sc->tri32.as<float4>());
+                           gpu_prep ? (const int32_t*)nullptr : dbvh_ids.as<int32_t>(), sc->n_bvh, (int64_t)0,
+                           dv32.as<float>(), sc->tplaneid.as<int32_t>(), sc->tgroup.as<int32_t>(),
+                           sc->tri32.as<float4>());
         SBR_LAUNCH_CHECK();
       }
       if (sc->n_big > 0) {
@@ -722,6 +853,8 @@ sbr_status sbr_trace(sbr_context_t ctx, sbr_scene_t scene, const double* tx_xyz,
               (long long)Nt * R);
     set_device(c);
     hipStream_t s = c->stream;
+    std::optional<HostPhase> hp_step;
+    hp_step.emplace("host:trace_setup");
     const auto htx = to_host(tx_xyz, (size_t)Nt * 3, flags, s);
     SBR_CHECK(finite_all(htx.data(), htx.size()), SBR_E_INVALID_ARG, "tx coordinates must be finite");
     auto* tr = new sbr_trace_s();
@@ -752,6 +885,7 @@ sbr_status sbr_trace(sbr_context_t ctx, sbr_scene_t scene, const double* tx_xyz,
       L.block = 256;
       L.grid = c->num_cus * c->tune.trace_blocks_per_cu;
       L.chunk = c->tune.trace_chunk;
+      hp_step.emplace("host:trace_launch");
       launch_trace(L, ra, rb, s);
     } catch (...) {
       release(tr);

@@ -93,6 +93,11 @@ struct Buf {
   Buf& operator=(const Buf&) = delete;
   ~Buf() { reset(); }
   void alloc(size_t n, hipStream_t s);
+  // a non-owning view of n bytes inside another Buf's block (reset() only forgets it)
+  void view(void* base, size_t n) {
+    reset();
+    p = base, bytes = n;
+  }
   void reset();
   template <class T> T* as() const { return static_cast<T*>(p); }
 };
@@ -163,6 +168,7 @@ struct sbr_context_s : sbr::Handle {
   bool count_work = false;
   void* stage = nullptr;  // pinned host staging for uploads
   size_t stage_bytes = 0;
+  hipEvent_t ev_inputs = nullptr;  // marks the end of a scene's input copies
   std::vector<sbr::TraceGraph*> graphs;  // cached bounce-loop graphs
   // cached geodesic edge statistics per N
   std::vector<std::pair<int, double>> alpha_cache;
@@ -198,6 +204,7 @@ struct sbr_scene_s : sbr::Handle {
   sbr::Buf gmat;     // float4 per group: eps_r, sigma, rough, 0
   sbr::Buf gstart;   // int[G+1]
   sbr::Buf gtri;     // int[T]
+  sbr::Buf tables;   // one block holding tplane .. gtri (those are views into it)
   sbr_scene_s() : Handle(sbr::kScene) {}
   ~sbr_scene_s() override;
 };
@@ -278,6 +285,9 @@ struct BvhOut {
   // optional: asynchronous build.  The depth is written to this device word
   // and build_bvh returns 0 without synchronising (root_host is not filled).
   uint32_t* depth_dev = nullptr;
+  // optional: scene bounds (lo xyz, hi xyz) in device memory, used for the
+  // Morton codes instead of scene_lo / scene_hi (which may then be null)
+  const float* bounds_dev = nullptr;
 };
 int build_bvh(const float* box_lo, const float* box_hi, int64_t n, const float scene_lo[3],
               const float scene_hi[3], BvhOut out, hipStream_t s, bool linear = false);
