@@ -79,7 +79,7 @@ def committed_traffic(workload):
 
 KERNEL_CLASSES = ["bounce", "replay_capture", "rebuild", "channel", "keys", "sort", "scan", "order", "bvh", "stats",
                   "misc", "alpha", "host:scene_build", "host:scene_inputs", "host:face_groups", "host:scene_upload",
-                  "host:rx_tree", "host:trace_setup", "host:trace_launch"]
+                  "host:rx_tree", "host:receive", "host:trace_setup", "host:trace_launch"]
 
 
 def breakdown(S, ctx, run, steps=2, exclude=()):

@@ -18,6 +18,7 @@
 // from.
 #include "sbr_device.hpp"
 #include "sbr_internal.hpp"
+#include "lds_sort.hpp"
 
 namespace sbr {
 namespace {
@@ -29,6 +30,22 @@ __device__ inline uint32_t spread10(uint32_t v) {
   v = (v | (v << 4)) & 0x030C30C3u;
   v = (v | (v << 2)) & 0x09249249u;
   return v;
+}
+
+// 30-bit Morton code of primitive i's box centre, quantised to 1024 cells per
+// axis of the scene box slo + [0, 1/inv_ext]
+__device__ inline uint32_t morton_code(const float* __restrict__ lo, const float* __restrict__ hi, int64_t i,
+                                       float3 slo, float3 inv_ext) {
+  const float cx = 0.5f * (lo[3 * i] + hi[3 * i]);
+  const float cy = 0.5f * (lo[3 * i + 1] + hi[3 * i + 1]);
+  const float cz = 0.5f * (lo[3 * i + 2] + hi[3 * i + 2]);
+  auto q = [](float c, float l, float ie) {
+    float u = (c - l) * ie;
+    u = fminf(fmaxf(u, 0.0f), 1.0f);
+    return (uint32_t)fminf(u * 1024.0f, 1023.0f);
+  };
+  return (spread10(q(cx, slo.x, inv_ext.x)) << 2) | (spread10(q(cy, slo.y, inv_ext.y)) << 1) |
+         spread10(q(cz, slo.z, inv_ext.z));
 }
 
 // Quantised centroid positions in the scene box slo + [0, 1/inv_ext]; with
@@ -45,31 +62,21 @@ __global__ void k_morton(const float* __restrict__ lo, const float* __restrict__
     inv_ext.y = bounds[4] > bounds[1] ? 1.0f / (bounds[4] - bounds[1]) : 0.0f;
     inv_ext.z = bounds[5] > bounds[2] ? 1.0f / (bounds[5] - bounds[2]) : 0.0f;
   }
-  const float cx = 0.5f * (lo[3 * i] + hi[3 * i]);
-  const float cy = 0.5f * (lo[3 * i + 1] + hi[3 * i + 1]);
-  const float cz = 0.5f * (lo[3 * i + 2] + hi[3 * i + 2]);
-  auto q = [](float c, float l, float ie) {
-    float u = (c - l) * ie;
-    u = fminf(fmaxf(u, 0.0f), 1.0f);
-    return (uint32_t)fminf(u * 1024.0f, 1023.0f);
-  };
-  const uint32_t m = (spread10(q(cx, slo.x, inv_ext.x)) << 2) | (spread10(q(cy, slo.y, inv_ext.y)) << 1) |
-                     spread10(q(cz, slo.z, inv_ext.z));
-  code[i] = m;
+  code[i] = morton_code(lo, hi, i, slo, inv_ext);
   idx[i] = (uint32_t)i;
 }
 
-__device__ inline int delta(const uint64_t* __restrict__ code, int64_t n, int64_t i, int64_t j) {
+__device__ inline int delta(const uint64_t* code, int64_t n, int64_t i, int64_t j) {
   if (j < 0 || j >= n) return -1;
   const uint64_t a = code[i], b = code[j];
   if (a == b) return 64 + __clz((uint32_t)(i ^ j));
   return __clzll(a ^ b);
 }
 
-__global__ void k_karras(const uint64_t* __restrict__ code, int64_t n, float4* __restrict__ nodes,
-                         int32_t* __restrict__ parent_int, int32_t* __restrict__ parent_leaf) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n - 1) return;
+// Children of internal node i of the Karras hierarchy over n sorted codes
+// (unique as (code, index)): its key range from the longest common prefix,
+// then the split; a child is a leaf (~index) when its range is one key.
+__device__ inline void karras_node(const uint64_t* code, int64_t n, int64_t i, int32_t& cl, int32_t& cr) {
   const int d = (delta(code, n, i, i + 1) - delta(code, n, i, i - 1)) >= 0 ? 1 : -1;
   const int dmin = delta(code, n, i, i - d);
   int64_t lmax = 2;
@@ -86,21 +93,20 @@ __global__ void k_karras(const uint64_t* __restrict__ code, int64_t n, float4* _
   } while (t > 1);
   const int64_t gamma = i + s * d + (d < 0 ? -1 : 0);
   const int64_t lo = i < j ? i : j, hi = i < j ? j : i;
+  cl = lo == gamma ? ~(int32_t)gamma : (int32_t)gamma;
+  cr = hi == gamma + 1 ? ~(int32_t)(gamma + 1) : (int32_t)(gamma + 1);
+}
+
+__global__ void k_karras(const uint64_t* __restrict__ code, int64_t n, float4* __restrict__ nodes,
+                         int32_t* __restrict__ parent_int, int32_t* __restrict__ parent_leaf) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n - 1) return;
   int32_t cl, cr;
-  if (lo == gamma) {
-    cl = ~(int32_t)gamma;
-    parent_leaf[gamma] = (int32_t)i;
-  } else {
-    cl = (int32_t)gamma;
-    parent_int[gamma] = (int32_t)i;
-  }
-  if (hi == gamma + 1) {
-    cr = ~(int32_t)(gamma + 1);
-    parent_leaf[gamma + 1] = (int32_t)i;
-  } else {
-    cr = (int32_t)(gamma + 1);
-    parent_int[gamma + 1] = (int32_t)i;
-  }
+  karras_node(code, n, i, cl, cr);
+  if (cl < 0) parent_leaf[~cl] = (int32_t)i;
+  else parent_int[cl] = (int32_t)i;
+  if (cr < 0) parent_leaf[~cr] = (int32_t)i;
+  else parent_int[cr] = (int32_t)i;
   nodes[4 * i + 3] = make_float4(__int_as_float(cl), __int_as_float(cr), 0.0f, 0.0f);
   if (i == 0) parent_int[0] = -1;
 }
@@ -162,6 +168,88 @@ __global__ void k_depth(const int32_t* __restrict__ parent_int, const int32_t* _
     ++d;
   }
   atomicMax(depth, d);
+}
+
+// Small linear trees (receiver sets, small scenes) in one workgroup: the
+// same Morton codes, stable sort, hierarchy and boxes as the multi-kernel
+// path (so the same tree), with codes, links and node boxes in LDS.  The
+// refit climbs from every leaf; an LDS counter per node lets the second
+// arrival merge it (its sibling's box and height were stored before the
+// sibling's release-increment), and node heights give the depth: the
+// number of internal nodes on the longest root-to-leaf path.
+constexpr int kLbvhSmall = 2048;
+__global__ __launch_bounds__(kSmallThreads) void k_lbvh_small(const float* __restrict__ lo,
+                                                            const float* __restrict__ hi, int n, float3 slo,
+                                                            float3 inv_ext, float4* __restrict__ nodes,
+                                                            uint32_t* __restrict__ order, float* __restrict__ root_box,
+                                                            uint32_t* __restrict__ depth) {
+  __shared__ uint64_t lk[kLbvhSmall];
+  __shared__ uint32_t lv[kLbvhSmall];
+  __shared__ uint16_t hist[kSmallWaves][256];
+  __shared__ uint32_t dsum[kSmallWaves / 4];
+  __shared__ int32_t ch[kLbvhSmall][2];
+  __shared__ int32_t par_int[kLbvhSmall], par_leaf[kLbvhSmall];
+  __shared__ float nbox[kLbvhSmall][6];
+  __shared__ uint32_t ht[kLbvhSmall], arrive[kLbvhSmall];
+  const int t = threadIdx.x;
+  for (int i = t; i < n; i += kSmallThreads) {
+    lk[i] = morton_code(lo, hi, i, slo, inv_ext);
+    lv[i] = (uint32_t)i;
+    arrive[i] = 0;
+  }
+  __syncthreads();
+  lds_radix_sort_pairs<kLbvhSmall / kSmallThreads>(lk, lv, hist, dsum, n, 0, 30);
+  for (int i = t; i < n - 1; i += kSmallThreads) {
+    int32_t cl, cr;
+    karras_node(lk, n, i, cl, cr);
+    ch[i][0] = cl, ch[i][1] = cr;
+    if (cl < 0) par_leaf[~cl] = i;
+    else par_int[cl] = i;
+    if (cr < 0) par_leaf[~cr] = i;
+    else par_int[cr] = i;
+  }
+  for (int i = t; i < n; i += kSmallThreads) order[i] = lv[i];
+  __syncthreads();
+  auto leaf_box = [&](int leaf, float* b) {
+    const uint32_t prim = lv[leaf];
+    for (int k = 0; k < 3; ++k) {
+      b[k] = nextafterf(lo[3 * prim + k], -INFINITY);
+      b[3 + k] = nextafterf(hi[3 * prim + k], INFINITY);
+    }
+  };
+  for (int i = t; i < n; i += kSmallThreads) {
+    int32_t p = par_leaf[i];
+    while (true) {
+      const uint32_t old = __hip_atomic_fetch_add(&arrive[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (old == 0) break;  // the other child is not finished; its climb continues here
+      float b[2][6];
+      uint32_t h = 0;
+      for (int c = 0; c < 2; ++c) {
+        const int32_t x = ch[p][c];
+        if (x < 0) {
+          leaf_box(~x, b[c]);
+        } else {
+          for (int k = 0; k < 6; ++k) b[c][k] = nbox[x][k];
+          h = max(h, ht[x]);
+        }
+      }
+      float u[6];
+      for (int k = 0; k < 3; ++k) u[k] = fminf(b[0][k], b[1][k]), u[3 + k] = fmaxf(b[0][3 + k], b[1][3 + k]);
+      for (int k = 0; k < 6; ++k) nbox[p][k] = u[k];
+      ht[p] = h + 1;
+      float4* o = nodes + 4 * (int64_t)p;
+      o[0] = make_float4(b[0][0], b[0][1], b[0][2], b[0][3]);
+      o[1] = make_float4(b[0][4], b[0][5], b[1][0], b[1][1]);
+      o[2] = make_float4(b[1][2], b[1][3], b[1][4], b[1][5]);
+      o[3] = make_float4(__int_as_float(ch[p][0]), __int_as_float(ch[p][1]), 0.0f, 0.0f);
+      if (p == 0) {
+        for (int k = 0; k < 6; ++k) root_box[k] = u[k];
+        *depth = h + 1;
+        break;
+      }
+      p = par_int[p];
+    }
+  }
 }
 
 __global__ void k_single_leaf(const float* __restrict__ lo, const float* __restrict__ hi, float4* nodes,
@@ -531,6 +619,31 @@ int build_bvh(const float* box_lo, const float* box_hi, int64_t n, const float s
     return 1;
   }
   const bool ploc = !linear && n <= kPlocMax;
+  if (!ploc && n <= kLbvhSmall) {
+    float3 slo = make_float3(0.0f, 0.0f, 0.0f), ie = make_float3(0.0f, 0.0f, 0.0f);
+    if (!out.bounds_dev) {
+      slo = make_float3(scene_lo[0], scene_lo[1], scene_lo[2]);
+      ie.x = scene_hi[0] > scene_lo[0] ? 1.0f / (scene_hi[0] - scene_lo[0]) : 0.0f;
+      ie.y = scene_hi[1] > scene_lo[1] ? 1.0f / (scene_hi[1] - scene_lo[1]) : 0.0f;
+      ie.z = scene_hi[2] > scene_lo[2] ? 1.0f / (scene_hi[2] - scene_lo[2]) : 0.0f;
+    }
+    SBR_CHECK(!out.bounds_dev, SBR_E_UNSUPPORTED, "device scene bounds with the small linear builder");
+    Buf dword;
+    uint32_t* dd = out.depth_dev;
+    if (!dd) {
+      dword.alloc(4, s);
+      dd = dword.as<uint32_t>();
+    }
+    { ::sbr::TimedLaunch tl_("bvh", s); hipLaunchKernelGGL(k_lbvh_small, dim3(1), dim3(kSmallThreads), 0, s, box_lo, box_hi, (int)n, slo, ie,
+                       out.nodes, out.order, out.root_box, dd); }
+    SBR_LAUNCH_CHECK();
+    if (out.depth_dev) return 0;
+    uint32_t depth = 0;
+    SBR_HIP(hipMemcpyAsync(&depth, dd, 4, hipMemcpyDeviceToHost, s));
+    if (out.root_host) SBR_HIP(hipMemcpyAsync(out.root_host, out.root_box, 24, hipMemcpyDeviceToHost, s));
+    SBR_HIP(hipStreamSynchronize(s));
+    return (int)depth;
+  }
   Buf codes, codes2, idx, parents, flags, temp;
   codes.alloc(n * 8, s);
   codes2.alloc(n * 8, s);

@@ -553,8 +553,9 @@ void run_receive(sbr_paths_s* ps, const double* hrx, hipStream_t s) {
   // ---------------- Rx BVH (FP32 boxes in a frame centred on the Rx bounding sphere).
   // Receiver points are clustered with the Morton-ordered LBVH: it builds
   // faster than PLOC for point sets and the capture queries ran faster on it.
-  HostPhase hp_rx("host:rx_tree");
-  std::optional<HostPhase> hp_step;
+  HostPhase hp_all("host:receive");
+  std::optional<HostPhase> hp_rx, hp_step;
+  hp_rx.emplace("host:rx_tree");
   hp_step.emplace("host:rx_boxes");
   double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
   for (int q = 0; q < Nr; ++q)
@@ -593,6 +594,7 @@ void run_receive(sbr_paths_s* ps, const double* hrx, hipStream_t s) {
                 /*linear=*/true);
   SBR_CHECK(rdepth <= 64, SBR_E_UNSUPPORTED, "receiver tree depth %d", rdepth);
   hp_step.reset();
+  hp_rx.reset();
 
   // ---------------- replay + capture (grow the event buffer and retry on overflow)
   ReplayParams P{};

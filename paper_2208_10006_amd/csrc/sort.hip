@@ -8,6 +8,7 @@
 // counts of earlier waves and earlier rounds gives the stable local offset.
 #include "sbr_device.hpp"
 #include "sbr_internal.hpp"
+#include "lds_sort.hpp"
 
 namespace sbr {
 
@@ -228,19 +229,9 @@ void gather_u64(const uint64_t* src, const uint32_t* idx, uint64_t* dst, int64_t
 }
 
 // Small arrays (up to kSmallSort keys): the whole LSD radix sort in one
-// workgroup with 8-bit digits, keys and values resident in LDS between one
-// coalesced load and one coalesced store.  Wave w owns the contiguous block
-// [w * 64 * P, (w + 1) * 64 * P) of the current order, P = ceil(n / 1024),
-// and walks it in rounds of 64 (element w*64*P + u*64 + lane in round u), so
-// the order (wave, round, lane) is the array order.  In a round, the lanes
-// holding the same digit are found with eight ballots; the lowest of them
-// adds the group's size to the wave's digit count in LDS after every lane of
-// the group has read the count, which gives each element its place among the
-// wave's equal digits.  A scan of the counts in (digit, wave) order turns
-// them into offsets, and every element is written to offset + place: a
-// stable counting sort per pass.
-constexpr int kSmallThreads = 1024, kSmallPer = 12, kSmallSort = kSmallThreads * kSmallPer;
-constexpr int kSmallWaves = kSmallThreads / 64;
+// workgroup (lds_radix_sort_pairs), keys and values resident in LDS between
+// one coalesced load and one coalesced store.
+constexpr int kSmallPer = 12, kSmallSort = kSmallThreads * kSmallPer;
 
 __global__ __launch_bounds__(kSmallThreads) void k_radix_sort_small(const uint64_t* __restrict__ kin,
                                                                   const uint32_t* __restrict__ vin,
@@ -248,77 +239,12 @@ __global__ __launch_bounds__(kSmallThreads) void k_radix_sort_small(const uint64
                                                                   int n, int bit_lo, int bit_hi) {
   __shared__ uint64_t lk[kSmallSort];
   __shared__ uint32_t lv[kSmallSort];
-  __shared__ uint16_t hist[kSmallWaves][256];  // per wave and digit: count, then offset
-  __shared__ uint32_t dsum[kSmallWaves / 4];    // digit totals of the scan's 4 waves
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int P = (n + kSmallThreads - 1) / kSmallThreads;  // rounds per wave, <= kSmallPer
-  const int w0 = wv * 64 * P;
-  const int npass = (bit_hi - bit_lo + 7) / 8;
-  const uint64_t lt = lanemask_lt();
+  __shared__ uint16_t hist[kSmallWaves][256];
+  __shared__ uint32_t dsum[kSmallWaves / 4];
+  const int t = threadIdx.x;
   for (int i = t; i < n; i += kSmallThreads) lk[i] = kin[i], lv[i] = vin[i];
   __syncthreads();
-  for (int p = 0; p < npass; ++p) {
-    const int shift = bit_lo + 8 * p;
-    for (int d = lane; d < 256; d += 64) hist[wv][d] = 0;
-    uint64_t ck[kSmallPer];
-    uint32_t cv[kSmallPer];
-    uint32_t place[kSmallPer];
-#pragma unroll
-    for (int u = 0; u < kSmallPer; ++u) {
-      if (u >= P) break;  // wave-uniform
-      const int i = w0 + u * 64 + lane;
-      const bool ok = i < n;
-      uint32_t d = 0;
-      if (ok) {
-        ck[u] = lk[i], cv[u] = lv[i];
-        d = (uint32_t)(ck[u] >> shift) & 255u;
-      }
-      uint64_t m = __ballot(ok);
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        const uint64_t bb = __ballot(ok && ((d >> b) & 1u));
-        m &= ((d >> b) & 1u) ? bb : ~bb;
-      }
-      const uint32_t before = ok ? hist[wv][d] : 0u;  // every lane reads before the leader writes
-      place[u] = before + (uint32_t)__popcll(m & lt);
-      if (ok && (m & lt) == 0) hist[wv][d] = (uint16_t)(before + (uint32_t)__popcll(m));
-    }
-    __syncthreads();
-    // offsets in (digit, wave) order: threads 0..255 own one digit each
-    uint32_t excl_digit = 0;
-    if (t < 256) {
-      uint32_t run = 0;
-#pragma unroll
-      for (int w = 0; w < kSmallWaves; ++w) {
-        const uint32_t c = hist[w][t];
-        hist[w][t] = (uint16_t)run;
-        run += c;
-      }
-      const uint32_t incl = wave_inclusive_scan(run, lane);
-      if (lane == 63) dsum[wv] = incl;
-      excl_digit = incl - run;  // digits before this one within the scanning wave
-    }
-    __syncthreads();
-    if (t < 256) {
-      uint32_t base = excl_digit;
-      for (int w = 0; w < wv; ++w) base += dsum[w];
-#pragma unroll
-      for (int w = 0; w < kSmallWaves; ++w) hist[w][t] = (uint16_t)(hist[w][t] + base);
-    }
-    __syncthreads();  // offsets complete; every element was read before the first barrier
-#pragma unroll
-    for (int u = 0; u < kSmallPer; ++u) {
-      if (u >= P) break;
-      const int i = w0 + u * 64 + lane;
-      if (i < n) {
-        const uint32_t d = (uint32_t)(ck[u] >> shift) & 255u;
-        const uint32_t pos = (uint32_t)hist[wv][d] + place[u];
-        lk[pos] = ck[u];
-        lv[pos] = cv[u];
-      }
-    }
-    __syncthreads();
-  }
+  lds_radix_sort_pairs<kSmallPer>(lk, lv, hist, dsum, n, bit_lo, bit_hi);
   for (int i = t; i < n; i += kSmallThreads) {
     kout[i] = lk[i];
     vout[i] = lv[i];
