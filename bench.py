@@ -82,13 +82,16 @@ KERNEL_CLASSES = ["bounce", "replay_capture", "rebuild", "channel", "keys", "sor
                   "host:rx_tree", "host:receive", "host:trace_setup", "host:trace_launch"]
 
 
-def breakdown(S, ctx, run, steps=2, exclude=()):
+def breakdown(S, ctx, run, steps=2, exclude=(), more=()):
     """Per-class kernel and host-phase times from extra, untimed steps with
     every class profiled (the event records add host overhead, which is why
-    the timed steps profile the dominant kernel only)."""
+    the timed steps profile the dominant kernel only).  With several contexts
+    (`more`: contexts that work concurrently) the times are summed over them."""
     import torch
-    S.sbr_profile_only(ctx, None)
-    S.sbr_profile_enable(ctx, True)
+    ctxs = [ctx, *more]
+    for c in ctxs:
+        S.sbr_profile_only(c, None)
+        S.sbr_profile_enable(c, True)
     for _ in range(steps):
         h = run()
         del h
@@ -97,11 +100,20 @@ def breakdown(S, ctx, run, steps=2, exclude=()):
     for name in KERNEL_CLASSES:
         if name in exclude:
             continue
-        ms, n = S.sbr_profile_query(ctx, name)
+        ms = n = 0
+        for c in ctxs:
+            a, b = S.sbr_profile_query(c, name)
+            ms, n = ms + a, n + b
         if n:
             out[name] = {"ms_per_step": ms / steps, "launches_per_step": n / steps}
-    S.sbr_profile_enable(ctx, False)
+    for c in ctxs:
+        S.sbr_profile_enable(c, False)
     return out
+
+
+def w_cost(w):
+    """Rough trace cost of a workload: rays x (bounces + 1)."""
+    return len(w.tx) * (10 * w.geodesic_N ** 2 + 2) * (w.max_bounces + 1)
 
 
 def describe(w):
@@ -167,14 +179,43 @@ def batched_main(args):
     log(f"[bench] batched: {len(ws)} scenes, T {sum(w.T for w in ws)} triangles, "
         f"{sum(w.rays_per_element for w in ws)} rays")
 
+    # The per-scene tails (receive, channel, statistics) run on a pool of
+    # contexts, each with its own stream and host thread, largest traces
+    # first: the kernels of one small scene do not fill the GPU, and the
+    # host work of one scene overlaps the kernels of others.  A batched
+    # trace has finished when sbr_trace_batch returns, so any context may
+    # receive it.
+    import concurrent.futures as cf
+    import itertools
+    n_tail = max(1, min(args.tail_contexts, len(ws)))
+    tail_ctx = [S.Context(0) for _ in range(n_tail)]
+    pool = cf.ThreadPoolExecutor(n_tail)
+    order = sorted(range(len(ws)), key=lambda i: -w_cost(ws[i]))
+
+    def tails(trs):
+        nxt = itertools.count()
+
+        def worker(c):
+            while True:
+                k = next(nxt)
+                if k >= len(order):
+                    break
+                i = order[k]
+                w, d = ws[i], ins[i]
+                ps = S.sbr_receive(c, trs[i], d["rx"], 0.0, w.radius_coeff)
+                S.sbr_channel(c, ps, d["freq"], None, None, S.SBR_POL_V, S.SBR_POL_V, H_c64=d["H"])
+                S.sbr_stats_device(ps, d["pg"], d["tau"], d["ang"])
+            S.sbr_synchronize(c)
+
+        for f in [pool.submit(worker, c) for c in tail_ctx]:
+            f.result()
+
     def one_step():
-        scenes = [S.sbr_scene_build(ctx, d["tri"], d["eps"], d["sig"], d["rough"]) for d in ins]
+        scenes = S.sbr_scene_build_batch(ctx, [d["tri"] for d in ins], [d["eps"] for d in ins],
+                                         [d["sig"] for d in ins], [d["rough"] for d in ins])
         trs = S.sbr_trace_batch(ctx, scenes, [d["tx"] for d in ins], [w.geodesic_N for w in ws],
                                 [w.max_bounces for w in ws])
-        for w, d, tr in zip(ws, ins, trs):
-            ps = S.sbr_receive(ctx, tr, d["rx"], 0.0, w.radius_coeff)
-            S.sbr_channel(ctx, ps, d["freq"], None, None, S.SBR_POL_V, S.SBR_POL_V, H_c64=d["H"])
-            S.sbr_stats_device(ps, d["pg"], d["tau"], d["ang"])
+        tails(trs)
         return scenes, trs
 
     for i in range(args.warmup):
@@ -196,7 +237,8 @@ def batched_main(args):
     bounce_ms, bounce_n = S.sbr_profile_query(ctx, "bounce")
     S.sbr_profile_enable(ctx, False)
     kernels = {"bounce": {"ms_per_step": bounce_ms / args.steps, "launches_per_step": bounce_n / args.steps}}
-    kernels.update(breakdown(S, ctx, one_step, exclude=("bounce",)))
+    kernels.update(breakdown(S, ctx, one_step, exclude=("bounce",), more=tail_ctx))
+    pool.shutdown()
     lat = np.array(lat)
     out = {"metric": "traced ray-segments/s (batched uneven scenes)", "value": segs * args.steps / (t1 - t0),
            "unit": "ray-segments/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -294,6 +336,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--scenes", type=int, default=64, help="batched_uneven: number of scenes")
+    ap.add_argument("--tail-contexts", type=int, default=8,
+                    help="batched_uneven: contexts (streams and host threads) for the per-scene receives")
     ap.add_argument("--surrogate-steps", type=int, default=0, help="surrogate: training steps per member")
     ap.add_argument("--bvh-ploc-max", type=int, default=None,
                     help="largest scene (triangles) clustered with PLOC; larger ones use the LBVH")

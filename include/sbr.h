@@ -75,7 +75,12 @@ typedef struct {
 
 /* ------------------------------------------------------------------------ */
 /* Context.  device: HIP ordinal.  hip_stream: a hipStream_t to run on, or
- * NULL for a library-owned stream.  */
+ * NULL for a library-owned stream.  Contexts are independent: calls on
+ * different contexts may run at the same time from different host threads
+ * (one thread per context at a time).  A handle made on one context may be
+ * passed to calls on another once the work that made it has finished: scene
+ * builds, batched traces and receives finish before they return; after
+ * sbr_trace call sbr_synchronize on its context first.  */
 sbr_status sbr_context_create(int device, void* hip_stream, sbr_context_t* out);
 /* Block until all work queued by this context has finished. */
 sbr_status sbr_synchronize(sbr_context_t ctx);
@@ -91,6 +96,20 @@ sbr_status sbr_synchronize(sbr_context_t ctx);
 sbr_status sbr_scene_build(sbr_context_t ctx, const double* tri_xyz, int64_t T, const float* eps_r,
                            const float* sigma_S_per_m, const float* rough_std_m, uint32_t flags,
                            sbr_scene_t* out);
+/* Several scenes at once (the batched form of sbr_scene_build, for the many
+ * scenes of a batched trace): scene i from tri_xyz[i] ([T[i]][3][3]) and the
+ * material arrays eps_r[i], sigma_S_per_m[i], rough_std_m[i], all host or all
+ * device arrays as `flags` says.  Up to 8 worker threads, each with its own
+ * stream and pinned staging area, build the scenes largest first, so the host
+ * work (validation, planes, face groups) of different scenes and their tree
+ * builds on the GPU overlap.  The scenes are the ones sbr_scene_build would
+ * return and belong to ctx like them.  Device inputs are read after the
+ * context's stream has finished its earlier work.  out[i] receives scene i;
+ * on error no scene is returned (out untouched) and the message names the
+ * failing scene.  Not to be called concurrently on one context. */
+sbr_status sbr_scene_build_batch(sbr_context_t ctx, int32_t n, const double* const* tri_xyz, const int64_t* T,
+                                 const float* const* eps_r, const float* const* sigma_S_per_m,
+                                 const float* const* rough_std_m, uint32_t flags, sbr_scene_t* out);
 
 /* Launch + trace (Sec. II-A-1, II-A-2).  Every Tx element (eq. (11)) launches
  * 10 N^2 + 2 rays along the frequency-N icosahedral geodesic directions

@@ -10,6 +10,8 @@
 #include <functional>
 #include <mutex>
 #include <optional>
+#include <string>
+#include <thread>
 #include <vector>
 
 #include "sbr_device.hpp"
@@ -188,6 +190,19 @@ void release(Handle* h) {
   if (h && h->refs.fetch_sub(1) == 1) delete h;
 }
 
+void HostStage::reserve(size_t need) {
+  if (bytes >= need) return;
+  if (p) (void)hipHostFree(p);
+  p = nullptr;
+  bytes = 0;
+  SBR_HIP(hipHostMalloc(&p, need, hipHostMallocDefault));
+  bytes = need;
+}
+HostStage::~HostStage() {
+  if (p) (void)hipHostFree(p);
+  if (ev) (void)hipEventDestroy(ev);
+}
+
 namespace {
 
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -253,25 +268,21 @@ void upload(Buf& b, const T* p, size_t n, uint32_t flags, hipStream_t s) {
 // asynchronously; the caller synchronises the stream before the staging area
 // is written again.
 struct Stager {
-  sbr_context_s* c;
+  HostStage* c;
   size_t off = 0;
-  explicit Stager(sbr_context_s* cc) : c(cc) {}
+  explicit Stager(HostStage& h) : c(&h) {}
   template <class T>
   void put(Buf& b, const T* src, size_t n, hipStream_t s) {
     b.alloc(n * sizeof(T), s);
     if (n == 0) return;
     const size_t bytes = n * sizeof(T);
     const size_t at = (off + 255) & ~size_t(255);
-    if (at + bytes > c->stage_bytes) {
+    if (at + bytes > c->bytes) {
       SBR_CHECK(off == 0, SBR_E_DEVICE, "staging area resized while in use");
-      if (c->stage) (void)hipHostFree(c->stage);
-      c->stage = nullptr;
-      c->stage_bytes = 0;
-      SBR_HIP(hipHostMalloc(&c->stage, at + bytes + (1 << 20), hipHostMallocDefault));
-      c->stage_bytes = at + bytes + (1 << 20);
+      c->reserve(at + bytes + (1 << 20));
     }
-    std::memcpy(static_cast<char*>(c->stage) + at, src, bytes);
-    SBR_HIP(hipMemcpyAsync(b.p, static_cast<char*>(c->stage) + at, bytes, hipMemcpyHostToDevice, s));
+    std::memcpy(static_cast<char*>(c->p) + at, src, bytes);
+    SBR_HIP(hipMemcpyAsync(b.p, static_cast<char*>(c->p) + at, bytes, hipMemcpyHostToDevice, s));
     off = at + bytes;
   }
   // Packed uploads: add() places arrays side by side in the staging area,
@@ -287,8 +298,8 @@ struct Stager {
   void add(Buf& b, const T* src, size_t n) {
     const size_t bytes = n * sizeof(T);
     const size_t at = (off + 255) & ~size_t(255);
-    SBR_CHECK(at + bytes <= c->stage_bytes, SBR_E_DEVICE, "staging area too small for packed uploads");
-    if (bytes) std::memcpy(static_cast<char*>(c->stage) + at, src, bytes);
+    SBR_CHECK(at + bytes <= c->bytes, SBR_E_DEVICE, "staging area too small for packed uploads");
+    if (bytes) std::memcpy(static_cast<char*>(c->p) + at, src, bytes);
     parts.push_back(Part{&b, at, bytes});
     off = at + bytes;
   }
@@ -296,7 +307,7 @@ struct Stager {
     if (parts.empty()) return;
     const size_t first = parts.front().at, total = std::max<size_t>(off - first, 1);
     block.alloc(total, s);
-    SBR_HIP(hipMemcpyAsync(block.p, static_cast<char*>(c->stage) + first, off - first, hipMemcpyHostToDevice, s));
+    SBR_HIP(hipMemcpyAsync(block.p, static_cast<char*>(c->p) + first, off - first, hipMemcpyHostToDevice, s));
     for (const Part& q : parts) q.b->view(block.as<char>() + (q.at - first), q.bytes);
     parts.clear();
   }
@@ -332,6 +343,8 @@ __global__ void k_tri_gather(const uint32_t* __restrict__ order, const int32_t* 
 // (float)(hi - centre).  Non-finite values (inputs the host then rejects)
 // become 0 so that the tree build always sees finite boxes.
 constexpr int kPrepBlocks = 64;
+// worker threads (and streams) of a batched scene build
+constexpr int kSceneWorkers = 8;
 __global__ __launch_bounds__(256) void k_scene_bounds(const double* __restrict__ tri, int64_t nv,
                                                       double* __restrict__ part) {
   __shared__ double red[6][4];
@@ -421,12 +434,23 @@ __global__ void k_count_segments(const int32_t* __restrict__ seq, int64_t NR, in
   if ((threadIdx.x & 63) == 0 && c) atomicAdd(total, c);
 }
 
+// Mean edge angle of the class-I geodesic of frequency N: a function of N
+// alone (fixed-order FP64 sums), so one process-wide cache serves every
+// context and thread.
+std::mutex g_alpha_mu;
+std::vector<std::pair<int, double>> g_alpha;
 double alpha_for(sbr_context_s* c, int N) {
-  for (auto& pr : c->alpha_cache)
-    if (pr.first == N) return pr.second;
+  {
+    std::lock_guard<std::mutex> lk(g_alpha_mu);
+    for (auto& pr : g_alpha)
+      if (pr.first == N) return pr.second;
+  }
   double mean = 0;
   geodesic_edge_stats(N, &mean, nullptr, nullptr, c->stream);
-  c->alpha_cache.emplace_back(N, mean);
+  std::lock_guard<std::mutex> lk(g_alpha_mu);
+  for (auto& pr : g_alpha)
+    if (pr.first == N) return pr.second;
+  g_alpha.emplace_back(N, mean);
   return mean;
 }
 
@@ -464,8 +488,13 @@ sbr_context_s::~sbr_context_s() {
     buf_cache_flush(stream);
     (void)hipStreamSynchronize(stream);
   }
-  if (stage) (void)hipHostFree(stage);
-  if (ev_inputs) (void)hipEventDestroy(ev_inputs);
+  for (SceneWorker* w : workers) {
+    (void)hipStreamSynchronize(w->stream);
+    buf_cache_flush(w->stream);
+    (void)hipStreamSynchronize(w->stream);
+    (void)hipStreamDestroy(w->stream);
+    delete w;
+  }
   prof.clear();
   prof.destroy_events();
   if (g_prof == &prof) g_prof = nullptr;
@@ -541,6 +570,272 @@ sbr_status sbr_synchronize(sbr_context_t ctx) {
   });
 }
 
+// One scene built on stream s with staging area hs (the context's own, or a
+// batch worker's); returns the scene once its build has finished on s.
+static sbr_scene_s* scene_build_on(sbr_context_s* c, hipStream_t s, HostStage& hs, const double* tri_xyz, int64_t T,
+                                   const float* eps_r, const float* sigma, const float* rough, uint32_t flags) {
+  const bool dev_in = (flags & SBR_IN_DEVICE) != 0;
+  // Scenes clustered with PLOC keep every triangle in the tree; they are
+  // prepared on the device, so that the tree build starts at once and the
+  // host's face grouping overlaps it.  Larger scenes (Morton-ordered LBVH
+  // with a list of oversized triangles) are prepared on the host.
+  const bool gpu_prep = T > 0 && T <= c->tune.bvh_ploc_max;
+  // One pinned staging area serves the copies of device inputs (read
+  // before the first upload) and the uploads; its size is set here, before
+  // either is issued.
+  const size_t bt = (size_t)T * 72, bm = (size_t)T * 4, o1 = (bt + 255) & ~size_t(255);
+  const size_t o2 = o1 + ((bm + 255) & ~size_t(255)), o3 = o2 + ((bm + 255) & ~size_t(255));
+  const size_t need = std::max(o3 + bm, (size_t)T * (72 + 32 + 8 + 32 + 16 + 4 + 4 + 60 + 4) + 4 + 20 * 256);
+  hs.reserve(need);
+  if (dev_in && gpu_prep && !hs.ev) SBR_HIP(hipEventCreateWithFlags(&hs.ev, hipEventDisableTiming));
+  auto* sc = new sbr_scene_s();
+  sc->ctx = c;
+  retain(c);
+  try {
+    sc->T = T;
+    std::vector<double> tri;
+    std::vector<float> er, sg, rh;
+    Stager st(hs);
+    Buf dv32, dlo, dhi, order, dbvh_ids, dbig_ids, dpart, dbounds;
+    uint32_t* depth_dev = nullptr;
+    auto alloc_tree = [&] {
+      sc->nodes.alloc((size_t)std::max<int64_t>(sc->n_bvh - 1, 1) * 64, s);
+      sc->root_box.alloc(32, s);  // 6 floats of root box, then the depth word
+      sc->tri32.alloc((size_t)T * 48, s);
+      depth_dev = reinterpret_cast<uint32_t*>(sc->root_box.as<float>() + 6);
+    };
+    {
+      HostPhase hp("host:scene_inputs");
+      char* stg = static_cast<char*>(hs.p);
+      if (dev_in && T > 0) {
+        // device inputs: four copies into the staging area, then (device
+        // preparation) an event the host waits for, or one synchronisation
+        SBR_HIP(hipMemcpyAsync(stg, tri_xyz, bt, hipMemcpyDeviceToHost, s));
+        SBR_HIP(hipMemcpyAsync(stg + o1, eps_r, bm, hipMemcpyDeviceToHost, s));
+        SBR_HIP(hipMemcpyAsync(stg + o2, sigma, bm, hipMemcpyDeviceToHost, s));
+        SBR_HIP(hipMemcpyAsync(stg + o3, rough, bm, hipMemcpyDeviceToHost, s));
+        if (gpu_prep) SBR_HIP(hipEventRecord(hs.ev, s));
+        else SBR_HIP(hipStreamSynchronize(s));
+      } else if (T > 0) {
+        tri.assign(tri_xyz, tri_xyz + (size_t)T * 9);
+        er.assign(eps_r, eps_r + T), sg.assign(sigma, sigma + T), rh.assign(rough, rough + T);
+      }
+      if (gpu_prep) {
+        if (dev_in) upload(sc->tri64, tri_xyz, (size_t)T * 9, flags, s);
+        else st.put(sc->tri64, tri.data(), tri.size(), s);
+        sc->n_big = 0;
+        sc->n_bvh = T;
+        alloc_tree();
+        dv32.alloc((size_t)T * 36, s), dlo.alloc((size_t)T * 12, s), dhi.alloc((size_t)T * 12, s);
+        dbounds.alloc(32, s), dpart.alloc((size_t)kPrepBlocks * 48, s), order.alloc((size_t)T * 4, s);
+        const int nb = (int)std::min<int64_t>(kPrepBlocks, (3 * T + 255) / 256);
+        hipLaunchKernelGGL(k_scene_bounds, dim3(nb), dim3(256), 0, s, sc->tri64.as<double>(), 3 * T,
+                           dpart.as<double>());
+        SBR_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_scene_prep, dim3(nblk(T, 256)), dim3(256), 0, s, sc->tri64.as<double>(), T,
+                           dpart.as<double>(), nb, dv32.as<float>(), dlo.as<float>(), dhi.as<float>(),
+                           dbounds.as<float>());
+        SBR_LAUNCH_CHECK();
+        BvhOut bo{sc->nodes.as<float4>(), order.as<uint32_t>(), sc->root_box.as<float>(), nullptr, depth_dev};
+        bo.bounds_dev = dbounds.as<float>();
+        build_bvh(dlo.as<float>(), dhi.as<float>(), T, nullptr, nullptr, bo, s, false);
+        if (dev_in) SBR_HIP(hipEventSynchronize(hs.ev));
+      }
+      if (dev_in && T > 0) {
+        tri.assign(reinterpret_cast<const double*>(stg), reinterpret_cast<const double*>(stg) + (size_t)T * 9);
+        er.assign(reinterpret_cast<const float*>(stg + o1), reinterpret_cast<const float*>(stg + o1) + T);
+        sg.assign(reinterpret_cast<const float*>(stg + o2), reinterpret_cast<const float*>(stg + o2) + T);
+        rh.assign(reinterpret_cast<const float*>(stg + o3), reinterpret_cast<const float*>(stg + o3) + T);
+      }
+    }
+    SBR_CHECK(finite_all(tri.data(), tri.size()), SBR_E_INVALID_ARG, "triangle coordinates must be finite");
+    for (int64_t t = 0; t < T; ++t) {
+      SBR_CHECK(std::isfinite(er[t]) && er[t] >= 1.0f, SBR_E_INVALID_ARG, "eps_r[%lld] = %g (needs >= 1)",
+                (long long)t, er[t]);
+      SBR_CHECK(std::isfinite(sg[t]) && sg[t] >= 0.0f, SBR_E_INVALID_ARG, "sigma[%lld] = %g", (long long)t,
+                sg[t]);
+      SBR_CHECK(std::isfinite(rh[t]) && rh[t] >= 0.0f, SBR_E_INVALID_ARG, "rough[%lld] = %g", (long long)t,
+                rh[t]);
+    }
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t t = 0; t < T; ++t)
+      for (int v = 0; v < 3; ++v)
+        for (int k = 0; k < 3; ++k) {
+          lo[k] = std::min(lo[k], tri[9 * t + 3 * v + k]);
+          hi[k] = std::max(hi[k], tri[9 * t + 3 * v + k]);
+        }
+    if (T > 0) {
+      for (int k = 0; k < 3; ++k) sc->center[k] = 0.5 * (lo[k] + hi[k]);
+      sc->diag = std::sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
+                           (hi[2] - lo[2]) * (hi[2] - lo[2]));
+    }
+    if (T == 0) {
+      HostPhase hp("host:face_groups");
+      face_groups({}, er.data(), sg.data(), rh.data(), sc->diag, sc->h_group, sc->h_plane, sc->n_groups,
+                  sc->n_planes);
+      sc->gstart.alloc(4, s);
+      fill_u32(sc->gstart.as<uint32_t>(), 0, 1, s);
+      SBR_HIP(hipStreamSynchronize(s));
+      return sc;
+    }
+    if (!gpu_prep) {
+      // ---- host preparation, uploaded first so that the GPU builds the
+      // BVH while the host groups faces.
+      // Scenes built with the Morton-ordered LBVH (above the context's
+      // bvh_ploc_max triangles) keep oversized triangles (box diagonal above
+      // a quarter of the scene's, at most kMaxBig, largest first) out of the
+      // tree: there every ancestor of such a leaf gets a box as large as the
+      // scene (a city's ground plane inflates a whole root-to-leaf chain),
+      // so nearly every ray would descend those chains.  Every ray tests them
+      // directly instead, before the traversal.  PLOC clustering merges
+      // large boxes late, near the root, by itself, so smaller scenes keep
+      // every triangle in the tree.
+      constexpr int kMaxBig = 16;
+      std::vector<std::pair<double, int32_t>> cand;
+      for (int64_t t = 0; t < T; ++t) {
+        double d2 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+          const double a = tri[9 * t + k], b = tri[9 * t + 3 + k], cc = tri[9 * t + 6 + k];
+          const double e = std::max(a, std::max(b, cc)) - std::min(a, std::min(b, cc));
+          d2 += e * e;
+        }
+        if (d2 > 0.0625 * sc->diag * sc->diag) cand.push_back({d2, (int32_t)t});
+      }
+      std::sort(cand.begin(), cand.end(), [](const auto& x, const auto& y) {
+        return x.first > y.first || (x.first == y.first && x.second < y.second);
+      });
+      if (cand.size() > (size_t)kMaxBig) cand.resize(kMaxBig);
+      std::vector<int32_t> big_ids;
+      std::vector<char> is_big((size_t)T, 0);
+      for (const auto& cb : cand) big_ids.push_back(cb.second), is_big[cb.second] = 1;
+      std::sort(big_ids.begin(), big_ids.end());
+      std::vector<int32_t> bvh_ids;
+      for (int64_t t = 0; t < T; ++t)
+        if (!is_big[t]) bvh_ids.push_back((int32_t)t);
+      sc->n_big = (int)big_ids.size();
+      sc->n_bvh = (int64_t)bvh_ids.size();
+      // FP32 vertices centred on the scene box; boxes of the tree's
+      // triangles (rounded outward in the builder)
+      std::vector<float> v32((size_t)T * 9), blo((size_t)sc->n_bvh * 3), bhi((size_t)sc->n_bvh * 3);
+      float slo[3] = {1e30f, 1e30f, 1e30f}, shi[3] = {-1e30f, -1e30f, -1e30f};
+      for (int64_t t = 0; t < T; ++t)
+        for (int k = 0; k < 3; ++k)
+          for (int v = 0; v < 3; ++v) v32[9 * t + 3 * v + k] = (float)(tri[9 * t + 3 * v + k] - sc->center[k]);
+      for (int64_t j = 0; j < sc->n_bvh; ++j) {
+        const int64_t t = bvh_ids[j];
+        for (int k = 0; k < 3; ++k) {
+          float mn = 1e30f, mx = -1e30f;
+          for (int v = 0; v < 3; ++v)
+            mn = std::min(mn, v32[9 * t + 3 * v + k]), mx = std::max(mx, v32[9 * t + 3 * v + k]);
+          blo[3 * j + k] = mn, bhi[3 * j + k] = mx;
+          slo[k] = std::min(slo[k], mn), shi[k] = std::max(shi[k], mx);
+        }
+      }
+      {
+        HostPhase hp_up("host:scene_upload");
+        st.put(dv32, v32.data(), v32.size(), s);
+        st.put(dlo, blo.data(), blo.size(), s);
+        st.put(dhi, bhi.data(), bhi.size(), s);
+        st.put(dbvh_ids, bvh_ids.data(), bvh_ids.size(), s);
+        st.put(dbig_ids, big_ids.data(), big_ids.size(), s);
+      }
+      alloc_tree();
+      if (sc->n_bvh > 0) {
+        order.alloc((size_t)sc->n_bvh * 4, s);
+        build_bvh(dlo.as<float>(), dhi.as<float>(), sc->n_bvh, slo, shi,
+                  BvhOut{sc->nodes.as<float4>(), order.as<uint32_t>(), sc->root_box.as<float>(), nullptr, depth_dev},
+                  s, /*linear=*/true);
+      }
+    }
+    // ---- planes, face groups and group tables on the host (overlapping the build)
+    std::vector<Plane> pl((size_t)T);
+    for (int64_t t = 0; t < T; ++t) {
+      const d3 a = ld3(&tri[9 * t]), b = ld3(&tri[9 * t + 3]), cc = ld3(&tri[9 * t + 6]);
+      const d3 nn = cross(b - a, cc - a);
+      const double area2 = norm(nn);
+      SBR_CHECK(0.5 * area2 > 1e-12 * sc->diag * sc->diag, SBR_E_INVALID_ARG,
+                "triangle %lld is degenerate (area %g)", (long long)t, 0.5 * area2);
+      const d3 n = nn * (1.0 / area2);
+      pl[t] = Plane{{n.x, n.y, n.z}, dot(n, a)};
+    }
+    {
+      HostPhase hp("host:face_groups");
+      face_groups(pl, er.data(), sg.data(), rh.data(), sc->diag, sc->h_group, sc->h_plane, sc->n_groups,
+                  sc->n_planes);
+    }
+    // per-triangle FP64 planes, per-group plane/material/members
+    std::vector<double4> tpl((size_t)T);
+    for (int64_t t = 0; t < T; ++t) tpl[t] = make_double4(pl[t].n[0], pl[t].n[1], pl[t].n[2], pl[t].c);
+    const int G = sc->n_groups;
+    std::vector<int32_t> gfirst(G, -1), gstart(G + 1, 0), gtri((size_t)T), fill(G, 0);
+    for (int64_t t = 0; t < T; ++t) {
+      const int g = sc->h_group[t];
+      if (gfirst[g] < 0) gfirst[g] = (int)t;
+      gstart[g + 1]++;
+    }
+    for (int g = 0; g < G; ++g) gstart[g + 1] += gstart[g];
+    for (int64_t t = 0; t < T; ++t) {
+      const int g = sc->h_group[t];
+      gtri[gstart[g] + fill[g]++] = (int)t;
+    }
+    std::vector<double4> gpl(G);
+    std::vector<float4> gmt(G);
+    for (int g = 0; g < G; ++g) {
+      gpl[g] = tpl[gfirst[g]];
+      gmt[g] = make_float4(er[gfirst[g]], sg[gfirst[g]], rh[gfirst[g]], 0.0f);
+    }
+    {
+      HostPhase hp_up("host:scene_upload");
+      if (!gpu_prep) st.put(sc->tri64, tri.data(), tri.size(), s);
+      st.add(sc->tplane, tpl.data(), tpl.size());
+      st.add(sc->tgroup, sc->h_group.data(), sc->h_group.size());
+      st.add(sc->tplaneid, sc->h_plane.data(), sc->h_plane.size());
+      st.add(sc->gplane, gpl.data(), gpl.size());
+      st.add(sc->gmat, gmt.data(), gmt.size());
+      st.add(sc->gstart, gstart.data(), gstart.size());
+      st.add(sc->gtri, gtri.data(), gtri.size());
+      st.flush(sc->tables, s);
+    }
+    if (sc->n_bvh > 0) {
+      // leaves in tree order; device-prepared scenes hold every triangle in the tree
+      hipLaunchKernelGGL(k_tri_gather, dim3(nblk(sc->n_bvh, 256)), dim3(256), 0, s, order.as<uint32_t>(),
+                         gpu_prep ? (const int32_t*)nullptr : dbvh_ids.as<int32_t>(), sc->n_bvh, (int64_t)0,
+                         dv32.as<float>(), sc->tplaneid.as<int32_t>(), sc->tgroup.as<int32_t>(),
+                         sc->tri32.as<float4>());
+      SBR_LAUNCH_CHECK();
+    }
+    if (sc->n_big > 0) {
+      hipLaunchKernelGGL(k_tri_gather, dim3(1), dim3(64), 0, s, (const uint32_t*)nullptr, dbig_ids.as<int32_t>(),
+                         (int64_t)sc->n_big, sc->n_bvh, dv32.as<float>(), sc->tplaneid.as<int32_t>(),
+                         sc->tgroup.as<int32_t>(), sc->tri32.as<float4>());
+      SBR_LAUNCH_CHECK();
+    }
+    // one synchronisation: root box and depth of the tree; it also frees the staging area
+    sc->bvh_depth = 1;
+    if (sc->n_bvh > 0) {
+      float rb[7];
+      SBR_HIP(hipMemcpyAsync(rb, sc->root_box.p, sizeof rb, hipMemcpyDeviceToHost, s));
+      SBR_HIP(hipStreamSynchronize(s));
+      for (int k = 0; k < 6; ++k) sc->root_host[k] = rb[k];
+      uint32_t depth;
+      std::memcpy(&depth, &rb[6], 4);
+      SBR_CHECK(depth != 0xffffffffu, SBR_E_DEVICE, "BVH clustering did not reach a single root");
+      sc->bvh_depth = (int)depth;
+      SBR_CHECK(sc->bvh_depth <= 64, SBR_E_UNSUPPORTED, "BVH depth %d exceeds the traversal stack",
+                sc->bvh_depth);
+    } else {
+      SBR_HIP(hipStreamSynchronize(s));
+    }
+  } catch (...) {
+    // copies from the staging area and the tree build may still be in
+    // flight: let them finish before the scene and the staging area go
+    (void)hipStreamSynchronize(s);
+    release(sc);
+    throw;
+  }
+  return sc;
+}
+
 sbr_status sbr_scene_build(sbr_context_t ctx, const double* tri_xyz, int64_t T, const float* eps_r,
                            const float* sigma, const float* rough, uint32_t flags, sbr_scene_t* out) {
   return guard([&] {
@@ -549,275 +844,82 @@ sbr_status sbr_scene_build(sbr_context_t ctx, const double* tri_xyz, int64_t T, 
     SBR_CHECK(T >= 0 && T < (int64_t(1) << 30), SBR_E_INVALID_ARG, "triangle count %lld", (long long)T);
     if (T > 0) SBR_CHECK(tri_xyz && eps_r && sigma && rough, SBR_E_INVALID_ARG, "input array is NULL");
     set_device(c);
-    hipStream_t s = c->stream;
     HostPhase hp_all("host:scene_build");
-    const bool dev_in = (flags & SBR_IN_DEVICE) != 0;
-    // Scenes clustered with PLOC keep every triangle in the tree; they are
-    // prepared on the device, so that the tree build starts at once and the
-    // host's face grouping overlaps it.  Larger scenes (Morton-ordered LBVH
-    // with a list of oversized triangles) are prepared on the host.
-    const bool gpu_prep = T > 0 && T <= c->tune.bvh_ploc_max;
-    // One pinned staging area serves the copies of device inputs (read
-    // before the first upload) and the uploads; its size is set here, before
-    // either is issued.
-    const size_t bt = (size_t)T * 72, bm = (size_t)T * 4, o1 = (bt + 255) & ~size_t(255);
-    const size_t o2 = o1 + ((bm + 255) & ~size_t(255)), o3 = o2 + ((bm + 255) & ~size_t(255));
-    const size_t need = std::max(o3 + bm, (size_t)T * (72 + 32 + 8 + 32 + 16 + 4 + 4 + 60 + 4) + 4 + 20 * 256);
-    if (c->stage_bytes < need) {
-      if (c->stage) (void)hipHostFree(c->stage);
-      c->stage = nullptr;
-      c->stage_bytes = 0;
-      SBR_HIP(hipHostMalloc(&c->stage, need, hipHostMallocDefault));
-      c->stage_bytes = need;
+    *out = scene_build_on(c, c->stream, c->stage, tri_xyz, T, eps_r, sigma, rough, flags);
+  });
+}
+
+sbr_status sbr_scene_build_batch(sbr_context_t ctx, int32_t n, const double* const* tri_xyz, const int64_t* T,
+                                 const float* const* eps_r, const float* const* sigma, const float* const* rough,
+                                 uint32_t flags, sbr_scene_t* out) {
+  return guard([&] {
+    auto* c = check_handle<sbr_context_s>(ctx, kContext, "context");
+    SBR_CHECK(n >= 1 && tri_xyz && T && eps_r && sigma && rough && out, SBR_E_INVALID_ARG, "batch arguments");
+    for (int i = 0; i < n; ++i) {
+      SBR_CHECK(T[i] >= 0 && T[i] < (int64_t(1) << 30), SBR_E_INVALID_ARG, "triangle count %lld of scene %d",
+                (long long)T[i], i);
+      if (T[i] > 0)
+        SBR_CHECK(tri_xyz[i] && eps_r[i] && sigma[i] && rough[i], SBR_E_INVALID_ARG, "input array of scene %d is NULL",
+                  i);
     }
-    if (dev_in && gpu_prep && !c->ev_inputs) SBR_HIP(hipEventCreateWithFlags(&c->ev_inputs, hipEventDisableTiming));
-    auto* sc = new sbr_scene_s();
-    sc->ctx = c;
-    retain(c);
-    try {
-      sc->T = T;
-      std::vector<double> tri;
-      std::vector<float> er, sg, rh;
-      Stager st(c);
-      Buf dv32, dlo, dhi, order, dbvh_ids, dbig_ids, dpart, dbounds;
-      uint32_t* depth_dev = nullptr;
-      auto alloc_tree = [&] {
-        sc->nodes.alloc((size_t)std::max<int64_t>(sc->n_bvh - 1, 1) * 64, s);
-        sc->root_box.alloc(32, s);  // 6 floats of root box, then the depth word
-        sc->tri32.alloc((size_t)T * 48, s);
-        depth_dev = reinterpret_cast<uint32_t*>(sc->root_box.as<float>() + 6);
-      };
-      {
-        HostPhase hp("host:scene_inputs");
-        char* stg = static_cast<char*>(c->stage);
-        if (dev_in && T > 0) {
-          // device inputs: four copies into the staging area, then (device
-          // preparation) an event the host waits for, or one synchronisation
-          SBR_HIP(hipMemcpyAsync(stg, tri_xyz, bt, hipMemcpyDeviceToHost, s));
-          SBR_HIP(hipMemcpyAsync(stg + o1, eps_r, bm, hipMemcpyDeviceToHost, s));
-          SBR_HIP(hipMemcpyAsync(stg + o2, sigma, bm, hipMemcpyDeviceToHost, s));
-          SBR_HIP(hipMemcpyAsync(stg + o3, rough, bm, hipMemcpyDeviceToHost, s));
-          if (gpu_prep) SBR_HIP(hipEventRecord(c->ev_inputs, s));
-          else SBR_HIP(hipStreamSynchronize(s));
-        } else if (T > 0) {
-          tri.assign(tri_xyz, tri_xyz + (size_t)T * 9);
-          er.assign(eps_r, eps_r + T), sg.assign(sigma, sigma + T), rh.assign(rough, rough + T);
-        }
-        if (gpu_prep) {
-          if (dev_in) upload(sc->tri64, tri_xyz, (size_t)T * 9, flags, s);
-          else st.put(sc->tri64, tri.data(), tri.size(), s);
-          sc->n_big = 0;
-          sc->n_bvh = T;
-          alloc_tree();
-          dv32.alloc((size_t)T * 36, s), dlo.alloc((size_t)T * 12, s), dhi.alloc((size_t)T * 12, s);
-          dbounds.alloc(32, s), dpart.alloc((size_t)kPrepBlocks * 48, s), order.alloc((size_t)T * 4, s);
-          const int nb = (int)std::min<int64_t>(kPrepBlocks, (3 * T + 255) / 256);
-          hipLaunchKernelGGL(k_scene_bounds, dim3(nb), dim3(256), 0, s, sc->tri64.as<double>(), 3 * T,
-                             dpart.as<double>());
-          SBR_LAUNCH_CHECK();
-          hipLaunchKernelGGL(k_scene_prep, dim3(nblk(T, 256)), dim3(256), 0, s, sc->tri64.as<double>(), T,
-                             dpart.as<double>(), nb, dv32.as<float>(), dlo.as<float>(), dhi.as<float>(),
-                             dbounds.as<float>());
-          SBR_LAUNCH_CHECK();
-          BvhOut bo{sc->nodes.as<float4>(), order.as<uint32_t>(), sc->root_box.as<float>(), nullptr, depth_dev};
-          bo.bounds_dev = dbounds.as<float>();
-          build_bvh(dlo.as<float>(), dhi.as<float>(), T, nullptr, nullptr, bo, s, false);
-          if (dev_in) SBR_HIP(hipEventSynchronize(c->ev_inputs));
-        }
-        if (dev_in && T > 0) {
-          tri.assign(reinterpret_cast<const double*>(stg), reinterpret_cast<const double*>(stg) + (size_t)T * 9);
-          er.assign(reinterpret_cast<const float*>(stg + o1), reinterpret_cast<const float*>(stg + o1) + T);
-          sg.assign(reinterpret_cast<const float*>(stg + o2), reinterpret_cast<const float*>(stg + o2) + T);
-          rh.assign(reinterpret_cast<const float*>(stg + o3), reinterpret_cast<const float*>(stg + o3) + T);
-        }
+    set_device(c);
+    HostPhase hp_all("host:scene_build");
+    // device inputs may have been written by earlier work on the context's
+    // stream; the workers' streams read them only after it
+    if (flags & SBR_IN_DEVICE) SBR_HIP(hipStreamSynchronize(c->stream));
+    const int nw = std::min(n, kSceneWorkers);
+    while ((int)c->workers.size() < nw) {
+      auto* w = new SceneWorker();
+      const hipError_t e = hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking);
+      if (e != hipSuccess) {
+        delete w;
+        SBR_HIP(e);
       }
-      SBR_CHECK(finite_all(tri.data(), tri.size()), SBR_E_INVALID_ARG, "triangle coordinates must be finite");
-      for (int64_t t = 0; t < T; ++t) {
-        SBR_CHECK(std::isfinite(er[t]) && er[t] >= 1.0f, SBR_E_INVALID_ARG, "eps_r[%lld] = %g (needs >= 1)",
-                  (long long)t, er[t]);
-        SBR_CHECK(std::isfinite(sg[t]) && sg[t] >= 0.0f, SBR_E_INVALID_ARG, "sigma[%lld] = %g", (long long)t,
-                  sg[t]);
-        SBR_CHECK(std::isfinite(rh[t]) && rh[t] >= 0.0f, SBR_E_INVALID_ARG, "rough[%lld] = %g", (long long)t,
-                  rh[t]);
-      }
-      double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-      for (int64_t t = 0; t < T; ++t)
-        for (int v = 0; v < 3; ++v)
-          for (int k = 0; k < 3; ++k) {
-            lo[k] = std::min(lo[k], tri[9 * t + 3 * v + k]);
-            hi[k] = std::max(hi[k], tri[9 * t + 3 * v + k]);
-          }
-      if (T > 0) {
-        for (int k = 0; k < 3; ++k) sc->center[k] = 0.5 * (lo[k] + hi[k]);
-        sc->diag = std::sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
-                             (hi[2] - lo[2]) * (hi[2] - lo[2]));
-      }
-      if (T == 0) {
-        HostPhase hp("host:face_groups");
-        face_groups({}, er.data(), sg.data(), rh.data(), sc->diag, sc->h_group, sc->h_plane, sc->n_groups,
-                    sc->n_planes);
-        sc->gstart.alloc(4, s);
-        fill_u32(sc->gstart.as<uint32_t>(), 0, 1, s);
-        SBR_HIP(hipStreamSynchronize(s));
-        *out = sc;
-        return;
-      }
-      if (!gpu_prep) {
-        // ---- host preparation, uploaded first so that the GPU builds the
-        // BVH while the host groups faces.
-        // Scenes built with the Morton-ordered LBVH (above the context's
-        // bvh_ploc_max triangles) keep oversized triangles (box diagonal above
-        // a quarter of the scene's, at most kMaxBig, largest first) out of the
-        // tree: there every ancestor of such a leaf gets a box as large as the
-        // scene (a city's ground plane inflates a whole root-to-leaf chain),
-        // so nearly every ray would descend those chains.  Every ray tests them
-        // directly instead, before the traversal.  PLOC clustering merges
-        // large boxes late, near the root, by itself, so smaller scenes keep
-        // every triangle in the tree.
-        constexpr int kMaxBig = 16;
-        std::vector<std::pair<double, int32_t>> cand;
-        for (int64_t t = 0; t < T; ++t) {
-          double d2 = 0.0;
-          for (int k = 0; k < 3; ++k) {
-            const double a = tri[9 * t + k], b = tri[9 * t + 3 + k], cc = tri[9 * t + 6 + k];
-            const double e = std::max(a, std::max(b, cc)) - std::min(a, std::min(b, cc));
-            d2 += e * e;
-          }
-          if (d2 > 0.0625 * sc->diag * sc->diag) cand.push_back({d2, (int32_t)t});
-        }
-        std::sort(cand.begin(), cand.end(), [](const auto& x, const auto& y) {
-          return x.first > y.first || (x.first == y.first && x.second < y.second);
-        });
-        if (cand.size() > (size_t)kMaxBig) cand.resize(kMaxBig);
-        std::vector<int32_t> big_ids;
-        std::vector<char> is_big((size_t)T, 0);
-        for (const auto& cb : cand) big_ids.push_back(cb.second), is_big[cb.second] = 1;
-        std::sort(big_ids.begin(), big_ids.end());
-        std::vector<int32_t> bvh_ids;
-        for (int64_t t = 0; t < T; ++t)
-          if (!is_big[t]) bvh_ids.push_back((int32_t)t);
-        sc->n_big = (int)big_ids.size();
-        sc->n_bvh = (int64_t)bvh_ids.size();
-        // FP32 vertices centred on the scene box; boxes of the tree's
-        // triangles (rounded outward in the builder)
-        std::vector<float> v32((size_t)T * 9), blo((size_t)sc->n_bvh * 3), bhi((size_t)sc->n_bvh * 3);
-        float slo[3] = {1e30f, 1e30f, 1e30f}, shi[3] = {-1e30f, -1e30f, -1e30f};
-        for (int64_t t = 0; t < T; ++t)
-          for (int k = 0; k < 3; ++k)
-            for (int v = 0; v < 3; ++v) v32[9 * t + 3 * v + k] = (float)(tri[9 * t + 3 * v + k] - sc->center[k]);
-        for (int64_t j = 0; j < sc->n_bvh; ++j) {
-          const int64_t t = bvh_ids[j];
-          for (int k = 0; k < 3; ++k) {
-            float mn = 1e30f, mx = -1e30f;
-            for (int v = 0; v < 3; ++v)
-              mn = std::min(mn, v32[9 * t + 3 * v + k]), mx = std::max(mx, v32[9 * t + 3 * v + k]);
-            blo[3 * j + k] = mn, bhi[3 * j + k] = mx;
-            slo[k] = std::min(slo[k], mn), shi[k] = std::max(shi[k], mx);
-          }
-        }
-        {
-          HostPhase hp_up("host:scene_upload");
-          st.put(dv32, v32.data(), v32.size(), s);
-          st.put(dlo, blo.data(), blo.size(), s);
-          st.put(dhi, bhi.data(), bhi.size(), s);
-          st.put(dbvh_ids, bvh_ids.data(), bvh_ids.size(), s);
-          st.put(dbig_ids, big_ids.data(), big_ids.size(), s);
-        }
-        alloc_tree();
-        if (sc->n_bvh > 0) {
-          order.alloc((size_t)sc->n_bvh * 4, s);
-          build_bvh(dlo.as<float>(), dhi.as<float>(), sc->n_bvh, slo, shi,
-                    BvhOut{sc->nodes.as<float4>(), order.as<uint32_t>(), sc->root_box.as<float>(), nullptr, depth_dev},
-                    s, /*linear=*/true);
-        }
-      }
-      // ---- planes, face groups and group tables on the host (overlapping the build)
-      std::vector<Plane> pl((size_t)T);
-      for (int64_t t = 0; t < T; ++t) {
-        const d3 a = ld3(&tri[9 * t]), b = ld3(&tri[9 * t + 3]), cc = ld3(&tri[9 * t + 6]);
-        const d3 nn = cross(b - a, cc - a);
-        const double area2 = norm(nn);
-        SBR_CHECK(0.5 * area2 > 1e-12 * sc->diag * sc->diag, SBR_E_INVALID_ARG,
-                  "triangle %lld is degenerate (area %g)", (long long)t, 0.5 * area2);
-        const d3 n = nn * (1.0 / area2);
-        pl[t] = Plane{{n.x, n.y, n.z}, dot(n, a)};
-      }
-      {
-        HostPhase hp("host:face_groups");
-        face_groups(pl, er.data(), sg.data(), rh.data(), sc->diag, sc->h_group, sc->h_plane, sc->n_groups,
-                    sc->n_planes);
-      }
-      // per-triangle FP64 planes, per-group plane/material/members
-      std::vector<double4> tpl((size_t)T);
-      for (int64_t t = 0; t < T; ++t) tpl[t] = make_double4(pl[t].n[0], pl[t].n[1], pl[t].n[2], pl[t].c);
-      const int G = sc->n_groups;
-      std::vector<int32_t> gfirst(G, -1), gstart(G + 1, 0), gtri((size_t)T), fill(G, 0);
-      for (int64_t t = 0; t < T; ++t) {
-        const int g = sc->h_group[t];
-        if (gfirst[g] < 0) gfirst[g] = (int)t;
-        gstart[g + 1]++;
-      }
-      for (int g = 0; g < G; ++g) gstart[g + 1] += gstart[g];
-      for (int64_t t = 0; t < T; ++t) {
-        const int g = sc->h_group[t];
-        gtri[gstart[g] + fill[g]++] = (int)t;
-      }
-      std::vector<double4> gpl(G);
-      std::vector<float4> gmt(G);
-      for (int g = 0; g < G; ++g) {
-        gpl[g] = tpl[gfirst[g]];
-        gmt[g] = make_float4(er[gfirst[g]], sg[gfirst[g]], rh[gfirst[g]], 0.0f);
-      }
-      {
-        HostPhase hp_up("host:scene_upload");
-        if (!gpu_prep) st.put(sc->tri64, tri.data(), tri.size(), s);
-        st.add(sc->tplane, tpl.data(), tpl.size());
-        st.add(sc->tgroup, sc->h_group.data(), sc->h_group.size());
-        st.add(sc->tplaneid, sc->h_plane.data(), sc->h_plane.size());
-        st.add(sc->gplane, gpl.data(), gpl.size());
-        st.add(sc->gmat, gmt.data(), gmt.size());
-        st.add(sc->gstart, gstart.data(), gstart.size());
-        st.add(sc->gtri, gtri.data(), gtri.size());
-        st.flush(sc->tables, s);
-      }
-      if (sc->n_bvh > 0) {
-        // leaves in tree order; device-prepared scenes hold every triangle in the tree
-        hipLaunchKernelGGL(k_tri_gather, dim3(nblk(sc->n_bvh, 256)), dim3(256), 0, s, order.as<uint32_t>(),
-                           gpu_prep ? (const int32_t*)nullptr : dbvh_ids.as<int32_t>(), sc->n_bvh, (int64_t)0,
-                           dv32.as<float>(), sc->tplaneid.as<int32_t>(), sc->tgroup.as<int32_t>(),
-                           sc->tri32.as<float4>());
-        SBR_LAUNCH_CHECK();
-      }
-      if (sc->n_big > 0) {
-        hipLaunchKernelGGL(k_tri_gather, dim3(1), dim3(64), 0, s, (const uint32_t*)nullptr, dbig_ids.as<int32_t>(),
-                           (int64_t)sc->n_big, sc->n_bvh, dv32.as<float>(), sc->tplaneid.as<int32_t>(),
-                           sc->tgroup.as<int32_t>(), sc->tri32.as<float4>());
-        SBR_LAUNCH_CHECK();
-      }
-      // one synchronisation: root box and depth of the tree; it also frees the staging area
-      sc->bvh_depth = 1;
-      if (sc->n_bvh > 0) {
-        float rb[7];
-        SBR_HIP(hipMemcpyAsync(rb, sc->root_box.p, sizeof rb, hipMemcpyDeviceToHost, s));
-        SBR_HIP(hipStreamSynchronize(s));
-        for (int k = 0; k < 6; ++k) sc->root_host[k] = rb[k];
-        uint32_t depth;
-        std::memcpy(&depth, &rb[6], 4);
-        SBR_CHECK(depth != 0xffffffffu, SBR_E_DEVICE, "BVH clustering did not reach a single root");
-        sc->bvh_depth = (int)depth;
-        SBR_CHECK(sc->bvh_depth <= 64, SBR_E_UNSUPPORTED, "BVH depth %d exceeds the traversal stack",
-                  sc->bvh_depth);
-      } else {
-        SBR_HIP(hipStreamSynchronize(s));
-      }
-    } catch (...) {
-      // copies from the staging area and the tree build may still be in
-      // flight: let them finish before the scene and the staging area go
-      (void)hipStreamSynchronize(s);
-      release(sc);
-      throw;
+      c->workers.push_back(w);
     }
-    *out = sc;
+    // Workers take scenes from a shared counter, largest first (the build
+    // time grows with the triangle count, so the big scenes start early and
+    // the small ones fill in); each builds on its own stream and staging
+    // area.  Profiling stays with the calling thread (the workers record no
+    // events).  A failure stops the others after their current scene; its
+    // message names the scene.
+    std::vector<int> by_size((size_t)n);
+    for (int i = 0; i < n; ++i) by_size[i] = i;
+    std::stable_sort(by_size.begin(), by_size.end(), [&](int a, int b) { return T[a] > T[b]; });
+    std::vector<sbr_scene_s*> res((size_t)n, nullptr);
+    std::atomic<int> next{0};
+    std::atomic<bool> failed{false};
+    std::mutex err_mu;
+    sbr_status err_st = SBR_OK;
+    std::string err_text;
+    auto work = [&](int w) {
+      int i = -1;
+      try {
+        SBR_HIP(hipSetDevice(c->device));
+        SceneWorker& wk = *c->workers[w];
+        for (int k; !failed.load() && (k = next.fetch_add(1)) < n;) {
+          i = by_size[k];
+          res[i] = scene_build_on(c, wk.stream, wk.stage, tri_xyz[i], T[i], eps_r[i], sigma[i], rough[i], flags);
+          res[i]->rehome(c->stream);
+        }
+      } catch (const Error& e) {
+        std::lock_guard<std::mutex> lk(err_mu);
+        if (!failed.exchange(true)) err_st = e.st, err_text = "scene " + std::to_string(i) + ": " + g_err;
+      } catch (...) {
+        std::lock_guard<std::mutex> lk(err_mu);
+        if (!failed.exchange(true)) err_st = SBR_E_DEVICE, err_text = "unexpected internal error in a scene build";
+      }
+    };
+    std::vector<std::thread> th;
+    for (int w = 0; w < nw; ++w) th.emplace_back(work, w);
+    for (auto& t : th) t.join();
+    if (failed.load()) {
+      for (sbr_scene_s* sc : res)
+        if (sc) release(sc);
+      set_error("%s", err_text.c_str());
+      throw Error{err_st};
+    }
+    for (int i = 0; i < n; ++i) out[i] = res[i];
   });
 }
 
@@ -929,18 +1031,12 @@ sbr_status sbr_trace_batch(sbr_context_t ctx, int32_t n, const sbr_scene_t* scen
         tr->seq.alloc((size_t)(tr->K + 1) * tr->NR * 4, s);
         tr->counters.alloc(4, s);
       }
-      Stager st(c);
       {
         size_t need = 0;
         for (auto* tr : trs) need += tr->h_tx.size() * 8 + 256;
-        if (c->stage_bytes < need) {
-          if (c->stage) (void)hipHostFree(c->stage);
-          c->stage = nullptr;
-          c->stage_bytes = 0;
-          SBR_HIP(hipHostMalloc(&c->stage, need, hipHostMallocDefault));
-          c->stage_bytes = need;
-        }
+        c->stage.reserve(need);
       }
+      Stager st(c->stage);
       for (auto* tr : trs) st.put(tr->tx, tr->h_tx.data(), tr->h_tx.size(), s);
       int Kmax = 0;
       for (auto* tr : trs) Kmax = std::max(Kmax, tr->K);

@@ -158,6 +158,26 @@ struct TraceGraph {
 
 }  // namespace sbr
 
+namespace sbr {
+// Pinned host memory for uploads and for copies of device inputs, with an
+// event that marks the end of a scene build's input copies.
+struct HostStage {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipEvent_t ev = nullptr;
+  void reserve(size_t need);  // grows only; never while copies from it are in flight
+  HostStage() = default;
+  HostStage(const HostStage&) = delete;
+  HostStage& operator=(const HostStage&) = delete;
+  ~HostStage();
+};
+// a stream and staging area of the batched scene build (one per worker thread)
+struct SceneWorker {
+  hipStream_t stream = nullptr;
+  HostStage stage;
+};
+}  // namespace sbr
+
 struct sbr_context_s : sbr::Handle {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -166,12 +186,9 @@ struct sbr_context_s : sbr::Handle {
   sbr::Tuning tune;
   sbr::Prof prof;
   bool count_work = false;
-  void* stage = nullptr;  // pinned host staging for uploads
-  size_t stage_bytes = 0;
-  hipEvent_t ev_inputs = nullptr;  // marks the end of a scene's input copies
+  sbr::HostStage stage;  // pinned host staging for this context's stream
+  std::vector<sbr::SceneWorker*> workers;  // batched scene builds (created on first use)
   std::vector<sbr::TraceGraph*> graphs;  // cached bounce-loop graphs
-  // cached geodesic edge statistics per N
-  std::vector<std::pair<int, double>> alpha_cache;
   // grow-only device scratch reused by successive calls on this context's
   // stream (the two ray buffers of a trace); large per-call allocations from
   // the stream-ordered pool can stall while the pool grows
@@ -205,6 +222,13 @@ struct sbr_scene_s : sbr::Handle {
   sbr::Buf gstart;   // int[G+1]
   sbr::Buf gtri;     // int[T]
   sbr::Buf tables;   // one block holding tplane .. gtri (those are views into it)
+  // hand every buffer to stream s (built on a worker stream that has finished:
+  // releases then follow the order of the stream that uses the scene)
+  void rehome(hipStream_t s) {
+    for (sbr::Buf* b : {&nodes, &root_box, &tri32, &tri64, &tplane, &tgroup, &tplaneid, &gplane, &gmat, &gstart,
+                        &gtri, &tables})
+      if (b->p) b->stream = s;
+  }
   sbr_scene_s() : Handle(sbr::kScene) {}
   ~sbr_scene_s() override;
 };

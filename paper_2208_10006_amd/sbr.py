@@ -57,6 +57,7 @@ def _load():
         "sbr_context_create": [C.c_int, P, P],
         "sbr_synchronize": [P],
         "sbr_scene_build": [P, P, I64, P, P, P, U32, P],
+        "sbr_scene_build_batch": [P, I32, P, P, P, P, P, U32, P],
         "sbr_scene_info": [P, P, P, P],
         "sbr_scene_groups": [P, P, P],
         "sbr_trace": [P, P, P, I32, I32, I32, U32, P],
@@ -192,6 +193,20 @@ def sbr_scene_build(ctx: Context, tri, eps_r, sigma, rough) -> Scene:
     h = C.c_void_p()
     _call("sbr_scene_build", ctx.h, a[0].ptr, T, a[1].ptr, a[2].ptr, a[3].ptr, _flags(a, SBR_IN_DEVICE), C.byref(h))
     return Scene(h, (ctx,))
+
+
+def sbr_scene_build_batch(ctx: Context, tris, eps_rs, sigmas, roughs):
+    """Scenes built concurrently (worker threads and streams); returns one Scene per input."""
+    n = len(tris)
+    arrs = [[_Arr(t, np.float64, F64), _Arr(e, np.float32, F32), _Arr(g, np.float32, F32), _Arr(r, np.float32, F32)]
+            for t, e, g, r in zip(tris, eps_rs, sigmas, roughs)]
+    flags = _flags([a for row in arrs for a in row], SBR_IN_DEVICE)
+    T = np.array([(row[0].ref.numel() if _is_torch(row[0].ref) else row[0].ref.size) // 9 for row in arrs], np.int64)
+    ptrs = [(C.c_void_p * n)(*[row[k].ptr for row in arrs]) for k in range(4)]
+    out = (C.c_void_p * n)()
+    _call("sbr_scene_build_batch", ctx.h, n, ptrs[0], T.ctypes.data_as(C.c_void_p), ptrs[1], ptrs[2], ptrs[3], flags,
+          out)
+    return [Scene(C.c_void_p(out[i]), (ctx,)) for i in range(n)]
 
 
 def sbr_scene_info(scene: Scene):

@@ -359,6 +359,78 @@ def test_batched_trace_matches_individual(S, ctx):
         assert np.array_equal(Hb, Hi)
 
 
+@pytest.mark.parametrize("device", [False, True])
+def test_scene_build_batch_matches_single(S, ctx, device):
+    """Scenes built concurrently by worker threads on their own streams equal
+    the ones built one by one: groups, planes, tree depth and the hit chains
+    of a trace (bit for bit)."""
+    banner("batched scene build", "device inputs" if device else "host inputs")
+    import torch
+    ws = [W.tiny_room(N=24), W.random_box_scene(31, n_boxes=12, n_rx=3, N=16, K=4), W.batched_uneven(4005),
+          W.free_space(N=5), W.urban_canyon(N=20, K=3, n_rx=10, nf=4), W.random_box_scene(32, n_boxes=3, N=9, K=2)]
+    dev = torch.device("cuda", 0)
+    conv = (lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)) if device else \
+        (lambda a, dt: a)
+    tris = [conv(w.tri, torch.float64) for w in ws]
+    mats = [[conv(m, torch.float32) for m in (w.eps_r, w.sigma, w.rough)] for w in ws]
+    for rep in range(2):  # the second call reuses the worker streams and staging areas
+        batch = S.sbr_scene_build_batch(ctx, tris, [m[0] for m in mats], [m[1] for m in mats], [m[2] for m in mats])
+        assert len(batch) == len(ws)
+        for w, sb, t, m in zip(ws, batch, tris, mats):
+            ss = S.sbr_scene_build(ctx, t, m[0], m[1], m[2])
+            assert S.sbr_scene_info(sb) == S.sbr_scene_info(ss), w.name
+            gb, pb = S.sbr_scene_groups(sb, w.T)
+            gs, ps = S.sbr_scene_groups(ss, w.T)
+            assert np.array_equal(gb, gs) and np.array_equal(pb, ps), w.name
+            tb = S.sbr_trace(ctx, sb, w.tx, w.geodesic_N, w.max_bounces)
+            ts = S.sbr_trace(ctx, ss, w.tx, w.geodesic_N, w.max_bounces)
+            assert np.array_equal(S.sbr_trace_hits(tb), S.sbr_trace_hits(ts)), w.name
+        del batch
+
+
+def test_scene_build_batch_error_names_scene(S, ctx):
+    """An invalid scene fails the whole batch, and the message names it."""
+    banner("batched scene build with an invalid scene")
+    ws = [W.tiny_room(N=8), W.random_box_scene(33, n_boxes=4, N=8, K=2), W.tiny_room(N=8)]
+    tris = [w.tri.copy() for w in ws]
+    tris[1][3, 1, 2] = np.nan
+    with pytest.raises(S.SbrError, match="scene 1"):
+        S.sbr_scene_build_batch(ctx, tris, [w.eps_r for w in ws], [w.sigma for w in ws], [w.rough for w in ws])
+    # the context still works afterwards
+    ok = S.sbr_scene_build_batch(ctx, [w.tri for w in ws], [w.eps_r for w in ws], [w.sigma for w in ws],
+                                 [w.rough for w in ws])
+    assert len(ok) == 3
+
+
+def test_receive_on_other_contexts_from_threads(S, ctx):
+    """Receives, channels and statistics of batched traces run on a pool of
+    contexts from several host threads give the results of the same calls
+    on the tracing context, bit for bit."""
+    banner("receives on worker contexts from threads")
+    import concurrent.futures as cf
+    ws = [W.random_box_scene(41 + i, n_boxes=6 + i, n_rx=3, N=12 + i, K=3) for i in range(6)]
+    scenes = S.sbr_scene_build_batch(ctx, [w.tri for w in ws], [w.eps_r for w in ws], [w.sigma for w in ws],
+                                     [w.rough for w in ws])
+    trs = S.sbr_trace_batch(ctx, scenes, [w.tx for w in ws], [w.geodesic_N for w in ws], [w.max_bounces for w in ws])
+
+    def tail(c, i):
+        w = ws[i]
+        ps = S.sbr_receive(c, trs[i], w.rx)
+        H = np.zeros((len(w.freq), len(w.rx), 1), np.complex128)
+        S.sbr_channel(c, ps, w.freq, H_c128=H)
+        return S.sbr_paths_info(ps), H, S.sbr_stats(ps)
+
+    ref = [tail(ctx, i) for i in range(len(ws))]
+    pool_ctx = [S.Context(0) for _ in range(3)]
+    with cf.ThreadPoolExecutor(3) as ex:
+        got = list(ex.map(lambda i: tail(pool_ctx[i % 3], i), range(len(ws))))
+    for i, (a, b) in enumerate(zip(ref, got)):
+        assert a[0] == b[0], i
+        np.testing.assert_array_equal(a[1], b[1], err_msg=str(i))
+        for x, y in zip(a[2], b[2]):  # NaN (no path) equals NaN here
+            np.testing.assert_array_equal(np.asarray(x), np.asarray(y), err_msg=str(i))
+
+
 def test_trace_graph_replays(S, ctx):
     """The cached hipGraph bounce loop gives the eager result on every replay,
     with eager traces and synchronisations in between, across scenes that
