@@ -80,7 +80,11 @@ __global__ __launch_bounds__(1024) void k_replay_capture(const ReplayParams P) {
       const float3 dir = make_float3((float)d.x, (float)d.y, (float)d.z);
       const float infl = (float)(rmax + 1e-5 * (fabs(o.x - rc.x) + fabs(o.y - rc.y) + fabs(o.z - rc.z) + thi) + 1e-6);
       const float tmax = (float)thi * 1.00001f + 1e-6f;
-      auto safe_inv = [](float v) { return 1.0f / (fabsf(v) > 1e-20f ? v : copysignf(1e-20f, v)); };
+      // hardware reciprocal (about 1 ulp): the boxes are inflated by far more
+      // (1e-5 of the distances) than its error moves a slab distance
+      auto safe_inv = [](float v) {
+        return __builtin_amdgcn_rcpf(fabsf(v) > 1e-20f ? v : copysignf(1e-20f, v));
+      };
       const float3 inv = make_float3(safe_inv(dir.x), safe_inv(dir.y), safe_inv(dir.z));
       auto box_hit = [&](float lx, float ly, float lz, float hx, float hy, float hz) {
         lx -= infl, ly -= infl, lz -= infl, hx += infl, hy += infl, hz += infl;
