@@ -31,27 +31,6 @@ __device__ inline cd cadd(cd a, cd b) { return cd{a.re + b.re, a.im + b.im}; }
 __device__ inline cd csub(cd a, cd b) { return cd{a.re - b.re, a.im - b.im}; }
 __device__ inline cd cmul(cd a, cd b) { return cd{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
 __device__ inline cd cscale(cd a, double s) { return cd{a.re * s, a.im * s}; }
-__device__ inline cd cdiv(cd a, cd b) {
-  // Smith's algorithm (avoids overflow for large |b|)
-  if (fabs(b.re) >= fabs(b.im)) {
-    double r = b.im / b.re, den = b.re + b.im * r;
-    return cd{(a.re + a.im * r) / den, (a.im - a.re * r) / den};
-  }
-  double r = b.re / b.im, den = b.re * r + b.im;
-  return cd{(a.re * r + a.im) / den, (a.im * r - a.re) / den};
-}
-// principal square root
-__device__ inline cd csqrt_p(cd z) {
-  double m = hypot(z.re, z.im);
-  if (m == 0.0) return cd{0.0, 0.0};
-  if (z.re >= 0.0) {
-    double r = sqrt(0.5 * (m + z.re));
-    return cd{r, z.im / (2.0 * r)};
-  }
-  double i = sqrt(0.5 * (m - z.re));
-  if (z.im < 0.0 || (z.im == 0.0 && signbit(z.im))) i = -i;
-  return cd{z.im / (2.0 * i), i};
-}
 
 // ----------------------------------------------------------------- geodesic
 // Icosahedron tables passed by value to kernels (built on the host by search).
