@@ -168,6 +168,7 @@ struct KeyParams {
   int64_t R, NR;
   int Nt;
   int64_t n;
+  int hbits;  // hash bits below the segment index in the sort key
 };
 
 __device__ inline int ev_groups(const KeyParams& P, int64_t e, int32_t* g) {
@@ -177,9 +178,10 @@ __device__ inline int ev_groups(const KeyParams& P, int64_t e, int32_t* g) {
   return k;
 }
 
-// sort key of a capture: (segment = rx * Nt + tx) << 32 | 32-bit hash of the
-// face-group sequence.  Hash collisions only lengthen an equal-key run; the
-// dedup below compares the exact sequences inside each run.
+// sort key of a capture: (segment = rx * Nt + tx) << hbits | the top hbits
+// bits of a 32-bit hash of the face-group sequence.  Hash collisions only
+// lengthen an equal-key run; the dedup below compares the exact sequences
+// inside each run.
 __global__ void k_event_keys(const KeyParams P, uint64_t* __restrict__ key, uint32_t* __restrict__ vals) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= P.n) return;
@@ -190,7 +192,8 @@ __global__ void k_event_keys(const KeyParams P, uint64_t* __restrict__ key, uint
   const uint32_t rid = P.ev_ray[e];
   const int64_t p = rid / P.R;
   const uint64_t q = P.ev_qk[e] >> 5;
-  key[e] = ((q * (uint64_t)P.Nt + (uint64_t)p) << 32) | (uint32_t)(h ^ (h >> 32));
+  const uint32_t h32 = (uint32_t)(h ^ (h >> 32));
+  key[e] = ((q * (uint64_t)P.Nt + (uint64_t)p) << P.hbits) | (uint64_t)(h32 >> (32 - P.hbits));
   vals[e] = (uint32_t)e;
 }
 
@@ -659,15 +662,21 @@ void run_receive(sbr_paths_s* ps, const double* hrx, hipStream_t s) {
     return;
   }
   // ---------------- keys, one sort by (segment, hash), exact dedup
-  KeyParams kp{ev_ray.as<uint32_t>(), ev_qk.as<uint32_t>(), tr->seq.as<int32_t>(), sc->tgroup.as<int32_t>(),
-               tr->R, tr->NR, Nt, E};
   const int sbits = std::max(1, bits_for((uint64_t)nseg));
+  // Sort key: segment index, then a hash of the face-group sequence.  The
+  // hash only groups equal keys (k_unique_heads compares the sequences
+  // themselves within a run of equal sort keys), so it is cut to fill 32 bits
+  // when the segment index leaves at least 16: four 8-bit passes instead of
+  // six for up to 65,536 (rx, tx) pairs.
+  const int hbits = std::max(16, 32 - sbits);
+  KeyParams kp{ev_ray.as<uint32_t>(), ev_qk.as<uint32_t>(), tr->seq.as<int32_t>(), sc->tgroup.as<int32_t>(),
+               tr->R, tr->NR, Nt, E, hbits};
   Buf k1, k2, v1, v2, temp;
   k1.alloc(E * 8, s), k2.alloc(E * 8, s), v1.alloc(E * 4, s), v2.alloc(E * 4, s);
   temp.alloc(std::max(radix_sort_temp_bytes(E), scan_temp_bytes(E)), s);
   { ::sbr::TimedLaunch tl_("keys", s); hipLaunchKernelGGL(k_event_keys, dim3(nblk(E, 256)), dim3(256), 0, s, kp, k1.as<uint64_t>(), v1.as<uint32_t>()); }
   SBR_LAUNCH_CHECK();
-  radix_sort_pairs(k1.as<uint64_t>(), v1.as<uint32_t>(), k2.as<uint64_t>(), v2.as<uint32_t>(), E, 0, 32 + sbits,
+  radix_sort_pairs(k1.as<uint64_t>(), v1.as<uint32_t>(), k2.as<uint64_t>(), v2.as<uint32_t>(), E, 0, hbits + sbits,
                    temp.p, s);
   // now: v2 = event permutation, k2 = sorted keys
   Buf head, pos, tot;
