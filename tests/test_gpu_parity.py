@@ -159,6 +159,20 @@ def test_plane_scenes(S, ctx, scene):
     _full_case(S, ctx, w, coeff=exhaustive(w.geodesic_N), exact_keys=True)
 
 
+@pytest.mark.parametrize("n_tri", [1, 2])
+def test_one_and_two_triangle_scenes(S, ctx, n_tri):
+    """The smallest trees: a single leaf (one triangle) and one node over two
+    leaves, built from device-prepared inputs; the specular point of the wall
+    lies in its first triangle."""
+    import dataclasses
+    banner("triangles", n_tri)
+    w0 = W.one_plane(K=1, N=24)
+    w = dataclasses.replace(w0, tri=w0.tri[:n_tri].copy(), eps_r=w0.eps_r[:n_tri].copy(),
+                            sigma=w0.sigma[:n_tri].copy(), rough=w0.rough[:n_tri].copy())
+    assert w.T == n_tri
+    _full_case(S, ctx, w, coeff=exhaustive(w.geodesic_N), exact_keys=True)
+
+
 @pytest.mark.parametrize("pol", [(0, 1), (1, 0), (1, 1)])
 def test_polarisations(S, ctx, pol):
     banner("polarisation", pol)
