@@ -288,9 +288,9 @@ __device__ bool leg_blocked(const RebuildParams& P, int32_t* stk, d3 a, d3 b, in
     return tmin <= tmx * (1.0 + 1e-12) + 1e-300;
   };
   auto tri_block = [&](int32_t leaf) -> bool {
-    const int grp = __float_as_int(P.tri32[3 * leaf + 2].w);
+    const int grp = __float_as_int(P.tri32[kTriVecs * leaf + 2].w);
     if (grp == ga || grp == gb) return false;
-    const int orig = __float_as_int(P.tri32[3 * leaf].w);
+    const int orig = __float_as_int(P.tri32[kTriVecs * leaf].w);
     const double* t = P.tri64 + 9 * (int64_t)orig;
     const d3 v0 = ld3(t), e1 = ld3(t + 3) - v0, e2 = ld3(t + 6) - v0;
     const d3 pv = cross(D, e2);

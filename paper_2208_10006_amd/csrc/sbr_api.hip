@@ -318,8 +318,10 @@ void set_device(sbr_context_s* c) {
   g_prof = &c->prof;
 }
 
-// tri[off + i] = triangle m(order ? order[i] : i), m = map or the identity
-// (FP32 vertices | original id, plane id, group id)
+// triangle off + i of the FP32 array = triangle m(order ? order[i] : i), m =
+// map or the identity: its vertices in the three cyclic axis orders (layout z
+// holds axes z + 1, z + 2, z, so a ray whose dominant axis is z finds the
+// coordinates of its shear frame in place), each vertex with one id in .w
 __global__ void k_tri_gather(const uint32_t* __restrict__ order, const int32_t* __restrict__ map, int64_t n,
                              int64_t off, const float* __restrict__ v32, const int32_t* __restrict__ plane,
                              const int32_t* __restrict__ group, float4* __restrict__ tri) {
@@ -328,10 +330,12 @@ __global__ void k_tri_gather(const uint32_t* __restrict__ order, const int32_t* 
   const uint32_t u = order ? order[i] : (uint32_t)i;
   const int32_t t = map ? map[u] : (int32_t)u;
   const float* v = v32 + 9 * (int64_t)t;
-  const int64_t o = 3 * (off + i);
-  tri[o] = make_float4(v[0], v[1], v[2], __int_as_float(t));
-  tri[o + 1] = make_float4(v[3], v[4], v[5], __int_as_float(plane[t]));
-  tri[o + 2] = make_float4(v[6], v[7], v[8], __int_as_float(group[t]));
+  const int64_t o = kTriVecs * (off + i);
+  const float w[3] = {__int_as_float(t), __int_as_float(plane[t]), __int_as_float(group[t])};
+  for (int z = 0; z < 3; ++z) {
+    const int x = z == 2 ? 0 : z + 1, y = x == 2 ? 0 : x + 1;
+    for (int j = 0; j < 3; ++j) tri[o + 3 * z + j] = make_float4(v[3 * j + x], v[3 * j + y], v[3 * j + z], w[j]);
+  }
 }
 
 // Scene preparation on the device, so that the tree build starts before the
@@ -601,7 +605,7 @@ static sbr_scene_s* scene_build_on(sbr_context_s* c, hipStream_t s, HostStage& h
     auto alloc_tree = [&] {
       sc->nodes.alloc((size_t)std::max<int64_t>(sc->n_bvh - 1, 1) * 64, s);
       sc->root_box.alloc(32, s);  // 6 floats of root box, then the depth word
-      sc->tri32.alloc((size_t)T * 48, s);
+      sc->tri32.alloc((size_t)T * kTriVecs * sizeof(float4), s);
       depth_dev = reinterpret_cast<uint32_t*>(sc->root_box.as<float>() + 6);
     };
     {

@@ -339,6 +339,11 @@ void launch_trace(const TraceLaunch& L, void* ray_a, void* ray_b, hipStream_t s)
 void launch_trace_batch(const std::vector<sbr_trace_s*>& trs, int grid, int chunk, void* ray_a, void* ray_b,
                         uint32_t* counters, unsigned long long* t_first, unsigned long long* t_last, hipStream_t s);
 size_t trace_ray_bytes(int64_t NR);
+// FP32 triangles in leaf order: kTriVecs float4 per triangle, its three
+// vertices in each of the three cyclic axis orders (x y z | y z x | z x y),
+// the .w lanes holding the original id, plane id and group id (vertex 0, 1, 2)
+constexpr int kTriVecs = 9;
+
 // Trace counters: per bounce a block of kCtrWords words holding, for each of
 // the 8 ray regions x, the queue position (kCtrQueue + 32 x), the number of
 // survivors written (kCtrOut + 32 x) and an "empty" flag (kCtrDone + 32 x).

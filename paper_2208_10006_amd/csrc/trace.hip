@@ -171,7 +171,7 @@ __global__ void k_fill_u32_graph(uint32_t* p, uint32_t v, int64_t n) {
 // Everything the bounce kernel needs about one scene and its launch.
 struct SceneDesc {
   const float4* nodes;
-  const float4* tri;      // 3 per leaf: v0|orig id, v1|plane id, v2|group id
+  const float4* tri;      // kTriVecs per leaf: 3 axis orders x (v0|orig id, v1|plane id, v2|group id)
   const double4* tplane;  // per original triangle
   const int32_t* tplaneid;
   const double* tx;
@@ -327,18 +327,20 @@ __global__ __launch_bounds__(256) void k_bounce(const BounceParams P) {
       auto safe_inv = [](float v) { return 1.0f / (fabsf(v) > 1e-20f ? v : copysignf(1e-20f, v)); };
       const float3 inv = make_float3(safe_inv(dir.x), safe_inv(dir.y), safe_inv(dir.z));
       const float3 oinv = make_float3(org.x * inv.x, org.y * inv.y, org.z * inv.z);
-      // watertight shear constants
+      // watertight shear constants: kz is the dominant axis of the direction,
+      // kx and ky the next two in cyclic order.  The usual swap of kx and ky
+      // for a negative dir[kz] only fixes the winding; the test is double
+      // sided (U, V, W, det and Tn all change sign together), so the cyclic
+      // order serves, and the triangle array holds every triangle in the
+      // three cyclic orders: the ray reads layout kz and needs no selects.
       const float ax = fabsf(dir.x), ay = fabsf(dir.y), az = fabsf(dir.z);
-      int kz = ax > ay ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
-      int kx = kz == 2 ? 0 : kz + 1;
-      int ky = kx == 2 ? 0 : kx + 1;
-      if (sel(dir, kz) < 0.0f) {
-        const int t = kx;
-        kx = ky;
-        ky = t;
-      }
+      const int kz = ax > ay ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
+      const int kx = kz == 2 ? 0 : kz + 1;
+      const int ky = kx == 2 ? 0 : kx + 1;
       const float dz = sel(dir, kz);
       const float Sx = sel(dir, kx) / dz, Sy = sel(dir, ky) / dz, Sz = 1.0f / dz;
+      const float3 orgs = make_float3(sel(org, kx), sel(org, ky), sel(org, kz));  // origin in layout kz
+      const int lay = 3 * kz;
 
       auto box_hit = [&](float lx, float ly, float lz, float hx, float hy, float hz, float tmax, float& tn) {
         const float t0x = fmaf(lx, inv.x, -oinv.x), t1x = fmaf(hx, inv.x, -oinv.x);
@@ -349,21 +351,19 @@ __global__ __launch_bounds__(256) void k_bounce(const BounceParams P) {
         tn = tmin;
         return tmin <= tmx * 1.0000004f;
       };
-      // All 48 bytes of the triangle are loaded before any decision, so a
+      // All 48 bytes of the triangle's layout are loaded before any decision, so a
       // test costs one memory round trip; the rejections are folded into one
       // final predicate instead of early exits.  t = Tn / det is formed with
       // the hardware reciprocal (about 1 ulp): t only ranks candidates, and
       // the selected hit is re-evaluated in FP64 on its plane afterwards.
       auto tri_test = [&](int32_t leaf) {
         if (COUNT) ++n_tri;
-        const float4 a = tri[3 * leaf], b = tri[3 * leaf + 1], c = tri[3 * leaf + 2];
-        const float3 A = make_float3(a.x - org.x, a.y - org.y, a.z - org.z);
-        const float3 B = make_float3(b.x - org.x, b.y - org.y, b.z - org.z);
-        const float3 C = make_float3(c.x - org.x, c.y - org.y, c.z - org.z);
-        const float Akz = sel(A, kz), Bkz = sel(B, kz), Ckz = sel(C, kz);
-        const float Ax = sel(A, kx) - Sx * Akz, Ay = sel(A, ky) - Sy * Akz;
-        const float Bx = sel(B, kx) - Sx * Bkz, By = sel(B, ky) - Sy * Bkz;
-        const float Cx = sel(C, kx) - Sx * Ckz, Cy = sel(C, ky) - Sy * Ckz;
+        const float4* tv = tri + (int64_t)kTriVecs * leaf + lay;
+        const float4 a = tv[0], b = tv[1], c = tv[2];
+        const float Akz = a.z - orgs.z, Bkz = b.z - orgs.z, Ckz = c.z - orgs.z;
+        const float Ax = (a.x - orgs.x) - Sx * Akz, Ay = (a.y - orgs.y) - Sy * Akz;
+        const float Bx = (b.x - orgs.x) - Sx * Bkz, By = (b.y - orgs.y) - Sy * Bkz;
+        const float Cx = (c.x - orgs.x) - Sx * Ckz, Cy = (c.y - orgs.y) - Sy * Ckz;
         float U = Cx * By - Cy * Bx, V = Ax * Cy - Ay * Cx, W = Bx * Ay - By * Ax;
         if (U == 0.0f || V == 0.0f || W == 0.0f) {
           U = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
@@ -426,7 +426,7 @@ __global__ __launch_bounds__(256) void k_bounce(const BounceParams P) {
           if (done) break;
         }
       }
-      if (hit >= 0) hit = __float_as_int(tri[3 * hit].w);  // original triangle id
+      if (hit >= 0) hit = __float_as_int(tri[(int64_t)kTriVecs * hit].w);  // original triangle id
     }
     // ------------------------------------------------ record, reflect in FP64, compact
     const int32_t orig = hit;
