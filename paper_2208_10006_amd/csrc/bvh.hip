@@ -177,12 +177,18 @@ __global__ void k_depth(const int32_t* __restrict__ parent_int, const int32_t* _
 // arrival merge it (its sibling's box and height were stored before the
 // sibling's release-increment), and node heights give the depth: the
 // number of internal nodes on the longest root-to-leaf path.
-constexpr int kLbvhSmall = 2048;
 __global__ __launch_bounds__(kSmallThreads) void k_lbvh_small(const float* __restrict__ lo,
                                                             const float* __restrict__ hi, int n, float3 slo,
-                                                            float3 inv_ext, float4* __restrict__ nodes,
+                                                            float3 inv_ext, const float* __restrict__ bounds,
+                                                            float4* __restrict__ nodes,
                                                             uint32_t* __restrict__ order, float* __restrict__ root_box,
                                                             uint32_t* __restrict__ depth) {
+  if (bounds) {  // scene box from the device, by the same float operations as the host
+    slo = make_float3(bounds[0], bounds[1], bounds[2]);
+    inv_ext.x = bounds[3] > bounds[0] ? 1.0f / (bounds[3] - bounds[0]) : 0.0f;
+    inv_ext.y = bounds[4] > bounds[1] ? 1.0f / (bounds[4] - bounds[1]) : 0.0f;
+    inv_ext.z = bounds[5] > bounds[2] ? 1.0f / (bounds[5] - bounds[2]) : 0.0f;
+  }
   __shared__ uint64_t lk[kLbvhSmall];
   __shared__ uint32_t lv[kLbvhSmall];
   __shared__ uint16_t hist[kSmallWaves][256];
@@ -627,7 +633,6 @@ int build_bvh(const float* box_lo, const float* box_hi, int64_t n, const float s
       ie.y = scene_hi[1] > scene_lo[1] ? 1.0f / (scene_hi[1] - scene_lo[1]) : 0.0f;
       ie.z = scene_hi[2] > scene_lo[2] ? 1.0f / (scene_hi[2] - scene_lo[2]) : 0.0f;
     }
-    SBR_CHECK(!out.bounds_dev, SBR_E_UNSUPPORTED, "device scene bounds with the small linear builder");
     Buf dword;
     uint32_t* dd = out.depth_dev;
     if (!dd) {
@@ -635,7 +640,7 @@ int build_bvh(const float* box_lo, const float* box_hi, int64_t n, const float s
       dd = dword.as<uint32_t>();
     }
     { ::sbr::TimedLaunch tl_("bvh", s); hipLaunchKernelGGL(k_lbvh_small, dim3(1), dim3(kSmallThreads), 0, s, box_lo, box_hi, (int)n, slo, ie,
-                       out.nodes, out.order, out.root_box, dd); }
+                       out.bounds_dev, out.nodes, out.order, out.root_box, dd); }
     SBR_LAUNCH_CHECK();
     if (out.depth_dev) return 0;
     uint32_t depth = 0;

@@ -43,6 +43,10 @@ struct ReplayParams {
   float rroot[6];
   const double* rx;
   double rc[3], rrad;  // Rx bounding sphere (FP64); FP32 Rx frame centred on rc
+  // device-prepared receiver sets: rc xyz and rrad (4 doubles) and the root
+  // box (6 floats) in device memory, used instead of the fields above
+  const double* rdev;
+  const float* rroot_dev;
   double rfac;         // coeff * alpha / sqrt(3)
   uint32_t* ev_count;
   uint64_t ev_cap;
@@ -50,18 +54,45 @@ struct ReplayParams {
   uint32_t* ev_qk;     // q << 5 | k
 };
 
-template <int STACK>
+// SE: stack entry type (int16_t for trees of up to kLbvhSmall primitives,
+// whose node and leaf references fit 16 bits).  DEV: the receiver frame and
+// root box come from device memory (P.rdev, P.rroot_dev) instead of the
+// parameters; they are uniform and are moved to scalar registers.
+__device__ inline double uniform_f64(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+template <int STACK, typename SE, bool DEV>
 __global__ __launch_bounds__(1024) void k_replay_capture(const ReplayParams P) {
-  extern __shared__ int32_t stack_dyn[];  // [waves][STACK][64]
+  // The wave's stack: entry e of a lane at slot(e).  For 4-byte entries slot
+  // e is word e * 64 + lane; 2-byte entries are paired per lane (entries 2i
+  // and 2i + 1 in the two halves of word i * 64 + lane), so that no two lanes
+  // share an LDS word.
+  extern __shared__ unsigned char stack_raw[];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  int32_t* stk = stack_dyn + (wv * STACK) * kWave + lane;
+  SE* const stk_base = reinterpret_cast<SE*>(stack_raw) + (size_t)wv * STACK * kWave;
+  auto slot = [&](int e) -> SE& {
+    if (sizeof(SE) == 2) return stk_base[((e >> 1) * kWave + lane) * 2 + (e & 1)];
+    return stk_base[e * kWave + lane];
+  };
   const int64_t rid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (rid >= P.NR) return;
   const int p = (int)(rid / P.R);
   d3 o = ld3(P.tx + 3 * p);
   d3 d = geo_dir(P.G, P.N, rid - (int64_t)p * P.R);
   double L = 0.0;
-  const d3 rc = mk3(P.rc[0], P.rc[1], P.rc[2]);
+  d3 rc = mk3(P.rc[0], P.rc[1], P.rc[2]);
+  double rrad = P.rrad;
+  float rroot[6];
+  for (int k = 0; k < 6; ++k) rroot[k] = P.rroot[k];
+  if (DEV) {
+    rc = mk3(uniform_f64(P.rdev[0]), uniform_f64(P.rdev[1]), uniform_f64(P.rdev[2]));
+    rrad = uniform_f64(P.rdev[3]);
+    for (int k = 0; k < 6; ++k)
+      rroot[k] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(P.rroot_dev[k])));
+  }
   for (int k = 0; k <= P.K; ++k) {
     int32_t tri = P.seq[(int64_t)k * P.NR + rid];
     if (tri >= P.T) tri = -1;  // defensive: chain entries are triangle ids or -1
@@ -73,7 +104,7 @@ __global__ __launch_bounds__(1024) void k_replay_capture(const ReplayParams P) {
     }
     // ---------------- capture test of segment (o, d, [0, tend], L)
     // any capture has t* = (q - o).d <= |q - o| <= |o - rc| + rrad
-    const double thi = fmin(tend, norm(o - rc) + P.rrad);
+    const double thi = fmin(tend, norm(o - rc) + rrad);
     if (thi >= 0.0) {
       const double rmax = P.rfac * (L + thi);
       const float3 org = make_float3((float)(o.x - rc.x), (float)(o.y - rc.y), (float)(o.z - rc.z));
@@ -110,7 +141,7 @@ __global__ __launch_bounds__(1024) void k_replay_capture(const ReplayParams P) {
           }
         }
       };
-      if (box_hit(P.rroot[0], P.rroot[1], P.rroot[2], P.rroot[3], P.rroot[4], P.rroot[5])) {
+      if (box_hit(rroot[0], rroot[1], rroot[2], rroot[3], rroot[4], rroot[5])) {
         int sp = 0;
         int32_t node = 0;
         while (true) {
@@ -129,7 +160,7 @@ __global__ __launch_bounds__(1024) void k_replay_capture(const ReplayParams P) {
           }
           if (cr < 0) hr = false;
           if (hl && hr) {
-            stk[kWave * sp] = cr;
+            slot(sp) = (SE)cr;
             ++sp;
             node = cl;
           } else if (hl) {
@@ -139,7 +170,7 @@ __global__ __launch_bounds__(1024) void k_replay_capture(const ReplayParams P) {
           } else {
             if (sp == 0) break;
             --sp;
-            node = stk[kWave * sp];
+            node = (int32_t)slot(sp);
           }
         }
       }
@@ -551,6 +582,98 @@ int bits_for(uint64_t v) {
   return b;
 }
 
+// Receiver frame of a set of up to kLbvhSmall points, on the device (one
+// workgroup): FP64 box, centre rc = 0.5 (lo + hi), radius max |x - rc| (times
+// 1 + 1e-12, plus 1e-12), FP32 point boxes nextafter((float)(x - rc)) outward
+// and their bounds -- the host's operations for larger sets -- and the input
+// checks of a receive: bad[0] = lowest receiver with a non-finite coordinate,
+// bad[1] = lowest q Nt + p with receiver q on transmitter p (both preset to
+// all ones by the host).  Outputs: frame = rc xyz, rrad; bounds = lo xyz, hi xyz.
+constexpr int kRxPrepThreads = 1024;
+// replay stack of trees from the one-workgroup builder: at most 41 entries
+// (one per internal node on a path); 44 two-byte entries keep a 256-thread
+// block at 22.5 KB of LDS, so that 7 blocks fit a CU
+constexpr int kRxSmallStack = 44;
+__global__ __launch_bounds__(kRxPrepThreads) void k_rx_prep(const double* __restrict__ rx, int Nr,
+                                                            const double* __restrict__ tx, int Nt,
+                                                            float* __restrict__ blo, float* __restrict__ bhi,
+                                                            float* __restrict__ bounds, double* __restrict__ frame,
+                                                            uint32_t* __restrict__ bad) {
+  constexpr int W = kRxPrepThreads / kWave;
+  __shared__ double dred[6][W];
+  __shared__ float fred[6][W];
+  __shared__ double lohi[6];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  auto lesser = [](double a, double b) { return b < a ? b : a; };
+  auto greater = [](double a, double b) { return a < b ? b : a; };
+  // box
+  double b[6] = {1e300, 1e300, 1e300, -1e300, -1e300, -1e300};
+  for (int q = t; q < Nr; q += kRxPrepThreads)
+    for (int c = 0; c < 3; ++c) {
+      const double x = rx[3 * q + c];
+      if (!isfinite(x)) atomicMin(bad, (uint32_t)q);
+      b[c] = lesser(b[c], x), b[3 + c] = greater(b[3 + c], x);
+    }
+  for (int o = 32; o > 0; o >>= 1)
+    for (int k = 0; k < 6; ++k) {
+      const double y = __shfl_xor(b[k], o, 64);
+      b[k] = k < 3 ? lesser(b[k], y) : greater(b[k], y);
+    }
+  if (lane == 0)
+    for (int k = 0; k < 6; ++k) dred[k][wv] = b[k];
+  __syncthreads();
+  if (t < 6) {
+    double r = dred[t][0];
+    for (int w = 1; w < W; ++w) r = t < 3 ? lesser(r, dred[t][w]) : greater(r, dred[t][w]);
+    lohi[t] = r;
+  }
+  __syncthreads();
+  const double rcx = 0.5 * (lohi[0] + lohi[3]), rcy = 0.5 * (lohi[1] + lohi[4]), rcz = 0.5 * (lohi[2] + lohi[5]);
+  // radius and FP32 boxes
+  double rad = 0.0;
+  float fb[6] = {1e30f, 1e30f, 1e30f, -1e30f, -1e30f, -1e30f};
+  for (int q = t; q < Nr; q += kRxPrepThreads) {
+    const double v[3] = {rx[3 * q] - rcx, rx[3 * q + 1] - rcy, rx[3 * q + 2] - rcz};
+    double d2 = 0.0;
+    for (int c = 0; c < 3; ++c) d2 += v[c] * v[c];
+    rad = greater(rad, sqrt(d2));
+    for (int c = 0; c < 3; ++c) {
+      const float l = nextafterf((float)v[c], -INFINITY), h = nextafterf((float)v[c], INFINITY);
+      blo[3 * q + c] = l, bhi[3 * q + c] = h;
+      fb[c] = fminf(fb[c], l), fb[3 + c] = fmaxf(fb[3 + c], h);
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    rad = greater(rad, __shfl_xor(rad, o, 64));
+    for (int k = 0; k < 6; ++k) {
+      const float y = __shfl_xor(fb[k], o, 64);
+      fb[k] = k < 3 ? fminf(fb[k], y) : fmaxf(fb[k], y);
+    }
+  }
+  __syncthreads();  // the box reduction's LDS is reused
+  if (lane == 0) {
+    dred[0][wv] = rad;
+    for (int k = 0; k < 6; ++k) fred[k][wv] = fb[k];
+  }
+  __syncthreads();
+  if (t == 0) {
+    double r = dred[0][0];
+    for (int w = 1; w < W; ++w) r = greater(r, dred[0][w]);
+    frame[0] = rcx, frame[1] = rcy, frame[2] = rcz, frame[3] = r * (1.0 + 1e-12) + 1e-12;
+  }
+  if (t < 6) {
+    float r = fred[t][0];
+    for (int w = 1; w < W; ++w) r = t < 3 ? fminf(r, fred[t][w]) : fmaxf(r, fred[t][w]);
+    bounds[t] = r;
+  }
+  // a receiver on a transmitter
+  for (int64_t i = t; i < (int64_t)Nr * Nt; i += kRxPrepThreads) {
+    const int q = (int)(i / Nt), p = (int)(i - (int64_t)q * Nt);
+    if (rx[3 * q] == tx[3 * p] && rx[3 * q + 1] == tx[3 * p + 1] && rx[3 * q + 2] == tx[3 * p + 2])
+      atomicMin(bad + 1, (uint32_t)i);
+  }
+}
+
 }  // namespace
 
 void run_receive(sbr_paths_s* ps, const double* hrx, hipStream_t s) {
@@ -563,43 +686,64 @@ void run_receive(sbr_paths_s* ps, const double* hrx, hipStream_t s) {
   HostPhase hp_all("host:receive");
   std::optional<HostPhase> hp_rx, hp_step;
   hp_rx.emplace("host:rx_tree");
-  hp_step.emplace("host:rx_boxes");
-  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-  for (int q = 0; q < Nr; ++q)
-    for (int c = 0; c < 3; ++c) lo[c] = std::min(lo[c], hrx[3 * q + c]), hi[c] = std::max(hi[c], hrx[3 * q + c]);
-  double rc[3], rrad = 0.0;
-  for (int c = 0; c < 3; ++c) rc[c] = 0.5 * (lo[c] + hi[c]);
-  for (int q = 0; q < Nr; ++q) {
-    double d2 = 0;
-    for (int c = 0; c < 3; ++c) d2 += (hrx[3 * q + c] - rc[c]) * (hrx[3 * q + c] - rc[c]);
-    rrad = std::max(rrad, std::sqrt(d2));
-  }
-  rrad = rrad * (1.0 + 1e-12) + 1e-12;
-  std::vector<float> blo(3 * (size_t)Nr), bhi(3 * (size_t)Nr);
-  float flo[3] = {1e30f, 1e30f, 1e30f}, fhi[3] = {-1e30f, -1e30f, -1e30f};
-  for (int q = 0; q < Nr; ++q)
-    for (int c = 0; c < 3; ++c) {
-      const double v = hrx[3 * q + c] - rc[c];
-      blo[3 * q + c] = std::nextafter((float)v, -INFINITY);
-      bhi[3 * q + c] = std::nextafter((float)v, INFINITY);
-      flo[c] = std::min(flo[c], blo[3 * q + c]);
-      fhi[c] = std::max(fhi[c], bhi[3 * q + c]);
-    }
-  Buf dlo, dhi, rnodes, rorder, rroot;
-  dlo.alloc(blo.size() * 4, s);
-  dhi.alloc(bhi.size() * 4, s);
-  SBR_HIP(hipMemcpyAsync(dlo.p, blo.data(), blo.size() * 4, hipMemcpyHostToDevice, s));
-  SBR_HIP(hipMemcpyAsync(dhi.p, bhi.data(), bhi.size() * 4, hipMemcpyHostToDevice, s));
-  hp_step.emplace("host:rx_lbvh");
+  // Sets of up to kLbvhSmall receivers: frame, boxes, input checks and tree
+  // on the device with no synchronisation (the replay reads the frame and the
+  // root box from device memory and needs no depth: such a tree has at most
+  // 41 internal nodes on a path, within its kRxSmallStack-entry stack).
+  // Larger sets: the same steps on the host, then the tree.
+  const bool dev_prep = Nr <= kLbvhSmall;
+  Buf dlo, dhi, rnodes, rorder, rroot, rframe, bad;
+  dlo.alloc((size_t)Nr * 12, s);
+  dhi.alloc((size_t)Nr * 12, s);
   rnodes.alloc((size_t)std::max(Nr - 1, 1) * 64, s);
   rorder.alloc((size_t)Nr * 4, s);
-  rroot.alloc(32, s);
-  float hroot[8];
-  const int rdepth =
-      build_bvh(dlo.as<float>(), dhi.as<float>(), Nr, flo, fhi, BvhOut{rnodes.as<float4>(), rorder.as<uint32_t>(),
-                                                                         rroot.as<float>(), hroot}, s,
-                /*linear=*/true);
-  SBR_CHECK(rdepth <= 64, SBR_E_UNSUPPORTED, "receiver tree depth %d", rdepth);
+  rroot.alloc(32, s);  // 6 floats of root box, then the depth word
+  float hroot[8] = {};
+  int rdepth = 0;
+  double rc[3] = {0.0, 0.0, 0.0}, rrad = 0.0;
+  if (dev_prep) {
+    rframe.alloc(64, s);  // rc xyz, rrad (doubles); then the FP32 bounds at byte 32
+    bad.alloc(8, s);
+    fill_u32(bad.as<uint32_t>(), 0xffffffffu, 2, s);
+    float* dbounds = reinterpret_cast<float*>(rframe.as<char>() + 32);
+    { ::sbr::TimedLaunch tl_("bvh", s); hipLaunchKernelGGL(k_rx_prep, dim3(1), dim3(kRxPrepThreads), 0, s, ps->rx.as<double>(), Nr,
+                       tr->tx.as<double>(), Nt, dlo.as<float>(), dhi.as<float>(), dbounds, rframe.as<double>(),
+                       bad.as<uint32_t>()); }
+    SBR_LAUNCH_CHECK();
+    BvhOut bo{rnodes.as<float4>(), rorder.as<uint32_t>(), rroot.as<float>(), nullptr,
+              reinterpret_cast<uint32_t*>(rroot.as<float>() + 6)};
+    bo.bounds_dev = dbounds;
+    build_bvh(dlo.as<float>(), dhi.as<float>(), Nr, nullptr, nullptr, bo, s, /*linear=*/true);
+  } else {
+    hp_step.emplace("host:rx_boxes");
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int q = 0; q < Nr; ++q)
+      for (int c = 0; c < 3; ++c) lo[c] = std::min(lo[c], hrx[3 * q + c]), hi[c] = std::max(hi[c], hrx[3 * q + c]);
+    for (int c = 0; c < 3; ++c) rc[c] = 0.5 * (lo[c] + hi[c]);
+    for (int q = 0; q < Nr; ++q) {
+      double d2 = 0;
+      for (int c = 0; c < 3; ++c) d2 += (hrx[3 * q + c] - rc[c]) * (hrx[3 * q + c] - rc[c]);
+      rrad = std::max(rrad, std::sqrt(d2));
+    }
+    rrad = rrad * (1.0 + 1e-12) + 1e-12;
+    std::vector<float> blo(3 * (size_t)Nr), bhi(3 * (size_t)Nr);
+    float flo[3] = {1e30f, 1e30f, 1e30f}, fhi[3] = {-1e30f, -1e30f, -1e30f};
+    for (int q = 0; q < Nr; ++q)
+      for (int c = 0; c < 3; ++c) {
+        const double v = hrx[3 * q + c] - rc[c];
+        blo[3 * q + c] = std::nextafter((float)v, -INFINITY);
+        bhi[3 * q + c] = std::nextafter((float)v, INFINITY);
+        flo[c] = std::min(flo[c], blo[3 * q + c]);
+        fhi[c] = std::max(fhi[c], bhi[3 * q + c]);
+      }
+    SBR_HIP(hipMemcpyAsync(dlo.p, blo.data(), blo.size() * 4, hipMemcpyHostToDevice, s));
+    SBR_HIP(hipMemcpyAsync(dhi.p, bhi.data(), bhi.size() * 4, hipMemcpyHostToDevice, s));
+    hp_step.emplace("host:rx_lbvh");
+    rdepth = build_bvh(dlo.as<float>(), dhi.as<float>(), Nr, flo, fhi,
+                       BvhOut{rnodes.as<float4>(), rorder.as<uint32_t>(), rroot.as<float>(), hroot}, s,
+                       /*linear=*/true);
+    SBR_CHECK(rdepth <= 64, SBR_E_UNSUPPORTED, "receiver tree depth %d", rdepth);
+  }
   hp_step.reset();
   hp_rx.reset();
 
@@ -617,13 +761,14 @@ void run_receive(sbr_paths_s* ps, const double* hrx, hipStream_t s) {
   P.rx = ps->rx.as<double>();
   for (int c = 0; c < 3; ++c) P.rc[c] = rc[c];
   P.rrad = rrad;
+  if (dev_prep) P.rdev = rframe.as<double>(), P.rroot_dev = rroot.as<float>();
   P.rfac = ps->coeff * ps->alpha / std::sqrt(3.0);
   Buf cnt;
   cnt.alloc(16, s);
   uint64_t cap = std::max<uint64_t>(1u << 20, (uint64_t)tr->NR / 8);
   Buf& ev_ray = ps->ev_ray;
   Buf& ev_qk = ps->ev_qk;
-  uint32_t n_ev = 0;
+  uint32_t n_ev = 0, hbad[2] = {0xffffffffu, 0xffffffffu};
   for (int attempt = 0; attempt < 3; ++attempt) {
     ev_ray.alloc(cap * 4, s);
     ev_qk.alloc(cap * 4, s);
@@ -634,17 +779,25 @@ void run_receive(sbr_paths_s* ps, const double* hrx, hipStream_t s) {
     P.ev_qk = ev_qk.as<uint32_t>();
     const int rb = ps->ctx->tune.replay_block;
     const unsigned g = nblk(tr->NR, rb);
-    const size_t lds = (size_t)(rb / kWave) * kWave * sizeof(int32_t) * (rdepth <= 16 ? 16 : rdepth <= 32 ? 32 : 64);
+    const size_t lds = dev_prep ? (size_t)(rb / kWave) * kWave * sizeof(int16_t) * kRxSmallStack
+                                : (size_t)(rb / kWave) * kWave * sizeof(int32_t) *
+                                      (rdepth <= 16 ? 16 : rdepth <= 32 ? 32 : 64);
     ::sbr::TimedLaunch tl_("replay_capture", s);
-    if (rdepth <= 16)
-      hipLaunchKernelGGL(k_replay_capture<16>, dim3(g), dim3(rb), lds, s, P);
+    if (dev_prep)
+      hipLaunchKernelGGL((k_replay_capture<kRxSmallStack, int16_t, true>), dim3(g), dim3(rb), lds, s, P);
+    else if (rdepth <= 16)
+      hipLaunchKernelGGL((k_replay_capture<16, int32_t, false>), dim3(g), dim3(rb), lds, s, P);
     else if (rdepth <= 32)
-      hipLaunchKernelGGL(k_replay_capture<32>, dim3(g), dim3(rb), lds, s, P);
+      hipLaunchKernelGGL((k_replay_capture<32, int32_t, false>), dim3(g), dim3(rb), lds, s, P);
     else
-      hipLaunchKernelGGL(k_replay_capture<64>, dim3(g), dim3(rb), lds, s, P);
+      hipLaunchKernelGGL((k_replay_capture<64, int32_t, false>), dim3(g), dim3(rb), lds, s, P);
     SBR_LAUNCH_CHECK();
     SBR_HIP(hipMemcpyAsync(&n_ev, cnt.p, 4, hipMemcpyDeviceToHost, s));
+    if (dev_prep) SBR_HIP(hipMemcpyAsync(hbad, bad.p, 8, hipMemcpyDeviceToHost, s));
     SBR_HIP(hipStreamSynchronize(s));
+    SBR_CHECK(hbad[0] == 0xffffffffu, SBR_E_INVALID_ARG, "rx coordinates must be finite (rx %u)", hbad[0]);
+    SBR_CHECK(hbad[1] == 0xffffffffu, SBR_E_INVALID_ARG, "rx %u coincides with tx %u", hbad[1] / (uint32_t)Nt,
+              hbad[1] % (uint32_t)Nt);
     if (n_ev <= cap) break;
     cap = (uint64_t)n_ev + n_ev / 8 + 1024;
   }

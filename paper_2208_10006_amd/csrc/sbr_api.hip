@@ -1141,13 +1141,21 @@ sbr_status sbr_receive(sbr_context_t ctx, sbr_trace_t t, const double* rx_xyz, i
     SBR_CHECK(std::isfinite(alpha_rad), SBR_E_INVALID_ARG, "alpha must be finite");
     set_device(c);
     hipStream_t s = c->stream;
-    const auto hrx = to_host(rx_xyz, (size_t)Nr * 3, flags, s);
-    SBR_CHECK(finite_all(hrx.data(), hrx.size()), SBR_E_INVALID_ARG, "rx coordinates must be finite");
-    for (int q = 0; q < Nr; ++q)
-      for (int p = 0; p < tr->Nt; ++p)
-        SBR_CHECK(!(hrx[3 * q] == tr->h_tx[3 * p] && hrx[3 * q + 1] == tr->h_tx[3 * p + 1] &&
-                    hrx[3 * q + 2] == tr->h_tx[3 * p + 2]),
-                  SBR_E_INVALID_ARG, "rx %d coincides with tx %d", q, p);
+    // Up to kLbvhSmall receivers are prepared and checked on the device (a
+    // host copy of device-resident points would wait for the trace queued
+    // before it); larger sets go through the host.
+    const bool dev_prep = Nr <= kLbvhSmall;
+    SBR_CHECK(rx_xyz != nullptr, SBR_E_INVALID_ARG, "rx is NULL");
+    std::vector<double> hrx;
+    if (!dev_prep) {
+      hrx = to_host(rx_xyz, (size_t)Nr * 3, flags, s);
+      SBR_CHECK(finite_all(hrx.data(), hrx.size()), SBR_E_INVALID_ARG, "rx coordinates must be finite");
+      for (int q = 0; q < Nr; ++q)
+        for (int p = 0; p < tr->Nt; ++p)
+          SBR_CHECK(!(hrx[3 * q] == tr->h_tx[3 * p] && hrx[3 * q + 1] == tr->h_tx[3 * p + 1] &&
+                      hrx[3 * q + 2] == tr->h_tx[3 * p + 2]),
+                    SBR_E_INVALID_ARG, "rx %d coincides with tx %d", q, p);
+    }
     auto* ps = new sbr_paths_s();
     ps->ctx = c, ps->trace = tr;
     retain(c), retain(tr);
@@ -1155,9 +1163,9 @@ sbr_status sbr_receive(sbr_context_t ctx, sbr_trace_t t, const double* rx_xyz, i
       ps->Nr = Nr;
       ps->coeff = radius_coeff;
       ps->alpha = alpha_rad > 0 ? alpha_rad : alpha_for(c, tr->N);
-      if (flags & SBR_IN_DEVICE) upload(ps->rx, rx_xyz, hrx.size(), flags, s);
-      else upload(ps->rx, hrx.data(), hrx.size(), 0, s);
-      run_receive(ps, hrx.data(), s);
+      if (flags & SBR_IN_DEVICE) upload(ps->rx, rx_xyz, (size_t)Nr * 3, flags, s);
+      else upload(ps->rx, rx_xyz, (size_t)Nr * 3, 0, s);
+      run_receive(ps, dev_prep ? nullptr : hrx.data(), s);
     } catch (...) {
       release(ps);
       throw;

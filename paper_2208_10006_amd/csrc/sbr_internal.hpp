@@ -313,6 +313,10 @@ struct BvhOut {
   // Morton codes instead of scene_lo / scene_hi (which may then be null)
   const float* bounds_dev = nullptr;
 };
+// Linear trees of up to kLbvhSmall primitives are built by one workgroup.
+// A root-to-leaf path has at most 41 internal nodes: along it the common
+// prefix of the (30-bit code, 11-bit index) keys grows at every node.
+constexpr int kLbvhSmall = 2048;
 int build_bvh(const float* box_lo, const float* box_hi, int64_t n, const float scene_lo[3],
               const float scene_hi[3], BvhOut out, hipStream_t s, bool linear = false);
 
@@ -351,7 +355,7 @@ constexpr int kCtrQueue = 0, kCtrOut = 256, kCtrDone = 512, kCtrWords = 1024;
 int64_t trace_counter_words(int K);
 
 // receive.hip
-void run_receive(sbr_paths_s* ps, const double* hrx, hipStream_t s);  // hrx: host copy of the Rx points
+void run_receive(sbr_paths_s* ps, const double* hrx, hipStream_t s);  // hrx: host copy of the Rx points (null for sets of up to kLbvhSmall, prepared on the device)
 
 // channel.hip
 struct ChannelArgs {
