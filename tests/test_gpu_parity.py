@@ -313,6 +313,11 @@ def test_error_paths(S, ctx):
     tr = S.sbr_trace(ctx, sc, w.tx, 8, 2)
     with pytest.raises(S.SbrError):
         S.sbr_receive(ctx, tr, w.tx)  # Rx on the Tx
+    bad_rx = np.concatenate([w.rx, w.rx + 0.5])
+    bad_rx[1, 2] = np.nan
+    with pytest.raises(S.SbrError) as e:
+        S.sbr_receive(ctx, tr, bad_rx)
+    assert "finite" in str(e.value)
     ps = S.sbr_receive(ctx, tr, w.rx)
     with pytest.raises(S.SbrError) as e:
         S.sbr_stats(ps)
@@ -414,6 +419,34 @@ def test_scene_build_batch_error_names_scene(S, ctx):
     ok = S.sbr_scene_build_batch(ctx, [w.tri for w in ws], [w.eps_r for w in ws], [w.sigma for w in ws],
                                  [w.rough for w in ws])
     assert len(ok) == 3
+
+
+def test_large_and_small_receiver_sets_agree(S, ctx):
+    """Receiver sets above 2,048 points are prepared on the host, smaller ones
+    on the device; a receiver's paths do not depend on the other receivers,
+    so receiving 2,100 points at once or in two halves gives the same
+    channel and statistics for every point.  The sort key keeps fewer hash
+    bits when there are more receivers, so paths of one receiver may be
+    summed in another order: equal up to FP64 rounding."""
+    banner("receiver sets across the device-preparation limit")
+    w = W.random_box_scene(51, n_boxes=10, n_rx=2100, N=24, K=2, freq=(28e9, 60e9))
+    sc = S.sbr_scene_build(ctx, w.tri, w.eps_r, w.sigma, w.rough)
+    tr = S.sbr_trace(ctx, sc, w.tx, w.geodesic_N, w.max_bounces)
+
+    def run(rx):
+        ps = S.sbr_receive(ctx, tr, rx)
+        H = np.zeros((len(w.freq), len(rx), 1), np.complex128)
+        S.sbr_channel(ctx, ps, w.freq, H_c128=H)
+        return H, S.sbr_stats(ps)
+
+    H_all, st_all = run(w.rx)
+    halves = [run(w.rx[:1050]), run(w.rx[1050:])]
+    H_halves = np.concatenate([h[0] for h in halves], axis=1)
+    np.testing.assert_allclose(H_all, H_halves, rtol=1e-12, atol=1e-14 * np.abs(H_all).max())
+    for k in range(3):
+        x = np.concatenate([h[1][k] for h in halves], axis=0)
+        np.testing.assert_allclose(st_all[k], x, rtol=1e-5, atol=1e-6 * np.abs(x).max())
+    assert np.any(np.abs(H_all) > 0)
 
 
 def test_receive_on_other_contexts_from_threads(S, ctx):
