@@ -230,6 +230,11 @@ sbr_status sbr_trace_work(sbr_trace_t tr, int64_t* node_visits, int64_t* tri_tes
  *   "trace_blocks_per_cu"  resident 256-thread blocks per CU of the persistent
  *                          bounce grid (1..32, default 4)
  *   "trace_chunk"          rays a wave takes from its queue per atomic (multiple of 64, <= 4096)
+ *   "trace_leaf_share"     leaves found during the closest-hit traversal wait until
+ *                          this many 64ths of the wave's tracing lanes hold one (or
+ *                          no lane can go on without a test) and are then tested
+ *                          together (1..64, default 40; 1: every traversal step
+ *                          tests the leaves it found)
  *   "replay_block"         threads per block of the capture replay (64..1024)
  *   "trace_graph"          1: the bounce loop of sbr_trace runs as a hipGraph built
  *                          once per (bounces, tree depth class) and replayed with

@@ -1,8 +1,9 @@
 """Autotuner for the trace launch parameters.
 
 Searches the persistent bounce grid (resident blocks per CU), the number of
-rays a wave takes from its XCD queue per atomic, and direct launches versus
-the cached hipGraph bounce loop, by timing real traces of the caller's
+rays a wave takes from its XCD queue per atomic, direct launches versus the
+cached hipGraph bounce loop, and the share of a wave's lanes that must hold a
+leaf before the wave tests its queued leaves, by timing real traces of the caller's
 problem with the library's live HIP-event timing.  Results are cached per
 (GPU architecture, problem class) in a JSON file so later runs reuse them.
 
@@ -11,6 +12,7 @@ Only launch parameters are tuned: every setting computes identical results
 """
 from __future__ import annotations
 
+import itertools
 import json
 import math
 import os
@@ -19,7 +21,8 @@ from typing import Dict, Iterable, Optional
 from . import sbr as S
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "sbr_mi355x", "tuning.json")
-GRID = {"trace_blocks_per_cu": (2, 4, 8), "trace_chunk": (64, 128, 256), "trace_graph": (0, 1)}
+GRID = {"trace_blocks_per_cu": (2, 4, 8), "trace_chunk": (64, 128, 256), "trace_graph": (0, 1),
+        "trace_leaf_share": (40, 56)}
 KEYS = tuple(GRID)
 
 
@@ -78,15 +81,15 @@ def autotune(ctx: S.Context, run, key: str, reps: int = 2, cache_path: Optional[
     best = None
     results = []
     saved = current(ctx)
-    for bpc in grid["trace_blocks_per_cu"]:
-        for chunk in grid["trace_chunk"]:
-            for graph in grid["trace_graph"]:
-                cfg = {"trace_blocks_per_cu": bpc, "trace_chunk": chunk, "trace_graph": graph}
-                apply(ctx, cfg)
-                ms = _time_trace(ctx, run, reps)
-                results.append({"config": cfg, "bounce_ms": ms})
-                if best is None or ms < best["bounce_ms"]:
-                    best = {"config": cfg, "bounce_ms": ms}
+    # keys the grid leaves out keep the context's current value
+    axes = [tuple(grid[k]) if k in grid else (saved[k],) for k in KEYS]
+    for values in itertools.product(*axes):
+        cfg = dict(zip(KEYS, values))
+        apply(ctx, cfg)
+        ms = _time_trace(ctx, run, reps)
+        results.append({"config": cfg, "bounce_ms": ms})
+        if best is None or ms < best["bounce_ms"]:
+            best = {"config": cfg, "bounce_ms": ms}
     apply(ctx, saved)
     apply(ctx, best["config"])
     entry = {"config": best["config"], "bounce_ms": best["bounce_ms"], "searched": results}

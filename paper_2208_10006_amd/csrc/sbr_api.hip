@@ -991,6 +991,7 @@ sbr_status sbr_trace(sbr_context_t ctx, sbr_scene_t scene, const double* tx_xyz,
       L.block = 256;
       L.grid = c->num_cus * c->tune.trace_blocks_per_cu;
       L.chunk = c->tune.trace_chunk;
+      L.leaf_share = c->tune.trace_leaf_share;
       hp_step.emplace("host:trace_launch");
       launch_trace(L, ra, rb, s);
     } catch (...) {
@@ -1050,8 +1051,8 @@ sbr_status sbr_trace_batch(sbr_context_t ctx, int32_t n, const sbr_scene_t* scen
       cnt.alloc((size_t)trace_counter_words(Kmax) * 4, s);
       stamps.alloc((size_t)2 * n * 8, s);
       unsigned long long* t_first = stamps.as<unsigned long long>();
-      launch_trace_batch(trs, c->num_cus * c->tune.trace_blocks_per_cu, c->tune.trace_chunk, ra, rb,
-                         cnt.as<uint32_t>(), t_first, t_first + n, s);
+      launch_trace_batch(trs, c->num_cus * c->tune.trace_blocks_per_cu, c->tune.trace_chunk,
+                         c->tune.trace_leaf_share, ra, rb, cnt.as<uint32_t>(), t_first, t_first + n, s);
       std::vector<unsigned long long> h(2 * (size_t)n);
       SBR_HIP(hipMemcpyAsync(h.data(), stamps.p, h.size() * 8, hipMemcpyDeviceToHost, s));
       SBR_HIP(hipStreamSynchronize(s));
@@ -1405,6 +1406,9 @@ sbr_status sbr_context_set_tuning(sbr_context_t ctx, const char* key, int32_t va
     } else if (k == "trace_chunk") {
       SBR_CHECK(value >= 64 && value <= 4096 && value % 64 == 0, SBR_E_INVALID_ARG, "trace_chunk = %d", value);
       c->tune.trace_chunk = value;
+    } else if (k == "trace_leaf_share") {
+      SBR_CHECK(value >= 1 && value <= 64, SBR_E_INVALID_ARG, "trace_leaf_share = %d", value);
+      c->tune.trace_leaf_share = value;
     } else if (k == "replay_block") {
       SBR_CHECK(value >= 64 && value <= 1024 && value % 64 == 0, SBR_E_INVALID_ARG, "replay_block = %d", value);
       c->tune.replay_block = value;
@@ -1427,6 +1431,7 @@ sbr_status sbr_context_get_tuning(sbr_context_t ctx, const char* key, int32_t* v
     const std::string k(key);
     if (k == "trace_blocks_per_cu") *value = c->tune.trace_blocks_per_cu;
     else if (k == "trace_chunk") *value = c->tune.trace_chunk;
+    else if (k == "trace_leaf_share") *value = c->tune.trace_leaf_share;
     else if (k == "replay_block") *value = c->tune.replay_block;
     else if (k == "trace_graph") *value = c->tune.trace_graph;
     else if (k == "bvh_ploc_max") *value = c->tune.bvh_ploc_max;

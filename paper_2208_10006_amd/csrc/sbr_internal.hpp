@@ -141,6 +141,7 @@ void prof_add(const char* name, double ms);
 struct Tuning {
   int trace_blocks_per_cu = 4; // resident 256-thread blocks per CU of the persistent grid
   int trace_chunk = 64;        // rays per wave per queue pull (64 or 128)
+  int trace_leaf_share = 40;   // 64ths of a wave's tracing lanes holding leaves before they are tested together
   int replay_block = 256;
   int trace_graph = 0;         // 1: replay the bounce loop as a cached hipGraph
   int bvh_ploc_max = 65536;    // scenes up to this many triangles are clustered with PLOC
@@ -335,13 +336,14 @@ struct TraceLaunch {
   int32_t* seq;
   uint32_t* counters;  // trace_counter_words(K): one kCtrWords block per bounce
   unsigned long long* work;  // node visits, triangle tests, or null (no counting)
-  int grid, block, chunk;
+  int grid, block, chunk, leaf_share;
 };
 void launch_trace(const TraceLaunch& L, void* ray_a, void* ray_b, hipStream_t s);
 // one persistent launch per bounce over the rays of all traces (their seq,
 // tx, N, K and scenes set); per-trace first/last wall-clock stamps
-void launch_trace_batch(const std::vector<sbr_trace_s*>& trs, int grid, int chunk, void* ray_a, void* ray_b,
-                        uint32_t* counters, unsigned long long* t_first, unsigned long long* t_last, hipStream_t s);
+void launch_trace_batch(const std::vector<sbr_trace_s*>& trs, int grid, int chunk, int leaf_share, void* ray_a,
+                        void* ray_b, uint32_t* counters, unsigned long long* t_first, unsigned long long* t_last,
+                        hipStream_t s);
 size_t trace_ray_bytes(int64_t NR);
 // FP32 triangles in leaf order: kTriVecs float4 per triangle, its three
 // vertices in each of the three cyclic axis orders (x y z | y z x | z x y),

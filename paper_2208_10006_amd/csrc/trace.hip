@@ -198,6 +198,7 @@ struct BounceParams {
   uint32_t* ctr;
   const uint32_t* ctr_in;
   int chunk;
+  int leaf_share;  // a wave tests its queued leaves once this many 64ths of its tracing lanes hold one
   unsigned long long* work;
   unsigned long long* t_first;  // batched: per-scene first/last wall-clock stamp
   unsigned long long* t_last;
@@ -382,48 +383,78 @@ __global__ __launch_bounds__(256) void k_bounce(const BounceParams P) {
       for (int b = 0; b < SD.n_big; ++b) tri_test(SD.big_off + b);
       float tn;
       if (SD.has_bvh && box_hit(SD.root[0], SD.root[1], SD.root[2], SD.root[3], SD.root[4], SD.root[5], thit, tn)) {
+        // Leaves are not tested where they are found: a step finds a leaf in
+        // a few lanes only, and a test site entered for them would idle the
+        // rest of the wave.  Each lane keeps the leaf pairs of up to two
+        // steps (a0 b0, a1 b1, in the order found) and keeps descending while
+        // its second pair slot is empty; the wave tests the queues together
+        // once `leaf_share` / 64 of its tracing lanes hold a leaf, or when no
+        // lane can take another step.  The closest hit does not change: a
+        // queued leaf only lets its lane visit nodes that an earlier test
+        // could have culled, and those hold no closer triangle.
         int sp = 0;
         int32_t node = 0;
+        bool trav = true;
+        int32_t a0 = -1, b0 = -1, a1 = -1, b1 = -1;
+        const int share = P.leaf_share;
         while (true) {
-          if (COUNT) ++n_node;
-          const float4 n0 = nodes[4 * node], n1 = nodes[4 * node + 1], n2 = nodes[4 * node + 2],
-                       n3 = nodes[4 * node + 3];
-          // the entry a pop would take, read while the node is in flight
-          // (slot 0 when the stack is empty: in bounds, and then unused)
-          const int32_t top = stk[kWave * (sp > 0 ? sp - 1 : 0)];
-          float tl, tr;
-          bool hl = box_hit(n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, thit, tl);
-          bool hr = box_hit(n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, thit, tr);
-          const int32_t cl = __float_as_int(n3.x), cr = __float_as_int(n3.y);
-          // leaf children are collected (left first) and tested at one site
-          // below, so lanes with a left and lanes with a right leaf share a pass
-          int32_t la = -1, lb = -1;
-          if (hl && cl < 0) {
-            la = ~cl;
-            hl = false;
-          }
-          if (hr && cr < 0) {
-            if (cr != cl) {
-              if (la < 0) la = ~cr;
-              else lb = ~cr;
+          if (trav && a1 < 0) {
+            if (COUNT) ++n_node;
+            const float4 n0 = nodes[4 * node], n1 = nodes[4 * node + 1], n2 = nodes[4 * node + 2],
+                         n3 = nodes[4 * node + 3];
+            // the entry a pop would take, read while the node is in flight
+            // (slot 0 when the stack is empty: in bounds, and then unused)
+            const int32_t top = stk[kWave * (sp > 0 ? sp - 1 : 0)];
+            float tl, tr;
+            bool hl = box_hit(n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, thit, tl);
+            bool hr = box_hit(n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, thit, tr);
+            const int32_t cl = __float_as_int(n3.x), cr = __float_as_int(n3.y);
+            int32_t la = -1, lb = -1;
+            if (hl && cl < 0) {
+              la = ~cl;
+              hl = false;
             }
-            hr = false;
+            if (hr && cr < 0) {
+              if (cr != cl) {
+                if (la < 0) la = ~cr;
+                else lb = ~cr;
+              }
+              hr = false;
+            }
+            // both hit: descend into the nearer, push the other; one hit:
+            // descend; none: pop (the decision is written as selects so that
+            // the stack read above is not deferred into a pop branch)
+            const bool both = hl && hr, none = !hl && !hr;
+            const bool lnear = tl <= tr;
+            if (both) stk[kWave * sp] = lnear ? cr : cl;
+            if (none && sp == 0) trav = false;
+            node = both ? (lnear ? cl : cr) : hl ? cl : hr ? cr : top;
+            sp += both ? 1 : (none && sp > 0) ? -1 : 0;
+            // the step's pair goes to the first empty pair slot; a slot is
+            // empty when its first entry is -1, so storing a step that found
+            // no leaf (la = -1) leaves the slot empty and needs no branch
+            const bool e0 = a0 < 0;
+            a1 = e0 ? a1 : la;
+            b1 = e0 ? b1 : lb;
+            a0 = e0 ? la : a0;
+            b0 = e0 ? lb : b0;
           }
-          // both hit: descend into the nearer, push the other; one hit:
-          // descend; none: pop (the decision is written as selects so that
-          // the stack read above is not deferred into a pop branch)
-          const bool both = hl && hr, none = !hl && !hr;
-          const bool lnear = tl <= tr;
-          if (both) stk[kWave * sp] = lnear ? cr : cl;
-          const bool done = none && sp == 0;
-          node = both ? (lnear ? cl : cr) : hl ? cl : hr ? cr : top;
-          sp += both ? 1 : (none && sp > 0) ? -1 : 0;
-          while (la >= 0) {
-            tri_test(la);
-            la = lb;
-            lb = -1;
+          const uint64_t held = __ballot(a0 >= 0);
+          const uint64_t going = __ballot(trav && a1 < 0);
+          if (going == 0 || __popcll(held) * 64 >= share * __popcll(__ballot(1))) {
+#pragma unroll 1
+            while (a0 >= 0) {
+              tri_test(a0);
+              // next in discovery order: b0 if the first pair held two
+              // leaves, else a1 (a pair's b is set only with its a)
+              const bool two = b0 >= 0;
+              a0 = two ? b0 : a1;
+              b0 = two ? a1 : b1;
+              a1 = two ? b1 : -1;
+              b1 = -1;
+            }
           }
-          if (done) break;
+          if (!trav && a0 < 0) break;
         }
       }
       if (hit >= 0) hit = __float_as_int(tri[(int64_t)kTriVecs * hit].w);  // original triangle id
@@ -604,6 +635,7 @@ void launch_trace(const TraceLaunch& T, void* ray_a, void* ray_b, hipStream_t s)
   P.n_first = T.NR;
   P.work = T.work;
   P.chunk = T.chunk;
+  P.leaf_share = T.leaf_share;
   const int depth = T.scene->bvh_depth;
   RaySoA A = soa_of(ray_a, T.NR), B = soa_of(ray_b, T.NR);
   std::vector<BounceParams> Pk(T.K + 1, P);
@@ -631,8 +663,9 @@ void launch_trace(const TraceLaunch& T, void* ray_a, void* ray_b, hipStream_t s)
   }
 }
 
-void launch_trace_batch(const std::vector<sbr_trace_s*>& trs, int grid, int chunk, void* ray_a, void* ray_b,
-                        uint32_t* counters, unsigned long long* t_first, unsigned long long* t_last, hipStream_t s) {
+void launch_trace_batch(const std::vector<sbr_trace_s*>& trs, int grid, int chunk, int leaf_share, void* ray_a,
+                        void* ray_b, uint32_t* counters, unsigned long long* t_first, unsigned long long* t_last,
+                        hipStream_t s) {
   const int n = (int)trs.size();
   std::vector<SceneDesc> tab(n);
   std::vector<int64_t> offs(n + 1);
@@ -662,6 +695,7 @@ void launch_trace_batch(const std::vector<sbr_trace_s*>& trs, int grid, int chun
   P.G = geo_tables();
   P.n_first = off;
   P.chunk = chunk;
+  P.leaf_share = leaf_share;
   P.t_first = t_first;
   P.t_last = t_last;
   RaySoA A = soa_of(ray_a, off), B = soa_of(ray_b, off);

@@ -503,6 +503,36 @@ def test_trace_graph_replays(S, ctx):
         S.sbr_context_set_tuning(ctx, "trace_graph", 0)
 
 
+@pytest.mark.parametrize("scene", ["boxes", "urban"])
+def test_leaf_share_keeps_hits(S, ctx, scene):
+    """Queued leaf tests only let a lane visit nodes an earlier test could have
+    culled, so every share (1: test at each step) traces the same hits."""
+    banner(f"leaf-test share, {scene}")
+    if scene == "boxes":
+        w = W.random_box_scene(61, n_boxes=40, n_rx=2, N=96, K=5)
+    else:
+        w = W.urban_canyon(N=96, n_rx=10)
+    sc = S.sbr_scene_build(ctx, w.tri, w.eps_r, w.sigma, w.rough)
+    old = S.sbr_context_get_tuning(ctx, "trace_leaf_share")
+    try:
+        ref = None
+        for share in (1, 8, 24, 40, 64):
+            S.sbr_context_set_tuning(ctx, "trace_leaf_share", share)
+            tr = S.sbr_trace(ctx, sc, w.tx, w.geodesic_N, w.max_bounces)
+            hits = S.sbr_trace_hits(tr)
+            if ref is None:
+                ref, segs = hits, S.sbr_trace_info(tr)["segments"]
+                assert np.count_nonzero(ref[:, 1] >= 0) > 0
+            else:
+                assert np.array_equal(hits, ref), f"share {share}"
+                assert S.sbr_trace_info(tr)["segments"] == segs
+    finally:
+        S.sbr_context_set_tuning(ctx, "trace_leaf_share", old)
+    for bad in (0, 65):
+        with pytest.raises(S.SbrError):
+            S.sbr_context_set_tuning(ctx, "trace_leaf_share", bad)
+
+
 def test_autotuner_picks_and_applies(S, ctx, tmp_path):
     banner("autotuner")
     from paper_2208_10006_amd import autotune as A
