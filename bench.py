@@ -398,12 +398,18 @@ def main():
                           "launches_per_step": bounce_launches / args.steps}}
     kernels.update(breakdown(S, ctx, lambda: step(S, ctx, w, d), exclude=("bounce",)))
 
-    # work counts for the dominant kernel (a separate, untimed trace)
+    # work counts for the dominant kernel (a separate, untimed trace), taken
+    # with every traversal step testing its own leaves: queued leaf tests let
+    # lanes visit nodes an earlier test could have culled, and that extra
+    # work is not part of the algorithm's count
+    share = S.sbr_context_get_tuning(ctx, "trace_leaf_share")
+    S.sbr_context_set_tuning(ctx, "trace_leaf_share", 1)
     S.sbr_context_count_work(ctx, True)
     sc = S.sbr_scene_build(ctx, d["tri"], d["eps"], d["sig"], d["rough"])
     tr = S.sbr_trace(ctx, sc, d["tx"], w.geodesic_N, w.max_bounces)
     work = S.sbr_trace_work(tr)
     S.sbr_context_count_work(ctx, False)
+    S.sbr_context_set_tuning(ctx, "trace_leaf_share", share)
     del sc, tr
     bounce_ms = kernels.get("bounce", {}).get("ms_per_step", float("nan"))
     traffic = committed_traffic(w.name)
