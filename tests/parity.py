@@ -32,7 +32,7 @@ def key_tuple(p, q, k, groups):
 
 
 @dataclass
-class GpuRun:
+class GpuResult:
     res: S.Result
     keys: list
     hits: np.ndarray
@@ -42,14 +42,14 @@ class GpuRun:
     trace_info: dict
 
 
-def gpu_run(ctx, w, alpha=0.0, coeff=None, pol_tx=0, pol_rx=0) -> GpuRun:
+def gpu_run(ctx, w, alpha=0.0, coeff=None, pol_tx=0, pol_rx=0) -> GpuResult:
     res = S.run_workload(ctx, w, alpha=alpha, coeff=coeff, pol_tx=pol_tx, pol_rx=pol_rx)
     rec = res.records
     keys = [key_tuple(r["tx"], r["rx"], r["order"], r["groups"]) for r in rec]
     hits = S.sbr_trace_hits(res.trace)
     ev = S.sbr_paths_events(res.paths)
     a = S.sbr_path_field(ctx, res.paths, w.freq, w.atm_db_per_m, w.atm_deg_per_m, pol_tx, pol_rx)
-    return GpuRun(res, keys, hits, ev, a, S.sbr_paths_info(res.paths), S.sbr_trace_info(res.trace))
+    return GpuResult(res, keys, hits, ev, a, S.sbr_paths_info(res.paths), S.sbr_trace_info(res.trace))
 
 
 @dataclass
@@ -85,7 +85,7 @@ def compare_hits(gpu_hits, ora_seq, ora_amb, ray_ids=None):
     return n, int(bad.sum()), int(excused.sum()), np.nonzero(bad)[0]
 
 
-def compare(w, gr: GpuRun, ora: O.FullResult, tri_group: np.ndarray, pol_tx=0, pol_rx=0) -> Report:
+def compare(w, gr: GpuResult, ora: O.FullResult, tri_group: np.ndarray, pol_tx=0, pol_rx=0) -> Report:
     rep = Report()
     K = w.max_bounces
     R = 10 * w.geodesic_N ** 2 + 2
