@@ -117,11 +117,14 @@ __global__ __launch_bounds__(1024) void k_replay_capture(const ReplayParams P) {
         return __builtin_amdgcn_rcpf(fabsf(v) > 1e-20f ? v : copysignf(1e-20f, v));
       };
       const float3 inv = make_float3(safe_inv(dir.x), safe_inv(dir.y), safe_inv(dir.z));
+      // slab distances of the inflated box, (lo - infl - org) * inv and
+      // (hi + infl - org) * inv, as one FMA each with per-segment constants
+      const float3 clo = make_float3(-(org.x + infl) * inv.x, -(org.y + infl) * inv.y, -(org.z + infl) * inv.z);
+      const float3 chi = make_float3(-(org.x - infl) * inv.x, -(org.y - infl) * inv.y, -(org.z - infl) * inv.z);
       auto box_hit = [&](float lx, float ly, float lz, float hx, float hy, float hz) {
-        lx -= infl, ly -= infl, lz -= infl, hx += infl, hy += infl, hz += infl;
-        const float t0x = (lx - org.x) * inv.x, t1x = (hx - org.x) * inv.x;
-        const float t0y = (ly - org.y) * inv.y, t1y = (hy - org.y) * inv.y;
-        const float t0z = (lz - org.z) * inv.z, t1z = (hz - org.z) * inv.z;
+        const float t0x = fmaf(lx, inv.x, clo.x), t1x = fmaf(hx, inv.x, chi.x);
+        const float t0y = fmaf(ly, inv.y, clo.y), t1y = fmaf(hy, inv.y, chi.y);
+        const float t0z = fmaf(lz, inv.z, clo.z), t1z = fmaf(hz, inv.z, chi.z);
         const float tmin = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
         const float tmx = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
         return tmin <= tmx * 1.0000004f;
