@@ -220,9 +220,8 @@ def batched_main(args):
 
     for i in range(args.warmup):
         scenes, trs = one_step()
+        del scenes, trs
     torch.cuda.synchronize()
-    segs = sum(S.sbr_trace_info(t)["segments"] for t in trs)
-    del scenes, trs
     S.sbr_profile_only(ctx, "bounce")
     S.sbr_profile_enable(ctx, True)
     torch.cuda.synchronize()
@@ -231,9 +230,12 @@ def batched_main(args):
     for i in range(args.steps):
         scenes, trs = one_step()
         lat += [S.sbr_trace_latency(t) for t in trs]
-        del scenes, trs
+        if i + 1 < args.steps:  # the last step's traces give the (fixed) segment count
+            del scenes, trs
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    segs = sum(S.sbr_trace_info(t)["segments"] for t in trs)
+    del scenes, trs
     bounce_ms, bounce_n = S.sbr_profile_query(ctx, "bounce")
     S.sbr_profile_enable(ctx, False)
     kernels = {"bounce": {"ms_per_step": bounce_ms / args.steps, "launches_per_step": bounce_n / args.steps}}
@@ -346,6 +348,9 @@ def main():
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding "
               "is a design note, not a measured path", file=sys.stderr)
         sys.exit(2)
+    if args.steps < 1 or args.warmup < 0:
+        print(f"--steps must be >= 1 and --warmup >= 0 (got {args.steps}, {args.warmup})", file=sys.stderr)
+        sys.exit(2)
 
     if args.workload == "batched_uneven":
         return batched_main(args)
@@ -369,13 +374,10 @@ def main():
     del sc0
     log(f"[bench] tuned launch: {tuned['config']} ({tuned['bounce_ms']:.3f} ms per trace)")
     for i in range(args.warmup):
-        sc, tr, ps = step(S, ctx, w, d)
+        handles = step(S, ctx, w, d)
+        del handles
         log(f"[bench] warmup {i} done")
     torch.cuda.synchronize()
-    info = S.sbr_trace_info(tr)
-    pinfo = S.sbr_paths_info(ps)
-    segments = info["segments"]
-    del sc, tr, ps
 
     # timed steps: live HIP-event timing of the dominant kernel only (two
     # event records per bounce launch), so the step time carries no
@@ -386,9 +388,15 @@ def main():
     t0 = time.perf_counter()
     for i in range(args.steps):
         handles = step(S, ctx, w, d)
-        del handles
+        if i + 1 < args.steps:  # the last step's handles give the (fixed) work counts
+            del handles
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    sc, tr, ps = handles
+    info = S.sbr_trace_info(tr)
+    pinfo = S.sbr_paths_info(ps)
+    segments = info["segments"]
+    del sc, tr, ps, handles
     bounce_ms_total, bounce_launches = S.sbr_profile_query(ctx, "bounce")
     S.sbr_profile_enable(ctx, False)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
