@@ -263,7 +263,8 @@ int orc_scene_groups(const double* tri, int T, const float* eps, const float* si
  * are skipped (the reflected ray leaves that plane).
  * Ambiguity flags (where an FP32 tracer may legitimately disagree):
  *   1 hit within 1e-5 (barycentric) of an edge of its triangle
- *   2 another triangle crossed within 1e-5 of its edges no farther than the hit
+ *   2 another triangle (not the hit) crossed within 1e-5 of its edges no
+ *     farther than the hit
  *   4 a second hit within 1e-5 relative in t
  *   8 grazing incidence |d.n| < 1e-5
  * ===================================================================== */
@@ -272,7 +273,11 @@ typedef struct { int tri; double t; double u, v; uint8_t amb; } hit_t;
 static hit_t closest_hit(const scene_t* S, v3 o, v3 d, int skip_plane) {
   hit_t h = {-1, INFINITY, 0, 0, 0};
   double tmin = 1e-12 * S->diag;
-  double t_edge = INFINITY;   /* nearest near-edge crossing of any triangle */
+  /* the two nearest near-edge crossings (distance and triangle): the flag
+   * concerns triangles other than the hit, so the second one stands in when
+   * the nearest is the hit triangle itself */
+  double t_edge = INFINITY, t_edge2 = INFINITY;
+  int edge_tri = -1;
   double t2 = INFINITY;       /* second-nearest hit */
   for (int t = 0; t < S->T; ++t) {
     if (skip_plane >= 0 && S->plane[t] == skip_plane) continue;
@@ -289,7 +294,10 @@ static hit_t closest_hit(const scene_t* S, v3 o, v3 d, int skip_plane) {
     double tt = dot(e2, qv) * inv;
     if (!(tt > tmin)) continue;
     double mb = fmin(fmin(u, v), 1.0 - u - v);
-    if (fabs(mb) < 1e-5 && tt < t_edge) t_edge = tt;
+    if (fabs(mb) < 1e-5) {
+      if (tt < t_edge) { t_edge2 = t_edge; t_edge = tt; edge_tri = t; }
+      else if (tt < t_edge2) t_edge2 = tt;
+    }
     if (mb >= 0.0) {
       if (tt < h.t) { t2 = h.t; h.t = tt; h.tri = t; h.u = u; h.v = v; }
       else if (tt < t2) t2 = tt;
@@ -298,7 +306,8 @@ static hit_t closest_hit(const scene_t* S, v3 o, v3 d, int skip_plane) {
   if (h.tri >= 0) {
     double mb = fmin(fmin(h.u, h.v), 1.0 - h.u - h.v);
     if (mb < 1e-5) h.amb |= 1;
-    if (t_edge <= h.t * (1.0 + 1e-5)) h.amb |= 2;
+    double t_other = edge_tri == h.tri ? t_edge2 : t_edge;
+    if (t_other <= h.t * (1.0 + 1e-5)) h.amb |= 2;
     if (t2 - h.t <= 1e-5 * h.t) h.amb |= 4;
     if (fabs(dot(d, S->n[h.tri])) < 1e-5) h.amb |= 8;
   } else if (t_edge < INFINITY) {
