@@ -180,6 +180,8 @@ typedef struct {
   int* gfirst;          /* lowest triangle of each group */
   int* gstart; int* gtri; /* CSR: triangles of each group */
   double diag;
+  v3 center;            /* centre of the scene's bounding box */
+  double* hgt;          /* [T][3] height of each triangle over the edge opposite vertex 0, 1, 2 */
 } scene_t;
 
 static int uf_find(int* p, int x) { while (p[x] != x) { p[x] = p[p[x]]; x = p[x]; } return x; }
@@ -192,6 +194,7 @@ static int scene_init(scene_t* S, const double* tri, int T, const float* eps, co
   S->T = T; S->tri = tri; S->eps = eps; S->sig = sig; S->rough = rough;
   if (T == 0) { S->gstart = calloc(1, sizeof(int)); return 0; }
   S->n = malloc(sizeof(v3) * T); S->c = malloc(sizeof(double) * T);
+  S->hgt = malloc(sizeof(double) * 3 * T);
   S->plane = malloc(sizeof(int) * T); S->group = malloc(sizeof(int) * T);
   v3 lo = mk(1e300, 1e300, 1e300), hi = mk(-1e300, -1e300, -1e300);
   for (int t = 0; t < T; ++t) {
@@ -203,8 +206,13 @@ static int scene_init(scene_t* S, const double* tri, int T, const float* eps, co
     v3 nn = crs(sub(tv(S, t, 1), tv(S, t, 0)), sub(tv(S, t, 2), tv(S, t, 0)));
     S->n[t] = unit(nn);
     S->c[t] = dot(S->n[t], tv(S, t, 0));
+    double twoA = nrm(nn);
+    S->hgt[3 * t] = twoA / nrm(sub(tv(S, t, 2), tv(S, t, 1)));
+    S->hgt[3 * t + 1] = twoA / nrm(sub(tv(S, t, 2), tv(S, t, 0)));
+    S->hgt[3 * t + 2] = twoA / nrm(sub(tv(S, t, 1), tv(S, t, 0)));
   }
   S->diag = nrm(sub(hi, lo));
+  S->center = scl(add(lo, hi), 0.5);
   int* pp = malloc(sizeof(int) * T);
   int* pg = malloc(sizeof(int) * T);
   for (int t = 0; t < T; ++t) pp[t] = pg[t] = t;
@@ -243,7 +251,7 @@ static int scene_init(scene_t* S, const double* tri, int T, const float* eps, co
 }
 
 static void scene_free(scene_t* S) {
-  free(S->n); free(S->c); free(S->plane); free(S->group); free(S->gfirst); free(S->gstart); free(S->gtri);
+  free(S->n); free(S->c); free(S->hgt); free(S->plane); free(S->group); free(S->gfirst); free(S->gstart); free(S->gtri);
 }
 
 int orc_scene_groups(const double* tri, int T, const float* eps, const float* sig, const float* rough,
@@ -262,13 +270,40 @@ int orc_scene_groups(const double* tri, int T, const float* eps, const float* si
  * to the lower triangle index; triangles in the plane of the previous hit
  * are skipped (the reflected ray leaves that plane).
  * Ambiguity flags (where an FP32 tracer may legitimately disagree):
- *   1 hit within 1e-5 (barycentric) of an edge of its triangle
- *   2 another triangle (not the hit) crossed within 1e-5 of its edges no
- *     farther than the hit
+ *   1 hit near an edge of its triangle
+ *   2 another triangle (not the hit) crossed near its edges no farther than
+ *     the hit
  *   4 a second hit within 1e-5 relative in t
  *   8 grazing incidence |d.n| < 1e-5
  * ===================================================================== */
 typedef struct { int tri; double t; double u, v; uint8_t amb; } hit_t;
+
+/* "Near an edge": within 1e-5 in barycentric terms, or within an absolute
+ * distance of the triangle's boundary that FP32 positions cannot resolve:
+ * 4e-6 (about 32 single-precision units in the last place) of the crossing
+ * point's distance from the scene centre plus the distance travelled to it.
+ * The second band matters on slivers (a 5 cm partition face is 5e-7 m wide
+ * in barycentric terms at 1e-5, below FP32 resolution at 15 m). */
+static double seg_dist(v3 p, v3 a, v3 b) {
+  v3 e = sub(b, a);
+  double s = dot(sub(p, a), e) / dot(e, e);
+  s = s < 0.0 ? 0.0 : (s > 1.0 ? 1.0 : s);
+  return nrm(sub(p, add(a, scl(e, s))));
+}
+static int near_edge(const scene_t* S, int t, v3 P, double tt, double u, double v) {
+  double b[3] = {1.0 - u - v, u, v};
+  double mb = fmin(fmin(b[0], b[1]), b[2]);
+  if (fabs(mb) < 1e-5) return 1;
+  double band = 4e-6 * (nrm(sub(P, S->center)) + tt);
+  /* the distance to an edge's line (|b_i| times the height over that edge)
+   * bounds the distance to the edge from below: skip the exact test when
+   * every line is farther than the band */
+  const double* h = S->hgt + 3 * t;
+  if (fabs(b[0]) * h[0] > band && fabs(b[1]) * h[1] > band && fabs(b[2]) * h[2] > band) return 0;
+  v3 a = tv(S, t, 0), bb = tv(S, t, 1), c = tv(S, t, 2);
+  double dmin = fmin(fmin(seg_dist(P, bb, c), seg_dist(P, c, a)), seg_dist(P, a, bb));
+  return dmin <= band;
+}
 
 static hit_t closest_hit(const scene_t* S, v3 o, v3 d, int skip_plane) {
   hit_t h = {-1, INFINITY, 0, 0, 0};
@@ -294,7 +329,7 @@ static hit_t closest_hit(const scene_t* S, v3 o, v3 d, int skip_plane) {
     double tt = dot(e2, qv) * inv;
     if (!(tt > tmin)) continue;
     double mb = fmin(fmin(u, v), 1.0 - u - v);
-    if (fabs(mb) < 1e-5) {
+    if (near_edge(S, t, add(o, scl(d, tt)), tt, u, v)) {
       if (tt < t_edge) { t_edge2 = t_edge; t_edge = tt; edge_tri = t; }
       else if (tt < t_edge2) t_edge2 = tt;
     }
@@ -304,8 +339,7 @@ static hit_t closest_hit(const scene_t* S, v3 o, v3 d, int skip_plane) {
     }
   }
   if (h.tri >= 0) {
-    double mb = fmin(fmin(h.u, h.v), 1.0 - h.u - h.v);
-    if (mb < 1e-5) h.amb |= 1;
+    if (near_edge(S, h.tri, add(o, scl(d, h.t)), h.t, h.u, h.v)) h.amb |= 1;
     double t_other = edge_tri == h.tri ? t_edge2 : t_edge;
     if (t_other <= h.t * (1.0 + 1e-5)) h.amb |= 2;
     if (t2 - h.t <= 1e-5 * h.t) h.amb |= 4;

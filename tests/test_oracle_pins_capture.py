@@ -325,3 +325,20 @@ def test_grazing_incidence(dn, flag):
     hit, t, amb = _trace_one([tri])
     assert hit == 0 and abs(t - 5.0) < 1e-6
     assert amb == flag, amb
+
+
+@pytest.mark.parametrize("gap,flag", [(1e-5, 1), (1e-4, 0)])
+def test_sliver_edge_band_is_absolute(gap, flag):
+    """On a sliver 1 cm wide the 1e-5 barycentric band is 1e-7 m, below what
+    FP32 positions resolve; the edge band also holds points within 4e-6 of
+    (distance from the scene centre + distance travelled) of the boundary,
+    here about 2e-5 m: a hit 1e-5 m inside the long edge is flagged, one
+    1e-4 m inside is not (barycentric 1e-3 and 1e-2, outside that band)."""
+    u, P, E1, E2 = _setup()
+    e1, e2 = E1 / 2.0, E2 / 2.0
+    # long edge along e2 through P - gap e1; the sliver spans 1 cm across
+    A = P - gap * e1 - 1.0 * e2
+    tri = np.array([A, A + 2.0 * e2, A + 0.01 * e1 + 1.0 * e2])
+    hit, t, amb = _trace_one([tri])
+    assert hit == 0 and abs(t - 5.0) < 1e-12
+    assert amb == flag, amb
