@@ -109,15 +109,18 @@ def test_scene_groups(S, ctx, which):
 
 
 # ------------------------------------------------------------------ full parity cases
-def _full_case(S, ctx, w, coeff=None, pol=(0, 0), exact_keys=False):
+def _full_case(S, ctx, w, coeff=None, pol=(0, 0), exact_keys=False, max_excused_ray_frac=None):
     from tests import parity as PT
     g, _, _ = O.scene_groups(w)
     gr = PT.gpu_run(ctx, w, coeff=coeff, pol_tx=pol[0], pol_rx=pol[1])
     ora = O.run(w, coeff=coeff)
     rep = PT.compare(w, gr, ora, g, pol_tx=pol[0], pol_rx=pol[1])
     print(rep)
-    PT.assert_report(rep, allow_excused=not exact_keys)
-    assert gr.trace_info["segments"] == ora.trace.segments or rep.hit_excused > 0
+    assert rep.common > 0, "nothing compared"
+    PT.assert_report(rep, allow_excused=not exact_keys,
+                     max_excused_ray_frac=PT.MAX_EXCUSED_RAY_FRAC if max_excused_ray_frac is None
+                     else max_excused_ray_frac)
+    PT.assert_segments(gr.trace_info["segments"], ora.trace.segments, rep, w.max_bounces)
     return gr, ora, rep
 
 
@@ -227,7 +230,10 @@ def test_duplicated_triangles(S, ctx):
     og, op, ng = O.scene_groups(w)
     assert np.array_equal(g, og) and np.array_equal(p, op)
     del sc
-    _full_case(S, ctx, w)
+    # every hit ties with its two copies (R21 flag 4), so either side may name
+    # any copy of a triangle: the face groups hit must agree
+    gr, ora, rep = _full_case(S, ctx, w)
+    assert rep.hit_same_group > 0
 
 
 def test_profile_only_times_one_class(S, ctx):
@@ -267,10 +273,113 @@ def test_urban_reduced_full(S, ctx):
 @pytest.mark.slow
 def test_office_subset_full(S, ctx):
     """Massive-MIMO office (5,004 triangles, 8x8 Rx UPA, 100 GHz) with two Tx
-    elements at a reduced density and 16 subcarriers, full oracle."""
-    banner("office 2 tx N=40 K=4")
-    w = W.massive_mimo_office(N=40, nf=16).subset_tx([0, 255])
-    _full_case(S, ctx, w)
+    elements at a reduced density (N = 80) and 16 subcarriers, full oracle; path gain,
+    RMS delay spread and mean angles on every one of the 128 links.  Two
+    elements trace in element-minor ray order (the order of every array)."""
+    from tests import parity as PT
+    banner("office 2 tx N=80 K=4")
+    # at N = 80 the sphere (about 0.15 m at the array) is small enough for
+    # paths to pass the partitions around the Rx array: every link has one
+    w = W.massive_mimo_office(N=80, nf=16).subset_tx([0, 255])
+    gr, ora, rep = _full_case(S, ctx, w)
+    assert rep.common >= 100, rep.common
+    n = PT.check_stats(S.sbr_stats(gr.res.paths), ora, rep, len(w.rx), len(w.tx))
+    assert n >= 100, n
+
+
+def test_large_receiver_set_against_oracle(S, ctx):
+    """3,000 receivers, above the 2,048 whose tree the device builds (so the
+    host-prepared receiver tree), and about 19,000 capture events, above the
+    12,288 keys of the one-workgroup sort (so the multi-pass radix sort),
+    against the oracle; statistics on every link.  The replay with 1,024
+    threads per block (its LDS stacks then need the block size cut) gives the
+    same paths and H."""
+    from tests import parity as PT
+    banner("random scene 71, 3000 Rx, N=40, K=3")
+    w = W.random_box_scene(71, n_boxes=20, n_rx=3000, N=40, K=3, freq=(28e9, 60e9))
+    gr, ora, rep = _full_case(S, ctx, w)
+    assert len(w.rx) > 2048 and gr.info["events"] > 12288, gr.info
+    n = PT.check_stats(S.sbr_stats(gr.res.paths), ora, rep, len(w.rx), len(w.tx))
+    assert n >= 2000, n
+    old = S.sbr_context_get_tuning(ctx, "replay_block")
+    try:
+        S.sbr_context_set_tuning(ctx, "replay_block", 1024)
+        ps = S.sbr_receive(ctx, gr.res.trace, w.rx, w.alpha, w.radius_coeff)
+        H = np.zeros_like(gr.res.H)
+        S.sbr_channel(ctx, ps, w.freq, w.atm_db_per_m, w.atm_deg_per_m, H_c128=H)
+    finally:
+        S.sbr_context_set_tuning(ctx, "replay_block", old)
+    assert S.sbr_paths_info(ps)["paths"] == gr.info["paths"]
+    np.testing.assert_allclose(H, gr.res.H, rtol=1e-12, atol=1e-14 * np.abs(gr.res.H).max())
+
+
+def test_event_capacity_retry_is_exact(S, ctx):
+    """A receive whose capture events overflow the first event buffer grows it
+    and replays again: the same events, paths and H, bit for bit."""
+    banner("capture-event retry")
+    w = W.random_box_scene(72, n_boxes=12, n_rx=40, N=40, K=3, freq=(28e9, 60e9))
+    ref = S.run_workload(ctx, w)
+    old = S.sbr_context_get_tuning(ctx, "receive_event_capacity")
+    try:
+        S.sbr_context_set_tuning(ctx, "receive_event_capacity", 64)
+        got = S.run_workload(ctx, w)
+    finally:
+        S.sbr_context_set_tuning(ctx, "receive_event_capacity", old)
+    assert S.sbr_paths_info(got.paths)["events"] > 64
+    assert S.sbr_paths_info(got.paths) == S.sbr_paths_info(ref.paths)
+    assert got.H.tobytes() == ref.H.tobytes()
+    assert got.records.tobytes() == ref.records.tobytes()
+
+
+def test_batched_scenes_against_oracle(S, ctx):
+    """Every problem of one batched launch (uneven scenes, one of them a
+    four-element array in element-minor order) against the oracle."""
+    from tests import parity as PT
+    banner("batched trace against the oracle")
+    arr = W.random_box_scene(83, n_boxes=10, n_rx=4, N=20, K=3, freq=(28e9,))
+    arr.tx = W.upa((0.0, 0.0, 6.0), 2, 0.5)
+    ws = [W.random_box_scene(81, n_boxes=15, n_rx=6, N=24, K=3, freq=(28e9, 140e9)),
+          W.tiny_room(N=24, K=2), arr,
+          W.random_box_scene(82, n_boxes=6, n_rx=3, N=17, K=5)]
+    scenes = [S.sbr_scene_build(ctx, w.tri, w.eps_r, w.sigma, w.rough) for w in ws]
+    trs = S.sbr_trace_batch(ctx, scenes, [w.tx for w in ws], [w.geodesic_N for w in ws],
+                            [w.max_bounces for w in ws])
+    for w, tr in zip(ws, trs):
+        print("[case] batched member", w.name, flush=True)
+        g, _, _ = O.scene_groups(w)
+        gr = PT.gpu_run(ctx, w, trace=tr)
+        ora = O.run(w)
+        rep = PT.compare(w, gr, ora, g)
+        print(rep)
+        assert rep.common > 0, "nothing compared"
+        PT.assert_report(rep)
+        PT.assert_segments(gr.trace_info["segments"], ora.trace.segments, rep, w.max_bounces)
+
+
+def test_trace_order_keeps_results(S, ctx):
+    """Element-minor and element-major ray positions trace the same rays:
+    identical hit chains (by global ray id), segments, events, paths and H."""
+    banner("trace order")
+    w = W.massive_mimo_office(N=24, nf=8).subset_tx([0, 1, 17, 200, 255])
+    old = S.sbr_context_get_tuning(ctx, "trace_order")
+    out = []
+    try:
+        for order in (0, 1):
+            S.sbr_context_set_tuning(ctx, "trace_order", order)
+            r = S.run_workload(ctx, w)
+            ev = S.sbr_paths_events(r.paths)
+            evs = sorted(zip(*[np.asarray(x).tolist() for x in ev]))
+            out.append((S.sbr_trace_hits(r.trace), S.sbr_trace_info(r.trace), evs, r.records, r.H))
+    finally:
+        S.sbr_context_set_tuning(ctx, "trace_order", old)
+    a, b = out
+    assert np.array_equal(a[0], b[0])
+    assert a[1] == b[1]
+    assert a[2] == b[2] and len(a[2]) > 0
+    assert a[3].tobytes() == b[3].tobytes()
+    assert a[4].tobytes() == b[4].tobytes()
+    with pytest.raises(S.SbrError):
+        S.sbr_context_set_tuning(ctx, "trace_order", 2)
 
 
 # ------------------------------------------------------------------ capacity
