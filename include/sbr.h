@@ -235,13 +235,23 @@ sbr_status sbr_trace_work(sbr_trace_t tr, int64_t* node_visits, int64_t* tri_tes
  *                          no lane can go on without a test) and are then tested
  *                          together (1..64, default 40; 1: every traversal step
  *                          tests the leaves it found)
- *   "replay_block"         threads per block of the capture replay (64..1024)
+ *   "replay_block"         threads per block of the capture replay (64..1024, a multiple
+ *                          of 64); a receive lowers it in whole waves when the
+ *                          traversal stacks of a block (deep receiver trees) would
+ *                          not fit 64 KiB of LDS
  *   "trace_graph"          1: the bounce loop of sbr_trace runs as a hipGraph built
  *                          once per (bounces, tree depth class) and replayed with
  *                          updated kernel arguments; 0 (default): direct launches
  *   "bvh_ploc_max"         scenes built later with up to this many triangles get a
  *                          PLOC-clustered BVH, larger ones the Morton-ordered LBVH
  *                          with an oversized-triangle list (0..65536, default 65536)
+ *   "trace_order"          1 (default): traces of several Tx elements keep their rays
+ *                          element-minor (neighbouring lanes follow one launch
+ *                          direction from neighbouring elements); 0: element-major.
+ *                          Results are the same either way
+ *   "receive_event_capacity"  first size of the capture-event buffer of a receive
+ *                          (>= 0; 0, the default: max(2^20, rays / 8)); a receive
+ *                          that overflows it grows it and replays again
  * Unknown keys or out-of-range values: SBR_E_INVALID_ARG. */
 sbr_status sbr_context_set_tuning(sbr_context_t ctx, const char* key, int32_t value);
 sbr_status sbr_context_get_tuning(sbr_context_t ctx, const char* key, int32_t* value);

@@ -23,6 +23,7 @@
 
 #include "sbr_device.hpp"
 #include "sbr_internal.hpp"
+#include "launch_rules.hpp"
 
 namespace sbr {
 namespace {
@@ -35,6 +36,7 @@ struct ReplayParams {
   int N, K, Nr;
   int64_t T;
   int64_t R, NR;
+  RayOrder ord;
   const double* tx;
   const int32_t* seq;
   const double4* tplane;
@@ -77,11 +79,13 @@ __global__ __launch_bounds__(1024) void k_replay_capture(const ReplayParams P) {
     if (sizeof(SE) == 2) return stk_base[((e >> 1) * kWave + lane) * 2 + (e & 1)];
     return stk_base[e * kWave + lane];
   };
-  const int64_t rid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t rid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // ray position
   if (rid >= P.NR) return;
-  const int p = (int)(rid / P.R);
+  int p;
+  int64_t r;
+  ray_of_pos(P.ord, rid, p, r);
   d3 o = ld3(P.tx + 3 * p);
-  d3 d = geo_dir(P.G, P.N, rid - (int64_t)p * P.R);
+  d3 d = geo_dir(P.G, P.N, r);
   double L = 0.0;
   d3 rc = mk3(P.rc[0], P.rc[1], P.rc[2]);
   double rrad = P.rrad;
@@ -195,7 +199,7 @@ __device__ inline uint64_t mix64(uint64_t h, uint64_t v) {
 }
 
 struct KeyParams {
-  const uint32_t* ev_ray;
+  const uint32_t* ev_ray;  // ray position of each capture
   const uint32_t* ev_qk;
   const int32_t* seq;
   const int32_t* tgroup;
@@ -203,7 +207,15 @@ struct KeyParams {
   int Nt;
   int64_t n;
   int hbits;  // hash bits below the segment index in the sort key
+  int emin;   // ray positions in element-minor order
 };
+
+__device__ inline int ev_tx(const KeyParams& P, uint32_t pos) {
+  int p;
+  int64_t r;
+  ray_of_pos(RayOrder{P.R, P.Nt, P.emin}, (int64_t)pos, p, r);
+  return p;
+}
 
 __device__ inline int ev_groups(const KeyParams& P, int64_t e, int32_t* g) {
   const uint32_t rid = P.ev_ray[e];
@@ -223,8 +235,7 @@ __global__ void k_event_keys(const KeyParams P, uint64_t* __restrict__ key, uint
   const int k = ev_groups(P, e, g);
   uint64_t h = mix64(0x5bd1e995ull, (uint64_t)k);
   for (int i = 0; i < k; ++i) h = mix64(h, (uint64_t)(uint32_t)g[i]);
-  const uint32_t rid = P.ev_ray[e];
-  const int64_t p = rid / P.R;
+  const int64_t p = ev_tx(P, P.ev_ray[e]);
   const uint64_t q = P.ev_qk[e] >> 5;
   const uint32_t h32 = (uint32_t)(h ^ (h >> 32));
   key[e] = ((q * (uint64_t)P.Nt + (uint64_t)p) << P.hbits) | (uint64_t)(h32 >> (32 - P.hbits));
@@ -408,8 +419,7 @@ __global__ __launch_bounds__(128) void k_rebuild(const RebuildParams P) {
   if (have) {
     e = P.key_event[i];
     k = ev_groups(P.kp, e, g);
-    const uint32_t rid = P.kp.ev_ray[e];
-    p = (int)(rid / P.kp.R);
+    p = ev_tx(P.kp, P.kp.ev_ray[e]);
     q = (int)(P.kp.ev_qk[e] >> 5);
     if (sub == 0) {
       int32_t* kk = P.key + i * (4 + P.K);
@@ -754,6 +764,7 @@ void run_receive(sbr_paths_s* ps, const double* hrx, hipStream_t s) {
   ReplayParams P{};
   P.G = geo_tables();
   P.N = tr->N, P.K = K, P.Nr = Nr, P.R = tr->R, P.NR = tr->NR;
+  P.ord = RayOrder{tr->R, (int32_t)tr->Nt, (int32_t)tr->emin};
   P.T = sc->T;
   P.tx = tr->tx.as<double>();
   P.seq = tr->seq.as<int32_t>();
@@ -768,7 +779,8 @@ void run_receive(sbr_paths_s* ps, const double* hrx, hipStream_t s) {
   P.rfac = ps->coeff * ps->alpha / std::sqrt(3.0);
   Buf cnt;
   cnt.alloc(16, s);
-  uint64_t cap = std::max<uint64_t>(1u << 20, (uint64_t)tr->NR / 8);
+  const int cap0 = ps->ctx->tune.receive_event_capacity;
+  uint64_t cap = cap0 > 0 ? (uint64_t)cap0 : std::max<uint64_t>(1u << 20, (uint64_t)tr->NR / 8);
   Buf& ev_ray = ps->ev_ray;
   Buf& ev_qk = ps->ev_qk;
   uint32_t n_ev = 0, hbad[2] = {0xffffffffu, 0xffffffffu};
@@ -780,11 +792,13 @@ void run_receive(sbr_paths_s* ps, const double* hrx, hipStream_t s) {
     P.ev_cap = cap;
     P.ev_ray = ev_ray.as<uint32_t>();
     P.ev_qk = ev_qk.as<uint32_t>();
-    const int rb = ps->ctx->tune.replay_block;
+    // the block's traversal stacks live in LDS: a deep receiver tree caps
+    // the block size so that they fit the 64 KiB a workgroup may allocate
+    const size_t stack_bytes = dev_prep ? sizeof(int16_t) * kRxSmallStack
+                                        : sizeof(int32_t) * (rdepth <= 16 ? 16 : rdepth <= 32 ? 32 : 64);
+    const int rb = replay_block_for(ps->ctx->tune.replay_block, stack_bytes);
     const unsigned g = nblk(tr->NR, rb);
-    const size_t lds = dev_prep ? (size_t)(rb / kWave) * kWave * sizeof(int16_t) * kRxSmallStack
-                                : (size_t)(rb / kWave) * kWave * sizeof(int32_t) *
-                                      (rdepth <= 16 ? 16 : rdepth <= 32 ? 32 : 64);
+    const size_t lds = (size_t)rb * stack_bytes;
     ::sbr::TimedLaunch tl_("replay_capture", s);
     if (dev_prep)
       hipLaunchKernelGGL((k_replay_capture<kRxSmallStack, int16_t, true>), dim3(g), dim3(rb), lds, s, P);
@@ -826,7 +840,7 @@ void run_receive(sbr_paths_s* ps, const double* hrx, hipStream_t s) {
   // six for up to 65,536 (rx, tx) pairs.
   const int hbits = std::max(16, 32 - sbits);
   KeyParams kp{ev_ray.as<uint32_t>(), ev_qk.as<uint32_t>(), tr->seq.as<int32_t>(), sc->tgroup.as<int32_t>(),
-               tr->R, tr->NR, Nt, E, hbits};
+               tr->R, tr->NR, Nt, E, hbits, tr->emin};
   Buf k1, k2, v1, v2, temp;
   k1.alloc(E * 8, s), k2.alloc(E * 8, s), v1.alloc(E * 4, s), v2.alloc(E * 4, s);
   temp.alloc(std::max(radix_sort_temp_bytes(E), scan_temp_bytes(E)), s);

@@ -409,9 +409,12 @@ __global__ __launch_bounds__(256) void k_scene_prep(const double* __restrict__ t
   for (int k = 0; k < 3; ++k) blo[3 * t + k] = mn[k], bhi[3 * t + k] = mx[k];
 }
 
-__global__ void k_hits_out(const int32_t* __restrict__ seq, int64_t NR, int K, int32_t* __restrict__ out) {
+// hit chains by global ray id: thread = ray position, row = its global id
+__global__ void k_hits_out(const int32_t* __restrict__ seq, int64_t NR, int K, RayOrder ord,
+                           int32_t* __restrict__ out) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= NR) return;
+  const int64_t g = rid_of_pos(ord, r);
   bool ended = false;
   for (int k = 0; k <= K; ++k) {
     int32_t v = -2;
@@ -419,7 +422,7 @@ __global__ void k_hits_out(const int32_t* __restrict__ seq, int64_t NR, int K, i
       v = seq[(int64_t)k * NR + r];
       if (v < 0) ended = true;
     }
-    out[r * (K + 1) + k] = v;
+    out[g * (K + 1) + k] = v;
   }
 }
 
@@ -968,6 +971,7 @@ sbr_status sbr_trace(sbr_context_t ctx, sbr_scene_t scene, const double* tx_xyz,
     retain(c), retain(sc);
     try {
       tr->Nt = Nt, tr->N = N, tr->K = K, tr->R = R, tr->NR = (int64_t)Nt * R;
+      tr->emin = Nt > 1 && c->tune.trace_order == 1;
       tr->h_tx = htx;
       // a device-resident input is copied on the device (no second host round trip)
       if (flags & SBR_IN_DEVICE) upload(tr->tx, tx_xyz, tr->h_tx.size(), flags, s);
@@ -979,6 +983,7 @@ sbr_status sbr_trace(sbr_context_t ctx, sbr_scene_t scene, const double* tx_xyz,
       TraceLaunch L{};
       L.ctx = c;
       L.scene = sc, L.tx = tr->tx.as<double>(), L.Nt = Nt, L.N = N, L.K = K, L.R = R, L.NR = tr->NR;
+      L.emin = tr->emin;
       L.seq = tr->seq.as<int32_t>();
       L.counters = tr->counters.as<uint32_t>();
       L.work = nullptr;
@@ -1031,6 +1036,7 @@ sbr_status sbr_trace_batch(sbr_context_t ctx, int32_t n, const sbr_scene_t* scen
         trs.push_back(tr);
         tr->Nt = Nt[i], tr->N = Nv[i], tr->K = Kv[i], tr->R = 10LL * Nv[i] * Nv[i] + 2;
         tr->NR = (int64_t)Nt[i] * tr->R;
+        tr->emin = Nt[i] > 1 && c->tune.trace_order == 1;
         tr->h_tx = htx;
         tr->batched = true;
         tr->seq.alloc((size_t)(tr->K + 1) * tr->NR * 4, s);
@@ -1120,7 +1126,7 @@ sbr_status sbr_trace_hits(sbr_trace_t t, int32_t* seq, uint32_t flags) {
       dst = tmp.as<int32_t>();
     }
     { ::sbr::TimedLaunch tl_("misc", s); hipLaunchKernelGGL(k_hits_out, dim3(nblk(tr->NR, 256)), dim3(256), 0, s, tr->seq.as<int32_t>(), tr->NR, tr->K,
-                       dst); }
+                       RayOrder{tr->R, (int32_t)tr->Nt, (int32_t)tr->emin}, dst); }
     SBR_LAUNCH_CHECK();
     if (!(flags & SBR_OUT_DEVICE)) {
       SBR_HIP(hipMemcpyAsync(seq, dst, n * 4, hipMemcpyDeviceToHost, s));
@@ -1206,8 +1212,10 @@ sbr_status sbr_paths_events(sbr_paths_t p, int64_t capacity, uint32_t* ray, int3
       SBR_HIP(hipMemcpyAsync(qk.data(), ps->ev_qk.p, n * 4, hipMemcpyDeviceToHost, s));
       SBR_HIP(hipStreamSynchronize(s));
     }
+    const sbr_trace_s* tr = ps->trace;
+    const RayOrder ord{tr->R, (int32_t)tr->Nt, (int32_t)tr->emin};
     for (int64_t i = 0; i < n; ++i) {
-      if (ray) ray[i] = r[i];
+      if (ray) ray[i] = (uint32_t)rid_of_pos(ord, (int64_t)r[i]);
       if (rx) rx[i] = (int32_t)(qk[i] >> 5);
       if (k) k[i] = (int32_t)(qk[i] & 31u);
     }
@@ -1418,6 +1426,12 @@ sbr_status sbr_context_set_tuning(sbr_context_t ctx, const char* key, int32_t va
     } else if (k == "bvh_ploc_max") {
       SBR_CHECK(value >= 0 && value <= kBvhPlocMax, SBR_E_INVALID_ARG, "bvh_ploc_max = %d", value);
       c->tune.bvh_ploc_max = value;
+    } else if (k == "trace_order") {
+      SBR_CHECK(value == 0 || value == 1, SBR_E_INVALID_ARG, "trace_order = %d", value);
+      c->tune.trace_order = value;
+    } else if (k == "receive_event_capacity") {
+      SBR_CHECK(value >= 0, SBR_E_INVALID_ARG, "receive_event_capacity = %d", value);
+      c->tune.receive_event_capacity = value;
     } else {
       SBR_CHECK(false, SBR_E_INVALID_ARG, "unknown tuning key '%s'", key);
     }
@@ -1435,6 +1449,8 @@ sbr_status sbr_context_get_tuning(sbr_context_t ctx, const char* key, int32_t* v
     else if (k == "replay_block") *value = c->tune.replay_block;
     else if (k == "trace_graph") *value = c->tune.trace_graph;
     else if (k == "bvh_ploc_max") *value = c->tune.bvh_ploc_max;
+    else if (k == "trace_order") *value = c->tune.trace_order;
+    else if (k == "receive_event_capacity") *value = c->tune.receive_event_capacity;
     else SBR_CHECK(false, SBR_E_INVALID_ARG, "unknown tuning key '%s'", key);
   });
 }

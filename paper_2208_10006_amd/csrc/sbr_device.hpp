@@ -75,6 +75,37 @@ __device__ inline d3 geo_dir(const GeoTables& G, int N, int64_t id) {
   return normalize(a + (b - a) * wi + (c - a) * wj);
 }
 
+// ----------------------------------------------------------------- ray positions
+// A trace keeps its rays (hit chain, ray buffers, replay threads) in one of
+// two orders.  Element-major: position i is direction i % R of element i / R.
+// Element-minor, for arrays of several elements: position i is direction
+// i / Nt of element i % Nt, so the 64 lanes of a wave follow one launch
+// direction from 64 neighbouring elements -- nearly parallel rays a few
+// millimetres apart that visit the same tree nodes and mostly hit the same
+// triangles.  Outside the library a ray is always named by its global id
+// p R + r, whatever the order.
+struct RayOrder {
+  int64_t R;   // rays per element
+  int32_t Nt;  // elements
+  int32_t emin;  // 1: element-minor
+};
+__host__ __device__ inline void ray_of_pos(const RayOrder& o, int64_t pos, int& p, int64_t& r) {
+  if (o.emin) {
+    const int64_t q = pos / o.Nt;
+    p = (int)(pos - q * o.Nt);
+    r = q;
+  } else {
+    p = (int)(pos / o.R);
+    r = pos - (int64_t)p * o.R;
+  }
+}
+__host__ __device__ inline int64_t rid_of_pos(const RayOrder& o, int64_t pos) {
+  int p;
+  int64_t r;
+  ray_of_pos(o, pos, p, r);
+  return (int64_t)p * o.R + r;
+}
+
 // ----------------------------------------------------------------- FP64 ray step
 // Exact continuation of a ray whose FP32 traversal selected a triangle with
 // plane (n, c): the hit distance is re-evaluated in FP64 on that plane, so the

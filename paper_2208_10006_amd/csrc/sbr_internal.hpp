@@ -145,6 +145,8 @@ struct Tuning {
   int replay_block = 256;
   int trace_graph = 0;         // 1: replay the bounce loop as a cached hipGraph
   int bvh_ploc_max = 65536;    // scenes up to this many triangles are clustered with PLOC
+  int trace_order = 1;         // 1: element-minor ray positions for traces of several elements (RayOrder)
+  int receive_event_capacity = 0;  // initial capture-event capacity of a receive; 0: max(2^20, rays / 8)
 };
 
 // An instantiated bounce-loop graph: init kernels + one kernel node per bounce,
@@ -238,6 +240,7 @@ struct sbr_trace_s : sbr::Handle {
   sbr_context_s* ctx = nullptr;
   sbr_scene_s* scene = nullptr;
   int Nt = 0, N = 0, K = 0;
+  int emin = 0;  // ray positions in element-minor order (RayOrder)
   int64_t R = 0, NR = 0;
   std::vector<double> h_tx;
   sbr::Buf tx;      // double[Nt][3]
@@ -332,6 +335,7 @@ struct TraceLaunch {
   const sbr_scene_s* scene;
   const double* tx;
   int Nt, N, K;
+  int emin;
   int64_t R, NR;
   int32_t* seq;
   uint32_t* counters;  // trace_counter_words(K): one kCtrWords block per bounce

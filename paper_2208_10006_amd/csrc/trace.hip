@@ -180,7 +180,8 @@ struct SceneDesc {
   int has_bvh, N, K, n_big;
   int big_off, pad;       // oversized triangles: tri entries big_off .. big_off + n_big - 1
   double cx, cy, cz;      // FP32 frame centre
-  int64_t R, NR, ray_off; // rays per element, rays of the scene, first global ray id
+  int64_t R, NR, ray_off; // rays per element, rays of the scene, first position of the scene
+  int32_t Nt, emin;       // elements; 1: element-minor ray positions (RayOrder)
 };
 
 struct BounceParams {
@@ -276,7 +277,7 @@ __global__ __launch_bounds__(256) void k_bounce(const BounceParams P) {
     // ------------------------------------------------ load / generate the FP64 ray
     d3 o = mk3(0, 0, 0), d = mk3(0, 0, 1);
     double L = 0.0;
-    uint32_t rid = 0;  // global ray id
+    uint32_t rid = 0;  // ray position (over all scenes of a batch)
     int32_t prev = -1;
     if (active) {
       if (first) {
@@ -304,9 +305,11 @@ __global__ __launch_bounds__(256) void k_bounce(const BounceParams P) {
     }
     const bool last = P.k == SD.K;
     if (active && first) {
-      const int p = (int)(lrid / (uint64_t)SD.R);
+      int p;
+      int64_t r;
+      ray_of_pos(RayOrder{SD.R, SD.Nt, SD.emin}, (int64_t)lrid, p, r);
       o = ld3(SD.tx + 3 * p);
-      d = geo_dir(P.G, SD.N, (int64_t)(lrid - (uint64_t)p * SD.R));
+      d = geo_dir(P.G, SD.N, r);
     }
     // ------------------------------------------------ FP32 closest hit
     int32_t hit = -1;  // leaf (sorted) index
@@ -499,8 +502,8 @@ __global__ __launch_bounds__(256) void k_bounce(const BounceParams P) {
   }
 }
 
-SceneDesc scene_desc(const sbr_scene_s* sc, const double* tx, int N, int K, int64_t R, int64_t NR, int32_t* seq,
-                     int64_t ray_off) {
+SceneDesc scene_desc(const sbr_scene_s* sc, const double* tx, int Nt, int emin, int N, int K, int64_t R, int64_t NR,
+                     int32_t* seq, int64_t ray_off) {
   SceneDesc D{};
   D.has_bvh = sc->n_bvh > 0;
   D.n_big = sc->n_big;
@@ -513,6 +516,7 @@ SceneDesc scene_desc(const sbr_scene_s* sc, const double* tx, int N, int K, int6
   D.cx = sc->center[0], D.cy = sc->center[1], D.cz = sc->center[2];
   D.tx = tx;
   D.N = N, D.K = K, D.R = R, D.NR = NR, D.seq = seq, D.ray_off = ray_off;
+  D.Nt = Nt, D.emin = emin;
   return D;
 }
 
@@ -629,7 +633,7 @@ void launch_trace_graph(const TraceLaunch& T, const BounceParams* P, int nP, hip
 
 void launch_trace(const TraceLaunch& T, void* ray_a, void* ray_b, hipStream_t s) {
   BounceParams P{};
-  P.one = scene_desc(T.scene, T.tx, T.N, T.K, T.R, T.NR, T.seq, 0);
+  P.one = scene_desc(T.scene, T.tx, T.Nt, T.emin, T.N, T.K, T.R, T.NR, T.seq, 0);
   P.n_scenes = 1;
   P.G = geo_tables();
   P.n_first = T.NR;
@@ -673,7 +677,8 @@ void launch_trace_batch(const std::vector<sbr_trace_s*>& trs, int grid, int chun
   int depth = 1, Kmax = 0;
   for (int i = 0; i < n; ++i) {
     sbr_trace_s* t = trs[i];
-    tab[i] = scene_desc(t->scene, t->tx.as<double>(), t->N, t->K, t->R, t->NR, t->seq.as<int32_t>(), off);
+    tab[i] = scene_desc(t->scene, t->tx.as<double>(), t->Nt, t->emin, t->N, t->K, t->R, t->NR, t->seq.as<int32_t>(),
+                        off);
     offs[i] = off;
     off += t->NR;
     depth = std::max(depth, t->scene->bvh_depth);
