@@ -1,11 +1,14 @@
 #!/usr/bin/env python3
 """Throughput of the SBR hot path on one MI355X: traced ray-segments/s.
 
-One step = the whole path over one synthetic urban-canyon workload, inputs
-already resident in HBM: scene build (face groups + BVH), launch + trace
+One step = the whole path over one synthetic workload, inputs already
+resident in HBM: scene build (face groups + BVH), launch + trace
 (breadth-first bounce loop), reception + path extraction (capture, dedup,
-exact image-method rebuild), channel (H[f, Nr, Nt] in FP64, complex64 out) and
-per-link statistics (path gain, RMS delay spread, mean angles).
+exact image-method rebuild), channel (H[f, Nr, Nt] in FP64, complex64 out),
+per-link statistics (path gain, RMS delay spread, mean angles) and, for
+arrays at both ends, MIMO capacity.  The default workload is the largest
+single-GPU one: the massive-MIMO office (256-element Tx UPA x 998,562 rays,
+64-element Rx UPA, K = 4, 1,024 subcarriers).
 
 Prints one JSON line with the metric, a roofline entry for the dominant
 kernel (live HIP-event timing inside the library) and the CPU oracle timed on
@@ -21,8 +24,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# FP32 arithmetic per BVH node visit (two slab tests) and per watertight
-# ray-triangle test, counted from the traversal source
+# Algorithmic work of one traced segment (one closest-hit query of one ray
+# at one bounce): read the ray (40 B), write the continued ray (40 B) and the
+# hit (8 B); the binding roofline of the trace is HBM bandwidth on this
+# stream.  VALU work: about 24 operations per BVH node visit (two slab tests
+# with a precomputed reciprocal direction) and 40 per watertight triangle
+# test, with visit counts from a counting trace.
+SEG_BYTES = 88
+OPS_PER_NODE = 24
+OPS_PER_TRI = 40
+# the same work counted instruction by instruction from the traversal source
 FLOP_PER_NODE = 50
 FLOP_PER_TRI = 41
 PEAK_FP32_TFLOPS = 157.3
@@ -77,7 +88,8 @@ def committed_traffic(workload):
     return (rec["fetch_bytes_per_step"] + rec["write_bytes_per_step"]) / rec["launches_per_step"]
 
 
-KERNEL_CLASSES = ["bounce", "replay_capture", "rebuild", "channel", "keys", "sort", "scan", "order", "bvh", "stats",
+KERNEL_CLASSES = ["bounce", "replay_capture", "rebuild", "channel", "capacity", "keys", "sort", "scan", "order", "bvh",
+                  "stats",
                   "misc", "alpha", "host:scene_build", "host:scene_inputs", "host:face_groups", "host:scene_upload",
                   "host:rx_tree", "host:receive", "host:trace_setup", "host:trace_launch"]
 
@@ -334,7 +346,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="urban_canyon")
+    ap.add_argument("--workload", default="massive_mimo_office")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--scenes", type=int, default=64, help="batched_uneven: number of scenes")
@@ -420,15 +432,28 @@ def main():
     S.sbr_context_set_tuning(ctx, "trace_leaf_share", share)
     del sc, tr
     bounce_ms = kernels.get("bounce", {}).get("ms_per_step", float("nan"))
+    launches = kernels.get("bounce", {}).get("launches_per_step", float("nan"))
     traffic = committed_traffic(w.name)
+    # HBM roofline on the algorithmic segment stream: bytes per launch over
+    # the average launch time (both per step here, same ratio)
+    gbs = SEG_BYTES * segments / (bounce_ms * 1e-3) / 1e9
+    ops = OPS_PER_NODE * work["node_visits"] + OPS_PER_TRI * work["tri_tests"]
+    valu = ops / (bounce_ms * 1e-3) / 1e12
     flop = FLOP_PER_NODE * work["node_visits"] + FLOP_PER_TRI * work["tri_tests"]
-    achieved = flop / (bounce_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
+    roofline = {"bound": "hbm", "achieved": round(gbs, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic,
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "algorithmic_bytes_per_launch": SEG_BYTES * segments / launches,
+                "bytes_per_segment": SEG_BYTES,
                 "kernel": "k_bounce (closest-hit traversal + FP64 reflect + ballot compaction)",
-                "node_visits_per_step": work["node_visits"], "tri_tests_per_step": work["tri_tests"],
-                "ms_per_step": round(bounce_ms, 3)}
+                "segments_per_step": segments, "launches_per_step": launches, "ms_per_step": round(bounce_ms, 3),
+                "valu": {"achieved": round(valu, 3), "peak": PEAK_FP32_TFLOPS, "unit": "Tops/s",
+                         "frac": round(valu / PEAK_FP32_TFLOPS, 4), "ops_per_node": OPS_PER_NODE,
+                         "ops_per_tri": OPS_PER_TRI, "node_visits_per_step": work["node_visits"],
+                         "tri_tests_per_step": work["tri_tests"]},
+                "valu_source_count": {"achieved": round(flop / (bounce_ms * 1e-3) / 1e12, 3),
+                                      "frac": round(flop / (bounce_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4),
+                                      "flop_per_node": FLOP_PER_NODE, "flop_per_tri": FLOP_PER_TRI}}
 
     out = {"metric": "traced ray-segments/s", "value": value, "unit": "ray-segments/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,

@@ -357,6 +357,119 @@ __global__ __launch_bounds__(256) void k_cap_mean(const double* __restrict__ cf,
   }
 }
 
+// Capacity for n = min(Nr, Nt) <= kCapRegN with every matrix in registers
+// (block per frequency, 256 threads, no work buffer).  Thread t owns the
+// 4 x 4 tile (ti, tj) = (t / 16, t % 16) of the 64 x 64 matrices, the
+// problem padded with zero rows (whose pivots are 1 and add log2 1 = 0).
+//  1. Gram: W = s^2 X X^H with X = H_f (Nt >= Nr) or H_f^T; X is staged in
+//     LDS kCapChunk columns at a time and every thread accumulates its tile
+//     in FP64.  For Nt < Nr this forms the conjugate of H^H H, which has the
+//     same determinant.
+//  2. For every SNR: M = I + (SNR / Nt) W and its LDL^H factorisation by
+//     right-looking elimination: at step j the owners of column j publish it
+//     to LDS (double-buffered, one barrier per step), every thread updates
+//     its entries below and right of the pivot, M_il -= M_ij conj(M_lj) / d_j,
+//     and log2 det M = sum_j log2 d_j.
+constexpr int kCapRegN = 64;
+constexpr int kCapChunk = 32;
+constexpr int kCapSnrMax = 64;  // SNR values passed by value
+struct CapSnr {
+  double db[kCapSnrMax];
+};
+
+__global__ __launch_bounds__(256) void k_cap_logdet_reg(const float2* __restrict__ H, int Nr, int Nt,
+                                                        const double* __restrict__ scale2,
+                                                        const double* __restrict__ snr_dev, const CapSnr snr_val,
+                                                        int Nsnr, double* __restrict__ cf) {
+  const int f = blockIdx.x, Nf = gridDim.x;
+  const int n = Nr <= Nt ? Nr : Nt;
+  const int m = Nr <= Nt ? Nt : Nr;
+  const bool rows = Nt >= Nr;
+  const int t = threadIdx.x, ti = t >> 4, tj = t & 15;
+  __shared__ float2 xs[kCapChunk][kCapRegN + 2];  // X chunk by column; +2 keeps 16-byte rows off one bank
+  __shared__ double2 colb[2][kCapRegN];
+  const float2* Hf = H + (int64_t)f * Nr * Nt;
+  double2 w[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) w[i][j] = make_double2(0.0, 0.0);
+  for (int c0 = 0; c0 < m; c0 += kCapChunk) {
+    const int nc = m - c0 < kCapChunk ? m - c0 : kCapChunk;
+    __syncthreads();
+    for (int e = t; e < kCapChunk * kCapRegN; e += 256) {
+      int r, c;
+      if (rows) r = e / kCapChunk, c = e - r * kCapChunk;  // X[r][c0 + c] = H[r][c0 + c]: along c
+      else c = e / kCapRegN, r = e - c * kCapRegN;         // X[r][c0 + c] = H[c0 + c][r]: along r
+      float2 v = make_float2(0.0f, 0.0f);
+      if (r < n && c < nc) v = rows ? Hf[(int64_t)r * Nt + c0 + c] : Hf[(int64_t)(c0 + c) * Nt + r];
+      xs[c][r] = v;
+    }
+    __syncthreads();
+    for (int c = 0; c < nc; ++c) {
+      double2 a[4], b[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float2 x = xs[c][4 * ti + k], y = xs[c][4 * tj + k];
+        a[k] = make_double2(x.x, x.y);
+        b[k] = make_double2(y.x, y.y);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {  // w += a_i conj(b_j)
+          w[i][j].x += a[i].x * b[j].x + a[i].y * b[j].y;
+          w[i][j].y += a[i].y * b[j].x - a[i].x * b[j].y;
+        }
+    }
+  }
+  const double s2 = *scale2;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) w[i][j] = make_double2(w[i][j].x * s2, w[i][j].y * s2);
+  for (int si = 0; si < Nsnr; ++si) {
+    const double g = pow(10.0, (snr_dev ? snr_dev[si] : snr_val.db[si]) / 10.0) / Nt;
+    double2 M[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        M[i][j] = make_double2((4 * ti + i == 4 * tj + j ? 1.0 : 0.0) + g * w[i][j].x, g * w[i][j].y);
+    double lsum = 0.0;
+    for (int jb = 0; jb < kCapRegN / 4; ++jb) {
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int j = 4 * jb + jj;
+        double2* buf = colb[j & 1];
+        if (tj == jb) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) buf[4 * ti + i] = M[i][jj];
+        }
+        __syncthreads();
+        const double d = buf[j].x;
+        if (t == 0) lsum += log2(d);
+        const double inv = 1.0 / d;
+        double2 ci[4], cl[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) ci[k] = buf[4 * ti + k], cl[k] = buf[4 * tj + k];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int l = 0; l < 4; ++l) {
+            if (4 * ti + i > j && 4 * tj + l > j) {  // M_il -= c_i conj(c_l) / d
+              const double re = (ci[i].x * cl[l].x + ci[i].y * cl[l].y) * inv;
+              const double im = (ci[i].y * cl[l].x - ci[i].x * cl[l].y) * inv;
+              M[i][l].x -= re;
+              M[i][l].y -= im;
+            }
+          }
+      }
+    }
+    if (t == 0) cf[(int64_t)si * Nf + f] = lsum;
+  }
+}
+
 FieldArgs field_args(const ChannelArgs& a) { return FieldArgs{a.freq, a.atm_db, a.atm_deg, a.Nf, a.pol_tx, a.pol_rx}; }
 
 }  // namespace
@@ -402,13 +515,18 @@ void run_capacity(const float2* H, int Nf, int Nr, int Nt, const double* snr_db,
   Buf frob, sc, work, cf;
   frob.alloc((size_t)Nf * 8, s);
   sc.alloc(8, s);
-  work.alloc((size_t)Nf * 2 * n * n * sizeof(double2), s);
   cf.alloc((size_t)Nf * Nsnr * 8, s);
   { ::sbr::TimedLaunch tl_("capacity", s); hipLaunchKernelGGL(k_cap_frob, dim3(Nf), dim3(256), 0, s, H, Nr, Nt, frob.as<double>()); }
   { ::sbr::TimedLaunch tl_("capacity", s); hipLaunchKernelGGL(k_cap_scale, dim3(1), dim3(256), 0, s, frob.as<double>(), Nf, Nr, Nt, normalize,
                      sc.as<double>()); }
-  { ::sbr::TimedLaunch tl_("capacity", s); hipLaunchKernelGGL(k_cap_logdet, dim3(Nf), dim3(256), 0, s, H, Nr, Nt, sc.as<double>(), snr_db, Nsnr,
-                     work.as<double2>(), cf.as<double>()); }
+  if (n <= kCapRegN) {
+    { ::sbr::TimedLaunch tl_("capacity", s); hipLaunchKernelGGL(k_cap_logdet_reg, dim3(Nf), dim3(256), 0, s, H, Nr, Nt, sc.as<double>(), snr_db,
+                       CapSnr{}, Nsnr, cf.as<double>()); }
+  } else {
+    work.alloc((size_t)Nf * 2 * n * n * sizeof(double2), s);
+    { ::sbr::TimedLaunch tl_("capacity", s); hipLaunchKernelGGL(k_cap_logdet, dim3(Nf), dim3(256), 0, s, H, Nr, Nt, sc.as<double>(), snr_db, Nsnr,
+                       work.as<double2>(), cf.as<double>()); }
+  }
   { ::sbr::TimedLaunch tl_("capacity", s); hipLaunchKernelGGL(k_cap_mean, dim3(1), dim3(256), 0, s, cf.as<double>(), Nf, Nsnr, C_out); }
   SBR_LAUNCH_CHECK();
   SBR_HIP(hipStreamSynchronize(s));

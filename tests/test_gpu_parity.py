@@ -383,7 +383,8 @@ def test_trace_order_keeps_results(S, ctx):
 
 
 # ------------------------------------------------------------------ capacity
-@pytest.mark.parametrize("shape", [(1, 1, 1), (3, 4, 8), (5, 8, 4), (2, 64, 64), (2, 16, 128)])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (3, 4, 8), (5, 8, 4), (2, 64, 64), (2, 16, 128), (3, 64, 256),
+                                   (2, 61, 7), (2, 96, 100), (1, 128, 128)])
 def test_capacity(S, ctx, shape):
     banner("capacity", shape)
     rng = np.random.default_rng(sum(shape))
