@@ -197,6 +197,19 @@ sbr_status sbr_capacity(sbr_context_t ctx, const void* H_c64, int32_t Nf, int32_
                         const double* snr_db, int32_t Nsnr, int32_t normalize, double* C_bits_per_hz,
                         uint32_t flags);
 
+/* Allocation-free form of sbr_capacity, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same result as sbr_capacity.
+ * H_c64: device pointer [Nf][Nr][Nt] interleaved FP32 on the context's
+ * device; C_bits_per_hz: device pointer [Nsnr] FP64; snr_db: host array of
+ * Nsnr values (passed to the kernels by value).  Limits: min(Nr, Nt) <= 64,
+ * Nsnr <= 64, Nf * (Nsnr + 1) <= 1,048,544 (SBR_E_CAPACITY beyond).  Queued
+ * on the context stream without waiting; the work lives in one fixed 8 MiB
+ * device array per GPU that every call on that GPU shares, so calls that
+ * overlap on one GPU (several streams, threads or contexts) race: order them. */
+sbr_status sbr_capacity_noalloc(sbr_context_t ctx, const void* H_c64, int32_t Nf, int32_t Nr, int32_t Nt,
+                                const double* snr_db, int32_t Nsnr, int32_t normalize, double* C_bits_per_hz);
+
 /* Launch directions (Sec. II-A-1) for parity checks: dirs [count][3] FP64 of
  * ray ids first .. first+count-1; and the edge-angle statistics (radians) of
  * the geodesic triangulation (any output may be NULL). */

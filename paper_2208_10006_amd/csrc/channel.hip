@@ -16,6 +16,7 @@
 // reduction with a fixed order and no atomics.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "sbr_device.hpp"
 #include "sbr_internal.hpp"
@@ -530,6 +531,56 @@ void run_capacity(const float2* H, int Nf, int Nr, int Nt, const double* snr_db,
   { ::sbr::TimedLaunch tl_("capacity", s); hipLaunchKernelGGL(k_cap_mean, dim3(1), dim3(256), 0, s, cf.as<double>(), Nf, Nsnr, C_out); }
   SBR_LAUNCH_CHECK();
   SBR_HIP(hipStreamSynchronize(s));
+}
+
+// ---------------------------------------------------------------- allocation-free capacity
+// A fixed device array holds the per-frequency norms, the normalisation and
+// the per-(SNR, frequency) log-determinants of sbr_capacity_noalloc.  Host
+// code never uses its name as an address: each device's address is looked up
+// once (hipGetSymbolAddress with that device current) and kept in cap_scratch_ptr.
+static __device__ __align__(256) unsigned char cap_scratch[kCapScratchBytes];
+
+namespace {
+std::mutex g_cap_scratch_mu;
+void* g_cap_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+void capacity_scratch_setup(int device) {
+  SBR_CHECK(device >= 0 && device < kMaxDevices, SBR_E_UNSUPPORTED, "device %d", device);
+  std::lock_guard<std::mutex> lk(g_cap_scratch_mu);
+  if (g_cap_scratch_ptr[device]) return;
+  void* p = nullptr;
+  SBR_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(cap_scratch)));
+  SBR_CHECK(p != nullptr, SBR_E_DEVICE, "no address for the capacity scratch on device %d", device);
+  g_cap_scratch_ptr[device] = p;
+}
+
+void* capacity_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_cap_scratch_mu);
+  return g_cap_scratch_ptr[device];
+}
+
+bool capacity_noalloc_fits(int Nf, int Nr, int Nt, int Nsnr) {
+  return std::min(Nr, Nt) <= kCapRegN && Nsnr <= kCapSnrMax &&
+         ((uint64_t)Nf * (uint64_t)(Nsnr + 1) + 32) * 8 <= (uint64_t)kCapScratchBytes;
+}
+
+// Same kernels as run_capacity (n <= 64), their buffers in `scratch`: the
+// normalisation at offset 0, the norms from byte 256, the log-determinants
+// after them.  Queued on s; nothing is allocated, nothing waits.
+void run_capacity_noalloc(const float2* H, int Nf, int Nr, int Nt, const double* snr_db, int Nsnr, int normalize,
+                          double* C_out, void* scratch, hipStream_t s) {
+  double* sc = static_cast<double*>(scratch);
+  double* frob = sc + 32;
+  double* cf = frob + Nf;
+  CapSnr sv{};
+  for (int i = 0; i < Nsnr; ++i) sv.db[i] = snr_db[i];
+  hipLaunchKernelGGL(k_cap_frob, dim3(Nf), dim3(256), 0, s, H, Nr, Nt, frob);
+  hipLaunchKernelGGL(k_cap_scale, dim3(1), dim3(256), 0, s, frob, Nf, Nr, Nt, normalize, sc);
+  hipLaunchKernelGGL(k_cap_logdet_reg, dim3(Nf), dim3(256), 0, s, H, Nr, Nt, sc, (const double*)nullptr, sv, Nsnr, cf);
+  hipLaunchKernelGGL(k_cap_mean, dim3(1), dim3(256), 0, s, cf, Nf, Nsnr, C_out);
+  SBR_LAUNCH_CHECK();
 }
 
 }  // namespace sbr

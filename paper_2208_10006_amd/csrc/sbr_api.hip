@@ -544,6 +544,8 @@ sbr_status sbr_context_create(int device, void* hip_stream, sbr_context_t* out) 
     SBR_HIP(hipGetDeviceCount(&ndev));
     SBR_CHECK(device >= 0 && device < ndev, SBR_E_INVALID_ARG, "device %d of %d", device, ndev);
     SBR_HIP(hipSetDevice(device));
+    // the allocation-free capacity's device array: its address on this device
+    capacity_scratch_setup(device);
     auto* c = new sbr_context_s();
     c->device = device;
     if (hip_stream) {
@@ -1367,6 +1369,24 @@ sbr_status sbr_capacity(sbr_context_t ctx, const void* H_c64, int32_t Nf, int32_
     SBR_HIP(hipMemcpyAsync(C, out.p, (size_t)Nsnr * 8,
                            (flags & SBR_OUT_DEVICE) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
     SBR_HIP(hipStreamSynchronize(s));
+  });
+}
+
+sbr_status sbr_capacity_noalloc(sbr_context_t ctx, const void* H_c64, int32_t Nf, int32_t Nr, int32_t Nt,
+                                const double* snr_db, int32_t Nsnr, int32_t normalize, double* C) {
+  return guard([&] {
+    auto* c = check_handle<sbr_context_s>(ctx, kContext, "context");
+    SBR_CHECK(Nf >= 1 && Nr >= 1 && Nt >= 1 && Nsnr >= 1, SBR_E_INVALID_ARG, "capacity sizes");
+    SBR_CHECK(H_c64 && snr_db && C, SBR_E_INVALID_ARG, "NULL argument");
+    SBR_CHECK(capacity_noalloc_fits(Nf, Nr, Nt, Nsnr), SBR_E_CAPACITY,
+              "sbr_capacity_noalloc takes min(Nr, Nt) <= 64, Nsnr <= 64 and Nf * (Nsnr + 1) <= %lld "
+              "(got Nf %d, Nr %d, Nt %d, Nsnr %d)",
+              (long long)(kCapScratchBytes / 8 - 32), Nf, Nr, Nt, Nsnr);
+    void* scratch = capacity_scratch(c->device);
+    SBR_CHECK(scratch != nullptr, SBR_E_STATE, "capacity scratch of device %d not set up", c->device);
+    set_device(c);
+    run_capacity_noalloc(static_cast<const float2*>(H_c64), Nf, Nr, Nt, snr_db, Nsnr, normalize, C, scratch,
+                         c->stream);
   });
 }
 

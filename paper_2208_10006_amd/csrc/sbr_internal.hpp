@@ -375,6 +375,14 @@ void run_path_field(sbr_paths_s* ps, const ChannelArgs& a, double2* out, hipStre
 void run_stats(sbr_paths_s* ps, float* pg_db, float* tau, float* angles, hipStream_t s);
 void run_capacity(const float2* H, int Nf, int Nr, int Nt, const double* snr_db, int Nsnr, int normalize,
                   double* C_out, hipStream_t s);
+// allocation-free capacity: a fixed device array of kCapScratchBytes per GPU
+constexpr size_t kCapScratchBytes = size_t(8) << 20;
+constexpr int kMaxDevices = 64;
+void capacity_scratch_setup(int device);  // once per device, with it current (context creation)
+void* capacity_scratch(int device);       // its address on `device`, or null before setup
+bool capacity_noalloc_fits(int Nf, int Nr, int Nt, int Nsnr);
+void run_capacity_noalloc(const float2* H, int Nf, int Nr, int Nt, const double* snr_db_host, int Nsnr,
+                          int normalize, double* C_out, void* scratch, hipStream_t s);
 
 // nn.hip (surrogate)
 void nn_gemm(int M, int N, int K, const void* A, int64_t a_si, int64_t a_sk, const void* B, int64_t b_sk,

@@ -72,6 +72,7 @@ def _load():
         "sbr_path_field": [P, P, P, I32, P, P, I32, I32, P, U32],
         "sbr_stats": [P, P, P, P, U32],
         "sbr_capacity": [P, P, I32, I32, I32, P, I32, I32, P, U32],
+        "sbr_capacity_noalloc": [P, P, I32, I32, I32, P, I32, I32, P],
         "sbr_geodesic": [P, I32, I64, I64, P, U32],
         "sbr_geodesic_alpha": [P, I32, P, P, P],
         "sbr_profile_enable": [P, C.c_int],
@@ -136,12 +137,12 @@ def _flags(arrs, bit):
 def _torch_dtypes():
     try:
         import torch
-        return torch.float64, torch.float32, torch.int32
+        return torch.float64, torch.float32, torch.int32, torch.complex64
     except ImportError:  # numpy-only use
-        return None, None, None
+        return None, None, None, None
 
 
-F64, F32, I32T = _torch_dtypes()
+F64, F32, I32T, C64 = _torch_dtypes()
 
 
 class _Handle:
@@ -381,6 +382,22 @@ def sbr_capacity(ctx: Context, H_c64, snr_db, normalize: int = 1):
     _call("sbr_capacity", ctx.h, h.ptr, Nf, Nr, Nt, s.ptr, ns, int(normalize), out.ctypes.data_as(C.c_void_p),
           _flags([h, s], SBR_IN_DEVICE))
     return out
+
+
+def sbr_capacity_noalloc(ctx: Context, H_c64, snr_db, out, normalize: int = 1):
+    """Allocation-free capacity: H_c64 (complex64 [Nf, Nr, Nt]) and out (float64
+    [Nsnr]) are tensors on the context's device, snr_db a host sequence.
+    Queued on the context stream; synchronise before reading out."""
+    if not (_is_torch(H_c64) and H_c64.is_cuda and _is_torch(out) and out.is_cuda):
+        raise ValueError("sbr_capacity_noalloc takes device tensors for H and the output")
+    if H_c64.dtype != C64 or not H_c64.is_contiguous() or out.dtype != F64 or not out.is_contiguous():
+        raise ValueError("H must be contiguous complex64 and out contiguous float64")
+    Nf, Nr, Nt = tuple(H_c64.shape)[:3]
+    snr = np.ascontiguousarray(snr_db, np.float64)
+    if out.numel() < snr.size:
+        raise ValueError("out holds fewer values than snr_db")
+    _call("sbr_capacity_noalloc", ctx.h, C.c_void_p(H_c64.data_ptr()), Nf, Nr, Nt,
+          snr.ctypes.data_as(C.c_void_p), snr.size, int(normalize), C.c_void_p(out.data_ptr()))
 
 
 def sbr_geodesic(ctx: Context, N: int, first: int = 0, count: Optional[int] = None):
