@@ -378,7 +378,10 @@ __global__ __launch_bounds__(256) void k_bounce(const BounceParams P) {
         const float det = U + V + W;
         const float Tn = U * (Sz * Akz) + V * (Sz * Bkz) + W * (Sz * Ckz);
         const float t = Tn * __builtin_amdgcn_rcpf(det);
-        if (!outside && det != 0.0f && __float_as_int(b.w) != skip_plane && t > 0.0f && t < thit) {
+        // an exact tie in t goes to the lower leaf, so the order in which the
+        // traversal meets the candidates does not decide between them
+        if (!outside && det != 0.0f && __float_as_int(b.w) != skip_plane && t > 0.0f &&
+            (t < thit || (t == thit && leaf < hit))) {
           thit = t;
           hit = leaf;
         }
