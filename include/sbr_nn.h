@@ -31,11 +31,28 @@ extern "C" {
 sbr_status sbr_nn_gemm_bf16(sbr_context_t ctx, int32_t M, int32_t N, int32_t K, const void* A, int64_t a_si,
                             int64_t a_sk, const void* B, int64_t b_sk, int64_t b_sj, const float* bias, void* C,
                             int64_t ldc, uint32_t flags);
+/* sbr_nn_gemm_bf16 with two backward-pass options (both may be NULL):
+ * relu_mask (bf16, [M][ld_mask], ld_mask >= N): the product is set to 0 where
+ *   relu_mask[i*ld_mask + j] <= 0 before bias, accumulation, ReLU and rounding,
+ *   i.e. C = dY * (Y > 0) for a ReLU layer's output Y (ReLU backward fused into
+ *   the backward-data product);
+ * bsum (FP32, [N]): bsum[j] = sum_k B(k,j) (+= with SBR_NN_ACCUMULATE),
+ *   accumulated in FP32 on the same matrix cores as one more row of A that is
+ *   all ones (the bias gradient of a layer from its bf16 output gradient,
+ *   fused into the backward-weight product).  M may then be 0 (A unused).
+ * The K reduction is deterministic: split-K slices are summed in a fixed order. */
+sbr_status sbr_nn_gemm_bf16_ex(sbr_context_t ctx, int32_t M, int32_t N, int32_t K, const void* A, int64_t a_si,
+                               int64_t a_sk, const void* B, int64_t b_sk, int64_t b_sj, const float* bias, void* C,
+                               int64_t ldc, uint32_t flags, const void* relu_mask, int64_t ld_mask, float* bsum);
 /* 3x3, stride 2, zero-padding 1 patches of x[n][H][W][C] (bf16, channels
  * last) into col[n*(H/2)*(W/2)][9*C] (bf16, column (ky*3+kx)*C + c); H, W even. */
 sbr_status sbr_nn_im2col(sbr_context_t ctx, const void* x, int32_t n, int32_t H, int32_t W, int32_t C, void* col);
 /* adjoint of sbr_nn_im2col: dx[n][H][W][C] = sum of the dcol entries that read it (FP32) */
 sbr_status sbr_nn_col2im(sbr_context_t ctx, const float* dcol, int32_t n, int32_t H, int32_t W, int32_t C, float* dx);
+/* dz[n][H][W][C] (bf16) = that adjoint where y > 0, else 0 (y bf16, same shape):
+ * the ReLU backward of the convolution layer whose output is y, fused with col2im */
+sbr_status sbr_nn_col2im_relu_backward(sbr_context_t ctx, const float* dcol, int32_t n, int32_t H, int32_t W,
+                                       int32_t C, const void* y, void* dz);
 /* feature rows out[n][F] (bf16): emb[scene[i]][0..E), x[i][0..D), then
  * sin(2^l pi x_d), cos(2^l pi x_d) for d < D, l < L (d-major), then
  * extra[i][0..X) (extra may be NULL when X == 0), zero padded to F. */
@@ -73,6 +90,13 @@ sbr_status sbr_nn_cast_bf16(sbr_context_t ctx, const float* a, int64_t n, void* 
  * weight may be NULL), dpred = d loss / d pred (row stride ldd), loss FP64 [1] */
 sbr_status sbr_nn_mse(sbr_context_t ctx, const float* pred, int64_t ldp, const float* target, const float* weight,
                       int64_t n, int32_t T, float scale, float* dpred, int64_t ldd, double* loss);
+/* The ReLU backward of a [M][N] matrix (row stride N, 1 <= N <= 256) and
+ * the column sums of its result in one pass:
+ * gout / gbf (either may be NULL) = g * (y > 0), colsum[j] = sum_i of
+ * that result's column j (FP64 sums in a fixed order, FP32 out): the
+ * bias gradient of the layer, computed while the gradient is produced. */
+sbr_status sbr_nn_relu_backward_colsum(sbr_context_t ctx, const float* g, const void* y, int64_t M, int32_t N,
+                                       float* gout, void* gbf, float* colsum);
 /* out[j] (+)= sum_i g[i*ld + j], j < N (bias gradients) */
 sbr_status sbr_nn_colsum(sbr_context_t ctx, const float* g, int64_t M, int32_t N, int64_t ld, float* out,
                          int32_t accumulate);

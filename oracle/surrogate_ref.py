@@ -208,34 +208,33 @@ def mse(out, target, weight):
 
 
 def backward(arch: Arch, P, cache, dout, use_bf16=False):
-    """Gradients of all parameters for d loss / d out = dout."""
+    """Gradients of all parameters for d loss / d out = dout.  use_bf16: each
+    layer's output gradient is rounded to bfloat16 once and both its weight
+    and its bias gradient are formed from the rounded value."""
     r = bf16 if use_bf16 else (lambda a: np.asarray(a, np.float64))
     W = cache["W"]
     G = {}
     g = r(dout)
     G["out_w"] = cache["last"].T @ g
-    G["out_b"] = dout.sum(axis=0)
+    G["out_b"] = g.sum(axis=0)
     dh = g @ W["out_w"].T
     for i in reversed(range(arch.depth)):
         h_in, h_out = cache[f"mlp{i}"]
-        dz = dh * (h_out > 0)
-        G[f"mlp{i}_b"] = dz.sum(axis=0)
-        dzr = r(dz)
+        dzr = r(dh * (h_out > 0))
+        G[f"mlp{i}_b"] = dzr.sum(axis=0)
         G[f"mlp{i}_w"] = h_in.T @ dzr
         dh = dzr @ W[f"mlp{i}_w"].T
     S = cache["emb"].shape[0]
     demb = np.zeros((S, arch.E))
     np.add.at(demb, cache["scene"], r(dh[:, :arch.E]))
-    dz = demb * (cache["emb"] > 0)
-    G["emb_b"] = dz.sum(axis=0)
-    dzr = r(dz)
+    dzr = r(demb * (cache["emb"] > 0))
+    G["emb_b"] = dzr.sum(axis=0)
     G["emb_w"] = cache["flat"].T @ dzr
     da = dzr @ W["emb_w"].T
     for i in reversed(range(len(arch.chans) - 1)):
         col, a_out, in_shape = cache[f"conv{i}"]
-        dz = da.reshape(a_out.shape) * (a_out > 0)
-        G[f"conv{i}_b"] = dz.sum(axis=0)
-        dzr = r(dz)
+        dzr = r(da.reshape(a_out.shape) * (a_out > 0))
+        G[f"conv{i}_b"] = dzr.sum(axis=0)
         G[f"conv{i}_w"] = col.T @ dzr
         if i > 0:
             dcol = dzr @ W[f"conv{i}_w"].T

@@ -50,7 +50,9 @@ struct TileLoader {
   static constexpr int CHUNKS = ROWS * BK / 8 / 256;  // 16-byte chunks per thread
   bf16x8 v[CHUNKS];
 
-  __device__ void load(const __bf16* __restrict__ X, int64_t s_r, int64_t s_k, int r0, int rmax, int k0, int kend) {
+  // one_r: index of a virtual row of ones beyond the rmax stored rows (-1: none)
+  __device__ void load(const __bf16* __restrict__ X, int64_t s_r, int64_t s_k, int r0, int rmax, int k0, int kend,
+                       int one_r) {
     const int tid = threadIdx.x;
 #pragma unroll
     for (int c = 0; c < CHUNKS; ++c) {
@@ -63,7 +65,9 @@ struct TileLoader {
         } else {
 #pragma unroll
           for (int t = 0; t < 8; ++t)
-            v[c][t] = (row < rmax && k + t < kend) ? X[(int64_t)row * s_r + k + t] : f2bf(0.0f);
+            v[c][t] = k + t >= kend ? f2bf(0.0f)
+                      : row < rmax  ? X[(int64_t)row * s_r + k + t]
+                                    : f2bf(row == one_r ? 1.0f : 0.0f);
         }
       } else {  // chunk = 8 consecutive rows of one k
         const int kk = q / (ROWS / 8), r8 = (q % (ROWS / 8)) * 8;
@@ -73,7 +77,9 @@ struct TileLoader {
         } else {
 #pragma unroll
           for (int t = 0; t < 8; ++t)
-            v[c][t] = (k < kend && row + t < rmax) ? X[(int64_t)(row + t) * s_r + (int64_t)k * s_k] : f2bf(0.0f);
+            v[c][t] = k >= kend        ? f2bf(0.0f)
+                      : row + t < rmax ? X[(int64_t)(row + t) * s_r + (int64_t)k * s_k]
+                                       : f2bf(row + t == one_r ? 1.0f : 0.0f);
         }
       }
     }
@@ -107,9 +113,19 @@ struct GemmArgs {
   int64_t ldc;
   uint32_t flags;
   float* partial;  // [splits][M][N] when split, else nullptr
+  int ones_row;    // row of A that is all ones (= rows of A stored; M = ones_row + 1), -1: none
+  float* bsum;     // destination of that row: bsum[j] = sum_k B(k,j)
+  const __bf16* mask;  // ReLU-backward mask: the product is zeroed where mask[i*ldm + j] <= 0
+  int64_t ldm;
 };
 
 __device__ inline void epilogue_store(const GemmArgs& g, int i, int j, float v) {
+  if (i == g.ones_row) {
+    if (g.flags & kAccum) v += g.bsum[j];
+    g.bsum[j] = v;
+    return;
+  }
+  if (g.mask && !(bf2f(g.mask[(int64_t)i * g.ldm + j]) > 0.0f)) v = 0.0f;
   if (g.bias) v += g.bias[j];
   const int64_t o = (int64_t)i * g.ldc + j;
   if (g.flags & kAccum) v += (g.flags & kOutBf16) ? bf2f(static_cast<const __bf16*>(g.C)[o]) : static_cast<const float*>(g.C)[o];
@@ -139,9 +155,10 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
     for (int c = 0; c < FT; ++c) acc[r][c] = f32x4{0, 0, 0, 0};
   TileLoader<T, AMODE> la;
   TileLoader<T, BMODE> lb;
+  const int ma = g.ones_row >= 0 ? g.ones_row : g.M;  // rows of A in memory
   if (kb < ke) {
-    la.load(g.A, g.a_si, g.a_sk, i0, g.M, kb, ke);
-    lb.load(g.B, g.b_sj, g.b_sk, j0, g.N, kb, ke);
+    la.load(g.A, g.a_si, g.a_sk, i0, ma, kb, ke, g.ones_row);
+    lb.load(g.B, g.b_sj, g.b_sk, j0, g.N, kb, ke, -1);
   }
   const int fr = lane & 15, fk = (lane >> 4) * 8;
   for (int k0 = kb; k0 < ke; k0 += BK) {
@@ -149,8 +166,8 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
     lb.store(Bs);
     __syncthreads();
     if (k0 + BK < ke) {  // next step's loads in flight during this step's MFMAs
-      la.load(g.A, g.a_si, g.a_sk, i0, g.M, k0 + BK, ke);
-      lb.load(g.B, g.b_sj, g.b_sk, j0, g.N, k0 + BK, ke);
+      la.load(g.A, g.a_si, g.a_sk, i0, ma, k0 + BK, ke, g.ones_row);
+      lb.load(g.B, g.b_sj, g.b_sk, j0, g.N, k0 + BK, ke, -1);
     }
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 32) {
@@ -184,13 +201,22 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
     }
 }
 
-__global__ void k_gemm_reduce(GemmArgs g, int splits) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// 64 outputs per block, one per lane; wave w sums the w-th quarter of the
+// k-slices in slice order and the quarters are added in wave order, so the
+// result does not depend on scheduling.
+__global__ __launch_bounds__(256) void k_gemm_reduce(GemmArgs g, int splits) {
+  __shared__ float quarter[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t mn = (int64_t)g.M * g.N;
-  if (e >= mn) return;
+  const int64_t e = (int64_t)blockIdx.x * 64 + lane;
+  const int q = (splits + 3) / 4, z0 = w * q, z1 = min(splits, z0 + q);
   float s = 0.0f;
-  for (int z = 0; z < splits; ++z) s += g.partial[z * mn + e];
-  epilogue_store(g, (int)(e / g.N), (int)(e % g.N), s);
+  if (e < mn)
+    for (int z = z0; z < z1; ++z) s += g.partial[(int64_t)z * mn + e];
+  quarter[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && e < mn)
+    epilogue_store(g, (int)(e / g.N), (int)(e % g.N), ((quarter[0][lane] + quarter[1][lane]) + quarter[2][lane]) + quarter[3][lane]);
 }
 
 // ---------------------------------------------------------------- fused MLP inference
@@ -300,7 +326,9 @@ __global__ void k_im2col(const __bf16* __restrict__ x, int n, int H, int W, int 
 }
 
 // dx[b][iy][ix][c] = sum over the (at most 4) output positions and taps that read it
-__global__ void k_col2im(const float* __restrict__ dcol, int n, int H, int W, int C, float* __restrict__ dx) {
+// y == nullptr: dx = sum; else dz_bf = bf16(y > 0 ? sum : 0) (ReLU backward of the layer whose output is y)
+__global__ void k_col2im(const float* __restrict__ dcol, int n, int H, int W, int C, float* __restrict__ dx,
+                         const __bf16* __restrict__ y, __bf16* __restrict__ dz_bf) {
   const int Ho = H / 2, Wo = W / 2;
   const int64_t total = (int64_t)n * H * W * C;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -319,7 +347,8 @@ __global__ void k_col2im(const float* __restrict__ dcol, int n, int H, int W, in
       s += dcol[p * 9 * C + (ky * 3 + kx) * C + c];
     }
   }
-  dx[e] = s;
+  if (y) dz_bf[e] = f2bf(bf2f(y[e]) > 0.0f ? s : 0.0f);
+  else dx[e] = s;
 }
 
 // ---------------------------------------------------------------- elementwise
@@ -409,6 +438,44 @@ __global__ void k_relu_bwd(const float* __restrict__ g, const __bf16* __restrict
   if (gbf) gbf[e] = f2bf(v);
 }
 
+// The ReLU backward of a [M][N] gradient (N at most 256) fused with the
+// column sums of its result (the bias gradient), so the matrix is read once.
+// Block b covers rows [b R, (b + 1) R) with R = kReluColPerThread G and
+// G = 256 / N row groups: thread t = g N + j takes column j of rows r0 + g,
+// r0 + g + G, ... (kReluColPerThread of them, so that even a few thousand
+// rows spread over many blocks); the groups' FP64 sums of a column are added
+// in group order and go to partial[b][N], and k_colsum_final adds the blocks
+// in order.
+constexpr int kReluColPerThread = 32;
+__global__ __launch_bounds__(256) void k_relu_bwd_colsum(const float* __restrict__ g, const __bf16* __restrict__ y,
+                                                         int64_t M, int N, float* __restrict__ gout,
+                                                         __bf16* __restrict__ gbf, double* __restrict__ partial) {
+  const int t = threadIdx.x;
+  const int groups = 256 / N;
+  const int gi = t / N, j = t - gi * N;
+  const int64_t rows = (int64_t)kReluColPerThread * groups;
+  const int64_t r0 = (int64_t)blockIdx.x * rows;
+  const int64_t r1 = min<int64_t>(M, r0 + rows);
+  double s = 0.0;
+  if (gi < groups) {
+    for (int64_t r = r0 + gi; r < r1; r += groups) {
+      const int64_t e = r * N + j;
+      const float v = bf2f(y[e]) > 0.0f ? g[e] : 0.0f;
+      if (gout) gout[e] = v;
+      if (gbf) gbf[e] = f2bf(v);
+      s += v;
+    }
+  }
+  __shared__ double sm[256];
+  sm[t] = s;
+  __syncthreads();
+  if (t < N) {
+    double acc = 0.0;
+    for (int k = 0; k < groups; ++k) acc += sm[k * N + t];
+    partial[(int64_t)blockIdx.x * N + t] = acc;
+  }
+}
+
 __global__ void k_cast_f32_bf16(const float* __restrict__ a, int64_t n, __bf16* __restrict__ b) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < n) b[e] = f2bf(a[e]);
@@ -456,13 +523,21 @@ __global__ __launch_bounds__(256) void k_colsum_part(const float* __restrict__ g
   if (rg == 0 && j < N) partial[(int64_t)blockIdx.y * N + j] = ((sm[0][jl] + sm[1][jl]) + sm[2][jl]) + sm[3][jl];
 }
 
-__global__ void k_colsum_final(const double* __restrict__ partial, int chunks, int N, float* __restrict__ out,
-                               int accumulate) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= N) return;
+// block per column j: thread t adds chunks t, t + 256, ... and a fixed tree
+// adds the threads' sums, so many chunks of a narrow matrix reduce in parallel
+__global__ __launch_bounds__(256) void k_colsum_final(const double* __restrict__ partial, int chunks, int N,
+                                                      float* __restrict__ out, int accumulate) {
+  const int j = blockIdx.x;
   double s = 0.0;
-  for (int c = 0; c < chunks; ++c) s += partial[(int64_t)c * N + j];
-  out[j] = (accumulate ? out[j] : 0.0f) + (float)s;
+  for (int c = threadIdx.x; c < chunks; c += 256) s += partial[(int64_t)c * N + j];
+  __shared__ double sm[256];
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[j] = (accumulate ? out[j] : 0.0f) + (float)sm[0];
 }
 
 __global__ void k_sum_f64(const double* __restrict__ p, int64_t n, double* __restrict__ out) {
@@ -568,28 +643,34 @@ void launch_gemm_t(const GemmArgs& g, int am, int bm, int blocks, hipStream_t s)
 }  // namespace
 
 void nn_gemm(int M, int N, int K, const void* A, int64_t a_si, int64_t a_sk, const void* B, int64_t b_sk,
-             int64_t b_sj, const float* bias, void* C, int64_t ldc, uint32_t flags, hipStream_t s) {
-  if (M <= 0 || N <= 0) return;
+             int64_t b_sj, const float* bias, void* C, int64_t ldc, uint32_t flags, hipStream_t s,
+             const void* mask, int64_t ldm, float* bsum) {
+  if (N <= 0 || (M <= 0 && !bsum)) return;
   int num_cus = 256;
   {
     int dev = 0;
     if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&num_cus, hipDeviceAttributeMultiprocessorCount, dev);
   }
+  // column sums of B ride along as one more row of A (all ones)
+  const int Mr = M + (bsum ? 1 : 0);
   // 128-wide tiles when they alone fill the chip, else 64
-  const int64_t t128 = (int64_t)((M + 127) / 128) * ((N + 127) / 128);
+  const int64_t t128 = (int64_t)((Mr + 127) / 128) * ((N + 127) / 128);
   const int T = t128 >= 2 * num_cus ? 128 : 64;
-  const int tiles_m = (M + T - 1) / T, tiles_n = (N + T - 1) / T, ntiles = tiles_m * tiles_n;
-  // split K when the tiles leave the chip idle and K is long
+  const int tiles_m = (Mr + T - 1) / T, tiles_n = (N + T - 1) / T, ntiles = tiles_m * tiles_n;
+  // split K only when the tiles leave CUs idle and K is long; at most 64
+  // slices so that the ordered reduction stays short
   const int ksteps = (K + BK - 1) / BK;
   int splits = 1;
-  if (ntiles < 2 * num_cus && ksteps >= 8) splits = std::max(1, std::min((4 * num_cus + ntiles - 1) / ntiles, ksteps / 4));
+  if (ntiles < num_cus && ksteps >= 8)
+    splits = std::max(1, std::min(std::min((2 * num_cus + ntiles - 1) / ntiles, ksteps / 4), 64));
   const int kchunk = ((ksteps + splits - 1) / splits) * BK;
   if (K > 0) splits = (K + kchunk - 1) / kchunk;
-  GemmArgs g{M, N, K, kchunk, tiles_n, ntiles, static_cast<const __bf16*>(A), a_si, a_sk,
-             static_cast<const __bf16*>(B), b_sk, b_sj, bias, C, ldc, flags, nullptr};
+  GemmArgs g{Mr, N, K, kchunk, tiles_n, ntiles, static_cast<const __bf16*>(A), a_si, a_sk,
+             static_cast<const __bf16*>(B), b_sk, b_sj, bias, C, ldc, flags, nullptr,
+             bsum ? M : -1, bsum, static_cast<const __bf16*>(mask), ldm};
   Buf part;
   if (splits > 1) {
-    part.alloc((size_t)splits * M * N * 4, s);
+    part.alloc((size_t)splits * Mr * N * 4, s);
     g.partial = part.as<float>();
   }
   const int am = load_mode(A, a_si, a_sk), bm = load_mode(B, b_sj, b_sk);
@@ -597,8 +678,8 @@ void nn_gemm(int M, int N, int K, const void* A, int64_t a_si, int64_t a_sk, con
   if (T == 128) launch_gemm_t<128>(g, am, bm, ntiles * splits, s);
   else launch_gemm_t<64>(g, am, bm, ntiles * splits, s);
   if (splits > 1) {
-    const int64_t mn = (int64_t)M * N;
-    hipLaunchKernelGGL(k_gemm_reduce, dim3(nblk(mn, 256)), dim3(256), 0, s, g, splits);
+    const int64_t mn = (int64_t)Mr * N;
+    hipLaunchKernelGGL(k_gemm_reduce, dim3(nblk(mn, 64)), dim3(256), 0, s, g, splits);
   }
   SBR_LAUNCH_CHECK();
 }
@@ -625,10 +706,11 @@ void nn_im2col(const void* x, int n, int H, int W, int C, void* col, hipStream_t
                      static_cast<__bf16*>(col));
   SBR_LAUNCH_CHECK();
 }
-void nn_col2im(const float* dcol, int n, int H, int W, int C, float* dx, hipStream_t s) {
+void nn_col2im(const float* dcol, int n, int H, int W, int C, float* dx, hipStream_t s, const void* y, void* dz_bf) {
   const int64_t total = (int64_t)n * H * W * C;
   ::sbr::TimedLaunch tl_("nn_conv", s);
-  hipLaunchKernelGGL(k_col2im, dim3(nblk(total, 256)), dim3(256), 0, s, dcol, n, H, W, C, dx);
+  hipLaunchKernelGGL(k_col2im, dim3(nblk(total, 256)), dim3(256), 0, s, dcol, n, H, W, C, dx,
+                     static_cast<const __bf16*>(y), static_cast<__bf16*>(dz_bf));
   SBR_LAUNCH_CHECK();
 }
 void nn_fourier(const float* x, int64_t n, int D, int L, const void* emb, int E, const int32_t* scene,
@@ -667,14 +749,25 @@ void nn_mse(const float* pred, int64_t ldp, const float* target, const float* we
   hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(256), 0, s, part.as<double>(), nb, loss);
   SBR_LAUNCH_CHECK();
 }
+void nn_relu_bwd_colsum(const float* g, const void* y, int64_t M, int N, float* gout, void* gbf, float* colsum,
+                        hipStream_t s) {
+  const int64_t rows = (int64_t)kReluColPerThread * (256 / N);
+  const int chunks = (int)std::max<int64_t>(1, (M + rows - 1) / rows);
+  Buf part;
+  part.alloc((size_t)chunks * N * 8, s);
+  ::sbr::TimedLaunch tl_("nn_elem", s);
+  hipLaunchKernelGGL(k_relu_bwd_colsum, dim3(chunks), dim3(256), 0, s, g, static_cast<const __bf16*>(y), M, N, gout,
+                     static_cast<__bf16*>(gbf), part.as<double>());
+  hipLaunchKernelGGL(k_colsum_final, dim3(N), dim3(256), 0, s, part.as<double>(), chunks, N, colsum, 0);
+  SBR_LAUNCH_CHECK();
+}
 void nn_colsum(const float* g, int64_t M, int N, int64_t ld, float* out, int accumulate, hipStream_t s) {
   const int chunks = (int)std::max<int64_t>(1, (M + kColsumRows - 1) / kColsumRows);
   Buf part;
   part.alloc((size_t)chunks * N * 8, s);
   ::sbr::TimedLaunch tl_("nn_elem", s);
   hipLaunchKernelGGL(k_colsum_part, dim3((N + 63) / 64, chunks), dim3(256), 0, s, g, M, N, ld, part.as<double>());
-  hipLaunchKernelGGL(k_colsum_final, dim3((N + 255) / 256), dim3(256), 0, s, part.as<double>(), chunks, N, out,
-                     accumulate);
+  hipLaunchKernelGGL(k_colsum_final, dim3(N), dim3(256), 0, s, part.as<double>(), chunks, N, out, accumulate);
   SBR_LAUNCH_CHECK();
 }
 void nn_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,

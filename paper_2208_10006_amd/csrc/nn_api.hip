@@ -27,6 +27,18 @@ sbr_status sbr_nn_gemm_bf16(sbr_context_t ctx, int32_t M, int32_t N, int32_t K, 
   });
 }
 
+sbr_status sbr_nn_gemm_bf16_ex(sbr_context_t ctx, int32_t M, int32_t N, int32_t K, const void* A, int64_t a_si,
+                               int64_t a_sk, const void* B, int64_t b_sk, int64_t b_sj, const float* bias, void* C,
+                               int64_t ldc, uint32_t flags, const void* relu_mask, int64_t ld_mask, float* bsum) {
+  NN_ENTRY({
+    NN_REQUIRE(M >= 0 && N >= 0 && K >= 0 && (M == 0 || N == 0 || (C && (K == 0 || (A && B)))), "gemm arguments");
+    NN_REQUIRE(!bsum || N == 0 || K == 0 || B, "gemm column sums need B");
+    NN_REQUIRE(!relu_mask || ld_mask >= N, "gemm mask leading dimension %lld < N %d", (long long)ld_mask, N);
+    NN_REQUIRE((flags & ~7u) == 0, "gemm flags 0x%x", flags);
+    nn_gemm(M, N, K, A, a_si, a_sk, B, b_sk, b_sj, bias, C, ldc, flags, s, relu_mask, ld_mask, bsum);
+  });
+}
+
 sbr_status sbr_nn_im2col(sbr_context_t ctx, const void* x, int32_t n, int32_t H, int32_t W, int32_t C, void* col) {
   NN_ENTRY({
     NN_REQUIRE(x && col && n > 0 && H > 0 && W > 0 && C > 0 && H % 2 == 0 && W % 2 == 0, "im2col arguments");
@@ -38,6 +50,15 @@ sbr_status sbr_nn_col2im(sbr_context_t ctx, const float* dcol, int32_t n, int32_
   NN_ENTRY({
     NN_REQUIRE(dcol && dx && n > 0 && H > 0 && W > 0 && C > 0 && H % 2 == 0 && W % 2 == 0, "col2im arguments");
     nn_col2im(dcol, n, H, W, C, dx, s);
+  });
+}
+
+sbr_status sbr_nn_col2im_relu_backward(sbr_context_t ctx, const float* dcol, int32_t n, int32_t H, int32_t W,
+                                       int32_t C, const void* y, void* dz) {
+  NN_ENTRY({
+    NN_REQUIRE(dcol && y && dz && n > 0 && H > 0 && W > 0 && C > 0 && H % 2 == 0 && W % 2 == 0,
+               "col2im_relu_backward arguments");
+    nn_col2im(dcol, n, H, W, C, nullptr, s, y, dz);
   });
 }
 
@@ -102,6 +123,15 @@ sbr_status sbr_nn_mse(sbr_context_t ctx, const float* pred, int64_t ldp, const f
   NN_ENTRY({
     NN_REQUIRE(pred && target && dpred && loss && n >= 0 && T > 0, "mse arguments");
     nn_mse(pred, ldp, target, weight, n, T, scale, dpred, ldd, loss, s);
+  });
+}
+
+sbr_status sbr_nn_relu_backward_colsum(sbr_context_t ctx, const float* g, const void* y, int64_t M, int32_t N,
+                                       float* gout, void* gbf, float* colsum) {
+  NN_ENTRY({
+    NN_REQUIRE(g && y && colsum && M >= 0 && N >= 1 && N <= 256 && (gout || gbf),
+               "relu_backward_colsum arguments (1 <= N <= 256)");
+    nn_relu_bwd_colsum(g, y, M, N, gout, gbf, colsum, s);
   });
 }
 

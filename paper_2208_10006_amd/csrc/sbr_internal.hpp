@@ -385,10 +385,15 @@ void run_capacity_noalloc(const float2* H, int Nf, int Nr, int Nt, const double*
                           int normalize, double* C_out, void* scratch, hipStream_t s);
 
 // nn.hip (surrogate)
+// mask (bf16, may be null): the product is zeroed where mask[i*ldm + j] <= 0;
+// bsum (may be null): bsum[j] = sum_k B(k,j) from the same FP32 accumulation
 void nn_gemm(int M, int N, int K, const void* A, int64_t a_si, int64_t a_sk, const void* B, int64_t b_sk,
-             int64_t b_sj, const float* bias, void* C, int64_t ldc, uint32_t flags, hipStream_t s);
+             int64_t b_sj, const float* bias, void* C, int64_t ldc, uint32_t flags, hipStream_t s,
+             const void* mask = nullptr, int64_t ldm = 0, float* bsum = nullptr);
 void nn_im2col(const void* x, int n, int H, int W, int C, void* col, hipStream_t s);
-void nn_col2im(const float* dcol, int n, int H, int W, int C, float* dx, hipStream_t s);
+// y == null: dx (FP32) = adjoint of im2col; else dz_bf (bf16) = that sum where y > 0, else 0
+void nn_col2im(const float* dcol, int n, int H, int W, int C, float* dx, hipStream_t s, const void* y = nullptr,
+               void* dz_bf = nullptr);
 void nn_fourier(const float* x, int64_t n, int D, int L, const void* emb, int E, const int32_t* scene,
                 const float* extra, int X, int F, void* out, hipStream_t s);
 void nn_mlp_fused(int64_t n, const void* shared, const void* emb, const int32_t* scene, const void* wt,
@@ -398,6 +403,8 @@ void nn_transpose(const void* src, int rows, int cols, void* dst, hipStream_t s)
 void nn_link_features(const float* raw, int64_t n, const int32_t* scene, const void* hmap, int H, float half,
                       int samples, float* x, float* extra, hipStream_t s);
 void nn_relu_bwd(const float* g, const void* y, int64_t n, float* gout, void* gbf, hipStream_t s);
+void nn_relu_bwd_colsum(const float* g, const void* y, int64_t M, int N, float* gout, void* gbf, float* colsum,
+                        hipStream_t s);
 void nn_cast(const float* a, int64_t n, void* b, hipStream_t s);
 void nn_mse(const float* pred, int64_t ldp, const float* target, const float* weight, int64_t n, int T, float scale,
             float* dpred, int64_t ldd, double* loss, hipStream_t s);

@@ -14,14 +14,17 @@ L = S._lib
 P, I32, I64, U32, F = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_float
 _SIG = {
     "sbr_nn_gemm_bf16": [P, I32, I32, I32, P, I64, I64, P, I64, I64, P, P, I64, U32],
+    "sbr_nn_gemm_bf16_ex": [P, I32, I32, I32, P, I64, I64, P, I64, I64, P, P, I64, U32, P, I64, P],
     "sbr_nn_im2col": [P, P, I32, I32, I32, I32, P],
     "sbr_nn_col2im": [P, P, I32, I32, I32, I32, P],
+    "sbr_nn_col2im_relu_backward": [P, P, I32, I32, I32, I32, P, P],
     "sbr_nn_fourier": [P, P, I64, I32, I32, P, I32, P, P, I32, I32, P],
     "sbr_nn_link_features": [P, P, I64, P, P, I32, F, I32, P, P],
     "sbr_nn_relu_backward": [P, P, P, I64, P, P],
     "sbr_nn_cast_bf16": [P, P, I64, P],
     "sbr_nn_mse": [P, P, I64, P, P, I64, I32, F, P, I64, P],
     "sbr_nn_colsum": [P, P, I64, I32, I64, P, I32],
+    "sbr_nn_relu_backward_colsum": [P, P, P, I64, I32, P, P, P],
     "sbr_nn_adam": [P, P, P, P, P, I64, F, F, F, F, F, I32, P],
     "sbr_nn_ensemble": [P, P, I32, I64, I64, I64, I32, F, P, P, P],
     "sbr_nn_gather_rows": [P, P, I64, P, I64, P],
@@ -48,12 +51,22 @@ def sbr_nn_gemm_bf16(ctx, M, N, K, A, a_si, a_sk, B, b_sk, b_sj, bias, Cout, ldc
     S._call("sbr_nn_gemm_bf16", ctx.h, M, N, K, _p(A), a_si, a_sk, _p(B), b_sk, b_sj, _p(bias), _p(Cout), ldc, flags)
 
 
+def sbr_nn_gemm_bf16_ex(ctx, M, N, K, A, a_si, a_sk, B, b_sk, b_sj, bias, Cout, ldc, flags=0, relu_mask=None,
+                        ld_mask=0, bsum=None):
+    S._call("sbr_nn_gemm_bf16_ex", ctx.h, M, N, K, _p(A), a_si, a_sk, _p(B), b_sk, b_sj, _p(bias), _p(Cout), ldc,
+            flags, _p(relu_mask), ld_mask, _p(bsum))
+
+
 def sbr_nn_im2col(ctx, x, n, H, W, Cch, col):
     S._call("sbr_nn_im2col", ctx.h, _p(x), n, H, W, Cch, _p(col))
 
 
 def sbr_nn_col2im(ctx, dcol, n, H, W, Cch, dx):
     S._call("sbr_nn_col2im", ctx.h, _p(dcol), n, H, W, Cch, _p(dx))
+
+
+def sbr_nn_col2im_relu_backward(ctx, dcol, n, H, W, Cch, y, dz):
+    S._call("sbr_nn_col2im_relu_backward", ctx.h, _p(dcol), n, H, W, Cch, _p(y), _p(dz))
 
 
 def sbr_nn_fourier(ctx, x, n, D, Lb, emb, E, scene, Fw, out, extra=None, X=0):
@@ -74,6 +87,10 @@ def sbr_nn_cast_bf16(ctx, a, n, b):
 
 def sbr_nn_mse(ctx, pred, ldp, target, weight, n, T, scale, dpred, ldd, loss):
     S._call("sbr_nn_mse", ctx.h, _p(pred), ldp, _p(target), _p(weight), n, T, float(scale), _p(dpred), ldd, _p(loss))
+
+
+def sbr_nn_relu_backward_colsum(ctx, g, y, M, N, colsum, gout=None, gbf=None):
+    S._call("sbr_nn_relu_backward_colsum", ctx.h, _p(g), _p(y), M, N, _p(gout), _p(gbf), _p(colsum))
 
 
 def sbr_nn_colsum(ctx, g, M, N, ld, out, accumulate=0):

@@ -14,7 +14,7 @@ path produces at the carrier, from
   * an MLP of six ReLU layers of width 256 and a linear output of width 2.
 Rx where SBR finds no path are trained towards a -200 dB floor and a
 prediction below -180 dB reads as "no path".  Four members (different
-initialisations, bootstrap resamples of the training set) form an
+initialisations, bootstrap resamples of the training scenes) form an
 ensemble; where the members' PG spread exceeds a threshold (1 dB) the
 caller re-runs the full SBR path for that Rx.
 
@@ -236,15 +236,12 @@ class Workspace:
             wmax = max(a.width, a.F)
             self.dout = torch.empty((n, a.T), dtype=F32, device=device)
             self.g_bf = torch.empty((n, a.T), dtype=BF16, device=device)
-            self.dh = torch.empty((n, wmax), dtype=F32, device=device)
-            self.dz = torch.empty((n, wmax), dtype=F32, device=device)
-            self.dz_bf = torch.empty((n, wmax), dtype=BF16, device=device)
+            # bf16 layer gradients, two of each so a layer's input gradient can
+            # be written while its output gradient is read
+            self.dz_bf = [torch.empty((n, wmax), dtype=BF16, device=device) for _ in range(2)]
             self.onehot = torch.empty((n, S_), dtype=BF16, device=device)
-            self.demb = torch.empty((S_, a.E), dtype=F32, device=device)
             big = max(max(c.numel() for c in self.col), S_ * a.flat, *(t.numel() for t in self.act))
-            self.sdz = torch.empty(big, dtype=F32, device=device)
-            self.sdz_bf = torch.empty(big, dtype=BF16, device=device)
-            self.sda = torch.empty(big, dtype=F32, device=device)
+            self.sdz_bf = [torch.empty(big, dtype=BF16, device=device) for _ in range(2)]
             self.sdcol = torch.empty(big, dtype=F32, device=device)
             self.loss = torch.zeros(1, dtype=torch.float64, device=device)
 
@@ -284,54 +281,66 @@ def mlp_forward(mem: Member, ws: Workspace, x: torch.Tensor, scene: torch.Tensor
     _gemm(ctx, n, a.T, fin, h, fin, 1, mem.view(mem.wbf, "out_w"), a.T, 1, mem.view(mem.w32, "out_b"), out, a.T)
 
 
+def _gemm_bwd(ctx, M, N, Kd, A, a_si, a_sk, B, b_sk, b_sj, C, ldc, flags=0, mask=None, ldm=0, bsum=None):
+    K.sbr_nn_gemm_bf16_ex(ctx, M, N, Kd, A, a_si, a_sk, B, b_sk, b_sj, None, C, ldc, flags, mask, ldm, bsum)
+
+
 def backward(mem: Member, ws: Workspace, hmap_bf: torch.Tensor, scene: torch.Tensor, n: int,
              trace: Optional[dict] = None) -> None:
     """Gradients of all parameters into mem.grad from ws.dout = d loss / d out.
-    trace: if a dict, receives copies of the bfloat16 intermediate gradients
-    (layer checks)."""
+
+    Every layer's output gradient is rounded to bf16 once, in the epilogue of
+    the product that makes it, with the ReLU backward of that layer applied
+    there (zero where the layer's output is not positive); the weight
+    gradient and the bias gradient (its column sums, as a row of ones in the
+    same product) both come from that bf16 gradient.
+    trace: if a dict, receives copies of the bf16 layer gradients (layer checks)."""
     a, ctx = mem.arch, mem.ctx
     keep = (lambda name, t: trace.__setitem__(name, t.clone())) if trace is not None else (lambda name, t: None)
     G = lambda name: mem.view(mem.grad, name)  # noqa: E731
     Wb = lambda name: mem.view(mem.wbf, name)  # noqa: E731
-    T, Wd = a.T, a.width
+    T, Wd, E = a.T, a.width, a.E
     K.sbr_nn_cast_bf16(ctx, ws.dout, n * T, ws.g_bf)
     keep("g", ws.g_bf)
     last = ws.h[a.depth - 1]
-    _gemm(ctx, Wd, T, n, last, 1, Wd, ws.g_bf, T, 1, None, G("out_w"), T)
-    K.sbr_nn_colsum(ctx, ws.dout, n, T, T, G("out_b"), 0)
-    _gemm(ctx, n, Wd, T, ws.g_bf, T, 1, Wb("out_w"), 1, T, None, ws.dh, Wd)
+    _gemm_bwd(ctx, Wd, T, n, last, 1, Wd, ws.g_bf, T, 1, G("out_w"), T, bsum=G("out_b"))
+    cur, nxt = ws.dz_bf
+    _gemm_bwd(ctx, n, Wd, T, ws.g_bf, T, 1, Wb("out_w"), 1, T, cur, Wd, K.OUT_BF16, mask=last, ldm=Wd)
     for i in reversed(range(a.depth)):
         h_in = ws.h[i - 1] if i > 0 else ws.feat
         fin = Wd if i > 0 else a.F
-        K.sbr_nn_relu_backward(ctx, ws.dh, ws.h[i], n * Wd, ws.dz, ws.dz_bf)
-        keep(f"mlp{i}", ws.dz_bf.view(-1)[:n * Wd])
-        K.sbr_nn_colsum(ctx, ws.dz, n, Wd, Wd, G(f"mlp{i}_b"), 0)
-        _gemm(ctx, fin, Wd, n, h_in, 1, fin, ws.dz_bf, Wd, 1, None, G(f"mlp{i}_w"), Wd)
-        # d input: all columns for hidden layers, only the embedding columns for the first
-        nout = fin if i > 0 else a.E
-        _gemm(ctx, n, nout, Wd, ws.dz_bf, Wd, 1, Wb(f"mlp{i}_w"), 1, Wd, None, ws.dh, nout)
-    # embedding: per-scene sum of the bf16 gradient rows, as onehot^T @ dh_emb
-    K.sbr_nn_cast_bf16(ctx, ws.dh, n * a.E, ws.dz_bf)
-    keep("dh_emb", ws.dz_bf.view(-1)[:n * a.E])
-    K.sbr_nn_onehot_bf16(ctx, scene, n, ws.S, ws.onehot)
-    _gemm(ctx, ws.S, a.E, n, ws.onehot, 1, ws.S, ws.dz_bf, a.E, 1, None, ws.demb, a.E)
+        keep(f"mlp{i}", cur.view(-1)[:n * Wd])
+        _gemm_bwd(ctx, fin, Wd, n, h_in, 1, fin, cur, Wd, 1, G(f"mlp{i}_w"), Wd, bsum=G(f"mlp{i}_b"))
+        # d input: all columns (through the ReLU of the layer below) for hidden
+        # layers, only the embedding columns for the first
+        if i > 0:
+            _gemm_bwd(ctx, n, Wd, Wd, cur, Wd, 1, Wb(f"mlp{i}_w"), 1, Wd, nxt, Wd, K.OUT_BF16, mask=ws.h[i - 1],
+                      ldm=Wd)
+        else:
+            _gemm_bwd(ctx, n, E, Wd, cur, Wd, 1, Wb(f"mlp{i}_w"), 1, Wd, nxt, E, K.OUT_BF16)
+        cur, nxt = nxt, cur
+    keep("dh_emb", cur.view(-1)[:n * E])
+    # embedding: per-scene sum of the bf16 gradient rows, as onehot^T @ dh_emb,
+    # through the embedding ReLU
     Sn = ws.S
-    K.sbr_nn_relu_backward(ctx, ws.demb, ws.emb, Sn * a.E, ws.sdz, ws.sdz_bf)
-    keep("emb", ws.sdz_bf[:Sn * a.E])
-    K.sbr_nn_colsum(ctx, ws.sdz, Sn, a.E, a.E, G("emb_b"), 0)
-    _gemm(ctx, a.flat, a.E, Sn, ws.act[-1], 1, a.flat, ws.sdz_bf, a.E, 1, None, G("emb_w"), a.E)
-    _gemm(ctx, Sn, a.flat, a.E, ws.sdz_bf, a.E, 1, Wb("emb_w"), 1, a.E, None, ws.sda, a.flat)
+    K.sbr_nn_onehot_bf16(ctx, scene, n, Sn, ws.onehot)
+    sc, sn = ws.sdz_bf
+    _gemm_bwd(ctx, Sn, E, n, ws.onehot, 1, Sn, cur, E, 1, sc, E, K.OUT_BF16, mask=ws.emb, ldm=E)
+    keep("emb", sc[:Sn * E])
+    _gemm_bwd(ctx, a.flat, E, Sn, ws.act[-1], 1, a.flat, sc, E, 1, G("emb_w"), E, bsum=G("emb_b"))
+    _gemm_bwd(ctx, Sn, a.flat, E, sc, E, 1, Wb("emb_w"), 1, E, sn, a.flat, K.OUT_BF16, mask=ws.act[-1],
+              ldm=a.flat)
+    sc, sn = sn, sc
     hw = a.stem_hw
     for i in reversed(range(a.n_conv)):
         C, Co = a.chans[i], a.chans[i + 1]
         rows = ws.act[i].shape[0]
-        K.sbr_nn_relu_backward(ctx, ws.sda, ws.act[i], rows * Co, ws.sdz, ws.sdz_bf)
-        keep(f"conv{i}", ws.sdz_bf[:rows * Co])
-        K.sbr_nn_colsum(ctx, ws.sdz, rows, Co, Co, G(f"conv{i}_b"), 0)
-        _gemm(ctx, 9 * C, Co, rows, ws.col[i], 1, 9 * C, ws.sdz_bf, Co, 1, None, G(f"conv{i}_w"), Co)
+        keep(f"conv{i}", sc[:rows * Co])
+        _gemm_bwd(ctx, 9 * C, Co, rows, ws.col[i], 1, 9 * C, sc, Co, 1, G(f"conv{i}_w"), Co, bsum=G(f"conv{i}_b"))
         if i > 0:
-            _gemm(ctx, rows, 9 * C, Co, ws.sdz_bf, Co, 1, Wb(f"conv{i}_w"), 1, Co, None, ws.sdcol, 9 * C)
-            K.sbr_nn_col2im(ctx, ws.sdcol, Sn, 2 * hw, 2 * hw, C, ws.sda)
+            _gemm_bwd(ctx, rows, 9 * C, Co, sc, Co, 1, Wb(f"conv{i}_w"), 1, Co, ws.sdcol, 9 * C)
+            K.sbr_nn_col2im_relu_backward(ctx, ws.sdcol, Sn, 2 * hw, 2 * hw, C, ws.act[i - 1], sn)
+            sc, sn = sn, sc
         hw *= 2
 
 
@@ -346,6 +355,7 @@ class Dataset:
     target: torch.Tensor        # [n][2] f32
     weight: torch.Tensor        # [n][2] f32
     pg_db: np.ndarray           # [n] SBR PG (dB; -inf where no path), host
+    scene_np: Optional[np.ndarray] = None  # [n] scene of each point, host
     meta: dict = field(default_factory=dict)
 
     @property
@@ -395,7 +405,7 @@ def make_dataset(rt: Runtime, scenes, labels, arch: Optional[Arch] = None) -> Da
         extra = torch.empty((n, arch.X), dtype=F32, device="cuda")
         K.sbr_nn_link_features(rt.ctx, raw, n, scene, hmap, arch.H, HALF_EXTENT_M, LINK_SAMPLES, x, extra)
         d = Dataset(hmap, x, extra, scene, cuda(np.concatenate(ts), F32), cuda(np.concatenate(ws), F32),
-                    np.concatenate(pgs))
+                    np.concatenate(pgs), np.concatenate(sc))
     rt.synchronize()
     return d
 
@@ -417,41 +427,67 @@ class Ensemble:
 
     # -- training
     def train(self, data: Dataset, steps: int, batch: int = 4096, lr: float = 2e-3, lr_end: float = 1e-4,
-              seed: int = 0, log=None, weight_decay: float = 0.0) -> List[float]:
-        """Adam on each member over bootstrap resamples (cosine learning-rate
-        decay); the stem runs on every training scene each step."""
+              seed: int = 0, log=None, weight_decay: float = 0.0, bootstrap: str = "scene") -> List[float]:
+        """Adam on each member over a bootstrap resample of the training
+        scenes (cosine learning-rate decay).  Resampling whole scenes, not
+        points, makes the members differ where a city unlike the training
+        cities would.  bootstrap="none" trains every member on all scenes
+        (for a handful of scenes, where a resample would leave some out)."""
+        if bootstrap not in ("scene", "none"):
+            raise ValueError(f"bootstrap must be 'scene' or 'none', not {bootstrap!r}")
         self.weight_decay = weight_decay
         with self.rt:
-            losses = self._train(data, steps, batch, lr, lr_end, seed, log)
+            losses = self._train(data, steps, batch, lr, lr_end, seed, log, bootstrap == "scene")
         self.rt.synchronize()
         return losses
 
-    def _train(self, data, steps, batch, lr, lr_end, seed, log):
+    def _train(self, data, steps, batch, lr, lr_end, seed, log, scene_boot):
+        # Each step draws a few scenes from the member's bootstrap sample of
+        # scenes (enough to hold a batch), runs the stem on their height maps
+        # only and draws the batch from their points, so the cost of a step
+        # does not grow with the number of training scenes.
         ctx, a = self.ctx, self.arch
-        valid = np.arange(data.n)
         Sn = int(data.hmap.shape[0])
-        ws = self.workspace(Sn, batch, True)
+        scene_np = data.scene_np if data.scene_np is not None else data.scene.cpu().numpy()
+        by_scene = [np.nonzero(scene_np == s)[0] for s in range(Sn)]
+        per = max(1, int(np.median([len(b) for b in by_scene])))
+        spb = min(Sn, max(8, -(-batch // per)))
+        ws = self.workspace(spb, batch, True)
+        hb = torch.empty((spb, a.H, a.H), dtype=BF16, device="cuda")
         xb = torch.empty((batch, a.D), dtype=F32, device="cuda")
         eb = torch.empty((batch, a.X), dtype=F32, device="cuda")
-        sb = torch.empty(batch, dtype=torch.int32, device="cuda")
         tb = torch.empty((batch, a.T), dtype=F32, device="cuda")
         wb = torch.empty((batch, a.T), dtype=F32, device="cuda")
         losses = []
         for mi, mem in enumerate(self.members):
             rng = np.random.Generator(np.random.PCG64(seed * 7919 + mi))
-            boot = rng.choice(valid, size=len(valid), replace=True)
-            idx_all = torch.as_tensor(rng.choice(boot, size=(steps, batch), replace=True).astype(np.int64)).cuda()
+            # the member's bootstrap sample of scenes
+            boot = rng.integers(0, Sn, size=Sn) if scene_boot else np.arange(Sn)
+            chosen = boot[rng.integers(0, Sn, size=(steps, spb))]
+            idx = np.empty((steps, batch), np.int64)
+            loc = np.empty((steps, batch), np.int32)
             for it in range(steps):
-                idx = idx_all[it]
-                K.sbr_nn_gather_rows(ctx, data.x, 4 * a.D, idx, batch, xb)
-                K.sbr_nn_gather_rows(ctx, data.extra, 4 * a.X, idx, batch, eb)
-                K.sbr_nn_gather_rows(ctx, data.scene, 4, idx, batch, sb)
-                K.sbr_nn_gather_rows(ctx, data.target, 4 * a.T, idx, batch, tb)
-                K.sbr_nn_gather_rows(ctx, data.weight, 4 * a.T, idx, batch, wb)
-                stem_forward(mem, ws, data.hmap)
+                pts = [by_scene[s] for s in chosen[it]]
+                cnt = np.array([len(p) for p in pts])
+                start = np.concatenate([[0], np.cumsum(cnt)[:-1]])
+                pick = rng.integers(0, int(cnt.sum()), size=batch)
+                which = np.searchsorted(start, pick, side="right") - 1
+                idx[it] = np.concatenate(pts)[pick]
+                loc[it] = which
+            idx_d = torch.as_tensor(idx).cuda()
+            loc_d = torch.as_tensor(loc).cuda()
+            chosen_d = torch.as_tensor(chosen.astype(np.int64)).cuda()
+            for it in range(steps):
+                ii, sb = idx_d[it], loc_d[it]
+                K.sbr_nn_gather_rows(ctx, data.hmap, 2 * a.H * a.H, chosen_d[it], spb, hb)
+                K.sbr_nn_gather_rows(ctx, data.x, 4 * a.D, ii, batch, xb)
+                K.sbr_nn_gather_rows(ctx, data.extra, 4 * a.X, ii, batch, eb)
+                K.sbr_nn_gather_rows(ctx, data.target, 4 * a.T, ii, batch, tb)
+                K.sbr_nn_gather_rows(ctx, data.weight, 4 * a.T, ii, batch, wb)
+                stem_forward(mem, ws, hb)
                 mlp_forward(mem, ws, xb, sb, batch, ws.out, keep=True, extra=eb)
                 K.sbr_nn_mse(ctx, ws.out, a.T, tb, wb, batch, a.T, 1.0 / batch, ws.dout, a.T, ws.loss)
-                backward(mem, ws, data.hmap, sb, batch)
+                backward(mem, ws, hb, sb, batch)
                 frac = it / max(steps - 1, 1)
                 mem.adam(lr_end + 0.5 * (lr - lr_end) * (1 + math.cos(math.pi * frac)), wd=self.weight_decay)
                 if log is not None and (it % 200 == 0 or it == steps - 1):
@@ -562,25 +598,35 @@ def surrogate_with_fallback(ens: Ensemble, scenes: Sequence, data: Dataset, thre
                         "fallback_stage_s": stage}
 
 
-def gate(pg_pred: np.ndarray, pg_sbr: np.ndarray) -> dict:
-    """Path-gain error against plain SBR over the Rx where SBR found a path."""
+def gate(pg_pred: np.ndarray, pg_sbr: np.ndarray, threshold_db: float = 1.0) -> dict:
+    """Path-gain error against plain SBR.  The gate is the mean absolute error
+    over the Rx where SBR found a path (a prediction of no path counts at the
+    -200 dB floor); the Rx without an SBR path are reported apart: the
+    fraction of them given a path ("false_path_frac")."""
     ok = np.isfinite(pg_sbr)
     pred = np.where(np.isfinite(pg_pred), pg_pred, PG_FLOOR_DB)
     e = np.abs(pred[ok] - pg_sbr[ok])
+    n_np = int((~ok).sum())
+    false_path = float(np.isfinite(pg_pred[~ok]).mean()) if n_np else 0.0
     if e.size == 0:
-        return {"mae_db": 0.0, "p90_db": 0.0, "p99_db": 0.0, "n": 0}
-    return {"mae_db": float(e.mean()), "p90_db": float(np.percentile(e, 90)), "p99_db": float(np.percentile(e, 99)),
-            "n": int(e.size)}
+        return {"mae_db": 0.0, "p90_db": 0.0, "p99_db": 0.0, "n": 0, "no_path_n": n_np,
+                "false_path_frac": false_path, "passed": True, "threshold_db": threshold_db}
+    mae = float(e.mean())
+    return {"mae_db": mae, "p90_db": float(np.percentile(e, 90)), "p99_db": float(np.percentile(e, 99)),
+            "n": int(e.size), "no_path_n": n_np, "false_path_frac": false_path, "passed": mae <= threshold_db,
+            "threshold_db": threshold_db}
 
 
 # ---------------------------------------------------------------- full pipeline
 @dataclass
 class PipelineConfig:
     """Radio-map surrogate workload: urban scenes of the canyon generator with
-    f_c ~ logU(28, 300) GHz and a random outdoor Tx at 25 m."""
-    train_seeds: Sequence[int] = tuple(range(5000, 5100))
+    f_c ~ logU(28, 300) GHz and a random outdoor Tx at 25 m.  100,000
+    training labels drawn as 1,000 scenes x 100 Rx (the same count as
+    100 x 1,000 with ten times the cities)."""
+    train_seeds: Sequence[int] = tuple(range(5000, 6000))
     test_seeds: Sequence[int] = tuple(range(6000, 6064))
-    n_rx_train: int = 1000
+    n_rx_train: int = 100
     n_rx_test: int = 15625
     geodesic_N: int = 1024
     max_bounces: int = 6
@@ -681,7 +727,7 @@ def run_pipeline(cfg: PipelineConfig, log=print) -> dict:
     S.sbr_profile_enable(rt.ctx, False)
     pg, tau, mask, tm = surrogate_with_fallback(ens, test, tdata, threshold_db=cfg.threshold_db)
     t_sur = tm["surrogate_s"] + tm["fallback_s"]
-    g = gate(pg, pg_ref)
+    g = gate(pg, pg_ref, 1.0)
     # other spread thresholds, reusing one prediction (fallback time measured per threshold)
     mean, spread, _ = ens.predict(tdata.hmap, tdata.x, tdata.extra, tdata.scene)
     pred = (mean.cpu().numpy(), spread.cpu().numpy())
@@ -691,7 +737,7 @@ def run_pipeline(cfg: PipelineConfig, log=print) -> dict:
         sweep.append({"threshold_db": th, "fallback_frac": float(m2.mean()), "fallback_scenes": t2["fallback_scenes"],
                       "fallback_scene_ms": t2["fallback_scene_ms"], "fallback_stage_s": t2["fallback_stage_s"],
                       "with_fallback_s": tm["surrogate_s"] + t2["fallback_s"],
-                      "gain": t_sbr / (tm["surrogate_s"] + t2["fallback_s"]), "gate": gate(p2, pg_ref)})
+                      "gain": t_sbr / (tm["surrogate_s"] + t2["fallback_s"]), "gate": gate(p2, pg_ref, 1.0)})
         log(f"[surrogate] threshold {th} dB: {sweep[-1]}")
     res["sweep"] = sweep
     res["fallback_scene_ms"] = tm["fallback_scene_ms"]
@@ -703,7 +749,8 @@ def run_pipeline(cfg: PipelineConfig, log=print) -> dict:
         "sbr_s": t_sbr, "sbr_rx_per_s": n / t_sbr,
         "surrogate_only_s": t_inf, "surrogate_only_rx_per_s": n / t_inf,
         "surrogate_s": tm["surrogate_s"], "fallback_s": tm["fallback_s"], "fallback_scenes": tm["fallback_scenes"],
-        "fallback_frac": float(mask.mean()), "with_fallback_s": t_sur, "with_fallback_rx_per_s": n / t_sur,
+        "fallback_frac": float(mask.mean()), "fallback_scene_frac": tm["fallback_scenes"] / len(test),
+        "with_fallback_s": t_sur, "with_fallback_rx_per_s": n / t_sur,
         "gain": t_sbr / t_sur, "gate": g,
         "inference_flops": flops, "mlp_flops": mlp_flops, "mlp_ms": mlp_ms, "mlp_launches": mlp_n,
         "mlp_tflops": mlp_flops / (mlp_ms * 1e-3) / 1e12 if mlp_ms > 0 else None, "stem_gemm_ms": stem_ms,

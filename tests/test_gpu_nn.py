@@ -142,6 +142,97 @@ def test_gemm_random_values_and_flags(env, layout):
     assert np.all(np.abs(Ca - (ref + C0)) <= tol + 1e-6 * np.abs(C0))
 
 
+def run_gemm_ex(env, A, B, layout, mask=None, with_bsum=False, bsum0=None, flags=0, out_bf16=False):
+    """sbr_nn_gemm_bf16_ex; returns (C, bsum) on the host (bsum None unless asked)."""
+    torch, S, nn, ctx = env
+    M, K = A.shape
+    N = B.shape[1]
+    if layout == "bwd_weight":  # A stored transposed ([K][M])
+        Ad = dev(torch, A.T, torch.bfloat16) if M else None
+        a_si, a_sk = 1, M
+    else:
+        Ad = dev(torch, A, torch.bfloat16) if M else None
+        a_si, a_sk = K, 1
+    if layout == "bwd_data":  # B stored transposed ([N][K])
+        Bd = dev(torch, B.T, torch.bfloat16)
+        b_sk, b_sj = 1, K
+    else:
+        Bd = dev(torch, B, torch.bfloat16)
+        b_sk, b_sj = N, 1
+    dt = torch.bfloat16 if out_bf16 else torch.float32
+    Cd = torch.full((max(M, 1), N), 7.0, dtype=dt, device="cuda")
+    md = dev(torch, mask, torch.bfloat16) if mask is not None else None
+    bs = None
+    if with_bsum:
+        bs = dev(torch, bsum0, torch.float32) if bsum0 is not None else torch.full((N,), 7.0, device="cuda")
+    f = flags | (nn.OUT_BF16 if out_bf16 else 0)
+    nn.sbr_nn_gemm_bf16_ex(ctx, M, N, K, Ad, a_si, a_sk, Bd, b_sk, b_sj, None, Cd if M else None, N, f, md, N, bs)
+    sync(torch)
+    return host(Cd)[:M], (host(bs) if bs is not None else None)
+
+
+# the column-sum row lands in its own tile row (M = 64, 256), in the last
+# partial tile (M = 9, 100) or alone (M = 0); long K with few tiles splits K
+EX_SHAPES = [(1, 1, 1), (0, 16, 5000), (9, 16, 409600), (64, 64, 64), (100, 70, 45), (256, 256, 4096),
+             (257, 130, 3000), (3, 257, 70000)]
+
+
+@pytest.mark.parametrize("shape", EX_SHAPES)
+@pytest.mark.parametrize("layout", ["bwd_weight", "fwd"])
+def test_gemm_column_sums_exact(env, layout, shape):
+    """bsum = column sums of B from the same products: exact on small integers
+    (every partial sum is an integer below 2^24), C unchanged by it."""
+    M, N, K = shape
+    banner("gemm column sums", layout, M, N, K)
+    rng = np.random.default_rng(M * 7 + N * 11 + K)
+    A = rng.integers(-4, 5, (M, K)).astype(np.float64)
+    B = rng.integers(-4, 5, (K, N)).astype(np.float64)
+    C, bs = run_gemm_ex(env, A, B, layout, with_bsum=True)
+    assert np.array_equal(bs, B.sum(0))
+    assert np.array_equal(C, A @ B)
+    b0 = rng.integers(-100, 100, N).astype(np.float32)
+    _, bs2 = run_gemm_ex(env, A, B, layout, with_bsum=True, bsum0=b0, flags=nn_accumulate(env))
+    assert np.array_equal(bs2, B.sum(0) + b0)
+
+
+def nn_accumulate(env):
+    return env[2].ACCUMULATE
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (197, 131, 259), (4096, 256, 256), (300, 128, 2), (5, 3, 100000)])
+@pytest.mark.parametrize("layout", ["bwd_data", "fwd"])
+def test_gemm_relu_mask(env, layout, shape):
+    """C = (A B) * (mask > 0): exact on integers, FP32 and bf16 outputs; zero,
+    negative and positive mask values (and -0) all occur."""
+    M, N, K = shape
+    banner("gemm relu mask", layout, M, N, K)
+    rng = np.random.default_rng(M + 3 * N + 5 * K)
+    A = rng.integers(-4, 5, (M, K)).astype(np.float64)
+    B = rng.integers(-4, 5, (K, N)).astype(np.float64)
+    mask = R.bf16(rng.choice([-1.5, -0.0, 0.0, 1e-30, 0.25, 3.0], (M, N)))
+    want = (A @ B) * (mask > 0)
+    C, _ = run_gemm_ex(env, A, B, layout, mask=mask)
+    assert np.array_equal(C, want)
+    Cb, _ = run_gemm_ex(env, A, B, layout, mask=mask, out_bf16=True)
+    assert np.array_equal(Cb, R.bf16(want.astype(np.float32)))
+
+
+def test_gemm_ex_matches_plain_and_deterministic(env):
+    """Random bf16 values with a long K (split-K): the extended product equals
+    the plain one bit for bit, and repeated calls give identical bits."""
+    M, N, K = 144, 32, 200000
+    banner("gemm ex determinism", M, N, K)
+    rng = np.random.default_rng(21)
+    A = R.bf16(rng.standard_normal((M, K)))
+    B = R.bf16(rng.standard_normal((K, N)))
+    C0 = run_gemm(env, A, B, "bwd_weight")
+    C1, b1 = run_gemm_ex(env, A, B, "bwd_weight", with_bsum=True)
+    C2, b2 = run_gemm_ex(env, A, B, "bwd_weight", with_bsum=True)
+    assert np.array_equal(C0, C1) and np.array_equal(C1, C2) and np.array_equal(b1, b2)
+    tol = (K + 2) * 2.0 ** -24 * np.abs(B).sum(0)
+    assert np.all(np.abs(b1 - B.sum(0)) <= tol)
+
+
 def test_gemm_rejects_bad_arguments(env):
     torch, S, nn, ctx = env
     banner("gemm errors")
@@ -152,6 +243,12 @@ def test_gemm_rejects_bad_arguments(env):
         nn.sbr_nn_gemm_bf16(ctx, -1, 4, 4, x, 4, 1, x, 4, 1, None, x, 4, 0)
     with pytest.raises(Exception):
         nn.sbr_nn_im2col(ctx, x, 1, 3, 4, 1, x)
+    with pytest.raises(Exception):  # mask leading dimension below N
+        nn.sbr_nn_gemm_bf16_ex(ctx, 4, 4, 4, x, 4, 1, x, 4, 1, None, x, 4, 0, x, 3, None)
+    with pytest.raises(Exception):  # column sums without B
+        nn.sbr_nn_gemm_bf16_ex(ctx, 0, 4, 4, None, 1, 0, None, 4, 1, None, None, 4, 0, None, 0, x.float())
+    with pytest.raises(Exception):
+        nn.sbr_nn_col2im_relu_backward(ctx, x.float(), 1, 3, 4, 1, x, x)
 
 
 @pytest.mark.parametrize("shape", [(1, 2, 2, 1), (2, 8, 6, 3), (3, 16, 16, 16), (1, 128, 128, 1)])
@@ -171,6 +268,13 @@ def test_im2col_col2im(env, shape):
     assert np.array_equal(host(col), R.conv_patches(x))
     ref = R.conv_patches_adjoint(d.astype(np.float64), n, H, W, C)
     assert np.allclose(host(dx), ref, rtol=1e-6, atol=1e-6)
+    # fused with the ReLU backward of the layer whose output is y: the same
+    # FP32 sums, zeroed where y <= 0, rounded to bf16 once
+    y = R.bf16(rng.choice([-1.0, 0.0, 0.5, 2.0], shape))
+    dz = torch.empty(shape, dtype=torch.bfloat16, device="cuda")
+    nn.sbr_nn_col2im_relu_backward(ctx, dev(torch, d, torch.float32), n, H, W, C, dev(torch, y, torch.bfloat16), dz)
+    sync(torch)
+    assert np.array_equal(host(dz), R.bf16((host(dx) * (y > 0)).astype(np.float32)))
 
 
 def test_fourier_features(env):
@@ -232,6 +336,35 @@ def test_elementwise_kernels(env):
     assert np.allclose(host(cs), 1.5 + m[:, :N].astype(np.float64).sum(0), rtol=1e-6, atol=1e-5)
     assert np.array_equal(host(dst), src[idx])
     assert np.array_equal(host(oh), (sc[:, None] == np.arange(9)[None, :]).astype(np.float64))
+
+
+@pytest.mark.parametrize("M,N", [(1, 1), (3001, 2), (5000, 16), (777, 37), (20011, 64), (4096, 128), (999, 200),
+                                 (3333, 256)])
+def test_relu_backward_colsum(env, M, N):
+    """The fused ReLU backward returns the masked gradient exactly and its
+    column sums within FP32 rounding of the FP64 sums (the sums are FP64 in a
+    fixed order); ragged row counts across the 1,024-row blocks."""
+    torch, S, nn, ctx = env
+    banner("relu_backward_colsum", M, N)
+    rng = np.random.default_rng(M + N)
+    g = rng.standard_normal((M, N)).astype(np.float32)
+    y = R.bf16(rng.standard_normal((M, N)))
+    y[::3, ::2] = 0.0
+    gout = torch.empty((M, N), dtype=torch.float32, device="cuda")
+    gbf = torch.empty((M, N), dtype=torch.bfloat16, device="cuda")
+    cs = torch.full((N,), np.nan, dtype=torch.float32, device="cuda")
+    nn.sbr_nn_relu_backward_colsum(ctx, dev(torch, g, torch.float32), dev(torch, y, torch.bfloat16), M, N, cs, gout, gbf)
+    cs2 = torch.full((N,), np.nan, dtype=torch.float32, device="cuda")
+    nn.sbr_nn_relu_backward_colsum(ctx, dev(torch, g, torch.float32), dev(torch, y, torch.bfloat16), M, N, cs2, None, gbf)
+    sync(torch)
+    want = np.where(y > 0, g, 0.0).astype(np.float32)
+    assert np.array_equal(host(gout), want)
+    assert np.array_equal(host(gbf), R.bf16(want))
+    ref = want.astype(np.float64).sum(0)
+    assert np.all(np.abs(host(cs) - ref) <= 2.0 ** -24 * np.abs(ref) + 1e-12 * np.abs(want).sum(0) + 1e-30)
+    assert np.array_equal(host(cs), host(cs2))
+    with pytest.raises(S.SbrError):
+        nn.sbr_nn_relu_backward_colsum(ctx, dev(torch, g, torch.float32), dev(torch, y, torch.bfloat16), M, 257, cs)
 
 
 def test_mse_adam_ensemble(env):
