@@ -436,7 +436,11 @@ def main():
     S.sbr_context_set_tuning(ctx, "trace_leaf_share", share)
     del sc, tr
     bounce_ms = kernels.get("bounce", {}).get("ms_per_step", float("nan"))
-    launches = kernels.get("bounce", {}).get("launches_per_step", float("nan"))
+    # k_bounce runs once per bounce (K + 1 launches per trace) whether the
+    # bounces are launched directly or replayed as one graph (whose event
+    # pair then brackets all of them and the counter clear before them)
+    launches = w.max_bounces + 1
+    kernels.get("bounce", {})["kernel_launches_per_step"] = launches
     traffic = committed_traffic(w.name)
     # HBM roofline on the algorithmic segment stream: bytes per launch over
     # the average launch time (both per step here, same ratio)
@@ -451,6 +455,7 @@ def main():
                 "bytes_per_segment": SEG_BYTES,
                 "kernel": "k_bounce (closest-hit traversal + FP64 reflect + ballot compaction)",
                 "segments_per_step": segments, "launches_per_step": launches, "ms_per_step": round(bounce_ms, 3),
+                "ms_per_launch": round(bounce_ms / launches, 4),
                 "valu": {"achieved": round(valu, 3), "peak": PEAK_FP32_TFLOPS, "unit": "Tops/s",
                          "frac": round(valu / PEAK_FP32_TFLOPS, 4), "ops_per_node": OPS_PER_NODE,
                          "ops_per_tri": OPS_PER_TRI, "node_visits_per_step": work["node_visits"],

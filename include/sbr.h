@@ -197,6 +197,18 @@ sbr_status sbr_capacity(sbr_context_t ctx, const void* H_c64, int32_t Nf, int32_
                         const double* snr_db, int32_t Nsnr, int32_t normalize, double* C_bits_per_hz,
                         uint32_t flags);
 
+/* Received power per antenna port pair, eq. (14): h_qp = sqrt(P_qp) e^{i theta_qp}
+ * with the paths of (p, q) combined with phase in H (sbr_channel), so
+ * P[q][p] = (1/Nf) sum_f |H_f[q][p]|^2, the band mean (FP64; FP32 H entries
+ * squared exactly).  The spread of P over the Rx ports of an array is the
+ * spatial non-stationarity of Sec. IV-C.  H_c64: [Nf][Nr][Nt] interleaved
+ * FP32 (host, or device with SBR_IN_DEVICE; a device H is read in place);
+ * P: [Nr][Nt] FP64 (host, or device with SBR_OUT_DEVICE: then the call is
+ * queued on the context stream and returns without waiting).  Deterministic:
+ * the band is summed in a fixed order. */
+sbr_status sbr_port_power(sbr_context_t ctx, const void* H_c64, int32_t Nf, int32_t Nr, int32_t Nt, double* P,
+                          uint32_t flags);
+
 /* Allocation-free form of sbr_capacity, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid allocation).  Same result as sbr_capacity.

@@ -510,6 +510,42 @@ void run_stats(sbr_paths_s* ps, float* pg_db, float* tau, float* angles, hipStre
   SBR_LAUNCH_CHECK();
 }
 
+// ---------------------------------------------------------------- per-port power
+// Received power of every (Rx port q, Tx port p) entry with its paths combined
+// with phase (eq. (14): h_qp = sqrt(P_qp) e^{i theta_qp}), averaged over the
+// band: P[q][p] = (1/Nf) sum_f |H_f[q][p]|^2 in FP64.  64 entries per block,
+// one per lane (64 consecutive entries of one frequency plane per wave load);
+// wave w sums the w-th sixteenth of the band in frequency order and the
+// sixteen sums are added in wave order.
+constexpr int kPortWaves = 16;
+__global__ __launch_bounds__(64 * kPortWaves) void k_port_power(const float2* __restrict__ H, int Nf, int64_t nq,
+                                                                 double* __restrict__ P) {
+  __shared__ double part[kPortWaves][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t e = (int64_t)blockIdx.x * 64 + lane;
+  const int per = (Nf + kPortWaves - 1) / kPortWaves, f0 = w * per, f1 = min(Nf, f0 + per);
+  double acc = 0.0;
+  if (e < nq)
+    for (int f = f0; f < f1; ++f) {
+      const float2 h = H[(int64_t)f * nq + e];
+      acc += (double)h.x * (double)h.x + (double)h.y * (double)h.y;
+    }
+  part[w][lane] = acc;
+  __syncthreads();
+  if (w == 0 && e < nq) {
+    double t = 0.0;
+    for (int i = 0; i < kPortWaves; ++i) t += part[i][lane];
+    P[e] = t / Nf;
+  }
+}
+
+void run_port_power(const float2* H, int Nf, int Nr, int Nt, double* P, hipStream_t s) {
+  const int64_t nq = (int64_t)Nr * Nt;
+  ::sbr::TimedLaunch tl_("port_power", s);
+  hipLaunchKernelGGL(k_port_power, dim3((unsigned)((nq + 63) / 64)), dim3(64 * kPortWaves), 0, s, H, Nf, nq, P);
+  SBR_LAUNCH_CHECK();
+}
+
 void run_capacity(const float2* H, int Nf, int Nr, int Nt, const double* snr_db, int Nsnr, int normalize,
                   double* C_out, hipStream_t s) {
   const int n = std::min(Nr, Nt);

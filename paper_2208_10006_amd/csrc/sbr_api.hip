@@ -1372,6 +1372,34 @@ sbr_status sbr_capacity(sbr_context_t ctx, const void* H_c64, int32_t Nf, int32_
   });
 }
 
+sbr_status sbr_port_power(sbr_context_t ctx, const void* H_c64, int32_t Nf, int32_t Nr, int32_t Nt, double* P,
+                          uint32_t flags) {
+  return guard([&] {
+    auto* c = check_handle<sbr_context_s>(ctx, kContext, "context");
+    SBR_CHECK(Nf >= 1 && Nr >= 1 && Nt >= 1, SBR_E_INVALID_ARG, "port power sizes");
+    SBR_CHECK(H_c64 && P, SBR_E_INVALID_ARG, "NULL argument");
+    set_device(c);
+    hipStream_t s = c->stream;
+    const size_t nq = (size_t)Nr * Nt;
+    Buf h, out;
+    const float2* Hd = static_cast<const float2*>(H_c64);
+    if (!(flags & SBR_IN_DEVICE)) {
+      upload(h, Hd, (size_t)Nf * nq, flags, s);
+      Hd = h.as<float2>();
+    }
+    double* Pd = P;
+    if (!(flags & SBR_OUT_DEVICE)) {
+      out.alloc(nq * 8, s);
+      Pd = out.as<double>();
+    }
+    run_port_power(Hd, Nf, Nr, Nt, Pd, s);
+    if (!(flags & SBR_OUT_DEVICE)) {
+      SBR_HIP(hipMemcpyAsync(P, Pd, nq * 8, hipMemcpyDeviceToHost, s));
+      SBR_HIP(hipStreamSynchronize(s));
+    }
+  });
+}
+
 sbr_status sbr_capacity_noalloc(sbr_context_t ctx, const void* H_c64, int32_t Nf, int32_t Nr, int32_t Nt,
                                 const double* snr_db, int32_t Nsnr, int32_t normalize, double* C) {
   return guard([&] {

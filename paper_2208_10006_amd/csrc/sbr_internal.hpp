@@ -375,6 +375,8 @@ void run_path_field(sbr_paths_s* ps, const ChannelArgs& a, double2* out, hipStre
 void run_stats(sbr_paths_s* ps, float* pg_db, float* tau, float* angles, hipStream_t s);
 void run_capacity(const float2* H, int Nf, int Nr, int Nt, const double* snr_db, int Nsnr, int normalize,
                   double* C_out, hipStream_t s);
+// P[q][p] = band mean of |H_f[q][p]|^2 (FP64), H [Nf][Nr][Nt]
+void run_port_power(const float2* H, int Nf, int Nr, int Nt, double* P, hipStream_t s);
 // allocation-free capacity: a fixed device array of kCapScratchBytes per GPU
 constexpr size_t kCapScratchBytes = size_t(8) << 20;
 constexpr int kMaxDevices = 64;

@@ -72,6 +72,7 @@ def _load():
         "sbr_path_field": [P, P, P, I32, P, P, I32, I32, P, U32],
         "sbr_stats": [P, P, P, P, U32],
         "sbr_capacity": [P, P, I32, I32, I32, P, I32, I32, P, U32],
+        "sbr_port_power": [P, P, I32, I32, I32, P, U32],
         "sbr_capacity_noalloc": [P, P, I32, I32, I32, P, I32, I32, P],
         "sbr_geodesic": [P, I32, I64, I64, P, U32],
         "sbr_geodesic_alpha": [P, I32, P, P, P],
@@ -381,6 +382,23 @@ def sbr_capacity(ctx: Context, H_c64, snr_db, normalize: int = 1):
     out = np.zeros(ns, np.float64)
     _call("sbr_capacity", ctx.h, h.ptr, Nf, Nr, Nt, s.ptr, ns, int(normalize), out.ctypes.data_as(C.c_void_p),
           _flags([h, s], SBR_IN_DEVICE))
+    return out
+
+
+def sbr_port_power(ctx: Context, H_c64, out=None):
+    """P[q][p] = band mean of |H_f[q][p]|^2 (FP64).  H_c64: complex64 [Nf, Nr, Nt]
+    (numpy or a contiguous device tensor).  out: None (returns numpy [Nr, Nt]) or a
+    float64 device tensor of Nr*Nt values (queued on the context stream)."""
+    h = _Arr(H_c64, np.complex64)
+    Nf, Nr, Nt = tuple(h.ref.shape)[:3]
+    if out is None:
+        res = np.zeros((Nr, Nt), np.float64)
+        _call("sbr_port_power", ctx.h, h.ptr, Nf, Nr, Nt, res.ctypes.data_as(C.c_void_p), _flags([h], SBR_IN_DEVICE))
+        return res
+    if not (_is_torch(out) and out.is_cuda and out.dtype == F64 and out.is_contiguous() and out.numel() >= Nr * Nt):
+        raise ValueError("out must be a contiguous float64 device tensor of Nr*Nt values")
+    _call("sbr_port_power", ctx.h, h.ptr, Nf, Nr, Nt, C.c_void_p(out.data_ptr()),
+          _flags([h], SBR_IN_DEVICE) | SBR_OUT_DEVICE)
     return out
 
 
