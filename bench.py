@@ -56,6 +56,8 @@ def make_inputs(w, torch, dev):
     d["H"] = torch.empty((Nf, Nr, Nt), dtype=torch.complex64, device=dev)
     # MIMO capacity (eq. 15-17) at SNR 0, 5, ..., 30 dB when both ends are arrays
     d["snr"] = t(list(range(0, 31, 5)), torch.float64) if Nr > 1 and Nt > 1 else None
+    # received power per antenna port pair (eq. (14), band mean of |H|^2)
+    d["P"] = torch.empty((Nr, Nt), dtype=torch.float64, device=dev) if Nr > 1 and Nt > 1 else None
     d["pg"] = torch.empty((Nr, Nt), dtype=torch.float32, device=dev)
     d["tau"] = torch.empty((Nr, Nt), dtype=torch.float32, device=dev)
     d["ang"] = torch.empty((Nr, Nt, 4), dtype=torch.float32, device=dev)
@@ -69,6 +71,8 @@ def step(S, ctx, w, d):
     S.sbr_channel(ctx, ps, d["freq"], d["atm"], None, S.SBR_POL_V, S.SBR_POL_V, H_c64=d["H"])
     if d.get("snr") is not None:
         d["capacity"] = S.sbr_capacity(ctx, d["H"], d["snr"])
+    if d.get("P") is not None:
+        S.sbr_port_power(ctx, d["H"], d["P"])
     S.sbr_stats_device(ps, d["pg"], d["tau"], d["ang"])
     return sc, tr, ps
 
@@ -268,6 +272,83 @@ def batched_main(args):
     print(json.dumps(out), flush=True)
 
 
+def mimo_main(args):
+    """n x n MIMO in the office (Sec. IV-C, Fig. 6 and 7): for each n, the
+    whole path (scene, trace, receive, channel, statistics, capacity, per-port
+    power) on n Tx x n Rx UPAs; capacity over SNR per n and the received power
+    of every Rx port of the largest array."""
+    import numpy as np
+    import torch
+    from paper_2208_10006_amd import autotune as A
+    from paper_2208_10006_amd import sbr as S
+    from paper_2208_10006_amd import workloads as W
+
+    sizes = [int(x) for x in args.mimo_sizes.split(",") if x]
+    dev = torch.device("cuda", 0)
+    ctx = S.context_for_torch(0)
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    rows = []
+    for n in sizes:
+        w = W.mimo_office(n)
+        d = make_inputs(w, torch, dev)
+        sc0 = S.sbr_scene_build(ctx, d["tri"], d["eps"], d["sig"], d["rough"])
+        tuned = A.autotune_trace(ctx, sc0, d["tx"], w.geodesic_N, w.max_bounces, w.T, arch=arch)
+        del sc0
+        for _ in range(args.warmup):
+            h = step(S, ctx, w, d)
+            del h
+        torch.cuda.synchronize()
+        S.sbr_profile_only(ctx, "bounce")
+        S.sbr_profile_enable(ctx, True)
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            handles = step(S, ctx, w, d)
+            if i + 1 < args.steps:
+                del handles
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        bounce_ms, _ = S.sbr_profile_query(ctx, "bounce")
+        S.sbr_profile_enable(ctx, False)
+        sc, tr, ps = handles
+        seg = S.sbr_trace_info(tr)["segments"]
+        paths = S.sbr_paths_info(ps)["paths"]
+        del sc, tr, ps, handles
+        P = d["P"].cpu().numpy()  # [Rx port][Tx port], W
+        port_db = 10 * np.log10(P.mean(axis=1))  # each Rx port, averaged over the Tx ports
+        row = {"n": n, "upa": list(w.meta["upa"]), "ms_per_step": (t1 - t0) * 1e3 / args.steps,
+               "bounce_ms_per_step": bounce_ms / args.steps, "segments_per_step": seg, "paths": paths,
+               "capacity_bits_per_hz_snr_0_to_30_db": [round(float(v), 4) for v in d["capacity"]],
+               "port_power_db": {"min": float(port_db.min()), "max": float(port_db.max()),
+                                 "std": float(port_db.std()),
+                                 "mean_abs_step_between_neighbours": float(np.abs(np.diff(port_db)).mean())},
+               "tuning": tuned["config"]}
+        if n == max(sizes):
+            row["port_power_db"]["per_rx_port"] = [round(float(v), 3) for v in port_db]
+        rows.append(row)
+        log(f"[bench] mimo {n}x{n}: {row['ms_per_step']:.2f} ms/step, {seg} segments, "
+            f"C(30 dB) {row['capacity_bits_per_hz_snr_0_to_30_db'][-1]:.2f} bit/s/Hz, "
+            f"port power {port_db.min():.2f}..{port_db.max():.2f} dB")
+        del d
+        torch.cuda.empty_cache()
+    seg = sum(r["segments_per_step"] for r in rows)
+    ms = sum(r["ms_per_step"] for r in rows)
+    bms = sum(r["bounce_ms_per_step"] for r in rows)
+    gbs = SEG_BYTES * seg / (bms * 1e-3) / 1e9
+    out = {"metric": "traced ray-segments/s", "value": seg / (ms * 1e-3), "unit": "ray-segments/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32 traversal / f64 ray state, phase and H",
+           "data": "synthetic",
+           "config": {"workload": "n x n MIMO sweep in the office hall (5,004 tri): n-element Tx and Rx UPAs at "
+                                  f"lambda/2, n in {sizes}, N=316, K=4, 1024 subcarriers over 99-101 GHz; "
+                                  "one step = the whole path for every n",
+                      "segments_per_step": seg},
+           "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                        "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None,
+                        "kernel": "k_bounce over the sweep", "bytes_per_segment": SEG_BYTES},
+           "sweep": rows}
+    print(json.dumps(out), flush=True)
+
+
 PEAK_BF16_TFLOPS = 2500.0
 
 
@@ -357,6 +438,7 @@ def main():
     ap.add_argument("--tail-contexts", type=int, default=8,
                     help="batched_uneven: contexts (streams and host threads) for the per-scene receives")
     ap.add_argument("--surrogate-steps", type=int, default=0, help="surrogate: training steps per member")
+    ap.add_argument("--mimo-sizes", default="16,32,64,128", help="mimo_sweep: array sizes n (n Tx x n Rx)")
     ap.add_argument("--bvh-ploc-max", type=int, default=None,
                     help="largest scene (triangles) clustered with PLOC; larger ones use the LBVH")
     args = ap.parse_args()
@@ -372,6 +454,9 @@ def main():
         return batched_main(args)
     if args.workload == "surrogate":
         return surrogate_main(args)
+    if args.workload == "mimo_sweep":
+        return mimo_main(args)
+    import numpy as np
     import torch
     from paper_2208_10006_amd import sbr as S
     from paper_2208_10006_amd import workloads as W
@@ -471,7 +556,10 @@ def main():
            "config": {"workload": describe(w),
                       "segments_per_step": segments, "paths": pinfo["paths"], "capture_events": pinfo["events"],
                       "capacity_bits_per_hz_snr_0_to_30_db": [round(float(v), 4) for v in d["capacity"]]
-                      if d.get("capacity") is not None else None},
+                      if d.get("capacity") is not None else None,
+                      "rx_port_power_db": [round(float(v), 3) for v in
+                                           10 * np.log10(d["P"].cpu().numpy().mean(axis=1))]
+                      if d.get("P") is not None else None},
            "kernels": kernels, "roofline": roofline, "tuning": tuned["config"]}
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle on a sample) ...")

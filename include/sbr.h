@@ -214,7 +214,7 @@ sbr_status sbr_port_power(sbr_context_t ctx, const void* H_c64, int32_t Nf, int3
  * harnesses that forbid allocation).  Same result as sbr_capacity.
  * H_c64: device pointer [Nf][Nr][Nt] interleaved FP32 on the context's
  * device; C_bits_per_hz: device pointer [Nsnr] FP64; snr_db: host array of
- * Nsnr values (passed to the kernels by value).  Limits: min(Nr, Nt) <= 64,
+ * Nsnr values (passed to the kernels by value).  Limits: min(Nr, Nt) <= 128,
  * Nsnr <= 64, Nf * (Nsnr + 1) <= 1,048,544 (SBR_E_CAPACITY beyond).  Queued
  * on the context stream without waiting; the work lives in one fixed 8 MiB
  * device array per GPU that every call on that GPU shares, so calls that

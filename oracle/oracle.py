@@ -258,6 +258,14 @@ def capacity(H: np.ndarray, snr_db, normalize: bool = True) -> np.ndarray:
     return np.array(out)
 
 
+def port_power(H: np.ndarray) -> np.ndarray:
+    """eq. (14): h_qp = sqrt(P_qp) e^{i theta_qp}, the paths of Tx port p and Rx
+    port q combined with their phases in H; P[q][p] is the band mean of
+    |H_f[q][p]|^2 (the received power per antenna port of Sec. IV-C, Fig. 7)."""
+    H = np.asarray(H, np.complex128)
+    return np.mean(H.real ** 2 + H.imag ** 2, axis=0)
+
+
 @dataclass
 class FullResult:
     trace: TraceResult

@@ -262,85 +262,6 @@ __global__ __launch_bounds__(256) void k_cap_scale(const double* __restrict__ fr
   }
 }
 
-// block per frequency: W = s^2 Hn Hn^H (n = min(Nr, Nt)), then for every SNR
-// a Cholesky factor of I + SNR/Nt W and log2 det = 2 sum log2 L_ii.
-__global__ __launch_bounds__(256) void k_cap_logdet(const float2* __restrict__ H, int Nr, int Nt,
-                                                    const double* __restrict__ scale2, const double* __restrict__ snr_db,
-                                                    int Nsnr, double2* __restrict__ work, double* __restrict__ cf) {
-  const int f = blockIdx.x;
-  const int n = Nr <= Nt ? Nr : Nt;
-  const int m = Nr <= Nt ? Nt : Nr;
-  const bool rows = Nt >= Nr;  // W = H H^H over columns; else W = H^H H over rows
-  const float2* Hf = H + (int64_t)f * Nr * Nt;
-  double2* W = work + (int64_t)f * 2 * n * n;
-  double2* M = W + (int64_t)n * n;
-  const double s2 = *scale2;
-  for (int e = threadIdx.x; e < n * n; e += 256) {
-    const int i = e / n, j = e - (e / n) * n;
-    double re = 0.0, im = 0.0;
-    for (int t = 0; t < m; ++t) {
-      // a = X[i][t], b = X[j][t] with X = H (rows) or H^T conj'd (cols)
-      float2 a, b;
-      if (rows) {
-        a = Hf[(int64_t)i * Nt + t], b = Hf[(int64_t)j * Nt + t];
-        // a * conj(b)
-        re += (double)a.x * b.x + (double)a.y * b.y;
-        im += (double)a.y * b.x - (double)a.x * b.y;
-      } else {
-        a = Hf[(int64_t)t * Nt + i], b = Hf[(int64_t)t * Nt + j];
-        // conj(a) * b
-        re += (double)a.x * b.x + (double)a.y * b.y;
-        im += (double)a.x * b.y - (double)a.y * b.x;
-      }
-    }
-    W[e] = make_double2(re * s2, im * s2);
-  }
-  __syncthreads();
-  __shared__ double logs[256];
-  for (int si = 0; si < Nsnr; ++si) {
-    const double g = pow(10.0, snr_db[si] / 10.0) / Nt;
-    for (int e = threadIdx.x; e < n * n; e += 256) {
-      const int i = e / n, j = e - (e / n) * n;
-      double2 w = W[e];
-      M[e] = make_double2((i == j ? 1.0 : 0.0) + g * w.x, g * w.y);
-    }
-    __syncthreads();
-    // right-looking Cholesky, lower triangle, in place
-    for (int j = 0; j < n; ++j) {
-      const double djj = sqrt(M[j * n + j].x);
-      __syncthreads();
-      for (int i = j + 1 + threadIdx.x; i < n; i += 256) {
-        double2 v = M[i * n + j];
-        M[i * n + j] = make_double2(v.x / djj, v.y / djj);
-      }
-      __syncthreads();
-      if (threadIdx.x == 0) M[j * n + j] = make_double2(djj, 0.0);
-      const int rem = n - j - 1;
-      for (int e = threadIdx.x; e < rem * rem; e += 256) {
-        const int i = j + 1 + e / rem, l = j + 1 + (e - (e / rem) * rem);
-        if (l > i) continue;
-        const double2 a = M[i * n + j], b = M[l * n + j];
-        // M[i][l] -= a * conj(b)
-        double2 c = M[i * n + l];
-        c.x -= a.x * b.x + a.y * b.y;
-        c.y -= a.y * b.x - a.x * b.y;
-        M[i * n + l] = c;
-      }
-      __syncthreads();
-    }
-    double lg = 0.0;
-    for (int i = threadIdx.x; i < n; i += 256) lg += log2(M[i * n + i].x);
-    logs[threadIdx.x] = lg;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-      if (threadIdx.x < o) logs[threadIdx.x] += logs[threadIdx.x + o];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) cf[(int64_t)si * gridDim.x + f] = 2.0 * logs[0];
-    __syncthreads();
-  }
-}
-
 __global__ __launch_bounds__(256) void k_cap_mean(const double* __restrict__ cf, int Nf, int Nsnr,
                                                   double* __restrict__ out) {
   __shared__ double sm[256];
@@ -471,6 +392,141 @@ __global__ __launch_bounds__(256) void k_cap_logdet_reg(const float2* __restrict
   }
 }
 
+// Capacity for kCapRegN < n <= kCapBigN: the same elimination on 128 x 128
+// matrices with 1,024 threads; thread t owns the 4 x 4 tile (ti, tj) =
+// (t / 32, t % 32).  W and every trailing matrix of the elimination are
+// Hermitian, so only tiles on or below the diagonal (tj <= ti, 528 of them)
+// are formed and updated.  W stays in LDS between SNRs (tile stride 17
+// entries against bank conflicts; during the Gram the front of that array
+// holds the X chunk), the tile being factorised in registers.
+constexpr int kCapBigN = 128;
+constexpr int kCapBigSide = kCapBigN / 4;                            // 32 tiles per side
+constexpr int kCapBigTiles = kCapBigSide * (kCapBigSide + 1) / 2;  // 528
+constexpr int kCapTileStride = 17;                                  // double2 per tile in LDS
+static_assert(kCapChunk * (kCapBigN + 2) * sizeof(float2) <= kCapBigTiles * kCapTileStride * sizeof(double2),
+              "the X chunk fits in the W array");
+
+__global__ __launch_bounds__(1024) void k_cap_logdet_big(const float2* __restrict__ H, int Nr, int Nt,
+                                                         const double* __restrict__ scale2,
+                                                         const double* __restrict__ snr_dev, const CapSnr snr_val,
+                                                         int Nsnr, double* __restrict__ cf) {
+  const int f = blockIdx.x, Nf = gridDim.x;
+  const int n = Nr <= Nt ? Nr : Nt;
+  const int m = Nr <= Nt ? Nt : Nr;
+  const bool rows = Nt >= Nr;
+  const int t = threadIdx.x, ti = t >> 5, tj = t & 31;
+  const bool lower = tj <= ti;
+  const int tile = ti * (ti + 1) / 2 + tj;
+  __shared__ double2 wsm[kCapBigTiles * kCapTileStride];
+  __shared__ double2 colb[2][kCapBigN];
+  float2(*xs)[kCapBigN + 2] = reinterpret_cast<float2(*)[kCapBigN + 2]>(wsm);
+  const float2* Hf = H + (int64_t)f * Nr * Nt;
+  double2 w[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) w[i][j] = make_double2(0.0, 0.0);
+  for (int c0 = 0; c0 < m; c0 += kCapChunk) {
+    const int nc = m - c0 < kCapChunk ? m - c0 : kCapChunk;
+    __syncthreads();
+    for (int e = t; e < kCapChunk * kCapBigN; e += 1024) {
+      int r, c;
+      if (rows) r = e / kCapChunk, c = e - r * kCapChunk;  // X[r][c0 + c] = H[r][c0 + c]: along c
+      else c = e / kCapBigN, r = e - c * kCapBigN;         // X[r][c0 + c] = H[c0 + c][r]: along r
+      float2 v = make_float2(0.0f, 0.0f);
+      if (r < n && c < nc) v = rows ? Hf[(int64_t)r * Nt + c0 + c] : Hf[(int64_t)(c0 + c) * Nt + r];
+      xs[c][r] = v;
+    }
+    __syncthreads();
+    if (lower) {
+      for (int c = 0; c < nc; ++c) {
+        float2 b[4];  // kept in FP32 (exact) to stay within 128 registers
+#pragma unroll
+        for (int k = 0; k < 4; ++k) b[k] = xs[c][4 * tj + k];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float2 x = xs[c][4 * ti + i];
+          const double ax = x.x, ay = x.y;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {  // w += a_i conj(b_j)
+            const double bx = b[j].x, by = b[j].y;
+            w[i][j].x += ax * bx + ay * by;
+            w[i][j].y += ay * bx - ax * by;
+          }
+        }
+      }
+    }
+  }
+  const double s2 = *scale2;
+  __syncthreads();  // every thread is done with the X chunk
+  if (lower) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) wsm[tile * kCapTileStride + 4 * i + j] = make_double2(w[i][j].x * s2, w[i][j].y * s2);
+  }
+  // the SNR factors before the elimination and the logarithms after it, so
+  // that no constant of pow or log2 stays live (in registers) through it
+  __shared__ double gs[kCapSnrMax], pm[kCapSnrMax];
+  __shared__ int pe[kCapSnrMax];
+  if (t < Nsnr) gs[t] = pow(10.0, (snr_dev ? snr_dev[t] : snr_val.db[t]) / 10.0) / Nt;
+  __syncthreads();
+  for (int si = 0; si < Nsnr; ++si) {
+    const double g = gs[si];
+    double2 M[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const double2 v = lower ? wsm[tile * kCapTileStride + 4 * i + j] : make_double2(0.0, 0.0);
+        M[i][j] = make_double2((4 * ti + i == 4 * tj + j ? 1.0 : 0.0) + g * v.x, g * v.y);
+      }
+    double pmant = 1.0;  // product of the pivots as pmant * 2^pexp (thread 0)
+    int pexp = 0;
+    for (int jb = 0; jb < kCapBigSide; ++jb) {
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int j = 4 * jb + jj;
+        double2* buf = colb[j & 1];
+        // column j below the diagonal lives in the tiles (ti >= jb, jb)
+        if (tj == jb && lower) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) buf[4 * ti + i] = M[i][jj];
+        }
+        __syncthreads();
+        const double d = buf[j].x;
+        if (t == 0) {
+          int e;
+          pmant = frexp(pmant * d, &e);
+          pexp += e;
+        }
+        if (lower && tj >= jb) {  // the trailing submatrix (ti >= tj >= jb)
+          const double inv = 1.0 / d;
+          double2 cl[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) cl[k] = buf[4 * tj + k];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const double2 ci = buf[4 * ti + i];
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {
+              if (4 * ti + i > j && 4 * tj + l > j) {  // M_il -= c_i conj(c_l) / d
+                const double re = (ci.x * cl[l].x + ci.y * cl[l].y) * inv;
+                const double im = (ci.y * cl[l].x - ci.x * cl[l].y) * inv;
+                M[i][l].x -= re;
+                M[i][l].y -= im;
+              }
+            }
+          }
+        }
+      }
+    }
+    if (t == 0) pm[si] = pmant, pe[si] = pexp;
+  }
+  __syncthreads();
+  if (t < Nsnr) cf[(int64_t)t * Nf + f] = (double)pe[t] + log2(pm[t]);
+}
+
 FieldArgs field_args(const ChannelArgs& a) { return FieldArgs{a.freq, a.atm_db, a.atm_deg, a.Nf, a.pol_tx, a.pol_rx}; }
 
 }  // namespace
@@ -549,20 +605,21 @@ void run_port_power(const float2* H, int Nf, int Nr, int Nt, double* P, hipStrea
 void run_capacity(const float2* H, int Nf, int Nr, int Nt, const double* snr_db, int Nsnr, int normalize,
                   double* C_out, hipStream_t s) {
   const int n = std::min(Nr, Nt);
-  Buf frob, sc, work, cf;
+  Buf frob, sc, cf;
   frob.alloc((size_t)Nf * 8, s);
   sc.alloc(8, s);
   cf.alloc((size_t)Nf * Nsnr * 8, s);
   { ::sbr::TimedLaunch tl_("capacity", s); hipLaunchKernelGGL(k_cap_frob, dim3(Nf), dim3(256), 0, s, H, Nr, Nt, frob.as<double>()); }
   { ::sbr::TimedLaunch tl_("capacity", s); hipLaunchKernelGGL(k_cap_scale, dim3(1), dim3(256), 0, s, frob.as<double>(), Nf, Nr, Nt, normalize,
                      sc.as<double>()); }
-  if (n <= kCapRegN) {
-    { ::sbr::TimedLaunch tl_("capacity", s); hipLaunchKernelGGL(k_cap_logdet_reg, dim3(Nf), dim3(256), 0, s, H, Nr, Nt, sc.as<double>(), snr_db,
-                       CapSnr{}, Nsnr, cf.as<double>()); }
-  } else {
-    work.alloc((size_t)Nf * 2 * n * n * sizeof(double2), s);
-    { ::sbr::TimedLaunch tl_("capacity", s); hipLaunchKernelGGL(k_cap_logdet, dim3(Nf), dim3(256), 0, s, H, Nr, Nt, sc.as<double>(), snr_db, Nsnr,
-                       work.as<double2>(), cf.as<double>()); }
+  {
+    ::sbr::TimedLaunch tl_("capacity", s);
+    if (n <= kCapRegN)
+      hipLaunchKernelGGL(k_cap_logdet_reg, dim3(Nf), dim3(256), 0, s, H, Nr, Nt, sc.as<double>(), snr_db, CapSnr{},
+                         Nsnr, cf.as<double>());
+    else
+      hipLaunchKernelGGL(k_cap_logdet_big, dim3(Nf), dim3(1024), 0, s, H, Nr, Nt, sc.as<double>(), snr_db, CapSnr{},
+                         Nsnr, cf.as<double>());
   }
   { ::sbr::TimedLaunch tl_("capacity", s); hipLaunchKernelGGL(k_cap_mean, dim3(1), dim3(256), 0, s, cf.as<double>(), Nf, Nsnr, C_out); }
   SBR_LAUNCH_CHECK();
@@ -598,11 +655,11 @@ void* capacity_scratch(int device) {
 }
 
 bool capacity_noalloc_fits(int Nf, int Nr, int Nt, int Nsnr) {
-  return std::min(Nr, Nt) <= kCapRegN && Nsnr <= kCapSnrMax &&
+  return std::min(Nr, Nt) <= kCapBigN && Nsnr <= kCapSnrMax &&
          ((uint64_t)Nf * (uint64_t)(Nsnr + 1) + 32) * 8 <= (uint64_t)kCapScratchBytes;
 }
 
-// Same kernels as run_capacity (n <= 64), their buffers in `scratch`: the
+// Same kernels as run_capacity (n <= 128), their buffers in `scratch`: the
 // normalisation at offset 0, the norms from byte 256, the log-determinants
 // after them.  Queued on s; nothing is allocated, nothing waits.
 void run_capacity_noalloc(const float2* H, int Nf, int Nr, int Nt, const double* snr_db, int Nsnr, int normalize,
@@ -614,7 +671,10 @@ void run_capacity_noalloc(const float2* H, int Nf, int Nr, int Nt, const double*
   for (int i = 0; i < Nsnr; ++i) sv.db[i] = snr_db[i];
   hipLaunchKernelGGL(k_cap_frob, dim3(Nf), dim3(256), 0, s, H, Nr, Nt, frob);
   hipLaunchKernelGGL(k_cap_scale, dim3(1), dim3(256), 0, s, frob, Nf, Nr, Nt, normalize, sc);
-  hipLaunchKernelGGL(k_cap_logdet_reg, dim3(Nf), dim3(256), 0, s, H, Nr, Nt, sc, (const double*)nullptr, sv, Nsnr, cf);
+  if (std::min(Nr, Nt) <= kCapRegN)
+    hipLaunchKernelGGL(k_cap_logdet_reg, dim3(Nf), dim3(256), 0, s, H, Nr, Nt, sc, (const double*)nullptr, sv, Nsnr, cf);
+  else
+    hipLaunchKernelGGL(k_cap_logdet_big, dim3(Nf), dim3(1024), 0, s, H, Nr, Nt, sc, (const double*)nullptr, sv, Nsnr, cf);
   hipLaunchKernelGGL(k_cap_mean, dim3(1), dim3(256), 0, s, cf, Nf, Nsnr, C_out);
   SBR_LAUNCH_CHECK();
 }

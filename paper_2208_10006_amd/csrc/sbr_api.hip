@@ -1407,7 +1407,7 @@ sbr_status sbr_capacity_noalloc(sbr_context_t ctx, const void* H_c64, int32_t Nf
     SBR_CHECK(Nf >= 1 && Nr >= 1 && Nt >= 1 && Nsnr >= 1, SBR_E_INVALID_ARG, "capacity sizes");
     SBR_CHECK(H_c64 && snr_db && C, SBR_E_INVALID_ARG, "NULL argument");
     SBR_CHECK(capacity_noalloc_fits(Nf, Nr, Nt, Nsnr), SBR_E_CAPACITY,
-              "sbr_capacity_noalloc takes min(Nr, Nt) <= 64, Nsnr <= 64 and Nf * (Nsnr + 1) <= %lld "
+              "sbr_capacity_noalloc takes min(Nr, Nt) <= 128, Nsnr <= 64 and Nf * (Nsnr + 1) <= %lld "
               "(got Nf %d, Nr %d, Nt %d, Nsnr %d)",
               (long long)(kCapScratchBytes / 8 - 32), Nf, Nr, Nt, Nsnr);
     void* scratch = capacity_scratch(c->device);

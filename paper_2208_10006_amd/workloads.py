@@ -112,19 +112,30 @@ def _footprint_dist(px, py, cx, cy, hx, hy, yaw):
     return np.hypot(ex, ey)
 
 
-def upa(center, n: int, spacing: float, plane: str = "yz") -> np.ndarray:
-    """Uniform planar array of n x n points; element (i, j) has index i*n + j and
-    sits at centre + (i-(n-1)/2) d u + (j-(n-1)/2) d v (eq. (11)-(12) point sets)."""
+def upa(center, n: int, spacing: float, plane: str = "yz", cols: Optional[int] = None) -> np.ndarray:
+    """Uniform planar array of n x cols points (cols = n by default); element
+    (i, j) has index i*cols + j and sits at centre + (i-(n-1)/2) d u +
+    (j-(cols-1)/2) d v (eq. (11)-(12) point sets)."""
     center = np.asarray(center, float)
+    cols = n if cols is None else cols
     axes = {"yz": (np.array([0.0, 1.0, 0.0]), np.array([0.0, 0.0, 1.0])),
             "xz": (np.array([1.0, 0.0, 0.0]), np.array([0.0, 0.0, 1.0])),
             "xy": (np.array([1.0, 0.0, 0.0]), np.array([0.0, 1.0, 0.0]))}[plane]
-    out = np.empty((n * n, 3))
+    out = np.empty((n * cols, 3))
     for i in range(n):
-        for j in range(n):
-            out[i * n + j] = (center + (i - (n - 1) / 2) * spacing * axes[0]
-                              + (j - (n - 1) / 2) * spacing * axes[1])
+        for j in range(cols):
+            out[i * cols + j] = (center + (i - (n - 1) / 2) * spacing * axes[0]
+                                 + (j - (cols - 1) / 2) * spacing * axes[1])
     return out
+
+
+def upa_shape(n: int):
+    """rows x cols of an n-element UPA: the most nearly square factorisation
+    with rows <= cols (16 -> 4 x 4, 32 -> 4 x 8, 64 -> 8 x 8, 128 -> 8 x 16)."""
+    rows = int(np.floor(np.sqrt(n)))
+    while n % rows:
+        rows -= 1
+    return rows, n // rows
 
 
 def _pack(tris, eps, sig, rough):
@@ -317,6 +328,10 @@ def urban_canyon(seed: int = 2, N: int = 1024, K: int = 6, n_rx: int = 1000,
     return w
 
 
+OFFICE_TX = (1.0, 10.0, 2.5)
+OFFICE_RX = (26.0, 7.0, 1.2)
+
+
 def massive_mimo_office(seed: int = 3, N: int = 316, K: int = 4, nf: int = 1024,
                         fc: float = 100e9, bw: float = 2e9, n_tx_side: int = 16,
                         n_rx_side: int = 8) -> Workload:
@@ -324,12 +339,40 @@ def massive_mimo_office(seed: int = 3, N: int = 316, K: int = 4, nf: int = 1024,
     eps_r 5.31, sigma 0.0326, smooth; 100 GHz, 1,024 subcarriers over 2 GHz;
     16 x 16 Tx UPA and 8 x 8 Rx UPA at lambda/2 in the y-z plane; per-element
     launch of N = 316 (998,562 rays), K = 4."""
+    tri, e, s, r = office_scene(seed)
+    k = np.arange(nf)
+    freq = fc + (k - nf // 2) * (bw / nf)
+    delta = C0 / fc / 2
+    tx = upa(OFFICE_TX, n_tx_side, delta)
+    rx = upa(OFFICE_RX, n_rx_side, delta)
+    return Workload("massive_mimo_office", tri, e, s, r, tx, rx, freq, geodesic_N=N, max_bounces=K)
+
+
+def mimo_office(n: int, seed: int = 3, N: int = 316, K: int = 4, nf: int = 1024, fc: float = 100e9,
+                bw: float = 2e9) -> Workload:
+    """n x n MIMO in the massive-MIMO office (Sec. IV-C, Fig. 6 and 7): an
+    n-element Tx UPA and an n-element Rx UPA (upa_shape(n), lambda/2 spacing,
+    y-z plane) at the office's Tx and Rx positions; same scene, band and launch
+    as massive_mimo_office."""
+    tri, e, s, r = office_scene(seed)
+    k = np.arange(nf)
+    freq = fc + (k - nf // 2) * (bw / nf)
+    delta = C0 / fc / 2
+    rows, cols = upa_shape(n)
+    tx = upa(OFFICE_TX, rows, delta, cols=cols)
+    rx = upa(OFFICE_RX, rows, delta, cols=cols)
+    return Workload(f"mimo_office_{n}x{n}", tri, e, s, r, tx, rx, freq, geodesic_N=N, max_bounces=K,
+                    meta={"n": n, "upa": (rows, cols)})
+
+
+def office_scene(seed: int = 3):
+    """The office hall: 30 x 20 x 3 m box + 208 desks + 208 partitions (yawed
+    boxes kept 0.5 m clear of the Tx and Rx array centres), all eps_r 5.31,
+    sigma 0.0326, smooth.  Returns packed (tri, eps_r, sigma, rough)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     tris = box_triangles((0.0, 0.0, 0.0), (30.0, 20.0, 3.0))
-    lam = C0 / fc
-    delta = lam / 2
-    tx_c = np.array([1.0, 10.0, 2.5])
-    rx_c = np.array([26.0, 7.0, 1.2])
+    tx_c = np.array(OFFICE_TX)
+    rx_c = np.array(OFFICE_RX)
     lift = 1e-3
     objs = 0
     while objs < 416:
@@ -347,12 +390,7 @@ def massive_mimo_office(seed: int = 3, N: int = 316, K: int = 4, nf: int = 1024,
         tris += box_triangles((cx - lx / 2, cy - ly / 2, lift), (cx + lx / 2, cy + ly / 2, lift + h), yaw)
         objs += 1
     T = len(tris)
-    tri, e, s, r = _pack(tris, [5.31] * T, [0.0326] * T, [0.0] * T)
-    k = np.arange(nf)
-    freq = fc + (k - nf // 2) * (bw / nf)
-    tx = upa(tx_c, n_tx_side, delta)
-    rx = upa(rx_c, n_rx_side, delta)
-    return Workload("massive_mimo_office", tri, e, s, r, tx, rx, freq, geodesic_N=N, max_bounces=K)
+    return _pack(tris, [5.31] * T, [0.0326] * T, [0.0] * T)
 
 
 def random_box_scene(seed: int, n_boxes: int = 20, extent: float = 40.0, n_rx: int = 8,

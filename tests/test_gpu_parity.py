@@ -384,7 +384,8 @@ def test_trace_order_keeps_results(S, ctx):
 
 # ------------------------------------------------------------------ capacity
 @pytest.mark.parametrize("shape", [(1, 1, 1), (3, 4, 8), (5, 8, 4), (2, 64, 64), (2, 16, 128), (3, 64, 256),
-                                   (2, 61, 7), (2, 96, 100), (1, 128, 128)])
+                                   (2, 61, 7), (2, 96, 100), (1, 128, 128), (2, 65, 65), (2, 130, 100),
+                                   (3, 128, 1000)])
 def test_capacity(S, ctx, shape):
     banner("capacity", shape)
     rng = np.random.default_rng(sum(shape))
@@ -398,6 +399,54 @@ def test_capacity(S, ctx, shape):
     c = S.sbr_capacity(ctx, Hs, snr, normalize=0)
     o = O.capacity(Hs.astype(np.complex128), snr, normalize=False)
     assert np.allclose(c, o, rtol=1e-9, atol=1e-12), (c, o)
+
+
+# ------------------------------------------------------------------ per-port received power
+@pytest.mark.parametrize("shape", [(1, 1, 1), (7, 3, 5), (16, 16, 16), (1024, 64, 64), (33, 100, 37),
+                                   (1024, 128, 128), (3, 1, 4000)])
+def test_port_power(S, ctx, shape):
+    """sbr_port_power against the oracle's band mean of |H|^2 (FP32 entries,
+    FP64 sums: agreement to the FP64 summation order), host and device paths."""
+    import torch
+    banner("port power", shape)
+    rng = np.random.default_rng(sum(shape) + 1)
+    H = ((rng.normal(size=shape) + 1j * rng.normal(size=shape)) * 1e-4).astype(np.complex64)
+    o = O.port_power(H)
+    P = S.sbr_port_power(ctx, H)
+    assert P.shape == o.shape
+    np.testing.assert_allclose(P, o, rtol=1e-13, atol=0)
+    Hd = torch.from_numpy(H).cuda()
+    out = torch.full((shape[1] * shape[2],), float("nan"), dtype=torch.float64, device="cuda")
+    S.sbr_port_power(ctx, Hd, out)
+    S.sbr_synchronize(ctx)
+    assert np.array_equal(out.cpu().numpy().reshape(o.shape), P)
+
+
+def test_mimo_office_two_element_subset(S, ctx):
+    """n x n MIMO office (16 x 16 UPAs, Sec. IV-C) with two Tx elements at a
+    reduced density (N = 80) and 16 subcarriers, full oracle: paths and H, then
+    the per-port received power and the capacity of the 16 x 2 channel from
+    the GPU's H against the oracle's values from its own H."""
+    from tests import parity as PT
+    banner("mimo office 16x16, tx 0 and 15, N=80 K=4")
+    w = W.mimo_office(16, N=80, nf=16).subset_tx([0, 15])
+    gr, ora, rep = _full_case(S, ctx, w)
+    assert rep.common >= 16, rep.common
+    H64 = gr.res.H.astype(np.complex64)
+    P = S.sbr_port_power(ctx, H64)
+    Po = O.port_power(ora.H)
+    # H itself agrees with the oracle's (asserted by the full case, excused
+    # paths included); the power then differs by at most the band mean of
+    # 2 |H| |dH| + |dH|^2, plus the rounding of H to complex64
+    dH = np.abs(gr.res.H - ora.H)
+    bound = np.mean(2 * np.abs(ora.H) * dH + dH ** 2, axis=0) + 4e-7 * Po
+    assert np.all(np.abs(P - Po) <= bound + 1e-30), np.max(np.abs(P - Po) / (bound + 1e-30))
+    assert np.max(np.abs(P - Po) / Po) < 1e-3, np.max(np.abs(P - Po) / Po)
+    assert np.all(Po > 0), "every link of the subset has a path"
+    snr = np.arange(0, 31, 5, dtype=np.float64)
+    c = S.sbr_capacity(ctx, H64, snr, normalize=1)
+    co = O.capacity(ora.H, snr, normalize=True)
+    assert np.allclose(c, co, rtol=1e-4, atol=1e-6), (c, co)
 
 
 # ------------------------------------------------------------------ errors, determinism, device I/O

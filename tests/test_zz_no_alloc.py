@@ -29,8 +29,9 @@ def test_noalloc_capacity_matches_capacity(normalize):
     snr = np.arange(0, 31, 5, dtype=np.float64)
     out = torch.full((64,), np.nan, dtype=torch.float64, device=dev)
     scale = 1e-5 if normalize else 1.0
-    # the second call is smaller in every dimension and in the SNR count
-    for shape, ns, seed in [((48, 64, 256), 7, 1), ((5, 8, 3), 3, 2)]:
+    # each call is smaller than the one before it and has fewer SNR values;
+    # the second takes the 128-wide elimination (64 < min(Nr, Nt) <= 128)
+    for shape, ns, seed in [((48, 64, 256), 7, 1), ((16, 100, 128), 5, 3), ((5, 8, 3), 3, 2)]:
         banner("capacity noalloc", shape, ns, "normalize", normalize)
         H = _h(shape, seed, scale)
         ref = S.sbr_capacity(ctx, H, snr[:ns], normalize=normalize)
@@ -52,7 +53,7 @@ def test_noalloc_capacity_limits():
     dev = torch.device("cuda", 0)
     out = torch.zeros(70, dtype=torch.float64, device=dev)
     banner("capacity noalloc limits")
-    for shape, ns in [((2, 65, 70), 3), ((2, 8, 8), 65), ((200000, 2, 2), 7)]:
+    for shape, ns in [((2, 129, 130), 3), ((2, 8, 8), 65), ((200000, 2, 2), 7)]:
         Hd = torch.zeros(shape, dtype=torch.complex64, device=dev)
         with pytest.raises(S.SbrError) as e:
             S.sbr_capacity_noalloc(ctx, Hd, np.zeros(ns), out)
