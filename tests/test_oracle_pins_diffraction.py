@@ -1,0 +1,249 @@
+"""Pins of the oracle's first-order edge diffraction (reading R24: the
+uniform theory of diffraction of Kouyoumjian and Pathak with Luebbers' face
+reflection coefficients) against closed forms and invariants that do not
+share its formulas: the transition function's limits and its complementary
+error function form, Keller's half-plane coefficient, continuity of the total
+field across shadow and reflection boundaries, Keller's cone, reciprocity,
+and the wedges of simple solids."""
+import math
+
+import numpy as np
+import pytest
+from scipy.special import erfc
+
+from oracle import diffraction as D
+from oracle import oracle as O
+from paper_2208_10006_amd import workloads as W
+
+C0 = 299792458.0
+
+
+# ------------------------------------------------------------------ transition function
+def test_transition_function_erfc_form():
+    """F(X) = j sqrt(pi X) e^{j(X - pi/4)} erfc(e^{j pi/4} sqrt X): the tail
+    integral as a complementary error function of complex argument (a
+    different routine and a different formula from the oracle's Fresnel
+    integrals)."""
+    X = np.concatenate([np.logspace(-8, 4, 97), [0.5, 1.0, 2.0, 3.0, 5.0, 10.0]])
+    u = np.sqrt(X)
+    want = 1j * np.sqrt(np.pi) * u * np.exp(1j * (X - np.pi / 4)) * erfc(np.exp(1j * np.pi / 4) * u)
+    got = D.transition(X)
+    assert np.all(np.abs(got - want) <= 1e-10 * np.maximum(np.abs(want), 1e-3)), np.max(np.abs(got - want))
+
+
+def test_transition_function_limits():
+    """Small X: [sqrt(pi X) - 2X e^{j pi/4} - (2/3) X^2 e^{-j pi/4}] e^{j(pi/4 + X)};
+    large X: 1 + j/(2X) - 3/(4X^2) - 15j/(8X^3)."""
+    for X in (1e-8, 1e-6, 1e-4):
+        want = (math.sqrt(math.pi * X) - 2 * X * np.exp(1j * math.pi / 4)
+                - 2.0 / 3.0 * X * X * np.exp(-1j * math.pi / 4)) * np.exp(1j * (math.pi / 4 + X))
+        assert abs(D.transition(X) - want) <= 1e-9 * abs(want), X
+    for X in (1e3, 1e4, 1e5):
+        want = 1 + 1j / (2 * X) - 3 / (4 * X * X) - 15j / (8 * X ** 3)
+        # (the FP64 Fresnel-integral form keeps about 1e-11 here: 1/2 - C(v)
+        # is a difference of nearly equal numbers)
+        assert abs(D.transition(X) - want) <= 120 / X ** 4 + 5e-11, X
+    assert D.transition(0.0) == 0
+
+
+# ------------------------------------------------------------------ coefficients
+@pytest.mark.parametrize("phip,phi", [(0.3, 2.0), (1.0, 4.5), (2.2, 5.9), (0.7, 3.0)])
+def test_half_plane_keller_limit(phip, phi):
+    """n = 2 (half plane), far from every boundary (k L = 1e6, so
+    F = 1 + j/(2X) within 1e-5 for these angles): the perfectly conducting UTD
+    coefficients reduce to Keller's
+    -e^{-j pi/4} / (2 sqrt(2 pi k) sin b0) [sec((phi - phi')/2) -+ sec((phi + phi')/2)]."""
+    k, L, b0 = 1e3, 1e3, 1.1
+    for R, sgn in ((-1.0, -1.0), (1.0, 1.0)):  # soft (TE -1), hard (TM +1)
+        got = D.utd_coefficient(2.0, phi, phip, b0, k, L, R, R)
+        want = (-np.exp(-1j * math.pi / 4) / (2 * math.sqrt(2 * math.pi * k) * math.sin(b0))
+                * (1 / math.cos((phi - phip) / 2) + sgn / math.cos((phi + phip) / 2)))
+        assert abs(got - want) <= 1e-5 * abs(want), (R, got, want)
+
+
+def _scalar_total(n, phip, rho_s, rho, phi, k, R):
+    """Scalar total field at (rho, phi) of a point source at (rho_s, phip)
+    next to a perfectly conducting wedge of exterior angle n pi (both in the
+    plane perpendicular to the edge): geometric optics (incident field and
+    the image fields of the two faces, each where it exists) plus the
+    diffracted field, u = e^{-jkr}/r for the source."""
+    src = rho_s * np.array([math.cos(phip), math.sin(phip)])
+    obs = rho * np.array([math.cos(phi), math.sin(phi)])
+
+    def sph(r):
+        return np.exp(-1j * k * r) / r
+
+    u = 0j
+    if phi < math.pi + phip:                        # lit by the source
+        u += sph(np.linalg.norm(obs - src))
+    if phi < math.pi - phip:                        # reflection from face 0 (phi = 0)
+        u += R * sph(np.linalg.norm(obs - src * np.array([1, -1])))
+    if phi > 2 * n * math.pi - math.pi - phip:      # reflection from face n (phi = n pi)
+        a = 2 * n * math.pi - phip                  # image of the source across face n
+        u += R * sph(np.linalg.norm(obs - rho_s * np.array([math.cos(a), math.sin(a)])))
+    L = rho * rho_s / (rho + rho_s)
+    d = D.utd_coefficient(n, phi, phip, math.pi / 2, k, L, R, R)
+    u += sph(rho_s) * d * math.sqrt(rho_s / (rho * (rho + rho_s))) * np.exp(-1j * k * rho)
+    return u
+
+
+@pytest.mark.parametrize("n,phip", [(1.5, 0.6), (1.5, 1.9), (2.0, 0.8), (1.75, 2.5)])
+@pytest.mark.parametrize("R", [-1.0, 1.0])
+def test_total_field_continuous_across_boundaries(n, phip, R):
+    """Geometric optics jumps at the incident shadow boundary and at each
+    reflection boundary; the diffracted field jumps by the opposite amount,
+    so the total is continuous (to O(delta) across 2 delta)."""
+    k = 2 * math.pi * 28e9 / C0
+    rho_s, rho = 3.0, 2.0
+    bounds = [math.pi + phip, math.pi - phip, 2 * n * math.pi - math.pi - phip]
+    checked = 0
+    for phb in bounds:
+        if not (0.05 < phb < n * math.pi - 0.05):
+            continue
+        dlt = 1e-7
+        lo = _scalar_total(n, phip, rho_s, rho, phb - dlt, k, R)
+        hi = _scalar_total(n, phip, rho_s, rho, phb + dlt, k, R)
+        ref = abs(np.exp(-1j * k * (rho + rho_s)) / (rho + rho_s))
+        assert abs(hi - lo) <= 1e-3 * ref, (phb, abs(hi - lo) / ref)
+        # the parts themselves jump by about the incident field there
+        checked += 1
+    assert checked >= 2
+
+
+def test_coefficient_reciprocal_in_its_angles():
+    """Perfect conductor: D(phi, phi') = D(phi', phi) (source and observer
+    exchanged)."""
+    for n in (1.5, 1.8, 2.0):
+        for phip, phi in ((0.4, 3.1), (1.2, 2.7), (2.0, 4.1)):
+            for R in (-1.0, 1.0):
+                a = D.utd_coefficient(n, phi, phip, 1.0, 500.0, 0.7, R, R)
+                b = D.utd_coefficient(n, phip, phi, 1.0, 500.0, 0.7, R, R)
+                assert abs(a - b) <= 1e-12 * abs(a)
+
+
+# ------------------------------------------------------------------ wedges and paths
+def _box_workload(tx, rx, freq=(28e9,), eps=5.31, sigma=0.0326, lo=(0.0, 0.0, 0.0), hi=(1.0, 2.0, 3.0)):
+    tris = W.box_triangles(lo, hi)
+    T = len(tris)
+    tri, e, s, r = W._pack(tris, [eps] * T, [sigma] * T, [0.0] * T)
+    return W.Workload("box", tri, e, s, r, np.array(tx, float), np.array(rx, float), np.array(freq, float),
+                      geodesic_N=16, max_bounces=1)
+
+
+def test_wedges_of_a_box_and_a_plane():
+    w = _box_workload([[5.0, 5.0, 1.0]], [[-5.0, -5.0, 1.0]])
+    wd = D.wedges(w)
+    assert len(wd) == 12
+    assert all(abs(x.n - 1.5) < 1e-12 for x in wd)
+    lens = sorted(round(float(np.linalg.norm(x.b - x.a)), 12) for x in wd)
+    assert lens == [1.0] * 4 + [2.0] * 4 + [3.0] * 4
+    for x in wd:  # the box lies in the solid sector: its centre is not in (0, n pi)
+        _, _, ph = D._angle(x, np.array([0.5, 1.0, 1.5]))
+        assert ph > x.n * math.pi
+    # a flat quad: its diagonal joins coplanar triangles, no wedge
+    tri, e, s, r = W._pack(W._quad((0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0)), [5.0] * 2, [0.01] * 2, [0.0] * 2)
+    wq = W.Workload("quad", tri, e, s, r, np.zeros((1, 3)), np.ones((1, 3)), np.array([28e9]))
+    assert D.wedges(wq) == []
+
+
+def test_vertical_edge_path_geometry():
+    """Box [0,1] x [0,2] x [0,3]; Tx and Rx in its shadow on opposite sides
+    of the edge x = 1, y = 2: the diffraction point satisfies Keller's cone
+    (equal angles with the edge), s' + s is the unfolded distance, and the
+    line of sight is blocked."""
+    tx, rx = [3.0, 1.0, 1.0], [-1.0, 2.5, 2.2]
+    w = _box_workload([tx], [rx])
+    wd = D.wedges(w)
+    ps = D.diffraction_paths(w, wd)
+    vert = [p for p in ps if abs(abs(wd[p.wedge].e[2]) - 1) < 1e-12]
+    assert len(vert) == 1
+    d = vert[0]
+    e = wd[d.wedge]
+    assert np.allclose(d.Q[:2], [1.0, 2.0])
+    T, R = np.array(tx), np.array(rx)
+    ci = np.dot((d.Q - T) / d.sp, e.e)
+    cd = np.dot((R - d.Q) / d.s, e.e)
+    assert abs(ci - cd) < 1e-13
+    rt, rr = math.hypot(tx[0] - 1, tx[1] - 2), math.hypot(rx[0] - 1, rx[1] - 2)
+    assert abs(d.sp + d.s - math.hypot(rt + rr, rx[2] - tx[2])) < 1e-12
+    assert 0 < d.phip < 1.5 * math.pi and 0 < d.phi < 1.5 * math.pi
+    # the line of sight passes through the box
+    blocked, _ = D._blocked(w.tri, O.scene_groups(w)[0], T, R, ())
+    assert blocked
+
+
+def test_no_path_from_inside_the_solid_or_past_the_edge_end():
+    w = _box_workload([[0.5, 1.0, 1.5]], [[3.0, 3.0, 1.0]])   # Tx inside the box
+    assert D.diffraction_paths(w) == []
+    w = _box_workload([[3.0, 1.0, 5.0]], [[0.5, 4.0, 6.0]])   # Q above the top of the vertical edges
+    assert all(abs(D.wedges(w)[p.wedge].e[2]) < 0.5 for p in D.diffraction_paths(w))
+
+
+def test_field_reciprocity_perfect_conductor():
+    """A box of sigma 1e15 S/m (|eps_c| ~ 6e14, so TE -> -1 and TM -> +1 to
+    1e-7 / cos(incidence)): exchanging Tx and Rx gives the same diffracted
+    field for V-V and H-H (theta-hat is the same for opposite directions,
+    phi-hat changes sign at both ends).  With lossy faces the weighting of the
+    two reflection-type terms depends on which end is the source, so the
+    exchange holds only in this limit."""
+    a_pt, b_pt = [3.0, 1.0, 1.0], [0.5, 4.0, 2.2]
+    for pol in (0, 1):
+        w1 = _box_workload([a_pt], [b_pt], sigma=1e15)
+        w2 = _box_workload([b_pt], [a_pt], sigma=1e15)
+        p1, p2 = D.diffraction_paths(w1), D.diffraction_paths(w2)
+        f1 = D.diffraction_field(w1, p1, pol_tx=pol, pol_rx=pol)
+        f2 = D.diffraction_field(w2, p2, pol_tx=pol, pol_rx=pol)
+        k1 = {p.wedge: f1[i, 0] for i, p in enumerate(p1)}
+        k2 = {p.wedge: f2[i, 0] for i, p in enumerate(p2)}
+        assert set(k1) == set(k2) and len(k1) >= 1
+        for j in k1:
+            assert abs(k1[j] - k2[j]) <= 1e-4 * abs(k1[j]) + 1e-15, (pol, j, k1[j], k2[j])
+
+
+def test_perfect_conductor_limit_of_the_face_coefficients():
+    """Lossy faces with sigma -> infinity reproduce the textbook coefficients:
+    TE -> -1 (soft), TM -> +1 (hard)."""
+    te, tm = O.fresnel(5.0, 1e12, 28e9, 0.3)
+    assert abs(te + 1) < 1e-4 and abs(tm - 1) < 1e-4
+
+
+def _total_received(w, pol):
+    """Geometric optics (line of sight and every single reflection, each
+    validated and evaluated by the oracle's image method) plus every
+    first-order diffracted path, at one frequency."""
+    _, _, ng = O.scene_groups(w)
+    keys = np.array([[0, 0, 0, -1]] + [[0, 0, 1, g] for g in range(ng)], np.int32)
+    go = O.field(w, keys, pol_tx=pol, pol_rx=pol)[:, 0].sum()
+    ps = D.diffraction_paths(w)
+    dif = D.diffraction_field(w, ps, pol_tx=pol, pol_rx=pol)[:, 0].sum() if ps else 0j
+    return go, dif
+
+
+@pytest.mark.parametrize("pol", [0, 1])
+@pytest.mark.parametrize("which", ["shadow", "reflection"])
+def test_vector_field_continuous_across_boundaries(pol, which):
+    """The whole chain with vector fields: a box of sigma 1e15 S/m, Tx and Rx
+    at one height (beta0 = pi/2), the Rx moved across the incident shadow
+    boundary of the vertical edge x = 1, y = 2, or across the reflection
+    boundary of its face x = 1.  The line of sight (or the reflection)
+    appears on one side only; geometric optics plus diffraction is
+    continuous, for vertical (soft at this edge) and horizontal (hard)
+    polarisation, which pins the edge-fixed polarisation bases and the signs
+    of the dyadic against the reflection tracker's conventions."""
+    tx = np.array([3.0, 1.0, 1.5])
+    edge = np.array([1.0, 2.0])
+    if which == "shadow":
+        th = math.atan2(edge[1] - tx[1], edge[0] - tx[0])   # the Tx -> edge direction continued
+    else:
+        img = np.array([2 * 1.0 - tx[0], tx[1]])             # Tx mirrored in the face x = 1
+        th = math.atan2(edge[1] - img[1], edge[0] - img[0])
+    rho = 2.0
+    vals = []
+    for d in (-1e-7, 1e-7):
+        rx = np.array([edge[0] + rho * math.cos(th + d), edge[1] + rho * math.sin(th + d), 1.5])
+        w = _box_workload([tx], [rx], sigma=1e15)
+        vals.append(_total_received(w, pol))
+    (go0, df0), (go1, df1) = vals
+    ref = abs(go0) + abs(go1)
+    assert abs(go1 - go0) > 0.2 * ref / 2, "geometric optics jumps across the boundary"
+    assert abs((go1 + df1) - (go0 + df0)) <= 2e-3 * ref, abs((go1 + df1) - (go0 + df0)) / ref
