@@ -349,6 +349,55 @@ def mimo_main(args):
     print(json.dumps(out), flush=True)
 
 
+def diffraction_main(args):
+    """First-order edge diffraction on the massive-MIMO office: every (wedge,
+    Tx element, Rx element) candidate, both legs against the BVH, and the
+    diffracted fields of all paths added to H over the band.  One step =
+    sbr_diffract + sbr_diff_channel (the scene is built before the timed
+    region; its wedge table is built once, on the first call)."""
+    import numpy as np
+    import torch
+    from paper_2208_10006_amd import sbr as S
+    from paper_2208_10006_amd import workloads as W
+
+    w = W.massive_mimo_office()
+    dev = torch.device("cuda", 0)
+    d = make_inputs(w, torch, dev)
+    ctx = S.context_for_torch(0)
+    sc = S.sbr_scene_build(ctx, d["tri"], d["eps"], d["sig"], d["rough"])
+
+    def one():
+        df = S.sbr_diffract(ctx, sc, d["tx"], d["rx"])
+        S.sbr_diff_channel(ctx, df, d["freq"], pol_tx=S.SBR_POL_V, pol_rx=S.SBR_POL_V, H_c64=d["H"])
+        return df
+
+    for _ in range(args.warmup):
+        h = one()
+        del h
+    torch.cuda.synchronize()
+    S.sbr_profile_only(ctx, "diffraction")
+    S.sbr_profile_enable(ctx, True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        h = one()
+        if i + 1 < args.steps:
+            del h
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kms, kn = S.sbr_profile_query(ctx, "diffraction")
+    S.sbr_profile_enable(ctx, False)
+    info = S.sbr_diff_info(h)
+    ms = (t1 - t0) * 1e3 / args.steps
+    out = {"metric": "diffraction candidates/s (wedge x Tx element x Rx element)",
+           "value": info["candidates"] / (ms * 1e-3), "unit": "candidates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64 geometry and UTD field, f32 BVH boxes", "data": "synthetic",
+           "config": {"workload": f"first-order edge diffraction, {describe(w)}", **info,
+                      "paths_per_pair": info["paths"] / (len(w.tx) * len(w.rx)),
+                      "kernel_ms_per_step": kms / args.steps, "kernel_launches_per_step": kn / args.steps}}
+    print(json.dumps(out), flush=True)
+
+
 PEAK_BF16_TFLOPS = 2500.0
 
 
@@ -456,6 +505,8 @@ def main():
         return surrogate_main(args)
     if args.workload == "mimo_sweep":
         return mimo_main(args)
+    if args.workload == "office_diffraction":
+        return diffraction_main(args)
     import numpy as np
     import torch
     from paper_2208_10006_amd import sbr as S

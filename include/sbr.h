@@ -58,6 +58,7 @@ typedef struct sbr_context_s* sbr_context_t; /* device, stream, tuning         *
 typedef struct sbr_scene_s* sbr_scene_t;     /* triangles, face groups, BVH    */
 typedef struct sbr_trace_s* sbr_trace_t;     /* per-ray hit chains ("RT tree") */
 typedef struct sbr_paths_s* sbr_paths_t;     /* unique validated paths         */
+typedef struct sbr_diff_s* sbr_diff_t;       /* first-order diffraction paths  */
 
 /* One propagation path (Sec. II-A-4: a multipath component of eq. (2)/(4)).
  * tx, rx: element indices; order: number of reflections; groups: the face
@@ -179,6 +180,55 @@ sbr_status sbr_channel(sbr_context_t ctx, sbr_paths_t ps, const double* freq_hz,
 sbr_status sbr_path_field(sbr_context_t ctx, sbr_paths_t ps, const double* freq_hz, int32_t Nf,
                           const float* atm_db_per_m, const float* atm_deg_per_m, int32_t pol_tx, int32_t pol_rx,
                           double* a_c128, uint32_t flags);
+
+/* ------------------------------------------------------------------------ */
+/* First-order edge diffraction (Sec. II-A-2 and Fig. B(b) name it, Table I
+ * uses it; the paper gives no coefficient).  The uniform theory of
+ * diffraction of Kouyoumjian and Pathak for straight wedges, the two
+ * reflection-type terms weighted by the faces' Fresnel coefficients (TE for
+ * the soft, TM for the hard coefficient) and roughness factors at the true
+ * incidence angle on each face (Luebbers' form for lossy wedges).
+ * Wedges: triangle edges shared by exactly two triangles of different face
+ * groups whose planes are not parallel; the solid fills the smaller sector
+ * between the faces (exterior angle n pi, 1 < n < 2); face 0 is the triangle
+ * of lower index; wedges are numbered by (lower triangle, its edge from
+ * vertex i to vertex i+1).  A path Tx -> Q -> Rx exists when Tx and Rx lie
+ * strictly inside the exterior sector, Q (on Keller's cone) lies strictly
+ * inside the edge, and neither leg crosses a triangle outside the wedge's two
+ * face groups (the image-method margins).  Only diffraction alone is
+ * modelled (no reflection before or after it).
+ * sbr_diffract: tx_xyz [Nt][3], rx_xyz [Nr][3] FP64 (host, or device with
+ * SBR_IN_DEVICE); finishes before it returns; the handle keeps the scene.
+ * Errors: INVALID_ARG (NULL, sizes, non-finite points), UNSUPPORTED when
+ * wedges x Nt x Nr >= 2^32. */
+sbr_status sbr_diffract(sbr_context_t ctx, sbr_scene_t sc, const double* tx_xyz, int32_t Nt, const double* rx_xyz,
+                        int32_t Nr, uint32_t flags, sbr_diff_t* out);
+/* counts: wedges of the scene, (wedge, Tx, Rx) candidates, candidates past the
+ * sector and edge tests, paths (any output may be NULL) */
+sbr_status sbr_diff_info(sbr_diff_t d, int64_t* wedges, int64_t* candidates, int64_t* geometric, int64_t* paths);
+/* the first min(capacity, paths) paths, ordered by (Rx, Tx, wedge), to host
+ * arrays: ids [n][3] int32 (tx, rx, wedge); rec [n][8] FP64 (Q xyz, s' = |Q - Tx|,
+ * s = |Rx - Q|, beta0, phi', phi in radians) */
+sbr_status sbr_diff_paths(sbr_diff_t d, int64_t capacity, int32_t* ids, double* rec, int64_t* written);
+/* the scene's wedges in their numbering, to host arrays: geo [n][8] FP64 (start
+ * xyz, end xyz, exterior angle / pi, length), groups [n][2] (face 0, face n);
+ * count = number of wedges (either output may be NULL) */
+sbr_status sbr_scene_wedges(sbr_context_t ctx, sbr_scene_t sc, int64_t capacity, double* geo, int32_t* groups,
+                            int64_t* count);
+/* H[f][q][p] += the diffracted fields of the pair's paths, summed in a fixed
+ * order (FP64), with the arguments of sbr_channel (H_c64 and/or H_c128 hold
+ * the field to add to: host, or device with SBR_OUT_DEVICE) */
+sbr_status sbr_diff_channel(sbr_context_t ctx, sbr_diff_t d, const double* freq_hz, int32_t Nf,
+                            const float* atm_db_per_m, const float* atm_deg_per_m, int32_t pol_tx, int32_t pol_rx,
+                            void* H_c64, double* H_c128, uint32_t flags);
+/* per-path diffracted fields [paths][Nf] interleaved FP64 (diagnostic / parity output) */
+sbr_status sbr_diff_field(sbr_context_t ctx, sbr_diff_t d, const double* freq_hz, int32_t Nf,
+                          const float* atm_db_per_m, const float* atm_deg_per_m, int32_t pol_tx, int32_t pol_rx,
+                          double* a_c128, uint32_t flags);
+/* the transition function F(X) = 2j sqrt(X) e^{jX} int_{sqrt X}^inf e^{-j t^2} dt
+ * of the diffraction coefficients at X[n] >= 0 (F = 0 at X = 0), interleaved
+ * FP64 (diagnostic / parity output) */
+sbr_status sbr_utd_transition(sbr_context_t ctx, const double* X, int64_t n, double* F_c128, uint32_t flags);
 
 /* Per (Rx, Tx) statistics from the path powers of the last sbr_channel:
  * pg_db: 10 log10 sum P_n (incoherent path gain; -inf when no path),

@@ -11,7 +11,10 @@ for lossy wedges:
 * a wedge is a triangle edge shared by exactly two triangles of different
   face groups whose planes are not parallel; the solid occupies the smaller
   angular sector alpha < pi between the two faces, the field the exterior
-  sector n pi = 2 pi - alpha (1 < n < 2);
+  sector n pi = 2 pi - alpha (1 < n < 2); an edge that lies on a triangle of
+  a third face group (both ends within 1e-9 (1 + max |coordinate|) of its
+  plane, the edge's midpoint inside it with the 1e-9 barycentric margin) is
+  not a wedge: it is where a solid rests on another surface;
 * face 0 is the triangle of lower index, angles are measured from face 0
   towards face n through the exterior: phi' at the Tx, phi at the Rx, both
   strictly inside (0, n pi);
@@ -153,10 +156,35 @@ def wedges(w, groups=None):
         if np.dot(n0, t1) > 0:
             n0 = -n0
         alpha = math.acos(max(-1.0, min(1.0, float(np.dot(t0, t1)))))
+        if _covered(tri, groups, a, b, (groups[ta], groups[tb])):
+            continue
         out.append(((ta, ia), Wedge(a, b, e, t0, n0, 2.0 - alpha / math.pi, ta, tb, int(groups[ta]),
                                     int(groups[tb]))))
     out.sort(key=lambda x: x[0])
     return [wd for _, wd in out]
+
+
+def _covered(tri, groups, a, b, skip):
+    """Whether the edge a-b lies on a triangle outside face groups `skip`."""
+    keep = ~np.isin(groups, list(skip))
+    T = tri[keep]
+    if len(T) == 0:
+        return False
+    nrm = np.cross(T[:, 1] - T[:, 0], T[:, 2] - T[:, 0])
+    nrm = nrm / np.linalg.norm(nrm, axis=1)[:, None]
+    c = np.einsum("ij,ij->i", nrm, T[:, 0])
+    eps = 1e-9 * (1.0 + max(np.abs(a).max(), np.abs(b).max()))
+    onp = (np.abs(nrm @ a - c) <= eps) & (np.abs(nrm @ b - c) <= eps)
+    if not onp.any():
+        return False
+    m = 0.5 * (a + b)
+    for t, n in zip(T[onp], nrm[onp]):
+        # barycentric coordinates of m from the three edge functions
+        w = [np.dot(n, np.cross(t[(i + 1) % 3] - t[i], m - t[i])) for i in range(3)]
+        area = np.dot(n, np.cross(t[1] - t[0], t[2] - t[0]))
+        if min(w) / area >= -1e-9:
+            return True
+    return False
 
 
 def _angle(wd: Wedge, P):
@@ -270,13 +298,18 @@ def _pol_vec(u, pol):
     return np.array([u[2] * cp, u[2] * sp_, -st])
 
 
-def diffraction_field(w, paths, wds=None, freq=None, atm_db=None, atm_deg=None, pol_tx=0, pol_rx=0):
-    """a[path][f]: the received diffracted field of every path (complex)."""
+def diffraction_field(w, paths, wds=None, freq=None, atm_db=None, atm_deg=None, pol_tx=0, pol_rx=0,
+                      with_scale=False):
+    """a[path][f]: the received diffracted field of every path (complex).
+    with_scale: also the magnitude each value is a sum of,
+    |amp| (|D_s e_b r_b| + |D_h e_p r_p|) (the rounding scale of a cross-polar
+    value in which the two terms nearly cancel)."""
     if wds is None:
         wds = wedges(w)
     freq = np.asarray(w.freq if freq is None else freq, np.float64)
     eps, sig, rough = (np.asarray(x, np.float64) for x in (w.eps_r, w.sigma, w.rough))
     out = np.zeros((len(paths), len(freq)), np.complex128)
+    scale = np.zeros((len(paths), len(freq)))
     for i, d in enumerate(paths):
         wd = wds[d.wedge]
         Tx, R = np.asarray(w.tx[d.p], np.float64), np.asarray(w.rx[d.q], np.float64)
@@ -315,7 +348,8 @@ def diffraction_field(w, paths, wds=None, freq=None, atm_db=None, atm_deg=None, 
             if atm_deg is not None:
                 phs += math.pi * float(atm_deg[fi]) * length / 180.0
             out[i, fi] = amp * pol * np.exp(-1j * phs)
-    return out
+            scale[i, fi] = amp * (abs(Ds * eb * rb) + abs(Dh * ep * rp))
+    return (out, scale) if with_scale else out
 
 
 def channel_matrix(w, paths, a):

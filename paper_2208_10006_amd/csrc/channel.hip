@@ -33,27 +33,6 @@ struct FieldArgs {
   int Nf, ptx, prx;
 };
 
-// a / b with one division: conj(b) a / |b|^2.  The Fresnel terms are of
-// moderate size (|eps_c| below about 1e8 even for metals at 1 GHz), so |b|^2
-// neither overflows nor underflows, and the result is within a few ulps of
-// the exact quotient.
-__device__ inline cd cdiv_mod(cd a, cd b) {
-  const double inv = 1.0 / (b.re * b.re + b.im * b.im);
-  return cd{(a.re * b.re + a.im * b.im) * inv, (a.im * b.re - a.re * b.im) * inv};
-}
-// principal square root, |z| by a plain square root (moderate sizes as above)
-__device__ inline cd csqrt_mod(cd z) {
-  const double m = sqrt(z.re * z.re + z.im * z.im);
-  if (m == 0.0) return cd{0.0, 0.0};
-  if (z.re >= 0.0) {
-    const double r = sqrt(0.5 * (m + z.re));
-    return cd{r, z.im / (2.0 * r)};
-  }
-  double i = sqrt(0.5 * (m - z.re));
-  if (z.im < 0.0 || (z.im == 0.0 && signbit(z.im))) i = -i;
-  return cd{z.im / (2.0 * i), i};
-}
-
 // divisions by constants as multiplications (within 1 ulp; at f d / c ~ 1e6
 // cycles that is ~1e-10 of a cycle of phase)
 constexpr double kInvC0 = 1.0 / kC0;

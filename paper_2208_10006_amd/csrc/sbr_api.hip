@@ -510,12 +510,18 @@ sbr_context_s::~sbr_context_s() {
 sbr_scene_s::~sbr_scene_s() {
   if (ctx) (void)hipSetDevice(ctx->device);
   nodes.reset(), root_box.reset(), tri32.reset(), tri64.reset(), tplane.reset(), tgroup.reset(), tplaneid.reset();
-  gplane.reset(), gmat.reset(), gstart.reset(), gtri.reset(), tables.reset();
+  gplane.reset(), gmat.reset(), gstart.reset(), gtri.reset(), tables.reset(), wedges.reset();
   if (ctx) release(ctx);
 }
 sbr_trace_s::~sbr_trace_s() {
   if (ctx) (void)hipSetDevice(ctx->device);
   tx.reset(), seq.reset(), counters.reset(), work.reset();
+  if (scene) release(scene);
+  if (ctx) release(ctx);
+}
+sbr_diff_s::~sbr_diff_s() {
+  if (ctx) (void)hipSetDevice(ctx->device);
+  tx.reset(), rx.reset(), ids.reset(), rec.reset(), seg_start.reset();
   if (scene) release(scene);
   if (ctx) release(ctx);
 }
@@ -1324,6 +1330,167 @@ sbr_status sbr_path_field(sbr_context_t ctx, sbr_paths_t p, const double* freq, 
     run_path_field(ps, F.a, dst, s);
     if (!(flags & SBR_OUT_DEVICE)) {
       if (n) SBR_HIP(hipMemcpyAsync(a_c128, dst, n * 16, hipMemcpyDeviceToHost, s));
+      SBR_HIP(hipStreamSynchronize(s));
+    }
+  });
+}
+
+// ---------------------------------------------------------------- diffraction
+sbr_status sbr_diffract(sbr_context_t ctx, sbr_scene_t scene, const double* tx_xyz, int32_t Nt, const double* rx_xyz,
+                        int32_t Nr, uint32_t flags, sbr_diff_t* out) {
+  return guard([&] {
+    auto* c = check_handle<sbr_context_s>(ctx, kContext, "context");
+    auto* sc = check_handle<sbr_scene_s>(scene, kScene, "scene");
+    SBR_CHECK(out != nullptr, SBR_E_INVALID_ARG, "out is NULL");
+    SBR_CHECK(Nt >= 1 && Nr >= 1 && (int64_t)Nt * Nr < (int64_t(1) << 31), SBR_E_INVALID_ARG, "Nt = %d, Nr = %d", Nt,
+              Nr);
+    SBR_CHECK(tx_xyz && rx_xyz, SBR_E_INVALID_ARG, "tx or rx is NULL");
+    set_device(c);
+    hipStream_t s = c->stream;
+    const auto htx = to_host(tx_xyz, (size_t)Nt * 3, flags, s);
+    const auto hrx = to_host(rx_xyz, (size_t)Nr * 3, flags, s);
+    SBR_CHECK(finite_all(htx.data(), htx.size()) && finite_all(hrx.data(), hrx.size()), SBR_E_INVALID_ARG,
+              "tx and rx coordinates must be finite");
+    auto* d = new sbr_diff_s();
+    d->ctx = c, d->scene = sc;
+    retain(c), retain(sc);
+    try {
+      d->Nt = Nt, d->Nr = Nr;
+      upload(d->tx, htx.data(), htx.size(), 0, s);
+      upload(d->rx, hrx.data(), hrx.size(), 0, s);
+      run_diffract(d, s);
+    } catch (...) {
+      release(d);
+      throw;
+    }
+    *out = d;
+  });
+}
+
+sbr_status sbr_diff_info(sbr_diff_t d, int64_t* wedges, int64_t* candidates, int64_t* geometric, int64_t* paths) {
+  return guard([&] {
+    auto* df = check_handle<sbr_diff_s>(d, kDiff, "diffraction");
+    if (wedges) *wedges = df->scene->n_wedges;
+    if (candidates) *candidates = df->n_candidates;
+    if (geometric) *geometric = df->n_geometric;
+    if (paths) *paths = df->n_paths;
+  });
+}
+
+sbr_status sbr_diff_paths(sbr_diff_t d, int64_t capacity, int32_t* ids, double* rec, int64_t* written) {
+  return guard([&] {
+    auto* df = check_handle<sbr_diff_s>(d, kDiff, "diffraction");
+    const int64_t n = std::min<int64_t>(capacity, df->n_paths);
+    SBR_CHECK(n <= 0 || (ids && rec), SBR_E_INVALID_ARG, "output is NULL");
+    set_device(df->ctx);
+    hipStream_t s = df->ctx->stream;
+    if (n > 0) {
+      SBR_HIP(hipMemcpyAsync(ids, df->ids.p, (size_t)n * 12, hipMemcpyDeviceToHost, s));
+      SBR_HIP(hipMemcpyAsync(rec, df->rec.p, (size_t)n * 64, hipMemcpyDeviceToHost, s));
+      SBR_HIP(hipStreamSynchronize(s));
+    }
+    if (written) *written = std::max<int64_t>(n, 0);
+  });
+}
+
+sbr_status sbr_scene_wedges(sbr_context_t ctx, sbr_scene_t scene, int64_t capacity, double* geo, int32_t* groups,
+                            int64_t* count) {
+  return guard([&] {
+    auto* c = check_handle<sbr_context_s>(ctx, kContext, "context");
+    auto* sc = check_handle<sbr_scene_s>(scene, kScene, "scene");
+    set_device(c);
+    hipStream_t s = c->stream;
+    scene_wedges(sc, s);
+    if (count) *count = sc->n_wedges;
+    const int64_t n = std::min<int64_t>(capacity, sc->n_wedges);
+    if (n <= 0) return;
+    SBR_CHECK(geo || groups, SBR_E_INVALID_ARG, "output is NULL");
+    std::vector<WedgeDev> h((size_t)n);
+    SBR_HIP(hipMemcpyAsync(h.data(), sc->wedges.p, (size_t)n * sizeof(WedgeDev), hipMemcpyDeviceToHost, s));
+    SBR_HIP(hipStreamSynchronize(s));
+    for (int64_t i = 0; i < n; ++i) {
+      const WedgeDev& w = h[(size_t)i];
+      if (geo) {
+        double* g = geo + 8 * i;
+        for (int k = 0; k < 3; ++k) g[k] = w.a[k], g[3 + k] = w.a[k] + w.len * w.e[k];
+        g[6] = w.nw, g[7] = w.len;
+      }
+      if (groups) groups[2 * i] = w.g0, groups[2 * i + 1] = w.gn;
+    }
+  });
+}
+
+sbr_status sbr_diff_channel(sbr_context_t ctx, sbr_diff_t d, const double* freq, int32_t Nf, const float* atm_db,
+                            const float* atm_deg, int32_t pol_tx, int32_t pol_rx, void* H_c64, double* H_c128,
+                            uint32_t flags) {
+  return guard([&] {
+    auto* c = check_handle<sbr_context_s>(ctx, kContext, "context");
+    auto* df = check_handle<sbr_diff_s>(d, kDiff, "diffraction");
+    SBR_CHECK(H_c64 || H_c128, SBR_E_INVALID_ARG, "no output");
+    set_device(c);
+    hipStream_t s = c->stream;
+    FieldInputs F;
+    field_inputs(F, freq, Nf, atm_db, atm_deg, pol_tx, pol_rx, flags, s);
+    const size_t nH = (size_t)Nf * df->Nr * df->Nt;
+    Buf t64, t128;
+    float2* d64 = static_cast<float2*>(H_c64);
+    double2* d128 = reinterpret_cast<double2*>(H_c128);
+    const bool dev_out = flags & SBR_OUT_DEVICE;
+    if (!dev_out) {  // host H: add to a device copy of it
+      if (H_c64) {
+        t64.alloc(nH * 8, s), d64 = t64.as<float2>();
+        SBR_HIP(hipMemcpyAsync(d64, H_c64, nH * 8, hipMemcpyHostToDevice, s));
+      }
+      if (H_c128) {
+        t128.alloc(nH * 16, s), d128 = t128.as<double2>();
+        SBR_HIP(hipMemcpyAsync(d128, H_c128, nH * 16, hipMemcpyHostToDevice, s));
+      }
+    }
+    run_diff_channel(df, F.a.freq, Nf, F.a.atm_db, F.a.atm_deg, pol_tx, pol_rx, d64, d128, s);
+    if (!dev_out) {
+      if (H_c64) SBR_HIP(hipMemcpyAsync(H_c64, d64, nH * 8, hipMemcpyDeviceToHost, s));
+      if (H_c128) SBR_HIP(hipMemcpyAsync(H_c128, d128, nH * 16, hipMemcpyDeviceToHost, s));
+      SBR_HIP(hipStreamSynchronize(s));
+    }
+  });
+}
+
+sbr_status sbr_diff_field(sbr_context_t ctx, sbr_diff_t d, const double* freq, int32_t Nf, const float* atm_db,
+                          const float* atm_deg, int32_t pol_tx, int32_t pol_rx, double* a_c128, uint32_t flags) {
+  return guard([&] {
+    auto* c = check_handle<sbr_context_s>(ctx, kContext, "context");
+    auto* df = check_handle<sbr_diff_s>(d, kDiff, "diffraction");
+    SBR_CHECK(a_c128 != nullptr || df->n_paths == 0, SBR_E_INVALID_ARG, "output is NULL");
+    set_device(c);
+    hipStream_t s = c->stream;
+    FieldInputs F;
+    field_inputs(F, freq, Nf, atm_db, atm_deg, pol_tx, pol_rx, flags, s);
+    const size_t n = (size_t)df->n_paths * Nf;
+    Buf tmp;
+    double2* dst = reinterpret_cast<double2*>(a_c128);
+    if (!(flags & SBR_OUT_DEVICE)) tmp.alloc(std::max<size_t>(n, 1) * 16, s), dst = tmp.as<double2>();
+    run_diff_field(df, F.a.freq, Nf, F.a.atm_db, F.a.atm_deg, pol_tx, pol_rx, dst, s);
+    if (!(flags & SBR_OUT_DEVICE)) {
+      if (n) SBR_HIP(hipMemcpyAsync(a_c128, dst, n * 16, hipMemcpyDeviceToHost, s));
+      SBR_HIP(hipStreamSynchronize(s));
+    }
+  });
+}
+
+sbr_status sbr_utd_transition(sbr_context_t ctx, const double* X, int64_t n, double* F_c128, uint32_t flags) {
+  return guard([&] {
+    auto* c = check_handle<sbr_context_s>(ctx, kContext, "context");
+    SBR_CHECK(n >= 0 && (n == 0 || (X && F_c128)), SBR_E_INVALID_ARG, "transition arguments");
+    if (n == 0) return;
+    set_device(c);
+    hipStream_t s = c->stream;
+    Buf x, out;
+    upload(x, X, (size_t)n, flags, s);
+    double2* dst = reinterpret_cast<double2*>(F_c128);
+    if (!(flags & SBR_OUT_DEVICE)) out.alloc((size_t)n * 16, s), dst = out.as<double2>();
+    run_utd_transition(x.as<double>(), n, dst, s);
+    if (!(flags & SBR_OUT_DEVICE)) {
+      SBR_HIP(hipMemcpyAsync(F_c128, dst, (size_t)n * 16, hipMemcpyDeviceToHost, s));
       SBR_HIP(hipStreamSynchronize(s));
     }
   });

@@ -31,6 +31,27 @@ __device__ inline cd cadd(cd a, cd b) { return cd{a.re + b.re, a.im + b.im}; }
 __device__ inline cd csub(cd a, cd b) { return cd{a.re - b.re, a.im - b.im}; }
 __device__ inline cd cmul(cd a, cd b) { return cd{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
 __device__ inline cd cscale(cd a, double s) { return cd{a.re * s, a.im * s}; }
+// a / b with one division: conj(b) a / |b|^2.  The Fresnel terms are of
+// moderate size (|eps_c| below about 1e8 even for metals at 1 GHz), so |b|^2
+// neither overflows nor underflows, and the result is within a few ulps of
+// the exact quotient.
+__device__ inline cd cdiv_mod(cd a, cd b) {
+  const double inv = 1.0 / (b.re * b.re + b.im * b.im);
+  return cd{(a.re * b.re + a.im * b.im) * inv, (a.im * b.re - a.re * b.im) * inv};
+}
+// principal square root, |z| by a plain square root (moderate sizes as above)
+__device__ inline cd csqrt_mod(cd z) {
+  const double m = sqrt(z.re * z.re + z.im * z.im);
+  if (m == 0.0) return cd{0.0, 0.0};
+  if (z.re >= 0.0) {
+    const double r = sqrt(0.5 * (m + z.re));
+    return cd{r, z.im / (2.0 * r)};
+  }
+  double i = sqrt(0.5 * (m - z.re));
+  if (z.im < 0.0 || (z.im == 0.0 && signbit(z.im))) i = -i;
+  return cd{z.im / (2.0 * i), i};
+}
+
 
 // ----------------------------------------------------------------- geodesic
 // Icosahedron tables passed by value to kernels (built on the host by search).

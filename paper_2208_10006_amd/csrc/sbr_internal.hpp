@@ -15,6 +15,7 @@
 
 #include <atomic>
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -65,7 +66,7 @@ struct Error {
 #define SBR_LAUNCH_CHECK() SBR_HIP(hipGetLastError())
 
 // ----------------------------------------------------------------- handles
-enum Kind : int { kContext = 0x5bc0, kScene, kTrace, kPaths };
+enum Kind : int { kContext = 0x5bc0, kScene, kTrace, kPaths, kDiff };
 
 struct Handle {
   int kind;
@@ -225,11 +226,16 @@ struct sbr_scene_s : sbr::Handle {
   sbr::Buf gstart;   // int[G+1]
   sbr::Buf gtri;     // int[T]
   sbr::Buf tables;   // one block holding tplane .. gtri (those are views into it)
+  // wedge edges for diffraction (sbr::WedgeDev), built on first use
+  std::mutex wedge_mu;
+  bool have_wedges = false;
+  int64_t n_wedges = 0;
+  sbr::Buf wedges;
   // hand every buffer to stream s (built on a worker stream that has finished:
   // releases then follow the order of the stream that uses the scene)
   void rehome(hipStream_t s) {
     for (sbr::Buf* b : {&nodes, &root_box, &tri32, &tri64, &tplane, &tgroup, &tplaneid, &gplane, &gmat, &gstart,
-                        &gtri, &tables})
+                        &gtri, &tables, &wedges})
       if (b->p) b->stream = s;
   }
   sbr_scene_s() : Handle(sbr::kScene) {}
@@ -273,6 +279,20 @@ struct sbr_paths_s : sbr::Handle {
   bool have_power = false;
   sbr_paths_s() : Handle(sbr::kPaths) {}
   ~sbr_paths_s() override;
+};
+
+// First-order edge-diffraction paths of one (scene, Tx set, Rx set).
+struct sbr_diff_s : sbr::Handle {
+  sbr_context_s* ctx = nullptr;
+  sbr_scene_s* scene = nullptr;
+  int Nt = 0, Nr = 0;
+  int64_t n_candidates = 0, n_geometric = 0, n_paths = 0;
+  sbr::Buf tx, rx;      // double[N][3]
+  sbr::Buf ids;         // int32[n][3]: tx, rx, wedge (ordered by rx, tx, wedge)
+  sbr::Buf rec;         // double[n][8]: Q xyz, s', s, beta0, phi', phi
+  sbr::Buf seg_start;   // int32[Nr*Nt + 1]
+  sbr_diff_s() : Handle(sbr::kDiff) {}
+  ~sbr_diff_s() override;
 };
 
 namespace sbr {
@@ -385,6 +405,24 @@ void* capacity_scratch(int device);       // its address on `device`, or null be
 bool capacity_noalloc_fits(int Nf, int Nr, int Nt, int Nsnr);
 void run_capacity_noalloc(const float2* H, int Nf, int Nr, int Nt, const double* snr_db_host, int Nsnr,
                           int normalize, double* C_out, void* scratch, hipStream_t s);
+
+// diffract.hip (first-order edge diffraction)
+// one wedge edge: start point a, unit edge direction e, unit vector t0 in face 0
+// perpendicular to the edge, unit normal n0 of face 0 on the exterior side,
+// edge length, exterior angle / pi, face groups of face 0 and face n
+struct WedgeDev {
+  double a[3], e[3], t0[3], n0[3];
+  double len, nw;
+  int32_t g0, gn;
+};
+void scene_wedges(sbr_scene_s* sc, hipStream_t s);  // builds sc->wedges once (thread-safe)
+void run_diffract(sbr_diff_s* d, hipStream_t s);
+// H[f][q][p] += the diffracted field of every path (H64 and/or H128 may be null)
+void run_diff_channel(sbr_diff_s* d, const double* freq, int Nf, const float* atm_db, const float* atm_deg, int ptx,
+                      int prx, float2* H64, double2* H128, hipStream_t s);
+void run_diff_field(sbr_diff_s* d, const double* freq, int Nf, const float* atm_db, const float* atm_deg, int ptx,
+                    int prx, double2* out, hipStream_t s);
+void run_utd_transition(const double* X, int64_t n, double2* out, hipStream_t s);
 
 // nn.hip (surrogate)
 // mask (bf16, may be null): the product is zeroed where mask[i*ldm + j] <= 0;

@@ -85,6 +85,13 @@ def _load():
         "sbr_context_get_tuning": [P, C.c_char_p, P],
         "sbr_trace_batch": [P, I32, P, P, P, P, P, U32, P],
         "sbr_trace_latency": [P, P],
+        "sbr_diffract": [P, P, P, I32, P, I32, U32, P],
+        "sbr_diff_info": [P, P, P, P, P],
+        "sbr_diff_paths": [P, I64, P, P, P],
+        "sbr_scene_wedges": [P, P, I64, P, P, P],
+        "sbr_diff_channel": [P, P, P, I32, P, P, I32, I32, P, P, U32],
+        "sbr_diff_field": [P, P, P, I32, P, P, I32, I32, P, U32],
+        "sbr_utd_transition": [P, P, I64, P, U32],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -180,6 +187,10 @@ class Trace(_Handle):
 
 
 class Paths(_Handle):
+    pass
+
+
+class Diffraction(_Handle):
     pass
 
 
@@ -355,6 +366,77 @@ def sbr_path_field(ctx: Context, ps: Paths, freq, atm_db_per_m=None, atm_deg_per
     _call("sbr_path_field", ctx.h, ps.h, fa[0].ptr, nf, fa[1].ptr, fa[2].ptr, pol_tx, pol_rx, o.ptr,
           _flags(fa, SBR_IN_DEVICE))
     return out
+
+
+# ---------------------------------------------------------------- diffraction
+def sbr_diffract(ctx: Context, sc: Scene, tx, rx) -> Diffraction:
+    """First-order edge-diffraction paths of every (Tx, Rx) pair over the scene's wedges."""
+    a = [_Arr(tx, np.float64, F64), _Arr(rx, np.float64, F64)]
+    nt = (a[0].ref.numel() if _is_torch(a[0].ref) else a[0].ref.size) // 3
+    nr = (a[1].ref.numel() if _is_torch(a[1].ref) else a[1].ref.size) // 3
+    h = C.c_void_p()
+    _call("sbr_diffract", ctx.h, sc.h, a[0].ptr, nt, a[1].ptr, nr, _flags(a, SBR_IN_DEVICE), C.byref(h))
+    d = Diffraction(h, (ctx, sc))
+    d.Nt, d.Nr = nt, nr
+    return d
+
+
+def sbr_diff_info(d: Diffraction):
+    w, c, g, n = (C.c_int64() for _ in range(4))
+    _call("sbr_diff_info", d.h, C.byref(w), C.byref(c), C.byref(g), C.byref(n))
+    return {"wedges": w.value, "candidates": c.value, "geometric": g.value, "paths": n.value}
+
+
+def sbr_diff_paths(d: Diffraction):
+    """(ids [n, 3] int32: tx, rx, wedge; rec [n, 8]: Q xyz, s', s, beta0, phi', phi)."""
+    n = sbr_diff_info(d)["paths"]
+    ids = np.zeros((n, 3), np.int32)
+    rec = np.zeros((n, 8), np.float64)
+    w = C.c_int64()
+    _call("sbr_diff_paths", d.h, n, ids.ctypes.data_as(C.c_void_p), rec.ctypes.data_as(C.c_void_p), C.byref(w))
+    return ids, rec
+
+
+def sbr_scene_wedges(ctx: Context, sc: Scene):
+    """(geo [W, 8]: start xyz, end xyz, exterior angle / pi, length; groups [W, 2])."""
+    cnt = C.c_int64()
+    _call("sbr_scene_wedges", ctx.h, sc.h, 0, None, None, C.byref(cnt))
+    geo = np.zeros((cnt.value, 8), np.float64)
+    grp = np.zeros((cnt.value, 2), np.int32)
+    _call("sbr_scene_wedges", ctx.h, sc.h, cnt.value, geo.ctypes.data_as(C.c_void_p),
+          grp.ctypes.data_as(C.c_void_p), C.byref(cnt))
+    return geo, grp
+
+
+def sbr_diff_channel(ctx: Context, d: Diffraction, freq, atm_db_per_m=None, atm_deg_per_m=None, pol_tx=SBR_POL_V,
+                     pol_rx=SBR_POL_V, H_c64=None, H_c128=None):
+    """Adds the diffracted fields to H_c64 and/or H_c128 ([Nf, Nr, Nt])."""
+    fa = _field_args(freq, atm_db_per_m, atm_deg_per_m)
+    nf = (fa[0].ref.numel() if _is_torch(fa[0].ref) else fa[0].ref.size)
+    outs = [_Arr(H_c64, np.complex64), _Arr(H_c128, np.complex128)]
+    _call("sbr_diff_channel", ctx.h, d.h, fa[0].ptr, nf, fa[1].ptr, fa[2].ptr, pol_tx, pol_rx, outs[0].ptr,
+          outs[1].ptr, _flags(fa, SBR_IN_DEVICE) | _flags(outs, SBR_OUT_DEVICE))
+    for x, a in zip((H_c64, H_c128), outs):
+        if x is not None and not _is_torch(x) and a.ref is not x:
+            np.copyto(x, a.ref)
+
+
+def sbr_diff_field(ctx: Context, d: Diffraction, freq, atm_db_per_m=None, atm_deg_per_m=None, pol_tx=SBR_POL_V,
+                   pol_rx=SBR_POL_V):
+    fa = _field_args(freq, atm_db_per_m, atm_deg_per_m)
+    nf = (fa[0].ref.numel() if _is_torch(fa[0].ref) else fa[0].ref.size)
+    n = sbr_diff_info(d)["paths"]
+    out = np.zeros((n, nf), np.complex128)
+    _call("sbr_diff_field", ctx.h, d.h, fa[0].ptr, nf, fa[1].ptr, fa[2].ptr, pol_tx, pol_rx,
+          out.ctypes.data_as(C.c_void_p), _flags(fa, SBR_IN_DEVICE))
+    return out
+
+
+def sbr_utd_transition(ctx: Context, X):
+    x = np.ascontiguousarray(X, np.float64)
+    out = np.zeros(x.size, np.complex128)
+    _call("sbr_utd_transition", ctx.h, x.ctypes.data_as(C.c_void_p), x.size, out.ctypes.data_as(C.c_void_p), 0)
+    return out.reshape(x.shape)
 
 
 def sbr_stats(ps: Paths):

@@ -146,6 +146,19 @@ def test_wedges_of_a_box_and_a_plane():
     assert D.wedges(wq) == []
 
 
+def test_edges_resting_on_another_surface_are_not_wedges():
+    """A box standing on a ground quad: its four bottom edges lie on the
+    ground (another face group) and are not wedges; lifted 1 mm, they are."""
+    ground = W._quad((-10, -10, 0), (10, -10, 0), (10, 10, 0), (-10, 10, 0))
+    for z0, want in ((0.0, 8), (1e-3, 12)):
+        tris = ground + W.box_triangles((0.0, 0.0, z0), (1.0, 2.0, 3.0))
+        T = len(tris)
+        tri, e, s, r = W._pack(tris, [6.0] * 2 + [5.31] * (T - 2), [0.0326] * T, [0.0] * T)
+        w = W.Workload("box_on_ground", tri, e, s, r, np.array([[5.0, 5.0, 2.0]]), np.array([[-5.0, -5.0, 1.5]]),
+                       np.array([28e9]))
+        assert len(D.wedges(w)) == want, z0
+
+
 def test_vertical_edge_path_geometry():
     """Box [0,1] x [0,2] x [0,3]; Tx and Rx in its shadow on opposite sides
     of the edge x = 1, y = 2: the diffraction point satisfies Keller's cone
