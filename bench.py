@@ -523,8 +523,13 @@ def main():
     sc0 = S.sbr_scene_build(ctx, d["tri"], d["eps"], d["sig"], d["rough"])
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     tuned = A.autotune_trace(ctx, sc0, d["tx"], w.geodesic_N, w.max_bounces, w.T, arch=arch)
-    del sc0
-    log(f"[bench] tuned launch: {tuned['config']} ({tuned['bounce_ms']:.3f} ms per trace)")
+    tr0 = S.sbr_trace(ctx, sc0, d["tx"], w.geodesic_N, w.max_bounces)
+    S.sbr_synchronize(ctx)
+    rtuned = A.autotune_receive(ctx, tr0, d["rx"], 0.0, w.radius_coeff, len(w.tx) * w.rays_per_element,
+                                w.max_bounces, arch=arch)
+    del tr0, sc0
+    log(f"[bench] tuned launch: {tuned['config']} ({tuned['bounce_ms']:.3f} ms per trace), "
+        f"receive {rtuned['config']} ({rtuned['replay_ms']:.3f} ms per replay)")
     for i in range(args.warmup):
         handles = step(S, ctx, w, d)
         del handles
@@ -611,7 +616,7 @@ def main():
                       "rx_port_power_db": [round(float(v), 3) for v in
                                            10 * np.log10(d["P"].cpu().numpy().mean(axis=1))]
                       if d.get("P") is not None else None},
-           "kernels": kernels, "roofline": roofline, "tuning": tuned["config"]}
+           "kernels": kernels, "roofline": roofline, "tuning": {**tuned["config"], **rtuned["config"]}}
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle on a sample) ...")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

@@ -707,3 +707,38 @@ def test_autotuner_picks_and_applies(S, ctx, tmp_path):
     e2 = A.autotune_trace(ctx, sc, w.tx, w.geodesic_N, w.max_bounces, w.T, cache_path=path)
     assert e2["config"] == e["config"]  # served from the cache
     A.apply(ctx, {"trace_blocks_per_cu": 4, "trace_chunk": 64, "trace_graph": 0})
+
+
+def test_autotuner_array_order_and_receive(S, ctx, tmp_path):
+    """An array trace also searches the ray order; the receive tuner searches
+    the capture replay's block size; both leave the results unchanged."""
+    banner("autotuner: ray order, replay block")
+    from paper_2208_10006_amd import autotune as A
+    w = W.massive_mimo_office(N=40, nf=4).subset_tx(list(range(8)))
+    sc = S.sbr_scene_build(ctx, w.tri, w.eps_r, w.sigma, w.rough)
+    saved = A.current(ctx, A.KEYS + A.RECEIVE_KEYS)
+    try:
+        ref = S.sbr_trace_hits(S.sbr_trace(ctx, sc, w.tx, w.geodesic_N, w.max_bounces))
+        path = str(tmp_path / "tuning.json")
+        one = {"trace_blocks_per_cu": (4,), "trace_chunk": (128,), "trace_graph": (0,), "trace_leaf_share": (40,)}
+        e = A.autotune_trace(ctx, sc, w.tx, w.geodesic_N, w.max_bounces, w.T, cache_path=path, reps=1, grid=one)
+        assert len(e["searched"]) == 2
+        assert sorted(x["config"]["trace_order"] for x in e["searched"]) == [0, 1]
+        tr = S.sbr_trace(ctx, sc, w.tx, w.geodesic_N, w.max_bounces)
+        assert np.array_equal(S.sbr_trace_hits(tr), ref)
+        S.sbr_synchronize(ctx)
+        ps0 = S.sbr_receive(ctx, tr, w.rx, w.alpha, w.radius_coeff)
+        H0 = np.zeros((len(w.freq), len(w.rx), len(w.tx)), np.complex128)
+        S.sbr_channel(ctx, ps0, w.freq, H_c128=H0)
+        rays = len(w.tx) * (10 * w.geodesic_N ** 2 + 2)
+        r = A.autotune_receive(ctx, tr, w.rx, w.alpha, w.radius_coeff, rays, w.max_bounces, cache_path=path, reps=1)
+        assert [x["config"]["replay_block"] for x in r["searched"]] == list(A.REPLAY_BLOCKS)
+        assert S.sbr_context_get_tuning(ctx, "replay_block") == r["config"]["replay_block"]
+        ps = S.sbr_receive(ctx, tr, w.rx, w.alpha, w.radius_coeff)
+        H = np.zeros_like(H0)
+        S.sbr_channel(ctx, ps, w.freq, H_c128=H)
+        assert S.sbr_paths_info(ps) == S.sbr_paths_info(ps0) and np.array_equal(H, H0)
+        r2 = A.autotune_receive(ctx, tr, w.rx, w.alpha, w.radius_coeff, rays, w.max_bounces, cache_path=path)
+        assert r2["config"] == r["config"]  # served from the cache
+    finally:
+        A.apply(ctx, saved)
