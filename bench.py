@@ -398,6 +398,60 @@ def diffraction_main(args):
     print(json.dumps(out), flush=True)
 
 
+def scattering_main(args):
+    """First-order directive scattering on the massive-MIMO office with every
+    face 0.1 mm rough: every (surface tile, Tx element, Rx element)
+    candidate, both legs against the BVH, and the scattered fields of all
+    paths added to H over the band.  One step = sbr_scatter +
+    sbr_scat_channel (the scene is built before the timed region; the tile
+    table is built on the host inside each step)."""
+    import numpy as np
+    import torch
+    from paper_2208_10006_amd import sbr as S
+    from paper_2208_10006_amd import workloads as W
+
+    w = W.massive_mimo_office()
+    w.rough = np.full(len(w.tri), 0.1e-3)
+    dev = torch.device("cuda", 0)
+    d = make_inputs(w, torch, dev)
+    ctx = S.context_for_torch(0)
+    sc = S.sbr_scene_build(ctx, d["tri"], d["eps"], d["sig"], d["rough"])
+    ta, alpha = args.tile_area, args.alpha
+
+    def one():
+        df = S.sbr_scatter(ctx, sc, d["tx"], d["rx"], ta, alpha)
+        S.sbr_scat_channel(ctx, df, d["freq"], pol_tx=S.SBR_POL_V, pol_rx=S.SBR_POL_V, H_c64=d["H"])
+        return df
+
+    for _ in range(args.warmup):
+        h = one()
+        del h
+    torch.cuda.synchronize()
+    S.sbr_profile_only(ctx, "scattering")
+    S.sbr_profile_enable(ctx, True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        h = one()
+        if i + 1 < args.steps:
+            del h
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kms, kn = S.sbr_profile_query(ctx, "scattering")
+    S.sbr_profile_enable(ctx, False)
+    info = S.sbr_scat_info(h)
+    ms = (t1 - t0) * 1e3 / args.steps
+    out = {"metric": "scattering candidates/s (surface tile x Tx element x Rx element)",
+           "value": info["candidates"] / (ms * 1e-3), "unit": "candidates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64 geometry and field, f32 BVH boxes", "data": "synthetic",
+           "config": {"workload": f"first-order directive scattering, {describe(w)}, faces 0.1 mm rough",
+                      "tile_area_m2": ta, "alpha": alpha, **info,
+                      "paths_per_pair": info["paths"] / (len(w.tx) * len(w.rx)),
+                      "path_frequency_amplitudes_per_s": info["paths"] * len(w.freq) / (ms * 1e-3),
+                      "kernel_ms_per_step": kms / args.steps, "kernel_launches_per_step": kn / args.steps}}
+    print(json.dumps(out), flush=True)
+
+
 PEAK_BF16_TFLOPS = 2500.0
 
 
@@ -488,6 +542,8 @@ def main():
                     help="batched_uneven: contexts (streams and host threads) for the per-scene receives")
     ap.add_argument("--surrogate-steps", type=int, default=0, help="surrogate: training steps per member")
     ap.add_argument("--mimo-sizes", default="16,32,64,128", help="mimo_sweep: array sizes n (n Tx x n Rx)")
+    ap.add_argument("--tile-area", type=float, default=0.25, help="office_scattering: surface tile area, m^2")
+    ap.add_argument("--alpha", type=int, default=4, help="office_scattering: lobe exponent")
     ap.add_argument("--bvh-ploc-max", type=int, default=None,
                     help="largest scene (triangles) clustered with PLOC; larger ones use the LBVH")
     args = ap.parse_args()
@@ -507,6 +563,8 @@ def main():
         return mimo_main(args)
     if args.workload == "office_diffraction":
         return diffraction_main(args)
+    if args.workload == "office_scattering":
+        return scattering_main(args)
     import numpy as np
     import torch
     from paper_2208_10006_amd import sbr as S

@@ -59,6 +59,7 @@ typedef struct sbr_scene_s* sbr_scene_t;     /* triangles, face groups, BVH    *
 typedef struct sbr_trace_s* sbr_trace_t;     /* per-ray hit chains ("RT tree") */
 typedef struct sbr_paths_s* sbr_paths_t;     /* unique validated paths         */
 typedef struct sbr_diff_s* sbr_diff_t;       /* first-order diffraction paths  */
+typedef struct sbr_scat_s* sbr_scat_t;       /* first-order scattering paths   */
 
 /* One propagation path (Sec. II-A-4: a multipath component of eq. (2)/(4)).
  * tx, rx: element indices; order: number of reflections; groups: the face
@@ -229,6 +230,62 @@ sbr_status sbr_diff_field(sbr_context_t ctx, sbr_diff_t d, const double* freq_hz
  * of the diffraction coefficients at X[n] >= 0 (F = 0 at X = 0), interleaved
  * FP64 (diagnostic / parity output) */
 sbr_status sbr_utd_transition(sbr_context_t ctx, const double* X, int64_t n, double* F_c128, uint32_t flags);
+
+/* ------------------------------------------------------------------------ */
+/* First-order directive diffuse scattering (the scattering coefficient S of
+ * the field of a path, eq. (2), and the directive model based on the
+ * effective-roughness theory, Sec. II-A-2 and Fig. 3(b); the paper gives no
+ * formula).  The single-lobe directive pattern, first order
+ * (Tx -> surface tile -> Rx):
+ * tiles: triangle t of area A is cut by its barycentric grid into m^2 equal
+ * sub-triangles, m = max(1, ceil(sqrt(A / tile_area))); a tile is one
+ * sub-triangle (centroid C, area dS = A / m^2), numbered by triangle, then the
+ * upward sub-triangles by (i, j), then the downward ones by (i, j).  A path
+ * exists when Tx and Rx lie strictly on the same side of the triangle's plane
+ * and neither leg crosses a triangle outside the tile's face group (the
+ * image-method margins).  Field: the specular reflection of the incidence at
+ * C (the faces' Fresnel coefficients, eq. (6)-(7), on the reflection
+ * tracker's TE/TM bases) without its component along the scattering
+ * direction k_s, carrying the share 1 - rho^2 of the reflected power that the
+ * Kirchhoff factor rho (eq. (8)) removes from the specular reflection, spread
+ * by the lobe ((1 + cos psi) / 2)^alpha around the specular direction and
+ * normalised by its half-space integral F_alpha(theta_i):
+ *   a = lambda / (4 pi r_i r_s) sqrt(dS cos theta_i / F_alpha)
+ *       sqrt(1 - rho^2) ((1 + cos psi) / 2)^(alpha / 2) (E_s . e_rx)
+ *       10^(-g (r_i + r_s) / 20) e^{-j (2 pi f (r_i + r_s) / c + pi phi (r_i + r_s) / 180)}.
+ * sbr_scatter: tx_xyz [Nt][3], rx_xyz [Nr][3] FP64 (host, or device with
+ * SBR_IN_DEVICE); tile_area > 0 in m^2; 0 <= alpha <= 32; finishes before it
+ * returns; the handle keeps the scene.  Errors: INVALID_ARG (NULL, sizes,
+ * non-finite points, tile_area or alpha out of range), UNSUPPORTED when
+ * tiles x Nt x Nr >= 2^32 or there are 2^31 tiles or more. */
+sbr_status sbr_scatter(sbr_context_t ctx, sbr_scene_t sc, const double* tx_xyz, int32_t Nt, const double* rx_xyz,
+                       int32_t Nr, double tile_area, int32_t alpha, uint32_t flags, sbr_scat_t* out);
+/* counts: tiles, (tile, Tx, Rx) candidates, candidates with Tx and Rx on the
+ * tile's side, paths (any output may be NULL) */
+sbr_status sbr_scat_info(sbr_scat_t d, int64_t* tiles, int64_t* candidates, int64_t* same_side, int64_t* paths);
+/* the first min(capacity, paths) paths, ordered by (Rx, Tx, tile), to host
+ * arrays: ids [n][3] int32 (tx, rx, tile); rec [n][2] FP64 (r_i = |C - Tx|,
+ * r_s = |Rx - C|) */
+sbr_status sbr_scat_paths(sbr_scat_t d, int64_t capacity, int32_t* ids, double* rec, int64_t* written);
+/* the tiles in their numbering, to host arrays: geo [n][4] FP64 (centroid
+ * xyz, area), tri [n] int32 (triangle); count = number of tiles (either
+ * output may be NULL) */
+sbr_status sbr_scat_tiles(sbr_scat_t d, int64_t capacity, double* geo, int32_t* tri, int64_t* count);
+/* H[f][q][p] += the scattered fields of the pair's paths, summed in a fixed
+ * order (FP64), with the arguments of sbr_channel (H_c64 and/or H_c128 hold
+ * the field to add to: host, or device with SBR_OUT_DEVICE) */
+sbr_status sbr_scat_channel(sbr_context_t ctx, sbr_scat_t d, const double* freq_hz, int32_t Nf,
+                            const float* atm_db_per_m, const float* atm_deg_per_m, int32_t pol_tx, int32_t pol_rx,
+                            void* H_c64, double* H_c128, uint32_t flags);
+/* per-path scattered fields [paths][Nf] interleaved FP64 (diagnostic / parity output) */
+sbr_status sbr_scat_field(sbr_context_t ctx, sbr_scat_t d, const double* freq_hz, int32_t Nf,
+                          const float* atm_db_per_m, const float* atm_deg_per_m, int32_t pol_tx, int32_t pol_rx,
+                          double* a_c128, uint32_t flags);
+/* the lobe normalisation F_alpha(theta_i) = half-space integral of
+ * ((1 + cos psi) / 2)^alpha at cos_i[n] in [0, 1], FP64 (diagnostic / parity
+ * output); 0 <= alpha <= 32 */
+sbr_status sbr_scatter_lobe_norm(sbr_context_t ctx, int32_t alpha, const double* cos_i, int64_t n, double* out,
+                                 uint32_t flags);
 
 /* Per (Rx, Tx) statistics from the path powers of the last sbr_channel:
  * pg_db: 10 log10 sum P_n (incoherent path gain; -inf when no path),

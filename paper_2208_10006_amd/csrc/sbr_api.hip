@@ -525,6 +525,12 @@ sbr_diff_s::~sbr_diff_s() {
   if (scene) release(scene);
   if (ctx) release(ctx);
 }
+sbr_scat_s::~sbr_scat_s() {
+  if (ctx) (void)hipSetDevice(ctx->device);
+  tx.reset(), rx.reset(), tiles.reset(), lobe.reset(), ids.reset(), rec.reset(), seg_start.reset();
+  if (scene) release(scene);
+  if (ctx) release(ctx);
+}
 sbr_paths_s::~sbr_paths_s() {
   if (ctx) (void)hipSetDevice(ctx->device);
   rx.reset(), key.reset(), geo.reset(), info.reset(), ang.reset(), power.reset(), seg_start.reset();
@@ -1491,6 +1497,167 @@ sbr_status sbr_utd_transition(sbr_context_t ctx, const double* X, int64_t n, dou
     run_utd_transition(x.as<double>(), n, dst, s);
     if (!(flags & SBR_OUT_DEVICE)) {
       SBR_HIP(hipMemcpyAsync(F_c128, dst, (size_t)n * 16, hipMemcpyDeviceToHost, s));
+      SBR_HIP(hipStreamSynchronize(s));
+    }
+  });
+}
+
+// ---------------------------------------------------------------- directive scattering
+sbr_status sbr_scatter(sbr_context_t ctx, sbr_scene_t scene, const double* tx_xyz, int32_t Nt, const double* rx_xyz,
+                       int32_t Nr, double tile_area, int32_t alpha, uint32_t flags, sbr_scat_t* out) {
+  return guard([&] {
+    auto* c = check_handle<sbr_context_s>(ctx, kContext, "context");
+    auto* sc = check_handle<sbr_scene_s>(scene, kScene, "scene");
+    SBR_CHECK(out != nullptr, SBR_E_INVALID_ARG, "out is NULL");
+    SBR_CHECK(Nt >= 1 && Nr >= 1 && (int64_t)Nt * Nr < (int64_t(1) << 31), SBR_E_INVALID_ARG, "Nt = %d, Nr = %d", Nt,
+              Nr);
+    SBR_CHECK(tx_xyz && rx_xyz, SBR_E_INVALID_ARG, "tx or rx is NULL");
+    SBR_CHECK(std::isfinite(tile_area) && tile_area > 0.0, SBR_E_INVALID_ARG, "tile_area = %g must be > 0",
+              tile_area);
+    SBR_CHECK(alpha >= 0 && alpha <= kMaxScatAlpha, SBR_E_INVALID_ARG, "alpha = %d outside [0, %d]", alpha,
+              kMaxScatAlpha);
+    set_device(c);
+    hipStream_t s = c->stream;
+    const auto htx = to_host(tx_xyz, (size_t)Nt * 3, flags, s);
+    const auto hrx = to_host(rx_xyz, (size_t)Nr * 3, flags, s);
+    SBR_CHECK(finite_all(htx.data(), htx.size()) && finite_all(hrx.data(), hrx.size()), SBR_E_INVALID_ARG,
+              "tx and rx coordinates must be finite");
+    auto* d = new sbr_scat_s();
+    d->ctx = c, d->scene = sc;
+    retain(c), retain(sc);
+    try {
+      d->Nt = Nt, d->Nr = Nr, d->alpha = alpha, d->tile_area = tile_area;
+      upload(d->tx, htx.data(), htx.size(), 0, s);
+      upload(d->rx, hrx.data(), hrx.size(), 0, s);
+      run_scatter(d, s);
+    } catch (...) {
+      release(d);
+      throw;
+    }
+    *out = d;
+  });
+}
+
+sbr_status sbr_scat_info(sbr_scat_t d, int64_t* tiles, int64_t* candidates, int64_t* same_side, int64_t* paths) {
+  return guard([&] {
+    auto* df = check_handle<sbr_scat_s>(d, kScat, "scattering");
+    if (tiles) *tiles = df->n_tiles;
+    if (candidates) *candidates = df->n_candidates;
+    if (same_side) *same_side = df->n_sides;
+    if (paths) *paths = df->n_paths;
+  });
+}
+
+sbr_status sbr_scat_paths(sbr_scat_t d, int64_t capacity, int32_t* ids, double* rec, int64_t* written) {
+  return guard([&] {
+    auto* df = check_handle<sbr_scat_s>(d, kScat, "scattering");
+    const int64_t n = std::min<int64_t>(capacity, df->n_paths);
+    SBR_CHECK(n <= 0 || (ids && rec), SBR_E_INVALID_ARG, "output is NULL");
+    set_device(df->ctx);
+    hipStream_t s = df->ctx->stream;
+    if (n > 0) {
+      SBR_HIP(hipMemcpyAsync(ids, df->ids.p, (size_t)n * 12, hipMemcpyDeviceToHost, s));
+      SBR_HIP(hipMemcpyAsync(rec, df->rec.p, (size_t)n * 16, hipMemcpyDeviceToHost, s));
+      SBR_HIP(hipStreamSynchronize(s));
+    }
+    if (written) *written = std::max<int64_t>(n, 0);
+  });
+}
+
+sbr_status sbr_scat_tiles(sbr_scat_t d, int64_t capacity, double* geo, int32_t* tri, int64_t* count) {
+  return guard([&] {
+    auto* df = check_handle<sbr_scat_s>(d, kScat, "scattering");
+    if (count) *count = df->n_tiles;
+    const int64_t n = std::min<int64_t>(capacity, df->n_tiles);
+    if (n <= 0) return;
+    SBR_CHECK(geo || tri, SBR_E_INVALID_ARG, "output is NULL");
+    set_device(df->ctx);
+    hipStream_t s = df->ctx->stream;
+    std::vector<TileDev> h((size_t)n);
+    SBR_HIP(hipMemcpyAsync(h.data(), df->tiles.p, (size_t)n * sizeof(TileDev), hipMemcpyDeviceToHost, s));
+    SBR_HIP(hipStreamSynchronize(s));
+    for (int64_t i = 0; i < n; ++i) {
+      const TileDev& t = h[(size_t)i];
+      if (geo) geo[4 * i] = t.c[0], geo[4 * i + 1] = t.c[1], geo[4 * i + 2] = t.c[2], geo[4 * i + 3] = t.ds;
+      if (tri) tri[i] = t.tri;
+    }
+  });
+}
+
+sbr_status sbr_scat_channel(sbr_context_t ctx, sbr_scat_t d, const double* freq, int32_t Nf, const float* atm_db,
+                            const float* atm_deg, int32_t pol_tx, int32_t pol_rx, void* H_c64, double* H_c128,
+                            uint32_t flags) {
+  return guard([&] {
+    auto* c = check_handle<sbr_context_s>(ctx, kContext, "context");
+    auto* df = check_handle<sbr_scat_s>(d, kScat, "scattering");
+    SBR_CHECK(H_c64 || H_c128, SBR_E_INVALID_ARG, "no output");
+    set_device(c);
+    hipStream_t s = c->stream;
+    FieldInputs F;
+    field_inputs(F, freq, Nf, atm_db, atm_deg, pol_tx, pol_rx, flags, s);
+    const size_t nH = (size_t)Nf * df->Nr * df->Nt;
+    Buf t64, t128;
+    float2* d64 = static_cast<float2*>(H_c64);
+    double2* d128 = reinterpret_cast<double2*>(H_c128);
+    const bool dev_out = flags & SBR_OUT_DEVICE;
+    if (!dev_out) {  // host H: add to a device copy of it
+      if (H_c64) {
+        t64.alloc(nH * 8, s), d64 = t64.as<float2>();
+        SBR_HIP(hipMemcpyAsync(d64, H_c64, nH * 8, hipMemcpyHostToDevice, s));
+      }
+      if (H_c128) {
+        t128.alloc(nH * 16, s), d128 = t128.as<double2>();
+        SBR_HIP(hipMemcpyAsync(d128, H_c128, nH * 16, hipMemcpyHostToDevice, s));
+      }
+    }
+    run_scat_channel(df, F.a.freq, Nf, F.a.atm_db, F.a.atm_deg, pol_tx, pol_rx, d64, d128, s);
+    if (!dev_out) {
+      if (H_c64) SBR_HIP(hipMemcpyAsync(H_c64, d64, nH * 8, hipMemcpyDeviceToHost, s));
+      if (H_c128) SBR_HIP(hipMemcpyAsync(H_c128, d128, nH * 16, hipMemcpyDeviceToHost, s));
+      SBR_HIP(hipStreamSynchronize(s));
+    }
+  });
+}
+
+sbr_status sbr_scat_field(sbr_context_t ctx, sbr_scat_t d, const double* freq, int32_t Nf, const float* atm_db,
+                          const float* atm_deg, int32_t pol_tx, int32_t pol_rx, double* a_c128, uint32_t flags) {
+  return guard([&] {
+    auto* c = check_handle<sbr_context_s>(ctx, kContext, "context");
+    auto* df = check_handle<sbr_scat_s>(d, kScat, "scattering");
+    SBR_CHECK(a_c128 != nullptr || df->n_paths == 0, SBR_E_INVALID_ARG, "output is NULL");
+    set_device(c);
+    hipStream_t s = c->stream;
+    FieldInputs F;
+    field_inputs(F, freq, Nf, atm_db, atm_deg, pol_tx, pol_rx, flags, s);
+    const size_t n = (size_t)df->n_paths * Nf;
+    Buf tmp;
+    double2* dst = reinterpret_cast<double2*>(a_c128);
+    if (!(flags & SBR_OUT_DEVICE)) tmp.alloc(std::max<size_t>(n, 1) * 16, s), dst = tmp.as<double2>();
+    run_scat_field(df, F.a.freq, Nf, F.a.atm_db, F.a.atm_deg, pol_tx, pol_rx, dst, s);
+    if (!(flags & SBR_OUT_DEVICE)) {
+      if (n) SBR_HIP(hipMemcpyAsync(a_c128, dst, n * 16, hipMemcpyDeviceToHost, s));
+      SBR_HIP(hipStreamSynchronize(s));
+    }
+  });
+}
+
+sbr_status sbr_scatter_lobe_norm(sbr_context_t ctx, int32_t alpha, const double* cos_i, int64_t n, double* out,
+                                 uint32_t flags) {
+  return guard([&] {
+    auto* c = check_handle<sbr_context_s>(ctx, kContext, "context");
+    SBR_CHECK(alpha >= 0 && alpha <= kMaxScatAlpha, SBR_E_INVALID_ARG, "alpha = %d outside [0, %d]", alpha,
+              kMaxScatAlpha);
+    SBR_CHECK(n >= 0 && (n == 0 || (cos_i && out)), SBR_E_INVALID_ARG, "lobe normalisation arguments");
+    if (n == 0) return;
+    set_device(c);
+    hipStream_t s = c->stream;
+    Buf x, o;
+    upload(x, cos_i, (size_t)n, flags, s);
+    double* dst = out;
+    if (!(flags & SBR_OUT_DEVICE)) o.alloc((size_t)n * 8, s), dst = o.as<double>();
+    run_lobe_norm(alpha, x.as<double>(), n, dst, s);
+    if (!(flags & SBR_OUT_DEVICE)) {
+      SBR_HIP(hipMemcpyAsync(out, dst, (size_t)n * 8, hipMemcpyDeviceToHost, s));
       SBR_HIP(hipStreamSynchronize(s));
     }
   });

@@ -66,7 +66,7 @@ struct Error {
 #define SBR_LAUNCH_CHECK() SBR_HIP(hipGetLastError())
 
 // ----------------------------------------------------------------- handles
-enum Kind : int { kContext = 0x5bc0, kScene, kTrace, kPaths, kDiff };
+enum Kind : int { kContext = 0x5bc0, kScene, kTrace, kPaths, kDiff, kScat };
 
 struct Handle {
   int kind;
@@ -295,6 +295,24 @@ struct sbr_diff_s : sbr::Handle {
   ~sbr_diff_s() override;
 };
 
+// First-order directive scattering paths of one (scene, tile area, exponent,
+// Tx set, Rx set).
+struct sbr_scat_s : sbr::Handle {
+  sbr_context_s* ctx = nullptr;
+  sbr_scene_s* scene = nullptr;
+  int Nt = 0, Nr = 0, alpha = 0;
+  double tile_area = 0.0;
+  int64_t n_tiles = 0, n_candidates = 0, n_sides = 0, n_paths = 0;
+  sbr::Buf tx, rx;      // double[N][3]
+  sbr::Buf tiles;       // sbr::TileDev[n_tiles]
+  sbr::Buf lobe;        // double[alpha / 2 + 1][alpha + 1]: lobe normalisation table
+  sbr::Buf ids;         // int32[n][3]: tx, rx, tile (ordered by rx, tx, tile)
+  sbr::Buf rec;         // double[n][2]: r_i, r_s
+  sbr::Buf seg_start;   // int32[Nr*Nt + 1]
+  sbr_scat_s() : Handle(sbr::kScat) {}
+  ~sbr_scat_s() override;
+};
+
 namespace sbr {
 
 // ----------------------------------------------------------------- launchers
@@ -423,6 +441,23 @@ void run_diff_channel(sbr_diff_s* d, const double* freq, int Nf, const float* at
 void run_diff_field(sbr_diff_s* d, const double* freq, int Nf, const float* atm_db, const float* atm_deg, int ptx,
                     int prx, double2* out, hipStream_t s);
 void run_utd_transition(const double* X, int64_t n, double2* out, hipStream_t s);
+
+// scatter.hip (first-order directive scattering)
+// one surface tile: centroid, unit normal of its triangle, area, triangle and
+// face group
+struct TileDev {
+  double c[3], n[3];
+  double ds;
+  int32_t tri, group;
+};
+void run_scatter(sbr_scat_s* d, hipStream_t s);
+// H[f][q][p] += the scattered field of every path (H64 and/or H128 may be null)
+void run_scat_channel(sbr_scat_s* d, const double* freq, int Nf, const float* atm_db, const float* atm_deg, int ptx,
+                      int prx, float2* H64, double2* H128, hipStream_t s);
+void run_scat_field(sbr_scat_s* d, const double* freq, int Nf, const float* atm_db, const float* atm_deg, int ptx,
+                    int prx, double2* out, hipStream_t s);
+void run_lobe_norm(int alpha, const double* cos_i, int64_t n, double* out, hipStream_t s);
+constexpr int kMaxScatAlpha = 32;
 
 // nn.hip (surrogate)
 // mask (bf16, may be null): the product is zeroed where mask[i*ldm + j] <= 0;

@@ -92,6 +92,13 @@ def _load():
         "sbr_diff_channel": [P, P, P, I32, P, P, I32, I32, P, P, U32],
         "sbr_diff_field": [P, P, P, I32, P, P, I32, I32, P, U32],
         "sbr_utd_transition": [P, P, I64, P, U32],
+        "sbr_scatter": [P, P, P, I32, P, I32, D, I32, U32, P],
+        "sbr_scat_info": [P, P, P, P, P],
+        "sbr_scat_paths": [P, I64, P, P, P],
+        "sbr_scat_tiles": [P, I64, P, P, P],
+        "sbr_scat_channel": [P, P, P, I32, P, P, I32, I32, P, P, U32],
+        "sbr_scat_field": [P, P, P, I32, P, P, I32, I32, P, U32],
+        "sbr_scatter_lobe_norm": [P, I32, P, I64, P, U32],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -191,6 +198,10 @@ class Paths(_Handle):
 
 
 class Diffraction(_Handle):
+    pass
+
+
+class Scattering(_Handle):
     pass
 
 
@@ -436,6 +447,78 @@ def sbr_utd_transition(ctx: Context, X):
     x = np.ascontiguousarray(X, np.float64)
     out = np.zeros(x.size, np.complex128)
     _call("sbr_utd_transition", ctx.h, x.ctypes.data_as(C.c_void_p), x.size, out.ctypes.data_as(C.c_void_p), 0)
+    return out.reshape(x.shape)
+
+
+# ---------------------------------------------------------------- directive scattering
+def sbr_scatter(ctx: Context, sc: Scene, tx, rx, tile_area, alpha) -> Scattering:
+    """First-order directive scattering paths of every (Tx, Rx) pair over the scene's surface tiles."""
+    a = [_Arr(tx, np.float64, F64), _Arr(rx, np.float64, F64)]
+    nt = (a[0].ref.numel() if _is_torch(a[0].ref) else a[0].ref.size) // 3
+    nr = (a[1].ref.numel() if _is_torch(a[1].ref) else a[1].ref.size) // 3
+    h = C.c_void_p()
+    _call("sbr_scatter", ctx.h, sc.h, a[0].ptr, nt, a[1].ptr, nr, float(tile_area), int(alpha),
+          _flags(a, SBR_IN_DEVICE), C.byref(h))
+    d = Scattering(h, (ctx, sc))
+    d.Nt, d.Nr = nt, nr
+    return d
+
+
+def sbr_scat_info(d: Scattering):
+    t, c, g, n = (C.c_int64() for _ in range(4))
+    _call("sbr_scat_info", d.h, C.byref(t), C.byref(c), C.byref(g), C.byref(n))
+    return {"tiles": t.value, "candidates": c.value, "same_side": g.value, "paths": n.value}
+
+
+def sbr_scat_paths(d: Scattering):
+    """(ids [n, 3] int32: tx, rx, tile; rec [n, 2]: r_i, r_s)."""
+    n = sbr_scat_info(d)["paths"]
+    ids = np.zeros((n, 3), np.int32)
+    rec = np.zeros((n, 2), np.float64)
+    w = C.c_int64()
+    _call("sbr_scat_paths", d.h, n, ids.ctypes.data_as(C.c_void_p), rec.ctypes.data_as(C.c_void_p), C.byref(w))
+    return ids, rec
+
+
+def sbr_scat_tiles(d: Scattering):
+    """(geo [n, 4]: centroid xyz, area; tri [n] int32)."""
+    n = sbr_scat_info(d)["tiles"]
+    geo = np.zeros((n, 4), np.float64)
+    tri = np.zeros(n, np.int32)
+    cnt = C.c_int64()
+    _call("sbr_scat_tiles", d.h, n, geo.ctypes.data_as(C.c_void_p), tri.ctypes.data_as(C.c_void_p), C.byref(cnt))
+    return geo, tri
+
+
+def sbr_scat_channel(ctx: Context, d: Scattering, freq, atm_db_per_m=None, atm_deg_per_m=None, pol_tx=SBR_POL_V,
+                     pol_rx=SBR_POL_V, H_c64=None, H_c128=None):
+    """Adds the scattered fields to H_c64 and/or H_c128 ([Nf, Nr, Nt])."""
+    fa = _field_args(freq, atm_db_per_m, atm_deg_per_m)
+    nf = (fa[0].ref.numel() if _is_torch(fa[0].ref) else fa[0].ref.size)
+    outs = [_Arr(H_c64, np.complex64), _Arr(H_c128, np.complex128)]
+    _call("sbr_scat_channel", ctx.h, d.h, fa[0].ptr, nf, fa[1].ptr, fa[2].ptr, pol_tx, pol_rx, outs[0].ptr,
+          outs[1].ptr, _flags(fa, SBR_IN_DEVICE) | _flags(outs, SBR_OUT_DEVICE))
+    for x, a in zip((H_c64, H_c128), outs):
+        if x is not None and not _is_torch(x) and a.ref is not x:
+            np.copyto(x, a.ref)
+
+
+def sbr_scat_field(ctx: Context, d: Scattering, freq, atm_db_per_m=None, atm_deg_per_m=None, pol_tx=SBR_POL_V,
+                   pol_rx=SBR_POL_V):
+    fa = _field_args(freq, atm_db_per_m, atm_deg_per_m)
+    nf = (fa[0].ref.numel() if _is_torch(fa[0].ref) else fa[0].ref.size)
+    n = sbr_scat_info(d)["paths"]
+    out = np.zeros((n, nf), np.complex128)
+    _call("sbr_scat_field", ctx.h, d.h, fa[0].ptr, nf, fa[1].ptr, fa[2].ptr, pol_tx, pol_rx,
+          out.ctypes.data_as(C.c_void_p), _flags(fa, SBR_IN_DEVICE))
+    return out
+
+
+def sbr_scatter_lobe_norm(ctx: Context, alpha, cos_i):
+    x = np.ascontiguousarray(cos_i, np.float64)
+    out = np.zeros(x.size, np.float64)
+    _call("sbr_scatter_lobe_norm", ctx.h, int(alpha), x.ctypes.data_as(C.c_void_p), x.size,
+          out.ctypes.data_as(C.c_void_p), 0)
     return out.reshape(x.shape)
 
 
