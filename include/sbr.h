@@ -260,9 +260,10 @@ sbr_status sbr_utd_transition(sbr_context_t ctx, const double* X, int64_t n, dou
  * tiles x Nt x Nr >= 2^32 or there are 2^31 tiles or more. */
 sbr_status sbr_scatter(sbr_context_t ctx, sbr_scene_t sc, const double* tx_xyz, int32_t Nt, const double* rx_xyz,
                        int32_t Nr, double tile_area, int32_t alpha, uint32_t flags, sbr_scat_t* out);
-/* counts: tiles, (tile, Tx, Rx) candidates, candidates with Tx and Rx on the
- * tile's side, paths (any output may be NULL) */
-sbr_status sbr_scat_info(sbr_scat_t d, int64_t* tiles, int64_t* candidates, int64_t* same_side, int64_t* paths);
+/* counts: tiles, (tile, Tx, Rx) candidates, (tile, Tx) and (tile, Rx) legs
+ * with the point off the tile's plane and nothing in the way, paths (any
+ * output may be NULL) */
+sbr_status sbr_scat_info(sbr_scat_t d, int64_t* tiles, int64_t* candidates, int64_t* clear_legs, int64_t* paths);
 /* the first min(capacity, paths) paths, ordered by (Rx, Tx, tile), to host
  * arrays: ids [n][3] int32 (tx, rx, tile); rec [n][2] FP64 (r_i = |C - Tx|,
  * r_s = |Rx - C|) */

@@ -1538,12 +1538,12 @@ sbr_status sbr_scatter(sbr_context_t ctx, sbr_scene_t scene, const double* tx_xy
   });
 }
 
-sbr_status sbr_scat_info(sbr_scat_t d, int64_t* tiles, int64_t* candidates, int64_t* same_side, int64_t* paths) {
+sbr_status sbr_scat_info(sbr_scat_t d, int64_t* tiles, int64_t* candidates, int64_t* clear_legs, int64_t* paths) {
   return guard([&] {
     auto* df = check_handle<sbr_scat_s>(d, kScat, "scattering");
     if (tiles) *tiles = df->n_tiles;
     if (candidates) *candidates = df->n_candidates;
-    if (same_side) *same_side = df->n_sides;
+    if (clear_legs) *clear_legs = df->n_clear;
     if (paths) *paths = df->n_paths;
   });
 }

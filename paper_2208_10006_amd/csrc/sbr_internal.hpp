@@ -302,7 +302,7 @@ struct sbr_scat_s : sbr::Handle {
   sbr_scene_s* scene = nullptr;
   int Nt = 0, Nr = 0, alpha = 0;
   double tile_area = 0.0;
-  int64_t n_tiles = 0, n_candidates = 0, n_sides = 0, n_paths = 0;
+  int64_t n_tiles = 0, n_candidates = 0, n_clear = 0, n_paths = 0;
   sbr::Buf tx, rx;      // double[N][3]
   sbr::Buf tiles;       // sbr::TileDev[n_tiles]
   sbr::Buf lobe;        // double[alpha / 2 + 1][alpha + 1]: lobe normalisation table

@@ -61,48 +61,62 @@ struct ScatScene {
 };
 
 // candidate c = ((q Nt + p) NT + tile)
-__device__ inline bool scat_geometry(const ScatArgs& A, int64_t c, int& p, int& q, int& ti) {
+__device__ inline void scat_decode(const ScatArgs& A, int64_t c, int& p, int& q, int& ti) {
   ti = (int)(c % A.NT);
   const int64_t pr = c / A.NT;
   q = (int)(pr / A.Nt);
   p = (int)(pr - (int64_t)q * A.Nt);
-  const TileDev t = A.tl[ti];
-  const d3 C = ld3(t.c), n = ld3(t.n);
-  const double ht = dot(ld3(A.tx + 3 * p) - C, n), hr = dot(ld3(A.rx + 3 * q) - C, n);
-  return ht * hr > 0.0;
 }
 
-__global__ __launch_bounds__(256) void k_scat_candidates(ScatArgs A, int64_t C, uint32_t* __restrict__ flag) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= C) return;
-  int p, q, ti;
-  flag[c] = scat_geometry(A, c, p, q, ti) ? 1u : 0u;
-}
-
-__global__ __launch_bounds__(256) void k_scat_compact(const uint32_t* __restrict__ flag,
-                                                      const uint32_t* __restrict__ pos, int64_t n,
-                                                      const int64_t* __restrict__ src, int64_t* __restrict__ dst) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || !flag[i]) return;
-  dst[pos[i]] = src ? src[i] : i;
-}
-
+// The legs factor: Tx -> C depends on (tile, Tx) only and C -> Rx on (tile,
+// Rx) only, so each is traced once per (point, tile) rather than once per
+// (tile, Tx, Rx) candidate.  h[j NT + tile] = (P_j - C) . n for the tile's
+// centroid C and its triangle's unit normal n, set to 0 when the leg between
+// P_j and C (from P_j when from_point, else from C) crosses a triangle outside
+// the tile's face group; clear counts the non-zero entries.
 template <int STACK>
-__global__ __launch_bounds__(128) void k_scat_legs(ScatArgs A, ScatScene S, const int64_t* __restrict__ cand,
-                                                   int64_t n, uint32_t* __restrict__ flag) {
+__global__ __launch_bounds__(128) void k_scat_side(ScatArgs A, ScatScene S, const double* __restrict__ pts, int Np,
+                                                   int from_point, double* __restrict__ h,
+                                                   unsigned long long* __restrict__ clear) {
   __shared__ int32_t stack_mem[2][STACK][kWave];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int32_t* stk = &stack_mem[wv][0][lane];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int p, q, ti;
-  bool ok = scat_geometry(A, cand[i], p, q, ti);
-  if (ok) {
+  bool nz = false;
+  if (i < (int64_t)Np * A.NT) {
+    const int j = (int)(i / A.NT);
+    const int ti = (int)(i - (int64_t)j * A.NT);
     const TileDev t = A.tl[ti];
-    const d3 C = ld3(t.c), T = ld3(A.tx + 3 * p), R = ld3(A.rx + 3 * q);
-    ok = !leg_blocked<STACK>(S, stk, T, C, t.group, t.group) && !leg_blocked<STACK>(S, stk, C, R, t.group, t.group);
+    const d3 C = ld3(t.c), P = ld3(pts + 3 * j);
+    double v = dot(P - C, ld3(t.n));
+    if (v != 0.0) {
+      const bool b = from_point ? leg_blocked<STACK>(S, stk, P, C, t.group, t.group)
+                                : leg_blocked<STACK>(S, stk, C, P, t.group, t.group);
+      if (b) v = 0.0;
+    }
+    h[i] = v;
+    nz = v != 0.0;
   }
-  flag[i] = ok ? 1u : 0u;
+  const unsigned long long m = __ballot(nz);
+  if (lane == 0 && m) atomicAdd(clear, (unsigned long long)__popcll(m));
+}
+
+// a path: Tx and Rx strictly on the same side of the tile's plane, both legs clear
+__global__ __launch_bounds__(256) void k_scat_candidates(ScatArgs A, int64_t C, const double* __restrict__ ht,
+                                                         const double* __restrict__ hr, uint32_t* __restrict__ flag) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  int p, q, ti;
+  scat_decode(A, c, p, q, ti);
+  flag[c] = ht[(int64_t)p * A.NT + ti] * hr[(int64_t)q * A.NT + ti] > 0.0 ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(256) void k_scat_compact(const uint32_t* __restrict__ flag,
+                                                      const uint32_t* __restrict__ pos, int64_t n,
+                                                      int64_t* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || !flag[i]) return;
+  dst[pos[i]] = i;
 }
 
 // ids[i] = (tx, rx, tile), rec[i] = (r_i, r_s); paths per (Rx, Tx) pair counted
@@ -112,7 +126,7 @@ __global__ __launch_bounds__(256) void k_scat_records(ScatArgs A, const int64_t*
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int p, q, ti;
-  scat_geometry(A, path[i], p, q, ti);
+  scat_decode(A, path[i], p, q, ti);
   const TileDev t = A.tl[ti];
   const d3 C = ld3(t.c), dt = C - ld3(A.tx + 3 * p), dr = ld3(A.rx + 3 * q) - C;
   ids[3 * i] = p, ids[3 * i + 1] = q, ids[3 * i + 2] = ti;
@@ -176,7 +190,7 @@ struct ScatRec {
   double er, sg;     // eps_r and -sigma / (2 pi eps0): eps = er + j sg / f
   double gc;         // 4 pi h cos theta_i / c (the roughness exponent g = gc f); 0 on smooth faces
   double len, base;  // r_i + r_s; the amplitude without lambda and sqrt(1 - rho^2)
-  double pad;
+  double len_c;      // (r_i + r_s) / c
 };
 
 __device__ inline ScatRec scat_rec(const ScatArgs& A, const ScatField& F, const int32_t* ids, const double* rec) {
@@ -213,7 +227,7 @@ __device__ inline ScatRec scat_rec(const ScatArgs& A, const ScatField& F, const 
   g.er = (double)m.x;
   g.sg = -(double)m.y * (1.0 / (2.0 * kPi * kEps0));
   g.gc = m.z > 0.0f ? 4.0 * kPi * (double)m.z * cs / kC0 : 0.0;
-  g.pad = 0.0;
+  g.len_c = g.len / kC0;
   return g;
 }
 
@@ -223,15 +237,22 @@ __device__ inline cd scat_amplitude(const ScatRec& g, const ScatField& F, int fi
   const double cs = g.cs;
   const cd ec{g.er, g.sg * inv_f};
   const cd root = csqrt_mod(cd{ec.re - g.s2, ec.im});
-  const cd te = cdiv_mod(cd{cs - root.re, -root.im}, cd{cs + root.re, root.im});
+  // te = (cs - root) / (cs + root), tm = (ecc - root) / (ecc + root), one
+  // reciprocal for both denominators' squared magnitudes
   const cd ecc = cscale(ec, cs);
-  const cd tm = cdiv_mod(csub(ecc, root), cadd(ecc, root));
+  const cd d1{cs + root.re, root.im}, d2 = cadd(ecc, root);
+  const double n1 = d1.re * d1.re + d1.im * d1.im, n2 = d2.re * d2.re + d2.im * d2.im;
+  const double inv = 1.0 / (n1 * n2);
+  const double i1 = inv * n2, i2 = inv * n1;
+  const cd a1{cs - root.re, -root.im}, a2 = csub(ecc, root);
+  const cd te{(a1.re * d1.re + a1.im * d1.im) * i1, (a1.im * d1.re - a1.re * d1.im) * i1};
+  const cd tm{(a2.re * d2.re + a2.im * d2.im) * i2, (a2.im * d2.re - a2.re * d2.im) * i2};
   const double gg = g.gc * f;
-  const double rho = exp(-0.5 * gg * gg);
+  const double rho2 = exp(-gg * gg);  // rho^2, eq. (8) squared
   const cd pol = cadd(cscale(te, g.wa), cscale(tm, g.wb));
-  double amp = g.base * kC0 * inv_f * sqrt(fmax(0.0, 1.0 - rho * rho));
+  double amp = g.base * kC0 * inv_f * sqrt(fmax(0.0, 1.0 - rho2));
   if (F.atm_db) amp *= exp10(-(double)F.atm_db[fi] * g.len * (1.0 / 20.0));
-  const double cyc = f * g.len / kC0;
+  const double cyc = f * g.len_c;
   double ph = 2.0 * (cyc - floor(cyc));
   if (F.atm_deg) ph += (double)F.atm_deg[fi] * g.len * (1.0 / 180.0);
   double sn, cn;
@@ -395,52 +416,49 @@ void run_scatter(sbr_scat_s* d, hipStream_t s) {
   d->n_candidates = C;
   d->seg_start.alloc((size_t)(npair + 1) * 4, s);
   d->ids.alloc(4, s), d->rec.alloc(8, s);
-  d->n_sides = d->n_paths = 0;
+  d->n_clear = d->n_paths = 0;
   if (C == 0) {
     fill_u32(d->seg_start.as<uint32_t>(), 0, npair + 1, s);
     return;
   }
   const ScatArgs A = scat_args(d);
-  Buf flag, pos, tot, temp;
-  flag.alloc(C * 4, s), pos.alloc(C * 4, s), tot.alloc(8, s);
-  temp.alloc(scan_temp_bytes(C), s);
-  { ::sbr::TimedLaunch tl_("scattering", s); hipLaunchKernelGGL(k_scat_candidates, dim3(nblk(C, 256)), dim3(256), 0, s, A, C, flag.as<uint32_t>()); }
-  SBR_LAUNCH_CHECK();
-  exclusive_scan_u32(flag.as<uint32_t>(), pos.as<uint32_t>(), C, tot.as<uint32_t>(), temp.p, s);
-  uint32_t n1 = 0;
-  SBR_HIP(hipMemcpyAsync(&n1, tot.p, 4, hipMemcpyDeviceToHost, s));
-  SBR_HIP(hipStreamSynchronize(s));
-  d->n_sides = n1;
-  if (n1 == 0) {
-    fill_u32(d->seg_start.as<uint32_t>(), 0, npair + 1, s);
-    return;
-  }
-  Buf cand;
-  cand.alloc((size_t)n1 * 8, s);
-  { ::sbr::TimedLaunch tl_("scattering", s); hipLaunchKernelGGL(k_scat_compact, dim3(nblk(C, 256)), dim3(256), 0, s, flag.as<uint32_t>(), pos.as<uint32_t>(), C,
-                     (const int64_t*)nullptr, cand.as<int64_t>()); }
-  SBR_LAUNCH_CHECK();
   ScatScene S{sc->nodes.as<float4>(), sc->tri32.as<float4>(), sc->tri64.as<double>(), {}, sc->center[0],
               sc->center[1], sc->center[2], sc->n_bvh > 0, sc->n_big, (int)sc->n_bvh};
   for (int k = 0; k < 6; ++k) S.root[k] = sc->root_host[k];
-  Buf flag2, pos2;
-  flag2.alloc((size_t)n1 * 4, s), pos2.alloc((size_t)n1 * 4, s);
+  Buf ht, hr, clear;
+  ht.alloc((size_t)d->Nt * d->n_tiles * 8, s), hr.alloc((size_t)d->Nr * d->n_tiles * 8, s);
+  clear.alloc(8, s);
+  fill_u32(clear.as<uint32_t>(), 0, 2, s);
   {
     ::sbr::TimedLaunch tl_("scattering", s);
-    const unsigned g = nblk(n1, 128);
     const int depth = sc->bvh_depth;
-    if (depth <= 16)
-      hipLaunchKernelGGL(k_scat_legs<16>, dim3(g), dim3(128), 0, s, A, S, cand.as<int64_t>(), (int64_t)n1, flag2.as<uint32_t>());
-    else if (depth <= 32)
-      hipLaunchKernelGGL(k_scat_legs<32>, dim3(g), dim3(128), 0, s, A, S, cand.as<int64_t>(), (int64_t)n1, flag2.as<uint32_t>());
-    else
-      hipLaunchKernelGGL(k_scat_legs<64>, dim3(g), dim3(128), 0, s, A, S, cand.as<int64_t>(), (int64_t)n1, flag2.as<uint32_t>());
-    SBR_LAUNCH_CHECK();
+    for (int side = 0; side < 2; ++side) {
+      const int Np = side ? d->Nr : d->Nt;
+      const double* pts = side ? d->rx.as<double>() : d->tx.as<double>();
+      double* h = side ? hr.as<double>() : ht.as<double>();
+      const unsigned g = nblk((int64_t)Np * d->n_tiles, 128);
+      auto* cl = clear.as<unsigned long long>();
+      if (depth <= 16)
+        hipLaunchKernelGGL(k_scat_side<16>, dim3(g), dim3(128), 0, s, A, S, pts, Np, 1 - side, h, cl);
+      else if (depth <= 32)
+        hipLaunchKernelGGL(k_scat_side<32>, dim3(g), dim3(128), 0, s, A, S, pts, Np, 1 - side, h, cl);
+      else
+        hipLaunchKernelGGL(k_scat_side<64>, dim3(g), dim3(128), 0, s, A, S, pts, Np, 1 - side, h, cl);
+      SBR_LAUNCH_CHECK();
+    }
   }
-  exclusive_scan_u32(flag2.as<uint32_t>(), pos2.as<uint32_t>(), n1, tot.as<uint32_t>(), temp.p, s);
+  Buf flag, pos, tot, temp;
+  flag.alloc(C * 4, s), pos.alloc(C * 4, s), tot.alloc(8, s);
+  temp.alloc(scan_temp_bytes(C), s);
+  { ::sbr::TimedLaunch tl_("scattering", s); hipLaunchKernelGGL(k_scat_candidates, dim3(nblk(C, 256)), dim3(256), 0, s, A, C, ht.as<double>(), hr.as<double>(), flag.as<uint32_t>()); }
+  SBR_LAUNCH_CHECK();
+  exclusive_scan_u32(flag.as<uint32_t>(), pos.as<uint32_t>(), C, tot.as<uint32_t>(), temp.p, s);
   uint32_t n2 = 0;
+  unsigned long long ncl = 0;
   SBR_HIP(hipMemcpyAsync(&n2, tot.p, 4, hipMemcpyDeviceToHost, s));
+  SBR_HIP(hipMemcpyAsync(&ncl, clear.p, 8, hipMemcpyDeviceToHost, s));
   SBR_HIP(hipStreamSynchronize(s));
+  d->n_clear = (int64_t)ncl;
   d->n_paths = n2;
   if (n2 == 0) {
     fill_u32(d->seg_start.as<uint32_t>(), 0, npair + 1, s);
@@ -448,8 +466,8 @@ void run_scatter(sbr_scat_s* d, hipStream_t s) {
   }
   Buf paths, cnt;
   paths.alloc((size_t)n2 * 8, s);
-  { ::sbr::TimedLaunch tl_("scattering", s); hipLaunchKernelGGL(k_scat_compact, dim3(nblk(n1, 256)), dim3(256), 0, s, flag2.as<uint32_t>(), pos2.as<uint32_t>(),
-                     (int64_t)n1, cand.as<int64_t>(), paths.as<int64_t>()); }
+  { ::sbr::TimedLaunch tl_("scattering", s); hipLaunchKernelGGL(k_scat_compact, dim3(nblk(C, 256)), dim3(256), 0, s, flag.as<uint32_t>(), pos.as<uint32_t>(), C,
+                     paths.as<int64_t>()); }
   SBR_LAUNCH_CHECK();
   d->ids.alloc((size_t)n2 * 12, s);
   d->rec.alloc((size_t)n2 * 16, s);

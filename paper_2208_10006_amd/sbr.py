@@ -467,7 +467,7 @@ def sbr_scatter(ctx: Context, sc: Scene, tx, rx, tile_area, alpha) -> Scattering
 def sbr_scat_info(d: Scattering):
     t, c, g, n = (C.c_int64() for _ in range(4))
     _call("sbr_scat_info", d.h, C.byref(t), C.byref(c), C.byref(g), C.byref(n))
-    return {"tiles": t.value, "candidates": c.value, "same_side": g.value, "paths": n.value}
+    return {"tiles": t.value, "candidates": c.value, "clear_legs": g.value, "paths": n.value}
 
 
 def sbr_scat_paths(d: Scattering):

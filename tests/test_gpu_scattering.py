@@ -7,6 +7,8 @@ import sys
 import numpy as np
 import pytest
 
+from oracle import diffraction as D
+from oracle import oracle as O
 from oracle import scattering as SC
 from paper_2208_10006_amd import workloads as W
 
@@ -53,7 +55,27 @@ def test_lobe_norm(S, ctx, alpha):
     assert np.all(np.abs(got - want) <= 5e-14 * want), np.max(np.abs(got - want) / want)
 
 
-def _compare(S, ctx, w, tile_area, alpha, pols=((0, 0), (1, 1), (0, 1))):
+def _clear_legs(w, tl):
+    """(tile, Tx) and (tile, Rx) legs with the point off the tile's plane and
+    nothing in the way, counted with the oracle's blocking test."""
+    tri = np.asarray(w.tri, np.float64)
+    groups = O.scene_groups(w)[0]
+    tt, cc, _ = tl
+    cnt = 0
+    for pts, from_point in ((w.tx, True), (w.rx, False)):
+        for P in np.asarray(pts, np.float64):
+            for j in range(len(tt)):
+                v0, v1, v2 = tri[tt[j]]
+                n = np.cross(v1 - v0, v2 - v0)
+                n /= np.linalg.norm(n)
+                if float(np.dot(P - cc[j], n)) == 0.0:
+                    continue
+                a, b = (P, cc[j]) if from_point else (cc[j], P)
+                cnt += not D._blocked(tri, groups, a, b, (int(groups[tt[j]]),))[0]
+    return cnt
+
+
+def _compare(S, ctx, w, tile_area, alpha, pols=((0, 0), (1, 1), (0, 1)), check_legs=False):
     """GPU tiles, paths, fields and H against the oracle on workload w;
     returns the number of paths compared."""
     sc = S.sbr_scene_build(ctx, w.tri, w.eps_r, w.sigma, w.rough)
@@ -66,6 +88,8 @@ def _compare(S, ctx, w, tile_area, alpha, pols=((0, 0), (1, 1), (0, 1))):
     assert np.allclose(geo[:, :3], cc, rtol=0, atol=1e-13 * scale)
     assert np.allclose(geo[:, 3], aa, rtol=1e-13, atol=0)
     assert info["candidates"] == len(tt) * len(w.tx) * len(w.rx)
+    if check_legs:
+        assert info["clear_legs"] == _clear_legs(w, (tt, cc, aa))
     ids, rec = S.sbr_scat_paths(d)
     ops = SC.scattering_paths(w, tile_area, tl=(tt, cc, aa))
     print(info, "oracle paths", len(ops), "ambiguous", sum(p.ambiguous for p in ops), flush=True)
@@ -116,7 +140,7 @@ def test_single_box(S, ctx):
     tx = [[3.0, 1.0, 1.0], [-2.0, -1.0, 4.0], [0.5, 5.0, 0.5]]
     rx = [[-1.0, 2.5, 2.2], [2.0, -2.0, 1.5], [0.3, 1.0, 5.0], [4.0, 4.0, 3.5]]
     w = _box(tx, rx, freq=(28e9, 300e9), rough=0.1e-3)
-    n = _compare(S, ctx, w, 0.1, 4)
+    n = _compare(S, ctx, w, 0.1, 4, check_legs=True)
     assert n >= 100, n
 
 
@@ -167,7 +191,7 @@ def test_free_space_and_rejects(S, ctx):
     w = W.free_space()
     sc = S.sbr_scene_build(ctx, w.tri, w.eps_r, w.sigma, w.rough)
     d = S.sbr_scatter(ctx, sc, w.tx, w.rx, 1.0, 4)
-    assert S.sbr_scat_info(d) == {"tiles": 0, "candidates": 0, "same_side": 0, "paths": 0}
+    assert S.sbr_scat_info(d) == {"tiles": 0, "candidates": 0, "clear_legs": 0, "paths": 0}
     H = np.full((1, 1, 1), 1 + 2j)
     S.sbr_scat_channel(ctx, d, w.freq, H_c128=H)
     assert H[0, 0, 0] == 1 + 2j
