@@ -287,6 +287,19 @@ def diffraction_paths(w, wds=None, groups=None):
     return out
 
 
+def path_records(w, paths):
+    """[n, 5] per diffraction path: the delay (s' + s) / c, then the
+    departure direction Tx -> Q and the arrival direction Rx -> Q as
+    (azimuth, elevation) in degrees (reading R17's senses)."""
+    out = np.zeros((len(paths), 5))
+    for i, d in enumerate(paths):
+        Tx, R = np.asarray(w.tx[d.p], np.float64), np.asarray(w.rx[d.q], np.float64)
+        out[i, 0] = (d.sp + d.s) / C0
+        out[i, 1:3] = O.az_el((d.Q - Tx) / d.sp)
+        out[i, 3:5] = O.az_el((d.Q - R) / d.s)
+    return out
+
+
 def _pol_vec(u, pol):
     """theta-hat (pol 0) or phi-hat (pol 1) of direction u (the reflection
     oracle's antenna convention)."""

@@ -236,6 +236,23 @@ def mean_angles(P, az_deg, el_deg):
     return float(az), el
 
 
+def az_el(u):
+    """Azimuth atan2(u_y, u_x) and elevation asin(u_z) of a unit vector, in
+    degrees (the angles of reading R17)."""
+    return (float(np.degrees(np.arctan2(u[1], u[0]))),
+            float(np.degrees(np.arcsin(min(1.0, max(-1.0, float(u[2])))))))
+
+
+def link_stats(P, tau, ang):
+    """One link's path gain (dB, R18), RMS delay spread (eq. (5)) and mean
+    departure and arrival angles from the band power, delay and
+    [aod_az, aod_el, aoa_az, aoa_el] (degrees) of each of its paths, whatever
+    mechanism made them."""
+    P, tau, ang = np.asarray(P, float), np.asarray(tau, float), np.asarray(ang, float).reshape(-1, 4)
+    return (path_gain_db(P), tau_rms(tau, P),
+            np.array([*mean_angles(P, ang[:, 0], ang[:, 1]), *mean_angles(P, ang[:, 2], ang[:, 3])]))
+
+
 def capacity(H: np.ndarray, snr_db, normalize: bool = True) -> np.ndarray:
     """eq. (15)-(17): band-averaged log2 det(I + SNR/Nt W), W = Hn Hn^H
     (Nt >= Nr) or Hn^H Hn, with Frobenius normalisation Hn = H sqrt(Nt Nr / Q)."""

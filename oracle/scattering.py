@@ -136,6 +136,19 @@ def scattering_paths(w, tile_area, groups=None, tl=None):
     return out
 
 
+def path_records(w, paths):
+    """[n, 5] per scattering path: the delay (r_i + r_s) / c, then the
+    departure direction Tx -> C and the arrival direction Rx -> C as
+    (azimuth, elevation) in degrees (reading R17's senses)."""
+    out = np.zeros((len(paths), 5))
+    for i, d in enumerate(paths):
+        Tx, R = np.asarray(w.tx[d.p], np.float64), np.asarray(w.rx[d.q], np.float64)
+        out[i, 0] = (d.ri + d.rs) / C0
+        out[i, 1:3] = O.az_el((d.C - Tx) / d.ri)
+        out[i, 3:5] = O.az_el((d.C - R) / d.rs)
+    return out
+
+
 def scattering_field(w, paths, alpha, freq=None, atm_db=None, atm_deg=None, pol_tx=0, pol_rx=0):
     """a[path][f]: the received scattered field of every path (complex)."""
     tri = np.asarray(w.tri, np.float64)
