@@ -294,6 +294,18 @@ sbr_status sbr_scatter_lobe_norm(sbr_context_t ctx, int32_t alpha, const double*
  * azimuth, arithmetic mean elevation) of AoD then AoA.  Any output may be
  * NULL.  SBR_E_STATE before sbr_channel. */
 sbr_status sbr_stats(sbr_paths_t ps, float* pg_db, float* tau_rms_s, float* mean_angles, uint32_t flags);
+/* The same statistics over every mechanism's paths of each (Rx, Tx) link
+ * (Table I's quantities from reflection and diffraction paths together):
+ * the reflection paths of ps, then, when given, the diffraction paths of d
+ * and the scattering paths of sc, each with its band power from its last
+ * channel call (sbr_channel, sbr_diff_channel, sbr_scat_channel), its delay
+ * (length / c) and its departure and arrival directions (Tx -> first
+ * interaction, Rx -> last interaction).  d and sc may be NULL (then the
+ * result is sbr_stats's); they must have been made for the same Tx and Rx
+ * points, bit for bit.  Errors: SBR_E_STATE before the channel calls,
+ * INVALID_ARG for other points or sizes. */
+sbr_status sbr_stats_all(sbr_paths_t ps, sbr_diff_t d, sbr_scat_t sc, float* pg_db, float* tau_rms_s,
+                         float* mean_angles, uint32_t flags);
 
 /* MIMO capacity, eq. (15)-(17): C(SNR) = band mean of
  * log2 det(I + SNR/Nt W_f), W = Hn Hn^H (Nt >= Nr) or Hn^H Hn (Nt < Nr).

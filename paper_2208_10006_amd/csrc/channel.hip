@@ -152,26 +152,36 @@ __global__ void k_path_field(const double* __restrict__ geo, int stride, int64_t
 }
 
 // per (rx, tx): incoherent path gain, RMS delay spread (eq. (5)), mean angles
-// One wave per (rx, tx) pair: lane l takes paths l, l + 64, ... of the pair
-// and the nine sums are combined by an xor butterfly (a fixed order).
-__global__ __launch_bounds__(256) void k_stats(const int32_t* __restrict__ seg_start, int64_t nseg,
-                                               const double* __restrict__ power, const double* __restrict__ info,
-                                               const float* __restrict__ ang, float* __restrict__ pg_db,
+// over up to kMaxStatSets sets of paths (reflection, diffraction,
+// scattering).  One wave per (rx, tx) pair: lane l takes paths l, l + 64, ...
+// of the pair in each set in turn, and the nine sums are combined by an xor
+// butterfly (a fixed order).
+struct StatSets {
+  StatSet s[kMaxStatSets];
+  int n;
+};
+__global__ __launch_bounds__(256) void k_stats(const StatSets S, int64_t nseg, float* __restrict__ pg_db,
                                                float* __restrict__ tau, float* __restrict__ angles) {
   const int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int lane = threadIdx.x & 63;
   if (s >= nseg) return;  // whole waves leave together
   double P = 0, Pt = 0, Pt2 = 0, cd_ = 0, sd = 0, ed = 0, ca = 0, sa = 0, ea = 0;
-  for (int n = seg_start[s] + lane; n < seg_start[s + 1]; n += kWave) {
-    const double w = power[n], t = info[2 * n + 1];
-    P += w;
-    Pt += w * t;
-    Pt2 += w * t * t;
-    double sn, cn;
-    sincospi((double)ang[4 * n] / 180.0, &sn, &cn);
-    cd_ += w * cn, sd += w * sn, ed += w * ang[4 * n + 1];
-    sincospi((double)ang[4 * n + 2] / 180.0, &sn, &cn);
-    ca += w * cn, sa += w * sn, ea += w * ang[4 * n + 3];
+#pragma unroll
+  for (int k = 0; k < kMaxStatSets; ++k) {
+    if (k >= S.n) break;
+    const StatSet& T = S.s[k];
+    for (int n = T.seg_start[s] + lane; n < T.seg_start[s + 1]; n += kWave) {
+      const double w = T.power[n], t = T.delay[(int64_t)n * T.dstride];
+      const float* a = T.ang + 4 * (int64_t)n;
+      P += w;
+      Pt += w * t;
+      Pt2 += w * t * t;
+      double sn, cn;
+      sincospi((double)a[0] / 180.0, &sn, &cn);
+      cd_ += w * cn, sd += w * sn, ed += w * a[1];
+      sincospi((double)a[2] / 180.0, &sn, &cn);
+      ca += w * cn, sa += w * sn, ea += w * a[3];
+    }
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -538,10 +548,29 @@ void run_path_field(sbr_paths_s* ps, const ChannelArgs& a, double2* out, hipStre
   SBR_LAUNCH_CHECK();
 }
 
+void run_stats_sets(const StatSet* sets, int nsets, int64_t nseg, float* pg_db, float* tau, float* angles,
+                    hipStream_t s) {
+  SBR_CHECK(nsets >= 1 && nsets <= kMaxStatSets, SBR_E_INVALID_ARG, "%d path sets", nsets);
+  StatSets S{};
+  for (int k = 0; k < nsets; ++k) S.s[k] = sets[k];
+  S.n = nsets;
+  { ::sbr::TimedLaunch tl_("stats", s); hipLaunchKernelGGL(k_stats, dim3(nblk(nseg * kWave, 256)), dim3(256), 0, s, S, nseg, pg_db, tau, angles); }
+  SBR_LAUNCH_CHECK();
+}
+
+StatSet stat_set(sbr_paths_s* ps) {
+  return StatSet{ps->seg_start.as<int32_t>(), ps->power.as<double>(), ps->info.as<double>() + 1, 2,
+                 ps->ang.as<float>()};
+}
+
 void run_stats(sbr_paths_s* ps, float* pg_db, float* tau, float* angles, hipStream_t s) {
-  const int64_t nseg = (int64_t)ps->Nr * ps->trace->Nt;
-  { ::sbr::TimedLaunch tl_("stats", s); hipLaunchKernelGGL(k_stats, dim3(nblk(nseg * kWave, 256)), dim3(256), 0, s, ps->seg_start.as<int32_t>(), nseg,
-                     ps->power.as<double>(), ps->info.as<double>(), ps->ang.as<float>(), pg_db, tau, angles); }
+  const StatSet one = stat_set(ps);
+  run_stats_sets(&one, 1, (int64_t)ps->Nr * ps->trace->Nt, pg_db, tau, angles, s);
+}
+
+void run_power_final(const double* part, int64_t n, int ntiles, int Nf, double* power, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_power_final, dim3(nblk(n, 256)), dim3(256), 0, s, part, n, ntiles, Nf, power);
   SBR_LAUNCH_CHECK();
 }
 

@@ -309,14 +309,16 @@ __device__ inline cd diff_amplitude(const DiffPathGeo& g, const DiffField& F, in
 
 // One block per ((Rx, Tx) pair, 64 frequencies): lane = frequency, the four
 // waves take every fourth path of the pair, each sums its paths in order and
-// the wave sums are added in wave order; the result is added to H.
+// the wave sums are added in wave order; the result is added to H.  Each
+// path's |a|^2 summed over the tile's frequencies goes to part[n][tile].
 constexpr int kDiffTile = 64, kDiffWaves = 4;
 __global__ __launch_bounds__(kDiffTile * kDiffWaves) void k_diff_channel(DiffArgs A, DiffField F,
                                                                          const int32_t* __restrict__ seg_start,
                                                                          const int32_t* __restrict__ ids,
                                                                          const double* __restrict__ rec, int ntiles,
                                                                          float2* __restrict__ H64,
-                                                                         double2* __restrict__ H128) {
+                                                                         double2* __restrict__ H128,
+                                                                         double* __restrict__ part) {
   __shared__ double sre[kDiffWaves][kDiffTile], sim[kDiffWaves][kDiffTile];
   const int64_t seg = blockIdx.x / ntiles;
   const int tile = (int)(blockIdx.x - seg * ntiles);
@@ -330,7 +332,15 @@ __global__ __launch_bounds__(kDiffTile * kDiffWaves) void k_diff_channel(DiffArg
   cd acc{0.0, 0.0};
   for (int n = n0 + wv; n < n1; n += kDiffWaves) {
     const DiffPathGeo g = diff_path_geo(A, F, ids + 3 * (int64_t)n, rec + 8 * (int64_t)n);
-    if (on) acc = cadd(acc, diff_amplitude(g, F, fi, f, inv_f));
+    double ps = 0.0;
+    if (on) {
+      const cd a = diff_amplitude(g, F, fi, f, inv_f);
+      acc = cadd(acc, a);
+      ps = a.re * a.re + a.im * a.im;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) ps += __shfl_xor(ps, o, 64);
+    if (lane == 0) part[(int64_t)n * ntiles + tile] = ps;
   }
   sre[wv][lane] = acc.re;
   sim[wv][lane] = acc.im;
@@ -349,6 +359,24 @@ __global__ __launch_bounds__(kDiffTile * kDiffWaves) void k_diff_channel(DiffArg
       H64[o] = make_float2((float)((double)h.x + re), (float)((double)h.y + im));
     }
   }
+}
+
+// per path: delay (s' + s) / c, departure Tx -> Q and arrival Rx -> Q as
+// (azimuth, elevation) in degrees, for the per-link statistics
+__global__ __launch_bounds__(256) void k_diff_aux(DiffArgs A, const int32_t* __restrict__ ids,
+                                                  const double* __restrict__ rec, int64_t n, double* __restrict__ delay,
+                                                  float* __restrict__ ang) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double* r = rec + 8 * i;
+  const d3 Q = ld3(r), T = ld3(A.tx + 3 * ids[3 * i]), R = ld3(A.rx + 3 * ids[3 * i + 1]);
+  delay[i] = (r[3] + r[4]) / kC0;
+  const d3 u = (Q - T) * (1.0 / r[3]), v = (Q - R) * (1.0 / r[4]);
+  constexpr double deg = 180.0 / kPi;
+  ang[4 * i] = (float)(atan2(u.y, u.x) * deg);
+  ang[4 * i + 1] = (float)(asin(fmax(-1.0, fmin(1.0, u.z))) * deg);
+  ang[4 * i + 2] = (float)(atan2(v.y, v.x) * deg);
+  ang[4 * i + 3] = (float)(asin(fmax(-1.0, fmin(1.0, v.z))) * deg);
 }
 
 // a[n][f] of every path (diagnostic and parity output)
@@ -572,13 +600,29 @@ void run_diffract(sbr_diff_s* d, hipStream_t s) {
 void run_diff_channel(sbr_diff_s* d, const double* freq, int Nf, const float* atm_db, const float* atm_deg, int ptx,
                       int prx, float2* H64, double2* H128, hipStream_t s) {
   const int64_t npair = (int64_t)d->Nr * d->Nt;
-  if (d->n_paths == 0 || Nf == 0) return;
+  const int64_t np = d->n_paths;
+  d->power.alloc((size_t)std::max<int64_t>(np, 1) * 8, s);
+  d->have_power = true;
+  if (np == 0 || Nf == 0) return;
   const int ntiles = (Nf + kDiffTile - 1) / kDiffTile;
   SBR_CHECK(npair * ntiles < (int64_t(1) << 31), SBR_E_UNSUPPORTED, "too many (rx, tx) pairs x frequency tiles");
   const DiffArgs A = diff_args(d);
   const DiffField F = diff_field_args(d, freq, Nf, atm_db, atm_deg, ptx, prx);
-  { ::sbr::TimedLaunch tl_("diffraction", s); hipLaunchKernelGGL(k_diff_channel, dim3((unsigned)(npair * ntiles)), dim3(kDiffTile * kDiffWaves), 0, s, A, F,
-                     d->seg_start.as<int32_t>(), d->ids.as<int32_t>(), d->rec.as<double>(), ntiles, H64, H128); }
+  Buf part;
+  part.alloc((size_t)np * ntiles * 8, s);
+  ::sbr::TimedLaunch tl_("diffraction", s);
+  hipLaunchKernelGGL(k_diff_channel, dim3((unsigned)(npair * ntiles)), dim3(kDiffTile * kDiffWaves), 0, s, A, F,
+                     d->seg_start.as<int32_t>(), d->ids.as<int32_t>(), d->rec.as<double>(), ntiles, H64, H128,
+                     part.as<double>());
+  SBR_LAUNCH_CHECK();
+  run_power_final(part.as<double>(), np, ntiles, Nf, d->power.as<double>(), s);
+}
+
+void run_diff_aux(sbr_diff_s* d, double* delay, float* ang, hipStream_t s) {
+  const int64_t n = d->n_paths;
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_diff_aux, dim3(nblk(n, 256)), dim3(256), 0, s, diff_args(d), d->ids.as<int32_t>(),
+                     d->rec.as<double>(), n, delay, ang);
   SBR_LAUNCH_CHECK();
 }
 

@@ -521,13 +521,13 @@ sbr_trace_s::~sbr_trace_s() {
 }
 sbr_diff_s::~sbr_diff_s() {
   if (ctx) (void)hipSetDevice(ctx->device);
-  tx.reset(), rx.reset(), ids.reset(), rec.reset(), seg_start.reset();
+  tx.reset(), rx.reset(), ids.reset(), rec.reset(), seg_start.reset(), power.reset();
   if (scene) release(scene);
   if (ctx) release(ctx);
 }
 sbr_scat_s::~sbr_scat_s() {
   if (ctx) (void)hipSetDevice(ctx->device);
-  tx.reset(), rx.reset(), tiles.reset(), lobe.reset(), ids.reset(), rec.reset(), seg_start.reset();
+  tx.reset(), rx.reset(), tiles.reset(), lobe.reset(), ids.reset(), rec.reset(), seg_start.reset(), power.reset();
   if (scene) release(scene);
   if (ctx) release(ctx);
 }
@@ -1679,6 +1679,72 @@ sbr_status sbr_stats(sbr_paths_t p, float* pg_db, float* tau, float* angles, uin
     if (tau) b.alloc(nseg * 4, s);
     if (angles) cbuf.alloc(nseg * 16, s);
     run_stats(ps, a.as<float>(), b.as<float>(), cbuf.as<float>(), s);
+    if (pg_db) SBR_HIP(hipMemcpyAsync(pg_db, a.p, nseg * 4, hipMemcpyDeviceToHost, s));
+    if (tau) SBR_HIP(hipMemcpyAsync(tau, b.p, nseg * 4, hipMemcpyDeviceToHost, s));
+    if (angles) SBR_HIP(hipMemcpyAsync(angles, cbuf.p, nseg * 16, hipMemcpyDeviceToHost, s));
+    SBR_HIP(hipStreamSynchronize(s));
+  });
+}
+
+namespace {
+// the set's Tx and Rx points must be the traced ones, bit for bit
+void same_points(const Buf& tx, const Buf& rx, const std::vector<double>& htx, const Buf& prx, int Nt, int Nr,
+                 const char* what, hipStream_t s) {
+  std::vector<double> a((size_t)Nt * 3), b((size_t)Nr * 3), c((size_t)Nr * 3);
+  SBR_HIP(hipMemcpyAsync(a.data(), tx.p, a.size() * 8, hipMemcpyDeviceToHost, s));
+  SBR_HIP(hipMemcpyAsync(b.data(), rx.p, b.size() * 8, hipMemcpyDeviceToHost, s));
+  SBR_HIP(hipMemcpyAsync(c.data(), prx.p, c.size() * 8, hipMemcpyDeviceToHost, s));
+  SBR_HIP(hipStreamSynchronize(s));
+  SBR_CHECK(std::memcmp(a.data(), htx.data(), a.size() * 8) == 0 && std::memcmp(b.data(), c.data(), b.size() * 8) == 0,
+            SBR_E_INVALID_ARG, "the %s paths were found for other Tx or Rx points than the reflection paths", what);
+}
+}  // namespace
+
+sbr_status sbr_stats_all(sbr_paths_t p, sbr_diff_t d, sbr_scat_t sc, float* pg_db, float* tau, float* angles,
+                         uint32_t flags) {
+  return guard([&] {
+    auto* ps = check_handle<sbr_paths_s>(p, kPaths, "paths");
+    SBR_CHECK(ps->have_power, SBR_E_STATE, "sbr_stats_all needs a preceding sbr_channel");
+    sbr_diff_s* df = d ? check_handle<sbr_diff_s>(d, kDiff, "diffraction") : nullptr;
+    sbr_scat_s* st = sc ? check_handle<sbr_scat_s>(sc, kScat, "scattering") : nullptr;
+    const int Nt = ps->trace->Nt, Nr = ps->Nr;
+    SBR_CHECK(!df || (df->Nt == Nt && df->Nr == Nr), SBR_E_INVALID_ARG, "diffraction paths of %d Tx x %d Rx, "
+              "reflection paths of %d x %d", df ? df->Nt : 0, df ? df->Nr : 0, Nt, Nr);
+    SBR_CHECK(!st || (st->Nt == Nt && st->Nr == Nr), SBR_E_INVALID_ARG, "scattering paths of %d Tx x %d Rx, "
+              "reflection paths of %d x %d", st ? st->Nt : 0, st ? st->Nr : 0, Nt, Nr);
+    SBR_CHECK(!df || df->have_power, SBR_E_STATE, "sbr_stats_all needs a preceding sbr_diff_channel");
+    SBR_CHECK(!st || st->have_power, SBR_E_STATE, "sbr_stats_all needs a preceding sbr_scat_channel");
+    set_device(ps->ctx);
+    hipStream_t s = ps->ctx->stream;
+    if (df) same_points(df->tx, df->rx, ps->trace->h_tx, ps->rx, Nt, Nr, "diffraction", s);
+    if (st) same_points(st->tx, st->rx, ps->trace->h_tx, ps->rx, Nt, Nr, "scattering", s);
+    StatSet sets[kMaxStatSets];
+    int n = 0;
+    sets[n++] = stat_set(ps);
+    Buf dd, da, sd, sa;
+    if (df) {
+      const size_t m = (size_t)std::max<int64_t>(df->n_paths, 1);
+      dd.alloc(m * 8, s), da.alloc(m * 16, s);
+      run_diff_aux(df, dd.as<double>(), da.as<float>(), s);
+      sets[n++] = StatSet{df->seg_start.as<int32_t>(), df->power.as<double>(), dd.as<double>(), 1, da.as<float>()};
+    }
+    if (st) {
+      const size_t m = (size_t)std::max<int64_t>(st->n_paths, 1);
+      sd.alloc(m * 8, s), sa.alloc(m * 16, s);
+      run_scat_aux(st, sd.as<double>(), sa.as<float>(), s);
+      sets[n++] = StatSet{st->seg_start.as<int32_t>(), st->power.as<double>(), sd.as<double>(), 1, sa.as<float>()};
+    }
+    const size_t nseg = (size_t)Nr * Nt;
+    if (flags & SBR_OUT_DEVICE) {
+      run_stats_sets(sets, n, (int64_t)nseg, pg_db, tau, angles, s);
+      SBR_HIP(hipStreamSynchronize(s));  // the per-path records above are freed on return
+      return;
+    }
+    Buf a, b, cbuf;
+    if (pg_db) a.alloc(nseg * 4, s);
+    if (tau) b.alloc(nseg * 4, s);
+    if (angles) cbuf.alloc(nseg * 16, s);
+    run_stats_sets(sets, n, (int64_t)nseg, a.as<float>(), b.as<float>(), cbuf.as<float>(), s);
     if (pg_db) SBR_HIP(hipMemcpyAsync(pg_db, a.p, nseg * 4, hipMemcpyDeviceToHost, s));
     if (tau) SBR_HIP(hipMemcpyAsync(tau, b.p, nseg * 4, hipMemcpyDeviceToHost, s));
     if (angles) SBR_HIP(hipMemcpyAsync(angles, cbuf.p, nseg * 16, hipMemcpyDeviceToHost, s));

@@ -291,6 +291,8 @@ struct sbr_diff_s : sbr::Handle {
   sbr::Buf ids;         // int32[n][3]: tx, rx, wedge (ordered by rx, tx, wedge)
   sbr::Buf rec;         // double[n][8]: Q xyz, s', s, beta0, phi', phi
   sbr::Buf seg_start;   // int32[Nr*Nt + 1]
+  sbr::Buf power;       // double[n]: band power of each path in the last sbr_diff_channel
+  bool have_power = false;
   sbr_diff_s() : Handle(sbr::kDiff) {}
   ~sbr_diff_s() override;
 };
@@ -309,6 +311,8 @@ struct sbr_scat_s : sbr::Handle {
   sbr::Buf ids;         // int32[n][3]: tx, rx, tile (ordered by rx, tx, tile)
   sbr::Buf rec;         // double[n][2]: r_i, r_s
   sbr::Buf seg_start;   // int32[Nr*Nt + 1]
+  sbr::Buf power;       // double[n]: band power of each path in the last sbr_scat_channel
+  bool have_power = false;
   sbr_scat_s() : Handle(sbr::kScat) {}
   ~sbr_scat_s() override;
 };
@@ -424,6 +428,24 @@ bool capacity_noalloc_fits(int Nf, int Nr, int Nt, int Nsnr);
 void run_capacity_noalloc(const float2* H, int Nf, int Nr, int Nt, const double* snr_db_host, int Nsnr,
                           int normalize, double* C_out, void* scratch, hipStream_t s);
 
+// per-link statistics over several path sets (channel.hip): a set is a CSR
+// per (rx, tx) pair, each path's band power, its delay at delay[n * dstride]
+// and its angles [n][4] (departure azimuth, elevation, arrival azimuth,
+// elevation, degrees)
+struct StatSet {
+  const int32_t* seg_start;
+  const double* power;
+  const double* delay;
+  int dstride;
+  const float* ang;
+};
+constexpr int kMaxStatSets = 3;
+StatSet stat_set(sbr_paths_s* ps);
+void run_stats_sets(const StatSet* sets, int nsets, int64_t nseg, float* pg_db, float* tau, float* angles,
+                    hipStream_t s);
+// power[n] = (1 / Nf) sum over tiles of part[n * ntiles + tile], tiles in order
+void run_power_final(const double* part, int64_t n, int ntiles, int Nf, double* power, hipStream_t s);
+
 // diffract.hip (first-order edge diffraction)
 // one wedge edge: start point a, unit edge direction e, unit vector t0 in face 0
 // perpendicular to the edge, unit normal n0 of face 0 on the exterior side,
@@ -441,6 +463,8 @@ void run_diff_channel(sbr_diff_s* d, const double* freq, int Nf, const float* at
 void run_diff_field(sbr_diff_s* d, const double* freq, int Nf, const float* atm_db, const float* atm_deg, int ptx,
                     int prx, double2* out, hipStream_t s);
 void run_utd_transition(const double* X, int64_t n, double2* out, hipStream_t s);
+// per path: delay (s) and angles [n][4] (degrees) for the per-link statistics
+void run_diff_aux(sbr_diff_s* d, double* delay, float* ang, hipStream_t s);
 
 // scatter.hip (first-order directive scattering)
 // one surface tile: centroid, unit normal of its triangle, area, triangle and
@@ -457,6 +481,7 @@ void run_scat_channel(sbr_scat_s* d, const double* freq, int Nf, const float* at
 void run_scat_field(sbr_scat_s* d, const double* freq, int Nf, const float* atm_db, const float* atm_deg, int ptx,
                     int prx, double2* out, hipStream_t s);
 void run_lobe_norm(int alpha, const double* cos_i, int64_t n, double* out, hipStream_t s);
+void run_scat_aux(sbr_scat_s* d, double* delay, float* ang, hipStream_t s);
 constexpr int kMaxScatAlpha = 32;
 
 // nn.hip (surrogate)

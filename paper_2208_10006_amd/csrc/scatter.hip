@@ -267,15 +267,19 @@ __global__ __launch_bounds__(256) void k_scat_geo(ScatArgs A, ScatField F, const
   if (i < n) out[i] = scat_rec(A, F, ids + 3 * i, rec + 2 * i);
 }
 
-// block = (Rx, Tx) pair x 64 frequencies; its 4 waves take every 4th path of
+// block = (Rx, Tx) pair x 256 frequencies, lane l holding frequencies
+// l, l + 64, l + 128, l + 192 of the tile; its 4 waves take every 4th path of
 // the pair (a path's record is wave-uniform), then add in a fixed order.
-// Paths on smooth faces (rho = 1) scatter nothing and are skipped.
-constexpr int kScatTile = 64, kScatWaves = 4;
-__global__ __launch_bounds__(kScatTile * kScatWaves) void k_scat_channel(ScatField F, int Nt, int Nr,
-                                                                         const int32_t* __restrict__ seg_start,
-                                                                         const ScatRec* __restrict__ recs, int ntiles,
-                                                                         float2* __restrict__ H64,
-                                                                         double2* __restrict__ H128) {
+// Paths on smooth faces (rho = 1) scatter nothing and are skipped.  Each
+// path's |a|^2 summed over the tile's frequencies (one wave reduction per
+// path and tile) goes to part[n][tile].
+constexpr int kScatLaneF = 4, kScatWaves = 4, kScatTile = 64 * kScatLaneF;
+__global__ __launch_bounds__(64 * kScatWaves) void k_scat_channel(ScatField F, int Nt, int Nr,
+                                                                  const int32_t* __restrict__ seg_start,
+                                                                  const ScatRec* __restrict__ recs, int ntiles,
+                                                                  float2* __restrict__ H64,
+                                                                  double2* __restrict__ H128,
+                                                                  double* __restrict__ part) {
   __shared__ double sre[kScatWaves][kScatTile], sim[kScatWaves][kScatTile];
   const int64_t seg = blockIdx.x / ntiles;
   const int tile = (int)(blockIdx.x - seg * ntiles);
@@ -284,24 +288,48 @@ __global__ __launch_bounds__(kScatTile * kScatWaves) void k_scat_channel(ScatFie
   const int q = (int)(seg / Nt), p = (int)(seg - (int64_t)q * Nt);
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int fi = tile * kScatTile + lane;
-  const bool on = fi < F.Nf;
-  const double f = on ? F.freq[fi] : 1.0, inv_f = 1.0 / f;
-  cd acc{0.0, 0.0};
+  int fi[kScatLaneF];
+  bool on[kScatLaneF];
+  double f[kScatLaneF], inv_f[kScatLaneF];
+  cd acc[kScatLaneF];
+#pragma unroll
+  for (int j = 0; j < kScatLaneF; ++j) {
+    fi[j] = tile * kScatTile + 64 * j + lane;
+    on[j] = fi[j] < F.Nf;
+    f[j] = on[j] ? F.freq[fi[j]] : 1.0;
+    inv_f[j] = 1.0 / f[j];
+    acc[j] = cd{0.0, 0.0};
+  }
   for (int n = n0 + wv; n < n1; n += kScatWaves) {
     const ScatRec g = recs[n];
-    if (g.gc == 0.0) continue;
-    const cd a = scat_amplitude(g, F, on ? fi : 0, f, inv_f);
-    if (on) acc = cadd(acc, a);
-  }
-  sre[wv][lane] = acc.re;
-  sim[wv][lane] = acc.im;
-  __syncthreads();
-  if (wv == 0 && on) {
-    double re = sre[0][lane], im = sim[0][lane];
+    double ps = 0.0;
+    if (g.gc != 0.0) {
 #pragma unroll
-    for (int w = 1; w < kScatWaves; ++w) re += sre[w][lane], im += sim[w][lane];
-    const int64_t o = ((int64_t)fi * Nr + q) * Nt + p;
+      for (int j = 0; j < kScatLaneF; ++j) {
+        const cd a = scat_amplitude(g, F, on[j] ? fi[j] : 0, f[j], inv_f[j]);
+        if (on[j]) {
+          acc[j] = cadd(acc[j], a);
+          ps += a.re * a.re + a.im * a.im;
+        }
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) ps += __shfl_xor(ps, o, 64);
+    }
+    if (lane == 0) part[(int64_t)n * ntiles + tile] = ps;
+  }
+#pragma unroll
+  for (int j = 0; j < kScatLaneF; ++j) {
+    sre[wv][64 * j + lane] = acc[j].re;
+    sim[wv][64 * j + lane] = acc[j].im;
+  }
+  __syncthreads();
+  // thread t of the block finishes frequency t of the tile
+  const int t = threadIdx.x, ft = tile * kScatTile + t;
+  if (ft < F.Nf) {
+    double re = sre[0][t], im = sim[0][t];
+#pragma unroll
+    for (int w = 1; w < kScatWaves; ++w) re += sre[w][t], im += sim[w][t];
+    const int64_t o = ((int64_t)ft * Nr + q) * Nt + p;
     if (H128) {
       const double2 h = H128[o];
       H128[o] = make_double2(h.x + re, h.y + im);
@@ -311,6 +339,24 @@ __global__ __launch_bounds__(kScatTile * kScatWaves) void k_scat_channel(ScatFie
       H64[o] = make_float2((float)((double)h.x + re), (float)((double)h.y + im));
     }
   }
+}
+
+// per path: delay (r_i + r_s) / c, departure Tx -> C and arrival Rx -> C as
+// (azimuth, elevation) in degrees, for the per-link statistics
+__global__ __launch_bounds__(256) void k_scat_aux(ScatArgs A, const int32_t* __restrict__ ids,
+                                                  const double* __restrict__ rec, int64_t n, double* __restrict__ delay,
+                                                  float* __restrict__ ang) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double ri = rec[2 * i], rs = rec[2 * i + 1];
+  const d3 C = ld3(A.tl[ids[3 * i + 2]].c), T = ld3(A.tx + 3 * ids[3 * i]), R = ld3(A.rx + 3 * ids[3 * i + 1]);
+  delay[i] = (ri + rs) / kC0;
+  const d3 u = (C - T) * (1.0 / ri), v = (C - R) * (1.0 / rs);
+  constexpr double deg = 180.0 / kPi;
+  ang[4 * i] = (float)(atan2(u.y, u.x) * deg);
+  ang[4 * i + 1] = (float)(asin(fmax(-1.0, fmin(1.0, u.z))) * deg);
+  ang[4 * i + 2] = (float)(atan2(v.y, v.x) * deg);
+  ang[4 * i + 3] = (float)(asin(fmax(-1.0, fmin(1.0, v.z))) * deg);
 }
 
 __global__ __launch_bounds__(256) void k_scat_field(ScatField F, const ScatRec* __restrict__ recs, int64_t n,
@@ -498,14 +544,28 @@ void scat_records(sbr_scat_s* d, const ScatField& F, Buf& recs, hipStream_t s) {
 void run_scat_channel(sbr_scat_s* d, const double* freq, int Nf, const float* atm_db, const float* atm_deg, int ptx,
                       int prx, float2* H64, double2* H128, hipStream_t s) {
   const int64_t npair = (int64_t)d->Nr * d->Nt;
-  if (d->n_paths == 0 || Nf == 0) return;
+  const int64_t np = d->n_paths;
+  d->power.alloc((size_t)std::max<int64_t>(np, 1) * 8, s);
+  d->have_power = true;
+  if (np == 0 || Nf == 0) return;
   const int ntiles = (Nf + kScatTile - 1) / kScatTile;
   SBR_CHECK(npair * ntiles < (int64_t(1) << 31), SBR_E_UNSUPPORTED, "too many (rx, tx) pairs x frequency tiles");
   const ScatField F{freq, atm_db, atm_deg, Nf, ptx, prx, d->alpha, d->lobe.as<double>(), d->scene->gmat.as<float4>()};
-  Buf recs;
+  Buf recs, part;
   scat_records(d, F, recs, s);
-  { ::sbr::TimedLaunch tl_("scattering", s); hipLaunchKernelGGL(k_scat_channel, dim3((unsigned)(npair * ntiles)), dim3(kScatTile * kScatWaves), 0, s, F,
-                     d->Nt, d->Nr, d->seg_start.as<int32_t>(), recs.as<ScatRec>(), ntiles, H64, H128); }
+  part.alloc((size_t)np * ntiles * 8, s);
+  ::sbr::TimedLaunch tl_("scattering", s);
+  hipLaunchKernelGGL(k_scat_channel, dim3((unsigned)(npair * ntiles)), dim3(64 * kScatWaves), 0, s, F, d->Nt,
+                     d->Nr, d->seg_start.as<int32_t>(), recs.as<ScatRec>(), ntiles, H64, H128, part.as<double>());
+  SBR_LAUNCH_CHECK();
+  run_power_final(part.as<double>(), np, ntiles, Nf, d->power.as<double>(), s);
+}
+
+void run_scat_aux(sbr_scat_s* d, double* delay, float* ang, hipStream_t s) {
+  const int64_t n = d->n_paths;
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_scat_aux, dim3(nblk(n, 256)), dim3(256), 0, s, scat_args(d), d->ids.as<int32_t>(),
+                     d->rec.as<double>(), n, delay, ang);
   SBR_LAUNCH_CHECK();
 }
 

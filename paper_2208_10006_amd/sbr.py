@@ -99,6 +99,7 @@ def _load():
         "sbr_scat_channel": [P, P, P, I32, P, P, I32, I32, P, P, U32],
         "sbr_scat_field": [P, P, P, I32, P, P, I32, I32, P, U32],
         "sbr_scatter_lobe_norm": [P, I32, P, I64, P, U32],
+        "sbr_stats_all": [P, P, P, P, P, P, U32],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -531,6 +532,18 @@ def sbr_stats(ps: Paths):
           ang.ctypes.data_as(C.c_void_p), 0)
     return pg, tau, ang
 
+
+
+def sbr_stats_all(ps: Paths, d: "Diffraction" = None, sc: "Scattering" = None):
+    """Per-link path gain, RMS delay spread and mean angles over the
+    reflection paths of ps and, when given, the diffraction paths of d and
+    the scattering paths of sc."""
+    pg = np.zeros((ps.Nr, ps.Nt), np.float32)
+    tau = np.zeros((ps.Nr, ps.Nt), np.float32)
+    ang = np.zeros((ps.Nr, ps.Nt, 4), np.float32)
+    _call("sbr_stats_all", ps.h, d.h if d is not None else None, sc.h if sc is not None else None,
+          pg.ctypes.data_as(C.c_void_p), tau.ctypes.data_as(C.c_void_p), ang.ctypes.data_as(C.c_void_p), 0)
+    return pg, tau, ang
 
 def sbr_stats_device(ps: Paths, pg, tau, ang):
     """Device outputs (torch tensors on the context device)."""
