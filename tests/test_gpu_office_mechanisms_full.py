@@ -1,0 +1,150 @@
+"""First-order diffraction and directive scattering on the full massive-MIMO
+office (256 Tx x 64 Rx elements, 1,024 subcarriers) in the calls and sizes
+that bench.py times (`office_diffraction`: every wedge; `office_scattering`:
+every face 0.1 mm rough, 0.25 m^2 tiles, alpha 4), checked on sampled
+(Tx, Rx) pairs that the oracle enumerates one by one (every wedge of the
+pair; for scattering a random subset of the 26,704 tiles), and H as the
+FP64 sum of every path's field at three subcarriers."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import diffraction as D
+from oracle import scattering as SC
+from paper_2208_10006_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+AMP_RTOL = 1e-7
+
+
+def banner(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def office():
+    import torch
+
+    import bench
+    from paper_2208_10006_amd import sbr as S
+    w = W.massive_mimo_office()
+    dev = torch.device("cuda", 0)
+    d = bench.make_inputs(w, torch, dev)
+    ctx = S.context_for_torch(0)
+    sc = S.sbr_scene_build(ctx, d["tri"], d["eps"], d["sig"], d["rough"])
+    return S, ctx, w, d, sc, torch
+
+
+def _pair(w, p, q):
+    w1 = w.subset_tx([p])
+    w1.rx = np.ascontiguousarray(w.rx[[q]])
+    return w1
+
+
+def _h_check(S, d, w, ids, a3, fs, torch):
+    """H (complex64, filled from zero by the channel call) at subcarriers fs
+    against the FP64 sum of the per-path fields a3 [paths, 3]."""
+    Nr, Nt = len(w.rx), len(w.tx)
+    idx = ids[:, 1].astype(np.int64) * Nt + ids[:, 0]
+    ref = np.zeros((len(fs), Nr, Nt), np.complex128)
+    for k in range(len(fs)):  # bincount adds in path order, in FP64
+        ref[k] = (np.bincount(idx, weights=a3[:, k].real, minlength=Nr * Nt)
+                  + 1j * np.bincount(idx, weights=a3[:, k].imag, minlength=Nr * Nt)).reshape(Nr, Nt)
+    H = d["H"].cpu().numpy()[fs]
+    den = np.abs(ref) + 1e-6 * np.abs(ref).max()
+    err = float(np.max(np.abs(H - ref) / den))
+    print("max H error", err, flush=True)
+    assert err <= 1e-5, err
+
+
+def test_diffraction_full_office(office):
+    S, ctx, w, d, sc, torch = office
+    banner("office diffraction full size: 5,004 wedges x 256 x 64")
+    d["H"].zero_()
+    df = S.sbr_diffract(ctx, sc, d["tx"], d["rx"])
+    S.sbr_diff_channel(ctx, df, d["freq"], pol_tx=S.SBR_POL_V, pol_rx=S.SBR_POL_V, H_c64=d["H"])
+    torch.cuda.synchronize()
+    info = S.sbr_diff_info(df)
+    ids, rec = S.sbr_diff_paths(df)
+    assert info["candidates"] == 5004 * len(w.tx) * len(w.rx) and info["paths"] > 10000, info
+    fs = np.array([0, len(w.freq) // 2, len(w.freq) - 1])
+    a3 = S.sbr_diff_field(ctx, df, w.freq[fs])
+    _h_check(S, d, w, ids, a3, fs, torch)
+    wd = D.wedges(w)
+    rng = np.random.default_rng(21)
+    # pairs with paths, and two drawn over all pairs
+    with_paths = np.unique(ids[:, :2], axis=0)
+    pairs = [tuple(x) for x in with_paths[rng.choice(len(with_paths), 4, replace=False)]]
+    pairs += [(int(rng.integers(len(w.tx))), int(rng.integers(len(w.rx)))) for _ in range(2)]
+    n = 0
+    for p, q in pairs:
+        w1 = _pair(w, p, q)
+        ops = D.diffraction_paths(w1, wd)
+        sel = np.nonzero((ids[:, 0] == p) & (ids[:, 1] == q))[0]
+        g = {int(ids[i, 2]): i for i in sel}
+        o = {x.wedge: x for x in ops}
+        for j in set(g) ^ set(o):
+            assert j in o and o[j].ambiguous, ("pair", p, q, "wedge", j, j in g)
+        common = sorted(set(g) & set(o))
+        for j in common:
+            x = o[j]
+            want = np.array([*x.Q, x.sp, x.s, x.beta0, x.phip, x.phi])
+            assert np.allclose(rec[g[j]], want, rtol=1e-12, atol=1e-12 * 30), (p, q, j)
+        if common:
+            a_o, m_o = D.diffraction_field(w1, [o[j] for j in common], wd, freq=w.freq[fs], with_scale=True)
+            den = np.maximum(m_o, 1e-6 * m_o.max())
+            err = float(np.max(np.abs(a3[[g[j] for j in common]] - a_o) / den))
+            assert err <= AMP_RTOL, (p, q, err)
+        n += len(common)
+        print("pair", p, q, "gpu", len(sel), "oracle", len(ops), flush=True)
+    assert n >= 4, n
+
+
+def test_scattering_full_office(office):
+    S, ctx, w, d, sc, torch = office
+    banner("office scattering full size: 0.25 m^2 tiles x 256 x 64, rough faces")
+    wr = W.massive_mimo_office()
+    wr.rough = np.full(len(wr.tri), 0.1e-3)
+    scr = S.sbr_scene_build(ctx, wr.tri, wr.eps_r, wr.sigma, wr.rough)
+    d["H"].zero_()
+    st = S.sbr_scatter(ctx, scr, d["tx"], d["rx"], 0.25, 4)
+    S.sbr_scat_channel(ctx, st, d["freq"], pol_tx=S.SBR_POL_V, pol_rx=S.SBR_POL_V, H_c64=d["H"])
+    torch.cuda.synchronize()
+    info = S.sbr_scat_info(st)
+    tt, cc, aa = SC.tiles(wr, 0.25)
+    assert info["tiles"] == len(tt) and info["paths"] > 1000000, info
+    ids, rec = S.sbr_scat_paths(st)
+    fs = np.array([0, len(w.freq) // 2, len(w.freq) - 1])
+    a3 = S.sbr_scat_field(ctx, st, w.freq[fs])
+    _h_check(S, d, w, ids, a3, fs, torch)
+    rng = np.random.default_rng(22)
+    sub = np.sort(rng.choice(len(tt), 1500, replace=False))
+    in_sub = np.zeros(len(tt), bool)
+    in_sub[sub] = True
+    n = 0
+    for _ in range(3):
+        p, q = int(rng.integers(len(w.tx))), int(rng.integers(len(w.rx)))
+        w1 = _pair(wr, p, q)
+        ops = SC.scattering_paths(w1, 0.25, tl=(tt[sub], cc[sub], aa[sub]))
+        o = {int(sub[x.tile]): x for x in ops}
+        sel = np.nonzero((ids[:, 0] == p) & (ids[:, 1] == q))[0]
+        g = {int(ids[i, 2]): i for i in sel if in_sub[ids[i, 2]]}
+        for j in set(g) ^ set(o):
+            assert j in o and o[j].ambiguous, ("pair", p, q, "tile", j, j in g)
+        common = sorted(set(g) & set(o))
+        for j in common:
+            assert np.allclose(rec[g[j]], [o[j].ri, o[j].rs], rtol=1e-13, atol=0), (p, q, j)
+        if common:
+            a_g = a3[[g[j] for j in common]]
+            a_o = SC.scattering_field(w1, [o[j] for j in common], 4, freq=w.freq[fs])
+            a_x = SC.scattering_field(w1, [o[j] for j in common], 4, freq=w.freq[fs], pol_rx=1)
+            den = np.sqrt(np.abs(a_o) ** 2 + np.abs(a_x) ** 2)
+            den = np.maximum(den, 1e-6 * den.max())
+            err = float(np.max(np.abs(a_g - a_o) / den))
+            assert err <= 1e-8, (p, q, err)
+        n += len(common)
+        print("pair", p, q, "tiles", len(sub), "gpu", len(g), "oracle", len(ops), flush=True)
+    assert n >= 20, n
