@@ -164,12 +164,22 @@ __global__ __launch_bounds__(256) void k_diff_records(DiffArgs A, const int64_t*
 // Kouyoumjian-Pathak transition function F(X) = 2j sqrt(X) e^{jX} int_{sqrt X}^inf e^{-j t^2} dt.
 //  X < 5: the tail as (sqrt(pi)/2) e^{-j pi/4} - G(u), u = sqrt(X), with the
 //         power series G(u) = sum_k (-j)^k u^{2k+1} / (k! (2k+1));
-//  X >= 5: Laplace's continued fraction of the complementary error function,
-//         F = u e^{j pi/4} / (w + (1/2) / (w + (2/2) / (w + (3/2) / ...))),
+//  5 <= X < 80: Laplace's continued fraction of the complementary error
+//         function, F = u e^{j pi/4} / (w + (1/2) / (w + (2/2) / (w + (3/2) / ...))),
 //         w = e^{j pi/4} u, evaluated from the bottom (60, 40 or 20 levels:
-//         below 1e-14 relative for X >= 5, 8, 20).
+//         below 1e-14 relative for X >= 5, 8, 20);
+//  X >= 80: the asymptotic series from repeated integration by parts,
+//         F ~ sum_n (2n - 1)!! (j / (2X))^n, twelve terms (the first omitted
+//         term is below 7e-15 relative at X = 80).
 __device__ inline cd utd_transition(double X) {
   if (!(X > 0.0)) return cd{0.0, 0.0};
+  if (X >= 80.0) {
+    const double y = 0.5 / X, y2 = y * y;
+    const double re = 1.0 + y2 * (-3.0 + y2 * (105.0 + y2 * (-10395.0 + y2 * (2027025.0 + y2 * -654729075.0))));
+    const double im =
+        y * (1.0 + y2 * (-15.0 + y2 * (945.0 + y2 * (-135135.0 + y2 * (34459425.0 + y2 * -13749310575.0)))));
+    return cd{re, im};
+  }
   const double u = sqrt(X);
   const double r2 = 0.70710678118654752440;  // cos(pi/4)
   if (X < 5.0) {
@@ -196,28 +206,41 @@ __device__ inline cd utd_transition(double X) {
   return cdiv_mod(w, t);
 }
 
-// cot((pi + sign beta) / (2n)) F(k L a^{sign}(beta)),
-// a^{+-}(beta) = 2 cos^2((2 n pi N - beta) / 2), N the integer nearest (beta +- pi) / (2 pi n)
-__device__ inline cd utd_term(double beta, double nw, double kL, double sign) {
+// One term of the coefficients, cot((pi + sign beta) / (2n)) F(k L a^{sign}(beta)),
+// a^{+-}(beta) = 2 cos^2((2 n pi N - beta) / 2), N the integer nearest
+// (beta +- pi) / (2 pi n): the cotangent and X / f = (2 pi / c) L a, which
+// depend on the path only.
+__device__ inline void utd_term_geo(double beta, double nw, double L, double sign, double& ct, double& xf) {
   const double N = rint((beta + sign * kPi) / (2.0 * kPi * nw));
   const double c = cos((2.0 * nw * kPi * N - beta) * 0.5);
-  const double ct = 1.0 / tan((kPi + sign * beta) / (2.0 * nw));
-  return cscale(utd_transition(kL * 2.0 * c * c), ct);
+  ct = 1.0 / tan((kPi + sign * beta) / (2.0 * nw));
+  xf = (2.0 * kPi / kC0) * L * 2.0 * c * c;
 }
 
-// TE and TM reflection coefficients times the roughness factor (eq. (6)-(8))
-__device__ inline void face_reflection(float4 m, double f, double inv_f, double cs, cd& te, cd& tm) {
-  const double eim = -(1.0 / (2.0 * kPi * kEps0)) * inv_f;
-  const cd ec{(double)m.x, (double)m.y * eim};
-  const cd root = csqrt_mod(cd{ec.re - (1.0 - cs * cs), ec.im});
-  te = cdiv_mod(cd{cs - root.re, -root.im}, cd{cs + root.re, root.im});
+// TE and TM reflection coefficients of one face times its roughness factor
+// (eq. (6)-(8)), from the face's record: eps = er + j sg / f, cos and sin^2 of
+// the incidence angle, roughness exponent g = gc f (0 on smooth faces); one
+// reciprocal serves both quotients.
+struct FaceRec {
+  double er, sg, cs, s2, gc;
+};
+__device__ inline void face_reflection(const FaceRec& m, double f, double inv_f, cd& te, cd& tm) {
+  const double cs = m.cs;
+  const cd ec{m.er, m.sg * inv_f};
+  const cd root = csqrt_mod(cd{ec.re - m.s2, ec.im});
   const cd ecc = cscale(ec, cs);
-  tm = cdiv_mod(csub(ecc, root), cadd(ecc, root));
-  if (m.z > 0.0f) {
-    const double g = 4.0 * kPi * (double)m.z * cs * f / kC0;
+  const cd d1{cs + root.re, root.im}, d2 = cadd(ecc, root);
+  const double n1 = d1.re * d1.re + d1.im * d1.im, n2 = d2.re * d2.re + d2.im * d2.im;
+  const double inv = 1.0 / (n1 * n2);
+  double i1 = inv * n2, i2 = inv * n1;
+  if (m.gc != 0.0) {
+    const double g = m.gc * f;
     const double rho = exp(-0.5 * g * g);
-    te = cscale(te, rho), tm = cscale(tm, rho);
+    i1 *= rho, i2 *= rho;
   }
+  const cd a1{cs - root.re, -root.im}, a2 = csub(ecc, root);
+  te = cd{(a1.re * d1.re + a1.im * d1.im) * i1, (a1.im * d1.re - a1.re * d1.im) * i1};
+  tm = cd{(a2.re * d2.re + a2.im * d2.im) * i2, (a2.im * d2.re - a2.re * d2.im) * i2};
 }
 
 // theta-hat (pol 0) or phi-hat (pol 1) of direction u
@@ -242,26 +265,31 @@ struct DiffField {
   const float4* gmat;
 };
 
-// frequency-independent part of one path
-struct DiffPathGeo {
-  double eb, ep, rb, rp;  // Tx polarisation on beta0', phi'; beta0, phi on the Rx polarisation
-  double c0, cn;          // incidence cosines on face 0 and face n
-  double L, len, sp, s, sb, phip, phi, nw;
-  float4 m0, mn;
+// frequency-independent part of one path for one polarisation pair, written
+// once per call by k_diff_geo and read by every frequency
+struct DiffRec {
+  double wb, wp;       // -(E . beta0')(beta0 . e_rx) and -(E . phi')(phi . e_rx)
+  FaceRec f0, fn;      // the two faces at their true incidence angles
+  double ct[4], xf[4]; // the four terms: cotangent and X / f
+  double magc;         // 1 / (2 n sqrt(2 pi k) sin beta0) times sqrt(f)
+  double ampc;         // (c / 4 pi) sqrt(s' / (s (s + s'))) / s', times 1 / f
+  double len, len_c;   // s' + s and (s' + s) / c
 };
 
-__device__ inline DiffPathGeo diff_path_geo(const DiffArgs& A, const DiffField& F, const int32_t* ids,
-                                            const double* rec) {
-  DiffPathGeo g;
+__device__ inline FaceRec face_rec(float4 m, double cs) {
+  return FaceRec{(double)m.x, -(double)m.y * (1.0 / (2.0 * kPi * kEps0)), cs, 1.0 - cs * cs,
+                 m.z > 0.0f ? 4.0 * kPi * (double)m.z * cs / kC0 : 0.0};
+}
+
+__device__ inline DiffRec diff_rec(const DiffArgs& A, const DiffField& F, const int32_t* ids, const double* rec) {
+  DiffRec g;
   const int p = ids[0], q = ids[1], wi = ids[2];
   const WedgeDev w = A.wd[wi];
   const d3 Q = mk3(rec[0], rec[1], rec[2]);
   const d3 T = ld3(A.tx + 3 * p), R = ld3(A.rx + 3 * q);
-  g.sp = rec[3], g.s = rec[4];
-  const double b0 = rec[5];
-  g.phip = rec[6], g.phi = rec[7], g.nw = w.nw;
+  const double sp = rec[3], s = rec[4], b0 = rec[5], phip = rec[6], phi = rec[7], nw = w.nw;
   const d3 e = ld3(w.e);
-  const d3 ih = (Q - T) * (1.0 / g.sp), sh = (R - Q) * (1.0 / g.s);
+  const d3 ih = (Q - T) * (1.0 / sp), sh = (R - Q) * (1.0 / s);
   d3 php = cross(e, ih) * -1.0;
   php = php * (1.0 / sqrt(dot(php, php)));
   const d3 bp = cross(php, ih);
@@ -269,37 +297,43 @@ __device__ inline DiffPathGeo diff_path_geo(const DiffArgs& A, const DiffField& 
   ph = ph * (1.0 / sqrt(dot(ph, ph)));
   const d3 bh = cross(ph, sh);
   const d3 Ei = pol_vec(ih, F.ptx), Er = pol_vec(sh, F.prx);
-  g.eb = dot(Ei, bp), g.ep = dot(Ei, php), g.rb = dot(bh, Er), g.rp = dot(ph, Er);
-  g.sb = sin(b0);
-  g.c0 = g.sb * fabs(sin(g.phip));
-  g.cn = g.sb * fabs(sin(g.nw * kPi - g.phi));
-  g.L = g.s * g.sp * g.sb * g.sb / (g.s + g.sp);
-  g.len = g.s + g.sp;
-  g.m0 = F.gmat[w.g0], g.mn = F.gmat[w.gn];
+  g.wb = -dot(Ei, bp) * dot(bh, Er);
+  g.wp = -dot(Ei, php) * dot(ph, Er);
+  const double sb = sin(b0);
+  g.f0 = face_rec(F.gmat[w.g0], sb * fabs(sin(phip)));
+  g.fn = face_rec(F.gmat[w.gn], sb * fabs(sin(nw * kPi - phi)));
+  const double L = s * sp * sb * sb / (s + sp);
+  const double bm = phi - phip, bs = phi + phip;
+  utd_term_geo(bm, nw, L, 1.0, g.ct[0], g.xf[0]);
+  utd_term_geo(bm, nw, L, -1.0, g.ct[1], g.xf[1]);
+  utd_term_geo(bs, nw, L, -1.0, g.ct[2], g.xf[2]);
+  utd_term_geo(bs, nw, L, 1.0, g.ct[3], g.xf[3]);
+  g.magc = 1.0 / (2.0 * nw * sqrt(2.0 * kPi * (2.0 * kPi / kC0)) * sb);
+  g.ampc = (kC0 / (4.0 * kPi)) / sp * sqrt(sp / (s * (s + sp)));
+  g.len = s + sp;
+  g.len_c = g.len / kC0;
   return g;
 }
 
-// received diffracted field of one path at frequency f
-__device__ inline cd diff_amplitude(const DiffPathGeo& g, const DiffField& F, int fi, double f, double inv_f) {
-  const double k = 2.0 * kPi * f / kC0;
-  const double kL = k * g.L;
+// received diffracted field of one path at frequency f (rsf = 1 / sqrt(f))
+__device__ inline cd diff_amplitude(const DiffRec& g, const DiffField& F, int fi, double f, double inv_f,
+                                    double rsf) {
   cd r0te, r0tm, rnte, rntm;
-  face_reflection(g.m0, f, inv_f, g.c0, r0te, r0tm);
-  face_reflection(g.mn, f, inv_f, g.cn, rnte, rntm);
-  const double bm = g.phi - g.phip, bp = g.phi + g.phip;
-  const cd t12 = cadd(utd_term(bm, g.nw, kL, 1.0), utd_term(bm, g.nw, kL, -1.0));
-  const cd t3 = utd_term(bp, g.nw, kL, -1.0), t4 = utd_term(bp, g.nw, kL, 1.0);
+  face_reflection(g.f0, f, inv_f, r0te, r0tm);
+  face_reflection(g.fn, f, inv_f, rnte, rntm);
+  const cd t12 = cadd(cscale(utd_transition(f * g.xf[0]), g.ct[0]), cscale(utd_transition(f * g.xf[1]), g.ct[1]));
+  const cd t3 = cscale(utd_transition(f * g.xf[2]), g.ct[2]), t4 = cscale(utd_transition(f * g.xf[3]), g.ct[3]);
   const cd ds = cadd(t12, cadd(cmul(r0te, t3), cmul(rnte, t4)));
   const cd dh = cadd(t12, cadd(cmul(r0tm, t3), cmul(rntm, t4)));
   // -e^{-j pi/4} / (2 n sqrt(2 pi k) sin beta0)
   const double r2 = 0.70710678118654752440;
-  const double mag = 1.0 / (2.0 * g.nw * sqrt(2.0 * kPi * k) * g.sb);
+  const double mag = g.magc * rsf;
   const cd pre{-r2 * mag, r2 * mag};
   // E^d . e_rx = -D_s (E^i . beta0') (beta0 . e_rx) - D_h (E^i . phi') (phi . e_rx)
-  const cd pol = cmul(pre, cadd(cscale(ds, -g.eb * g.rb), cscale(dh, -g.ep * g.rp)));
-  double amp = (kC0 / (4.0 * kPi)) * inv_f / g.sp * sqrt(g.sp / (g.s * (g.s + g.sp)));
+  const cd pol = cmul(pre, cadd(cscale(ds, g.wb), cscale(dh, g.wp)));
+  double amp = g.ampc * inv_f;
   if (F.atm_db) amp *= exp10(-(double)F.atm_db[fi] * g.len * (1.0 / 20.0));
-  const double cyc = f * g.len / kC0;
+  const double cyc = f * g.len_c;
   double ph = 2.0 * (cyc - floor(cyc));  // in units of pi
   if (F.atm_deg) ph += (double)F.atm_deg[fi] * g.len * (1.0 / 180.0);
   double sn, cn;
@@ -307,49 +341,74 @@ __device__ inline cd diff_amplitude(const DiffPathGeo& g, const DiffField& F, in
   return cmul(pol, cd{amp * cn, -amp * sn});
 }
 
-// One block per ((Rx, Tx) pair, 64 frequencies): lane = frequency, the four
-// waves take every fourth path of the pair, each sums its paths in order and
-// the wave sums are added in wave order; the result is added to H.  Each
-// path's |a|^2 summed over the tile's frequencies goes to part[n][tile].
-constexpr int kDiffTile = 64, kDiffWaves = 4;
-__global__ __launch_bounds__(kDiffTile * kDiffWaves) void k_diff_channel(DiffArgs A, DiffField F,
-                                                                         const int32_t* __restrict__ seg_start,
-                                                                         const int32_t* __restrict__ ids,
-                                                                         const double* __restrict__ rec, int ntiles,
-                                                                         float2* __restrict__ H64,
-                                                                         double2* __restrict__ H128,
-                                                                         double* __restrict__ part) {
+__global__ __launch_bounds__(256) void k_diff_geo(DiffArgs A, DiffField F, const int32_t* __restrict__ ids,
+                                                  const double* __restrict__ rec, int64_t n,
+                                                  DiffRec* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = diff_rec(A, F, ids + 3 * i, rec + 8 * i);
+}
+
+// One block per ((Rx, Tx) pair, 256 frequencies), lane l holding frequencies
+// l, l + 64, l + 128, l + 192 of the tile; the four waves take every fourth
+// path of the pair (a path's record is wave-uniform), each sums its paths in
+// order and the wave sums are added in wave order; the result is added to H.
+// Each path's |a|^2 summed over the tile's frequencies goes to part[n][tile].
+constexpr int kDiffLaneF = 4, kDiffWaves = 4, kDiffTile = 64 * kDiffLaneF;
+__global__ __launch_bounds__(64 * kDiffWaves) void k_diff_channel(DiffField F, int Nt, int Nr,
+                                                                  const int32_t* __restrict__ seg_start,
+                                                                  const DiffRec* __restrict__ recs, int ntiles,
+                                                                  float2* __restrict__ H64,
+                                                                  double2* __restrict__ H128,
+                                                                  double* __restrict__ part) {
   __shared__ double sre[kDiffWaves][kDiffTile], sim[kDiffWaves][kDiffTile];
   const int64_t seg = blockIdx.x / ntiles;
   const int tile = (int)(blockIdx.x - seg * ntiles);
   const int n0 = seg_start[seg], n1 = seg_start[seg + 1];
   if (n0 == n1) return;  // the whole block: no path for this pair
-  const int q = (int)(seg / A.Nt), p = (int)(seg - (int64_t)q * A.Nt);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int fi = tile * kDiffTile + lane;
-  const bool on = fi < F.Nf;
-  const double f = on ? F.freq[fi] : 1.0, inv_f = 1.0 / f;
-  cd acc{0.0, 0.0};
+  const int q = (int)(seg / Nt), p = (int)(seg - (int64_t)q * Nt);
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int fi[kDiffLaneF];
+  bool on[kDiffLaneF];
+  double f[kDiffLaneF], inv_f[kDiffLaneF], rsf[kDiffLaneF];
+  cd acc[kDiffLaneF];
+#pragma unroll
+  for (int j = 0; j < kDiffLaneF; ++j) {
+    fi[j] = tile * kDiffTile + 64 * j + lane;
+    on[j] = fi[j] < F.Nf;
+    f[j] = on[j] ? F.freq[fi[j]] : 1.0;
+    inv_f[j] = 1.0 / f[j];
+    rsf[j] = 1.0 / sqrt(f[j]);
+    acc[j] = cd{0.0, 0.0};
+  }
   for (int n = n0 + wv; n < n1; n += kDiffWaves) {
-    const DiffPathGeo g = diff_path_geo(A, F, ids + 3 * (int64_t)n, rec + 8 * (int64_t)n);
+    const DiffRec g = recs[n];
     double ps = 0.0;
-    if (on) {
-      const cd a = diff_amplitude(g, F, fi, f, inv_f);
-      acc = cadd(acc, a);
-      ps = a.re * a.re + a.im * a.im;
+#pragma unroll
+    for (int j = 0; j < kDiffLaneF; ++j) {
+      const cd a = diff_amplitude(g, F, on[j] ? fi[j] : 0, f[j], inv_f[j], rsf[j]);
+      if (on[j]) {
+        acc[j] = cadd(acc[j], a);
+        ps += a.re * a.re + a.im * a.im;
+      }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) ps += __shfl_xor(ps, o, 64);
     if (lane == 0) part[(int64_t)n * ntiles + tile] = ps;
   }
-  sre[wv][lane] = acc.re;
-  sim[wv][lane] = acc.im;
-  __syncthreads();
-  if (wv == 0 && on) {
-    double re = sre[0][lane], im = sim[0][lane];
 #pragma unroll
-    for (int w = 1; w < kDiffWaves; ++w) re += sre[w][lane], im += sim[w][lane];
-    const int64_t o = ((int64_t)fi * A.Nr + q) * A.Nt + p;
+  for (int j = 0; j < kDiffLaneF; ++j) {
+    sre[wv][64 * j + lane] = acc[j].re;
+    sim[wv][64 * j + lane] = acc[j].im;
+  }
+  __syncthreads();
+  // thread t of the block finishes frequency t of the tile
+  const int t = threadIdx.x, ft = tile * kDiffTile + t;
+  if (ft < F.Nf) {
+    double re = sre[0][t], im = sim[0][t];
+#pragma unroll
+    for (int w = 1; w < kDiffWaves; ++w) re += sre[w][t], im += sim[w][t];
+    const int64_t o = ((int64_t)ft * Nr + q) * Nt + p;
     if (H128) {
       const double2 h = H128[o];
       H128[o] = make_double2(h.x + re, h.y + im);
@@ -380,16 +439,15 @@ __global__ __launch_bounds__(256) void k_diff_aux(DiffArgs A, const int32_t* __r
 }
 
 // a[n][f] of every path (diagnostic and parity output)
-__global__ __launch_bounds__(256) void k_diff_field(DiffArgs A, DiffField F, const int32_t* __restrict__ ids,
-                                                    const double* __restrict__ rec, int64_t n,
+__global__ __launch_bounds__(256) void k_diff_field(DiffField F, const DiffRec* __restrict__ recs, int64_t n,
                                                     double2* __restrict__ out) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n * F.Nf) return;
   const int64_t i = e / F.Nf;
   const int fi = (int)(e - i * F.Nf);
-  const DiffPathGeo g = diff_path_geo(A, F, ids + 3 * i, rec + 8 * i);
+  const DiffRec g = recs[i];
   const double f = F.freq[fi];
-  const cd a = diff_amplitude(g, F, fi, f, 1.0 / f);
+  const cd a = diff_amplitude(g, F, fi, f, 1.0 / f, 1.0 / sqrt(f));
   out[e] = make_double2(a.re, a.im);
 }
 
@@ -597,6 +655,18 @@ void run_diffract(sbr_diff_s* d, hipStream_t s) {
   SBR_HIP(hipStreamSynchronize(s));
 }
 
+namespace {
+// the per-path records of one polarisation pair (n_paths of them)
+void diff_records(sbr_diff_s* d, const DiffField& F, Buf& recs, hipStream_t s) {
+  const int64_t n = d->n_paths;
+  recs.alloc((size_t)n * sizeof(DiffRec), s);
+  ::sbr::TimedLaunch tl_("diffraction", s);
+  hipLaunchKernelGGL(k_diff_geo, dim3(nblk(n, 256)), dim3(256), 0, s, diff_args(d), F, d->ids.as<int32_t>(),
+                     d->rec.as<double>(), n, recs.as<DiffRec>());
+  SBR_LAUNCH_CHECK();
+}
+}  // namespace
+
 void run_diff_channel(sbr_diff_s* d, const double* freq, int Nf, const float* atm_db, const float* atm_deg, int ptx,
                       int prx, float2* H64, double2* H128, hipStream_t s) {
   const int64_t npair = (int64_t)d->Nr * d->Nt;
@@ -606,14 +676,13 @@ void run_diff_channel(sbr_diff_s* d, const double* freq, int Nf, const float* at
   if (np == 0 || Nf == 0) return;
   const int ntiles = (Nf + kDiffTile - 1) / kDiffTile;
   SBR_CHECK(npair * ntiles < (int64_t(1) << 31), SBR_E_UNSUPPORTED, "too many (rx, tx) pairs x frequency tiles");
-  const DiffArgs A = diff_args(d);
   const DiffField F = diff_field_args(d, freq, Nf, atm_db, atm_deg, ptx, prx);
-  Buf part;
+  Buf recs, part;
+  diff_records(d, F, recs, s);
   part.alloc((size_t)np * ntiles * 8, s);
   ::sbr::TimedLaunch tl_("diffraction", s);
-  hipLaunchKernelGGL(k_diff_channel, dim3((unsigned)(npair * ntiles)), dim3(kDiffTile * kDiffWaves), 0, s, A, F,
-                     d->seg_start.as<int32_t>(), d->ids.as<int32_t>(), d->rec.as<double>(), ntiles, H64, H128,
-                     part.as<double>());
+  hipLaunchKernelGGL(k_diff_channel, dim3((unsigned)(npair * ntiles)), dim3(64 * kDiffWaves), 0, s, F, d->Nt, d->Nr,
+                     d->seg_start.as<int32_t>(), recs.as<DiffRec>(), ntiles, H64, H128, part.as<double>());
   SBR_LAUNCH_CHECK();
   run_power_final(part.as<double>(), np, ntiles, Nf, d->power.as<double>(), s);
 }
@@ -630,10 +699,11 @@ void run_diff_field(sbr_diff_s* d, const double* freq, int Nf, const float* atm_
                     int prx, double2* out, hipStream_t s) {
   const int64_t n = d->n_paths;
   if (n == 0 || Nf == 0) return;
-  const DiffArgs A = diff_args(d);
   const DiffField F = diff_field_args(d, freq, Nf, atm_db, atm_deg, ptx, prx);
-  { ::sbr::TimedLaunch tl_("diffraction", s); hipLaunchKernelGGL(k_diff_field, dim3(nblk(n * Nf, 256)), dim3(256), 0, s, A, F, d->ids.as<int32_t>(),
-                     d->rec.as<double>(), n, out); }
+  Buf recs;
+  diff_records(d, F, recs, s);
+  ::sbr::TimedLaunch tl_("diffraction", s);
+  hipLaunchKernelGGL(k_diff_field, dim3(nblk(n * Nf, 256)), dim3(256), 0, s, F, recs.as<DiffRec>(), n, out);
   SBR_LAUNCH_CHECK();
 }
 

@@ -45,10 +45,10 @@ def _box(tx, rx, freq=(28e9,), sigma=0.0326, rough=0.0):
 
 
 def test_transition_function(S, ctx):
-    """The GPU's series (X < 5) and continued fraction (X >= 5) against the
+    """The GPU's series (X < 5), continued fraction (5 <= X < 80) and asymptotic series (X >= 80) against the
     oracle's Fresnel-integral form (itself good to ~1e-11 at X ~ 1e5)."""
     banner("utd transition")
-    X = np.concatenate([[0.0], np.logspace(-9, 5, 281), [4.999999, 5.0, 5.000001, 7.99, 8.0, 19.99, 20.0]])
+    X = np.concatenate([[0.0], np.logspace(-9, 5, 281), [4.999999, 5.0, 5.000001, 7.99, 8.0, 19.99, 20.0, 79.999999, 80.0]])
     got = S.sbr_utd_transition(ctx, X)
     want = D.transition(X)
     tol = 1e-12 * np.maximum(np.abs(want), 1e-6) + 5e-11 * (X > 1e3)
