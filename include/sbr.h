@@ -257,7 +257,8 @@ sbr_status sbr_utd_transition(sbr_context_t ctx, const double* X, int64_t n, dou
  * SBR_IN_DEVICE); tile_area > 0 in m^2; 0 <= alpha <= 32; finishes before it
  * returns; the handle keeps the scene.  Errors: INVALID_ARG (NULL, sizes,
  * non-finite points, tile_area or alpha out of range), UNSUPPORTED when
- * tiles x Nt x Nr >= 2^32 or there are 2^31 tiles or more. */
+ * tiles x Nt x Nr >= 2^32, there are 2^31 tiles or more, or a triangle
+ * would need m >= 65536 (all checked before any tile is made). */
 sbr_status sbr_scatter(sbr_context_t ctx, sbr_scene_t sc, const double* tx_xyz, int32_t Nt, const double* rx_xyz,
                        int32_t Nr, double tile_area, int32_t alpha, uint32_t flags, sbr_scat_t* out);
 /* counts: tiles, (tile, Tx, Rx) candidates, (tile, Tx) and (tile, Rx) legs

@@ -412,7 +412,25 @@ void build_tiles(sbr_scat_s* d, hipStream_t s) {
     SBR_HIP(hipMemcpyAsync(tri.data(), sc->tri64.p, (size_t)T * 72, hipMemcpyDeviceToHost, s));
     SBR_HIP(hipStreamSynchronize(s));
   }
+  // grid size m of every triangle, and the limits checked before any tile is made
+  std::vector<int64_t> grid((size_t)T);
+  double total = 0.0;
+  for (int64_t t = 0; t < T; ++t) {
+    const double* v = tri.data() + 9 * t;
+    const double e1x = v[3] - v[0], e1y = v[4] - v[1], e1z = v[5] - v[2];
+    const double e2x = v[6] - v[0], e2y = v[7] - v[1], e2z = v[8] - v[2];
+    const double nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
+    const double md = std::ceil(std::sqrt(0.5 * std::sqrt(nx * nx + ny * ny + nz * nz) / d->tile_area));
+    SBR_CHECK(md < 65536.0, SBR_E_UNSUPPORTED, "triangle %lld needs %g x %g tiles of %g m^2", (long long)t, md, md,
+              d->tile_area);
+    grid[(size_t)t] = std::max<int64_t>(1, (int64_t)md);
+    total += (double)grid[(size_t)t] * (double)grid[(size_t)t];
+  }
+  SBR_CHECK(total < 2147483648.0 && total * d->Nt * d->Nr < 4294967296.0, SBR_E_UNSUPPORTED,
+            "%.0f tiles x %d Tx x %d Rx: at most 2^31 tiles and 2^32 (tile, Tx, Rx) candidates in one call", total,
+            d->Nt, d->Nr);
   std::vector<TileDev> out;
+  out.reserve((size_t)total);
   for (int64_t t = 0; t < T; ++t) {
     const double* v = tri.data() + 9 * t;
     const double e1x = v[3] - v[0], e1y = v[4] - v[1], e1z = v[5] - v[2];
@@ -420,8 +438,7 @@ void build_tiles(sbr_scat_s* d, hipStream_t s) {
     const double nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
     const double nn = std::sqrt(nx * nx + ny * ny + nz * nz);
     const double A = 0.5 * nn;
-    const int64_t m = std::max<int64_t>(1, (int64_t)std::ceil(std::sqrt(A / d->tile_area)));
-    SBR_CHECK((int64_t)out.size() + m * m < (int64_t(1) << 31), SBR_E_UNSUPPORTED, "more than 2^31 tiles");
+    const int64_t m = grid[(size_t)t];
     const double ax = e1x / m, ay = e1y / m, az = e1z / m, bx = e2x / m, by = e2y / m, bz = e2z / m;
     auto P = [&](int64_t i, int64_t j, int c) {
       const double a = c == 0 ? ax : c == 1 ? ay : az, b = c == 0 ? bx : c == 1 ? by : bz;

@@ -202,5 +202,13 @@ def test_free_space_and_rejects(S, ctx):
             S.sbr_scatter(ctx, sb, wb.tx, wb.rx, ta, al)
     with pytest.raises(S.SbrError):
         S.sbr_scatter(ctx, sb, np.full((1, 3), np.nan), wb.rx, 1.0, 4)
+    # limits, checked before the tile table is built: a triangle of about
+    # 1.5 m^2 at 1e-12 m^2 tiles (m ~ 1.2e6), and 12 triangles at 1e-5 m^2
+    # (about 1.8 M tiles) x 64 Tx x 64 Rx >= 2^32 candidates
+    with pytest.raises(S.SbrError):
+        S.sbr_scatter(ctx, sb, wb.tx, wb.rx, 1e-12, 4)
+    many = np.concatenate([wb.tx + [0.0, 0.0, 0.01 * i] for i in range(64)])
+    with pytest.raises(S.SbrError):
+        S.sbr_scatter(ctx, sb, many, many + [0.0, -4.0, 0.0], 1e-5, 4)
     with pytest.raises(S.SbrError):
         S.sbr_scatter_lobe_norm(ctx, 33, np.array([0.5]))
