@@ -201,7 +201,7 @@ sbr_status sbr_path_field(sbr_context_t ctx, sbr_paths_t ps, const double* freq_
  * sbr_diffract: tx_xyz [Nt][3], rx_xyz [Nr][3] FP64 (host, or device with
  * SBR_IN_DEVICE); finishes before it returns; the handle keeps the scene.
  * Errors: INVALID_ARG (NULL, sizes, non-finite points), UNSUPPORTED when
- * wedges x Nt x Nr >= 2^32. */
+ * wedges x Nt x Nr >= 2^32 or 2^31 paths or more are found. */
 sbr_status sbr_diffract(sbr_context_t ctx, sbr_scene_t sc, const double* tx_xyz, int32_t Nt, const double* rx_xyz,
                         int32_t Nr, uint32_t flags, sbr_diff_t* out);
 /* counts: wedges of the scene, (wedge, Tx, Rx) candidates, candidates past the
@@ -258,7 +258,8 @@ sbr_status sbr_utd_transition(sbr_context_t ctx, const double* X, int64_t n, dou
  * returns; the handle keeps the scene.  Errors: INVALID_ARG (NULL, sizes,
  * non-finite points, tile_area or alpha out of range), UNSUPPORTED when
  * tiles x Nt x Nr >= 2^32, there are 2^31 tiles or more, or a triangle
- * would need m >= 65536 (all checked before any tile is made). */
+ * would need m >= 65536 (all checked before any tile is made), and when
+ * 2^31 paths or more are found. */
 sbr_status sbr_scatter(sbr_context_t ctx, sbr_scene_t sc, const double* tx_xyz, int32_t Nt, const double* rx_xyz,
                        int32_t Nr, double tile_area, int32_t alpha, uint32_t flags, sbr_scat_t* out);
 /* counts: tiles, (tile, Tx, Rx) candidates, (tile, Tx) and (tile, Rx) legs
