@@ -631,7 +631,7 @@ void run_diffract(sbr_diff_s* d, hipStream_t s) {
   uint32_t n2 = 0;
   SBR_HIP(hipMemcpyAsync(&n2, tot.p, 4, hipMemcpyDeviceToHost, s));
   SBR_HIP(hipStreamSynchronize(s));
-  SBR_CHECK(n2 < (1u << 31), SBR_E_UNSUPPORTED, "%u paths; at most 2^31 - 1 in one call", n2);
+  SBR_CHECK(n2 < (1u << 31) - 64u, SBR_E_UNSUPPORTED, "%u paths; fewer than 2^31 - 64 in one call", n2);
   d->n_paths = n2;
   if (n2 == 0) {
     fill_u32(d->seg_start.as<uint32_t>(), 0, npair + 1, s);
