@@ -93,7 +93,7 @@ def committed_traffic(workload):
 
 
 KERNEL_CLASSES = ["bounce", "replay_capture", "rebuild", "channel", "capacity", "keys", "sort", "scan", "order", "bvh",
-                  "stats",
+                  "stats", "diffraction", "scattering",
                   "misc", "alpha", "host:scene_build", "host:scene_inputs", "host:face_groups", "host:scene_upload",
                   "host:rx_tree", "host:receive", "host:trace_setup", "host:trace_launch"]
 
@@ -452,6 +452,79 @@ def scattering_main(args):
     print(json.dumps(out), flush=True)
 
 
+def mechanisms_main(args):
+    """Reflection to K = 4 and first-order diffraction on the massive-MIMO
+    office, the mechanism set of the paper's Table I: the headline's scene
+    build, trace, receive and channel, then sbr_diffract + sbr_diff_channel
+    adding the diffracted field to the same H, the per-link statistics over
+    both path sets (sbr_stats_all), and capacity and per-port power of the
+    combined H, every step."""
+    import numpy as np
+    import torch
+    from paper_2208_10006_amd import autotune as A
+    from paper_2208_10006_amd import sbr as S
+    from paper_2208_10006_amd import workloads as W
+
+    w = W.massive_mimo_office()
+    dev = torch.device("cuda", 0)
+    d = make_inputs(w, torch, dev)
+    ctx = S.context_for_torch(0)
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    sc0 = S.sbr_scene_build(ctx, d["tri"], d["eps"], d["sig"], d["rough"])
+    A.autotune_trace(ctx, sc0, d["tx"], w.geodesic_N, w.max_bounces, w.T, arch=arch)
+    tr0 = S.sbr_trace(ctx, sc0, d["tx"], w.geodesic_N, w.max_bounces)
+    S.sbr_synchronize(ctx)
+    A.autotune_receive(ctx, tr0, d["rx"], 0.0, w.radius_coeff, len(w.tx) * w.rays_per_element, w.max_bounces,
+                       arch=arch)
+    del tr0, sc0
+
+    def one():
+        sc = S.sbr_scene_build(ctx, d["tri"], d["eps"], d["sig"], d["rough"])
+        tr = S.sbr_trace(ctx, sc, d["tx"], w.geodesic_N, w.max_bounces)
+        ps = S.sbr_receive(ctx, tr, d["rx"], 0.0, w.radius_coeff)
+        S.sbr_channel(ctx, ps, d["freq"], d["atm"], None, S.SBR_POL_V, S.SBR_POL_V, H_c64=d["H"])
+        df = S.sbr_diffract(ctx, sc, d["tx"], d["rx"])
+        S.sbr_diff_channel(ctx, df, d["freq"], d["atm"], None, S.SBR_POL_V, S.SBR_POL_V, H_c64=d["H"])
+        d["capacity"] = S.sbr_capacity(ctx, d["H"], d["snr"])
+        S.sbr_port_power(ctx, d["H"], d["P"])
+        d["stats"] = S.sbr_stats_all(ps, df)
+        return sc, tr, ps, df
+
+    for _ in range(args.warmup):
+        h = one()
+        del h
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        h = one()
+        if i + 1 < args.steps:
+            del h
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sc, tr, ps, df = h
+    segs = S.sbr_trace_info(tr)["segments"]
+    pinfo, dinfo = S.sbr_paths_info(ps), S.sbr_diff_info(df)
+    pg_all = d["stats"][0]
+    pg_ref = S.sbr_stats(ps)[0]
+    del sc, tr, ps, df, h
+    kernels = breakdown(S, ctx, one)
+    ms = (t1 - t0) * 1e3 / args.steps
+    fin = np.isfinite(pg_all)
+    out = {"metric": "traced ray-segments/s (reflection K=4 with first-order diffraction in H and the statistics)",
+           "value": segs / (ms * 1e-3), "unit": "ray-segments/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32 traversal / f64 ray state, phase, UTD field and H", "data": "synthetic",
+           "config": {"workload": f"reflection and first-order diffraction, {describe(w)}",
+                      "segments_per_step": segs, "reflection_paths": pinfo["paths"], "diffraction_paths": dinfo["paths"],
+                      "links_with_a_path": {"reflection": int(np.isfinite(pg_ref).sum()), "both": int(fin.sum()),
+                                            "of": int(pg_all.size)},
+                      "mean_path_gain_db": {"reflection": float(np.mean(pg_ref[np.isfinite(pg_ref)])),
+                                            "both": float(np.mean(pg_all[fin]))},
+                      "capacity_bits_per_hz_snr_0_to_30_db": [round(float(v), 4) for v in d["capacity"]]},
+           "kernels": kernels}
+    print(json.dumps(out), flush=True)
+
+
 PEAK_BF16_TFLOPS = 2500.0
 
 
@@ -565,6 +638,8 @@ def main():
         return diffraction_main(args)
     if args.workload == "office_scattering":
         return scattering_main(args)
+    if args.workload == "office_reflection_diffraction":
+        return mechanisms_main(args)
     import numpy as np
     import torch
     from paper_2208_10006_amd import sbr as S

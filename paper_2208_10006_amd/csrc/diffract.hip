@@ -492,13 +492,24 @@ void scene_wedges(sbr_scene_s* sc, hipStream_t s) {
   }
   auto vert = [&](int64_t t, int i) { return V3{tri[9 * t + 3 * i], tri[9 * t + 3 * i + 1], tri[9 * t + 3 * i + 2]}; };
   // the triangles (and their local edge index) on each undirected edge,
-  // matched by exact vertex coordinates
-  std::map<std::pair<V3, V3>, std::vector<std::pair<int64_t, int>>> owners;
+  // matched by exact vertex coordinates: (edge, triangle, edge index) sorted
+  struct EdgeRef {
+    V3 a, b;
+    int64_t t;
+    int i;
+  };
+  std::vector<EdgeRef> edges;
+  edges.reserve(3 * (size_t)T);
   for (int64_t t = 0; t < T; ++t)
     for (int i = 0; i < 3; ++i) {
       const V3 a = vert(t, i), b = vert(t, (i + 1) % 3);
-      owners[a < b ? std::make_pair(a, b) : std::make_pair(b, a)].push_back({t, i});
+      edges.push_back(a < b ? EdgeRef{a, b, t, i} : EdgeRef{b, a, t, i});
     }
+  std::sort(edges.begin(), edges.end(), [](const EdgeRef& x, const EdgeRef& y) {
+    if (x.a != y.a) return x.a < y.a;
+    if (x.b != y.b) return x.b < y.b;
+    return x.t != y.t ? x.t < y.t : x.i < y.i;
+  });
   // per triangle: unit normal, plane offset and bounding box (the test of an
   // edge lying on another surface)
   std::vector<V3> tn((size_t)T);
@@ -511,12 +522,38 @@ void scene_wedges(sbr_scene_s* sc, hipStream_t s) {
       thi[3 * t + c] = std::max({tri[9 * t + c], tri[9 * t + 3 + c], tri[9 * t + 6 + c]});
     }
   }
+  // A uniform grid over the triangles' boxes, each inflated by the largest
+  // tolerance a query can use (1e-9 (1 + the largest coordinate)), so that
+  // the cell of an edge's midpoint lists every triangle the test below can
+  // accept; the test itself is unchanged.
+  double glo[3] = {INFINITY, INFINITY, INFINITY}, ghi[3] = {-INFINITY, -INFINITY, -INFINITY}, amax = 0.0;
+  for (int64_t t = 0; t < T; ++t)
+    for (int c = 0; c < 3; ++c) {
+      glo[c] = std::min(glo[c], tlo[3 * t + c]), ghi[c] = std::max(ghi[c], thi[3 * t + c]);
+      amax = std::max({amax, std::fabs(tlo[3 * t + c]), std::fabs(thi[3 * t + c])});
+    }
+  const double geps = 1e-9 * (1.0 + amax) * 1.0000001;
+  const int G = T > 0 ? (int)std::min<int64_t>(64, std::max<int64_t>(1, (int64_t)std::cbrt((double)T) * 2)) : 1;
+  double cell[3];
+  for (int c = 0; c < 3; ++c) cell[c] = T > 0 && ghi[c] > glo[c] ? (ghi[c] - glo[c]) / G : 1.0;
+  auto cell_of = [&](double v, int c) {
+    const double f = (v - glo[c]) / cell[c];
+    return f <= 0.0 ? 0 : f >= G - 1 ? G - 1 : (int)f;
+  };
+  std::vector<std::vector<int32_t>> grid_tris((size_t)G * G * G);
+  for (int64_t t = 0; t < T; ++t) {
+    int lo[3], hi[3];
+    for (int c = 0; c < 3; ++c) lo[c] = cell_of(tlo[3 * t + c] - geps, c), hi[c] = cell_of(thi[3 * t + c] + geps, c);
+    for (int x = lo[0]; x <= hi[0]; ++x)
+      for (int y = lo[1]; y <= hi[1]; ++y)
+        for (int z = lo[2]; z <= hi[2]; ++z) grid_tris[((size_t)x * G + y) * G + z].push_back((int32_t)t);
+  }
   auto covered = [&](const V3& a, const V3& b, int ga, int gb) {
     const double eps =
         1e-9 * (1.0 + std::max({std::fabs(a[0]), std::fabs(a[1]), std::fabs(a[2]), std::fabs(b[0]), std::fabs(b[1]),
                                 std::fabs(b[2])}));
     const V3 m{0.5 * (a[0] + b[0]), 0.5 * (a[1] + b[1]), 0.5 * (a[2] + b[2])};
-    for (int64_t t = 0; t < T; ++t) {
+    for (const int32_t t : grid_tris[((size_t)cell_of(m[0], 0) * G + cell_of(m[1], 1)) * G + cell_of(m[2], 2)]) {
       const int g = sc->h_group[t];
       if (g == ga || g == gb) continue;
       bool box = true;
@@ -533,18 +570,20 @@ void scene_wedges(sbr_scene_s* sc, hipStream_t s) {
     return false;
   };
   std::vector<std::pair<std::pair<int64_t, int>, WedgeDev>> out;
-  for (auto& kv : owners) {
-    auto& v = kv.second;
-    if (v.size() != 2) continue;
-    std::sort(v.begin(), v.end());
-    const int64_t ta = v[0].first, tb = v[1].first;
-    const int ia = v[0].second, ib = v[1].second;
+  for (size_t e0 = 0; e0 < edges.size();) {
+    size_t e1 = e0 + 1;
+    while (e1 < edges.size() && edges[e1].a == edges[e0].a && edges[e1].b == edges[e0].b) ++e1;
+    const size_t first = e0, count = e1 - e0;
+    e0 = e1;
+    if (count != 2) continue;
+    const int64_t ta = edges[first].t, tb = edges[first + 1].t;
+    const int ia = edges[first].i, ib = edges[first + 1].i;
     if (sc->h_group[ta] == sc->h_group[tb]) continue;
     const V3 na = vunit(vcross(vsub(vert(ta, 1), vert(ta, 0)), vsub(vert(ta, 2), vert(ta, 0))));
     const V3 nb = vunit(vcross(vsub(vert(tb, 1), vert(tb, 0)), vsub(vert(tb, 2), vert(tb, 0))));
     const V3 cr = vcross(na, nb);
     if (std::sqrt(vdot(cr, cr)) < 1e-9) continue;
-    const V3 a = kv.first.first, b = kv.first.second;
+    const V3 a = edges[first].a, b = edges[first].b;
     const V3 ab = vsub(b, a);
     const double len = std::sqrt(vdot(ab, ab));
     const V3 e = vscale(ab, 1.0 / len);
