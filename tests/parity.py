@@ -1,6 +1,6 @@
 """Comparison of the HIP path against the CPU oracle (helpers for the GPU tests).
 
-Agreement rules (see the tolerance section of the design doc):
+Agreement rules (readings R21 and R22: ambiguity flags and bounded excusals):
 * hit sequences: identical up to the first bounce the oracle flags as
   ambiguous (within 1e-5 of a triangle edge, a near tie, grazing);
 * path keys: equal sets, except keys whose every capture is ambiguous on the
