@@ -26,9 +26,12 @@
 //    A = sqrt(s' / (s (s + s'))).
 //
 // Pipeline: a wedge table built on the host once per scene (exact vertex
-// matching) -> the sector and edge tests per (Rx, Tx, wedge) candidate ->
+// matching) -> the sector and edge tests per (wedge, Rx, Tx) candidate ->
 // ordered compaction -> both legs against the BVH with exact FP64 triangle
-// tests -> ordered compaction -> records and a CSR per (Rx, Tx) pair.  The
+// tests -> ordered compaction -> a stable sort of the paths by (Rx, Tx) pair
+// -> records and a CSR per pair.  Candidates are numbered wedge-major so that
+// the lanes of a wave test legs from neighbouring Tx elements to nearly the
+// same point of one edge, which traverse the BVH together.  The
 // field kernel sums each pair's paths per frequency in a fixed order and adds
 // them to H.
 #include <algorithm>
@@ -79,12 +82,13 @@ __device__ inline void edge_coords(const WedgeDev& w, d3 P, double& z, double& r
 
 // candidate c = ((q Nt + p) W + wedge): its indices and, when it passes the
 // sector and edge tests, the diffraction point and the two angles
+// candidate c = ((wedge Nr + q) Nt + p)
 __device__ inline bool diff_geometry(const DiffArgs& A, int64_t c, int& p, int& q, int& wi, d3& Q, double& ft,
                                      double& fr) {
-  wi = (int)(c % A.W);
-  const int64_t pr = c / A.W;
-  q = (int)(pr / A.Nt);
-  p = (int)(pr - (int64_t)q * A.Nt);
+  p = (int)(c % A.Nt);
+  const int64_t wq = c / A.Nt;
+  q = (int)(wq % A.Nr);
+  wi = (int)(wq / A.Nr);
   const WedgeDev w = A.wd[wi];
   const d3 T = ld3(A.tx + 3 * p), R = ld3(A.rx + 3 * q);
   double zt, rt, zr, rr;
@@ -140,7 +144,20 @@ __global__ __launch_bounds__(128) void k_diff_legs(DiffArgs A, DiffScene S, cons
 }
 
 // ids[i] = (tx, rx, wedge), rec[i] = (Q xyz, s', s, beta0, phi', phi); paths per (Rx, Tx) pair counted
-__global__ __launch_bounds__(256) void k_diff_records(DiffArgs A, const int64_t* __restrict__ path, int64_t n,
+// the (Rx, Tx) pair of each path, for the sort into pair order
+__global__ __launch_bounds__(256) void k_diff_pair_keys(DiffArgs A, const int64_t* __restrict__ path, int64_t n,
+                                                        uint64_t* __restrict__ key, uint32_t* __restrict__ val) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t c = path[i];
+  const int64_t wq = c / A.Nt;
+  key[i] = (uint64_t)(wq % A.Nr) * (uint64_t)A.Nt + (uint64_t)(c - wq * A.Nt);
+  val[i] = (uint32_t)i;
+}
+
+// record i is path order[i]
+__global__ __launch_bounds__(256) void k_diff_records(DiffArgs A, const int64_t* __restrict__ path,
+                                                      const uint32_t* __restrict__ order, int64_t n,
                                                       int32_t* __restrict__ ids, double* __restrict__ rec,
                                                       uint32_t* __restrict__ pair_count) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -148,7 +165,7 @@ __global__ __launch_bounds__(256) void k_diff_records(DiffArgs A, const int64_t*
   int p, q, wi;
   d3 Q;
   double ft, fr;
-  diff_geometry(A, path[i], p, q, wi, Q, ft, fr);
+  diff_geometry(A, path[order[i]], p, q, wi, Q, ft, fr);
   const WedgeDev w = A.wd[wi];
   const d3 T = ld3(A.tx + 3 * p), R = ld3(A.rx + 3 * q);
   const d3 dt = Q - T, dr = R - Q;
@@ -681,12 +698,25 @@ void run_diffract(sbr_diff_s* d, hipStream_t s) {
   { ::sbr::TimedLaunch tl_("diffraction", s); hipLaunchKernelGGL(k_diff_compact, dim3(nblk(n1, 256)), dim3(256), 0, s, flag2.as<uint32_t>(), pos2.as<uint32_t>(),
                      (int64_t)n1, cand.as<int64_t>(), paths.as<int64_t>()); }
   SBR_LAUNCH_CHECK();
+  // the paths in (Rx, Tx) pair order, wedges ascending within a pair (a
+  // stable sort of the wedge-major order by pair)
+  Buf keys, vals, keys2, order, stemp;
+  keys.alloc((size_t)n2 * 8, s), vals.alloc((size_t)n2 * 4, s);
+  keys2.alloc((size_t)n2 * 8, s), order.alloc((size_t)n2 * 4, s);
+  stemp.alloc(radix_sort_temp_bytes(n2), s);
+  { ::sbr::TimedLaunch tl_("diffraction", s); hipLaunchKernelGGL(k_diff_pair_keys, dim3(nblk(n2, 256)), dim3(256), 0, s, A, paths.as<int64_t>(), (int64_t)n2,
+                     keys.as<uint64_t>(), vals.as<uint32_t>()); }
+  SBR_LAUNCH_CHECK();
+  int pair_bits = 0;
+  while ((int64_t(1) << pair_bits) < npair) ++pair_bits;
+  radix_sort_pairs(keys.as<uint64_t>(), vals.as<uint32_t>(), keys2.as<uint64_t>(), order.as<uint32_t>(), (int64_t)n2, 0,
+                   pair_bits, stemp.p, s);
   d->ids.alloc((size_t)n2 * 12, s);
   d->rec.alloc((size_t)n2 * 64, s);
   cnt.alloc((size_t)npair * 4, s);
   fill_u32(cnt.as<uint32_t>(), 0, npair, s);
-  { ::sbr::TimedLaunch tl_("diffraction", s); hipLaunchKernelGGL(k_diff_records, dim3(nblk(n2, 256)), dim3(256), 0, s, A, paths.as<int64_t>(), (int64_t)n2,
-                     d->ids.as<int32_t>(), d->rec.as<double>(), cnt.as<uint32_t>()); }
+  { ::sbr::TimedLaunch tl_("diffraction", s); hipLaunchKernelGGL(k_diff_records, dim3(nblk(n2, 256)), dim3(256), 0, s, A, paths.as<int64_t>(), order.as<uint32_t>(),
+                     (int64_t)n2, d->ids.as<int32_t>(), d->rec.as<double>(), cnt.as<uint32_t>()); }
   SBR_LAUNCH_CHECK();
   Buf temp2;
   temp2.alloc(scan_temp_bytes(npair), s);
