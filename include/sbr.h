@@ -136,9 +136,13 @@ sbr_status sbr_trace_batch(sbr_context_t ctx, int32_t n, const sbr_scene_t* scen
 sbr_status sbr_trace_latency(sbr_trace_t tr, double* ms);
 /* rays = Nt (10N^2+2); segments = closest-hit queries actually traced. */
 sbr_status sbr_trace_info(sbr_trace_t tr, int64_t* rays, int64_t* segments);
-/* Per-ray hit triangles [rays][K+1] (original triangle index; -1 miss,
- * -2 not traced because the ray ended earlier).  Host or device output. */
-sbr_status sbr_trace_hits(sbr_trace_t tr, int32_t* seq, uint32_t flags);
+/* Per-ray hit triangles seq [rays][K+1] (original triangle index; -1 miss,
+ * -2 not traced because the ray ended earlier) and, when uv is not NULL, the
+ * barycentric coordinates uv [rays][K+1][2] of every hit on its triangle
+ * (P = (1 - u - v) v0 + u v1 + v v2, the ray's chain replayed in FP64 on the
+ * hit planes; NaN where seq < 0).  Rays by global id p R + r.  Either output
+ * may be NULL, not both.  Host or device outputs (diagnostic / parity). */
+sbr_status sbr_trace_hits(sbr_trace_t tr, int32_t* seq, float* uv, uint32_t flags);
 
 /* Reception (Sec. II-A-3) and path extraction.  A segment with origin o,
  * unit direction d, end t_end and unfolded length L before it is captured by

@@ -190,6 +190,46 @@ __global__ __launch_bounds__(1024) void k_replay_capture(const ReplayParams P) {
   }
 }
 
+// ---------------------------------------------------------------- hit barycentrics
+// (u, v) of every hit on its triangle, P = (1 - u - v) v0 + u v1 + v v2
+// (a diagnostic of the trace): each ray's chain replayed in FP64 as the
+// capture replays it (the hit triangle's plane, specular reflection), NaN
+// from the first segment without a hit; written by global ray id.
+__global__ __launch_bounds__(256) void k_hits_uv(const GeoTables G, int N, int K, int64_t NR, int64_t T, RayOrder ord,
+                                                 const double* __restrict__ tx, const int32_t* __restrict__ seq,
+                                                 const double4* __restrict__ tplane,
+                                                 const double* __restrict__ tri64, float* __restrict__ uv) {
+  const int64_t rid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (rid >= NR) return;
+  int p;
+  int64_t r;
+  ray_of_pos(ord, rid, p, r);
+  const int64_t g = rid_of_pos(ord, rid);
+  d3 o = ld3(tx + 3 * p);
+  d3 d = geo_dir(G, N, r);
+  bool ended = false;
+  for (int k = 0; k <= K; ++k) {
+    float u = NAN, v = NAN;
+    const int32_t tri = ended ? -1 : seq[(int64_t)k * NR + rid];
+    if (tri >= 0 && tri < T) {
+      const double4 pl = tplane[tri];
+      const d3 P = o + d * advance_t(pl, o, d);
+      const double* t = tri64 + 9 * (int64_t)tri;
+      const d3 v0 = ld3(t), e1 = ld3(t + 3) - v0, e2 = ld3(t + 6) - v0, w = P - v0;
+      const double d00 = dot(e1, e1), d01 = dot(e1, e2), d11 = dot(e2, e2), d20 = dot(w, e1), d21 = dot(w, e2);
+      const double den = d00 * d11 - d01 * d01;
+      u = (float)((d11 * d20 - d01 * d21) / den);
+      v = (float)((d00 * d21 - d01 * d20) / den);
+      o = P;
+      d = reflect(d, pl);
+    } else {
+      ended = true;
+    }
+    uv[2 * (g * (K + 1) + k)] = u;
+    uv[2 * (g * (K + 1) + k) + 1] = v;
+  }
+}
+
 // ---------------------------------------------------------------- keys
 __device__ inline uint64_t mix64(uint64_t h, uint64_t v) {
   h ^= v + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
@@ -879,6 +919,16 @@ void run_receive(sbr_paths_s* ps, const double* hrx, hipStream_t s) {
   SBR_LAUNCH_CHECK();
   // no final synchronisation: the path arrays are written in stream order and
   // the temporaries are released in stream order
+}
+
+void run_hits_uv(sbr_trace_s* tr, float* uv, hipStream_t s) {
+  const int64_t NR = tr->NR;
+  if (NR == 0) return;
+  ::sbr::TimedLaunch tl_("misc", s);
+  hipLaunchKernelGGL(k_hits_uv, dim3(nblk(NR, 256)), dim3(256), 0, s, geo_tables(), tr->N, tr->K, NR, tr->scene->T,
+                     RayOrder{tr->R, (int32_t)tr->Nt, (int32_t)tr->emin}, tr->tx.as<double>(), tr->seq.as<int32_t>(),
+                     tr->scene->tplane.as<double4>(), tr->scene->tri64.as<double>(), uv);
+  SBR_LAUNCH_CHECK();
 }
 
 }  // namespace sbr

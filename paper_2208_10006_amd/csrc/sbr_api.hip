@@ -1126,26 +1126,30 @@ sbr_status sbr_trace_info(sbr_trace_t t, int64_t* rays, int64_t* segments) {
   });
 }
 
-sbr_status sbr_trace_hits(sbr_trace_t t, int32_t* seq, uint32_t flags) {
+sbr_status sbr_trace_hits(sbr_trace_t t, int32_t* seq, float* uv, uint32_t flags) {
   return guard([&] {
     auto* tr = check_handle<sbr_trace_s>(t, kTrace, "trace");
-    SBR_CHECK(seq != nullptr, SBR_E_INVALID_ARG, "seq is NULL");
+    SBR_CHECK(seq != nullptr || uv != nullptr, SBR_E_INVALID_ARG, "seq and uv are NULL");
     set_device(tr->ctx);
     hipStream_t s = tr->ctx->stream;
     const size_t n = (size_t)tr->NR * (tr->K + 1);
-    Buf tmp;
-    int32_t* dst = seq;
-    if (!(flags & SBR_OUT_DEVICE)) {
-      tmp.alloc(n * 4, s);
-      dst = tmp.as<int32_t>();
+    const bool dev = flags & SBR_OUT_DEVICE;
+    Buf tmp, tmp_uv;
+    if (seq) {
+      int32_t* dst = seq;
+      if (!dev) tmp.alloc(n * 4, s), dst = tmp.as<int32_t>();
+      { ::sbr::TimedLaunch tl_("misc", s); hipLaunchKernelGGL(k_hits_out, dim3(nblk(tr->NR, 256)), dim3(256), 0, s, tr->seq.as<int32_t>(), tr->NR, tr->K,
+                         RayOrder{tr->R, (int32_t)tr->Nt, (int32_t)tr->emin}, dst); }
+      SBR_LAUNCH_CHECK();
+      if (!dev) SBR_HIP(hipMemcpyAsync(seq, dst, n * 4, hipMemcpyDeviceToHost, s));
     }
-    { ::sbr::TimedLaunch tl_("misc", s); hipLaunchKernelGGL(k_hits_out, dim3(nblk(tr->NR, 256)), dim3(256), 0, s, tr->seq.as<int32_t>(), tr->NR, tr->K,
-                       RayOrder{tr->R, (int32_t)tr->Nt, (int32_t)tr->emin}, dst); }
-    SBR_LAUNCH_CHECK();
-    if (!(flags & SBR_OUT_DEVICE)) {
-      SBR_HIP(hipMemcpyAsync(seq, dst, n * 4, hipMemcpyDeviceToHost, s));
-      SBR_HIP(hipStreamSynchronize(s));
+    if (uv) {
+      float* dst = uv;
+      if (!dev) tmp_uv.alloc(n * 8, s), dst = tmp_uv.as<float>();
+      run_hits_uv(tr, dst, s);
+      if (!dev) SBR_HIP(hipMemcpyAsync(uv, dst, n * 8, hipMemcpyDeviceToHost, s));
     }
+    if (!dev) SBR_HIP(hipStreamSynchronize(s));
   });
 }
 

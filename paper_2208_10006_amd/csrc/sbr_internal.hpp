@@ -463,6 +463,8 @@ void run_diff_channel(sbr_diff_s* d, const double* freq, int Nf, const float* at
 void run_diff_field(sbr_diff_s* d, const double* freq, int Nf, const float* atm_db, const float* atm_deg, int ptx,
                     int prx, double2* out, hipStream_t s);
 void run_utd_transition(const double* X, int64_t n, double2* out, hipStream_t s);
+// [global ray id][K+1][2] barycentric (u, v) of every hit, NaN after the chain ends (receive.hip)
+void run_hits_uv(sbr_trace_s* tr, float* uv, hipStream_t s);
 // per path: delay (s) and angles [n][4] (degrees) for the per-link statistics
 void run_diff_aux(sbr_diff_s* d, double* delay, float* ang, hipStream_t s);
 

@@ -62,7 +62,7 @@ def _load():
         "sbr_scene_groups": [P, P, P],
         "sbr_trace": [P, P, P, I32, I32, I32, U32, P],
         "sbr_trace_info": [P, P, P],
-        "sbr_trace_hits": [P, P, U32],
+        "sbr_trace_hits": [P, P, P, U32],
         "sbr_receive": [P, P, P, I32, D, D, U32, P],
         "sbr_paths_info": [P, P, P, P],
         "sbr_paths_count": [P, P],
@@ -292,12 +292,22 @@ def sbr_trace_info(tr: Trace):
     return {"rays": r.value, "segments": s.value}
 
 
-def sbr_trace_hits(tr: Trace, out=None):
+def sbr_trace_hits(tr: Trace, out=None, uv=None):
+    """Hit triangles [rays, K+1] (global ray ids); with uv (True or an array
+    [rays, K+1, 2] float32) also the barycentric (u, v) of every hit, NaN
+    where the chain has ended: returns (seq, uv) then."""
     if out is None:
         out = np.zeros((tr.Nt * tr.R, tr.K + 1), np.int32)
     o = _Arr(out, np.int32)
-    _call("sbr_trace_hits", tr.h, o.ptr, _flags([o], SBR_OUT_DEVICE))
-    return out
+    arrs = [o]
+    u = None
+    if uv is not None and uv is not False:
+        if uv is True:
+            uv = np.zeros((tr.Nt * tr.R, tr.K + 1, 2), np.float32)
+        u = _Arr(uv, np.float32)
+        arrs.append(u)
+    _call("sbr_trace_hits", tr.h, o.ptr, u.ptr if u is not None else None, _flags(arrs, SBR_OUT_DEVICE))
+    return out if u is None else (out, uv)
 
 
 def sbr_receive(ctx: Context, tr: Trace, rx, alpha_rad: float = 0.0, radius_coeff: float = 1.0) -> Paths:

@@ -662,6 +662,54 @@ def test_trace_graph_replays(S, ctx):
         S.sbr_context_set_tuning(ctx, "trace_graph", 0)
 
 
+
+@pytest.mark.parametrize("which", ["tiny_room", "random"])
+def test_hit_barycentrics(S, ctx, which):
+    """sbr_trace_hits' barycentric (u, v) of every hit: inside the hit
+    triangle, NaN after the chain ends, and equal to the barycentrics of the
+    hit point rebuilt from the oracle's FP64 hit distances (launch direction,
+    then specular reflection on each hit triangle's plane), computed here by
+    area ratios."""
+    banner("hit barycentrics", which)
+    w = W.tiny_room() if which == "tiny_room" else W.random_box_scene(5, n_boxes=12, n_rx=4, N=24, K=3)
+    sc = S.sbr_scene_build(ctx, w.tri, w.eps_r, w.sigma, w.rough)
+    tr = S.sbr_trace(ctx, sc, w.tx, w.geodesic_N, w.max_bounces)
+    seq, uv = S.sbr_trace_hits(tr, uv=True)
+    hit = seq >= 0
+    assert np.all(np.isnan(uv[~hit])) and not np.any(np.isnan(uv[hit]))
+    u, v = uv[..., 0][hit], uv[..., 1][hit]
+    assert (u >= -1e-5).all() and (v >= -1e-5).all() and (u + v <= 1 + 1e-5).all()
+    ora = O.sbr(w)
+    R = 10 * w.geodesic_N ** 2 + 2
+    ok = (ora.seq == seq).all(axis=1) & ~(ora.amb != 0).any(axis=1)
+    ids = np.nonzero(ok)[0]
+    assert len(ids) > 0.9 * len(seq)
+    tri = np.asarray(w.tri, np.float64)
+    o = np.asarray(w.tx, np.float64)[ids // R]
+    d = O.geodesic(w.geodesic_N)[ids % R]
+    alive = np.ones(len(ids), bool)
+    n_cmp = 0
+    for k in range(w.max_bounces + 1):
+        t_id = seq[ids, k]
+        alive &= t_id >= 0
+        if not alive.any():
+            break
+        a = np.nonzero(alive)[0]
+        P = o[a] + ora.t[ids[a], k][:, None] * d[a]
+        v0, v1, v2 = tri[t_id[a], 0], tri[t_id[a], 1], tri[t_id[a], 2]
+        e1, e2, wv = v1 - v0, v2 - v0, P - v0
+        n = np.cross(e1, e2)
+        nn = np.einsum("ij,ij->i", n, n)
+        uu = np.einsum("ij,ij->i", np.cross(wv, e2), n) / nn
+        vv = np.einsum("ij,ij->i", np.cross(e1, wv), n) / nn
+        err = np.maximum(np.abs(uv[ids[a], k, 0] - uu), np.abs(uv[ids[a], k, 1] - vv))
+        assert err.max() < 1e-6, (k, float(err.max()))
+        n_cmp += len(a)
+        nu = n / np.sqrt(nn)[:, None]
+        o[a] = P
+        d[a] = d[a] - 2.0 * np.einsum("ij,ij->i", d[a], nu)[:, None] * nu
+    assert n_cmp > len(ids)
+
 @pytest.mark.parametrize("scene", ["boxes", "urban"])
 def test_leaf_share_keeps_hits(S, ctx, scene):
     """Queued leaf tests only let a lane visit nodes an earlier test could have
