@@ -149,12 +149,19 @@ def path_records(w, paths):
     return out
 
 
-def scattering_field(w, paths, alpha, freq=None, atm_db=None, atm_deg=None, pol_tx=0, pol_rx=0):
-    """a[path][f]: the received scattered field of every path (complex)."""
+def scattering_field(w, paths, alpha, freq=None, atm_db=None, atm_deg=None, pol_tx=0, pol_rx=0,
+                     with_scale=False):
+    """a[path][f]: the received scattered field of every path (complex).
+    with_scale: also |amp| (|e_s (s . e_rx)| + |e_p (p_out . e_rx)|), the
+    field's two terms with the Fresnel coefficients at their bound 1: the
+    rounding scale of a value in which the TE and TM terms nearly cancel, or
+    whose R_TM is a near-cancelling quotient (incidence near the Brewster
+    angle, where R_TM is far below its own rounding error in a short format)."""
     tri = np.asarray(w.tri, np.float64)
     freq = np.asarray(w.freq if freq is None else freq, np.float64)
     eps, sig, rough = (np.asarray(x, np.float64) for x in (w.eps_r, w.sigma, w.rough))
     out = np.zeros((len(paths), len(freq)), np.complex128)
+    scale = np.zeros((len(paths), len(freq)))
     for i, d in enumerate(paths):
         Tx, R = np.asarray(w.tx[d.p], np.float64), np.asarray(w.rx[d.q], np.float64)
         v0, v1, v2 = tri[d.tri]
@@ -197,4 +204,5 @@ def scattering_field(w, paths, alpha, freq=None, atm_db=None, atm_deg=None, pol_
             if atm_deg is not None:
                 phs += math.pi * float(atm_deg[fi]) * length / 180.0
             out[i, fi] = amp * np.dot(Es, erx) * np.exp(-1j * phs)
-    return out
+            scale[i, fi] = amp * (abs(es * np.dot(s, erx)) + abs(ep * np.dot(p_out, erx)))
+    return (out, scale) if with_scale else out

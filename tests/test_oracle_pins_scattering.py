@@ -116,3 +116,39 @@ def test_lobe_peaks_in_the_specular_direction_and_same_side_rule():
     # Rx behind the wall: no scattering path
     w = W.Workload("wall", tri, e, s, r, tx[None], np.array([[-3.0, 2.0, 1.0]]), f, geodesic_N=8, max_bounces=1)
     assert SC.scattering_paths(w, 0.25, tl=(np.array([0]), C0_[None], np.array([0.25]))) == []
+
+
+def test_field_scale_is_the_terms_at_unit_fresnel_coefficients():
+    """with_scale: with Tx, the tile and Rx at one height on a vertical wall
+    the plane of incidence is horizontal, so a theta-polarised wave is pure
+    TE and a phi-polarised one pure TM: one term, |a| = scale |R_TE| or
+    scale |R_TM| (eq. (6)-(7)).  On a random scene |a| <= scale (triangle
+    inequality and |R| <= 1), strictly where both terms are present."""
+    tri, e, s, r = _wall()
+    f = np.array([28e9, 140e9])
+    w0 = W.Workload("wall", tri, e, s, r, np.array([[4.0, 1.0, 2.0]]), np.array([[6.0, 3.0, 1.0]]), f,
+                    geodesic_N=8, max_bounces=1)
+    tt, cc, aa = SC.tiles(w0, 400.0)
+    j = int(np.argmin(np.linalg.norm(cc - np.array([0.0, 2.0, 1.5]), axis=1)))
+    C = cc[j]
+    tx = np.array([4.0, 1.0, C[2]])
+    rx = np.array([5.0, 6.0, C[2]])
+    w = W.Workload("wall", tri, e, s, r, tx[None], rx[None], f, geodesic_N=8, max_bounces=1)
+    ps = [p for p in SC.scattering_paths(w, 400.0, tl=(tt, cc, aa)) if p.tile == j]
+    assert len(ps) == 1
+    d = ps[0]
+    ki = (d.C - tx) / d.ri
+    cs = abs(ki[0])  # the wall's normal is the x axis
+    for pol in (0, 1):
+        a, m = SC.scattering_field(w, ps, 4, pol_tx=pol, pol_rx=pol, with_scale=True)
+        assert np.all(np.abs(a) > 0)
+        R = np.array([abs(O.fresnel(float(np.float32(e[0])), float(np.float32(s[0])), fr, cs)[pol]) for fr in f])
+        assert np.allclose(np.abs(a), m * R, rtol=1e-12, atol=0), (pol, np.abs(a), m, R)
+    wr = W.random_box_scene(5, n_boxes=6, n_rx=3, freq=(28e9,))
+    wr.rough = np.full(len(wr.tri), 0.15e-3)
+    ps = SC.scattering_paths(wr, 4.0)
+    assert len(ps) > 50
+    for prx in (0, 1):
+        a, m = SC.scattering_field(wr, ps, 3, pol_tx=0, pol_rx=prx, with_scale=True)
+        assert np.all(np.abs(a) <= m * (1 + 1e-12))
+        assert np.any(np.abs(a) < 0.9 * m)
