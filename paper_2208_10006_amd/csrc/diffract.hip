@@ -248,7 +248,7 @@ __device__ inline void face_reflection(const FaceRec& m, double f, double inv_f,
   const cd ecc = cscale(ec, cs);
   const cd d1{cs + root.re, root.im}, d2 = cadd(ecc, root);
   const double n1 = d1.re * d1.re + d1.im * d1.im, n2 = d2.re * d2.re + d2.im * d2.im;
-  const double inv = 1.0 / (n1 * n2);
+  const double inv = rcp64(n1 * n2);
   double i1 = inv * n2, i2 = inv * n1;
   if (m.gc != 0.0) {
     const double g = m.gc * f;

@@ -31,25 +31,61 @@ __device__ inline cd cadd(cd a, cd b) { return cd{a.re + b.re, a.im + b.im}; }
 __device__ inline cd csub(cd a, cd b) { return cd{a.re - b.re, a.im - b.im}; }
 __device__ inline cd cmul(cd a, cd b) { return cd{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
 __device__ inline cd cscale(cd a, double s) { return cd{a.re * s, a.im * s}; }
-// a / b with one division: conj(b) a / |b|^2.  The Fresnel terms are of
-// moderate size (|eps_c| below about 1e8 even for metals at 1 GHz), so |b|^2
-// neither overflows nor underflows, and the result is within a few ulps of
-// the exact quotient.
+// The per-(path, subcarrier) field kernels spend much of their time in a
+// complex square root, a reciprocal and a square root per subcarrier.  Their
+// arguments stay in ranges where the scaling and special-case handling of
+// the general-purpose routines is not needed (the Fresnel terms are of
+// moderate size: |eps_c| below about 1e8 even for metals at 1 GHz, so no
+// square of them overflows or underflows), so these take the hardware
+// estimates and refine them, to within about one unit in the last place:
+//   * rcp64: the reciprocal estimate (relative error about 2^-23) and two
+//     Newton steps;
+//   * sqrt_hrsq: sqrt(x) and 1 / (2 sqrt(x)) together, from Goldschmidt's
+//     iteration on the reciprocal square root estimate (twice) and one
+//     Newton correction of the square root;
+//   * csqrt_mod: the principal square root through t = (|z| + |Re z|) / 2,
+//     sqrt(t) and Im z / (2 sqrt(t)) from one sqrt_hrsq (no division).
+__device__ inline double rcp64(double x) {  // finite x != 0, 1 / x normal
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+__device__ inline void sqrt_hrsq(double x, double& s, double& h) {  // normal x > 0 (0 gives NaN)
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, hh = 0.5 * y;
+  double r = fma(-g, hh, 0.5);
+  g = fma(g, r, g);
+  hh = fma(hh, r, hh);
+  r = fma(-g, hh, 0.5);
+  g = fma(g, r, g);
+  hh = fma(hh, r, hh);
+  const double d = fma(-g, g, x);
+  s = fma(d, hh, g);
+  h = hh;
+}
+__device__ inline double sqrt_nonneg(double x) {  // x >= 0
+  double s, h;
+  sqrt_hrsq(x, s, h);
+  return x > 0.0 ? s : 0.0;
+}
+// a / b = conj(b) a / |b|^2
 __device__ inline cd cdiv_mod(cd a, cd b) {
-  const double inv = 1.0 / (b.re * b.re + b.im * b.im);
+  const double inv = rcp64(b.re * b.re + b.im * b.im);
   return cd{(a.re * b.re + a.im * b.im) * inv, (a.im * b.re - a.re * b.im) * inv};
 }
-// principal square root, |z| by a plain square root (moderate sizes as above)
+// principal square root (0 for z = 0); on the negative real axis the sign of
+// Im z, -0 included, picks the branch
 __device__ inline cd csqrt_mod(cd z) {
-  const double m = sqrt(z.re * z.re + z.im * z.im);
-  if (m == 0.0) return cd{0.0, 0.0};
-  if (z.re >= 0.0) {
-    const double r = sqrt(0.5 * (m + z.re));
-    return cd{r, z.im / (2.0 * r)};
-  }
-  double i = sqrt(0.5 * (m - z.re));
-  if (z.im < 0.0 || (z.im == 0.0 && signbit(z.im))) i = -i;
-  return cd{z.im / (2.0 * i), i};
+  double m, hm;
+  sqrt_hrsq(fma(z.re, z.re, z.im * z.im), m, hm);
+  const double t = 0.5 * (m + fabs(z.re));
+  double s, h;
+  sqrt_hrsq(t, s, h);
+  if (!(t > 0.0)) s = h = 0.0;
+  const double w = z.im * h;  // Im z / (2 sqrt(t))
+  return z.re >= 0.0 ? cd{s, w} : cd{fabs(w), copysign(s, z.im)};
 }
 
 

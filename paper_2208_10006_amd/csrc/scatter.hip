@@ -242,7 +242,7 @@ __device__ inline cd scat_amplitude(const ScatRec& g, const ScatField& F, int fi
   const cd ecc = cscale(ec, cs);
   const cd d1{cs + root.re, root.im}, d2 = cadd(ecc, root);
   const double n1 = d1.re * d1.re + d1.im * d1.im, n2 = d2.re * d2.re + d2.im * d2.im;
-  const double inv = 1.0 / (n1 * n2);
+  const double inv = rcp64(n1 * n2);
   const double i1 = inv * n2, i2 = inv * n1;
   const cd a1{cs - root.re, -root.im}, a2 = csub(ecc, root);
   const cd te{(a1.re * d1.re + a1.im * d1.im) * i1, (a1.im * d1.re - a1.re * d1.im) * i1};
@@ -250,7 +250,7 @@ __device__ inline cd scat_amplitude(const ScatRec& g, const ScatField& F, int fi
   const double gg = g.gc * f;
   const double rho2 = exp(-gg * gg);  // rho^2, eq. (8) squared
   const cd pol = cadd(cscale(te, g.wa), cscale(tm, g.wb));
-  double amp = g.base * kC0 * inv_f * sqrt(fmax(0.0, 1.0 - rho2));
+  double amp = g.base * kC0 * inv_f * sqrt_nonneg(1.0 - rho2);
   if (F.atm_db) amp *= exp10(-(double)F.atm_db[fi] * g.len * (1.0 / 20.0));
   const double cyc = f * g.len_c;
   double ph = 2.0 * (cyc - floor(cyc));
