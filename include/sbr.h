@@ -400,6 +400,11 @@ sbr_status sbr_trace_work(sbr_trace_t tr, int64_t* node_visits, int64_t* tri_tes
  *                          element-minor (neighbouring lanes follow one launch
  *                          direction from neighbouring elements); 0: element-major.
  *                          Results are the same either way
+ *   "trace_packet"         1: the closest-hit search of a (single-scene) trace walks
+ *                          the tree once per wave, entering a node when any of the
+ *                          wave's rays enters it; 0 (default): every ray walks it on
+ *                          its own.  The hits are the same either way; traces that
+ *                          count work and batched traces always walk per ray
  *   "receive_event_capacity"  first size of the capture-event buffer of a receive
  *                          (>= 0; 0, the default: max(2^20, rays / 8)); a receive
  *                          that overflows it grows it and replays again

@@ -3,8 +3,10 @@
 Trace: the persistent bounce grid (resident blocks per CU), the number of
 rays a wave takes from its XCD queue per atomic, direct launches versus the
 cached hipGraph bounce loop, the share of a wave's lanes that must hold a
-leaf before the wave tests its queued leaves, and, for arrays of Tx
-elements, the ray order (element-minor or element-major).  Receive: the
+leaf before the wave tests its queued leaves, whether a wave walks the tree
+as one (then again over the grid and the chunk, which its smaller LDS
+footprint changes), and, for arrays of Tx elements, the ray order
+(element-minor or element-major).  Receive: the
 block size of the capture replay (cut to what its LDS stacks allow).  Each
 is searched by timing real runs of the caller's problem with the library's
 live HIP-event timing, and cached per (GPU architecture, problem class) in a
@@ -26,9 +28,10 @@ from . import sbr as S
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "sbr_mi355x", "tuning.json")
 GRID = {"trace_blocks_per_cu": (2, 4, 8), "trace_chunk": (64, 128, 256), "trace_graph": (0, 1),
         "trace_leaf_share": (40, 56)}
+PACKET_GRID = {"trace_blocks_per_cu": (4, 8, 16), "trace_chunk": (64, 128, 256)}
 ORDERS = (1, 0)                      # element-minor, element-major (arrays of Tx elements only)
 REPLAY_BLOCKS = (64, 128, 256, 512, 1024)
-KEYS = tuple(GRID) + ("trace_order",)
+KEYS = tuple(GRID) + ("trace_packet", "trace_order")
 RECEIVE_KEYS = ("replay_block",)
 
 
@@ -77,14 +80,14 @@ def _time_trace(ctx, run, reps: int, kernel: str = "bounce") -> float:
 
 def autotune(ctx: S.Context, run, key: str, reps: int = 2, cache_path: Optional[str] = DEFAULT_CACHE,
              grid: Optional[Dict[str, Iterable[int]]] = None, force: bool = False,
-             orders: Optional[Iterable[int]] = None) -> dict:
+             orders: Optional[Iterable[int]] = None, packet: bool = True) -> dict:
     """Tune for the trace launched by ``run()`` (a closure tracing the
     caller's problem on ``ctx``); returns and applies the best setting."""
     cache = _load(cache_path) if cache_path else {}
     if not force and key in cache:
         apply(ctx, cache[key]["config"])
         return cache[key]
-    grid = grid or GRID
+    grid = GRID if grid is None else grid
     best = None
     results = []
     saved = current(ctx)
@@ -97,6 +100,15 @@ def autotune(ctx: S.Context, run, key: str, reps: int = 2, cache_path: Optional[
         results.append({"config": cfg, "bounce_ms": ms})
         if best is None or ms < best["bounce_ms"]:
             best = {"config": cfg, "bounce_ms": ms}
+    # the wave-uniform traversal, over its own grid and chunk axes
+    if grid is GRID and packet:
+        for bpc, chunk in itertools.product(PACKET_GRID["trace_blocks_per_cu"], PACKET_GRID["trace_chunk"]):
+            cfg = dict(best["config"], trace_packet=1, trace_blocks_per_cu=bpc, trace_chunk=chunk)
+            apply(ctx, cfg)
+            ms = _time_trace(ctx, run, reps)
+            results.append({"config": cfg, "bounce_ms": ms})
+            if ms < best["bounce_ms"]:
+                best = {"config": cfg, "bounce_ms": ms}
     # the ray order of an array trace, at the best launch setting
     for order in (orders or ()):
         if order == best["config"]["trace_order"]:

@@ -1011,6 +1011,7 @@ sbr_status sbr_trace(sbr_context_t ctx, sbr_scene_t scene, const double* tx_xyz,
       L.grid = c->num_cus * c->tune.trace_blocks_per_cu;
       L.chunk = c->tune.trace_chunk;
       L.leaf_share = c->tune.trace_leaf_share;
+      L.packet = c->tune.trace_packet;
       hp_step.emplace("host:trace_launch");
       launch_trace(L, ra, rb, s);
     } catch (...) {
@@ -1881,6 +1882,9 @@ sbr_status sbr_context_set_tuning(sbr_context_t ctx, const char* key, int32_t va
     } else if (k == "trace_order") {
       SBR_CHECK(value == 0 || value == 1, SBR_E_INVALID_ARG, "trace_order = %d", value);
       c->tune.trace_order = value;
+    } else if (k == "trace_packet") {
+      SBR_CHECK(value == 0 || value == 1, SBR_E_INVALID_ARG, "trace_packet = %d", value);
+      c->tune.trace_packet = value;
     } else if (k == "receive_event_capacity") {
       SBR_CHECK(value >= 0, SBR_E_INVALID_ARG, "receive_event_capacity = %d", value);
       c->tune.receive_event_capacity = value;
@@ -1902,6 +1906,7 @@ sbr_status sbr_context_get_tuning(sbr_context_t ctx, const char* key, int32_t* v
     else if (k == "trace_graph") *value = c->tune.trace_graph;
     else if (k == "bvh_ploc_max") *value = c->tune.bvh_ploc_max;
     else if (k == "trace_order") *value = c->tune.trace_order;
+    else if (k == "trace_packet") *value = c->tune.trace_packet;
     else if (k == "receive_event_capacity") *value = c->tune.receive_event_capacity;
     else SBR_CHECK(false, SBR_E_INVALID_ARG, "unknown tuning key '%s'", key);
   });

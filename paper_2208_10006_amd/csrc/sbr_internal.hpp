@@ -147,13 +147,14 @@ struct Tuning {
   int trace_graph = 0;         // 1: replay the bounce loop as a cached hipGraph
   int bvh_ploc_max = 65536;    // scenes up to this many triangles are clustered with PLOC
   int trace_order = 1;         // 1: element-minor ray positions for traces of several elements (RayOrder)
+  int trace_packet = 0;        // 1: the wave traverses the tree as one (single-scene traces)
   int receive_event_capacity = 0;  // initial capture-event capacity of a receive; 0: max(2^20, rays / 8)
 };
 
 // An instantiated bounce-loop graph: init kernels + one kernel node per bounce,
 // built once per shape and replayed with updated kernel arguments.
 struct TraceGraph {
-  int K = -1, depth_bucket = 0, count = 0;
+  int K = -1, depth_bucket = 0, count = 0, packet = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<hipGraphNode_t> nodes;  // fill counters, bounce 0..K
@@ -383,6 +384,7 @@ struct TraceLaunch {
   uint32_t* counters;  // trace_counter_words(K): one kCtrWords block per bounce
   unsigned long long* work;  // node visits, triangle tests, or null (no counting)
   int grid, block, chunk, leaf_share;
+  int packet;  // wave-uniform traversal (ignored when counting work)
 };
 void launch_trace(const TraceLaunch& L, void* ray_a, void* ray_b, hipStream_t s);
 // one persistent launch per bounce over the rays of all traces (their seq,

@@ -215,6 +215,14 @@ __device__ inline float off1(float p, float n) {
   return fabsf(p) < kOrigin ? p + kFloatScale * n : pi;
 }
 
+// p[i] read through the constant address space: for memory that no kernel
+// writes while the reader runs, so that a wave-uniform index gives scalar loads
+__device__ inline float4 ld_const4(const float4* p, int64_t i) {
+  using cfloat = const __attribute__((address_space(4))) float;
+  cfloat* q = (cfloat*)p + 4 * i;
+  return make_float4(q[0], q[1], q[2], q[3]);
+}
+
 // scene of a global ray id: last s with offs[s] <= id
 __device__ inline int scene_of(const int64_t* offs, int n, uint64_t id) {
   int lo = 0, hi = n - 1;
@@ -226,9 +234,13 @@ __device__ inline int scene_of(const int64_t* offs, int n, uint64_t id) {
   return lo;
 }
 
-template <int STACK, bool COUNT, bool MULTI>
+// PACKET: the wave traverses the tree as one (single-scene, non-counting
+// launches only); otherwise every lane keeps its own traversal.
+template <int STACK, bool COUNT, bool MULTI, bool PACKET>
 __global__ __launch_bounds__(256) void k_bounce(const BounceParams P) {
-  __shared__ int32_t stack_mem[256 / kWave][STACK][kWave];
+  static_assert(!PACKET || (!COUNT && !MULTI), "packet traversal: one scene, no counting");
+  __shared__ int32_t stack_mem[256 / kWave][PACKET ? 1 : STACK][kWave];
+  __shared__ int32_t wave_stack[256 / kWave][PACKET ? STACK : 1];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int32_t* stk = &stack_mem[wv][0][lane];
   const bool first = P.k == 0;
@@ -388,7 +400,57 @@ __global__ __launch_bounds__(256) void k_bounce(const BounceParams P) {
       };
       for (int b = 0; b < SD.n_big; ++b) tri_test(SD.big_off + b);
       float tn;
-      if (SD.has_bvh && box_hit(SD.root[0], SD.root[1], SD.root[2], SD.root[3], SD.root[4], SD.root[5], thit, tn)) {
+      if (PACKET) {
+        // The wave walks the tree depth first as one: it enters a child when
+        // any of its lanes' rays enters the child's box (each lane against its
+        // own closest hit so far), tests a leaf child at once for the lanes
+        // that enter it, and goes first to the child most of the lanes that
+        // enter both find nearer.  Every lane still meets every box its own
+        // traversal would enter, and the extra ones can only offer triangles
+        // its ray really crosses, so each lane's closest hit (with its tie
+        // rule) is the one of the per-lane traversal.  The wave's stack holds
+        // one node per level in LDS, written by the wave's first active lane.
+        const bool want =
+            SD.has_bvh && box_hit(SD.root[0], SD.root[1], SD.root[2], SD.root[3], SD.root[4], SD.root[5], thit, tn);
+        if (__ballot(want) != 0) {
+          int32_t* ws = &wave_stack[wv][0];
+          const bool lead = lane == __builtin_ctzll(__ballot(1));
+          int sp = 0;
+          int32_t node = 0;
+          while (true) {
+            const float4 n0 = ld_const4(nodes, 4 * node), n1 = ld_const4(nodes, 4 * node + 1),
+                         n2 = ld_const4(nodes, 4 * node + 2), n3 = ld_const4(nodes, 4 * node + 3);
+            float tl, tr;
+            bool hl = want && box_hit(n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, thit, tl);
+            bool hr = want && box_hit(n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, thit, tr);
+            const int32_t cl = __builtin_amdgcn_readfirstlane(__float_as_int(n3.x));
+            const int32_t cr = __builtin_amdgcn_readfirstlane(__float_as_int(n3.y));
+            if (cl < 0) {
+              if (hl) tri_test(~cl);
+              hl = false;
+            }
+            if (cr < 0) {
+              if (hr && cr != cl) tri_test(~cr);
+              hr = false;
+            }
+            const bool gl = __ballot(hl) != 0, gr = __ballot(hr) != 0;
+            if (gl && gr) {
+              const int nb = __popcll(__ballot(hl && hr)), nl = __popcll(__ballot(hl && hr && tl <= tr));
+              const bool lfirst = 2 * nl >= nb;
+              if (lead) ws[sp] = lfirst ? cr : cl;
+              ++sp;
+              node = lfirst ? cl : cr;
+            } else if (gl || gr) {
+              node = gl ? cl : cr;
+            } else {
+              if (sp == 0) break;
+              --sp;
+              node = __builtin_amdgcn_readfirstlane(ws[sp]);
+            }
+          }
+        }
+      } else if (SD.has_bvh &&
+                 box_hit(SD.root[0], SD.root[1], SD.root[2], SD.root[3], SD.root[4], SD.root[5], thit, tn)) {
         // Leaves are not tested where they are found: a step finds a leaf in
         // a few lanes only, and a test site entered for them would idle the
         // rest of the wave.  Each lane keeps the leaf pairs of up to two
@@ -523,11 +585,11 @@ SceneDesc scene_desc(const sbr_scene_s* sc, const double* tx, int Nt, int emin, 
   return D;
 }
 
-template <bool COUNT, bool MULTI>
+template <bool COUNT, bool MULTI, bool PACKET = false>
 void launch_bounce(int depth, dim3 g, const BounceParams& P, hipStream_t s) {
-  if (depth <= 16) hipLaunchKernelGGL((k_bounce<16, COUNT, MULTI>), g, dim3(256), 0, s, P);
-  else if (depth <= 32) hipLaunchKernelGGL((k_bounce<32, COUNT, MULTI>), g, dim3(256), 0, s, P);
-  else hipLaunchKernelGGL((k_bounce<64, COUNT, MULTI>), g, dim3(256), 0, s, P);
+  if (depth <= 16) hipLaunchKernelGGL((k_bounce<16, COUNT, MULTI, PACKET>), g, dim3(256), 0, s, P);
+  else if (depth <= 32) hipLaunchKernelGGL((k_bounce<32, COUNT, MULTI, PACKET>), g, dim3(256), 0, s, P);
+  else hipLaunchKernelGGL((k_bounce<64, COUNT, MULTI, PACKET>), g, dim3(256), 0, s, P);
 }
 
 }  // namespace
@@ -567,11 +629,11 @@ TraceGraph::~TraceGraph() {
 }
 
 namespace {
-template <bool COUNT>
+template <bool COUNT, bool PACKET>
 const void* bounce_fn(int depth) {
-  if (depth <= 16) return reinterpret_cast<const void*>(&k_bounce<16, COUNT, false>);
-  if (depth <= 32) return reinterpret_cast<const void*>(&k_bounce<32, COUNT, false>);
-  return reinterpret_cast<const void*>(&k_bounce<64, COUNT, false>);
+  if (depth <= 16) return reinterpret_cast<const void*>(&k_bounce<16, COUNT, false, PACKET>);
+  if (depth <= 32) return reinterpret_cast<const void*>(&k_bounce<32, COUNT, false, PACKET>);
+  return reinterpret_cast<const void*>(&k_bounce<64, COUNT, false, PACKET>);
 }
 hipKernelNodeParams knode(const void* fn, dim3 g, dim3 b, void** args) {
   hipKernelNodeParams p{};
@@ -587,15 +649,17 @@ hipKernelNodeParams knode(const void* fn, dim3 g, dim3 b, void** args) {
 
 // The bounce loop as a graph: fill(counters) -> bounce 0 -> ... -> bounce K,
 // all kernel nodes (no memset nodes).  Built on first use for a
-// (K, depth class, counting) shape, then only the kernel arguments are updated.
+// (K, depth class, counting, traversal) shape, then only the kernel arguments
+// are updated.
 void launch_trace_graph(const TraceLaunch& T, const BounceParams* P, int nP, hipStream_t s) {
   sbr_context_s* c = T.ctx;
   const int depth = T.scene->bvh_depth;
   const int bucket = depth <= 16 ? 16 : depth <= 32 ? 32 : 64;
   const int count = T.work ? 1 : 0;
+  const int packet = !count && T.packet ? 1 : 0;
   TraceGraph* G = nullptr;
   for (auto* g : c->graphs)
-    if (g->K == T.K && g->depth_bucket == bucket && g->count == count) G = g;
+    if (g->K == T.K && g->depth_bucket == bucket && g->count == count && g->packet == packet) G = g;
   uint32_t* cnt = T.counters;
   int64_t ncnt = trace_counter_words(T.K);
   uint32_t v0 = 0;
@@ -605,10 +669,11 @@ void launch_trace_graph(const TraceLaunch& T, const BounceParams* P, int nP, hip
   for (int k = 0; k < nP; ++k) a_b[k] = &Pc[k];
   const void* ffill = reinterpret_cast<const void*>(&k_fill_u32_graph);
   const dim3 gc((unsigned)((ncnt + 255) / 256)), gb(T.grid), b256(256);
-  const void* fb = count ? bounce_fn<true>(depth) : bounce_fn<false>(depth);
+  const void* fb = count ? bounce_fn<true, false>(depth) : packet ? bounce_fn<false, true>(depth)
+                                                                   : bounce_fn<false, false>(depth);
   if (!G) {
     G = new TraceGraph();
-    G->K = T.K, G->depth_bucket = bucket, G->count = count;
+    G->K = T.K, G->depth_bucket = bucket, G->count = count, G->packet = packet;
     SBR_HIP(hipGraphCreate(&G->graph, 0));
     hipGraphNode_t prev = nullptr;
     auto add = [&](const void* fn, dim3 g, void** args) {
@@ -665,6 +730,7 @@ void launch_trace(const TraceLaunch& T, void* ray_a, void* ray_b, hipStream_t s)
   for (int k = 0; k <= T.K; ++k) {
     ::sbr::TimedLaunch tl_("bounce", s);
     if (T.work) launch_bounce<true, false>(depth, dim3(T.grid), Pk[k], s);
+    else if (T.packet) launch_bounce<false, false, true>(depth, dim3(T.grid), Pk[k], s);
     else launch_bounce<false, false>(depth, dim3(T.grid), Pk[k], s);
     SBR_LAUNCH_CHECK();
   }

@@ -740,6 +740,45 @@ def test_leaf_share_keeps_hits(S, ctx, scene):
             S.sbr_context_set_tuning(ctx, "trace_leaf_share", bad)
 
 
+@pytest.mark.parametrize("scene", ["boxes", "urban", "office"])
+def test_packet_traversal_keeps_hits(S, ctx, scene):
+    """A wave walking the tree as one meets every box each of its rays would
+    enter on its own, and the extra boxes only offer triangles the ray
+    crosses: the hit chains equal the per-ray traversal's, ray by ray, with
+    direct launches and with the graph bounce loop, in both ray orders."""
+    banner(f"packet traversal, {scene}")
+    if scene == "boxes":
+        w = W.random_box_scene(61, n_boxes=40, n_rx=2, N=96, K=5)
+    elif scene == "urban":
+        w = W.urban_canyon(N=96, n_rx=10)
+    else:
+        w = W.mimo_office(64, N=48, nf=2)
+    sc = S.sbr_scene_build(ctx, w.tri, w.eps_r, w.sigma, w.rough)
+    keys = ("trace_packet", "trace_graph", "trace_order")
+    old = {k: S.sbr_context_get_tuning(ctx, k) for k in keys}
+    try:
+        for order in ((1, 0) if len(w.tx) > 1 else (1,)):
+            S.sbr_context_set_tuning(ctx, "trace_order", order)
+            ref = None
+            for packet, graph in ((0, 0), (1, 0), (1, 1), (0, 1)):
+                S.sbr_context_set_tuning(ctx, "trace_packet", packet)
+                S.sbr_context_set_tuning(ctx, "trace_graph", graph)
+                tr = S.sbr_trace(ctx, sc, w.tx, w.geodesic_N, w.max_bounces)
+                hits = S.sbr_trace_hits(tr)
+                if ref is None:
+                    ref, segs = hits, S.sbr_trace_info(tr)["segments"]
+                    assert np.count_nonzero(ref[:, 1] >= 0) > 0
+                else:
+                    assert np.array_equal(hits, ref), f"order {order} packet {packet} graph {graph}"
+                    assert S.sbr_trace_info(tr)["segments"] == segs
+    finally:
+        for k, v in old.items():
+            S.sbr_context_set_tuning(ctx, k, v)
+    for bad in (-1, 2):
+        with pytest.raises(S.SbrError):
+            S.sbr_context_set_tuning(ctx, "trace_packet", bad)
+
+
 def test_autotuner_picks_and_applies(S, ctx, tmp_path):
     banner("autotuner")
     from paper_2208_10006_amd import autotune as A
