@@ -235,9 +235,15 @@ __device__ inline int scene_of(const int64_t* offs, int n, uint64_t id) {
 }
 
 // PACKET: the wave traverses the tree as one (single-scene, non-counting
-// launches only); otherwise every lane keeps its own traversal.
+// launches only); otherwise every lane keeps its own traversal.  The
+// wave-uniform traversal waits on one node fetch per step for the whole
+// wave, and more resident waves hide that: its registers are capped for 7
+// waves per SIMD (72 VGPRs, a few spilled; measured faster than 5, 6 or 8).
+// The per-lane traversal gained nothing from more waves and keeps its
+// registers.
 template <int STACK, bool COUNT, bool MULTI, bool PACKET>
-__global__ __launch_bounds__(256) void k_bounce(const BounceParams P) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PACKET ? 7 : 1))) void k_bounce(
+    const BounceParams P) {
   static_assert(!PACKET || (!COUNT && !MULTI), "packet traversal: one scene, no counting");
   __shared__ int32_t stack_mem[256 / kWave][PACKET ? 1 : STACK][kWave];
   __shared__ int32_t wave_stack[256 / kWave][PACKET ? STACK : 1];
