@@ -203,9 +203,11 @@ def batched_main(args):
     # receive it.
     import concurrent.futures as cf
     import itertools
-    n_tail = max(1, min(args.tail_contexts, len(ws)))
+    # --tail-contexts 0: every receive on the calling thread and the trace's
+    # own context, one scene after another (no worker threads).
+    n_tail = min(args.tail_contexts, len(ws))
     tail_ctx = [S.Context(0) for _ in range(n_tail)]
-    pool = cf.ThreadPoolExecutor(n_tail)
+    pool = cf.ThreadPoolExecutor(n_tail) if n_tail > 0 else None
     order = sorted(range(len(ws)), key=lambda i: -w_cost(ws[i]))
 
     def tails(trs):
@@ -223,6 +225,9 @@ def batched_main(args):
                 S.sbr_stats_device(ps, d["pg"], d["tau"], d["ang"])
             S.sbr_synchronize(c)
 
+        if pool is None:
+            worker(ctx)
+            return
         for f in [pool.submit(worker, c) for c in tail_ctx]:
             f.result()
 
@@ -256,7 +261,8 @@ def batched_main(args):
     S.sbr_profile_enable(ctx, False)
     kernels = {"bounce": {"ms_per_step": bounce_ms / args.steps, "launches_per_step": bounce_n / args.steps}}
     kernels.update(breakdown(S, ctx, one_step, exclude=("bounce",), more=tail_ctx))
-    pool.shutdown()
+    if pool is not None:
+        pool.shutdown()
     lat = np.array(lat)
     out = {"metric": "traced ray-segments/s (batched uneven scenes)", "value": segs * args.steps / (t1 - t0),
            "unit": "ray-segments/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -612,7 +618,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--scenes", type=int, default=64, help="batched_uneven: number of scenes")
     ap.add_argument("--tail-contexts", type=int, default=8,
-                    help="batched_uneven: contexts (streams and host threads) for the per-scene receives")
+                    help="batched_uneven: contexts (streams and host threads) for the per-scene receives; 0 = on the calling thread")
     ap.add_argument("--surrogate-steps", type=int, default=0, help="surrogate: training steps per member")
     ap.add_argument("--mimo-sizes", default="16,32,64,128", help="mimo_sweep: array sizes n (n Tx x n Rx)")
     ap.add_argument("--tile-area", type=float, default=0.25, help="office_scattering: surface tile area, m^2")
