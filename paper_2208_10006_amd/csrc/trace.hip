@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <type_traits>
 
 #include "sbr_device.hpp"
 #include "sbr_internal.hpp"
@@ -223,6 +224,23 @@ __device__ inline float4 ld_const4(const float4* p, int64_t i) {
   return make_float4(q[0], q[1], q[2], q[3]);
 }
 
+// Near and far planes of one axis for two boxes, chosen on the scalar unit
+// for the whole wave: neg != 0 (a ballot of the lanes whose direction
+// component is negative) takes hi as the near plane.  All operands are
+// wave-uniform (scalar registers); the outputs are early-clobber so that no
+// output shares a register with an input still to be read.
+__device__ inline void pick_planes(uint64_t neg, float lo_l, float hi_l, float lo_r, float hi_r, float& n_l, float& f_l,
+                                   float& n_r, float& f_r) {
+  asm("s_cmp_lg_u64 %4, 0\n\t"
+      "s_cselect_b32 %0, %6, %5\n\t"
+      "s_cselect_b32 %1, %5, %6\n\t"
+      "s_cselect_b32 %2, %8, %7\n\t"
+      "s_cselect_b32 %3, %7, %8"
+      : "=&s"(n_l), "=&s"(f_l), "=&s"(n_r), "=&s"(f_r)
+      : "s"(neg), "s"(lo_l), "s"(hi_l), "s"(lo_r), "s"(hi_r)
+      : "scc");
+}
+
 // scene of a global ray id: last s with offs[s] <= id
 __device__ inline int scene_of(const int64_t* offs, int n, uint64_t id) {
   int lo = 0, hi = n - 1;
@@ -373,6 +391,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PACKET ? 7 
         tn = tmin;
         return tmin <= tmx * 1.0000004f;
       };
+      // The same test with the near and far planes of every axis already
+      // chosen (by the sign of the direction): rounding is monotonic, so with
+      // inv > 0 the plane lo gives the smaller t and with inv < 0 the plane hi,
+      // so it makes box_hit's decision and returns its entry distance (up to
+      // the sign of a zero) with half its min / max.
+      auto box_nf = [&](float nx, float ny, float nz, float fx, float fy, float fz, float tmax, float& tn) {
+        const float tnx = fmaf(nx, inv.x, -oinv.x), tfx = fmaf(fx, inv.x, -oinv.x);
+        const float tny = fmaf(ny, inv.y, -oinv.y), tfy = fmaf(fy, inv.y, -oinv.y);
+        const float tnz = fmaf(nz, inv.z, -oinv.z), tfz = fmaf(fz, inv.z, -oinv.z);
+        const float tmin = fmaxf(fmaxf(tnx, tny), fmaxf(tnz, 0.0f));
+        const float tmx = fminf(fminf(tfx, tfy), fminf(tfz, tmax));
+        tn = tmin;
+        return tmin <= tmx * 1.0000004f;
+      };
       // All 48 bytes of the triangle's layout are loaded before any decision, so a
       // test costs one memory round trip; the rejections are folded into one
       // final predicate instead of early exits.  t = Tn / det is formed with
@@ -418,42 +450,71 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PACKET ? 7 
         // one node per level in LDS, written by the wave's first active lane.
         const bool want =
             SD.has_bvh && box_hit(SD.root[0], SD.root[1], SD.root[2], SD.root[3], SD.root[4], SD.root[5], thit, tn);
-        if (__ballot(want) != 0) {
+        const uint64_t wm = __ballot(want);
+        if (wm != 0) {
           int32_t* ws = &wave_stack[wv][0];
           const bool lead = lane == __builtin_ctzll(__ballot(1));
-          int sp = 0;
-          int32_t node = 0;
-          while (true) {
-            const float4 n0 = ld_const4(nodes, 4 * node), n1 = ld_const4(nodes, 4 * node + 1),
-                         n2 = ld_const4(nodes, 4 * node + 2), n3 = ld_const4(nodes, 4 * node + 3);
-            float tl, tr;
-            bool hl = want && box_hit(n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, thit, tl);
-            bool hr = want && box_hit(n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, thit, tr);
-            const int32_t cl = __builtin_amdgcn_readfirstlane(__float_as_int(n3.x));
-            const int32_t cr = __builtin_amdgcn_readfirstlane(__float_as_int(n3.y));
-            if (cl < 0) {
-              if (hl) tri_test(~cl);
-              hl = false;
+          // When the wanting lanes agree on the sign of every direction
+          // component (a wave of parallel or nearly parallel rays), the near
+          // and far planes of each box are chosen once for the wave, on the
+          // scalar unit, and the box test needs no per-lane min / max pairs.
+          const uint64_t mx = __ballot(want && inv.x < 0.0f), my = __ballot(want && inv.y < 0.0f),
+                         mz = __ballot(want && inv.z < 0.0f);
+
+          const bool same = (mx == 0 || mx == wm) && (my == 0 || my == wm) && (mz == 0 || mz == wm);
+          auto walk = [&](auto same_t) {
+            constexpr bool SAME = decltype(same_t)::value;
+            int sp = 0;
+            int32_t node = 0;
+            while (true) {
+              const float4 n0 = ld_const4(nodes, 4 * node), n1 = ld_const4(nodes, 4 * node + 1),
+                           n2 = ld_const4(nodes, 4 * node + 2), n3 = ld_const4(nodes, 4 * node + 3);
+              float tl, tr;
+              bool hl, hr;
+              // every lane computes both tests, and the masks are ballots of
+              // the bare comparisons (so they need no conversion) cut to the
+              // lanes that want the tree on the scalar unit
+              if constexpr (SAME) {
+                // left box lo (n0.x n0.y n0.z) hi (n0.w n1.x n1.y); right lo (n1.z n1.w n2.x) hi (n2.y n2.z n2.w)
+                float nlx, flx, nrx, frx, nly, fly, nry, fry, nlz, flz, nrz, frz;
+                pick_planes(mx, n0.x, n0.w, n1.z, n2.y, nlx, flx, nrx, frx);
+                pick_planes(my, n0.y, n1.x, n1.w, n2.z, nly, fly, nry, fry);
+                pick_planes(mz, n0.z, n1.y, n2.x, n2.w, nlz, flz, nrz, frz);
+                hl = box_nf(nlx, nly, nlz, flx, fly, flz, thit, tl);
+                hr = box_nf(nrx, nry, nrz, frx, fry, frz, thit, tr);
+              } else {
+                hl = box_hit(n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, thit, tl);
+                hr = box_hit(n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, thit, tr);
+              }
+              const uint64_t bl = __ballot(hl) & wm, br = __ballot(hr) & wm, bn = __ballot(tl <= tr);
+              const int32_t cl = __builtin_amdgcn_readfirstlane(__float_as_int(n3.x));
+              const int32_t cr = __builtin_amdgcn_readfirstlane(__float_as_int(n3.y));
+              // leaf children are tested at once by the lanes that enter them
+              if (cl < 0 && bl != 0) {
+                if (want && hl) tri_test(~cl);
+              }
+              if (cr < 0 && cr != cl && br != 0) {
+                if (want && hr) tri_test(~cr);
+              }
+              // inner children entered by some lane
+              const uint64_t ml = cl < 0 ? 0 : bl, mr = cr < 0 ? 0 : br;
+              if (ml != 0 && mr != 0) {
+                const int nb = __popcll(ml & mr), nl = __popcll(ml & mr & bn);
+                const bool lfirst = 2 * nl >= nb;
+                if (lead) ws[sp] = lfirst ? cr : cl;
+                ++sp;
+                node = lfirst ? cl : cr;
+              } else if (ml != 0 || mr != 0) {
+                node = ml != 0 ? cl : cr;
+              } else {
+                if (sp == 0) break;
+                --sp;
+                node = __builtin_amdgcn_readfirstlane(ws[sp]);
+              }
             }
-            if (cr < 0) {
-              if (hr && cr != cl) tri_test(~cr);
-              hr = false;
-            }
-            const bool gl = __ballot(hl) != 0, gr = __ballot(hr) != 0;
-            if (gl && gr) {
-              const int nb = __popcll(__ballot(hl && hr)), nl = __popcll(__ballot(hl && hr && tl <= tr));
-              const bool lfirst = 2 * nl >= nb;
-              if (lead) ws[sp] = lfirst ? cr : cl;
-              ++sp;
-              node = lfirst ? cl : cr;
-            } else if (gl || gr) {
-              node = gl ? cl : cr;
-            } else {
-              if (sp == 0) break;
-              --sp;
-              node = __builtin_amdgcn_readfirstlane(ws[sp]);
-            }
-          }
+          };
+          if (same) walk(std::true_type{});
+          else walk(std::false_type{});
         }
       } else if (SD.has_bvh &&
                  box_hit(SD.root[0], SD.root[1], SD.root[2], SD.root[3], SD.root[4], SD.root[5], thit, tn)) {
